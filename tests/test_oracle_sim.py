@@ -1,0 +1,197 @@
+"""Pins of the oracle's sampler and simulation step (CPU only).
+
+* the radial propagator sampler against the literal densities (KS tests);
+* the pair list against brute-force enumeration;
+* the selection rules' invariants and calibration;
+* exact single-pair statistics: one-step and multi-step reaction probability of
+  an isolated pair equals 1 - S_rad, the geminate-recombination fraction of a
+  dissociation equals 1 - S_rad(dt | a);
+* conservation of A + C and B + C and of the C <-> reserved-slot map.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, stats
+
+import oracle as O
+from paper_1107_0270_amd import inputs as I
+
+
+def _cdf_from_density(dens, lo, hi, n=4000):
+    xs = np.linspace(lo, hi, n)
+    ys = np.array([dens(x) for x in xs])
+    c = np.concatenate([[0.0], np.cumsum(0.5 * (ys[1:] + ys[:-1]) * np.diff(xs))])
+    c /= c[-1]
+    return lambda x: np.interp(x, xs, c)
+
+
+@pytest.mark.parametrize("tau", [0.08, 0.8, 50.0])
+@pytest.mark.parametrize("R0", [1.0, 1.3, 2.5])
+def test_sampler_3d_matches_propagator(tau, R0):
+    top = R0 + 14 * math.sqrt(tau) + 2
+    cdf = _cdf_from_density(lambda R: O.prop3_density(R, R0, tau), 1.0, top)
+    key = (12345, 678)
+    xs = np.array([O.sample_prop(3, R0, tau, 0, (k, 7, 3, 5), key)[0] for k in range(3000)])
+    assert np.all(xs >= 1.0)
+    assert stats.kstest(xs, cdf).pvalue > 1e-4
+
+
+@pytest.mark.parametrize("R0", [1.0, 1.3])
+def test_sampler_2d_matches_propagator(R0):
+    tau, n = 0.04, 12
+    top = R0 + 14 * math.sqrt(tau) + 1
+    cdf = _cdf_from_density(lambda R: O.prop2_density(R, R0, tau, n), 1.0, top)
+    xs = np.array([O.sample_prop(2, R0, tau, n, (k, 9, 1, 5), (1, 2))[0] for k in range(3000)])
+    assert stats.kstest(xs, cdf).pvalue > 1e-4
+
+
+def _sim(dim, bc, n_a, n_b, box, sigma, D=(1.0, 1.0, 0.5), dt=1e-6, seed=0, **kw):
+    sp, pos, _ = I.uniform_state(n_a, n_b, box=box, dim=dim, sigma=sigma, seed=seed, f32=False)
+    return O.OracleSim(dim=dim, bc=bc, box=[box] * dim, dt=dt, D=D, sigma=sigma, species=sp, pos=pos, seed=seed, **kw)
+
+
+@pytest.mark.parametrize("dim,box", [(3, 0.3), (2, 0.25), (3, 0.05)])
+def test_pair_list_is_brute_force(dim, box):
+    # box 0.05 um has fewer than three cells per edge: exercises the single-cell path
+    s = _sim(dim, O.BC_ABS, 300, 300, box, 0.004, dt=2e-6)
+    rc = s.derived()["rcut"]
+    for _ in range(3):
+        sp_before, _, _ = s.state()
+        s.step()
+        got = {(int(p["i"]), int(p["j"])) for p in s.pairs()}
+        # pairs are formed from the post-move positions of A and B that were live at step start
+        brute = _brute_pairs_from(s, sp_before, rc)
+        assert got == brute
+        assert len(got) > 0
+
+
+def _brute_pairs_from(s, sp, rcut):
+    x = s.moved()
+    box = np.array(s._p.box[: s.dim])
+    A, B = np.where(sp == O.SP_A)[0], np.where(sp == O.SP_B)[0]
+    d = x[B][None, :, :] - x[A][:, None, :]
+    d = np.where(d > 0.5 * box, d - box, np.where(d < -0.5 * box, d + box, d))
+    r2 = (d * d).sum(-1)
+    ia, ib = np.nonzero(r2 < rcut * rcut)
+    return set(zip(A[ia].tolist(), B[ib].tolist()))
+
+
+def test_selection_invariants_and_calibration():
+    # dense 3D radiation system: many A's with several candidates
+    s = _sim(3, O.BC_RAD, 400, 400, 0.12, 0.006, D=(1.0, 1.0, 0.5), dt=4e-6, kappa_a=0.05)
+    pred, hit = [], []
+    multi = 0
+    for _ in range(60):
+        s.step()
+        pr, pk, mt = s.pairs(), s.picks(), s.matches()
+        cand = pr[pr["cand"] == 1]
+        cset = {(int(a), int(b)) for a, b in zip(cand["i"], cand["j"])}
+        # every pick is a candidate, exactly one pick per A with candidates
+        assert {(int(a), int(b)) for a, b in zip(pk["i"], pk["j"])} <= cset
+        assert sorted(pk["i"].tolist()) == sorted(set(cand["i"].tolist()))
+        # every match is a pick, one match per picked B, every slot at most once
+        assert {(int(a), int(b)) for a, b in zip(mt["i"], mt["j"])} <= {(int(a), int(b)) for a, b in zip(pk["i"], pk["j"])}
+        assert sorted(mt["j"].tolist()) == sorted(set(pk["j"].tolist()))
+        assert len(set(mt["i"].tolist())) == len(mt) and len(set(mt["j"].tolist())) == len(mt)
+        # A-side calibration: P(pick k | candidates) = p_k / sum p
+        chosen = {int(a): int(b) for a, b in zip(pk["i"], pk["j"])}
+        for a in np.unique(cand["i"]):
+            rows = cand[cand["i"] == a]
+            if len(rows) < 2:
+                continue
+            multi += 1
+            T = rows["p"].sum()
+            for r in rows:
+                pred.append(r["p"] / T)
+                hit.append(1.0 if chosen[int(a)] == int(r["j"]) else 0.0)
+    assert multi > 200
+    pred, hit = np.array(pred), np.array(hit)
+    # binned reliability: observed frequency within 4.5 sigma of the prediction
+    edges = np.quantile(pred, np.linspace(0, 1, 6))
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        m = (pred >= lo) & (pred <= hi)
+        exp_, obs = pred[m].sum(), hit[m].sum()
+        var = (pred[m] * (1 - pred[m])).sum()
+        assert abs(obs - exp_) < 4.5 * math.sqrt(var) + 1
+
+
+def _isolated_pairs(M, spacing, r0, dim, seed):
+    rng = np.random.default_rng(seed)
+    side = int(math.ceil(M ** (1.0 / dim)))
+    grid = np.stack(np.meshgrid(*[np.arange(side)] * dim, indexing="ij"), -1).reshape(-1, dim)[:M]
+    a = (grid + 0.5) * spacing
+    u = rng.normal(size=(M, dim))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    b = a + r0 * u
+    pos = np.concatenate([a, b])
+    sp = np.concatenate([np.zeros(M, np.int32), np.ones(M, np.int32)])
+    return sp, pos, side * spacing
+
+
+@pytest.mark.parametrize("bc,steps", [(O.BC_RAD, 1), (O.BC_ABS, 1), (O.BC_RAD, 4)])
+def test_isolated_pair_reaction_probability(bc, steps):
+    # An isolated pair from r0 reacts within n dt with probability 1 - S(n dt | r0):
+    # one step gives int p_enc g_free x int p_reac prop = 1 - S_rad exactly
+    # (Secs. 2.2.1-2.2.3), and the radial end-point law is g_rad, so n steps
+    # compose by Chapman-Kolmogorov.  No cut-off loss: eps = 1e-14.
+    M, a, Deff, dt, ka = 60000, 0.005, 2.0, 1e-5, 0.1
+    R0 = 1.2
+    sp, pos, box = _isolated_pairs(M, 0.25, R0 * a, 3, seed=steps)
+    s = O.OracleSim(dim=3, bc=bc, box=[box] * 3, dt=dt, D=(1.0, 1.0, 0.5), sigma=a, kappa_a=ka,
+                    eps_cut=1e-14, species=sp, pos=pos, seed=11 + steps)
+    assert s.derived()["rcut"] < 0.1
+    s.step(steps)
+    spf, _, _ = s.state()
+    frac = np.mean(spf[:M] == O.SP_C)
+    tau, hh = Deff * steps * dt / a ** 2, ka / (4 * math.pi * a * Deff)
+    P = O.loss3_rad(R0, tau, hh) if bc == O.BC_RAD else O.loss3_abs(R0, tau)
+    sig = math.sqrt(P * (1 - P) / M)
+    assert abs(frac - P) < 4.5 * sig, (frac, P, sig)
+
+
+def test_dissociation_and_geminate_recombination():
+    # C at contact decays with p = 1 - e^{-k dt} (eq. rad_prob); the products
+    # recombine with probability int p_reac(.|a) prop(.|a) / (1 - S_abs(a)) =
+    # 1 - S_rad(dt | a), since 1 - S_abs(dt | a) = 1.
+    M, a, dt, ka, koff = 40000, 0.005, 1e-5, 0.5, 7e4
+    side = int(math.ceil(M ** (1 / 3)))
+    grid = np.stack(np.meshgrid(*[np.arange(side)] * 3, indexing="ij"), -1).reshape(-1, 3)[:M]
+    pos = np.concatenate([(grid + 0.5) * 0.25, np.zeros((M, 3))])
+    sp = np.concatenate([np.full(M, O.SP_C, np.int32), np.full(M, O.SP_RESERVED, np.int32)])
+    partner = np.concatenate([np.arange(M, 2 * M, dtype=np.uint32), np.full(M, 0xFFFFFFFF, np.uint32)])
+    s = O.OracleSim(dim=3, bc=O.BC_RAD, box=[side * 0.25] * 3, dt=dt, D=(1.0, 1.0, 0.5), sigma=a, kappa_a=ka,
+                    k_off=koff, species=sp, pos=pos, partner=partner, seed=5)
+    s.step()
+    ds = s.dissociations()
+    pu = -math.expm1(-koff * dt)
+    n_dec = len(ds)
+    assert abs(n_dec - pu * M) < 4.5 * math.sqrt(M * pu * (1 - pu))
+    tau, hh = 2.0 * dt / a ** 2, ka / (4 * math.pi * a * 2.0)
+    Pg = O.loss3_rad(1.0, tau, hh)
+    g = ds["recombined"].sum()
+    assert abs(g - Pg * n_dec) < 4.5 * math.sqrt(n_dec * Pg * (1 - Pg))
+    # escaped products sit R'' a apart around the old C position
+    spf, xf, pt = s.state()
+    esc = ds[ds["recombined"] == 0]
+    for row in esc[:50]:
+        c, j = int(row["c"]), int(row["j"])
+        assert spf[c] == O.SP_A and spf[j] == O.SP_B
+        d = xf[j] - xf[c]
+        assert np.linalg.norm(d) == pytest.approx(row["Rpp"] * a, rel=1e-9)
+
+
+def test_conservation_reversible():
+    s = _sim(3, O.BC_RAD, 500, 500, 0.2, 0.006, D=(1.0, 1.0, 0.5), dt=5e-6, kappa_a=0.5, k_off=2e4)
+    sp0, _, _ = s.state()
+    nA0, nB0 = (sp0 == O.SP_A).sum(), (sp0 == O.SP_B).sum()
+    seen_c = 0
+    for _ in range(40):
+        s.step()
+        sp, _, pt = s.state()
+        nA, nB, nC, nR = [(sp == k).sum() for k in (O.SP_A, O.SP_B, O.SP_C, O.SP_RESERVED)]
+        assert nA + nC == nA0 and nB + nC == nB0 and nR == nC
+        cs = np.where(sp == O.SP_C)[0]
+        assert sorted(pt[cs].tolist()) == sorted(np.where(sp == O.SP_RESERVED)[0].tolist())
+        seen_c = max(seen_c, nC)
+    assert seen_c > 0
