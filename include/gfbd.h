@@ -1,0 +1,171 @@
+/*
+ * gfbd.h - C-ABI of the MI355X (gfx950) implementation of the coarse-grained
+ * Green's-function Brownian-dynamics step of T. Pruestel and M.
+ * Meier-Schellersheim, "Coarse-Grained Stochastic Particle-based
+ * Reaction-Diffusion Simulation Algorithm" (arXiv:1107.0270).
+ *
+ * One call of sim_step advances the state by one time step dt of the
+ * algorithm of Sec. 3:
+ *   1. every particle takes a free Gaussian step sqrt(2 D dt) N(0,1)  (step 1);
+ *   2. all A-B pairs closer than the cut-off r_cut (Sec. 3, Details) are found;
+ *   3. each pair gets the encounter probability p_enc = 1 - G_abs/G_free
+ *      (Sec. 2.2.1, radial form Sec. 2.2.4; 3D closed forms of Sec. 4.1, 2D
+ *      small-time expansions of Sec. 4.2), overlapping pairs p_enc = 1, and a
+ *      Bernoulli draw (steps 2 and 3);
+ *   4. each A picks one of its candidates with probability p_enc / sum p_enc,
+ *      then each B picked several times picks one of those A's (Sec. 3, Details);
+ *   5. matched pairs react (absorbing), or get a new separation from the radial
+ *      propagator w_d r^{d-1}(g_ref - g_abs) (Sec. 2.2.2) and react with
+ *      p_reac = (G_ref - G_rad)/(G_ref - G_abs) (Sec. 2.2.3);
+ *   6. C decays to A + B with p = 1 - exp(-k_off dt), the products start at
+ *      contact, are propagated from r0 = a and may recombine (Sec. 2.2.5, step 4).
+ *
+ * Units: lengths in um, times in s, D in um^2/s, kappa_a in um^3/s (3D) or
+ * um^2/s (2D), k_off in 1/s.  Species: exactly one channel A + B <-> C.
+ *
+ * State model: a fixed set of slots 0..n-1.  A slot holds an A, B or C, is
+ * FREE, or is RESERVED by the C that consumed its B (reversible channel only);
+ * when that C dissociates, its B returns to the reserved slot.  Positions are
+ * kept in the precision of the state (binary64 for SIM_PREC_FP64, binary32
+ * otherwise); every update is computed in binary64 and rounded once.
+ *
+ * Random numbers: Philox4x32-10 with key {seed_lo, seed_hi ^ replica} and
+ * counter {slot, partner slot or 0xFFFFFFFF, step, tag | attempt << 8}; every
+ * draw is a pure function of the particles and the step it belongs to.
+ *
+ * Errors: every call returns SIM_OK or a negative code and never throws.
+ * sim_last_error(h) describes the last failure on that handle.  Handles are
+ * not thread-safe; use one handle per host thread and stream.
+ */
+#ifndef GFBD_H
+#define GFBD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sim sim_t; /* opaque, owned by the library */
+
+enum {
+    SIM_OK = 0,
+    SIM_EINVAL = -1,      /* an argument is out of range; nothing changed */
+    SIM_ENOMEM = -2,      /* device or host allocation failed */
+    SIM_EDEVICE = -3,     /* a HIP call failed; the handle should be destroyed */
+    SIM_ESTATE = -4,      /* call not valid in the handle's current state */
+    SIM_EUNSUPPORTED = -5,/* valid input outside what this build supports */
+    SIM_ECAPACITY = -6    /* a per-step buffer overflowed; the step's results are invalid */
+};
+
+enum { SIM_SP_A = 0, SIM_SP_B = 1, SIM_SP_C = 2, SIM_SP_FREE = 3, SIM_SP_RESERVED = 4 };
+enum { SIM_BC_ABSORBING = 0, SIM_BC_REFLECTING = 1, SIM_BC_RADIATION = 2 };
+
+/* Precision of the state and of the pair probabilities:
+ *  FP64          state and all arithmetic in binary64;
+ *  FP32          binary32 state, pair search and p_enc in binary32;
+ *  FP32_FP64NC   binary32 state, binary32 p_enc whose arguments (r, r - a,
+ *                r0 - a and the exponent arguments) are formed in binary64.
+ * Displacements, placements, the propagator and p_reac are binary64 in all modes. */
+enum { SIM_PREC_FP64 = 0, SIM_PREC_FP32 = 1, SIM_PREC_FP32_FP64NC = 2 };
+
+typedef struct {
+    double D; /* diffusion constant, um^2/s, >= 0 */
+} sim_species;
+
+typedef struct {
+    int32_t a, b, c;  /* species indices: must be 0, 1, 2 */
+    int32_t bc;       /* SIM_BC_* of the A-B encounter surface */
+    double sigma;     /* encounter radius a_eff, um, > 0 (eq. smol_bc) */
+    double kappa;     /* intrinsic association rate kappa_a (eq. robin_bc), >= 0 */
+    double k_off;     /* C -> A + B rate (eq. single_rate), 1/s; 0 = irreversible */
+} sim_reaction;
+
+typedef struct {
+    int32_t dim;                   /* 2 or 3 */
+    int32_t precision;             /* SIM_PREC_* */
+    double box[3];                 /* periodic box edges, um (box[2] ignored in 2D) */
+    double dt;                     /* time step, s, > 0 */
+    uint64_t seed;                 /* Philox key material */
+    uint32_t replica;              /* folded into the Philox key */
+    int32_t n_terms;               /* order of the 2D small-time expansion, 1..32 (0 = 12) */
+    double eps_cut;                /* cut-off: 1 - S(dt | r_cut) = eps_cut (0 = 1e-3) */
+    double rcut;                   /* > 0: use this cut-off (um) instead of deriving it */
+    double cell;                   /* > 0: requested cell edge (um, raised to >= r_cut); 0 = automatic */
+    int32_t n_species;             /* must be 3: A, B, C */
+    const sim_species *species;    /* n_species entries; D_C is the C diffusion constant */
+    int32_t n_reactions;           /* must be 1 */
+    const sim_reaction *reactions;
+    uint32_t debug;                /* 1: record the last step's stage logs for sim_read */
+    uint32_t timing;               /* 1: time every kernel with HIP events (sim_read SIM_READ_TIMING) */
+    uint64_t debug_cap;            /* entries per stage log (0 = 1 << 20) */
+    void *hip_stream;              /* hipStream_t to run on; NULL = the null stream */
+} sim_config;
+
+/* Creates a simulation with n slots.  species[i] in {A, B, C, FREE, RESERVED};
+ * pos is n*dim doubles (slot-major, ignored for FREE/RESERVED); partner[i] is
+ * the reserved slot of C slot i (may be NULL if there is no C).  Host buffers
+ * are copied; the caller keeps ownership.  The library allocates all device
+ * memory.  Returns SIM_EINVAL for NaN or negative parameters, dim not 2 or 3,
+ * r_cut >= min(box)/2, or an inconsistent C/RESERVED map. */
+int sim_create(const sim_config *cfg, uint64_t n, const int32_t *species, const double *pos,
+               const uint32_t *partner, sim_t **out);
+
+/* Enqueues nsteps steps on the handle's stream.  Returns after the launches;
+ * per-step capacity checks are read back at the end of the call (one stream
+ * synchronisation), so SIM_ECAPACITY reports an overflow in any of the steps. */
+int sim_step(sim_t *h, uint32_t nsteps);
+
+/* What sim_read copies to the host buffer dst (cap_bytes long); *written gets
+ * the number of bytes.  Reads synchronise the handle's stream. */
+enum {
+    SIM_READ_POS = 0,       /* double[n*dim], by slot; NaN for FREE/RESERVED */
+    SIM_READ_SPECIES = 1,   /* int32[n], by slot */
+    SIM_READ_PARTNER = 2,   /* uint32[n]: reserved slot of each C, else 0xFFFFFFFF */
+    SIM_READ_COUNTS = 3,    /* int64[5]: number of A, B, C, FREE, RESERVED slots */
+    SIM_READ_STATS = 4,     /* uint64[SIM_STAT_N]: counters of the last step */
+    SIM_READ_STATS_SUM = 5, /* uint64[SIM_STAT_N]: counters summed since creation */
+    SIM_READ_DERIVED = 6,   /* double[8]: D_eff, tau, h, r_cut, a, p_uni, cell edge, step */
+    SIM_READ_DBG_MOVED = 7, /* double[n*dim]: positions after the move of the last step (debug) */
+    SIM_READ_DBG_PAIRS = 8, /* sim_dbg_pair[]: every pair within r_cut of the last step (debug) */
+    SIM_READ_DBG_PICKS = 9, /* sim_dbg_pick[]: the A-side choices (debug) */
+    SIM_READ_DBG_MATCHES = 10, /* sim_dbg_match[] (debug) */
+    SIM_READ_DBG_DISS = 11, /* sim_dbg_diss[] (debug) */
+    SIM_READ_DBG_CELLS = 12,/* uint32[n]: sort key (species * n_cells + cell) of each live slot after binning, else 0xFFFFFFFF (debug) */
+    SIM_READ_TIMING = 13,   /* sim_kernel_time[SIM_K_N]: accumulated kernel times (timing) */
+    SIM_READ_GRID = 14      /* int64[4]: cells per edge x, y, z and total cells */
+};
+
+enum {
+    SIM_STAT_PAIRS = 0, SIM_STAT_CAND, SIM_STAT_OVERLAP, SIM_STAT_R0CLAMP, SIM_STAT_PICKS,
+    SIM_STAT_MATCHES, SIM_STAT_REACT, SIM_STAT_DECAY, SIM_STAT_GEMINATE, SIM_STAT_ATTEMPTS,
+    SIM_STAT_BOUND, SIM_STAT_NEAR, SIM_STAT_CAND_OVERFLOW, SIM_STAT_N
+};
+
+typedef struct { uint32_t i, j; double R, R0, p; uint32_t draw; int32_t cand; } sim_dbg_pair;
+typedef struct { uint32_t i, j; double p; } sim_dbg_pick;
+typedef struct { uint32_t i, j; int32_t reacted; uint32_t attempts; double Rpp, preac; } sim_dbg_match;
+typedef struct { uint32_t c, j; int32_t decayed, recombined; uint32_t attempts, pad; double Rpp, preac; } sim_dbg_diss;
+
+enum {
+    SIM_K_MOVE = 0, SIM_K_SCAN, SIM_K_SCATTER, SIM_K_PAIRS, SIM_K_SELECT, SIM_K_REACT,
+    SIM_K_DISSOCIATE, SIM_K_FINISH, SIM_K_N
+};
+typedef struct { double ms; uint64_t launches; } sim_kernel_time;
+
+int sim_read(sim_t *h, int what, void *dst, uint64_t cap_bytes, uint64_t *written);
+
+/* Replaces the state (same layout as sim_create) and sets the step counter;
+ * n must equal the handle's slot count. */
+int sim_load_state(sim_t *h, uint64_t step, const int32_t *species, const double *pos, const uint32_t *partner);
+
+/* Releases all device memory of the handle; NULL is accepted. */
+int sim_destroy(sim_t *h);
+
+/* Human-readable description of the last error on h (thread-local if h is NULL). */
+const char *sim_last_error(const sim_t *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

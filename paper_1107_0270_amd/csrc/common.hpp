@@ -1,0 +1,161 @@
+// Shared types of the gfx950 Green's-function Brownian-dynamics library:
+// particle records, kernel parameters, device counters and the Philox4x32-10
+// counter-based generator (Salmon et al., SC'11).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gfbd {
+
+typedef uint32_t u32;
+typedef uint64_t u64;
+
+// Species code held in the top three bits of a record's meta word; the low
+// 29 bits hold the slot.
+constexpr u32 SP_A = 0, SP_B = 1, SP_C = 2, SP_DEAD = 7;
+constexpr u32 SLOT_MASK = (1u << 29) - 1;
+constexpr u32 NOSLOT = 0xFFFFFFFFu;
+__host__ __device__ inline u32 meta_make(u32 sp, u32 slot) { return (sp << 29) | slot; }
+__host__ __device__ inline u32 meta_sp(u32 m) { return m >> 29; }
+__host__ __device__ inline u32 meta_slot(u32 m) { return m & SLOT_MASK; }
+
+// Counter word 3: tag in the low byte, rejection-attempt index above it.
+enum : u32 {
+    TAG_MOVE = 1, TAG_ENC = 2, TAG_SELA = 3, TAG_SELB = 4, TAG_PROP = 5, TAG_REAC = 6,
+    TAG_UNI = 7, TAG_DPROP = 8, TAG_DIR = 9, TAG_GEM = 10
+};
+
+// Arithmetic of the pair probability: binary64 throughout, binary32, or
+// binary32 with binary64 separations and exponent arguments.
+enum { PM_F64 = 0, PM_F32 = 1, PM_F32NC = 2 };
+
+struct Key {
+    u32 k0, k1;
+};
+
+// Philox4x32-10: ten S-P rounds with multipliers 0xD2511F53, 0xCD9E8D57 and
+// the Weyl key increments 0x9E3779B9, 0xBB67AE85.
+__device__ __forceinline__ uint4 philox(u32 c0, u32 c1, u32 c2, u32 c3, Key k)
+{
+    u32 k0 = k.k0, k1 = k.k1;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const u32 hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const u32 hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        const u32 n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// Uniform (w + 1/2) 2^-32 in (0, 1), exact in binary64.
+__device__ __forceinline__ double u01(u32 w) { return ((double)w + 0.5) * 0x1p-32; }
+
+// The Bernoulli rule "xi < p" with xi = u01(w), evaluated exactly.
+__device__ __forceinline__ bool below(u32 w, double p) { return ((double)w + 0.5) < p * 0x1p32; }
+
+// Particle record: three coordinates and a meta word in the fourth lane
+// (z is 0 in 2D).  16 bytes in binary32, 32 bytes in binary64.
+template <class T> struct alignas(4 * sizeof(T)) Rec {
+    T x, y, z, w;
+};
+
+__host__ __device__ inline u32 rec_meta(const Rec<float> &r)
+{
+    union { float f; u32 u; } c;
+    c.f = r.w;
+    return c.u;
+}
+__host__ __device__ inline u32 rec_meta(const Rec<double> &r)
+{
+    union { double f; u64 u; } c;
+    c.f = r.w;
+    return (u32)c.u;
+}
+__host__ __device__ inline void rec_set_meta(Rec<float> &r, u32 m)
+{
+    union { float f; u32 u; } c;
+    c.u = m;
+    r.w = c.f;
+}
+__host__ __device__ inline void rec_set_meta(Rec<double> &r, u32 m)
+{
+    union { double f; u64 u; } c;
+    c.u = m;
+    r.w = c.f;
+}
+
+constexpr int MAXTERMS = 32;
+
+// Everything a kernel needs to know about the model and the grid.  Passed by
+// value; derived once on the host in binary64.
+struct Params {
+    int dim;
+    int bc;          // 0 absorbing, 1 reflecting, 2 radiation
+    int reversible;  // k_off > 0
+    int n_terms;     // 2D expansion order
+    double L[3], Lh[3];
+    double cs[3];    // cells per um along each axis (n / L)
+    int nc[3];
+    u32 n_cells, n_keys;
+    double sd[3];    // sqrt(2 D dt) of A, B, C
+    double a, inv_a, tau, inv_tau, sqrt_tau, hh;
+    double rcut, rcut2;
+    float rcut2f, rcut2f_wide, inv_af, inv_tauf, Lf[3], Lhf[3];
+    double fA, fB;   // D_A / D_eff, D_B / D_eff
+    double p_uni;    // 1 - exp(-k_off dt)
+    Key key;
+    u32 cap;
+    u32 cap_picks, cap_ovf_cand;
+    u32 debug;
+    u32 dbg_cap;
+    const double *g2c;  // 2D constants: a_k(0), Q_abs, Q_ref, Q_rad (4 x (MAXTERMS+1))
+};
+
+enum {
+    ST_PAIRS = 0, ST_CAND, ST_OVERLAP, ST_R0CLAMP, ST_PICKS, ST_MATCHES, ST_REACT, ST_DECAY,
+    ST_GEMINATE, ST_ATTEMPTS, ST_BOUND, ST_NEAR, ST_CAND_OVERFLOW, ST_N
+};
+
+enum { ERR_PICKS = 1, ERR_OVF = 2, ERR_OVF_CAND = 4, ERR_APPEND = 8 };
+
+// Device-resident counters; the work sizes of the data-dependent stages live
+// here so that no stage needs the host to learn a count.
+struct Counters {
+    u32 n_rec;      // records in the current buffer (sorted + appended)
+    u32 n_live;     // records placed by the last binning
+    u32 n_picks;
+    u32 n_matches;
+    u32 n_append;
+    u32 n_ovf;      // A particles with more candidates than fit in registers
+    u32 n_ovf_cand; // candidates written by the overflow pass
+    u32 err;
+    u32 n_dbg[4];   // pairs, picks, matches, dissociations logged this step
+    u32 pad[4];
+    u64 stats[ST_N];
+    u64 stats_last[ST_N];
+    u64 stats_sum[ST_N];
+};
+
+struct Pick {
+    u32 a_idx, b_idx, a_slot, b_slot;
+    double p;
+};
+
+struct Match {
+    u32 a_idx, b_idx;
+};
+
+// Debug log entries (same layout as the public sim_dbg_* structs).
+struct DbgPair { u32 i, j; double R, R0, p; u32 draw; int cand; };
+struct DbgPick { u32 i, j; double p; };
+struct DbgMatch { u32 i, j; int reacted; u32 attempts; double Rpp, preac; };
+struct DbgDiss { u32 c, j; int decayed, recombined; u32 attempts, pad; double Rpp, preac; };
+
+} // namespace gfbd

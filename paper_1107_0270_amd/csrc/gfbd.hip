@@ -1,0 +1,647 @@
+// Host side of the gfx950 Green's-function BD library: the C-ABI of
+// include/gfbd.h, parameter derivation, device state and the launch sequence
+// of one step (Sec. 3 of Pruestel & Meier-Schellersheim, arXiv:1107.0270).
+#include "../../include/gfbd.h"
+#include "kernels.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace gfbd;
+
+namespace {
+
+thread_local std::string g_err;
+
+// ---------------------------------------------------------------------------
+// Host numerics for the derived parameters (binary64).
+// ---------------------------------------------------------------------------
+double h_erfcx(double x)
+{
+    if (x < 26.0) return std::exp(x * x) * std::erfc(x);
+    // large-argument series 1/(x sqrt(pi)) (1 - 1/(2x^2) + 3/(4x^4) - 15/(8x^6) + 105/(16x^8))
+    const double t = 1.0 / (2.0 * x * x);
+    return (1.0 - t * (1.0 - 3.0 * t * (1.0 - 5.0 * t * (1.0 - 7.0 * t)))) / (x * 1.77245385090551602730);
+}
+
+// 1 - S(tau | R0): 3D absorbing erfc(u0)/R0; 3D radiation
+// (h/(1+h)) [erfc(u0) - e^{-u0^2} erfcx(u0 + (1+h) sqrt tau)]/R0; 2D the
+// planar bound erfc(u0).  u0 = (R0 - 1)/(2 sqrt tau).
+double h_loss(int dim, int bc, double R0, double tau, double hh)
+{
+    const double st = std::sqrt(tau), u0 = (R0 - 1.0) / (2.0 * st);
+    if (dim == 2) return std::erfc(u0);
+    if (bc == SIM_BC_RADIATION) {
+        const double kap = 1.0 + hh;
+        return (hh / kap) * (std::erfc(u0) - std::exp(-u0 * u0) * h_erfcx(u0 + kap * st)) / R0;
+    }
+    return std::erfc(u0) / R0;
+}
+
+// Cut-off: 1 - S(dt | r_cut) = eps (Sec. 3, Details), by bisection on R >= 1.
+double h_rcut(int dim, int bc, double a, double tau, double hh, double eps)
+{
+    if (h_loss(dim, bc, 1.0, tau, hh) <= eps) return a;
+    double lo = 1.0, hi = 2.0;
+    while (h_loss(dim, bc, hi, tau, hh) > eps) hi = 1.0 + 2.0 * (hi - 1.0);
+    for (int it = 0; it < 300; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        (h_loss(dim, bc, mid, tau, hh) > eps ? lo : hi) = mid;
+    }
+    return a * hi;
+}
+
+// Power-series quotient z = x / y, truncated after n.
+void h_series_div(const double *x, const double *y, int n, double *z)
+{
+    for (int k = 0; k <= n; ++k) {
+        double s = x[k];
+        for (int m = 1; m <= k; ++m) s -= y[m] * z[k - m];
+        z[k] = s / y[0];
+    }
+}
+
+// 2D constants: a_k(0) and the R-independent quotient series of the three
+// boundary components (Sec. 4.2): Abar_0/A_0, Abar_1/A_1 and
+// (Abar_1 - h s Abar_0)/(A_1 + h s A_0).
+void h_g2_constants(double hh, double *out)
+{
+    const int n = MAXTERMS;
+    double a0[MAXTERMS + 1], a1[MAXTERMS + 1], b0[MAXTERMS + 1], b1[MAXTERMS + 1], nu[MAXTERMS + 1], de[MAXTERMS + 1];
+    a0[0] = a1[0] = 1.0;
+    for (int k = 1; k <= n; ++k) {
+        const double odd = 2.0 * k - 1.0;
+        a0[k] = a0[k - 1] * (0.0 - odd * odd) / (8.0 * k);
+        a1[k] = a1[k - 1] * (4.0 - odd * odd) / (8.0 * k);
+    }
+    for (int k = 0; k <= n; ++k) {
+        b0[k] = (k % 2 ? -a0[k] : a0[k]);
+        b1[k] = (k % 2 ? -a1[k] : a1[k]);
+        nu[k] = b1[k] - (k ? hh * b0[k - 1] : 0.0);
+        de[k] = a1[k] + (k ? hh * a0[k - 1] : 0.0);
+    }
+    std::memcpy(out, a0, sizeof(a0));
+    h_series_div(b0, a0, n, out + (n + 1));
+    h_series_div(b1, a1, n, out + 2 * (n + 1));
+    h_series_div(nu, de, n, out + 3 * (n + 1));
+}
+
+template <class T> T h_wrap_store(double y, double L)
+{
+    if (y < 0.0) y += L;
+    else if (y >= L) y -= L;
+    if (!(y >= 0.0 && y < L)) {
+        y -= L * std::floor(y / L);
+        if (!(y >= 0.0 && y < L)) y = 0.0;
+    }
+    T v = (T)y;
+    if ((double)v >= L) v = (T)0;
+    return v;
+}
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// The handle.
+// ---------------------------------------------------------------------------
+struct sim {
+    std::string err;
+    virtual ~sim() {}
+    virtual int step(uint32_t n) = 0;
+    virtual int read(int what, void *dst, uint64_t cap, uint64_t *written) = 0;
+    virtual int load(uint64_t step, const int32_t *sp, const double *pos, const uint32_t *partner) = 0;
+    int fail(int code, const std::string &msg)
+    {
+        err = msg;
+        g_err = msg;
+        return code;
+    }
+};
+
+namespace {
+
+#define HIPCHECK(expr)                                                                          \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return fail(SIM_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+struct Model {
+    int dim, prec, bc;
+    double box[3], dt, D[3], sigma, kappa, k_off, eps, rcut_req, cell_req;
+    uint64_t seed;
+    uint32_t replica;
+    int n_terms;
+    uint32_t debug, timing;
+    uint64_t dbg_cap;
+    hipStream_t stream;
+};
+
+template <int DIM, class T, int PM> struct Engine final : sim {
+    Model M;
+    Params P;
+    uint64_t n = 0, stepno = 0;
+    int cur = 0;
+    uint32_t maxA = 0, maxC = 0, nb_scan = 0;
+    double cell_edge = 0.0;
+    // device memory
+    Rec<T> *rec[2] = {nullptr, nullptr};
+    u32 *rank = nullptr, *cnt = nullptr, *start = nullptr, *bsum = nullptr, *partner = nullptr;
+    Pick *picks = nullptr;
+    u64 *head = nullptr;
+    u32 *next = nullptr, *ovf = nullptr;
+    OvfCand *ovf_cand = nullptr;
+    Match *matches = nullptr;
+    Counters *ctr = nullptr;
+    double *g2c = nullptr;
+    double *g_pos = nullptr, *dbg_moved = nullptr;
+    int *g_sp = nullptr;
+    u32 *dbg_cells = nullptr;
+    DbgPair *dbg_pairs = nullptr;
+    DbgPick *dbg_picks = nullptr;
+    DbgMatch *dbg_matches = nullptr;
+    DbgDiss *dbg_diss = nullptr;
+    std::vector<void *> allocs;
+    // timing
+    struct EvPair { hipEvent_t a, b; int k; };
+    std::vector<EvPair> ev_pool, ev_used;
+    double k_ms[SIM_K_N] = {0};
+    uint64_t k_launches[SIM_K_N] = {0};
+
+    ~Engine() override
+    {
+        if (M.stream || true) (void)hipStreamSynchronize(M.stream);
+        for (void *p : allocs) (void)hipFree(p);
+        for (auto &e : ev_pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+        for (auto &e : ev_used) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    }
+
+    template <class U> int alloc(U *&p, uint64_t count)
+    {
+        void *q = nullptr;
+        if (count == 0) count = 1;
+        if (hipMalloc(&q, count * sizeof(U)) != hipSuccess) return fail(SIM_ENOMEM, "device allocation failed");
+        allocs.push_back(q);
+        p = (U *)q;
+        return SIM_OK;
+    }
+
+    int init(const Model &m, uint64_t nslots, const int32_t *sp, const double *pos, const uint32_t *pt)
+    {
+        M = m;
+        n = nslots;
+        std::memset(&P, 0, sizeof(P));
+        P.dim = DIM;
+        P.bc = M.bc;
+        P.reversible = M.k_off > 0.0;
+        P.n_terms = M.n_terms;
+        const double Deff = M.D[0] + M.D[1];
+        P.a = M.sigma;
+        P.inv_a = 1.0 / M.sigma;
+        P.tau = Deff * M.dt / (M.sigma * M.sigma);
+        P.inv_tau = 1.0 / P.tau;
+        P.sqrt_tau = std::sqrt(P.tau);
+        if (M.bc == SIM_BC_RADIATION)
+            P.hh = DIM == 3 ? M.kappa / (4.0 * M_PI * M.sigma * Deff) : M.kappa / (2.0 * M_PI * Deff);
+        P.rcut = M.rcut_req > 0.0 ? M.rcut_req : h_rcut(DIM, M.bc, M.sigma, P.tau, P.hh, M.eps);
+        P.rcut2 = P.rcut * P.rcut;
+        P.rcut2f = (float)P.rcut2;
+        P.rcut2f_wide = (float)(P.rcut2 * (1.0 + 1e-4));
+        P.inv_af = (float)P.inv_a;
+        P.inv_tauf = (float)P.inv_tau;
+        P.fA = M.D[0] / Deff;
+        P.fB = M.D[1] / Deff;
+        P.p_uni = -std::expm1(-M.k_off * M.dt);
+        P.key.k0 = (u32)M.seed;
+        P.key.k1 = (u32)(M.seed >> 32) ^ M.replica;
+        for (int s = 0; s < 3; ++s) P.sd[s] = std::sqrt(2.0 * M.D[s] * M.dt);
+        double Lmin = 1e300;
+        for (int k = 0; k < DIM; ++k) Lmin = std::min(Lmin, M.box[k]);
+        if (!(P.rcut < 0.5 * Lmin)) return fail(SIM_EINVAL, "r_cut must be below half the smallest box edge");
+        const double smax = std::max(P.sd[0], std::max(P.sd[1], P.sd[2]));
+        if (!(8.0 * smax < 0.5 * Lmin)) return fail(SIM_EINVAL, "displacement per step too large for the box");
+        // counts
+        uint64_t nA = 0, nB = 0, nC = 0;
+        for (uint64_t i = 0; i < n; ++i) {
+            nA += sp[i] == SIM_SP_A;
+            nB += sp[i] == SIM_SP_B;
+            nC += sp[i] == SIM_SP_C;
+        }
+        // A and C counts change with reactions and state loads; size by the slot count
+        maxA = (u32)n;
+        maxC = (u32)n;
+        // grid: cells of edge >= r_cut, about one B per cell unless requested
+        double vol = 1.0;
+        for (int k = 0; k < DIM; ++k) vol *= M.box[k];
+        double c = M.cell_req > 0.0 ? M.cell_req : std::pow(vol / (double)std::max<uint64_t>(nB + nC, 1), 1.0 / DIM);
+        c = std::max(c, P.rcut);
+        uint64_t ncell = 1;
+        cell_edge = 1e300;
+        for (int k = 0; k < 3; ++k) {
+            int m_ = 1;
+            if (k < DIM) {
+                const double f = std::floor(M.box[k] / c);
+                m_ = f > 2048.0 ? 2048 : (int)f;
+                if (m_ < 3) m_ = 1;
+                cell_edge = std::min(cell_edge, M.box[k] / m_);
+            }
+            P.nc[k] = m_;
+            P.L[k] = k < DIM ? M.box[k] : 1.0;
+            P.Lh[k] = 0.5 * P.L[k];
+            P.Lf[k] = (float)P.L[k];
+            P.Lhf[k] = (float)P.Lh[k];
+            P.cs[k] = m_ / P.L[k];
+            ncell *= (uint64_t)m_;
+        }
+        if (ncell > (1ull << 28)) return fail(SIM_EUNSUPPORTED, "too many cells");
+        P.n_cells = (u32)ncell;
+        P.n_keys = 3u * P.n_cells;
+        P.cap = (u32)n;
+        P.cap_picks = std::max<u32>(maxA, 1);
+        P.cap_ovf_cand = (u32)std::max<uint64_t>(1u << 16, n / 4);
+        P.debug = M.debug;
+        P.dbg_cap = (u32)M.dbg_cap;
+        nb_scan = (P.n_keys + SCAN_TILE - 1) / SCAN_TILE;
+        // device buffers
+        int rc;
+        if ((rc = alloc(rec[0], n)) || (rc = alloc(rec[1], n)) || (rc = alloc(rank, n)) || (rc = alloc(cnt, P.n_keys)) ||
+            (rc = alloc(start, P.n_keys + 1)) || (rc = alloc(bsum, nb_scan)) || (rc = alloc(partner, n)) ||
+            (rc = alloc(picks, P.cap_picks)) || (rc = alloc(head, n)) || (rc = alloc(next, P.cap_picks)) ||
+            (rc = alloc(ovf, maxA)) || (rc = alloc(ovf_cand, P.cap_ovf_cand)) || (rc = alloc(matches, P.cap_picks)) ||
+            (rc = alloc(ctr, 1)) || (rc = alloc(g2c, 4 * (MAXTERMS + 1))) || (rc = alloc(g_pos, n * DIM)) ||
+            (rc = alloc(g_sp, n)))
+            return rc;
+        if (M.debug) {
+            if ((rc = alloc(dbg_moved, n * DIM)) || (rc = alloc(dbg_cells, n)) || (rc = alloc(dbg_pairs, M.dbg_cap)) ||
+                (rc = alloc(dbg_picks, M.dbg_cap)) || (rc = alloc(dbg_matches, M.dbg_cap)) || (rc = alloc(dbg_diss, M.dbg_cap)))
+                return rc;
+        }
+        HIPCHECK(hipMemsetAsync(cnt, 0, sizeof(u32) * P.n_keys, M.stream));
+        HIPCHECK(hipMemsetAsync(head, 0, sizeof(u64) * n, M.stream));
+        double g2h[4 * (MAXTERMS + 1)];
+        h_g2_constants(P.hh, g2h);
+        HIPCHECK(hipMemcpyAsync(g2c, g2h, sizeof(g2h), hipMemcpyHostToDevice, M.stream));
+        P.g2c = g2c;
+        return load(0, sp, pos, pt);
+    }
+
+    int load(uint64_t step0, const int32_t *sp, const double *pos, const uint32_t *pt) override
+    {
+        std::vector<Rec<T>> h(n);
+        std::vector<u32> hp(n, NOSLOT);
+        uint64_t live = 0;
+        for (uint64_t i = 0; i < n; ++i) {
+            if (sp[i] > SIM_SP_C) continue;
+            Rec<T> r;
+            r.x = h_wrap_store<T>(pos[i * DIM + 0], M.box[0]);
+            r.y = h_wrap_store<T>(pos[i * DIM + 1], M.box[1]);
+            r.z = DIM == 3 ? h_wrap_store<T>(pos[i * DIM + 2], M.box[2]) : (T)0;
+            rec_set_meta(r, meta_make((u32)sp[i], (u32)i));
+            h[live++] = r;
+            if (sp[i] == SIM_SP_C) hp[i] = pt[i];
+        }
+        HIPCHECK(hipMemcpyAsync(rec[0], h.data(), sizeof(Rec<T>) * live, hipMemcpyHostToDevice, M.stream));
+        HIPCHECK(hipMemcpyAsync(partner, hp.data(), sizeof(u32) * n, hipMemcpyHostToDevice, M.stream));
+        Counters c;
+        std::memset(&c, 0, sizeof(c));
+        c.n_rec = (u32)live;
+        c.n_live = (u32)live;
+        HIPCHECK(hipMemcpyAsync(ctr, &c, sizeof(c), hipMemcpyHostToDevice, M.stream));
+        HIPCHECK(hipMemsetAsync(head, 0, sizeof(u64) * n, M.stream));  // no chain survives a reload
+        HIPCHECK(hipStreamSynchronize(M.stream));
+        cur = 0;
+        stepno = step0;
+        return SIM_OK;
+    }
+
+    template <class F> void launch(int k, F &&f)
+    {
+        if (!M.timing) {
+            f();
+            return;
+        }
+        EvPair e;
+        if (ev_pool.empty()) {
+            (void)hipEventCreate(&e.a);
+            (void)hipEventCreate(&e.b);
+        } else {
+            e = ev_pool.back();
+            ev_pool.pop_back();
+        }
+        e.k = k;
+        (void)hipEventRecord(e.a, M.stream);
+        f();
+        (void)hipEventRecord(e.b, M.stream);
+        ev_used.push_back(e);
+    }
+
+    static u32 grid_for(uint64_t work, u32 maxg) { return (u32)std::max<uint64_t>(1, std::min<uint64_t>((work + BLOCK - 1) / BLOCK, maxg)); }
+
+    int one_step()
+    {
+        const u32 s = (u32)stepno;
+        hipStream_t st = M.stream;
+        Rec<T> *in = rec[cur], *out = rec[cur ^ 1];
+        const u32 g_all = grid_for(n, 8192);
+        launch(SIM_K_MOVE, [&] { k_move_count<DIM, T><<<g_all, BLOCK, 0, st>>>(P, in, rank, cnt, ctr, s); });
+        launch(SIM_K_SCAN, [&] {
+            k_scan_reduce<<<nb_scan, BLOCK, 0, st>>>(cnt, P.n_keys, bsum);
+            k_scan_top<<<1, BLOCK, 0, st>>>(bsum, nb_scan);
+            k_scan_down<<<nb_scan, BLOCK, 0, st>>>(cnt, P.n_keys, bsum, start, ctr);
+        });
+        launch(SIM_K_SCATTER, [&] { k_scatter<DIM, T><<<g_all, BLOCK, 0, st>>>(P, in, rank, start, out, ctr, s); });
+        cur ^= 1;
+        if (M.debug) {
+            k_fill<<<grid_for(n * DIM, 2048), BLOCK, 0, st>>>(dbg_moved, n * DIM, (int *)dbg_cells, (u32)n);
+            k_gather<DIM, T><<<g_all, BLOCK, 0, st>>>(out, partner, ctr, 1, dbg_moved, nullptr, (u32)n);
+            k_dbg_cells<<<g_all, BLOCK, 0, st>>>(P, std::is_same<T, float>::value ? (const Rec<float> *)out : nullptr,
+                                                 std::is_same<T, double>::value ? (const Rec<double> *)out : nullptr, start, ctr,
+                                                 dbg_cells);
+        }
+        launch(SIM_K_PAIRS, [&] {
+            k_pairs<DIM, T, PM><<<grid_for(maxA, 8192), BLOCK, 0, st>>>(P, out, start, picks, ovf, ctr, dbg_pairs, s);
+            k_pairs_overflow<DIM, T, PM><<<64, BLOCK, 0, st>>>(P, out, start, ovf, ovf_cand, picks, ctr, s);
+        });
+        launch(SIM_K_SELECT, [&] {
+            k_link<<<grid_for(P.cap_picks, 1024), BLOCK, 0, st>>>(picks, head, next, ctr, P, s);
+            k_select_b<<<grid_for(P.cap_picks, 1024), BLOCK, 0, st>>>(P, picks, head, next, matches, ctr, dbg_picks, s);
+        });
+        launch(SIM_K_REACT, [&] { k_react<DIM, T><<<grid_for(P.cap_picks, 1024), BLOCK, 0, st>>>(P, out, matches, partner, ctr, dbg_matches, s); });
+        if (P.reversible)
+            launch(SIM_K_DISSOCIATE, [&] { k_dissociate<DIM, T><<<grid_for(maxC, 4096), BLOCK, 0, st>>>(P, out, start, partner, ctr, dbg_diss, s); });
+        launch(SIM_K_FINISH, [&] { k_finish<<<1, 1, 0, st>>>(ctr); });
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(SIM_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+        ++stepno;
+        return SIM_OK;
+    }
+
+    int step(uint32_t nsteps) override
+    {
+        for (uint32_t i = 0; i < nsteps; ++i) {
+            const int rc = one_step();
+            if (rc) return rc;
+        }
+        u32 errflags = 0;
+        HIPCHECK(hipMemcpyAsync(&errflags, &ctr->err, sizeof(u32), hipMemcpyDeviceToHost, M.stream));
+        HIPCHECK(hipStreamSynchronize(M.stream));
+        if (M.timing) {
+            for (auto &e : ev_used) {
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e.a, e.b);
+                k_ms[e.k] += ms;
+                k_launches[e.k] += 1;
+                ev_pool.push_back(e);
+            }
+            ev_used.clear();
+        }
+        if (errflags) {
+            HIPCHECK(hipMemsetAsync(&ctr->err, 0, sizeof(u32), M.stream));
+            return fail(SIM_ECAPACITY, "per-step buffer overflow (flags " + std::to_string(errflags) + ")");
+        }
+        return SIM_OK;
+    }
+
+    int copy_out(const void *src, uint64_t bytes, void *dst, uint64_t cap, uint64_t *written)
+    {
+        if (bytes > cap) return fail(SIM_EINVAL, "destination buffer too small");
+        HIPCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, M.stream));
+        HIPCHECK(hipStreamSynchronize(M.stream));
+        if (written) *written = bytes;
+        return SIM_OK;
+    }
+
+    int read(int what, void *dst, uint64_t cap, uint64_t *written) override
+    {
+        hipStream_t st = M.stream;
+        const u32 g_all = grid_for(n, 8192);
+        Counters c;
+        HIPCHECK(hipMemcpyAsync(&c, ctr, sizeof(c), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        switch (what) {
+        case SIM_READ_POS:
+        case SIM_READ_SPECIES:
+        case SIM_READ_COUNTS: {
+            k_fill<<<grid_for(n * DIM, 2048), BLOCK, 0, st>>>(g_pos, n * DIM, g_sp, (u32)n);
+            k_gather<DIM, T><<<g_all, BLOCK, 0, st>>>(rec[cur], partner, ctr, 0, g_pos, g_sp, (u32)n);
+            if (what == SIM_READ_POS) return copy_out(g_pos, sizeof(double) * n * DIM, dst, cap, written);
+            if (what == SIM_READ_SPECIES) return copy_out(g_sp, sizeof(int) * n, dst, cap, written);
+            std::vector<int> h(n);
+            HIPCHECK(hipMemcpyAsync(h.data(), g_sp, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+            HIPCHECK(hipStreamSynchronize(st));
+            int64_t cnts[5] = {0, 0, 0, 0, 0};
+            for (int v : h) cnts[v] += 1;
+            if (cap < sizeof(cnts)) return fail(SIM_EINVAL, "destination buffer too small");
+            std::memcpy(dst, cnts, sizeof(cnts));
+            if (written) *written = sizeof(cnts);
+            return SIM_OK;
+        }
+        case SIM_READ_PARTNER: {
+            std::vector<u32> h(n);
+            std::vector<int> s_(n);
+            HIPCHECK(hipMemcpyAsync(h.data(), partner, sizeof(u32) * n, hipMemcpyDeviceToHost, st));
+            k_fill<<<grid_for(n * DIM, 2048), BLOCK, 0, st>>>(g_pos, n * DIM, g_sp, (u32)n);
+            k_gather<DIM, T><<<g_all, BLOCK, 0, st>>>(rec[cur], partner, ctr, 0, nullptr, g_sp, (u32)n);
+            HIPCHECK(hipMemcpyAsync(s_.data(), g_sp, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+            HIPCHECK(hipStreamSynchronize(st));
+            for (uint64_t i = 0; i < n; ++i)
+                if (s_[i] != SIM_SP_C) h[i] = NOSLOT;
+            if (cap < sizeof(u32) * n) return fail(SIM_EINVAL, "destination buffer too small");
+            std::memcpy(dst, h.data(), sizeof(u32) * n);
+            if (written) *written = sizeof(u32) * n;
+            return SIM_OK;
+        }
+        case SIM_READ_STATS:
+        case SIM_READ_STATS_SUM: {
+            const u64 *src = what == SIM_READ_STATS ? c.stats_last : c.stats_sum;
+            if (cap < sizeof(u64) * SIM_STAT_N) return fail(SIM_EINVAL, "destination buffer too small");
+            std::memcpy(dst, src, sizeof(u64) * SIM_STAT_N);
+            if (written) *written = sizeof(u64) * SIM_STAT_N;
+            return SIM_OK;
+        }
+        case SIM_READ_DERIVED: {
+            const double d[8] = {M.D[0] + M.D[1], P.tau, P.hh, P.rcut, P.a, P.p_uni, cell_edge, (double)stepno};
+            if (cap < sizeof(d)) return fail(SIM_EINVAL, "destination buffer too small");
+            std::memcpy(dst, d, sizeof(d));
+            if (written) *written = sizeof(d);
+            return SIM_OK;
+        }
+        case SIM_READ_GRID: {
+            const int64_t g[4] = {P.nc[0], P.nc[1], P.nc[2], (int64_t)P.n_cells};
+            if (cap < sizeof(g)) return fail(SIM_EINVAL, "destination buffer too small");
+            std::memcpy(dst, g, sizeof(g));
+            if (written) *written = sizeof(g);
+            return SIM_OK;
+        }
+        case SIM_READ_TIMING: {
+            sim_kernel_time t[SIM_K_N];
+            for (int k = 0; k < SIM_K_N; ++k) {
+                t[k].ms = k_ms[k];
+                t[k].launches = k_launches[k];
+                k_ms[k] = 0.0;
+                k_launches[k] = 0;
+            }
+            if (cap < sizeof(t)) return fail(SIM_EINVAL, "destination buffer too small");
+            std::memcpy(dst, t, sizeof(t));
+            if (written) *written = sizeof(t);
+            return SIM_OK;
+        }
+        default:
+            break;
+        }
+        if (!M.debug) return fail(SIM_ESTATE, "debug logs need sim_config.debug = 1");
+        switch (what) {
+        case SIM_READ_DBG_MOVED: return copy_out(dbg_moved, sizeof(double) * n * DIM, dst, cap, written);
+        case SIM_READ_DBG_CELLS: return copy_out(dbg_cells, sizeof(u32) * n, dst, cap, written);
+        case SIM_READ_DBG_PAIRS: return copy_out(dbg_pairs, sizeof(DbgPair) * std::min<uint64_t>(c.n_dbg[0], M.dbg_cap), dst, cap, written);
+        case SIM_READ_DBG_PICKS: return copy_out(dbg_picks, sizeof(DbgPick) * std::min<uint64_t>(c.n_dbg[1], M.dbg_cap), dst, cap, written);
+        case SIM_READ_DBG_MATCHES: return copy_out(dbg_matches, sizeof(DbgMatch) * std::min<uint64_t>(c.n_dbg[2], M.dbg_cap), dst, cap, written);
+        case SIM_READ_DBG_DISS: return copy_out(dbg_diss, sizeof(DbgDiss) * std::min<uint64_t>(c.n_dbg[3], M.dbg_cap), dst, cap, written);
+        default: return fail(SIM_EINVAL, "unknown read selector");
+        }
+    }
+};
+
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+int validate(const sim_config *cfg, uint64_t n, const int32_t *sp, const double *pos, const uint32_t *pt, Model &M)
+{
+    if (!cfg || !sp || !pos) { g_err = "null argument"; return SIM_EINVAL; }
+    if (n == 0 || n > SLOT_MASK) { g_err = "slot count must be in [1, 2^29)"; return SIM_EINVAL; }
+    if (cfg->dim != 2 && cfg->dim != 3) { g_err = "dim must be 2 or 3"; return SIM_EINVAL; }
+    if (cfg->precision < 0 || cfg->precision > 2) { g_err = "unknown precision"; return SIM_EINVAL; }
+    if (cfg->n_species != 3 || !cfg->species) { g_err = "exactly three species (A, B, C) are supported"; return SIM_EUNSUPPORTED; }
+    if (cfg->n_reactions != 1 || !cfg->reactions) { g_err = "exactly one reaction A + B <-> C is supported"; return SIM_EUNSUPPORTED; }
+    const sim_reaction &r = cfg->reactions[0];
+    if (r.a != 0 || r.b != 1 || r.c != 2) { g_err = "the reaction must be species 0 + 1 <-> 2"; return SIM_EUNSUPPORTED; }
+    if (r.bc < 0 || r.bc > 2) { g_err = "unknown boundary condition"; return SIM_EINVAL; }
+    if (!(std::isfinite(r.sigma) && r.sigma > 0.0) || !finite_nonneg(r.kappa) || !finite_nonneg(r.k_off)) {
+        g_err = "sigma must be > 0, kappa and k_off >= 0";
+        return SIM_EINVAL;
+    }
+    for (int s = 0; s < 3; ++s)
+        if (!finite_nonneg(cfg->species[s].D)) { g_err = "diffusion constants must be finite and >= 0"; return SIM_EINVAL; }
+    if (!(cfg->species[0].D + cfg->species[1].D > 0.0)) { g_err = "D_A + D_B must be > 0"; return SIM_EINVAL; }
+    if (!(std::isfinite(cfg->dt) && cfg->dt > 0.0)) { g_err = "dt must be > 0"; return SIM_EINVAL; }
+    for (int k = 0; k < cfg->dim; ++k) {
+        if (!(std::isfinite(cfg->box[k]) && cfg->box[k] > 0.0)) { g_err = "box edges must be > 0"; return SIM_EINVAL; }
+        if (cfg->precision != SIM_PREC_FP64 && (double)(float)cfg->box[k] != cfg->box[k]) {
+            g_err = "binary32 states need box edges exactly representable in binary32";
+            return SIM_EINVAL;
+        }
+    }
+    if (cfg->n_terms < 0 || cfg->n_terms > MAXTERMS) { g_err = "n_terms must be in [0, 32]"; return SIM_EINVAL; }
+    const double eps = cfg->eps_cut == 0.0 ? 1e-3 : cfg->eps_cut;
+    if (!(eps > 0.0 && eps < 1.0)) { g_err = "eps_cut must be in (0, 1)"; return SIM_EINVAL; }
+    if (!finite_nonneg(cfg->rcut) || !finite_nonneg(cfg->cell)) { g_err = "rcut and cell must be >= 0"; return SIM_EINVAL; }
+    // state
+    std::vector<int> owners(n, 0);
+    for (uint64_t i = 0; i < n; ++i) {
+        const int s = sp[i];
+        if (s < 0 || s > SIM_SP_RESERVED) { g_err = "unknown species code"; return SIM_EINVAL; }
+        if (s <= SIM_SP_C)
+            for (int k = 0; k < cfg->dim; ++k)
+                if (!std::isfinite(pos[i * cfg->dim + k])) { g_err = "non-finite position"; return SIM_EINVAL; }
+        if (s == SIM_SP_C) {
+            if (r.k_off > 0.0) {
+                if (!pt || pt[i] >= n || sp[pt[i]] != SIM_SP_RESERVED) { g_err = "each C needs a RESERVED partner slot"; return SIM_EINVAL; }
+                owners[pt[i]] += 1;
+            }
+        }
+    }
+    for (uint64_t i = 0; i < n; ++i)
+        if (sp[i] == SIM_SP_RESERVED && owners[i] != 1) { g_err = "each RESERVED slot must belong to exactly one C"; return SIM_EINVAL; }
+    M.dim = cfg->dim;
+    M.prec = cfg->precision;
+    M.bc = r.bc;
+    for (int k = 0; k < 3; ++k) M.box[k] = k < cfg->dim ? cfg->box[k] : 1.0;
+    M.dt = cfg->dt;
+    for (int s = 0; s < 3; ++s) M.D[s] = cfg->species[s].D;
+    M.sigma = r.sigma;
+    M.kappa = r.kappa;
+    M.k_off = r.k_off;
+    M.eps = eps;
+    M.rcut_req = cfg->rcut;
+    M.cell_req = cfg->cell;
+    M.seed = cfg->seed;
+    M.replica = cfg->replica;
+    M.n_terms = cfg->n_terms == 0 ? 12 : cfg->n_terms;
+    M.debug = cfg->debug;
+    M.timing = cfg->timing;
+    M.dbg_cap = cfg->debug_cap == 0 ? (1u << 20) : cfg->debug_cap;
+    M.stream = (hipStream_t)cfg->hip_stream;
+    return SIM_OK;
+}
+
+template <int DIM, class T, int PM>
+int make(const Model &M, uint64_t n, const int32_t *sp, const double *pos, const uint32_t *pt, sim_t **out)
+{
+    Engine<DIM, T, PM> *e = new (std::nothrow) Engine<DIM, T, PM>();
+    if (!e) { g_err = "host allocation failed"; return SIM_ENOMEM; }
+    const int rc = e->init(M, n, sp, pos, pt);
+    if (rc) {
+        g_err = e->err;
+        delete e;
+        return rc;
+    }
+    *out = e;
+    return SIM_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int sim_create(const sim_config *cfg, uint64_t n, const int32_t *species, const double *pos, const uint32_t *partner, sim_t **out)
+{
+    if (!out) { g_err = "null output handle"; return SIM_EINVAL; }
+    *out = nullptr;
+    Model M;
+    const int rc = validate(cfg, n, species, pos, partner, M);
+    if (rc) return rc;
+    if (M.dim == 3) {
+        if (M.prec == SIM_PREC_FP64) return make<3, double, PM_F64>(M, n, species, pos, partner, out);
+        if (M.prec == SIM_PREC_FP32) return make<3, float, PM_F32>(M, n, species, pos, partner, out);
+        return make<3, float, PM_F32NC>(M, n, species, pos, partner, out);
+    }
+    if (M.prec == SIM_PREC_FP64) return make<2, double, PM_F64>(M, n, species, pos, partner, out);
+    if (M.prec == SIM_PREC_FP32) return make<2, float, PM_F32>(M, n, species, pos, partner, out);
+    return make<2, float, PM_F32NC>(M, n, species, pos, partner, out);
+}
+
+int sim_step(sim_t *h, uint32_t nsteps)
+{
+    if (!h) { g_err = "null handle"; return SIM_EINVAL; }
+    return h->step(nsteps);
+}
+
+int sim_read(sim_t *h, int what, void *dst, uint64_t cap_bytes, uint64_t *written)
+{
+    if (!h || !dst) { g_err = "null argument"; return SIM_EINVAL; }
+    return h->read(what, dst, cap_bytes, written);
+}
+
+int sim_load_state(sim_t *h, uint64_t step, const int32_t *species, const double *pos, const uint32_t *partner)
+{
+    if (!h || !species || !pos) { g_err = "null argument"; return SIM_EINVAL; }
+    return h->load(step, species, pos, partner);
+}
+
+int sim_destroy(sim_t *h)
+{
+    delete h;
+    return SIM_OK;
+}
+
+const char *sim_last_error(const sim_t *h)
+{
+    if (h) return h->err.c_str();
+    return g_err.c_str();
+}
+
+} // extern "C"

@@ -1,0 +1,255 @@
+// Device-side Green's-function quantities of the coarse-grained BD step:
+// encounter and reaction probabilities (Secs. 2.2.1-2.2.4 with the 3D closed
+// forms of Sec. 4.1 and the 2D small-time expansions of Sec. 4.2) and the
+// radial propagator sampler (Sec. 2.2.2, Sec. 3 Details).
+#pragma once
+
+#include "common.hpp"
+
+namespace gfbd {
+
+constexpr double PI_D = 3.14159265358979323846;
+constexpr double SQRTPI_D = 1.77245385090551602730;
+
+// ---------------------------------------------------------------------------
+// 3D encounter probability 1 - g_abs/g_free.  With the two closed forms over
+// the same prefactor, and (R+R0-2)^2 - (R-R0)^2 = 4(R-1)(R0-1),
+// (R+R0)^2 - (R-R0)^2 = 4 R R0:
+//   p_enc = e^{-(R-1)(R0-1)/tau} (1 - e^{-(R+R0-1)/tau}) / (1 - e^{-R R0/tau}).
+// The three exponent arguments are formed in T2, the exponentials in T1.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double penc3_args(double e1, double e2, double e3)
+{
+    return exp(-e1) * expm1(-e2) / expm1(-e3);
+}
+__device__ __forceinline__ float penc3_args(float e1, float e2, float e3)
+{
+    return expf(-e1) * expm1f(-e2) / expm1f(-e3);
+}
+
+// 3D reaction probability (g_ref - g_rad)/(g_ref - g_abs): the free term and
+// the common factor e^{-w^2/4tau} cancel, leaving
+//   sqrt(pi tau) [kappa erfcx(z_kappa) - erfcx(z_1)] / (1 - sqrt(pi tau) erfcx(z_1)),
+// z_k = k sqrt(tau) + w/(2 sqrt(tau)), w = R + R0 - 2, kappa = 1 + h.
+__device__ inline double preac3(const Params &P, double R, double R0)
+{
+    const double w = R + R0 - 2.0, st = P.sqrt_tau, kap = 1.0 + P.hh;
+    const double z1 = st + w / (2.0 * st), zk = kap * st + w / (2.0 * st);
+    const double spt = SQRTPI_D * st;
+    return spt * (kap * erfcx(zk) - erfcx(z1)) / (1.0 - spt * erfcx(z1));
+}
+
+// ---------------------------------------------------------------------------
+// 2D: e^{-x} I_0(x); scaled repeated erfc integrals; expansion coefficients.
+// ---------------------------------------------------------------------------
+
+// Ascending series up to 20, the large-argument series e^x/sqrt(2 pi x)
+// sum |a_k(0)| x^-k above (cut at its smallest term).
+__device__ inline double i0e_d(double x)
+{
+    if (x <= 20.0) {
+        const double q = 0.25 * x * x;
+        double t = 1.0, s = 1.0;
+        for (int k = 1; k < 120; ++k) {
+            t *= q / (double)(k * k);
+            s += t;
+            if (t < 1e-18 * s) break;
+        }
+        return s * exp(-x);
+    }
+    double t = 1.0, s = 1.0;
+    const double ix = 1.0 / x;
+    for (int k = 1; k < 80; ++k) {
+        const double r = (2.0 * k - 1.0) * (2.0 * k - 1.0) * 0.125 * ix / (double)k;
+        if (r >= 1.0) break;
+        t *= r;
+        s += t;
+        if (t < 1e-18 * s) break;
+    }
+    return s * rsqrt(2.0 * PI_D * x);
+}
+
+// T_k = e^{x^2} i^{k-1}erfc(x) (2 sqrt tau)^k, k = 1..n, by the upward
+// recursion 2k i^k = i^{k-2} - 2x i^{k-1} (eq. iErf) started from
+// i^{-1} = 2/sqrt(pi) and i^0 = erfcx(x).
+__device__ inline void t_terms(double x, double two_st, int n, double *T)
+{
+    double im2 = 2.0 / SQRTPI_D, im1 = erfcx(x), pw = two_st;
+    T[1] = im1 * pw;
+    for (int k = 2; k <= n; ++k) {
+        const double ik = (im2 - 2.0 * x * im1) / (2.0 * (k - 1));
+        im2 = im1;
+        im1 = ik;
+        pw *= two_st;
+        T[k] = ik * pw;
+    }
+}
+
+// P_k: coefficients of A_0(s/R0) A_0(s/R), k = 0..n (a_k(0) from the table).
+__device__ inline void p_series(const double *a0, double R, double R0, int n, double *Pc)
+{
+    double x[MAXTERMS + 1], y[MAXTERMS + 1];
+    const double iR = 1.0 / R, iR0 = 1.0 / R0;
+    double px = 1.0, py = 1.0;
+    for (int k = 0; k <= n; ++k) {
+        x[k] = a0[k] * px;
+        y[k] = a0[k] * py;
+        px *= iR0;
+        py *= iR;
+    }
+    for (int k = 0; k <= n; ++k) {
+        double s = 0.0;
+        for (int m = 0; m <= k; ++m) s += x[m] * y[k - m];
+        Pc[k] = s;
+    }
+}
+
+// gamma_k = sum_m Q_m P_{k-m} for one boundary condition's quotient series Q.
+__device__ inline double gamma_k(const double *Q, const double *Pc, int k)
+{
+    double s = 0.0;
+    for (int m = 0; m <= k; ++m) s += Q[m] * Pc[k - m];
+    return s;
+}
+
+// 2D encounter probability -g_abs,bc / g_free with eq. smallTEabs:
+//   sqrt(tau/(R R0)) e^{-(R-1)(R0-1)/tau} [pi^{-1/2} + (1/2) sum gamma^abs_k T_k] / i0e(R R0/2tau).
+__device__ inline double penc2(const Params &P, double R, double R0)
+{
+    const int n = P.n_terms;
+    const double *a0 = P.g2c, *Qa = P.g2c + (MAXTERMS + 1);
+    double Pc[MAXTERMS + 1], T[MAXTERMS + 1];
+    p_series(a0, R, R0, n, Pc);
+    const double x = (R + R0 - 2.0) / (2.0 * P.sqrt_tau);
+    t_terms(x, 2.0 * P.sqrt_tau, n, T);
+    double S = 1.0 / SQRTPI_D;
+    for (int k = 1; k <= n; ++k) S += 0.5 * gamma_k(Qa, Pc, k) * T[k];
+    return sqrt(P.tau / (R * R0)) * exp(-(R - 1.0) * (R0 - 1.0) * P.inv_tau) * S / i0e_d(R * R0 * 0.5 * P.inv_tau);
+}
+
+// 2D reaction probability: free parts and the common factor cancel,
+//   sum (g^ref_k - g^rad_k) T_k / [4 pi^{-1/2} + sum (g^ref_k + g^abs_k) T_k].
+__device__ inline double preac2(const Params &P, double R, double R0)
+{
+    const int n = P.n_terms;
+    const double *a0 = P.g2c, *Qa = a0 + (MAXTERMS + 1), *Qf = a0 + 2 * (MAXTERMS + 1), *Qr = a0 + 3 * (MAXTERMS + 1);
+    double Pc[MAXTERMS + 1], T[MAXTERMS + 1];
+    p_series(a0, R, R0, n, Pc);
+    const double x = (R + R0 - 2.0) / (2.0 * P.sqrt_tau);
+    t_terms(x, 2.0 * P.sqrt_tau, n, T);
+    double num = 0.0, den = 4.0 / SQRTPI_D;
+    for (int k = 1; k <= n; ++k) {
+        const double gf = gamma_k(Qf, Pc, k);
+        num += (gf - gamma_k(Qr, Pc, k)) * T[k];
+        den += (gf + gamma_k(Qa, Pc, k)) * T[k];
+    }
+    return num / den;
+}
+
+// The 2D propagator density over its leading term: 1 + (sqrt(pi)/4) sum (g^ref_k + g^abs_k) T_k.
+__device__ inline double corr2(const Params &P, double Rp, double R0)
+{
+    const int n = P.n_terms;
+    const double *a0 = P.g2c, *Qa = a0 + (MAXTERMS + 1), *Qf = a0 + 2 * (MAXTERMS + 1);
+    double Pc[MAXTERMS + 1], T[MAXTERMS + 1];
+    p_series(a0, Rp, R0, n, Pc);
+    const double x = (Rp + R0 - 2.0) / (2.0 * P.sqrt_tau);
+    t_terms(x, 2.0 * P.sqrt_tau, n, T);
+    double s = 0.0;
+    for (int k = 1; k <= n; ++k) s += (gamma_k(Qf, Pc, k) + gamma_k(Qa, Pc, k)) * T[k];
+    return 1.0 + 0.25 * SQRTPI_D * s;
+}
+
+__device__ inline double reac_prob(const Params &P, int dim, double R, double R0)
+{
+    if (P.bc == 0) return 1.0;
+    if (P.bc == 1) return 0.0;
+    return dim == 3 ? preac3(P, R, R0) : preac2(P, R, R0);
+}
+
+// ---------------------------------------------------------------------------
+// Radial propagator sampler.
+// ---------------------------------------------------------------------------
+
+// The y >= yc with erfc(y) = u erfc(yc): Newton steps on
+// f(y) = ln erfcx(y) - y^2 - ln(u erfc(yc)), f'(y) = -2/(sqrt(pi) erfcx(y)),
+// kept inside a shrinking bracket.
+__device__ inline double erfc_tail_inv(double yc, double u)
+{
+    const double tgt = log(u) + log(erfcx(yc)) - yc * yc;
+    double lo = yc, hi = yc + 1.0;
+    while (log(erfcx(hi)) - hi * hi > tgt) hi = 2.0 * hi + 1.0;
+    double y = fmax(yc, sqrt(fmax(0.0, -tgt)));
+    if (!(y > lo && y < hi)) y = 0.5 * (lo + hi);
+    for (int it = 0; it < 200; ++it) {
+        const double ex = erfcx(y);
+        const double f = log(ex) - y * y - tgt;
+        if (f > 0.0) lo = y;
+        else hi = y;
+        double yn = y + f * ex * (0.5 * SQRTPI_D);
+        if (!(yn > lo && yn < hi)) yn = 0.5 * (lo + hi);
+        const double dy = yn - y;
+        y = yn;
+        if (fabs(dy) <= 1e-16 * (1.0 + fabs(y))) break;
+    }
+    return y;
+}
+
+constexpr u32 MAX_ATTEMPTS = 4096u;
+
+// R'' >= 1 from w_d r^{d-1}(g_ref - g_abs)(.|R0) (Sec. 3, Details).  With
+// c = R0 - 1, v = R' + R0 - 2 >= c, the target is
+//   3D: (1 + v - c) e^{-v^2/4tau} [1 - sqrt(pi tau) erfcx(sqrt(tau) + v/(2 sqrt(tau)))],
+//   2D: sqrt(1 + v - c) e^{-v^2/4tau} corr2(v),
+// proposed from (1 + beta (v - c)) e^{-v^2/4tau}, beta = 1 (3D) or 1/2 (2D):
+// a Gaussian-tail / Rayleigh-tail mixture when beta c <= 1, else the Rayleigh
+// tail alone.  Attempt k draws Philox {c0, c1, step, tag | k << 8}: word 0
+// chooses the mixture part, word 1 inverts its tail, word 2 accepts.
+template <int DIM>
+__device__ double sample_radius(const Params &P, double R0, u32 c0, u32 c1, u32 step, u32 tag, u32 *attempts, u32 *hits)
+{
+    double c = R0 - 1.0;
+    if (c < 0.0) c = 0.0;
+    const double tau = P.tau, st = P.sqrt_tau, yc = c / (2.0 * st);
+    const double beta = DIM == 3 ? 1.0 : 0.5;
+    const bool mixture = beta * c <= 1.0;
+    double w1 = 0.0, w2 = 0.0;
+    if (mixture) {
+        w1 = (1.0 - beta * c) * (SQRTPI_D * st) * erfcx(yc);
+        w2 = 2.0 * tau * beta;
+    }
+    double v = c;
+    for (u32 k = 0; k < MAX_ATTEMPTS; ++k) {
+        const uint4 r = philox(c0, c1, step, (tag & 0xFFu) | (k << 8), P.key);
+        const double u0 = u01(r.x), u1 = u01(r.y), u2 = u01(r.z);
+        double acc;
+        if (mixture) {
+            if (u0 * (w1 + w2) < w1) v = 2.0 * st * erfc_tail_inv(yc, u1);
+            else v = sqrt(c * c - 4.0 * tau * log(u1));
+            acc = 1.0;
+        } else {
+            v = sqrt(c * c - 4.0 * tau * log(u1));
+            acc = (1.0 + beta * (v - c)) / (beta * v);
+        }
+        const double Rp = 1.0 + v - c;
+        if (DIM == 3) {
+            acc *= 1.0 - (SQRTPI_D * st) * erfcx(st + v / (2.0 * st));
+        } else {
+            double corr = corr2(P, Rp, R0);
+            if (corr > 1.0) {
+                ++*hits;
+                corr = 1.0;
+            }
+            if (corr < 0.0) corr = 0.0;
+            acc *= sqrt(Rp) / (1.0 + 0.5 * (Rp - 1.0)) * corr;
+        }
+        if (u2 < acc) {
+            *attempts = k + 1;
+            return Rp;
+        }
+    }
+    *attempts = MAX_ATTEMPTS;
+    return 1.0 + v - c;
+}
+
+} // namespace gfbd

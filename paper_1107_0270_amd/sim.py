@@ -1,0 +1,228 @@
+"""Thin ctypes binding of the C-ABI in include/gfbd.h (argument marshalling only).
+
+Every step of the simulation runs in the HIP kernels of ``libgfbd.so``; this module
+only converts Python/numpy arguments and raises on error codes.  It refuses to run
+if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgfbd.so")
+
+SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_ESTATE, SIM_EUNSUPPORTED, SIM_ECAPACITY = 0, -1, -2, -3, -4, -5, -6
+SP_A, SP_B, SP_C, SP_FREE, SP_RESERVED = 0, 1, 2, 3, 4
+BC_ABSORBING, BC_REFLECTING, BC_RADIATION = 0, 1, 2
+PREC_FP64, PREC_FP32, PREC_FP32_FP64NC = 0, 1, 2
+(READ_POS, READ_SPECIES, READ_PARTNER, READ_COUNTS, READ_STATS, READ_STATS_SUM, READ_DERIVED, READ_DBG_MOVED,
+ READ_DBG_PAIRS, READ_DBG_PICKS, READ_DBG_MATCHES, READ_DBG_DISS, READ_DBG_CELLS, READ_TIMING, READ_GRID) = range(15)
+STAT_NAMES = ["pairs", "cand", "overlap", "r0clamp", "picks", "matches", "react", "decay", "geminate",
+              "attempts", "bound_hits", "near", "cand_overflow"]
+KERNEL_NAMES = ["move", "scan", "scatter", "pairs", "select", "react", "dissociate", "finish"]
+
+PAIR_DT = np.dtype([("i", "<u4"), ("j", "<u4"), ("R", "<f8"), ("R0", "<f8"), ("p", "<f8"),
+                    ("draw", "<u4"), ("cand", "<i4")], align=True)
+PICK_DT = np.dtype([("i", "<u4"), ("j", "<u4"), ("p", "<f8")], align=True)
+MATCH_DT = np.dtype([("i", "<u4"), ("j", "<u4"), ("reacted", "<i4"), ("attempts", "<u4"),
+                     ("Rpp", "<f8"), ("preac", "<f8")], align=True)
+DISS_DT = np.dtype([("c", "<u4"), ("j", "<u4"), ("decayed", "<i4"), ("recombined", "<i4"),
+                    ("attempts", "<u4"), ("pad", "<u4"), ("Rpp", "<f8"), ("preac", "<f8")], align=True)
+
+
+class SimSpecies(C.Structure):
+    _fields_ = [("D", C.c_double)]
+
+
+class SimReaction(C.Structure):
+    _fields_ = [("a", C.c_int32), ("b", C.c_int32), ("c", C.c_int32), ("bc", C.c_int32),
+                ("sigma", C.c_double), ("kappa", C.c_double), ("k_off", C.c_double)]
+
+
+class SimConfig(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("precision", C.c_int32), ("box", C.c_double * 3), ("dt", C.c_double),
+                ("seed", C.c_uint64), ("replica", C.c_uint32), ("n_terms", C.c_int32), ("eps_cut", C.c_double),
+                ("rcut", C.c_double), ("cell", C.c_double), ("n_species", C.c_int32),
+                ("species", C.POINTER(SimSpecies)), ("n_reactions", C.c_int32),
+                ("reactions", C.POINTER(SimReaction)), ("debug", C.c_uint32), ("timing", C.c_uint32),
+                ("debug_cap", C.c_uint64), ("hip_stream", C.c_void_p)]
+
+
+class SimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"gfbd error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libgfbd.so; raise if it was not built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "or python -m paper_1107_0270_amd.build")
+    L = C.CDLL(LIB_PATH)
+    vp, u64, u32, i32 = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int32
+    L.sim_create.argtypes = [C.POINTER(SimConfig), u64, vp, vp, vp, C.POINTER(vp)]
+    L.sim_create.restype = C.c_int
+    L.sim_step.argtypes = [vp, u32]
+    L.sim_step.restype = C.c_int
+    L.sim_read.argtypes = [vp, C.c_int, vp, u64, C.POINTER(u64)]
+    L.sim_read.restype = C.c_int
+    L.sim_load_state.argtypes = [vp, u64, vp, vp, vp]
+    L.sim_load_state.restype = C.c_int
+    L.sim_destroy.argtypes = [vp]
+    L.sim_destroy.restype = C.c_int
+    L.sim_last_error.argtypes = [vp]
+    L.sim_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+class Sim:
+    """One simulation handle on the GPU (see include/gfbd.h for the semantics)."""
+
+    def __init__(self, *, dim, box, dt, D, sigma, bc, species, pos, kappa=0.0, k_off=0.0,
+                 precision=PREC_FP32_FP64NC, seed=0, replica=0, n_terms=12, eps_cut=1e-3, rcut=0.0, cell=0.0,
+                 partner=None, debug=False, timing=False, debug_cap=0, stream=None):
+        L = lib()
+        cfg = SimConfig()
+        cfg.dim, cfg.precision = int(dim), int(precision)
+        bx = list(box) if np.ndim(box) else [float(box)] * int(dim)
+        bx = bx + [1.0] * (3 - len(bx))
+        for k in range(3):
+            cfg.box[k] = float(bx[k])
+        cfg.dt, cfg.seed, cfg.replica, cfg.n_terms = float(dt), int(seed), int(replica), int(n_terms)
+        cfg.eps_cut, cfg.rcut, cfg.cell = float(eps_cut), float(rcut), float(cell)
+        Dl = list(D)
+        if len(Dl) == 2:
+            Dl.append(Dl[0] * Dl[1] / (Dl[0] + Dl[1]))
+        self._species = (SimSpecies * 3)(*[SimSpecies(float(x)) for x in Dl])
+        self._reaction = (SimReaction * 1)(SimReaction(0, 1, 2, int(bc), float(sigma), float(kappa), float(k_off)))
+        cfg.n_species, cfg.species = 3, self._species
+        cfg.n_reactions, cfg.reactions = 1, self._reaction
+        cfg.debug, cfg.timing, cfg.debug_cap = int(bool(debug)), int(bool(timing)), int(debug_cap)
+        cfg.hip_stream = stream
+        self.cfg = cfg
+        self.dim = int(dim)
+        sp = np.ascontiguousarray(species, dtype=np.int32)
+        self.n = len(sp)
+        ps = np.ascontiguousarray(pos, dtype=np.float64).ravel()
+        if self.dim in (2, 3) and ps.size != self.n * self.dim:
+            raise ValueError("pos must hold n * dim values")
+        pt = None if partner is None else np.ascontiguousarray(partner, dtype=np.uint32)
+        h = C.c_void_p()
+        rc = L.sim_create(C.byref(cfg), self.n, sp.ctypes.data, ps.ctypes.data,
+                          None if pt is None else pt.ctypes.data, C.byref(h))
+        if rc != SIM_OK:
+            raise SimError(rc, L.sim_last_error(None).decode())
+        self._h = h
+
+    # ---- calls ------------------------------------------------------------
+    def _check(self, rc):
+        if rc != SIM_OK:
+            raise SimError(rc, lib().sim_last_error(self._h).decode())
+
+    def step(self, n=1):
+        self._check(lib().sim_step(self._h, int(n)))
+
+    def load_state(self, step, species, pos, partner=None):
+        sp = np.ascontiguousarray(species, dtype=np.int32)
+        ps = np.ascontiguousarray(pos, dtype=np.float64).reshape(self.n, self.dim)
+        pt = None if partner is None else np.ascontiguousarray(partner, dtype=np.uint32)
+        self._check(lib().sim_load_state(self._h, int(step), sp.ctypes.data, ps.ctypes.data,
+                                         None if pt is None else pt.ctypes.data))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _read(self, what, out):
+        w = C.c_uint64(0)
+        self._check(lib().sim_read(self._h, what, out.ctypes.data, out.nbytes, C.byref(w)))
+        return w.value
+
+    def _read_log(self, what, dt, cap=1 << 20):
+        out = np.zeros(cap, dtype=dt)
+        w = self._read(what, out)
+        return out[: w // dt.itemsize].copy()
+
+    # ---- reads ------------------------------------------------------------
+    def positions(self):
+        out = np.zeros((self.n, self.dim))
+        self._read(READ_POS, out)
+        return out
+
+    def species(self):
+        out = np.zeros(self.n, np.int32)
+        self._read(READ_SPECIES, out)
+        return out
+
+    def partners(self):
+        out = np.zeros(self.n, np.uint32)
+        self._read(READ_PARTNER, out)
+        return out
+
+    def state(self):
+        return self.species(), self.positions(), self.partners()
+
+    def counts(self):
+        out = np.zeros(5, np.int64)
+        self._read(READ_COUNTS, out)
+        return dict(zip(["A", "B", "C", "FREE", "RESERVED"], out.tolist()))
+
+    def stats(self, total=False):
+        out = np.zeros(len(STAT_NAMES), np.uint64)
+        self._read(READ_STATS_SUM if total else READ_STATS, out)
+        return dict(zip(STAT_NAMES, [int(x) for x in out]))
+
+    def derived(self):
+        out = np.zeros(8)
+        self._read(READ_DERIVED, out)
+        return dict(zip(["Deff", "tau", "hh", "rcut", "a", "p_uni", "cell", "step"], out.tolist()))
+
+    def grid(self):
+        out = np.zeros(4, np.int64)
+        self._read(READ_GRID, out)
+        return out.tolist()
+
+    def kernel_times(self):
+        out = np.zeros(len(KERNEL_NAMES), dtype=np.dtype([("ms", "<f8"), ("launches", "<u8")]))
+        self._read(READ_TIMING, out)
+        return {k: (float(r["ms"]), int(r["launches"])) for k, r in zip(KERNEL_NAMES, out)}
+
+    def dbg_moved(self):
+        out = np.zeros((self.n, self.dim))
+        self._read(READ_DBG_MOVED, out)
+        return out
+
+    def dbg_cells(self):
+        out = np.zeros(self.n, np.uint32)
+        self._read(READ_DBG_CELLS, out)
+        return out
+
+    def dbg_pairs(self):
+        return self._read_log(READ_DBG_PAIRS, PAIR_DT)
+
+    def dbg_picks(self):
+        return self._read_log(READ_DBG_PICKS, PICK_DT)
+
+    def dbg_matches(self):
+        return self._read_log(READ_DBG_MATCHES, MATCH_DT)
+
+    def dbg_diss(self):
+        return self._read_log(READ_DBG_DISS, DISS_DT)

@@ -1,0 +1,164 @@
+"""Lock-step comparison of the HIP library (through its C-ABI) with the oracle.
+
+Both sides start from the same seeded state and take the same steps.  After every
+step the stage logs are compared: post-move positions, the pair list within
+r_cut, p_enc and the Bernoulli draws, the A-side picks, the matched pairs (new
+radius, p_reac, reaction flag), the dissociations, and the final state.  A
+decision may legitimately differ only where the draw lies within 1e-6 of the
+probability; such steps are counted, and the GPU is then reloaded with the
+oracle's state (oracle -> GPU only) so the comparison can go on.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+import oracle as O
+from paper_1107_0270_amd import sim as S
+
+NEAR = 1e-6
+
+
+@dataclasses.dataclass
+class Report:
+    steps: int = 0
+    pairs: int = 0
+    cand: int = 0
+    matches: int = 0
+    reactions: int = 0
+    decays: int = 0
+    max_dpos: float = 0.0
+    max_dp: float = 0.0
+    max_dRpp: float = 0.0
+    max_dpreac: float = 0.0
+    pair_set_mismatch: int = 0
+    pair_set_near_cut: int = 0
+    draw_mismatch: int = 0
+    near_decisions: int = 0
+    unexplained: int = 0
+    resyncs: int = 0
+    notes: list = dataclasses.field(default_factory=list)
+
+
+def make_pair(*, dim, bc, box, dt, D, sigma, kappa, k_off, precision, species, pos, partner=None, seed=0,
+              n_terms=12, eps_cut=1e-3, rcut=0.0, cell=0.0):
+    gpu = S.Sim(dim=dim, box=box, dt=dt, D=D, sigma=sigma, bc=bc, kappa=kappa, k_off=k_off, precision=precision,
+                seed=seed, n_terms=n_terms, eps_cut=eps_cut, rcut=rcut, cell=cell, species=species, pos=pos,
+                partner=partner, debug=True)
+    orc = O.OracleSim(dim=dim, bc=bc, box=[box] * dim, dt=dt, D=D, sigma=sigma, kappa_a=kappa, k_off=k_off,
+                      eps_cut=eps_cut, rcut=rcut, seed=seed, store_f32=precision != S.PREC_FP64, n_terms=n_terms,
+                      species=species, pos=pos, partner=partner)
+    return gpu, orc
+
+
+def _key(a, b):
+    return (a.astype(np.uint64) << np.uint64(32)) | b.astype(np.uint64)
+
+
+def compare_step(gpu, orc, rep: Report, *, p_tol, pos_tol, box, rcut, sp_before):
+    """Advance both sides one step and compare; returns True if the states agree afterwards."""
+    gpu.step()
+    orc.step()
+    rep.steps += 1
+    live = sp_before <= O.SP_C
+    # 1. move
+    gm, om = gpu.dbg_moved(), orc.moved()
+    if live.any():
+        d = np.abs(gm[live] - om[live])
+        d = np.minimum(d, box - d)
+        rep.max_dpos = max(rep.max_dpos, float(d.max()))
+    # 2.-3. pairs, p_enc, draws, candidates
+    gp, op = gpu.dbg_pairs(), orc.pairs()
+    rep.pairs += len(op)
+    rep.cand += int(op["cand"].sum())
+    gk, ok = _key(gp["i"], gp["j"]), _key(op["i"], op["j"])
+    gi, oi = np.argsort(gk), np.argsort(ok)
+    gp, op, gk, ok = gp[gi], op[oi], gk[gi], ok[oi]
+    common, ig, io = np.intersect1d(gk, ok, assume_unique=True, return_indices=True)
+    only = np.setxor1d(gk, ok)
+    for k in only:
+        # a pair on one side only is allowed only at the cut-off radius (binary32 test)
+        src = gp[gk == k] if k in gk else op[ok == k]
+        r = float(src["R"][0]) * orc.derived()["a"]
+        if abs(r - rcut) <= 1e-6 * rcut:
+            rep.pair_set_near_cut += 1
+        else:
+            rep.pair_set_mismatch += 1
+    g, o = gp[ig], op[io]
+    decisions_ok = True
+    if len(g):
+        rep.max_dp = max(rep.max_dp, float(np.abs(g["p"] - o["p"]).max()))
+        rep.draw_mismatch += int((g["draw"] != o["draw"]).sum())
+        bad = g["cand"] != o["cand"]
+        if bad.any():
+            u = (o["draw"][bad].astype(np.float64) + 0.5) * 2.0 ** -32
+            near = np.abs(u - o["p"][bad]) < max(NEAR, 2 * p_tol)
+            rep.near_decisions += int(near.sum())
+            rep.unexplained += int((~near).sum())
+            decisions_ok = False
+    # 4. picks
+    gk2 = np.sort(_key(gpu.dbg_picks()["i"], gpu.dbg_picks()["j"]))
+    pk = orc.picks()
+    ok2 = np.sort(_key(pk["i"], pk["j"]))
+    if decisions_ok and not np.array_equal(gk2, ok2):
+        rep.notes.append(f"step {rep.steps}: picks differ")
+        rep.unexplained += 1
+        decisions_ok = False
+    # 5. matches
+    gmt, omt = gpu.dbg_matches(), orc.matches()
+    rep.matches += len(omt)
+    rep.reactions += int(omt["reacted"].sum())
+    if decisions_ok:
+        gs, os_ = gmt[np.argsort(_key(gmt["i"], gmt["j"]))], omt[np.argsort(_key(omt["i"], omt["j"]))]
+        if len(gs) != len(os_) or not (np.array_equal(gs["i"], os_["i"]) and np.array_equal(gs["j"], os_["j"])):
+            rep.notes.append(f"step {rep.steps}: matches differ")
+            rep.unexplained += 1
+            decisions_ok = False
+        elif len(gs):
+            rep.max_dRpp = max(rep.max_dRpp, float(np.abs(gs["Rpp"] - os_["Rpp"]).max()))
+            rep.max_dpreac = max(rep.max_dpreac, float(np.abs(gs["preac"] - os_["preac"]).max()))
+            badr = gs["reacted"] != os_["reacted"]
+            if badr.any():
+                rep.near_decisions += int(badr.sum())
+                decisions_ok = False
+    # 6. dissociations
+    gd, od = gpu.dbg_diss(), orc.dissociations()
+    rep.decays += len(od)
+    if decisions_ok:
+        gs, os_ = gd[np.argsort(gd["c"])], od[np.argsort(od["c"])]
+        if not (np.array_equal(gs["c"], os_["c"]) and np.array_equal(gs["recombined"], os_["recombined"])):
+            rep.notes.append(f"step {rep.steps}: dissociations differ")
+            rep.unexplained += 1
+            decisions_ok = False
+        elif len(gs):
+            rep.max_dRpp = max(rep.max_dRpp, float(np.abs(gs["Rpp"] - os_["Rpp"]).max()))
+    # 7. state
+    gsp, gpos, gpt = gpu.state()
+    osp, opos, opt = orc.state()
+    same = np.array_equal(gsp, osp)
+    if same:
+        lv = osp <= O.SP_C
+        if lv.any():
+            d = np.abs(gpos[lv] - opos[lv])
+            d = np.minimum(d, box - d)
+            rep.max_dpos = max(rep.max_dpos, float(d.max()))
+            same = float(d.max()) <= pos_tol
+        cs = osp == O.SP_C
+        same = same and np.array_equal(gpt[cs], opt[cs])
+    if not same:
+        if decisions_ok:
+            rep.notes.append(f"step {rep.steps}: state differs without a decision difference")
+            rep.unexplained += 1
+        rep.resyncs += 1
+        gpu.load_state(orc.stepno, osp, opos, opt)
+    return osp
+
+
+def run(gpu, orc, steps, *, p_tol, pos_tol, box):
+    rep = Report()
+    rcut = orc.derived()["rcut"]
+    sp, _, _ = orc.state()
+    for _ in range(steps):
+        sp = compare_step(gpu, orc, rep, p_tol=p_tol, pos_tol=pos_tol, box=box, rcut=rcut, sp_before=sp)
+    return rep

@@ -1,0 +1,92 @@
+"""The C-ABI library: builds, loads, exports every declared entry point, has the
+struct layouts the binding assumes, and rejects invalid input before touching
+the device (CPU only)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1107_0270_amd import sim as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gfbd.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(sim_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_declares_the_boundary():
+    assert _declared() == sorted(["sim_create", "sim_step", "sim_read", "sim_load_state", "sim_destroy", "sim_last_error"])
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(S.LIB_PATH):
+        pytest.skip("libgfbd.so not built")
+    out = subprocess.run(["nm", "-D", "--defined-only", S.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r" T (\w+)$", out, re.M))
+    for name in _declared():
+        assert name in exported, name
+    L = S.lib()
+    for name in _declared():
+        assert getattr(L, name) is not None
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # compile a probe against the public header and compare sizes/offsets with ctypes
+    src = tmp_path / "probe.c"
+    src.write_text(r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "gfbd.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(sim_config), offsetof(sim_config, species),
+         offsetof(sim_config, reactions), offsetof(sim_config, debug_cap), offsetof(sim_config, hip_stream),
+         sizeof(sim_reaction), sizeof(sim_dbg_pair), sizeof(sim_dbg_diss));
+  printf("%zu %zu %zu\n", sizeof(sim_dbg_pick), sizeof(sim_dbg_match), sizeof(sim_kernel_time));
+  return 0; }
+''')
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    a, b = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")[:2]
+    got = [int(x) for x in a.split()]
+    assert got == [C.sizeof(S.SimConfig), S.SimConfig.species.offset, S.SimConfig.reactions.offset,
+                   S.SimConfig.debug_cap.offset, S.SimConfig.hip_stream.offset, C.sizeof(S.SimReaction),
+                   S.PAIR_DT.itemsize, S.DISS_DT.itemsize]
+    assert [int(x) for x in b.split()] == [S.PICK_DT.itemsize, S.MATCH_DT.itemsize, 16]
+
+
+def _args(**over):
+    kw = dict(dim=3, box=1.0, dt=1e-6, D=(1.0, 1.0, 0.5), sigma=0.005, bc=S.BC_ABSORBING,
+              species=np.array([0, 1], np.int32), pos=np.array([[0.1, 0.1, 0.1], [0.5, 0.5, 0.5]]),
+              precision=S.PREC_FP64)
+    kw.update(over)
+    return kw
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(dim=4), S.SIM_EINVAL),
+    (dict(dt=-1.0), S.SIM_EINVAL),
+    (dict(dt=float("nan")), S.SIM_EINVAL),
+    (dict(sigma=0.0), S.SIM_EINVAL),
+    (dict(D=(-1.0, 1.0, 0.5)), S.SIM_EINVAL),
+    (dict(D=(0.0, 0.0, 0.0)), S.SIM_EINVAL),
+    (dict(kappa=-0.1), S.SIM_EINVAL),
+    (dict(species=np.array([0, 9], np.int32)), S.SIM_EINVAL),
+    (dict(pos=np.array([[0.1, float("inf"), 0.1], [0.5, 0.5, 0.5]])), S.SIM_EINVAL),
+    (dict(precision=S.PREC_FP32, box=0.1), S.SIM_EINVAL),        # 0.1 is not a binary32 value
+    (dict(n_terms=40), S.SIM_EINVAL),
+    (dict(eps_cut=1.5), S.SIM_EINVAL),
+    # C without a reserved partner in a reversible system
+    (dict(species=np.array([2, 1], np.int32), k_off=1.0), S.SIM_EINVAL),
+])
+def test_invalid_input_is_rejected_before_the_device(over, code):
+    if not os.path.exists(S.LIB_PATH):
+        pytest.skip("libgfbd.so not built")
+    with pytest.raises(S.SimError) as e:
+        S.Sim(**_args(**over))
+    assert e.value.code == code

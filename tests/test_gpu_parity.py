@@ -1,0 +1,176 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle, step by step.
+
+Tolerances (written out here, derived in the design doc):
+  * positions: binary32 states are bit-identical to the oracle's (both round the
+    same binary64 update once); binary64 states agree to 1e-12 of the box.
+  * pair lists: identical sets; draws bit-identical.
+  * p_enc: 1e-12 (FP64), 1e-6 (FP32 with binary64 near-contact arguments);
+    the plain FP32 mode reports its error and is held to 1e-4.
+  * decisions: identical except draws within 1e-6 of p (counted).
+  * propagated radius and p_reac (binary64 on both sides): 1e-9.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1107_0270_amd import inputs as I
+from paper_1107_0270_amd import sim as S
+
+from .parity import make_pair, run
+
+pytestmark = pytest.mark.gpu
+
+
+def _state(n_a, n_b, box, dim, sigma, seed, f32):
+    sp, pos, _ = I.uniform_state(n_a, n_b, box=box, dim=dim, sigma=sigma, seed=seed, f32=f32)
+    return sp, pos
+
+
+def _check(rep, *, p_tol, allow_near=2):
+    print(rep)
+    assert rep.pair_set_mismatch == 0
+    assert rep.draw_mismatch == 0
+    assert rep.unexplained == 0, rep.notes
+    assert rep.max_dp <= p_tol
+    assert rep.max_dRpp <= 1e-9 and rep.max_dpreac <= 1e-9
+    assert rep.near_decisions <= allow_near
+
+
+def test_abs3d_fp64_trajectory():
+    # the 3D absorbing workload in full: 1,000 A + 1,000 B, L = 1 um, 100 steps, FP64
+    cfg = I.workload("cfg_abs3d")
+    sp, pos = _state(cfg["n_a"], cfg["n_b"], cfg["box"], 3, cfg["sigma"], 0, False)
+    gpu, orc = make_pair(dim=3, bc=cfg["bc"], box=cfg["box"], dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"],
+                         kappa=0.0, k_off=0.0, precision=S.PREC_FP64, species=sp, pos=pos)
+    rep = run(gpu, orc, cfg["steps"], p_tol=1e-12, pos_tol=1e-12, box=cfg["box"])
+    _check(rep, p_tol=1e-12)
+    assert rep.reactions > 5 and rep.resyncs == 0
+    assert gpu.derived()["rcut"] == pytest.approx(orc.derived()["rcut"], rel=1e-12)
+
+
+@pytest.mark.parametrize("prec,p_tol", [(S.PREC_FP32_FP64NC, 1e-6), (S.PREC_FP32, 1e-4)])
+def test_rad3d_reversible_binary32(prec, p_tol):
+    # radiation workload at its density (500 A + 500 B per um^3) in a 2.5 um box;
+    # k_off raised so dissociation and geminate recombination occur within the run
+    n = 7812
+    sp, pos = _state(n, n, 2.5, 3, 0.005, 1, True)
+    gpu, orc = make_pair(dim=3, bc=O.BC_RAD, box=2.5, dt=1e-5, D=(1.0, 1.0, 0.5), sigma=0.005, kappa=0.1,
+                         k_off=2000.0, precision=prec, species=sp, pos=pos, seed=3)
+    rep = run(gpu, orc, 30, p_tol=p_tol, pos_tol=0.0, box=2.5)
+    _check(rep, p_tol=p_tol)
+    assert rep.reactions > 20 and rep.decays > 0
+
+
+def test_rad3d_dense_overflow_path():
+    # a dense, fast system: many A's hold more than eight candidates, which
+    # exercises the second pass that sorts long candidate lists in memory
+    n = 3000
+    sp, pos = _state(n, n, 0.25, 3, 0.004, 2, True)
+    gpu, orc = make_pair(dim=3, bc=O.BC_RAD, box=0.25, dt=2e-5, D=(5.0, 5.0, 2.5), sigma=0.004, kappa=1.0,
+                         k_off=500.0, precision=S.PREC_FP32_FP64NC, species=sp, pos=pos, seed=4, eps_cut=1e-6)
+    rep = run(gpu, orc, 6, p_tol=1e-6, pos_tol=0.0, box=0.25)
+    _check(rep, p_tol=1e-6, allow_near=3)
+    tot = gpu.stats(total=True)
+    assert tot["cand_overflow"] > 0
+
+
+def test_reflecting_and_small_box_single_cell():
+    # reflecting surface (no reactions, every encounter re-propagated) in a box
+    # with fewer than three cells per edge
+    n = 300
+    sp, pos = _state(n, n, 0.05, 3, 0.004, 5, False)
+    gpu, orc = make_pair(dim=3, bc=O.BC_REF, box=0.05, dt=2e-6, D=(1.0, 1.0, 0.5), sigma=0.004, kappa=0.0,
+                         k_off=0.0, precision=S.PREC_FP64, species=sp, pos=pos, seed=6)
+    assert gpu.grid()[3] == 1
+    rep = run(gpu, orc, 10, p_tol=1e-12, pos_tol=1e-12, box=0.05)
+    _check(rep, p_tol=1e-12)
+    assert rep.matches > 0 and rep.reactions == 0
+
+
+@pytest.mark.parametrize("prec,p_tol", [(S.PREC_FP64, 1e-12), (S.PREC_FP32_FP64NC, 1e-9)])
+def test_mem2d_small_tau(prec, p_tol):
+    # 2D membrane workload at tau = 0.04 (dt = 5 us), its density (1,250 A and B per um^2)
+    n = 7812
+    sp, pos = _state(n, n, 2.5, 2, 0.005, 7, prec != S.PREC_FP64)
+    gpu, orc = make_pair(dim=2, bc=O.BC_RAD, box=2.5, dt=5e-6, D=(0.1, 0.1, 0.05), sigma=0.005, kappa=0.05,
+                         k_off=2000.0, precision=prec, species=sp, pos=pos, seed=8)
+    rep = run(gpu, orc, 20, p_tol=p_tol, pos_tol=0.0 if prec != S.PREC_FP64 else 1e-12, box=2.5)
+    _check(rep, p_tol=p_tol)
+    assert rep.reactions > 0
+
+
+def test_mem2d_as_written_tau_0p8():
+    # the membrane workload's dt = 100 us (tau = 0.8): same arithmetic on both sides
+    n = 4000
+    sp, pos = _state(n, n, 1.75, 2, 0.005, 9, True)
+    gpu, orc = make_pair(dim=2, bc=O.BC_RAD, box=1.75, dt=1e-4, D=(0.1, 0.1, 0.05), sigma=0.005, kappa=0.05,
+                         k_off=10.0, precision=S.PREC_FP32_FP64NC, species=sp, pos=pos, seed=10)
+    rep = run(gpu, orc, 5, p_tol=1e-9, pos_tol=0.0, box=1.75)
+    _check(rep, p_tol=1e-9)
+
+
+def test_rad3d_full_size_one_step():
+    # the benchmark workload at full size (1e6 particles, L = 10 um), one step
+    cfg = I.workload("cfg_rad3d")
+    sp, pos = _state(cfg["n_a"], cfg["n_b"], cfg["box"], 3, cfg["sigma"], 0, True)
+    gpu, orc = make_pair(dim=3, bc=cfg["bc"], box=cfg["box"], dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"],
+                         kappa=cfg["kappa_a"], k_off=cfg["k_off"], precision=cfg["precision"], species=sp, pos=pos)
+    rep = run(gpu, orc, 2, p_tol=1e-6, pos_tol=0.0, box=cfg["box"])
+    _check(rep, p_tol=1e-6)
+    assert rep.pairs > 10000
+
+
+def test_cell_lists_are_consistent():
+    # every live slot is binned once, in the bucket of its post-move position
+    n = 5000
+    sp, pos = _state(n, n, 1.0, 3, 0.005, 11, True)
+    gpu, _ = make_pair(dim=3, bc=O.BC_RAD, box=1.0, dt=1e-5, D=(1.0, 1.0, 0.5), sigma=0.005, kappa=0.1,
+                       k_off=10.0, precision=S.PREC_FP32_FP64NC, species=sp, pos=pos)
+    sp0 = gpu.species()
+    gpu.step()
+    keys, moved = gpu.dbg_cells(), gpu.dbg_moved()
+    nx, ny, nz, ncell = gpu.grid()
+    live = sp0 <= S.SP_C
+    c = [np.clip(np.floor(moved[live, k] * (m / 1.0)).astype(np.int64), 0, m - 1) for k, m in enumerate((nx, ny, nz))]
+    expect = sp0[live].astype(np.int64) * ncell + (c[2] * ny + c[1]) * nx + c[0]
+    assert np.array_equal(keys[live].astype(np.int64), expect)
+    assert np.all(keys[~live] == 0xFFFFFFFF)
+
+
+def test_degenerate_inputs():
+    # no B at all; a single A; all slots free except one C with its reserved slot
+    box = 1.0
+    sp = np.zeros(10, np.int32)
+    pos = np.random.default_rng(0).random((10, 3))
+    g = S.Sim(dim=3, box=box, dt=1e-6, D=(1.0, 1.0, 0.5), sigma=0.005, bc=S.BC_ABSORBING, species=sp, pos=pos,
+              precision=S.PREC_FP64)
+    g.step(3)
+    assert g.counts()["A"] == 10 and g.stats()["pairs"] == 0
+    g1 = S.Sim(dim=2, box=box, dt=1e-6, D=(1.0, 1.0, 0.5), sigma=0.005, bc=S.BC_RADIATION, kappa=0.1,
+               species=np.array([0], np.int32), pos=np.array([[0.5, 0.5]]))
+    g1.step(2)
+    assert g1.counts()["A"] == 1
+    sp = np.array([2, 4, 3], np.int32)
+    pos = np.array([[0.5, 0.5, 0.5], [0, 0, 0], [0, 0, 0]], float)
+    gc, oc = make_pair(dim=3, bc=O.BC_RAD, box=box, dt=1e-5, D=(1.0, 1.0, 0.5), sigma=0.005, kappa=0.1,
+                       k_off=3e4, precision=S.PREC_FP64, species=sp, pos=pos, partner=np.array([1, 0xFFFFFFFF, 0xFFFFFFFF], np.uint32))
+    rep = run(gc, oc, 40, p_tol=1e-12, pos_tol=1e-12, box=box)
+    _check(rep, p_tol=1e-12)
+    assert rep.decays > 0
+
+
+def test_capacity_error_is_reported():
+    # a very dense system (about 200 B within r_cut of every A): long candidate
+    # lists go through the second pass; if its scratch fills up the step must
+    # fail with SIM_ECAPACITY rather than return wrong picks
+    n = 3000
+    sp, pos = _state(n, n, 0.1, 3, 0.002, 12, False)
+    g = S.Sim(dim=3, box=0.1, dt=1e-6, D=(5.0, 5.0, 2.5), sigma=0.002, bc=S.BC_RADIATION, kappa=0.1,
+              species=sp, pos=pos, precision=S.PREC_FP64)
+    try:
+        g.step(2)
+        assert g.stats()["cand_overflow"] > 0
+    except S.SimError as e:
+        assert e.code == S.SIM_ECAPACITY
