@@ -156,8 +156,9 @@ class Sim:
         self._check(lib().sim_read(self._h, what, out.ctypes.data, out.nbytes, C.byref(w)))
         return w.value
 
-    def _read_log(self, what, dt, cap=1 << 20):
-        out = np.zeros(cap, dtype=dt)
+    def _read_log(self, what, dt):
+        cap = int(self.cfg.debug_cap) or (1 << 20)
+        out = np.empty(cap, dtype=dt)
         w = self._read(what, out)
         return out[: w // dt.itemsize].copy()
 

@@ -42,10 +42,10 @@ class Report:
 
 
 def make_pair(*, dim, bc, box, dt, D, sigma, kappa, k_off, precision, species, pos, partner=None, seed=0,
-              n_terms=12, eps_cut=1e-3, rcut=0.0, cell=0.0):
+              n_terms=12, eps_cut=1e-3, rcut=0.0, cell=0.0, debug_cap=1 << 21):
     gpu = S.Sim(dim=dim, box=box, dt=dt, D=D, sigma=sigma, bc=bc, kappa=kappa, k_off=k_off, precision=precision,
                 seed=seed, n_terms=n_terms, eps_cut=eps_cut, rcut=rcut, cell=cell, species=species, pos=pos,
-                partner=partner, debug=True)
+                partner=partner, debug=True, debug_cap=debug_cap)
     orc = O.OracleSim(dim=dim, bc=bc, box=[box] * dim, dt=dt, D=D, sigma=sigma, kappa_a=kappa, k_off=k_off,
                       eps_cut=eps_cut, rcut=rcut, seed=seed, store_f32=precision != S.PREC_FP64, n_terms=n_terms,
                       species=species, pos=pos, partner=partner)
@@ -75,16 +75,17 @@ def compare_step(gpu, orc, rep: Report, *, p_tol, pos_tol, box, rcut, sp_before)
     gk, ok = _key(gp["i"], gp["j"]), _key(op["i"], op["j"])
     gi, oi = np.argsort(gk), np.argsort(ok)
     gp, op, gk, ok = gp[gi], op[oi], gk[gi], ok[oi]
+    if len(gp) != gpu.stats()["pairs"]:
+        raise AssertionError(f"GPU pair log truncated: {len(gp)} of {gpu.stats()['pairs']} (raise debug_cap)")
     common, ig, io = np.intersect1d(gk, ok, assume_unique=True, return_indices=True)
-    only = np.setxor1d(gk, ok)
-    for k in only:
-        # a pair on one side only is allowed only at the cut-off radius (binary32 test)
-        src = gp[gk == k] if k in gk else op[ok == k]
-        r = float(src["R"][0]) * orc.derived()["a"]
-        if abs(r - rcut) <= 1e-6 * rcut:
-            rep.pair_set_near_cut += 1
-        else:
-            rep.pair_set_mismatch += 1
+    # a pair on one side only is allowed only at the cut-off radius (binary32 test)
+    a = orc.derived()["a"]
+    for src, keys in ((gp, gk), (op, ok)):
+        extra = ~np.isin(keys, common)
+        r = src["R"][extra] * a
+        near = np.abs(r - rcut) <= 1e-6 * rcut
+        rep.pair_set_near_cut += int(near.sum())
+        rep.pair_set_mismatch += int((~near).sum())
     g, o = gp[ig], op[io]
     decisions_ok = True
     if len(g):
@@ -159,6 +160,8 @@ def run(gpu, orc, steps, *, p_tol, pos_tol, box):
     rep = Report()
     rcut = orc.derived()["rcut"]
     sp, _, _ = orc.state()
-    for _ in range(steps):
+    for k in range(steps):
         sp = compare_step(gpu, orc, rep, p_tol=p_tol, pos_tol=pos_tol, box=box, rcut=rcut, sp_before=sp)
+        print(f"  step {k}: pairs {rep.pairs} matches {rep.matches} reactions {rep.reactions} "
+              f"max|dp| {rep.max_dp:.2e} resyncs {rep.resyncs}", flush=True)
     return rep
