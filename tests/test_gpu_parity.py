@@ -66,12 +66,12 @@ def test_rad3d_reversible_binary32(prec, p_tol):
 def test_rad3d_dense_overflow_path():
     # a dense, fast system: many A's hold more than eight candidates, which
     # exercises the second pass that sorts long candidate lists in memory
-    # (20,000 A + 20,000 B in a 0.4 um box: about 2e5 pairs and 4e4 candidates per step)
+    # (20,000 A + 20,000 B in a 0.375 um box: about 3e5 pairs and 5e4 candidates per step)
     n = 20000
-    sp, pos = _state(n, n, 0.4, 3, 0.004, 2, True)
-    gpu, orc = make_pair(dim=3, bc=O.BC_RAD, box=0.4, dt=2e-5, D=(5.0, 5.0, 2.5), sigma=0.004, kappa=1.0,
+    sp, pos = _state(n, n, 0.375, 3, 0.004, 2, True)
+    gpu, orc = make_pair(dim=3, bc=O.BC_RAD, box=0.375, dt=2e-5, D=(5.0, 5.0, 2.5), sigma=0.004, kappa=1.0,
                          k_off=500.0, precision=S.PREC_FP32_FP64NC, species=sp, pos=pos, seed=4, eps_cut=0.05)
-    rep = run(gpu, orc, 5, p_tol=1e-6, pos_tol=0.0, box=0.4)
+    rep = run(gpu, orc, 5, p_tol=1e-6, pos_tol=0.0, box=0.375)
     _check(rep, p_tol=1e-6, allow_near=3)
     tot = gpu.stats(total=True)
     assert tot["cand_overflow"] > 0
