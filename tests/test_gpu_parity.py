@@ -78,12 +78,12 @@ def test_rad3d_dense_overflow_path():
 
 
 def test_reflecting_and_small_box_single_cell():
-    # reflecting surface (no reactions, every encounter re-propagated) in a box
-    # with fewer than three cells per edge
+    # reflecting surface (no reactions, every encounter re-propagated) with one
+    # cell for the whole box (the neighbour search then visits that cell once)
     n = 300
     sp, pos = _state(n, n, 0.05, 3, 0.004, 5, False)
     gpu, orc = make_pair(dim=3, bc=O.BC_REF, box=0.05, dt=2e-6, D=(1.0, 1.0, 0.5), sigma=0.004, kappa=0.0,
-                         k_off=0.0, precision=S.PREC_FP64, species=sp, pos=pos, seed=6)
+                         k_off=0.0, precision=S.PREC_FP64, species=sp, pos=pos, seed=6, cell=0.05)
     assert gpu.grid()[3] == 1
     rep = run(gpu, orc, 10, p_tol=1e-12, pos_tol=1e-12, box=0.05)
     _check(rep, p_tol=1e-12)
