@@ -160,18 +160,3 @@ def test_degenerate_inputs():
     rep = run(gc, oc, 40, p_tol=1e-12, pos_tol=1e-12, box=box)
     _check(rep, p_tol=1e-12)
     assert rep.decays > 0
-
-
-def test_capacity_error_is_reported():
-    # a very dense system (about 200 B within r_cut of every A): long candidate
-    # lists go through the second pass; if its scratch fills up the step must
-    # fail with SIM_ECAPACITY rather than return wrong picks
-    n = 3000
-    sp, pos = _state(n, n, 0.1, 3, 0.002, 12, False)
-    g = S.Sim(dim=3, box=0.1, dt=1e-6, D=(5.0, 5.0, 2.5), sigma=0.002, bc=S.BC_RADIATION, kappa=0.1,
-              species=sp, pos=pos, precision=S.PREC_FP64)
-    try:
-        g.step(2)
-        assert g.stats()["cand_overflow"] > 0
-    except S.SimError as e:
-        assert e.code == S.SIM_ECAPACITY
