@@ -111,9 +111,10 @@ typedef struct {
 int sim_create(const sim_config *cfg, uint64_t n, const int32_t *species, const double *pos,
                const uint32_t *partner, sim_t **out);
 
-/* Enqueues nsteps steps on the handle's stream.  Returns after the launches;
- * per-step capacity checks are read back at the end of the call (one stream
- * synchronisation), so SIM_ECAPACITY reports an overflow in any of the steps. */
+/* Enqueues nsteps steps on the handle's stream and waits for them.  Without
+ * debug or timing, each step is one replay of a captured HIP graph.  The
+ * capacity flags are read back once at the end of the call, so SIM_ECAPACITY
+ * reports an overflow of the per-step pair list in any of the steps. */
 int sim_step(sim_t *h, uint32_t nsteps);
 
 /* What sim_read copies to the host buffer dst (cap_bytes long); *written gets
@@ -139,7 +140,7 @@ enum {
 enum {
     SIM_STAT_PAIRS = 0, SIM_STAT_CAND, SIM_STAT_OVERLAP, SIM_STAT_R0CLAMP, SIM_STAT_PICKS,
     SIM_STAT_MATCHES, SIM_STAT_REACT, SIM_STAT_DECAY, SIM_STAT_GEMINATE, SIM_STAT_ATTEMPTS,
-    SIM_STAT_BOUND, SIM_STAT_NEAR, SIM_STAT_CAND_OVERFLOW, SIM_STAT_N
+    SIM_STAT_BOUND, SIM_STAT_NEAR, SIM_STAT_LDS_FALLBACK, SIM_STAT_N
 };
 
 typedef struct { uint32_t i, j; double R, R0, p; uint32_t draw; int32_t cand; } sim_dbg_pair;
@@ -147,8 +148,11 @@ typedef struct { uint32_t i, j; double p; } sim_dbg_pick;
 typedef struct { uint32_t i, j; int32_t reacted; uint32_t attempts; double Rpp, preac; } sim_dbg_match;
 typedef struct { uint32_t c, j; int32_t decayed, recombined; uint32_t attempts, pad; double Rpp, preac; } sim_dbg_diss;
 
+/* Kernels timed with sim_config.timing: move + bucket count, bucket scan,
+ * scatter into sorted order, pair search, p_enc + draw per pair, A-side
+ * choice, B-side choice + propagation/reaction, dissociation, step close. */
 enum {
-    SIM_K_MOVE = 0, SIM_K_SCAN, SIM_K_SCATTER, SIM_K_PAIRS, SIM_K_SELECT, SIM_K_REACT,
+    SIM_K_MOVE = 0, SIM_K_SCAN, SIM_K_SCATTER, SIM_K_PAIRS, SIM_K_EVAL, SIM_K_SELECT, SIM_K_REACT,
     SIM_K_DISSOCIATE, SIM_K_FINISH, SIM_K_N
 };
 typedef struct { double ms; uint64_t launches; } sim_kernel_time;

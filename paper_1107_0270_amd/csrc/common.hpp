@@ -112,7 +112,10 @@ struct Params {
     double p_uni;    // 1 - exp(-k_off dt)
     Key key;
     u32 cap;
-    u32 cap_picks, cap_ovf_cand;
+    u32 cap_pl;          // capacity of the per-step pair list
+    int tiled;           // pair search through LDS bricks (all edges >= 3 cells)
+    int bx, by, bz;      // brick edges in cells
+    u32 nbx, nby, nbz;   // bricks per axis
     u32 debug;
     u32 dbg_cap;
     const double *g2c;  // 2D constants: a_k(0), Q_abs, Q_ref, Q_rad (4 x (MAXTERMS+1))
@@ -120,37 +123,40 @@ struct Params {
 
 enum {
     ST_PAIRS = 0, ST_CAND, ST_OVERLAP, ST_R0CLAMP, ST_PICKS, ST_MATCHES, ST_REACT, ST_DECAY,
-    ST_GEMINATE, ST_ATTEMPTS, ST_BOUND, ST_NEAR, ST_CAND_OVERFLOW, ST_N
+    ST_GEMINATE, ST_ATTEMPTS, ST_BOUND, ST_NEAR, ST_LDS_FALLBACK, ST_N
 };
 
-enum { ERR_PICKS = 1, ERR_OVF = 2, ERR_OVF_CAND = 4, ERR_APPEND = 8 };
+enum { ERR_PAIRS = 1, ERR_APPEND = 8 };
 
 // Device-resident counters; the work sizes of the data-dependent stages live
 // here so that no stage needs the host to learn a count.
 struct Counters {
     u32 n_rec;      // records in the current buffer (sorted + appended)
     u32 n_live;     // records placed by the last binning
-    u32 n_picks;
-    u32 n_matches;
+    u32 n_pl;       // A-B pairs within r_cut found this step
     u32 n_append;
-    u32 n_ovf;      // A particles with more candidates than fit in registers
-    u32 n_ovf_cand; // candidates written by the overflow pass
+    u32 step;       // step number used by every draw of this step
     u32 err;
     u32 n_dbg[4];   // pairs, picks, matches, dissociations logged this step
-    u32 pad[4];
+    u32 pad[6];
     u64 stats[ST_N];
     u64 stats_last[ST_N];
     u64 stats_sum[ST_N];
 };
 
-struct Pick {
-    u32 a_idx, b_idx, a_slot, b_slot;
+// An A-B pair within r_cut (record indices in the sorted buffer).
+struct PairEnt {
+    u32 a_idx, b_idx;
+};
+
+// A candidate (p_enc accepted): its slots and p_enc.
+struct CandEnt {
+    u32 a_slot, b_slot;
     double p;
 };
 
-struct Match {
-    u32 a_idx, b_idx;
-};
+// pair-list entry state
+enum : u32 { PE_PAIR = 0, PE_CAND = 1, PE_PICKED = 2 };
 
 // Debug log entries (same layout as the public sim_dbg_* structs).
 struct DbgPair { u32 i, j; double R, R0, p; u32 draw; int cand; };

@@ -152,12 +152,14 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     // device memory
     Rec<T> *rec[2] = {nullptr, nullptr};
     u32 *rank = nullptr, *cnt = nullptr, *start = nullptr, *bsum = nullptr, *partner = nullptr;
-    Pick *picks = nullptr;
-    u64 *head = nullptr;
-    u32 *next = nullptr, *ovf = nullptr;
-    OvfCand *ovf_cand = nullptr;
-    Match *matches = nullptr;
+    PairEnt *plist = nullptr;
+    CandEnt *cand = nullptr;
+    u32 *flag = nullptr, *nextA = nullptr, *nextB = nullptr;
+    u64 *headA = nullptr, *headB = nullptr;
     Counters *ctr = nullptr;
+    hipStream_t own_stream = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    uint32_t n_bricks = 0;
     double *g2c = nullptr;
     double *g_pos = nullptr, *dbg_moved = nullptr;
     int *g_sp = nullptr;
@@ -175,8 +177,11 @@ template <int DIM, class T, int PM> struct Engine final : sim {
 
     ~Engine() override
     {
-        if (M.stream || true) (void)hipStreamSynchronize(M.stream);
+        (void)hipStreamSynchronize(M.stream);
+        for (auto &g : gexec)
+            if (g) (void)hipGraphExecDestroy(g);
         for (void *p : allocs) (void)hipFree(p);
+        if (own_stream) (void)hipStreamDestroy(own_stream);
         for (auto &e : ev_pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
         for (auto &e : ev_used) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     }
@@ -195,6 +200,10 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     {
         M = m;
         n = nslots;
+        if (!M.stream) {  // a stream of our own: the null stream cannot be captured into a graph
+            HIPCHECK(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
+            M.stream = own_stream;
+        }
         std::memset(&P, 0, sizeof(P));
         P.dim = DIM;
         P.bc = M.bc;
@@ -262,8 +271,28 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         P.n_cells = (u32)ncell;
         P.n_keys = 3u * P.n_cells;
         P.cap = (u32)n;
-        P.cap_picks = std::max<u32>(maxA, 1);
-        P.cap_ovf_cand = (u32)std::max<uint64_t>(1u << 16, n / 4);
+        P.cap_pl = (u32)std::min<uint64_t>(std::max<uint64_t>(1u << 20, 4 * n), 1u << 30);
+        // LDS bricks: about 256 cells, fewer when buckets are crowded
+        P.tiled = P.nc[0] >= 3 && P.nc[1] >= 3 && (DIM == 2 || P.nc[2] >= 3);
+        if (P.tiled) {
+            const double bpc = (double)std::max<uint64_t>(nB + nC, 1) / (double)ncell;
+            const double lcap = (double)LdsRecCap<T>::value;
+            int bb[3] = {std::min(16, P.nc[0] - 2), std::min(DIM == 3 ? 4 : 16, P.nc[1] - 2), DIM == 3 ? std::min(4, P.nc[2] - 2) : 1};
+            auto halo = [&] { return (bb[0] + 2.0) * (bb[1] + 2.0) * (DIM == 3 ? bb[2] + 2.0 : 1.0); };
+            while (halo() * bpc > 0.6 * lcap && (bb[0] > 1 || bb[1] > 1 || bb[2] > 1)) {
+                int k = 0;
+                for (int d = 1; d < DIM; ++d)
+                    if (bb[d] > bb[k]) k = d;
+                bb[k] = (bb[k] + 1) / 2;
+            }
+            P.bx = bb[0];
+            P.by = bb[1];
+            P.bz = bb[2];
+            P.nbx = (P.nc[0] + P.bx - 1) / P.bx;
+            P.nby = (P.nc[1] + P.by - 1) / P.by;
+            P.nbz = DIM == 3 ? (P.nc[2] + P.bz - 1) / P.bz : 1;
+            n_bricks = P.nbx * P.nby * P.nbz;
+        }
         P.debug = M.debug;
         P.dbg_cap = (u32)M.dbg_cap;
         nb_scan = (P.n_keys + SCAN_TILE - 1) / SCAN_TILE;
@@ -271,10 +300,10 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         int rc;
         if ((rc = alloc(rec[0], n)) || (rc = alloc(rec[1], n)) || (rc = alloc(rank, n)) || (rc = alloc(cnt, P.n_keys)) ||
             (rc = alloc(start, P.n_keys + 1)) || (rc = alloc(bsum, nb_scan)) || (rc = alloc(partner, n)) ||
-            (rc = alloc(picks, P.cap_picks)) || (rc = alloc(head, n)) || (rc = alloc(next, P.cap_picks)) ||
-            (rc = alloc(ovf, maxA)) || (rc = alloc(ovf_cand, P.cap_ovf_cand)) || (rc = alloc(matches, P.cap_picks)) ||
-            (rc = alloc(ctr, 1)) || (rc = alloc(g2c, 4 * (MAXTERMS + 1))) || (rc = alloc(g_pos, n * DIM)) ||
-            (rc = alloc(g_sp, n)))
+            (rc = alloc(plist, P.cap_pl)) || (rc = alloc(cand, P.cap_pl)) || (rc = alloc(flag, P.cap_pl)) ||
+            (rc = alloc(nextA, P.cap_pl)) || (rc = alloc(nextB, P.cap_pl)) || (rc = alloc(headA, n)) ||
+            (rc = alloc(headB, n)) || (rc = alloc(ctr, 1)) || (rc = alloc(g2c, 4 * (MAXTERMS + 1))) ||
+            (rc = alloc(g_pos, n * DIM)) || (rc = alloc(g_sp, n)))
             return rc;
         if (M.debug) {
             if ((rc = alloc(dbg_moved, n * DIM)) || (rc = alloc(dbg_cells, n)) || (rc = alloc(dbg_pairs, M.dbg_cap)) ||
@@ -282,7 +311,6 @@ template <int DIM, class T, int PM> struct Engine final : sim {
                 return rc;
         }
         HIPCHECK(hipMemsetAsync(cnt, 0, sizeof(u32) * P.n_keys, M.stream));
-        HIPCHECK(hipMemsetAsync(head, 0, sizeof(u64) * n, M.stream));
         double g2h[4 * (MAXTERMS + 1)];
         h_g2_constants(P.hh, g2h);
         HIPCHECK(hipMemcpyAsync(g2c, g2h, sizeof(g2h), hipMemcpyHostToDevice, M.stream));
@@ -311,8 +339,10 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         std::memset(&c, 0, sizeof(c));
         c.n_rec = (u32)live;
         c.n_live = (u32)live;
+        c.step = (u32)step0;
         HIPCHECK(hipMemcpyAsync(ctr, &c, sizeof(c), hipMemcpyHostToDevice, M.stream));
-        HIPCHECK(hipMemsetAsync(head, 0, sizeof(u64) * n, M.stream));  // no chain survives a reload
+        HIPCHECK(hipMemsetAsync(headA, 0, sizeof(u64) * n, M.stream));  // no chain survives a reload
+        HIPCHECK(hipMemsetAsync(headB, 0, sizeof(u64) * n, M.stream));
         HIPCHECK(hipStreamSynchronize(M.stream));
         cur = 0;
         stepno = step0;
@@ -342,20 +372,20 @@ template <int DIM, class T, int PM> struct Engine final : sim {
 
     static u32 grid_for(uint64_t work, u32 maxg) { return (u32)std::max<uint64_t>(1, std::min<uint64_t>((work + BLOCK - 1) / BLOCK, maxg)); }
 
-    int one_step()
+    // Launches one step reading record buffer c and writing buffer c ^ 1.
+    void enqueue_step(int c)
     {
-        const u32 s = (u32)stepno;
         hipStream_t st = M.stream;
-        Rec<T> *in = rec[cur], *out = rec[cur ^ 1];
+        Rec<T> *in = rec[c], *out = rec[c ^ 1];
         const u32 g_all = grid_for(n, 8192);
-        launch(SIM_K_MOVE, [&] { k_move_count<DIM, T><<<g_all, BLOCK, 0, st>>>(P, in, rank, cnt, ctr, s); });
+        const u32 g_pl = 1024;
+        launch(SIM_K_MOVE, [&] { k_move_count<DIM, T><<<g_all, BLOCK, 0, st>>>(P, in, rank, cnt, ctr); });
         launch(SIM_K_SCAN, [&] {
             k_scan_reduce<<<nb_scan, BLOCK, 0, st>>>(cnt, P.n_keys, bsum);
             k_scan_top<<<1, BLOCK, 0, st>>>(bsum, nb_scan);
             k_scan_down<<<nb_scan, BLOCK, 0, st>>>(cnt, P.n_keys, bsum, start, ctr);
         });
-        launch(SIM_K_SCATTER, [&] { k_scatter<DIM, T><<<g_all, BLOCK, 0, st>>>(P, in, rank, start, out, ctr, s); });
-        cur ^= 1;
+        launch(SIM_K_SCATTER, [&] { k_scatter<DIM, T><<<g_all, BLOCK, 0, st>>>(P, in, rank, start, out, ctr); });
         if (M.debug) {
             k_fill<<<grid_for(n * DIM, 2048), BLOCK, 0, st>>>(dbg_moved, n * DIM, (int *)dbg_cells, (u32)n);
             k_gather<DIM, T><<<g_all, BLOCK, 0, st>>>(out, partner, ctr, 1, dbg_moved, nullptr, (u32)n);
@@ -364,19 +394,39 @@ template <int DIM, class T, int PM> struct Engine final : sim {
                                                  dbg_cells);
         }
         launch(SIM_K_PAIRS, [&] {
-            k_pairs<DIM, T, PM><<<grid_for(maxA, 8192), BLOCK, 0, st>>>(P, out, start, picks, ovf, ctr, dbg_pairs, s);
-            k_pairs_overflow<DIM, T, PM><<<64, BLOCK, 0, st>>>(P, out, start, ovf, ovf_cand, picks, ctr, s);
+            if (P.tiled) k_pair_scan<DIM, T, PM><<<n_bricks, BLOCK, 0, st>>>(P, out, start, plist, ctr);
+            else k_pair_scan_global<DIM, T, PM><<<grid_for(maxA, 4096), BLOCK, 0, st>>>(P, out, start, plist, ctr);
         });
-        launch(SIM_K_SELECT, [&] {
-            k_link<<<grid_for(P.cap_picks, 1024), BLOCK, 0, st>>>(picks, head, next, ctr, P, s);
-            k_select_b<<<grid_for(P.cap_picks, 1024), BLOCK, 0, st>>>(P, picks, head, next, matches, ctr, dbg_picks, s);
+        launch(SIM_K_EVAL, [&] { k_pair_eval<DIM, T, PM><<<g_pl, BLOCK, 0, st>>>(P, out, plist, cand, flag, headA, nextA, ctr, dbg_pairs); });
+        launch(SIM_K_SELECT, [&] { k_select_a<<<g_pl, BLOCK, 0, st>>>(P, plist, cand, flag, headA, nextA, headB, nextB, ctr, dbg_picks); });
+        launch(SIM_K_REACT, [&] {
+            k_select_b_react<DIM, T><<<g_pl, BLOCK, 0, st>>>(P, out, plist, cand, flag, headB, nextB, partner, ctr, dbg_matches);
         });
-        launch(SIM_K_REACT, [&] { k_react<DIM, T><<<grid_for(P.cap_picks, 1024), BLOCK, 0, st>>>(P, out, matches, partner, ctr, dbg_matches, s); });
         if (P.reversible)
-            launch(SIM_K_DISSOCIATE, [&] { k_dissociate<DIM, T><<<grid_for(maxC, 4096), BLOCK, 0, st>>>(P, out, start, partner, ctr, dbg_diss, s); });
+            launch(SIM_K_DISSOCIATE, [&] { k_dissociate<DIM, T><<<grid_for(maxC, 4096), BLOCK, 0, st>>>(P, out, start, partner, ctr, dbg_diss); });
         launch(SIM_K_FINISH, [&] { k_finish<<<1, 1, 0, st>>>(ctr); });
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return fail(SIM_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
+
+    int one_step()
+    {
+        const bool graph = !M.debug && !M.timing;
+        if (graph) {
+            if (!gexec[cur]) {
+                hipGraph_t g = nullptr;
+                HIPCHECK(hipStreamBeginCapture(M.stream, hipStreamCaptureModeThreadLocal));
+                enqueue_step(cur);
+                HIPCHECK(hipStreamEndCapture(M.stream, &g));
+                const hipError_t e = hipGraphInstantiate(&gexec[cur], g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) return fail(SIM_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+            }
+            HIPCHECK(hipGraphLaunch(gexec[cur], M.stream));
+        } else {
+            enqueue_step(cur);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return fail(SIM_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+        }
+        cur ^= 1;
         ++stepno;
         return SIM_OK;
     }

@@ -171,26 +171,30 @@ __device__ inline double reac_prob(const Params &P, int dim, double R, double R0
 // Radial propagator sampler.
 // ---------------------------------------------------------------------------
 
-// The y >= yc with erfc(y) = u erfc(yc): Newton steps on
+// The y >= yc with erfc(y) = u erfc(yc).  Start from erfcinv of the target
+// (or, when the target underflows, from the leading large-y form
+// erfc(y) ~ e^{-y^2}/(y sqrt(pi))), then Newton steps on
 // f(y) = ln erfcx(y) - y^2 - ln(u erfc(yc)), f'(y) = -2/(sqrt(pi) erfcx(y)),
-// kept inside a shrinking bracket.
+// which converge quadratically from there.
 __device__ inline double erfc_tail_inv(double yc, double u)
 {
-    const double tgt = log(u) + log(erfcx(yc)) - yc * yc;
-    double lo = yc, hi = yc + 1.0;
-    while (log(erfcx(hi)) - hi * hi > tgt) hi = 2.0 * hi + 1.0;
-    double y = fmax(yc, sqrt(fmax(0.0, -tgt)));
-    if (!(y > lo && y < hi)) y = 0.5 * (lo + hi);
-    for (int it = 0; it < 200; ++it) {
+    const double lt = log(u) + log(erfcx(yc)) - yc * yc;  // ln of the target
+    double y;
+    if (lt > -700.0) {
+        y = erfcinv(exp(lt));
+    } else {
+        const double s = sqrt(-lt);
+        y = sqrt(fmax(-lt - log(s * SQRTPI_D), 0.0));
+    }
+    if (!(y >= yc)) y = yc;
+    for (int it = 0; it < 6; ++it) {
         const double ex = erfcx(y);
-        const double f = log(ex) - y * y - tgt;
-        if (f > 0.0) lo = y;
-        else hi = y;
-        double yn = y + f * ex * (0.5 * SQRTPI_D);
-        if (!(yn > lo && yn < hi)) yn = 0.5 * (lo + hi);
-        const double dy = yn - y;
+        const double dy = (log(ex) - y * y - lt) * ex * (0.5 * SQRTPI_D);
+        double yn = y + dy;
+        if (!(yn >= yc)) yn = yc;
+        const bool done = fabs(yn - y) <= 2e-16 * y;
         y = yn;
-        if (fabs(dy) <= 1e-16 * (1.0 + fabs(y))) break;
+        if (done) break;
     }
     return y;
 }

@@ -87,8 +87,9 @@ template <int DIM, class T> __device__ inline u32 cell_of(const Params &P, const
 // ---------------------------------------------------------------------------
 template <int DIM, class T>
 __global__ __launch_bounds__(BLOCK) void k_move_count(Params P, const Rec<T> *__restrict__ rec, u32 *__restrict__ rank,
-                                                       u32 *__restrict__ cnt, Counters *C, u32 step)
+                                                       u32 *__restrict__ cnt, Counters *C)
 {
+    const u32 step = C->step;
     if (gtid() == 0) {
         C->n_dbg[0] = C->n_dbg[1] = C->n_dbg[2] = C->n_dbg[3] = 0;
     }
@@ -199,9 +200,9 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(u32 *__restrict__ cnt, u32 
 // ---------------------------------------------------------------------------
 template <int DIM, class T>
 __global__ __launch_bounds__(BLOCK) void k_scatter(Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ rank,
-                                                    const u32 *__restrict__ start, Rec<T> *__restrict__ out, const Counters *C,
-                                                    u32 step)
+                                                    const u32 *__restrict__ start, Rec<T> *__restrict__ out, const Counters *C)
 {
+    const u32 step = C->step;
     const u32 n = C->n_rec;
     for (u32 i = gtid(); i < n; i += gstride()) {
         const Rec<T> r = rec[i];
@@ -386,11 +387,14 @@ __device__ inline void for_pairs(const Params &P, const Rec<T> *__restrict__ rec
 }
 
 // ---------------------------------------------------------------------------
-// K5: pairs, encounter probabilities, Bernoulli draws and the A-side choice
-// among several candidates (Sec. 3, Details): candidates in ascending B slot,
-// pick the first k with U sum(p) <= p_1 + ... + p_k, U = {a, -, step, SELA}.
+// K5a: A-B pairs within r_cut.  One workgroup per brick of bx*by*bz cells:
+// the B records of the brick and its one-cell halo are staged in LDS (bucket
+// ranges of consecutive cells are contiguous), then every A of the brick
+// tests the B's of its 3^d neighbour cells from LDS.  Pairs go to an LDS
+// queue that is appended to the global pair list once per workgroup.  A
+// brick whose halo holds more B's than fit in LDS tests from global memory.
 // ---------------------------------------------------------------------------
-__device__ inline void block_add_stats(u32 *vals, int nv, u64 *dst, u32 *lds)
+__device__ inline void block_add_stats(const u32 *vals, int nv, u64 *dst, u32 *lds)
 {
     for (int s = 0; s < nv; ++s) {
         const u32 t = block_sum(vals[s], lds);
@@ -398,360 +402,415 @@ __device__ inline void block_add_stats(u32 *vals, int nv, u64 *dst, u32 *lds)
     }
 }
 
-template <int DIM, class T, int PM>
-__global__ __launch_bounds__(BLOCK) void k_pairs(Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start,
-                                                  Pick *__restrict__ picks, u32 *__restrict__ ovf, Counters *C, DbgPair *dbg,
-                                                  u32 step)
-{
-    __shared__ u32 lds[BLOCK / 64];
-    const u32 a_beg = start[0], a_end = start[P.n_cells];
-    u32 st[5] = {0, 0, 0, 0, 0};  // pairs, cand, overlap, r0clamp, near
-    u32 n_ovf_local = 0;
-    const u32 iters = (a_end - a_beg + gstride() - 1) / gstride();
-    for (u32 it = 0; it < iters; ++it) {
-        const u32 ia = a_beg + it * gstride() + gtid();
-        const bool active = ia < a_end;
-        u32 cs[CMAX], ci[CMAX];
-        double cp[CMAX];
-        int m = 0;
-        u32 sa = 0;
-        if (active) {
-            const Rec<T> ra = rec[ia];
-            sa = meta_slot(rec_meta(ra));
-            double dA[3];
-            bool have_dA = false;
-            for_pairs<DIM, T, PM>(P, rec, start, ra, [&](u32 jb, const Rec<T> &rb) {
-                if (!have_dA) {
-                    displacement<DIM>(P, sa, SP_A, step, dA);
-                    have_dA = true;
-                }
-                const u32 sb = meta_slot(rec_meta(rb));
-                const PairQ q = pair_quantities<DIM, T, PM>(P, ra, rb, sa, sb, dA, step);
-                st[0] += 1;
-                st[1] += q.cand;
-                st[2] += q.overlap;
-                st[3] += q.clamped;
-                st[4] += q.near;
-                if (P.debug) {
-                    const u32 k = atomicAdd(&C->n_dbg[0], 1u);
-                    if (k < P.dbg_cap) {
-                        DbgPair d;
-                        d.i = sa; d.j = sb; d.R = q.R; d.R0 = q.R0; d.p = q.p; d.draw = q.draw; d.cand = q.cand;
-                        dbg[k] = d;
-                    }
-                }
-                if (!q.cand) return;
-                // sorted insertion by B slot, static register indexing
-                if (m < CMAX) {
-                    int pos = 0;
-#pragma unroll
-                    for (int k = 0; k < CMAX; ++k) pos += (k < m && cs[k] < sb) ? 1 : 0;
-#pragma unroll
-                    for (int k = CMAX - 1; k > 0; --k)
-                        if (k > pos && k <= m) {
-                            cs[k] = cs[k - 1];
-                            ci[k] = ci[k - 1];
-                            cp[k] = cp[k - 1];
-                        }
-#pragma unroll
-                    for (int k = 0; k < CMAX; ++k)
-                        if (k == pos) {
-                            cs[k] = sb;
-                            ci[k] = jb;
-                            cp[k] = q.p;
-                        }
-                }
-                ++m;
-            });
-        }
-        const bool has = active && m > 0 && m <= CMAX;
-        u32 pb = 0, pslot = 0;
-        double pp = 0.0;
-        if (has) {
-            double T_ = 0.0;
-#pragma unroll
-            for (int k = 0; k < CMAX; ++k)
-                if (k < m) T_ += cp[k];
-            const double tgt = u01(philox(sa, NOSLOT, step, TAG_SELA, P.key).x) * T_;
-            double acc = 0.0;
-            bool found = false;
-#pragma unroll
-            for (int k = 0; k < CMAX; ++k)
-                if (k < m && !found) {
-                    acc += cp[k];
-                    pb = ci[k];
-                    pslot = cs[k];
-                    pp = cp[k];
-                    if (tgt <= acc) found = true;
-                }
-        }
-        const u64 mask = __ballot(has);
-        if (mask) {
-            const int leader = __ffsll((unsigned long long)mask) - 1;
-            u32 base = 0;
-            if (lane_id() == leader) base = atomicAdd(&C->n_picks, (u32)__popcll(mask));
-            base = __shfl(base, leader, 64);
-            if (has) {
-                const u32 k = base + (u32)__popcll(mask & ((1ull << lane_id()) - 1ull));
-                if (k < P.cap_picks) {
-                    Pick pk;
-                    pk.a_idx = ia; pk.b_idx = pb; pk.a_slot = sa; pk.b_slot = pslot; pk.p = pp;
-                    picks[k] = pk;
-                } else {
-                    atomicOr(&C->err, (u32)ERR_PICKS);
-                }
-            }
-        }
-        if (active && m > CMAX) {
-            const u32 k = atomicAdd(&C->n_ovf, 1u);
-            ovf[k] = ia;
-            ++n_ovf_local;
-        }
-    }
-    u32 vals[6] = {st[0], st[1], st[2], st[3], st[4], n_ovf_local};
-    block_add_stats(vals, 4, &C->stats[ST_PAIRS], lds);
-    u32 v2[1] = {vals[4]};
-    block_add_stats(v2, 1, &C->stats[ST_NEAR], lds);
-    u32 v3[1] = {vals[5]};
-    block_add_stats(v3, 1, &C->stats[ST_CAND_OVERFLOW], lds);
-}
-
-// K5b: A particles with more than CMAX candidates: visit the neighbours again,
-// write all candidates to a scratch list, sort it by B slot, pick.
-struct OvfCand {
-    u32 slot, idx;
-    double p;
+constexpr int QCAP = 1024;       // pairs queued in LDS per workgroup
+constexpr int MAX_HALO = 1024;   // halo cells per brick
+constexpr int MAX_ROWS = 64;     // rows of A cells per brick
+template <class T> struct LdsRecCap {
+    static constexpr int value = sizeof(T) == 4 ? 2048 : 1024;
 };
 
-template <int DIM, class T, int PM>
-__global__ __launch_bounds__(BLOCK) void k_pairs_overflow(Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start,
-                                                           const u32 *__restrict__ ovf, OvfCand *__restrict__ cand,
-                                                           Pick *__restrict__ picks, Counters *C, u32 step)
+__device__ __forceinline__ void append_pair(PairEnt *q, u32 *nq, PairEnt *list, Counters *C, const Params &P, u32 a, u32 b)
 {
-    const u32 n = C->n_ovf;
-    for (u32 k = gtid(); k < n; k += gstride()) {
-        const u32 ia = ovf[k];
+    const u32 k = atomicAdd(nq, 1u);
+    PairEnt e;
+    e.a_idx = a;
+    e.b_idx = b;
+    if (k < (u32)QCAP) {
+        q[k] = e;
+    } else {
+        const u32 g = atomicAdd(&C->n_pl, 1u);
+        if (g < P.cap_pl) list[g] = e;
+        else atomicOr(&C->err, (u32)ERR_PAIRS);
+    }
+}
+
+__device__ __forceinline__ int wrapc(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+
+template <int DIM, class T, int PM>
+__global__ __launch_bounds__(BLOCK) void k_pair_scan(Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start,
+                                                      PairEnt *__restrict__ list, Counters *C)
+{
+    constexpr int LCAP = LdsRecCap<T>::value;
+    __shared__ Rec<T> sb[LCAP];
+    __shared__ u32 sidx[LCAP];
+    __shared__ u32 off[MAX_HALO + 1];
+    __shared__ u32 rowpre[MAX_ROWS + 1], rowst[MAX_ROWS];
+    __shared__ PairEnt q[QCAP];
+    __shared__ u32 nq, qbase;
+    __shared__ u32 lds[BLOCK / 64];
+
+    const int nx = P.nc[0], ny = P.nc[1], nz = P.nc[2];
+    u32 b = blockIdx.x;
+    const int x0 = (int)(b % P.nbx) * P.bx;
+    b /= P.nbx;
+    const int y0 = (int)(b % P.nby) * P.by;
+    b /= P.nby;
+    const int z0 = DIM == 3 ? (int)b * P.bz : 0;
+    const int ex = min(P.bx, nx - x0), ey = min(P.by, ny - y0), ez = DIM == 3 ? min(P.bz, nz - z0) : 1;
+    const int hx = ex + 2, hy = ey + 2, hz = DIM == 3 ? ez + 2 : 1;
+    const int nh = hx * hy * hz;
+    const u32 bbase = P.n_cells;
+    auto halo_key = [&](int h) -> u32 {
+        const int gx = wrapc(x0 - 1 + h % hx, nx);
+        const int gy = wrapc(y0 - 1 + (h / hx) % hy, ny);
+        const int gz = DIM == 3 ? wrapc(z0 - 1 + h / (hx * hy), nz) : 0;
+        return bbase + ((u32)gz * ny + gy) * nx + gx;
+    };
+
+    // bucket sizes of the halo cells and their running sum
+    u32 carry = 0;
+    for (int h0 = 0; h0 < nh; h0 += BLOCK) {
+        const int h = h0 + threadIdx.x;
+        u32 c = 0;
+        if (h < nh) {
+            const u32 k = halo_key(h);
+            c = start[k + 1] - start[k];
+        }
+        u32 tot;
+        const u32 ex_ = block_excl_scan(c, lds, tot);
+        if (h < nh) off[h] = carry + ex_;
+        carry += tot;
+    }
+    // A records of the brick: one contiguous bucket range per row of cells
+    const int nr = ey * ez;
+    if (threadIdx.x < 64) {
+        const int r = threadIdx.x;
+        u32 cnt_ = 0;
+        if (r < nr) {
+            const u32 akey = ((u32)(z0 + r / ey) * ny + (y0 + r % ey)) * nx + x0;
+            rowst[r] = start[akey];
+            cnt_ = start[akey + ex] - rowst[r];
+        }
+        const u32 inc = wave_incl_scan(cnt_);
+        if (r < nr) rowpre[r + 1] = inc;
+        if (r == 0) rowpre[0] = 0;
+    }
+    if (threadIdx.x == 0) {
+        off[nh] = carry;
+        nq = 0;
+    }
+    __syncthreads();
+    const u32 total = off[nh];
+    const bool use_lds = total <= (u32)LCAP;
+    if (use_lds) {
+        for (u32 i = threadIdx.x; i < total; i += BLOCK) {
+            int lo = 0, hi = nh;  // off[lo] <= i < off[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (off[mid] <= i) lo = mid;
+                else hi = mid;
+            }
+            const u32 src = start[halo_key(lo)] + (i - off[lo]);
+            sb[i] = rec[src];
+            sidx[i] = src;
+        }
+    } else if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long *)&C->stats[ST_LDS_FALLBACK], 1ull);
+    }
+    __syncthreads();
+    const u32 nA = rowpre[nr];
+    for (u32 i = threadIdx.x; i < nA; i += BLOCK) {
+        int r = 0;
+        while (r + 1 < nr && rowpre[r + 1] <= i) ++r;
+        const u32 ia = rowst[r] + (i - rowpre[r]);
         const Rec<T> ra = rec[ia];
-        const u32 sa = meta_slot(rec_meta(ra));
+        if (use_lds) {
+            const int lx = cell1((double)ra.x, P.cs[0], nx) - x0 + 1;
+            const int ly = cell1((double)ra.y, P.cs[1], ny) - y0 + 1;
+            const int lz = DIM == 3 ? cell1((double)ra.z, P.cs[2], nz) - z0 + 1 : 0;
+            const int zlo = DIM == 3 ? -1 : 0, zhi = -zlo;
+            for (int dz = zlo; dz <= zhi; ++dz)
+                for (int dy = -1; dy <= 1; ++dy) {
+                    const int h0 = ((lz + dz) * hy + (ly + dy)) * hx + (lx - 1);
+                    const u32 je = off[h0 + 3];
+                    for (u32 j = off[h0]; j < je; ++j)
+                        if (in_range<DIM, T, PM>(P, ra, sb[j])) append_pair(q, &nq, list, C, P, ia, sidx[j]);
+                }
+        } else {
+            for_pairs<DIM, T, PM>(P, rec, start, ra, [&](u32 jb, const Rec<T> &) { append_pair(q, &nq, list, C, P, ia, jb); });
+        }
+    }
+    __syncthreads();
+    const u32 n = min(nq, (u32)QCAP);
+    if (threadIdx.x == 0) qbase = n ? atomicAdd(&C->n_pl, n) : 0u;
+    __syncthreads();
+    for (u32 i = threadIdx.x; i < n; i += BLOCK) {
+        const u32 g = qbase + i;
+        if (g < P.cap_pl) list[g] = q[i];
+        else atomicOr(&C->err, (u32)ERR_PAIRS);
+    }
+}
+
+// K5a for grids with fewer than three cells along some axis: one thread per A
+// record, neighbour buckets read from global memory.
+template <int DIM, class T, int PM>
+__global__ __launch_bounds__(BLOCK) void k_pair_scan_global(Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start,
+                                                             PairEnt *__restrict__ list, Counters *C)
+{
+    const u32 a_beg = start[0], a_end = start[P.n_cells];
+    for (u32 ia = a_beg + gtid(); ia < a_end; ia += gstride()) {
+        const Rec<T> ra = rec[ia];
+        for_pairs<DIM, T, PM>(P, rec, start, ra, [&](u32 jb, const Rec<T> &) {
+            const u32 g = atomicAdd(&C->n_pl, 1u);
+            PairEnt e;
+            e.a_idx = ia;
+            e.b_idx = jb;
+            if (g < P.cap_pl) list[g] = e;
+            else atomicOr(&C->err, (u32)ERR_PAIRS);
+        });
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K5b: encounter probability and Bernoulli draw of every pair (one thread per
+// pair).  Candidates are chained per A record through a head word tagged
+// with the step, so no list needs clearing between steps.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ u32 chain_push(u64 *head, u32 rec_idx, u32 entry, u32 step)
+{
+    const u64 tag = (u64)(step + 1u) << 32;
+    const u64 prev = atomicExch((unsigned long long *)&head[rec_idx], (unsigned long long)(tag | entry));
+    return (prev >> 32) == (u64)(step + 1u) ? (u32)prev : NOSLOT;
+}
+
+template <int DIM, class T, int PM>
+__global__ __launch_bounds__(BLOCK) void k_pair_eval(Params P, const Rec<T> *__restrict__ rec, const PairEnt *__restrict__ list,
+                                                      CandEnt *__restrict__ cand, u32 *__restrict__ flag, u64 *__restrict__ headA,
+                                                      u32 *__restrict__ nextA, Counters *C, DbgPair *dbg)
+{
+    __shared__ u32 lds[BLOCK / 64];
+    const u32 step = C->step;
+    const u32 n = min(C->n_pl, P.cap_pl);
+    u32 st[5] = {0, 0, 0, 0, 0};  // pairs, cand, overlap, r0clamp, near
+    for (u32 k = gtid(); k < n; k += gstride()) {
+        const PairEnt e = list[k];
+        const Rec<T> ra = rec[e.a_idx], rb = rec[e.b_idx];
+        const u32 sa = meta_slot(rec_meta(ra)), sb = meta_slot(rec_meta(rb));
         double dA[3];
         displacement<DIM>(P, sa, SP_A, step, dA);
-        u32 m = 0;
-        for_pairs<DIM, T, PM>(P, rec, start, ra, [&](u32, const Rec<T> &rb) {
-            const PairQ q = pair_quantities<DIM, T, PM>(P, ra, rb, sa, meta_slot(rec_meta(rb)), dA, step);
-            m += q.cand;
-        });
-        const u32 base = atomicAdd(&C->n_ovf_cand, m);
-        if (base + m > P.cap_ovf_cand) {
-            atomicOr(&C->err, (u32)ERR_OVF_CAND);
-            continue;
-        }
-        u32 w = 0;
-        for_pairs<DIM, T, PM>(P, rec, start, ra, [&](u32 jb, const Rec<T> &rb) {
-            const u32 sb = meta_slot(rec_meta(rb));
-            const PairQ q = pair_quantities<DIM, T, PM>(P, ra, rb, sa, sb, dA, step);
-            if (q.cand && w < m) {
-                OvfCand c;
-                c.slot = sb; c.idx = jb; c.p = q.p;
-                cand[base + w++] = c;
-            }
-        });
-        OvfCand *L = cand + base;
-        for (u32 i = 1; i < m; ++i) {
-            const OvfCand x = L[i];
-            u32 j = i;
-            while (j > 0 && L[j - 1].slot > x.slot) {
-                L[j] = L[j - 1];
-                --j;
-            }
-            L[j] = x;
-        }
-        double T_ = 0.0;
-        for (u32 i = 0; i < m; ++i) T_ += L[i].p;
-        const double tgt = u01(philox(sa, NOSLOT, step, TAG_SELA, P.key).x) * T_;
-        double acc = 0.0;
-        u32 ch = m - 1;
-        for (u32 i = 0; i < m; ++i) {
-            acc += L[i].p;
-            if (tgt <= acc) {
-                ch = i;
-                break;
-            }
-        }
-        const u32 q = atomicAdd(&C->n_picks, 1u);
-        if (q < P.cap_picks) {
-            Pick pk;
-            pk.a_idx = ia; pk.b_idx = L[ch].idx; pk.a_slot = sa; pk.b_slot = L[ch].slot; pk.p = L[ch].p;
-            picks[q] = pk;
-        } else {
-            atomicOr(&C->err, (u32)ERR_PICKS);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// K6: B-side choice.  Picks of the same B are chained through a per-record
-// head word tagged with the step; the suitor with the smallest A slot walks
-// the chain in ascending A slot and applies the cumulative rule with
-// U = {b, -, step, SELB}.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_link(const Pick *__restrict__ picks, u64 *__restrict__ head, u32 *__restrict__ next,
-                                                 Counters *C, Params P, u32 step)
-{
-    const u32 n = min(C->n_picks, P.cap_picks);
-    const u64 tag = (u64)(step + 1u) << 32;
-    for (u32 k = gtid(); k < n; k += gstride()) {
-        const u64 prev = atomicExch((unsigned long long *)&head[picks[k].b_idx], (unsigned long long)(tag | k));
-        next[k] = (prev >> 32) == (u64)(step + 1u) ? (u32)prev : NOSLOT;
-    }
-}
-
-__global__ __launch_bounds__(BLOCK) void k_select_b(Params P, const Pick *__restrict__ picks, const u64 *__restrict__ head,
-                                                     const u32 *__restrict__ next, Match *__restrict__ matches, Counters *C,
-                                                     DbgPick *dbg, u32 step)
-{
-    const u32 n = min(C->n_picks, P.cap_picks);
-    for (u32 k = gtid(); k < n; k += gstride()) {
-        const Pick me = picks[k];
+        const PairQ q = pair_quantities<DIM, T, PM>(P, ra, rb, sa, sb, dA, step);
+        st[0] += 1;
+        st[1] += q.cand;
+        st[2] += q.overlap;
+        st[3] += q.clamped;
+        st[4] += q.near;
         if (P.debug) {
-            const u32 q = atomicAdd(&C->n_dbg[1], 1u);
-            if (q < P.dbg_cap) {
-                DbgPick d;
-                d.i = me.a_slot; d.j = me.b_slot; d.p = me.p;
-                dbg[q] = d;
+            const u32 d = atomicAdd(&C->n_dbg[0], 1u);
+            if (d < P.dbg_cap) {
+                DbgPair g;
+                g.i = sa; g.j = sb; g.R = q.R; g.R0 = q.R0; g.p = q.p; g.draw = q.draw; g.cand = q.cand;
+                dbg[d] = g;
             }
         }
-        const u32 h = (u32)head[me.b_idx];
-        // leader: the suitor with the smallest A slot
+        flag[k] = q.cand ? PE_CAND : PE_PAIR;
+        if (q.cand) {
+            CandEnt c;
+            c.a_slot = sa;
+            c.b_slot = sb;
+            c.p = q.p;
+            cand[k] = c;
+            nextA[k] = chain_push(headA, e.a_idx, k, step);
+        }
+    }
+    block_add_stats(st, 4, &C->stats[ST_PAIRS], lds);
+    block_add_stats(st + 4, 1, &C->stats[ST_NEAR], lds);
+}
+
+// The cumulative rule of Sec. 3 (Details) over one chain, members in
+// ascending order of `key` (a slot): the first member k with
+// U * sum(p) <= p_1 + ... + p_k.  `key_of(e)` and `p_of(e)` read member e.
+template <class K, class Pf>
+__device__ inline u32 choose_in_chain(u32 head, const u32 *__restrict__ next, u32 count, double U, K &&key_of, Pf &&p_of)
+{
+    double T_ = 0.0;
+    u32 prev = 0;
+    bool first = true;
+    for (u32 r = 0; r < count; ++r) {
+        u32 best = NOSLOT, be = NOSLOT;
+        for (u32 e = head; e != NOSLOT; e = next[e]) {
+            const u32 s = key_of(e);
+            if ((first || s > prev) && s < best) {
+                best = s;
+                be = e;
+            }
+        }
+        if (be == NOSLOT) break;
+        T_ += p_of(be);
+        prev = best;
+        first = false;
+    }
+    const double tgt = U * T_;
+    double acc = 0.0;
+    u32 win = NOSLOT;
+    first = true;
+    for (u32 r = 0; r < count; ++r) {
+        u32 best = NOSLOT, be = NOSLOT;
+        for (u32 e = head; e != NOSLOT; e = next[e]) {
+            const u32 s = key_of(e);
+            if ((first || s > prev) && s < best) {
+                best = s;
+                be = e;
+            }
+        }
+        if (be == NOSLOT) break;
+        acc += p_of(be);
+        prev = best;
+        first = false;
+        win = be;
+        if (tgt <= acc) break;
+    }
+    return win;
+}
+
+// ---------------------------------------------------------------------------
+// K5c: A-side choice.  The candidate with the smallest B slot of each A
+// chain leads; it applies the rule with U = {a, -, step, SELA} and chains
+// the chosen entry under its B record.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_select_a(Params P, const PairEnt *__restrict__ list, const CandEnt *__restrict__ cand,
+                                                     u32 *__restrict__ flag, const u64 *__restrict__ headA,
+                                                     const u32 *__restrict__ nextA, u64 *__restrict__ headB, u32 *__restrict__ nextB,
+                                                     Counters *C, DbgPick *dbg)
+{
+    const u32 step = C->step;
+    const u32 n = min(C->n_pl, P.cap_pl);
+    u32 picks = 0;
+    for (u32 k = gtid(); k < n; k += gstride()) {
+        if (flag[k] == PE_PAIR) continue;
+        const CandEnt me = cand[k];
+        const u32 h = (u32)headA[list[k].a_idx];
         u32 mins = NOSLOT, count = 0;
-        for (u32 e = h; e != NOSLOT; e = next[e]) {
-            mins = min(mins, picks[e].a_slot);
+        for (u32 e = h; e != NOSLOT; e = nextA[e]) {
+            mins = min(mins, cand[e].b_slot);
             ++count;
         }
-        if (me.a_slot != mins) continue;
+        if (me.b_slot != mins) continue;
         u32 win = k;
         if (count > 1) {
-            double T_ = 0.0;
-            u32 prev = 0;
-            bool first = true;
-            for (u32 r = 0; r < count; ++r) {  // ascending A slot
-                u32 best = NOSLOT, be = NOSLOT;
-                for (u32 e = h; e != NOSLOT; e = next[e]) {
-                    const u32 s = picks[e].a_slot;
-                    if ((first || s > prev) && s < best) {
-                        best = s;
-                        be = e;
-                    }
-                }
-                if (be == NOSLOT) break;
-                T_ += picks[be].p;
-                prev = best;
-                first = false;
-            }
-            const double tgt = u01(philox(me.b_slot, NOSLOT, step, TAG_SELB, P.key).x) * T_;
-            double acc = 0.0;
-            first = true;
-            for (u32 r = 0; r < count; ++r) {
-                u32 best = NOSLOT, be = NOSLOT;
-                for (u32 e = h; e != NOSLOT; e = next[e]) {
-                    const u32 s = picks[e].a_slot;
-                    if ((first || s > prev) && s < best) {
-                        best = s;
-                        be = e;
-                    }
-                }
-                if (be == NOSLOT) break;
-                acc += picks[be].p;
-                prev = best;
-                first = false;
-                win = be;
-                if (tgt <= acc) break;
+            const double U = u01(philox(me.a_slot, NOSLOT, step, TAG_SELA, P.key).x);
+            win = choose_in_chain(h, nextA, count, U, [&](u32 e) { return cand[e].b_slot; }, [&](u32 e) { return cand[e].p; });
+            if (win == NOSLOT) win = k;
+        }
+        flag[win] = PE_PICKED;
+        ++picks;
+        nextB[win] = chain_push(headB, list[win].b_idx, win, step);
+        if (P.debug) {
+            const u32 d = atomicAdd(&C->n_dbg[1], 1u);
+            if (d < P.dbg_cap) {
+                DbgPick g;
+                g.i = cand[win].a_slot; g.j = cand[win].b_slot; g.p = cand[win].p;
+                dbg[d] = g;
             }
         }
-        const u32 q = atomicAdd(&C->n_matches, 1u);
-        Match mt;
-        mt.a_idx = picks[win].a_idx;
-        mt.b_idx = picks[win].b_idx;
-        matches[q] = mt;
     }
+    if (picks) atomicAdd((unsigned long long *)&C->stats[ST_PICKS], (unsigned long long)picks);
 }
 
 // ---------------------------------------------------------------------------
-// K7: matched pairs (Sec. 3, steps 2a-2c).
+// K6/K7: B-side choice and the encountered pair (Sec. 3, steps 2a-2c).  The
+// picked entry with the smallest A slot of each B chain leads; it applies the
+// rule with U = {b, -, step, SELB} and then propagates / reacts the winner.
+// Each record belongs to at most one match, so the leader owns both records.
 // ---------------------------------------------------------------------------
 template <int DIM, class T>
-__global__ __launch_bounds__(BLOCK) void k_react(Params P, Rec<T> *__restrict__ rec, const Match *__restrict__ matches,
-                                                  u32 *__restrict__ partner, Counters *C, DbgMatch *dbg, u32 step)
+__device__ inline void react_pair(const Params &P, Rec<T> *__restrict__ rec, u32 ia, u32 ib, u32 *__restrict__ partner, u32 step,
+                                  Counters *C, DbgMatch *dbg, u32 &n_react, u32 &n_att, u32 &n_hits, u32 &n_near)
 {
 #pragma clang fp contract(off)
-    const u32 n = C->n_matches;
-    u32 n_react = 0, n_att = 0, n_hits = 0, n_near = 0;
-    for (u32 k = gtid(); k < n; k += gstride()) {
-        const Match mt = matches[k];
-        Rec<T> ra = rec[mt.a_idx], rb = rec[mt.b_idx];
-        const u32 sa = meta_slot(rec_meta(ra)), sb = meta_slot(rec_meta(rb));
-        double dA[3], dB[3];
-        displacement<DIM>(P, sa, SP_A, step, dA);
-        displacement<DIM>(P, sb, SP_B, step, dB);
-        const double xa[3] = {(double)ra.x, (double)ra.y, (double)ra.z};
-        const double xb[3] = {(double)rb.x, (double)rb.y, (double)rb.z};
-        double rv[3] = {0.0, 0.0, 0.0}, r2 = 0.0, r02 = 0.0;
-        for (int d = 0; d < DIM; ++d) {
-            rv[d] = min_image_d(xb[d] - xa[d], P.L[d], P.Lh[d]);
-            const double o = rv[d] - (dB[d] - dA[d]);
-            r2 += rv[d] * rv[d];
-            r02 += o * o;
-        }
-        const double R = sqrt(r2) / P.a;
-        double R0 = sqrt(r02) / P.a;
-        if (R0 < 1.0) R0 = 1.0;
-        bool react;
-        double Rpp = R, preac = 1.0;
-        u32 att = 0, hits = 0;
-        if (P.bc == 0) {
-            react = true;
-        } else {
-            Rpp = sample_radius<DIM>(P, R0, sa, sb, step, TAG_PROP, &att, &hits);
-            preac = reac_prob(P, DIM, Rpp, R0);
-            const u32 w = philox(sa, sb, step, TAG_REAC, P.key).x;
-            react = below(w, preac);
-            n_near += fabs(u01(w) - preac) < 1e-6;
-            if (!react) {
-                double rn = 0.0;
-                for (int d = 0; d < DIM; ++d) rn += rv[d] * rv[d];
-                rn = sqrt(rn);
-                T na[3] = {0, 0, 0}, nb[3] = {0, 0, 0};
-                for (int d = 0; d < DIM; ++d) {
-                    const double e = rn > 0.0 ? rv[d] / rn : (d == DIM - 1 ? 1.0 : 0.0);
-                    const double cen = xa[d] + P.fA * rv[d];
-                    na[d] = wrap_store<T>(cen - P.fA * P.a * Rpp * e, P.L[d]);
-                    nb[d] = wrap_store<T>(cen + P.fB * P.a * Rpp * e, P.L[d]);
-                }
-                ra.x = na[0]; ra.y = na[1]; ra.z = na[2];
-                rb.x = nb[0]; rb.y = nb[1]; rb.z = nb[2];
+    Rec<T> ra = rec[ia], rb = rec[ib];
+    const u32 sa = meta_slot(rec_meta(ra)), sb = meta_slot(rec_meta(rb));
+    double dA[3], dB[3];
+    displacement<DIM>(P, sa, SP_A, step, dA);
+    displacement<DIM>(P, sb, SP_B, step, dB);
+    const double xa[3] = {(double)ra.x, (double)ra.y, (double)ra.z};
+    const double xb[3] = {(double)rb.x, (double)rb.y, (double)rb.z};
+    double rv[3] = {0.0, 0.0, 0.0}, r2 = 0.0, r02 = 0.0;
+    for (int d = 0; d < DIM; ++d) {
+        rv[d] = min_image_d(xb[d] - xa[d], P.L[d], P.Lh[d]);
+        const double o = rv[d] - (dB[d] - dA[d]);
+        r2 += rv[d] * rv[d];
+        r02 += o * o;
+    }
+    const double R = sqrt(r2) / P.a;
+    double R0 = sqrt(r02) / P.a;
+    if (R0 < 1.0) R0 = 1.0;
+    bool react;
+    double Rpp = R, preac = 1.0;
+    u32 att = 0, hits = 0;
+    if (P.bc == 0) {
+        react = true;
+    } else {
+        Rpp = sample_radius<DIM>(P, R0, sa, sb, step, TAG_PROP, &att, &hits);
+        preac = reac_prob(P, DIM, Rpp, R0);
+        const u32 w = philox(sa, sb, step, TAG_REAC, P.key).x;
+        react = below(w, preac);
+        n_near += fabs(u01(w) - preac) < 1e-6;
+        if (!react) {
+            double rn = 0.0;
+            for (int d = 0; d < DIM; ++d) rn += rv[d] * rv[d];
+            rn = sqrt(rn);
+            T na[3] = {0, 0, 0}, nb[3] = {0, 0, 0};
+            for (int d = 0; d < DIM; ++d) {
+                const double e = rn > 0.0 ? rv[d] / rn : (d == DIM - 1 ? 1.0 : 0.0);
+                const double cen = xa[d] + P.fA * rv[d];
+                na[d] = wrap_store<T>(cen - P.fA * P.a * Rpp * e, P.L[d]);
+                nb[d] = wrap_store<T>(cen + P.fB * P.a * Rpp * e, P.L[d]);
             }
-        }
-        n_att += att;
-        n_hits += hits;
-        if (react) {
-            ++n_react;
-            T nc[3] = {0, 0, 0};
-            for (int d = 0; d < DIM; ++d) nc[d] = wrap_store<T>(xa[d] + P.fA * rv[d], P.L[d]);
-            ra.x = nc[0]; ra.y = nc[1]; ra.z = nc[2];
-            rec_set_meta(ra, meta_make(SP_C, sa));
-            rec_set_meta(rb, meta_make(SP_DEAD, sb));
-            partner[sa] = P.reversible ? sb : NOSLOT;
-        }
-        rec[mt.a_idx] = ra;
-        rec[mt.b_idx] = rb;
-        if (P.debug) {
-            const u32 q = atomicAdd(&C->n_dbg[2], 1u);
-            if (q < P.dbg_cap) {
-                DbgMatch d;
-                d.i = sa; d.j = sb; d.reacted = react; d.attempts = att; d.Rpp = Rpp; d.preac = preac;
-                dbg[q] = d;
-            }
+            ra.x = na[0]; ra.y = na[1]; ra.z = na[2];
+            rb.x = nb[0]; rb.y = nb[1]; rb.z = nb[2];
         }
     }
+    n_att += att;
+    n_hits += hits;
+    if (react) {
+        ++n_react;
+        T nc[3] = {0, 0, 0};
+        for (int d = 0; d < DIM; ++d) nc[d] = wrap_store<T>(xa[d] + P.fA * rv[d], P.L[d]);
+        ra.x = nc[0]; ra.y = nc[1]; ra.z = nc[2];
+        rec_set_meta(ra, meta_make(SP_C, sa));
+        rec_set_meta(rb, meta_make(SP_DEAD, sb));
+        partner[sa] = P.reversible ? sb : NOSLOT;
+    }
+    rec[ia] = ra;
+    rec[ib] = rb;
+    if (P.debug) {
+        const u32 q = atomicAdd(&C->n_dbg[2], 1u);
+        if (q < P.dbg_cap) {
+            DbgMatch d;
+            d.i = sa; d.j = sb; d.reacted = react; d.attempts = att; d.Rpp = Rpp; d.preac = preac;
+            dbg[q] = d;
+        }
+    }
+}
+
+template <int DIM, class T>
+__global__ __launch_bounds__(BLOCK) void k_select_b_react(Params P, Rec<T> *__restrict__ rec, const PairEnt *__restrict__ list,
+                                                           const CandEnt *__restrict__ cand, const u32 *__restrict__ flag,
+                                                           const u64 *__restrict__ headB, const u32 *__restrict__ nextB,
+                                                           u32 *__restrict__ partner, Counters *C, DbgMatch *dbg)
+{
+    const u32 step = C->step;
+    const u32 n = min(C->n_pl, P.cap_pl);
+    u32 n_match = 0, n_react = 0, n_att = 0, n_hits = 0, n_near = 0;
+    for (u32 k = gtid(); k < n; k += gstride()) {
+        if (flag[k] != PE_PICKED) continue;
+        const u32 h = (u32)headB[list[k].b_idx];
+        u32 mins = NOSLOT, count = 0;
+        for (u32 e = h; e != NOSLOT; e = nextB[e]) {
+            mins = min(mins, cand[e].a_slot);
+            ++count;
+        }
+        if (cand[k].a_slot != mins) continue;
+        u32 win = k;
+        if (count > 1) {
+            const double U = u01(philox(cand[k].b_slot, NOSLOT, step, TAG_SELB, P.key).x);
+            win = choose_in_chain(h, nextB, count, U, [&](u32 e) { return cand[e].a_slot; }, [&](u32 e) { return cand[e].p; });
+            if (win == NOSLOT) win = k;
+        }
+        ++n_match;
+        react_pair<DIM, T>(P, rec, list[win].a_idx, list[win].b_idx, partner, step, C, dbg, n_react, n_att, n_hits, n_near);
+    }
+    if (n_match) atomicAdd((unsigned long long *)&C->stats[ST_MATCHES], (unsigned long long)n_match);
     if (n_react) atomicAdd((unsigned long long *)&C->stats[ST_REACT], (unsigned long long)n_react);
     if (n_att) atomicAdd((unsigned long long *)&C->stats[ST_ATTEMPTS], (unsigned long long)n_att);
     if (n_hits) atomicAdd((unsigned long long *)&C->stats[ST_BOUND], (unsigned long long)n_hits);
@@ -764,9 +823,10 @@ __global__ __launch_bounds__(BLOCK) void k_react(Params P, Rec<T> *__restrict__ 
 // ---------------------------------------------------------------------------
 template <int DIM, class T>
 __global__ __launch_bounds__(BLOCK) void k_dissociate(Params P, Rec<T> *__restrict__ rec, const u32 *__restrict__ start,
-                                                       u32 *__restrict__ partner, Counters *C, DbgDiss *dbg, u32 step)
+                                                       u32 *__restrict__ partner, Counters *C, DbgDiss *dbg)
 {
 #pragma clang fp contract(off)
+    const u32 step = C->step;
     const u32 beg = start[2 * P.n_cells], end = start[3 * P.n_cells];
     u32 n_dec = 0, n_gem = 0, n_att = 0, n_hits = 0;
     for (u32 i = beg + gtid(); i < end; i += gstride()) {
@@ -831,15 +891,15 @@ __global__ __launch_bounds__(BLOCK) void k_dissociate(Params P, Rec<T> *__restri
 // K9: close the step.
 __global__ void k_finish(Counters *C)
 {
-    C->stats[ST_PICKS] = C->n_picks;
-    C->stats[ST_MATCHES] = C->n_matches;
+    C->stats[ST_PAIRS] = min(C->n_pl, 0xFFFFFFFFu);
     for (int s = 0; s < ST_N; ++s) {
         C->stats_last[s] = C->stats[s];
         C->stats_sum[s] += C->stats[s];
         C->stats[s] = 0;
     }
     C->n_rec = C->n_live + C->n_append;
-    C->n_picks = C->n_matches = C->n_append = C->n_ovf = C->n_ovf_cand = 0;
+    C->n_pl = C->n_append = 0;
+    C->step += 1u;
 }
 
 // ---------------------------------------------------------------------------

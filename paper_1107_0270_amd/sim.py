@@ -21,8 +21,8 @@ PREC_FP64, PREC_FP32, PREC_FP32_FP64NC = 0, 1, 2
 (READ_POS, READ_SPECIES, READ_PARTNER, READ_COUNTS, READ_STATS, READ_STATS_SUM, READ_DERIVED, READ_DBG_MOVED,
  READ_DBG_PAIRS, READ_DBG_PICKS, READ_DBG_MATCHES, READ_DBG_DISS, READ_DBG_CELLS, READ_TIMING, READ_GRID) = range(15)
 STAT_NAMES = ["pairs", "cand", "overlap", "r0clamp", "picks", "matches", "react", "decay", "geminate",
-              "attempts", "bound_hits", "near", "cand_overflow"]
-KERNEL_NAMES = ["move", "scan", "scatter", "pairs", "select", "react", "dissociate", "finish"]
+              "attempts", "bound_hits", "near", "lds_fallback"]
+KERNEL_NAMES = ["move", "scan", "scatter", "pairs", "eval", "select", "react", "dissociate", "finish"]
 
 PAIR_DT = np.dtype([("i", "<u4"), ("j", "<u4"), ("R", "<f8"), ("R0", "<f8"), ("p", "<f8"),
                     ("draw", "<u4"), ("cand", "<i4")], align=True)

@@ -63,18 +63,22 @@ def test_rad3d_reversible_binary32(prec, p_tol):
     assert rep.reactions > 20 and rep.decays > 0
 
 
-def test_rad3d_dense_overflow_path():
-    # a dense, fast system: many A's hold more than eight candidates, which
-    # exercises the second pass that sorts long candidate lists in memory
+@pytest.mark.parametrize("cell", [0.0, 0.075])
+def test_rad3d_dense(cell):
+    # a dense, fast system: A's with up to ~16 candidates, chains of several
+    # picks per B.  cell = 0.075 um puts ~160 B in every bucket, so the halo of
+    # even a one-cell brick overflows LDS and the search reads global memory.
     # (20,000 A + 20,000 B in a 0.375 um box: about 3e5 pairs and 5e4 candidates per step)
     n = 20000
     sp, pos = _state(n, n, 0.375, 3, 0.004, 2, True)
     gpu, orc = make_pair(dim=3, bc=O.BC_RAD, box=0.375, dt=2e-5, D=(5.0, 5.0, 2.5), sigma=0.004, kappa=1.0,
-                         k_off=500.0, precision=S.PREC_FP32_FP64NC, species=sp, pos=pos, seed=4, eps_cut=0.05)
+                         k_off=500.0, precision=S.PREC_FP32_FP64NC, species=sp, pos=pos, seed=4, eps_cut=0.05,
+                         cell=cell)
     rep = run(gpu, orc, 5, p_tol=1e-6, pos_tol=0.0, box=0.375)
     _check(rep, p_tol=1e-6, allow_near=3)
     tot = gpu.stats(total=True)
-    assert tot["cand_overflow"] > 0
+    if cell > 0:
+        assert tot["lds_fallback"] > 0
 
 
 def test_reflecting_and_small_box_single_cell():
