@@ -33,6 +33,7 @@ def algorithmic_bytes(kernel, n_live, n_a, n_b, n_keys, rec_bytes):
         "scan": 16 * n_keys,                                     # read counts twice, write starts, clear counts
         "scatter": (2 * rec_bytes + 8) * n_live,                 # read record + rank + start, write record
         "pairs": rec_bytes * (n_a + n_b) + 4 * n_keys // 3,      # A and B records once, B bucket starts
+        "eval": None,
     }.get(kernel)
 
 
@@ -55,28 +56,36 @@ def main():
     t0 = time.time()
     sp, pos, box, red = I.state_for(cfg, seed=0)
     log(f"[bench] state: {len(sp)} particles, {red} redrawn overlaps, {time.time() - t0:.1f}s")
-    sim = S.Sim(dim=3, box=box, dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
-                k_off=cfg["k_off"], precision=cfg["precision"], seed=0, species=sp, pos=pos,
-                timing=not args.no_timing)
-    der = sim.derived()
-    grid = sim.grid()
+    def make(timing):
+        return S.Sim(dim=3, box=box, dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
+                     k_off=cfg["k_off"], precision=cfg["precision"], seed=0, species=sp, pos=pos, timing=timing)
+
+    def timed(sim):
+        sim.step(args.warmup)
+        sim.kernel_times()  # drop warm-up timings
+        c0, s0 = sim.counts(), sim.stats(total=True)
+        t0 = time.perf_counter()
+        sim.step(args.steps)  # returns after a stream synchronisation
+        el = time.perf_counter() - t0
+        c1, s1 = sim.counts(), sim.stats(total=True)
+        n_live = 0.5 * ((c0["A"] + c0["B"] + c0["C"]) + (c1["A"] + c1["B"] + c1["C"]))
+        return el, n_live, s1["pairs"] - s0["pairs"], c0, c1, sim.kernel_times()
+
+    # pass 1: the step as one HIP graph replay (no per-kernel events) -> value
+    sim = make(False)
+    der, grid = sim.derived(), sim.grid()
     log(f"[bench] derived {der} grid {grid}")
-    sim.step(args.warmup)
-    sim.kernel_times()  # drop warm-up timings
-    c0 = sim.counts()
-    s0 = sim.stats(total=True)
-    t0 = time.perf_counter()
-    sim.step(args.steps)  # returns after a stream synchronisation
-    t1 = time.perf_counter()
-    c1 = sim.counts()
-    s1 = sim.stats(total=True)
-    kt = sim.kernel_times()
-    el = t1 - t0
-    n_live = 0.5 * ((c0["A"] + c0["B"] + c0["C"]) + (c1["A"] + c1["B"] + c1["C"]))
+    el, n_live, pairs, c0, c1, _ = timed(sim)
+    sim.close()
     ps = n_live * args.steps / el
-    pairs = s1["pairs"] - s0["pairs"]
-    log(f"[bench] {args.steps} steps in {el * 1e3:.1f} ms; {ps:.3e} particle-steps/s; {pairs / el:.3e} pair evals/s")
-    log(f"[bench] kernel times {kt}")
+    log(f"[bench] graph: {args.steps} steps in {el * 1e3:.1f} ms; {ps:.3e} particle-steps/s; {pairs / el:.3e} pair evals/s")
+    # pass 2: the same steps with HIP events around every kernel -> kernel durations
+    kt, el_ev = {}, None
+    if not args.no_timing:
+        sim = make(True)
+        el_ev, _, _, c0, c1, kt = timed(sim)
+        sim.close()
+        log(f"[bench] events: {args.steps} steps in {el_ev * 1e3:.1f} ms; kernel times {kt}")
 
     # dominant kernel and its roofline
     rec_bytes = 16
@@ -116,6 +125,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(el * 1e3 / args.steps, 5),
+        "ms_per_step_with_kernel_events": None if el_ev is None else round(el_ev * 1e3 / args.steps, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -125,7 +135,8 @@ def main():
         "config": {"workload": "3D reversible A+B<->C, radiation surface: 5e5 A + 5e5 B, periodic L=10 um, "
                                "D=1 um^2/s, sigma=5 nm, kappa=0.1 um^3/s, k_off=10/s, dt=10 us",
                    "precision": "binary32 state and p_enc, binary64 near-contact arguments and propagation",
-                   "particles": len(sp), "r_cut_um": der["rcut"], "cells": grid[:3], "timing_events": not args.no_timing},
+                   "particles": len(sp), "r_cut_um": der["rcut"], "cells": grid[:3],
+                   "step_launch": "one hipGraph replay per step"},
         "roofline": roof,
         "kernel_ms_per_step": {k: round(v[0] / max(args.steps, 1), 5) for k, v in kt.items()},
         "cpu_baseline": cpu,
