@@ -138,7 +138,8 @@ struct Counters {
     u32 step;       // step number used by every draw of this step
     u32 err;
     u32 n_dbg[4];   // pairs, picks, matches, dissociations logged this step
-    u32 pad[6];
+    u32 n_ev;       // events (matched pairs and decays) queued this step
+    u32 pad[5];
     u64 stats[ST_N];
     u64 stats_last[ST_N];
     u64 stats_sum[ST_N];

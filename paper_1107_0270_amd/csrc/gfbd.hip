@@ -154,7 +154,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     u32 *rank = nullptr, *cnt = nullptr, *start = nullptr, *bsum = nullptr, *partner = nullptr;
     PairEnt *plist = nullptr;
     CandEnt *cand = nullptr;
-    u32 *flag = nullptr, *nextA = nullptr, *nextB = nullptr;
+    u32 *flag = nullptr, *nextA = nullptr, *nextB = nullptr, *ev = nullptr;
     u64 *headA = nullptr, *headB = nullptr;
     Counters *ctr = nullptr;
     hipStream_t own_stream = nullptr;
@@ -272,12 +272,12 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         P.n_keys = 3u * P.n_cells;
         P.cap = (u32)n;
         P.cap_pl = (u32)std::min<uint64_t>(std::max<uint64_t>(1u << 20, 4 * n), 1u << 30);
-        // LDS bricks: about 256 cells, fewer when buckets are crowded
+        // LDS bricks: about 128 cells (halo <= MAX_HALO), fewer when buckets are crowded
         P.tiled = P.nc[0] >= 3 && P.nc[1] >= 3 && (DIM == 2 || P.nc[2] >= 3);
         if (P.tiled) {
             const double bpc = (double)std::max<uint64_t>(nB + nC, 1) / (double)ncell;
             const double lcap = (double)LdsRecCap<T>::value;
-            int bb[3] = {std::min(16, P.nc[0] - 2), std::min(DIM == 3 ? 4 : 16, P.nc[1] - 2), DIM == 3 ? std::min(4, P.nc[2] - 2) : 1};
+            int bb[3] = {std::min(8, P.nc[0] - 2), std::min(DIM == 3 ? 4 : 16, P.nc[1] - 2), DIM == 3 ? std::min(4, P.nc[2] - 2) : 1};
             auto halo = [&] { return (bb[0] + 2.0) * (bb[1] + 2.0) * (DIM == 3 ? bb[2] + 2.0 : 1.0); };
             while (halo() * bpc > 0.6 * lcap && (bb[0] > 1 || bb[1] > 1 || bb[2] > 1)) {
                 int k = 0;
@@ -302,7 +302,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             (rc = alloc(start, P.n_keys + 1)) || (rc = alloc(bsum, nb_scan)) || (rc = alloc(partner, n)) ||
             (rc = alloc(plist, P.cap_pl)) || (rc = alloc(cand, P.cap_pl)) || (rc = alloc(flag, P.cap_pl)) ||
             (rc = alloc(nextA, P.cap_pl)) || (rc = alloc(nextB, P.cap_pl)) || (rc = alloc(headA, n)) ||
-            (rc = alloc(headB, n)) || (rc = alloc(ctr, 1)) || (rc = alloc(g2c, 4 * (MAXTERMS + 1))) ||
+            (rc = alloc(headB, n)) || (rc = alloc(ev, n)) || (rc = alloc(ctr, 1)) || (rc = alloc(g2c, 4 * (MAXTERMS + 1))) ||
             (rc = alloc(g_pos, n * DIM)) || (rc = alloc(g_sp, n)))
             return rc;
         if (M.debug) {
@@ -394,16 +394,19 @@ template <int DIM, class T, int PM> struct Engine final : sim {
                                                  dbg_cells);
         }
         launch(SIM_K_PAIRS, [&] {
-            if (P.tiled) k_pair_scan<DIM, T, PM><<<n_bricks, BLOCK, 0, st>>>(P, out, start, plist, ctr);
+            if (P.tiled) k_pair_scan<DIM, T, PM><<<n_bricks, PBLOCK, 0, st>>>(P, out, start, plist, ctr);
             else k_pair_scan_global<DIM, T, PM><<<grid_for(maxA, 4096), BLOCK, 0, st>>>(P, out, start, plist, ctr);
         });
         launch(SIM_K_EVAL, [&] { k_pair_eval<DIM, T, PM><<<g_pl, BLOCK, 0, st>>>(P, out, plist, cand, flag, headA, nextA, ctr, dbg_pairs); });
         launch(SIM_K_SELECT, [&] { k_select_a<<<g_pl, BLOCK, 0, st>>>(P, plist, cand, flag, headA, nextA, headB, nextB, ctr, dbg_picks); });
-        launch(SIM_K_REACT, [&] {
-            k_select_b_react<DIM, T><<<g_pl, BLOCK, 0, st>>>(P, out, plist, cand, flag, headB, nextB, partner, ctr, dbg_matches);
-        });
+        launch(SIM_K_REACT, [&] { k_select_b<<<g_pl, BLOCK, 0, st>>>(P, plist, cand, flag, headB, nextB, ev, ctr); });
         if (P.reversible)
-            launch(SIM_K_DISSOCIATE, [&] { k_dissociate<DIM, T><<<grid_for(maxC, 4096), BLOCK, 0, st>>>(P, out, start, partner, ctr, dbg_diss); });
+            launch(SIM_K_DISSOCIATE, [&] {
+                k_decay_mark<<<grid_for(maxC, 2048), BLOCK, 0, st>>>(P, std::is_same<T, float>::value ? (const Rec<float> *)out : nullptr,
+                                                                    std::is_same<T, double>::value ? (const Rec<double> *)out : nullptr,
+                                                                    start, ev, ctr);
+            });
+        launch(SIM_K_EVENTS, [&] { k_events<DIM, T><<<256, BLOCK, 0, st>>>(P, out, plist, ev, partner, ctr, dbg_matches, dbg_diss); });
         launch(SIM_K_FINISH, [&] { k_finish<<<1, 1, 0, st>>>(ctr); });
     }
 

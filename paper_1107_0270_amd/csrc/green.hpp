@@ -208,52 +208,90 @@ constexpr u32 MAX_ATTEMPTS = 4096u;
 // proposed from (1 + beta (v - c)) e^{-v^2/4tau}, beta = 1 (3D) or 1/2 (2D):
 // a Gaussian-tail / Rayleigh-tail mixture when beta c <= 1, else the Rayleigh
 // tail alone.  Attempt k draws Philox {c0, c1, step, tag | k << 8}: word 0
-// chooses the mixture part, word 1 inverts its tail, word 2 accepts.
-template <int DIM>
-__device__ double sample_radius(const Params &P, double R0, u32 c0, u32 c1, u32 step, u32 tag, u32 *attempts, u32 *hits)
+// chooses the mixture part, word 1 inverts its tail, word 2 accepts.  The
+// result is the proposal of the first accepted attempt.
+struct PropSetup {
+    double c, yc, beta, w1, w2;
+    bool mixture;
+};
+
+template <int DIM> __device__ inline PropSetup prop_setup(const Params &P, double R0)
 {
-    double c = R0 - 1.0;
-    if (c < 0.0) c = 0.0;
-    const double tau = P.tau, st = P.sqrt_tau, yc = c / (2.0 * st);
-    const double beta = DIM == 3 ? 1.0 : 0.5;
-    const bool mixture = beta * c <= 1.0;
-    double w1 = 0.0, w2 = 0.0;
-    if (mixture) {
-        w1 = (1.0 - beta * c) * (SQRTPI_D * st) * erfcx(yc);
-        w2 = 2.0 * tau * beta;
+    PropSetup S;
+    S.c = R0 - 1.0;
+    if (S.c < 0.0) S.c = 0.0;
+    S.yc = S.c / (2.0 * P.sqrt_tau);
+    S.beta = DIM == 3 ? 1.0 : 0.5;
+    S.mixture = S.beta * S.c <= 1.0;
+    S.w1 = S.w2 = 0.0;
+    if (S.mixture) {
+        S.w1 = (1.0 - S.beta * S.c) * (SQRTPI_D * P.sqrt_tau) * erfcx(S.yc);
+        S.w2 = 2.0 * P.tau * S.beta;
     }
-    double v = c;
-    for (u32 k = 0; k < MAX_ATTEMPTS; ++k) {
-        const uint4 r = philox(c0, c1, step, (tag & 0xFFu) | (k << 8), P.key);
-        const double u0 = u01(r.x), u1 = u01(r.y), u2 = u01(r.z);
-        double acc;
-        if (mixture) {
-            if (u0 * (w1 + w2) < w1) v = 2.0 * st * erfc_tail_inv(yc, u1);
-            else v = sqrt(c * c - 4.0 * tau * log(u1));
-            acc = 1.0;
-        } else {
-            v = sqrt(c * c - 4.0 * tau * log(u1));
-            acc = (1.0 + beta * (v - c)) / (beta * v);
+    return S;
+}
+
+// One attempt: the proposed R' and whether it is accepted.
+template <int DIM>
+__device__ inline double prop_attempt(const Params &P, const PropSetup &S, double R0, u32 c0, u32 c1, u32 step, u32 tag, u32 k,
+                                      bool *accepted, bool *hit)
+{
+    const double tau = P.tau, st = P.sqrt_tau, c = S.c;
+    const uint4 r = philox(c0, c1, step, (tag & 0xFFu) | (k << 8), P.key);
+    const double u0 = u01(r.x), u1 = u01(r.y), u2 = u01(r.z);
+    double v, acc;
+    if (S.mixture) {
+        if (u0 * (S.w1 + S.w2) < S.w1) v = 2.0 * st * erfc_tail_inv(S.yc, u1);
+        else v = sqrt(c * c - 4.0 * tau * log(u1));
+        acc = 1.0;
+    } else {
+        v = sqrt(c * c - 4.0 * tau * log(u1));
+        acc = (1.0 + S.beta * (v - c)) / (S.beta * v);
+    }
+    const double Rp = 1.0 + v - c;
+    *hit = false;
+    if (DIM == 3) {
+        acc *= 1.0 - (SQRTPI_D * st) * erfcx(st + v / (2.0 * st));
+    } else {
+        double corr = corr2(P, Rp, R0);
+        if (corr > 1.0) {
+            *hit = true;
+            corr = 1.0;
         }
-        const double Rp = 1.0 + v - c;
-        if (DIM == 3) {
-            acc *= 1.0 - (SQRTPI_D * st) * erfcx(st + v / (2.0 * st));
-        } else {
-            double corr = corr2(P, Rp, R0);
-            if (corr > 1.0) {
-                ++*hits;
-                corr = 1.0;
-            }
-            if (corr < 0.0) corr = 0.0;
-            acc *= sqrt(Rp) / (1.0 + 0.5 * (Rp - 1.0)) * corr;
+        if (corr < 0.0) corr = 0.0;
+        acc *= sqrt(Rp) / (1.0 + 0.5 * (Rp - 1.0)) * corr;
+    }
+    *accepted = u2 < acc;
+    return Rp;
+}
+
+// The sampler for a whole wave working on one pair: lane l evaluates attempts
+// l, l + 64, ...; the first accepted attempt in order wins, exactly as if the
+// attempts were tried one after another.  Every lane of the wave must call it
+// with the same arguments; every lane gets the result.
+template <int DIM>
+__device__ double sample_radius_wave(const Params &P, double R0, u32 c0, u32 c1, u32 step, u32 tag, u32 *attempts, u32 *hits)
+{
+    const PropSetup S = prop_setup<DIM>(P, R0);
+    const int lane = threadIdx.x & 63;
+    u32 nh = 0;
+    double Rp = 1.0;
+    for (u32 k0 = 0; k0 < MAX_ATTEMPTS; k0 += 64) {
+        bool ok, hit;
+        Rp = prop_attempt<DIM>(P, S, R0, c0, c1, step, tag, k0 + lane, &ok, &hit);
+        const u64 okm = __ballot(ok), hm = __ballot(hit);
+        if (okm) {
+            const int first = __ffsll((unsigned long long)okm) - 1;
+            const u64 upto = first == 63 ? ~0ull : ((2ull << first) - 1ull);
+            *attempts = k0 + first + 1;
+            *hits = nh + (u32)__popcll(hm & upto);
+            return __shfl(Rp, first, 64);
         }
-        if (u2 < acc) {
-            *attempts = k + 1;
-            return Rp;
-        }
+        nh += (u32)__popcll(hm);
     }
     *attempts = MAX_ATTEMPTS;
-    return 1.0 + v - c;
+    *hits = nh;
+    return __shfl(Rp, 63, 64);
 }
 
 } // namespace gfbd

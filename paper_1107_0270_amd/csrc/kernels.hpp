@@ -402,12 +402,33 @@ __device__ inline void block_add_stats(const u32 *vals, int nv, u64 *dst, u32 *l
     }
 }
 
-constexpr int QCAP = 1024;       // pairs queued in LDS per workgroup
-constexpr int MAX_HALO = 1024;   // halo cells per brick
+constexpr int PBLOCK = 128;      // threads per pair-search workgroup
+constexpr int QCAP = 256;        // pairs queued in LDS per workgroup
+constexpr int MAX_HALO = 512;    // halo cells per brick
+constexpr int HALO_PER_T = MAX_HALO / PBLOCK;
 constexpr int MAX_ROWS = 64;     // rows of A cells per brick
 template <class T> struct LdsRecCap {
-    static constexpr int value = sizeof(T) == 4 ? 2048 : 1024;
+    static constexpr int value = sizeof(T) == 4 ? 1024 : 512;
 };
+
+// exclusive scan over a workgroup of NT threads (NT / 64 waves)
+template <int NT> __device__ inline u32 group_excl_scan(u32 v, u32 *lds, u32 &total)
+{
+    const u32 inc = wave_incl_scan(v);
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 63) lds[w] = inc;
+    __syncthreads();
+    u32 off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) {
+        const u32 x = lds[i];
+        off += i < w ? x : 0u;
+        tot += x;
+    }
+    __syncthreads();
+    total = tot;
+    return off + inc - v;
+}
 
 __device__ __forceinline__ void append_pair(PairEnt *q, u32 *nq, PairEnt *list, Counters *C, const Params &P, u32 a, u32 b)
 {
@@ -427,17 +448,17 @@ __device__ __forceinline__ void append_pair(PairEnt *q, u32 *nq, PairEnt *list, 
 __device__ __forceinline__ int wrapc(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
 template <int DIM, class T, int PM>
-__global__ __launch_bounds__(BLOCK) void k_pair_scan(Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start,
-                                                      PairEnt *__restrict__ list, Counters *C)
+__global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start,
+                                                       PairEnt *__restrict__ list, Counters *C)
 {
     constexpr int LCAP = LdsRecCap<T>::value;
     __shared__ Rec<T> sb[LCAP];
     __shared__ u32 sidx[LCAP];
-    __shared__ u32 off[MAX_HALO + 1];
+    __shared__ u32 off[MAX_HALO + 1], hsrc[MAX_HALO];
     __shared__ u32 rowpre[MAX_ROWS + 1], rowst[MAX_ROWS];
     __shared__ PairEnt q[QCAP];
     __shared__ u32 nq, qbase;
-    __shared__ u32 lds[BLOCK / 64];
+    __shared__ u32 lds[PBLOCK / 64];
 
     const int nx = P.nc[0], ny = P.nc[1], nz = P.nc[2];
     u32 b = blockIdx.x;
@@ -450,57 +471,73 @@ __global__ __launch_bounds__(BLOCK) void k_pair_scan(Params P, const Rec<T> *__r
     const int hx = ex + 2, hy = ey + 2, hz = DIM == 3 ? ez + 2 : 1;
     const int nh = hx * hy * hz;
     const u32 bbase = P.n_cells;
-    auto halo_key = [&](int h) -> u32 {
-        const int gx = wrapc(x0 - 1 + h % hx, nx);
-        const int gy = wrapc(y0 - 1 + (h / hx) % hy, ny);
-        const int gz = DIM == 3 ? wrapc(z0 - 1 + h / (hx * hy), nz) : 0;
-        return bbase + ((u32)gz * ny + gy) * nx + gx;
-    };
 
-    // bucket sizes of the halo cells and their running sum
-    u32 carry = 0;
-    for (int h0 = 0; h0 < nh; h0 += BLOCK) {
-        const int h = h0 + threadIdx.x;
-        u32 c = 0;
+    // 1. bucket ranges of this thread's halo cells and of the brick's A rows,
+    //    all global loads issued before any is used
+    u32 hs[HALO_PER_T], hc[HALO_PER_T];
+#pragma unroll
+    for (int t = 0; t < HALO_PER_T; ++t) {
+        const int h = threadIdx.x + t * PBLOCK;
+        hs[t] = hc[t] = 0;
         if (h < nh) {
-            const u32 k = halo_key(h);
-            c = start[k + 1] - start[k];
+            const int ix = h % hx, r = h / hx;
+            const int gx = wrapc(x0 - 1 + ix, nx);
+            const int gy = wrapc(y0 - 1 + r % hy, ny);
+            const int gz = DIM == 3 ? wrapc(z0 - 1 + r / hy, nz) : 0;
+            const u32 k = bbase + ((u32)gz * ny + gy) * nx + gx;
+            hs[t] = start[k];
+            hc[t] = start[k + 1];
         }
-        u32 tot;
-        const u32 ex_ = block_excl_scan(c, lds, tot);
-        if (h < nh) off[h] = carry + ex_;
-        carry += tot;
     }
-    // A records of the brick: one contiguous bucket range per row of cells
     const int nr = ey * ez;
-    if (threadIdx.x < 64) {
+    u32 rs = 0, rc = 0;
+    if ((int)threadIdx.x < nr) {
         const int r = threadIdx.x;
-        u32 cnt_ = 0;
-        if (r < nr) {
-            const u32 akey = ((u32)(z0 + r / ey) * ny + (y0 + r % ey)) * nx + x0;
-            rowst[r] = start[akey];
-            cnt_ = start[akey + ex] - rowst[r];
+        const u32 akey = ((u32)(z0 + r / ey) * ny + (y0 + r % ey)) * nx + x0;
+        rs = start[akey];
+        rc = start[akey + ex] - rs;
+    }
+    // prefix of the halo bucket sizes in h order (h = thread + t * PBLOCK)
+    u32 base = 0;
+#pragma unroll
+    for (int t = 0; t < HALO_PER_T; ++t) {
+        const int h = threadIdx.x + t * PBLOCK;
+        const u32 c = hc[t] - hs[t];
+        u32 tot;
+        const u32 e = group_excl_scan<PBLOCK>(c, lds, tot);
+        if (h < nh) {
+            off[h] = base + e;
+            hsrc[h] = hs[t];
         }
-        const u32 inc = wave_incl_scan(cnt_);
-        if (r < nr) rowpre[r + 1] = inc;
-        if (r == 0) rowpre[0] = 0;
+        base += tot;
+    }
+    if (threadIdx.x < 64) {
+        const u32 inc = wave_incl_scan(rc);
+        if ((int)threadIdx.x < nr) {
+            rowpre[threadIdx.x + 1] = inc;
+            rowst[threadIdx.x] = rs;
+        }
+        if (threadIdx.x == 0) rowpre[0] = 0;
     }
     if (threadIdx.x == 0) {
-        off[nh] = carry;
+        off[nh] = base;
         nq = 0;
     }
     __syncthreads();
-    const u32 total = off[nh];
+
+    // 2. stage the halo's B records in LDS (one global load per record)
+    const u32 total = base;
     const bool use_lds = total <= (u32)LCAP;
     if (use_lds) {
-        for (u32 i = threadIdx.x; i < total; i += BLOCK) {
+#pragma unroll 4
+        for (u32 i = threadIdx.x; i < total; i += PBLOCK) {
             int lo = 0, hi = nh;  // off[lo] <= i < off[hi]
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
                 if (off[mid] <= i) lo = mid;
                 else hi = mid;
             }
-            const u32 src = start[halo_key(lo)] + (i - off[lo]);
+            const u32 src = hsrc[lo] + (i - off[lo]);
             sb[i] = rec[src];
             sidx[i] = src;
         }
@@ -508,8 +545,10 @@ __global__ __launch_bounds__(BLOCK) void k_pair_scan(Params P, const Rec<T> *__r
         atomicAdd((unsigned long long *)&C->stats[ST_LDS_FALLBACK], 1ull);
     }
     __syncthreads();
+
+    // 3. every A of the brick against the B's of its 3^d neighbour cells
     const u32 nA = rowpre[nr];
-    for (u32 i = threadIdx.x; i < nA; i += BLOCK) {
+    for (u32 i = threadIdx.x; i < nA; i += PBLOCK) {
         int r = 0;
         while (r + 1 < nr && rowpre[r + 1] <= i) ++r;
         const u32 ia = rowst[r] + (i - rowpre[r]);
@@ -534,7 +573,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair_scan(Params P, const Rec<T> *__r
     const u32 n = min(nq, (u32)QCAP);
     if (threadIdx.x == 0) qbase = n ? atomicAdd(&C->n_pl, n) : 0u;
     __syncthreads();
-    for (u32 i = threadIdx.x; i < n; i += BLOCK) {
+    for (u32 i = threadIdx.x; i < n; i += PBLOCK) {
         const u32 g = qbase + i;
         if (g < P.cap_pl) list[g] = q[i];
         else atomicOr(&C->err, (u32)ERR_PAIRS);
@@ -707,14 +746,67 @@ __global__ __launch_bounds__(BLOCK) void k_select_a(Params P, const PairEnt *__r
 }
 
 // ---------------------------------------------------------------------------
-// K6/K7: B-side choice and the encountered pair (Sec. 3, steps 2a-2c).  The
-// picked entry with the smallest A slot of each B chain leads; it applies the
-// rule with U = {b, -, step, SELB} and then propagates / reacts the winner.
-// Each record belongs to at most one match, so the leader owns both records.
+// K6: B-side choice.  The picked entry with the smallest A slot of each B
+// chain leads; it applies the rule with U = {b, -, step, SELB} and queues the
+// winning pair as an event.
+// ---------------------------------------------------------------------------
+constexpr u32 EV_DECAY = 0x80000000u;
+
+__global__ __launch_bounds__(BLOCK) void k_select_b(Params P, const PairEnt *__restrict__ list, const CandEnt *__restrict__ cand,
+                                                     const u32 *__restrict__ flag, const u64 *__restrict__ headB,
+                                                     const u32 *__restrict__ nextB, u32 *__restrict__ ev, Counters *C)
+{
+    const u32 step = C->step;
+    const u32 n = min(C->n_pl, P.cap_pl);
+    u32 n_match = 0;
+    for (u32 k = gtid(); k < n; k += gstride()) {
+        if (flag[k] != PE_PICKED) continue;
+        const u32 h = (u32)headB[list[k].b_idx];
+        u32 mins = NOSLOT, count = 0;
+        for (u32 e = h; e != NOSLOT; e = nextB[e]) {
+            mins = min(mins, cand[e].a_slot);
+            ++count;
+        }
+        if (cand[k].a_slot != mins) continue;
+        u32 win = k;
+        if (count > 1) {
+            const double U = u01(philox(cand[k].b_slot, NOSLOT, step, TAG_SELB, P.key).x);
+            win = choose_in_chain(h, nextB, count, U, [&](u32 e) { return cand[e].a_slot; }, [&](u32 e) { return cand[e].p; });
+            if (win == NOSLOT) win = k;
+        }
+        ++n_match;
+        ev[atomicAdd(&C->n_ev, 1u)] = win;
+    }
+    if (n_match) atomicAdd((unsigned long long *)&C->stats[ST_MATCHES], (unsigned long long)n_match);
+}
+
+// K8a: which C records (those binned at the start of the step) decay:
+// xi < 1 - e^{-k_off dt} with xi = {c, -, step, UNI} (eq. rad_prob, step 4).
+__global__ __launch_bounds__(BLOCK) void k_decay_mark(Params P, const Rec<float> *recf, const Rec<double> *recd,
+                                                       const u32 *__restrict__ start, u32 *__restrict__ ev, Counters *C)
+{
+    const u32 step = C->step;
+    const u32 beg = start[2 * P.n_cells], end = start[3 * P.n_cells];
+    for (u32 i = beg + gtid(); i < end; i += gstride()) {
+        const u32 sc = meta_slot(recf ? rec_meta(recf[i]) : rec_meta(recd[i]));
+        if (below(philox(sc, NOSLOT, step, TAG_UNI, P.key).x, P.p_uni)) ev[atomicAdd(&C->n_ev, 1u)] = EV_DECAY | i;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K7: the events of the step, one wave per event.
+//  match (Sec. 3, steps 2a-2c): absorbing pairs react; reflecting and
+//    radiation pairs get R'' from the radial propagator and radiation pairs
+//    react with p_reac; the centre R (eq. Rcoo) keeps its free end point and
+//    the pair keeps the direction of its free separation.
+//  decay (Sec. 2.2.5): R'' from the propagator with r0 = a, geminate
+//    recombination with p_reac(R''|a), otherwise A and B placed R'' apart
+//    along a uniform direction around the old C, B into the reserved slot.
+// All lanes compute the same values; lane 0 writes.
 // ---------------------------------------------------------------------------
 template <int DIM, class T>
-__device__ inline void react_pair(const Params &P, Rec<T> *__restrict__ rec, u32 ia, u32 ib, u32 *__restrict__ partner, u32 step,
-                                  Counters *C, DbgMatch *dbg, u32 &n_react, u32 &n_att, u32 &n_hits, u32 &n_near)
+__device__ inline void ev_match(const Params &P, Rec<T> *__restrict__ rec, u32 ia, u32 ib, u32 *__restrict__ partner, u32 step,
+                                Counters *C, DbgMatch *dbg)
 {
 #pragma clang fp contract(off)
     Rec<T> ra = rec[ia], rb = rec[ib];
@@ -736,15 +828,15 @@ __device__ inline void react_pair(const Params &P, Rec<T> *__restrict__ rec, u32
     if (R0 < 1.0) R0 = 1.0;
     bool react;
     double Rpp = R, preac = 1.0;
-    u32 att = 0, hits = 0;
+    u32 att = 0, hits = 0, near = 0;
     if (P.bc == 0) {
         react = true;
     } else {
-        Rpp = sample_radius<DIM>(P, R0, sa, sb, step, TAG_PROP, &att, &hits);
+        Rpp = sample_radius_wave<DIM>(P, R0, sa, sb, step, TAG_PROP, &att, &hits);
         preac = reac_prob(P, DIM, Rpp, R0);
         const u32 w = philox(sa, sb, step, TAG_REAC, P.key).x;
         react = below(w, preac);
-        n_near += fabs(u01(w) - preac) < 1e-6;
+        near = fabs(u01(w) - preac) < 1e-6;
         if (!react) {
             double rn = 0.0;
             for (int d = 0; d < DIM; ++d) rn += rv[d] * rv[d];
@@ -760,87 +852,49 @@ __device__ inline void react_pair(const Params &P, Rec<T> *__restrict__ rec, u32
             rb.x = nb[0]; rb.y = nb[1]; rb.z = nb[2];
         }
     }
-    n_att += att;
-    n_hits += hits;
     if (react) {
-        ++n_react;
         T nc[3] = {0, 0, 0};
         for (int d = 0; d < DIM; ++d) nc[d] = wrap_store<T>(xa[d] + P.fA * rv[d], P.L[d]);
         ra.x = nc[0]; ra.y = nc[1]; ra.z = nc[2];
         rec_set_meta(ra, meta_make(SP_C, sa));
         rec_set_meta(rb, meta_make(SP_DEAD, sb));
-        partner[sa] = P.reversible ? sb : NOSLOT;
     }
-    rec[ia] = ra;
-    rec[ib] = rb;
-    if (P.debug) {
-        const u32 q = atomicAdd(&C->n_dbg[2], 1u);
-        if (q < P.dbg_cap) {
-            DbgMatch d;
-            d.i = sa; d.j = sb; d.reacted = react; d.attempts = att; d.Rpp = Rpp; d.preac = preac;
-            dbg[q] = d;
+    if (lane_id() == 0) {
+        if (react) partner[sa] = P.reversible ? sb : NOSLOT;
+        rec[ia] = ra;
+        rec[ib] = rb;
+        if (react) atomicAdd((unsigned long long *)&C->stats[ST_REACT], 1ull);
+        if (att) atomicAdd((unsigned long long *)&C->stats[ST_ATTEMPTS], (unsigned long long)att);
+        if (hits) atomicAdd((unsigned long long *)&C->stats[ST_BOUND], (unsigned long long)hits);
+        if (near) atomicAdd((unsigned long long *)&C->stats[ST_NEAR], 1ull);
+        if (P.debug) {
+            const u32 q = atomicAdd(&C->n_dbg[2], 1u);
+            if (q < P.dbg_cap) {
+                DbgMatch d;
+                d.i = sa; d.j = sb; d.reacted = react; d.attempts = att; d.Rpp = Rpp; d.preac = preac;
+                dbg[q] = d;
+            }
         }
     }
 }
 
 template <int DIM, class T>
-__global__ __launch_bounds__(BLOCK) void k_select_b_react(Params P, Rec<T> *__restrict__ rec, const PairEnt *__restrict__ list,
-                                                           const CandEnt *__restrict__ cand, const u32 *__restrict__ flag,
-                                                           const u64 *__restrict__ headB, const u32 *__restrict__ nextB,
-                                                           u32 *__restrict__ partner, Counters *C, DbgMatch *dbg)
-{
-    const u32 step = C->step;
-    const u32 n = min(C->n_pl, P.cap_pl);
-    u32 n_match = 0, n_react = 0, n_att = 0, n_hits = 0, n_near = 0;
-    for (u32 k = gtid(); k < n; k += gstride()) {
-        if (flag[k] != PE_PICKED) continue;
-        const u32 h = (u32)headB[list[k].b_idx];
-        u32 mins = NOSLOT, count = 0;
-        for (u32 e = h; e != NOSLOT; e = nextB[e]) {
-            mins = min(mins, cand[e].a_slot);
-            ++count;
-        }
-        if (cand[k].a_slot != mins) continue;
-        u32 win = k;
-        if (count > 1) {
-            const double U = u01(philox(cand[k].b_slot, NOSLOT, step, TAG_SELB, P.key).x);
-            win = choose_in_chain(h, nextB, count, U, [&](u32 e) { return cand[e].a_slot; }, [&](u32 e) { return cand[e].p; });
-            if (win == NOSLOT) win = k;
-        }
-        ++n_match;
-        react_pair<DIM, T>(P, rec, list[win].a_idx, list[win].b_idx, partner, step, C, dbg, n_react, n_att, n_hits, n_near);
-    }
-    if (n_match) atomicAdd((unsigned long long *)&C->stats[ST_MATCHES], (unsigned long long)n_match);
-    if (n_react) atomicAdd((unsigned long long *)&C->stats[ST_REACT], (unsigned long long)n_react);
-    if (n_att) atomicAdd((unsigned long long *)&C->stats[ST_ATTEMPTS], (unsigned long long)n_att);
-    if (n_hits) atomicAdd((unsigned long long *)&C->stats[ST_BOUND], (unsigned long long)n_hits);
-    if (n_near) atomicAdd((unsigned long long *)&C->stats[ST_NEAR], (unsigned long long)n_near);
-}
-
-// ---------------------------------------------------------------------------
-// K8: C -> A + B (Sec. 2.2.5 and step 4) for the C records that existed at
-// the start of the step (the C bucket range of this step's binning).
-// ---------------------------------------------------------------------------
-template <int DIM, class T>
-__global__ __launch_bounds__(BLOCK) void k_dissociate(Params P, Rec<T> *__restrict__ rec, const u32 *__restrict__ start,
-                                                       u32 *__restrict__ partner, Counters *C, DbgDiss *dbg)
+__device__ inline void ev_decay(const Params &P, Rec<T> *__restrict__ rec, u32 i, u32 *__restrict__ partner, u32 step,
+                                Counters *C, DbgDiss *dbg)
 {
 #pragma clang fp contract(off)
-    const u32 step = C->step;
-    const u32 beg = start[2 * P.n_cells], end = start[3 * P.n_cells];
-    u32 n_dec = 0, n_gem = 0, n_att = 0, n_hits = 0;
-    for (u32 i = beg + gtid(); i < end; i += gstride()) {
-        Rec<T> rc = rec[i];
-        const u32 sc = meta_slot(rec_meta(rc));
-        if (!below(philox(sc, NOSLOT, step, TAG_UNI, P.key).x, P.p_uni)) continue;
-        ++n_dec;
-        u32 att = 0, hits = 0;
-        const double Rpp = sample_radius<DIM>(P, 1.0, sc, NOSLOT, step, TAG_DPROP, &att, &hits);
-        n_att += att;
-        n_hits += hits;
-        const double preac = reac_prob(P, DIM, Rpp, 1.0);
-        const bool gem = below(philox(sc, NOSLOT, step, TAG_GEM, P.key).x, preac);
-        const u32 sb = partner[sc];
+    const Rec<T> rc = rec[i];
+    const u32 sc = meta_slot(rec_meta(rc));
+    u32 att = 0, hits = 0;
+    const double Rpp = sample_radius_wave<DIM>(P, 1.0, sc, NOSLOT, step, TAG_DPROP, &att, &hits);
+    const double preac = reac_prob(P, DIM, Rpp, 1.0);
+    const bool gem = below(philox(sc, NOSLOT, step, TAG_GEM, P.key).x, preac);
+    const u32 sb = partner[sc];
+    if (lane_id() == 0) {
+        atomicAdd((unsigned long long *)&C->stats[ST_DECAY], 1ull);
+        if (gem) atomicAdd((unsigned long long *)&C->stats[ST_GEMINATE], 1ull);
+        atomicAdd((unsigned long long *)&C->stats[ST_ATTEMPTS], (unsigned long long)att);
+        if (hits) atomicAdd((unsigned long long *)&C->stats[ST_BOUND], (unsigned long long)hits);
         if (P.debug) {
             const u32 q = atomicAdd(&C->n_dbg[3], 1u);
             if (q < P.dbg_cap) {
@@ -849,43 +903,53 @@ __global__ __launch_bounds__(BLOCK) void k_dissociate(Params P, Rec<T> *__restri
                 dbg[q] = d;
             }
         }
-        if (gem) {
-            ++n_gem;
-            continue;
-        }
-        const uint4 r = philox(sc, NOSLOT, step, TAG_DIR, P.key);
-        double e[3] = {0.0, 0.0, 0.0};
-        if (DIM == 3) {
-            const double z = 2.0 * u01(r.x) - 1.0, ph = (2.0 * PI_D) * u01(r.y), rho = sqrt(1.0 - z * z);
-            e[0] = rho * cos(ph);
-            e[1] = rho * sin(ph);
-            e[2] = z;
-        } else {
-            const double ph = (2.0 * PI_D) * u01(r.x);
-            e[0] = cos(ph);
-            e[1] = sin(ph);
-        }
-        const double X[3] = {(double)rc.x, (double)rc.y, (double)rc.z};
-        Rec<T> ra = rc, rb = rc;
-        T pa[3] = {0, 0, 0}, pb[3] = {0, 0, 0};
-        for (int d = 0; d < DIM; ++d) {
-            pa[d] = wrap_store<T>(X[d] - P.fA * P.a * Rpp * e[d], P.L[d]);
-            pb[d] = wrap_store<T>(X[d] + P.fB * P.a * Rpp * e[d], P.L[d]);
-        }
-        ra.x = pa[0]; ra.y = pa[1]; ra.z = pa[2];
-        rb.x = pb[0]; rb.y = pb[1]; rb.z = pb[2];
-        rec_set_meta(ra, meta_make(SP_A, sc));
-        rec_set_meta(rb, meta_make(SP_B, sb));
+    }
+    if (gem) return;
+    const uint4 r = philox(sc, NOSLOT, step, TAG_DIR, P.key);
+    double e[3] = {0.0, 0.0, 0.0};
+    if (DIM == 3) {
+        const double z = 2.0 * u01(r.x) - 1.0, ph = (2.0 * PI_D) * u01(r.y), rho = sqrt(1.0 - z * z);
+        e[0] = rho * cos(ph);
+        e[1] = rho * sin(ph);
+        e[2] = z;
+    } else {
+        const double ph = (2.0 * PI_D) * u01(r.x);
+        e[0] = cos(ph);
+        e[1] = sin(ph);
+    }
+    const double X[3] = {(double)rc.x, (double)rc.y, (double)rc.z};
+    Rec<T> ra = rc, rb = rc;
+    T pa[3] = {0, 0, 0}, pb[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) {
+        pa[d] = wrap_store<T>(X[d] - P.fA * P.a * Rpp * e[d], P.L[d]);
+        pb[d] = wrap_store<T>(X[d] + P.fB * P.a * Rpp * e[d], P.L[d]);
+    }
+    ra.x = pa[0]; ra.y = pa[1]; ra.z = pa[2];
+    rb.x = pb[0]; rb.y = pb[1]; rb.z = pb[2];
+    rec_set_meta(ra, meta_make(SP_A, sc));
+    rec_set_meta(rb, meta_make(SP_B, sb));
+    if (lane_id() == 0) {
         partner[sc] = NOSLOT;
         rec[i] = ra;
         const u32 q = C->n_live + atomicAdd(&C->n_append, 1u);
         if (q < P.cap) rec[q] = rb;
         else atomicOr(&C->err, (u32)ERR_APPEND);
     }
-    if (n_dec) atomicAdd((unsigned long long *)&C->stats[ST_DECAY], (unsigned long long)n_dec);
-    if (n_gem) atomicAdd((unsigned long long *)&C->stats[ST_GEMINATE], (unsigned long long)n_gem);
-    if (n_att) atomicAdd((unsigned long long *)&C->stats[ST_ATTEMPTS], (unsigned long long)n_att);
-    if (n_hits) atomicAdd((unsigned long long *)&C->stats[ST_BOUND], (unsigned long long)n_hits);
+}
+
+template <int DIM, class T>
+__global__ __launch_bounds__(BLOCK) void k_events(Params P, Rec<T> *__restrict__ rec, const PairEnt *__restrict__ list,
+                                                   const u32 *__restrict__ ev, u32 *__restrict__ partner, Counters *C,
+                                                   DbgMatch *dbg_m, DbgDiss *dbg_d)
+{
+    const u32 step = C->step;
+    const u32 n = min(C->n_ev, P.cap);
+    const u32 wave = (blockIdx.x * BLOCK + threadIdx.x) >> 6, nwaves = (gridDim.x * BLOCK) >> 6;
+    for (u32 w = wave; w < n; w += nwaves) {
+        const u32 e = ev[w];
+        if (e & EV_DECAY) ev_decay<DIM, T>(P, rec, e & ~EV_DECAY, partner, step, C, dbg_d);
+        else ev_match<DIM, T>(P, rec, list[e].a_idx, list[e].b_idx, partner, step, C, dbg_m);
+    }
 }
 
 // K9: close the step.
@@ -898,7 +962,7 @@ __global__ void k_finish(Counters *C)
         C->stats[s] = 0;
     }
     C->n_rec = C->n_live + C->n_append;
-    C->n_pl = C->n_append = 0;
+    C->n_pl = C->n_append = C->n_ev = 0;
     C->step += 1u;
 }
 
