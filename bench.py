@@ -29,11 +29,10 @@ def log(*a):
 def algorithmic_bytes(kernel, n_live, n_a, n_b, n_keys, rec_bytes):
     """HBM bytes one launch of a stage must move at least (each datum once)."""
     return {
-        "move": (rec_bytes + 4) * n_live + 8 * n_keys,           # read record, write rank, count buckets
-        "scan": 16 * n_keys,                                     # read counts twice, write starts, clear counts
-        "scatter": (2 * rec_bytes + 8) * n_live,                 # read record + rank + start, write record
+        "move": (2 * rec_bytes + 4) * n_live + 8 * n_keys,      # read record, write moved record + rank, count buckets
+        "scan": 12 * n_keys,                                     # read counts, write starts, clear counts
+        "scatter": (2 * rec_bytes + 8) * n_live,                 # read moved record + rank + start, write record
         "pairs": rec_bytes * (n_a + n_b) + 4 * n_keys // 3,      # A and B records once, B bucket starts
-        "eval": None,
     }.get(kernel)
 
 

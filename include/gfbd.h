@@ -150,11 +150,11 @@ typedef struct { uint32_t c, j; int32_t decayed, recombined; uint32_t attempts, 
 
 /* Kernels timed with sim_config.timing: move + bucket count, bucket scan,
  * scatter into sorted order, pair search, p_enc + draw per pair, A-side
- * choice, B-side choice, decay draws, matched pairs and decays (one wave
- * each: propagation, reaction, dissociation), step close. */
+ * choice, B-side choice + decay draws, matched pairs and decays (one wave
+ * each: propagation, reaction, dissociation; the last block closes the step). */
 enum {
-    SIM_K_MOVE = 0, SIM_K_SCAN, SIM_K_SCATTER, SIM_K_PAIRS, SIM_K_EVAL, SIM_K_SELECT, SIM_K_REACT,
-    SIM_K_DISSOCIATE, SIM_K_EVENTS, SIM_K_FINISH, SIM_K_N
+    SIM_K_MOVE = 0, SIM_K_SCAN, SIM_K_SCATTER, SIM_K_PAIRS, SIM_K_EVAL, SIM_K_SELECT_A, SIM_K_SELECT_B,
+    SIM_K_EVENTS, SIM_K_N
 };
 typedef struct { double ms; uint64_t launches; } sim_kernel_time;
 

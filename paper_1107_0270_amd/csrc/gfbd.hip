@@ -150,7 +150,8 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     uint32_t maxA = 0, maxC = 0, nb_scan = 0;
     double cell_edge = 0.0;
     // device memory
-    Rec<T> *rec[2] = {nullptr, nullptr};
+    Rec<T> *rec[2] = {nullptr, nullptr}, *tmp = nullptr;
+    u64 *scan_status = nullptr;
     u32 *rank = nullptr, *cnt = nullptr, *start = nullptr, *bsum = nullptr, *partner = nullptr;
     PairEnt *plist = nullptr;
     CandEnt *cand = nullptr;
@@ -221,6 +222,15 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         P.rcut2 = P.rcut * P.rcut;
         P.rcut2f = (float)P.rcut2;
         P.rcut2f_wide = (float)(P.rcut2 * (1.0 + 1e-4));
+        {
+            // prefilter radius for brick-relative binary32 coordinates: each
+            // coordinate is off by at most two binary32 roundings of a value
+            // below the box edge
+            double lmax = 0.0;
+            for (int k = 0; k < DIM; ++k) lmax = std::max(lmax, M.box[k]);
+            const double slack = 4.0 * std::ldexp(1.0, std::ilogb(lmax) - 23) * std::sqrt((double)DIM);
+            P.rcut2f_pre = (float)((P.rcut + slack) * (P.rcut + slack) * (1.0 + 1e-5));
+        }
         P.inv_af = (float)P.inv_a;
         P.inv_tauf = (float)P.inv_tau;
         P.fA = M.D[0] / Deff;
@@ -276,7 +286,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         P.tiled = P.nc[0] >= 3 && P.nc[1] >= 3 && (DIM == 2 || P.nc[2] >= 3);
         if (P.tiled) {
             const double bpc = (double)std::max<uint64_t>(nB + nC, 1) / (double)ncell;
-            const double lcap = (double)LdsRecCap<T>::value;
+            const double lcap = 1024.0;
             int bb[3] = {std::min(8, P.nc[0] - 2), std::min(DIM == 3 ? 4 : 16, P.nc[1] - 2), DIM == 3 ? std::min(4, P.nc[2] - 2) : 1};
             auto halo = [&] { return (bb[0] + 2.0) * (bb[1] + 2.0) * (DIM == 3 ? bb[2] + 2.0 : 1.0); };
             while (halo() * bpc > 0.6 * lcap && (bb[0] > 1 || bb[1] > 1 || bb[2] > 1)) {
@@ -298,7 +308,8 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         nb_scan = (P.n_keys + SCAN_TILE - 1) / SCAN_TILE;
         // device buffers
         int rc;
-        if ((rc = alloc(rec[0], n)) || (rc = alloc(rec[1], n)) || (rc = alloc(rank, n)) || (rc = alloc(cnt, P.n_keys)) ||
+        if ((rc = alloc(rec[0], n)) || (rc = alloc(rec[1], n)) || (rc = alloc(tmp, n)) || (rc = alloc(scan_status, nb_scan)) ||
+            (rc = alloc(rank, n)) || (rc = alloc(cnt, P.n_keys)) ||
             (rc = alloc(start, P.n_keys + 1)) || (rc = alloc(bsum, nb_scan)) || (rc = alloc(partner, n)) ||
             (rc = alloc(plist, P.cap_pl)) || (rc = alloc(cand, P.cap_pl)) || (rc = alloc(flag, P.cap_pl)) ||
             (rc = alloc(nextA, P.cap_pl)) || (rc = alloc(nextB, P.cap_pl)) || (rc = alloc(headA, n)) ||
@@ -343,6 +354,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         HIPCHECK(hipMemcpyAsync(ctr, &c, sizeof(c), hipMemcpyHostToDevice, M.stream));
         HIPCHECK(hipMemsetAsync(headA, 0, sizeof(u64) * n, M.stream));  // no chain survives a reload
         HIPCHECK(hipMemsetAsync(headB, 0, sizeof(u64) * n, M.stream));
+        HIPCHECK(hipMemsetAsync(scan_status, 0, sizeof(u64) * nb_scan, M.stream));
         HIPCHECK(hipStreamSynchronize(M.stream));
         cur = 0;
         stepno = step0;
@@ -379,13 +391,9 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         Rec<T> *in = rec[c], *out = rec[c ^ 1];
         const u32 g_all = grid_for(n, 8192);
         const u32 g_pl = 1024;
-        launch(SIM_K_MOVE, [&] { k_move_count<DIM, T><<<g_all, BLOCK, 0, st>>>(P, in, rank, cnt, ctr); });
-        launch(SIM_K_SCAN, [&] {
-            k_scan_reduce<<<nb_scan, BLOCK, 0, st>>>(cnt, P.n_keys, bsum);
-            k_scan_top<<<1, BLOCK, 0, st>>>(bsum, nb_scan);
-            k_scan_down<<<nb_scan, BLOCK, 0, st>>>(cnt, P.n_keys, bsum, start, ctr);
-        });
-        launch(SIM_K_SCATTER, [&] { k_scatter<DIM, T><<<g_all, BLOCK, 0, st>>>(P, in, rank, start, out, ctr); });
+        launch(SIM_K_MOVE, [&] { k_move_count<DIM, T><<<g_all, BLOCK, 0, st>>>(P, in, tmp, rank, cnt, ctr); });
+        launch(SIM_K_SCAN, [&] { k_scan<<<nb_scan, BLOCK, 0, st>>>(cnt, P.n_keys, start, scan_status, ctr, nb_scan); });
+        launch(SIM_K_SCATTER, [&] { k_scatter<DIM, T><<<g_all, BLOCK, 0, st>>>(P, tmp, rank, start, out, ctr); });
         if (M.debug) {
             k_fill<<<grid_for(n * DIM, 2048), BLOCK, 0, st>>>(dbg_moved, n * DIM, (int *)dbg_cells, (u32)n);
             k_gather<DIM, T><<<g_all, BLOCK, 0, st>>>(out, partner, ctr, 1, dbg_moved, nullptr, (u32)n);
@@ -398,16 +406,12 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             else k_pair_scan_global<DIM, T, PM><<<grid_for(maxA, 4096), BLOCK, 0, st>>>(P, out, start, plist, ctr);
         });
         launch(SIM_K_EVAL, [&] { k_pair_eval<DIM, T, PM><<<g_pl, BLOCK, 0, st>>>(P, out, plist, cand, flag, headA, nextA, ctr, dbg_pairs); });
-        launch(SIM_K_SELECT, [&] { k_select_a<<<g_pl, BLOCK, 0, st>>>(P, plist, cand, flag, headA, nextA, headB, nextB, ctr, dbg_picks); });
-        launch(SIM_K_REACT, [&] { k_select_b<<<g_pl, BLOCK, 0, st>>>(P, plist, cand, flag, headB, nextB, ev, ctr); });
-        if (P.reversible)
-            launch(SIM_K_DISSOCIATE, [&] {
-                k_decay_mark<<<grid_for(maxC, 2048), BLOCK, 0, st>>>(P, std::is_same<T, float>::value ? (const Rec<float> *)out : nullptr,
-                                                                    std::is_same<T, double>::value ? (const Rec<double> *)out : nullptr,
-                                                                    start, ev, ctr);
-            });
+        launch(SIM_K_SELECT_A, [&] { k_select_a<<<g_pl, BLOCK, 0, st>>>(P, plist, cand, flag, headA, nextA, headB, nextB, ctr, dbg_picks); });
+        const u32 nb_sel = g_pl, nb_dec = P.reversible ? grid_for(maxC, 2048) : 0;
+        launch(SIM_K_SELECT_B, [&] {
+            k_select_b<T><<<nb_sel + nb_dec, BLOCK, 0, st>>>(P, plist, cand, flag, headB, nextB, out, start, ev, ctr, nb_sel);
+        });
         launch(SIM_K_EVENTS, [&] { k_events<DIM, T><<<256, BLOCK, 0, st>>>(P, out, plist, ev, partner, ctr, dbg_matches, dbg_diss); });
-        launch(SIM_K_FINISH, [&] { k_finish<<<1, 1, 0, st>>>(ctr); });
     }
 
     int one_step()

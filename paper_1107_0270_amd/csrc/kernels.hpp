@@ -45,8 +45,10 @@ template <int DIM> __device__ inline void displacement(const Params &P, u32 slot
     const uint4 r = philox(slot, NOSLOT, step, TAG_MOVE, P.key);
     const double s = P.sd[sp];
     const double r0 = sqrt(-2.0 * log(u01(r.x))), t0 = (2.0 * PI_D) * u01(r.y);
-    d[0] = s * (r0 * cos(t0));
-    d[1] = s * (r0 * sin(t0));
+    double s0, c0;
+    sincos(t0, &s0, &c0);
+    d[0] = s * (r0 * c0);
+    d[1] = s * (r0 * s0);
     if (DIM == 3) {
         const double r1 = sqrt(-2.0 * log(u01(r.z))), t1 = (2.0 * PI_D) * u01(r.w);
         d[2] = s * (r1 * cos(t1));
@@ -86,8 +88,8 @@ template <int DIM, class T> __device__ inline u32 cell_of(const Params &P, const
 // K1: move every live record and count it into its (species, cell) bucket.
 // ---------------------------------------------------------------------------
 template <int DIM, class T>
-__global__ __launch_bounds__(BLOCK) void k_move_count(Params P, const Rec<T> *__restrict__ rec, u32 *__restrict__ rank,
-                                                       u32 *__restrict__ cnt, Counters *C)
+__global__ __launch_bounds__(BLOCK) void k_move_count(Params P, const Rec<T> *__restrict__ rec, Rec<T> *__restrict__ tmp,
+                                                       u32 *__restrict__ rank, u32 *__restrict__ cnt, Counters *C)
 {
     const u32 step = C->step;
     if (gtid() == 0) {
@@ -97,8 +99,12 @@ __global__ __launch_bounds__(BLOCK) void k_move_count(Params P, const Rec<T> *__
     for (u32 i = gtid(); i < n; i += gstride()) {
         const Rec<T> r = rec[i];
         const u32 m = rec_meta(r), sp = meta_sp(m);
-        if (sp > SP_C) continue;
+        if (sp > SP_C) {
+            tmp[i] = r;  // dead record: the scatter skips it
+            continue;
+        }
         const Rec<T> q = moved<DIM, T>(P, r, m, step);
+        tmp[i] = q;
         const u32 key = sp * P.n_cells + cell_of<DIM, T>(P, q);
         rank[i] = atomicAdd(&cnt[key], 1u);
     }
@@ -144,52 +150,74 @@ __device__ inline u32 block_sum(u32 v, u32 *lds)
     return t;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_scan_reduce(const u32 *__restrict__ cnt, u32 n, u32 *__restrict__ bsum)
+// One pass: tiles are claimed in order through a counter; each tile
+// publishes its sum, then adds the sums of the tiles before it (stopping at
+// the first tile that has published its inclusive prefix).  Status words are
+// tagged with the step, so they never need clearing.  A bounded wait: a
+// status that never arrives sets an error flag instead of hanging.
+constexpr u32 SCAN_AGG = 1u, SCAN_PRE = 2u;
+constexpr u64 SCAN_SPIN_LIMIT = 1ull << 24;
+
+__device__ __forceinline__ u64 scan_pack(u32 epoch, u32 flag, u32 v) { return ((u64)(epoch & 0x3FFFFFFFu) << 34) | ((u64)flag << 32) | v; }
+
+__global__ __launch_bounds__(BLOCK) void k_scan(u32 *__restrict__ cnt, u32 n, u32 *__restrict__ start, u64 *__restrict__ status,
+                                                 Counters *C, u32 ntiles)
 {
     __shared__ u32 lds[BLOCK / 64];
-    const u32 base = blockIdx.x * SCAN_TILE;
-    u32 s = 0;
+    __shared__ u32 tile_s, excl_s;
+    const u32 epoch = C->step + 1u;
+    if (threadIdx.x == 0) tile_s = atomicAdd(&C->scan_tile, 1u);
+    __syncthreads();
+    const u32 tile = tile_s;
+    const u32 base = tile * SCAN_TILE;
+    u32 v[SCAN_ITEMS], tsum = 0;
 #pragma unroll
     for (int j = 0; j < SCAN_ITEMS; ++j) {
         const u32 i = base + j * BLOCK + threadIdx.x;
-        s += i < n ? cnt[i] : 0u;
+        v[j] = i < n ? cnt[i] : 0u;
+        tsum += v[j];
     }
-    s = block_sum(s, lds);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = s;
-}
-
-__global__ __launch_bounds__(BLOCK) void k_scan_top(u32 *__restrict__ bsum, u32 nb)
-{
-    __shared__ u32 lds[BLOCK / 64];
-    u32 carry = 0;
-    for (u32 b = 0; b < nb; b += BLOCK) {
-        const u32 i = b + threadIdx.x;
-        const u32 v = i < nb ? bsum[i] : 0u;
-        u32 tot;
-        const u32 ex = block_excl_scan(v, lds, tot);
-        if (i < nb) bsum[i] = carry + ex;
-        carry += tot;
+    const u32 total = block_sum(tsum, lds);
+    if (threadIdx.x == 0) {
+        u32 excl = 0;
+        if (tile == 0) {
+            __hip_atomic_store(&status[0], scan_pack(epoch, SCAN_PRE, total), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(&status[tile], scan_pack(epoch, SCAN_AGG, total), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            int k = (int)tile - 1;
+            u64 spins = 0;
+            while (k >= 0) {
+                const u64 st = __hip_atomic_load(&status[k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                const u32 ep = (u32)(st >> 34), fl = (u32)(st >> 32) & 3u;
+                if (ep != (epoch & 0x3FFFFFFFu) || fl == 0u) {
+                    if (++spins > SCAN_SPIN_LIMIT) {
+                        atomicOr(&C->err, (u32)ERR_SCAN);
+                        break;
+                    }
+                    continue;
+                }
+                excl += (u32)st;
+                if (fl == SCAN_PRE) break;
+                --k;
+            }
+            __hip_atomic_store(&status[tile], scan_pack(epoch, SCAN_PRE, excl + total), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        excl_s = excl;
     }
-}
-
-__global__ __launch_bounds__(BLOCK) void k_scan_down(u32 *__restrict__ cnt, u32 n, const u32 *__restrict__ bsum,
-                                                      u32 *__restrict__ start, Counters *C)
-{
-    __shared__ u32 lds[BLOCK / 64];
-    const u32 base = blockIdx.x * SCAN_TILE;
-    u32 carry = bsum[blockIdx.x];
+    __syncthreads();
+    u32 carry = excl_s;
+#pragma unroll
     for (int j = 0; j < SCAN_ITEMS; ++j) {
         const u32 i = base + j * BLOCK + threadIdx.x;
-        const u32 v = i < n ? cnt[i] : 0u;
         u32 tot;
-        const u32 ex = block_excl_scan(v, lds, tot);
+        const u32 ex = block_excl_scan(v[j], lds, tot);
         if (i < n) {
             start[i] = carry + ex;
             cnt[i] = 0u;
         }
         carry += tot;
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    if (tile == ntiles - 1 && threadIdx.x == 0) {
         start[n] = carry;
         C->n_live = carry;
     }
@@ -199,16 +227,14 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(u32 *__restrict__ cnt, u32 
 // K3: write each moved record to its sorted place.
 // ---------------------------------------------------------------------------
 template <int DIM, class T>
-__global__ __launch_bounds__(BLOCK) void k_scatter(Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ rank,
+__global__ __launch_bounds__(BLOCK) void k_scatter(Params P, const Rec<T> *__restrict__ tmp, const u32 *__restrict__ rank,
                                                     const u32 *__restrict__ start, Rec<T> *__restrict__ out, const Counters *C)
 {
-    const u32 step = C->step;
     const u32 n = C->n_rec;
     for (u32 i = gtid(); i < n; i += gstride()) {
-        const Rec<T> r = rec[i];
-        const u32 m = rec_meta(r), sp = meta_sp(m);
+        const Rec<T> q = tmp[i];
+        const u32 sp = meta_sp(rec_meta(q));
         if (sp > SP_C) continue;
-        const Rec<T> q = moved<DIM, T>(P, r, m, step);
         const u32 key = sp * P.n_cells + cell_of<DIM, T>(P, q);
         const u32 dst = start[key] + rank[i];
         if (dst < P.cap) out[dst] = q;
@@ -451,9 +477,10 @@ template <int DIM, class T, int PM>
 __global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start,
                                                        PairEnt *__restrict__ list, Counters *C)
 {
-    constexpr int LCAP = LdsRecCap<T>::value;
-    __shared__ Rec<T> sb[LCAP];
-    __shared__ u32 sidx[LCAP];
+    constexpr int LCAP = 1024;
+    // B positions relative to the brick origin, periodic images already
+    // applied, and the B record index in the fourth lane
+    __shared__ float4 sbr[LCAP];
     __shared__ u32 off[MAX_HALO + 1], hsrc[MAX_HALO];
     __shared__ u32 rowpre[MAX_ROWS + 1], rowst[MAX_ROWS];
     __shared__ PairEnt q[QCAP];
@@ -471,6 +498,7 @@ __global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__
     const int hx = ex + 2, hy = ey + 2, hz = DIM == 3 ? ez + 2 : 1;
     const int nh = hx * hy * hz;
     const u32 bbase = P.n_cells;
+    const double ox = x0 / P.cs[0], oy = y0 / P.cs[1], oz = DIM == 3 ? z0 / P.cs[2] : 0.0;
 
     // 1. bucket ranges of this thread's halo cells and of the brick's A rows,
     //    all global loads issued before any is used
@@ -525,11 +553,11 @@ __global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__
     }
     __syncthreads();
 
-    // 2. stage the halo's B records in LDS (one global load per record)
+    // 2. stage the halo's B positions in LDS (one global load per record)
     const u32 total = base;
     const bool use_lds = total <= (u32)LCAP;
     if (use_lds) {
-#pragma unroll 4
+#pragma unroll 2
         for (u32 i = threadIdx.x; i < total; i += PBLOCK) {
             int lo = 0, hi = nh;  // off[lo] <= i < off[hi]
             while (hi - lo > 1) {
@@ -538,16 +566,26 @@ __global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__
                 else hi = mid;
             }
             const u32 src = hsrc[lo] + (i - off[lo]);
-            sb[i] = rec[src];
-            sidx[i] = src;
+            const Rec<T> rb = rec[src];
+            // periodic image of the halo cell relative to the brick
+            const int ix = x0 - 1 + lo % hx, r = lo / hx;
+            const int iy = y0 - 1 + r % hy, iz = z0 - 1 + r / hy;
+            double px = (double)rb.x - ox, py = (double)rb.y - oy, pz = DIM == 3 ? (double)rb.z - oz : 0.0;
+            px += ix < 0 ? -P.L[0] : (ix >= nx ? P.L[0] : 0.0);
+            py += iy < 0 ? -P.L[1] : (iy >= ny ? P.L[1] : 0.0);
+            if (DIM == 3) pz += iz < 0 ? -P.L[2] : (iz >= nz ? P.L[2] : 0.0);
+            sbr[i] = make_float4((float)px, (float)py, (float)pz, __uint_as_float(src));
         }
     } else if (threadIdx.x == 0) {
         atomicAdd((unsigned long long *)&C->stats[ST_LDS_FALLBACK], 1ull);
     }
     __syncthreads();
 
-    // 3. every A of the brick against the B's of its 3^d neighbour cells
+    // 3. every A of the brick against the B's of its 3^d neighbour cells: a
+    //    binary32 test against a radius widened by the rounding of the
+    //    relative coordinates, then the exact test on the few that pass
     const u32 nA = rowpre[nr];
+    const float rpre = P.rcut2f_pre;
     for (u32 i = threadIdx.x; i < nA; i += PBLOCK) {
         int r = 0;
         while (r + 1 < nr && rowpre[r + 1] <= i) ++r;
@@ -557,13 +595,21 @@ __global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__
             const int lx = cell1((double)ra.x, P.cs[0], nx) - x0 + 1;
             const int ly = cell1((double)ra.y, P.cs[1], ny) - y0 + 1;
             const int lz = DIM == 3 ? cell1((double)ra.z, P.cs[2], nz) - z0 + 1 : 0;
+            const float ax = (float)((double)ra.x - ox), ay = (float)((double)ra.y - oy);
+            const float az = DIM == 3 ? (float)((double)ra.z - oz) : 0.0f;
             const int zlo = DIM == 3 ? -1 : 0, zhi = -zlo;
             for (int dz = zlo; dz <= zhi; ++dz)
                 for (int dy = -1; dy <= 1; ++dy) {
                     const int h0 = ((lz + dz) * hy + (ly + dy)) * hx + (lx - 1);
                     const u32 je = off[h0 + 3];
-                    for (u32 j = off[h0]; j < je; ++j)
-                        if (in_range<DIM, T, PM>(P, ra, sb[j])) append_pair(q, &nq, list, C, P, ia, sidx[j]);
+                    for (u32 j = off[h0]; j < je; ++j) {
+                        const float4 v = sbr[j];
+                        const float ddx = v.x - ax, ddy = v.y - ay, ddz = v.z - az;
+                        if (ddx * ddx + ddy * ddy + ddz * ddz < rpre) {
+                            const u32 jb = __float_as_uint(v.w);
+                            if (in_range<DIM, T, PM>(P, ra, rec[jb])) append_pair(q, &nq, list, C, P, ia, jb);
+                        }
+                    }
                 }
         } else {
             for_pairs<DIM, T, PM>(P, rec, start, ra, [&](u32 jb, const Rec<T> &) { append_pair(q, &nq, list, C, P, ia, jb); });
@@ -745,21 +791,36 @@ __global__ __launch_bounds__(BLOCK) void k_select_a(Params P, const PairEnt *__r
     if (picks) atomicAdd((unsigned long long *)&C->stats[ST_PICKS], (unsigned long long)picks);
 }
 
+constexpr u32 EV_DECAY = 0x80000000u;
+
 // ---------------------------------------------------------------------------
 // K6: B-side choice.  The picked entry with the smallest A slot of each B
 // chain leads; it applies the rule with U = {b, -, step, SELB} and queues the
 // winning pair as an event.
 // ---------------------------------------------------------------------------
-constexpr u32 EV_DECAY = 0x80000000u;
-
+// Blocks [0, nb_sel) run the B-side choice over the pair list; the others
+// mark the C records (binned at the start of the step) that decay:
+// xi < 1 - e^{-k_off dt}, xi = {c, -, step, UNI} (eq. rad_prob, step 4).
+template <class T>
 __global__ __launch_bounds__(BLOCK) void k_select_b(Params P, const PairEnt *__restrict__ list, const CandEnt *__restrict__ cand,
                                                      const u32 *__restrict__ flag, const u64 *__restrict__ headB,
-                                                     const u32 *__restrict__ nextB, u32 *__restrict__ ev, Counters *C)
+                                                     const u32 *__restrict__ nextB, const Rec<T> *__restrict__ rec,
+                                                     const u32 *__restrict__ start, u32 *__restrict__ ev, Counters *C, u32 nb_sel)
 {
     const u32 step = C->step;
+    if (blockIdx.x >= nb_sel) {
+        if (!P.reversible) return;
+        const u32 beg = start[2 * P.n_cells], end = start[3 * P.n_cells];
+        const u32 t0 = (blockIdx.x - nb_sel) * BLOCK + threadIdx.x, ts = (gridDim.x - nb_sel) * BLOCK;
+        for (u32 i = beg + t0; i < end; i += ts) {
+            const u32 sc = meta_slot(rec_meta(rec[i]));
+            if (below(philox(sc, NOSLOT, step, TAG_UNI, P.key).x, P.p_uni)) ev[atomicAdd(&C->n_ev, 1u)] = EV_DECAY | i;
+        }
+        return;
+    }
     const u32 n = min(C->n_pl, P.cap_pl);
     u32 n_match = 0;
-    for (u32 k = gtid(); k < n; k += gstride()) {
+    for (u32 k = blockIdx.x * BLOCK + threadIdx.x; k < n; k += nb_sel * BLOCK) {
         if (flag[k] != PE_PICKED) continue;
         const u32 h = (u32)headB[list[k].b_idx];
         u32 mins = NOSLOT, count = 0;
@@ -780,17 +841,25 @@ __global__ __launch_bounds__(BLOCK) void k_select_b(Params P, const PairEnt *__r
     if (n_match) atomicAdd((unsigned long long *)&C->stats[ST_MATCHES], (unsigned long long)n_match);
 }
 
-// K8a: which C records (those binned at the start of the step) decay:
-// xi < 1 - e^{-k_off dt} with xi = {c, -, step, UNI} (eq. rad_prob, step 4).
-__global__ __launch_bounds__(BLOCK) void k_decay_mark(Params P, const Rec<float> *recf, const Rec<double> *recd,
-                                                       const u32 *__restrict__ start, u32 *__restrict__ ev, Counters *C)
+// K9: close the step (counters are read with device-scope atomics, since the
+// other blocks of the closing kernel wrote them the same way).
+__device__ inline u32 ld_u32(u32 *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline u64 ld_u64(u64 *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+__device__ inline void finish_step(Counters *C)
 {
-    const u32 step = C->step;
-    const u32 beg = start[2 * P.n_cells], end = start[3 * P.n_cells];
-    for (u32 i = beg + gtid(); i < end; i += gstride()) {
-        const u32 sc = meta_slot(recf ? rec_meta(recf[i]) : rec_meta(recd[i]));
-        if (below(philox(sc, NOSLOT, step, TAG_UNI, P.key).x, P.p_uni)) ev[atomicAdd(&C->n_ev, 1u)] = EV_DECAY | i;
+    C->stats[ST_PAIRS] = min(ld_u32(&C->n_pl), 0xFFFFFFFFu);
+    for (int s = 0; s < ST_N; ++s) {
+        const u64 v = ld_u64(&C->stats[s]);
+        C->stats_last[s] = v;
+        C->stats_sum[s] += v;
+        C->stats[s] = 0;
     }
+    C->n_rec = ld_u32(&C->n_live) + ld_u32(&C->n_append);
+    C->n_pl = C->n_append = C->n_ev = 0;
+    C->scan_tile = 0;
+    C->blocks_done = 0;
+    C->step += 1u;
 }
 
 // ---------------------------------------------------------------------------
@@ -950,20 +1019,15 @@ __global__ __launch_bounds__(BLOCK) void k_events(Params P, Rec<T> *__restrict__
         if (e & EV_DECAY) ev_decay<DIM, T>(P, rec, e & ~EV_DECAY, partner, step, C, dbg_d);
         else ev_match<DIM, T>(P, rec, list[e].a_idx, list[e].b_idx, partner, step, C, dbg_m);
     }
-}
-
-// K9: close the step.
-__global__ void k_finish(Counters *C)
-{
-    C->stats[ST_PAIRS] = min(C->n_pl, 0xFFFFFFFFu);
-    for (int s = 0; s < ST_N; ++s) {
-        C->stats_last[s] = C->stats[s];
-        C->stats_sum[s] += C->stats[s];
-        C->stats[s] = 0;
+    // K9: the last block to finish closes the step
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&C->blocks_done, 1u) == gridDim.x - 1) {
+            __threadfence();
+            finish_step(C);
+        }
     }
-    C->n_rec = C->n_live + C->n_append;
-    C->n_pl = C->n_append = C->n_ev = 0;
-    C->step += 1u;
 }
 
 // ---------------------------------------------------------------------------

@@ -22,7 +22,7 @@ PREC_FP64, PREC_FP32, PREC_FP32_FP64NC = 0, 1, 2
  READ_DBG_PAIRS, READ_DBG_PICKS, READ_DBG_MATCHES, READ_DBG_DISS, READ_DBG_CELLS, READ_TIMING, READ_GRID) = range(15)
 STAT_NAMES = ["pairs", "cand", "overlap", "r0clamp", "picks", "matches", "react", "decay", "geminate",
               "attempts", "bound_hits", "near", "lds_fallback"]
-KERNEL_NAMES = ["move", "scan", "scatter", "pairs", "eval", "select_a", "select_b", "decay_mark", "events", "finish"]
+KERNEL_NAMES = ["move", "scan", "scatter", "pairs", "eval", "select_a", "select_b", "events"]
 
 PAIR_DT = np.dtype([("i", "<u4"), ("j", "<u4"), ("R", "<f8"), ("R0", "<f8"), ("p", "<f8"),
                     ("draw", "<u4"), ("cand", "<i4")], align=True)
