@@ -178,31 +178,50 @@ __global__ __launch_bounds__(BLOCK) void k_scan(u32 *__restrict__ cnt, u32 n, u3
         tsum += v[j];
     }
     const u32 total = block_sum(tsum, lds);
-    if (threadIdx.x == 0) {
+    // publish this tile's sum; the first wave then looks back over windows of
+    // 64 predecessors at a time
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&status[tile], scan_pack(epoch, tile == 0 ? SCAN_PRE : SCAN_AGG, total), __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
         u32 excl = 0;
-        if (tile == 0) {
-            __hip_atomic_store(&status[0], scan_pack(epoch, SCAN_PRE, total), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(&status[tile], scan_pack(epoch, SCAN_AGG, total), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            int k = (int)tile - 1;
-            u64 spins = 0;
-            while (k >= 0) {
+        int top = (int)tile - 1;  // newest predecessor not yet added
+        u64 spins = 0;
+        bool bad = false;
+        while (top >= 0) {
+            const int k = top - lane;  // lane 0 looks at the nearest predecessor
+            u32 fl = SCAN_PRE, val = 0;
+            if (k >= 0) {
                 const u64 st = __hip_atomic_load(&status[k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                const u32 ep = (u32)(st >> 34), fl = (u32)(st >> 32) & 3u;
-                if (ep != (epoch & 0x3FFFFFFFu) || fl == 0u) {
-                    if (++spins > SCAN_SPIN_LIMIT) {
-                        atomicOr(&C->err, (u32)ERR_SCAN);
-                        break;
-                    }
-                    continue;
-                }
-                excl += (u32)st;
-                if (fl == SCAN_PRE) break;
-                --k;
+                fl = ((u32)(st >> 34) == (epoch & 0x3FFFFFFFu)) ? (u32)(st >> 32) & 3u : 0u;
+                val = (u32)st;
             }
-            __hip_atomic_store(&status[tile], scan_pack(epoch, SCAN_PRE, excl + total), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const u64 pre = __ballot(fl == SCAN_PRE), inv = __ballot(fl == 0u);
+            // lanes up to the nearest inclusive prefix must all be valid
+            const int first_pre = pre ? __ffsll((unsigned long long)pre) - 1 : 64;
+            const u64 need = first_pre >= 63 ? ~0ull : ((2ull << first_pre) - 1ull);
+            if (inv & need) {
+                if (++spins > SCAN_SPIN_LIMIT) {
+                    bad = true;
+                    break;
+                }
+                continue;
+            }
+            u32 add = lane <= first_pre ? val : 0u;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) add += __shfl_xor(add, o, 64);
+            excl += add;
+            if (first_pre < 64) break;
+            top -= 64;
         }
-        excl_s = excl;
+        if (lane == 0) {
+            if (bad) atomicOr(&C->err, (u32)ERR_SCAN);
+            if (tile != 0)
+                __hip_atomic_store(&status[tile], scan_pack(epoch, SCAN_PRE, excl + total), __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            excl_s = excl;
+        }
     }
     __syncthreads();
     u32 carry = excl_s;
