@@ -126,7 +126,7 @@ enum {
     ST_GEMINATE, ST_ATTEMPTS, ST_BOUND, ST_NEAR, ST_LDS_FALLBACK, ST_N
 };
 
-enum { ERR_PAIRS = 1, ERR_SCAN = 2, ERR_APPEND = 8 };
+enum { ERR_PAIRS = 1, ERR_APPEND = 8 };
 
 // Device-resident counters; the work sizes of the data-dependent stages live
 // here so that no stage needs the host to learn a count.
@@ -139,9 +139,8 @@ struct Counters {
     u32 err;
     u32 n_dbg[4];   // pairs, picks, matches, dissociations logged this step
     u32 n_ev;       // events (matched pairs and decays) queued this step
-    u32 scan_tile;  // next tile of the bucket scan
     u32 blocks_done;// blocks of the last kernel of the step that are done
-    u32 pad[3];
+    u32 pad[4];
     u64 stats[ST_N];
     u64 stats_last[ST_N];
     u64 stats_sum[ST_N];

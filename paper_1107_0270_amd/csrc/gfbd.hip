@@ -151,7 +151,6 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     double cell_edge = 0.0;
     // device memory
     Rec<T> *rec[2] = {nullptr, nullptr}, *tmp = nullptr;
-    u64 *scan_status = nullptr;
     u32 *rank = nullptr, *cnt = nullptr, *start = nullptr, *bsum = nullptr, *partner = nullptr;
     PairEnt *plist = nullptr;
     CandEnt *cand = nullptr;
@@ -282,12 +281,13 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         P.n_keys = 3u * P.n_cells;
         P.cap = (u32)n;
         P.cap_pl = (u32)std::min<uint64_t>(std::max<uint64_t>(1u << 20, 4 * n), 1u << 30);
-        // LDS bricks: about 128 cells (halo <= MAX_HALO), fewer when buckets are crowded
+        // LDS bricks: about 256 cells (halo <= MAX_HALO), fewer when buckets are crowded
         P.tiled = P.nc[0] >= 3 && P.nc[1] >= 3 && (DIM == 2 || P.nc[2] >= 3);
         if (P.tiled) {
             const double bpc = (double)std::max<uint64_t>(nB + nC, 1) / (double)ncell;
             const double lcap = 1024.0;
-            int bb[3] = {std::min(8, P.nc[0] - 2), std::min(DIM == 3 ? 4 : 16, P.nc[1] - 2), DIM == 3 ? std::min(4, P.nc[2] - 2) : 1};
+            int bb[3] = {std::min(DIM == 3 ? 8 : 16, P.nc[0] - 2), std::min(DIM == 3 ? 8 : 16, P.nc[1] - 2),
+                         DIM == 3 ? std::min(4, P.nc[2] - 2) : 1};
             auto halo = [&] { return (bb[0] + 2.0) * (bb[1] + 2.0) * (DIM == 3 ? bb[2] + 2.0 : 1.0); };
             while (halo() * bpc > 0.6 * lcap && (bb[0] > 1 || bb[1] > 1 || bb[2] > 1)) {
                 int k = 0;
@@ -295,6 +295,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
                     if (bb[d] > bb[k]) k = d;
                 bb[k] = (bb[k] + 1) / 2;
             }
+            if (halo() > MAX_HALO || bb[1] * bb[2] > MAX_ROWS) return fail(SIM_EUNSUPPORTED, "pair-search brick too large");
             P.bx = bb[0];
             P.by = bb[1];
             P.bz = bb[2];
@@ -308,9 +309,9 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         nb_scan = (P.n_keys + SCAN_TILE - 1) / SCAN_TILE;
         // device buffers
         int rc;
-        if ((rc = alloc(rec[0], n)) || (rc = alloc(rec[1], n)) || (rc = alloc(tmp, n)) || (rc = alloc(scan_status, nb_scan)) ||
-            (rc = alloc(rank, n)) || (rc = alloc(cnt, P.n_keys)) ||
-            (rc = alloc(start, P.n_keys + 1)) || (rc = alloc(bsum, nb_scan)) || (rc = alloc(partner, n)) ||
+        if ((rc = alloc(rec[0], n)) || (rc = alloc(rec[1], n)) || (rc = alloc(tmp, n)) ||
+            (rc = alloc(rank, n)) || (rc = alloc(cnt, (uint64_t)nb_scan * SCAN_TILE)) ||
+            (rc = alloc(start, (uint64_t)nb_scan * SCAN_TILE + 1)) || (rc = alloc(bsum, nb_scan)) || (rc = alloc(partner, n)) ||
             (rc = alloc(plist, P.cap_pl)) || (rc = alloc(cand, P.cap_pl)) || (rc = alloc(flag, P.cap_pl)) ||
             (rc = alloc(nextA, P.cap_pl)) || (rc = alloc(nextB, P.cap_pl)) || (rc = alloc(headA, n)) ||
             (rc = alloc(headB, n)) || (rc = alloc(ev, n)) || (rc = alloc(ctr, 1)) || (rc = alloc(g2c, 4 * (MAXTERMS + 1))) ||
@@ -321,7 +322,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
                 (rc = alloc(dbg_picks, M.dbg_cap)) || (rc = alloc(dbg_matches, M.dbg_cap)) || (rc = alloc(dbg_diss, M.dbg_cap)))
                 return rc;
         }
-        HIPCHECK(hipMemsetAsync(cnt, 0, sizeof(u32) * P.n_keys, M.stream));
+        HIPCHECK(hipMemsetAsync(cnt, 0, sizeof(u32) * nb_scan * SCAN_TILE, M.stream));  // padding stays zero
         double g2h[4 * (MAXTERMS + 1)];
         h_g2_constants(P.hh, g2h);
         HIPCHECK(hipMemcpyAsync(g2c, g2h, sizeof(g2h), hipMemcpyHostToDevice, M.stream));
@@ -354,7 +355,6 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         HIPCHECK(hipMemcpyAsync(ctr, &c, sizeof(c), hipMemcpyHostToDevice, M.stream));
         HIPCHECK(hipMemsetAsync(headA, 0, sizeof(u64) * n, M.stream));  // no chain survives a reload
         HIPCHECK(hipMemsetAsync(headB, 0, sizeof(u64) * n, M.stream));
-        HIPCHECK(hipMemsetAsync(scan_status, 0, sizeof(u64) * nb_scan, M.stream));
         HIPCHECK(hipStreamSynchronize(M.stream));
         cur = 0;
         stepno = step0;
@@ -392,7 +392,10 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         const u32 g_all = grid_for(n, 8192);
         const u32 g_pl = 1024;
         launch(SIM_K_MOVE, [&] { k_move_count<DIM, T><<<g_all, BLOCK, 0, st>>>(P, in, tmp, rank, cnt, ctr); });
-        launch(SIM_K_SCAN, [&] { k_scan<<<nb_scan, BLOCK, 0, st>>>(cnt, P.n_keys, start, scan_status, ctr, nb_scan); });
+        launch(SIM_K_SCAN, [&] {
+            k_scan_tiles<<<nb_scan, BLOCK, 0, st>>>(cnt, bsum);
+            k_scan<<<nb_scan, BLOCK, 0, st>>>(cnt, bsum, start, ctr);
+        });
         launch(SIM_K_SCATTER, [&] { k_scatter<DIM, T><<<g_all, BLOCK, 0, st>>>(P, tmp, rank, start, out, ctr); });
         if (M.debug) {
             k_fill<<<grid_for(n * DIM, 2048), BLOCK, 0, st>>>(dbg_moved, n * DIM, (int *)dbg_cells, (u32)n);

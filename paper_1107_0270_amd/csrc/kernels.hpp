@@ -112,7 +112,7 @@ __global__ __launch_bounds__(BLOCK) void k_move_count(Params P, const Rec<T> *__
 
 // ---------------------------------------------------------------------------
 // K2: exclusive scan of the bucket counts into bucket starts (and clear the
-// counts for the next step): reduce tiles, scan tile sums, scan tiles.
+// counts for the next step).
 // ---------------------------------------------------------------------------
 __device__ inline u32 wave_incl_scan(u32 v)
 {
@@ -150,95 +150,72 @@ __device__ inline u32 block_sum(u32 v, u32 *lds)
     return t;
 }
 
-// One pass: tiles are claimed in order through a counter; each tile
-// publishes its sum, then adds the sums of the tiles before it (stopping at
-// the first tile that has published its inclusive prefix).  Status words are
-// tagged with the step, so they never need clearing.  A bounded wait: a
-// status that never arrives sets an error flag instead of hanging.
-constexpr u32 SCAN_AGG = 1u, SCAN_PRE = 2u;
-constexpr u64 SCAN_SPIN_LIMIT = 1ull << 24;
+// Two passes, no waiting.  Each thread owns SCAN_ITEMS consecutive keys (four
+// 16-byte loads); the count and start arrays are padded to whole tiles and
+// the padding of the counts stays zero.  Pass 1 writes tile sums; pass 2 adds
+// up the sums of the tiles before its own (a few hundred values) and scans
+// its tile.
+static_assert(SCAN_ITEMS == 16, "four uint4 per thread");
 
-__device__ __forceinline__ u64 scan_pack(u32 epoch, u32 flag, u32 v) { return ((u64)(epoch & 0x3FFFFFFFu) << 34) | ((u64)flag << 32) | v; }
+__device__ __forceinline__ void load16(const u32 *p, u32 v[16])
+{
+    const uint4 *q = reinterpret_cast<const uint4 *>(p);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint4 t = q[k];
+        v[4 * k] = t.x;
+        v[4 * k + 1] = t.y;
+        v[4 * k + 2] = t.z;
+        v[4 * k + 3] = t.w;
+    }
+}
 
-__global__ __launch_bounds__(BLOCK) void k_scan(u32 *__restrict__ cnt, u32 n, u32 *__restrict__ start, u64 *__restrict__ status,
-                                                 Counters *C, u32 ntiles)
+__global__ __launch_bounds__(BLOCK) void k_scan_tiles(const u32 *__restrict__ cnt, u32 *__restrict__ tsum)
 {
     __shared__ u32 lds[BLOCK / 64];
-    __shared__ u32 tile_s, excl_s;
-    const u32 epoch = C->step + 1u;
-    if (threadIdx.x == 0) tile_s = atomicAdd(&C->scan_tile, 1u);
-    __syncthreads();
-    const u32 tile = tile_s;
-    const u32 base = tile * SCAN_TILE;
-    u32 v[SCAN_ITEMS], tsum = 0;
+    u32 v[16];
+    load16(cnt + (size_t)blockIdx.x * SCAN_TILE + SCAN_ITEMS * threadIdx.x, v);
+    u32 s = 0;
 #pragma unroll
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        const u32 i = base + j * BLOCK + threadIdx.x;
-        v[j] = i < n ? cnt[i] : 0u;
-        tsum += v[j];
-    }
-    const u32 total = block_sum(tsum, lds);
-    // publish this tile's sum; the first wave then looks back over windows of
-    // 64 predecessors at a time
-    if (threadIdx.x == 0)
-        __hip_atomic_store(&status[tile], scan_pack(epoch, tile == 0 ? SCAN_PRE : SCAN_AGG, total), __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
-        u32 excl = 0;
-        int top = (int)tile - 1;  // newest predecessor not yet added
-        u64 spins = 0;
-        bool bad = false;
-        while (top >= 0) {
-            const int k = top - lane;  // lane 0 looks at the nearest predecessor
-            u32 fl = SCAN_PRE, val = 0;
-            if (k >= 0) {
-                const u64 st = __hip_atomic_load(&status[k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                fl = ((u32)(st >> 34) == (epoch & 0x3FFFFFFFu)) ? (u32)(st >> 32) & 3u : 0u;
-                val = (u32)st;
-            }
-            const u64 pre = __ballot(fl == SCAN_PRE), inv = __ballot(fl == 0u);
-            // lanes up to the nearest inclusive prefix must all be valid
-            const int first_pre = pre ? __ffsll((unsigned long long)pre) - 1 : 64;
-            const u64 need = first_pre >= 63 ? ~0ull : ((2ull << first_pre) - 1ull);
-            if (inv & need) {
-                if (++spins > SCAN_SPIN_LIMIT) {
-                    bad = true;
-                    break;
-                }
-                continue;
-            }
-            u32 add = lane <= first_pre ? val : 0u;
+    for (int k = 0; k < 16; ++k) s += v[k];
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) tsum[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan(u32 *__restrict__ cnt, const u32 *__restrict__ tsum, u32 *__restrict__ start,
+                                                 Counters *C)
+{
+    __shared__ u32 lds[BLOCK / 64];
+    const size_t base = (size_t)blockIdx.x * SCAN_TILE + SCAN_ITEMS * threadIdx.x;
+    u32 v[16];
+    load16(cnt + base, v);
+    u32 before = 0;
+    for (u32 t = threadIdx.x; t < blockIdx.x; t += BLOCK) before += tsum[t];
+    const u32 carry = block_sum(before, lds);
+    u32 mine = 0;
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) add += __shfl_xor(add, o, 64);
-            excl += add;
-            if (first_pre < 64) break;
-            top -= 64;
-        }
-        if (lane == 0) {
-            if (bad) atomicOr(&C->err, (u32)ERR_SCAN);
-            if (tile != 0)
-                __hip_atomic_store(&status[tile], scan_pack(epoch, SCAN_PRE, excl + total), __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            excl_s = excl;
-        }
-    }
-    __syncthreads();
-    u32 carry = excl_s;
+    for (int k = 0; k < 16; ++k) mine += v[k];
+    u32 total;
+    u32 run = carry + block_excl_scan(mine, lds, total);
+    uint4 *o = reinterpret_cast<uint4 *>(start + base);
+    uint4 *z = reinterpret_cast<uint4 *>(cnt + base);
 #pragma unroll
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        const u32 i = base + j * BLOCK + threadIdx.x;
-        u32 tot;
-        const u32 ex = block_excl_scan(v[j], lds, tot);
-        if (i < n) {
-            start[i] = carry + ex;
-            cnt[i] = 0u;
-        }
-        carry += tot;
+    for (int k = 0; k < 4; ++k) {
+        uint4 t;
+        t.x = run;
+        run += v[4 * k];
+        t.y = run;
+        run += v[4 * k + 1];
+        t.z = run;
+        run += v[4 * k + 2];
+        t.w = run;
+        run += v[4 * k + 3];
+        o[k] = t;
+        z[k] = make_uint4(0u, 0u, 0u, 0u);
     }
-    if (tile == ntiles - 1 && threadIdx.x == 0) {
-        start[n] = carry;
-        C->n_live = carry;
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == BLOCK - 1) {
+        start[(size_t)gridDim.x * SCAN_TILE] = run;
+        C->n_live = run;
     }
 }
 
@@ -447,14 +424,11 @@ __device__ inline void block_add_stats(const u32 *vals, int nv, u64 *dst, u32 *l
     }
 }
 
-constexpr int PBLOCK = 128;      // threads per pair-search workgroup
-constexpr int QCAP = 256;        // pairs queued in LDS per workgroup
-constexpr int MAX_HALO = 512;    // halo cells per brick
-constexpr int HALO_PER_T = MAX_HALO / PBLOCK;
+constexpr int PBLOCK = 256;      // threads per pair-search workgroup
+constexpr int QCAP = 512;        // pairs queued in LDS per workgroup
+constexpr int MAX_HALO = 1024;   // halo cells per brick
+constexpr int CELLS_PER_T = MAX_HALO / PBLOCK;
 constexpr int MAX_ROWS = 64;     // rows of A cells per brick
-template <class T> struct LdsRecCap {
-    static constexpr int value = sizeof(T) == 4 ? 1024 : 512;
-};
 
 // exclusive scan over a workgroup of NT threads (NT / 64 waves)
 template <int NT> __device__ inline u32 group_excl_scan(u32 v, u32 *lds, u32 &total)
@@ -497,10 +471,10 @@ __global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__
                                                        PairEnt *__restrict__ list, Counters *C)
 {
     constexpr int LCAP = 1024;
-    // B positions relative to the brick origin, periodic images already
-    // applied, and the B record index in the fourth lane
+    // B positions relative to the brick origin (periodic image applied) and
+    // the B record index in the fourth lane, in halo-cell order
     __shared__ float4 sbr[LCAP];
-    __shared__ u32 off[MAX_HALO + 1], hsrc[MAX_HALO];
+    __shared__ u32 off[MAX_HALO + 1];
     __shared__ u32 rowpre[MAX_ROWS + 1], rowst[MAX_ROWS];
     __shared__ PairEnt q[QCAP];
     __shared__ u32 nq, qbase;
@@ -519,21 +493,26 @@ __global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__
     const u32 bbase = P.n_cells;
     const double ox = x0 / P.cs[0], oy = y0 / P.cs[1], oz = DIM == 3 ? z0 / P.cs[2] : 0.0;
 
-    // 1. bucket ranges of this thread's halo cells and of the brick's A rows,
-    //    all global loads issued before any is used
-    u32 hs[HALO_PER_T], hc[HALO_PER_T];
+    // 1. this thread's halo cells h = CELLS_PER_T * t + c: bucket ranges (all
+    //    loads issued together) and the periodic shift of each cell
+    u32 hs[CELLS_PER_T], he[CELLS_PER_T];
+    float sx[CELLS_PER_T], sy[CELLS_PER_T], sz[CELLS_PER_T];
+    u32 local = 0;
 #pragma unroll
-    for (int t = 0; t < HALO_PER_T; ++t) {
-        const int h = threadIdx.x + t * PBLOCK;
-        hs[t] = hc[t] = 0;
+    for (int c = 0; c < CELLS_PER_T; ++c) {
+        const int h = CELLS_PER_T * threadIdx.x + c;
+        hs[c] = he[c] = 0;
+        sx[c] = sy[c] = sz[c] = 0.0f;
         if (h < nh) {
-            const int ix = h % hx, r = h / hx;
-            const int gx = wrapc(x0 - 1 + ix, nx);
-            const int gy = wrapc(y0 - 1 + r % hy, ny);
-            const int gz = DIM == 3 ? wrapc(z0 - 1 + r / hy, nz) : 0;
+            const int r = h / hx;
+            const int ux = x0 - 1 + (h - r * hx), uy = y0 - 1 + r % hy, uz = z0 - 1 + r / hy;
+            const int gx = wrapc(ux, nx), gy = wrapc(uy, ny), gz = DIM == 3 ? wrapc(uz, nz) : 0;
             const u32 k = bbase + ((u32)gz * ny + gy) * nx + gx;
-            hs[t] = start[k];
-            hc[t] = start[k + 1];
+            hs[c] = start[k];
+            he[c] = start[k + 1];
+            sx[c] = ux < 0 ? -(float)P.L[0] : (ux >= nx ? (float)P.L[0] : 0.0f);
+            sy[c] = uy < 0 ? -(float)P.L[1] : (uy >= ny ? (float)P.L[1] : 0.0f);
+            if (DIM == 3) sz[c] = uz < 0 ? -(float)P.L[2] : (uz >= nz ? (float)P.L[2] : 0.0f);
         }
     }
     const int nr = ey * ez;
@@ -544,19 +523,15 @@ __global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__
         rs = start[akey];
         rc = start[akey + ex] - rs;
     }
-    // prefix of the halo bucket sizes in h order (h = thread + t * PBLOCK)
-    u32 base = 0;
 #pragma unroll
-    for (int t = 0; t < HALO_PER_T; ++t) {
-        const int h = threadIdx.x + t * PBLOCK;
-        const u32 c = hc[t] - hs[t];
-        u32 tot;
-        const u32 e = group_excl_scan<PBLOCK>(c, lds, tot);
-        if (h < nh) {
-            off[h] = base + e;
-            hsrc[h] = hs[t];
-        }
-        base += tot;
+    for (int c = 0; c < CELLS_PER_T; ++c) local += he[c] - hs[c];
+    u32 total;
+    u32 pos = group_excl_scan<PBLOCK>(local, lds, total);
+#pragma unroll
+    for (int c = 0; c < CELLS_PER_T; ++c) {
+        const int h = CELLS_PER_T * threadIdx.x + c;
+        if (h < nh) off[h] = pos;
+        pos += he[c] - hs[c];
     }
     if (threadIdx.x < 64) {
         const u32 inc = wave_incl_scan(rc);
@@ -567,33 +542,23 @@ __global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__
         if (threadIdx.x == 0) rowpre[0] = 0;
     }
     if (threadIdx.x == 0) {
-        off[nh] = base;
+        off[nh] = total;
         nq = 0;
     }
-    __syncthreads();
 
-    // 2. stage the halo's B positions in LDS (one global load per record)
-    const u32 total = base;
+    // 2. stage each cell's B records (the thread that owns the cell copies it)
     const bool use_lds = total <= (u32)LCAP;
     if (use_lds) {
-#pragma unroll 2
-        for (u32 i = threadIdx.x; i < total; i += PBLOCK) {
-            int lo = 0, hi = nh;  // off[lo] <= i < off[hi]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (off[mid] <= i) lo = mid;
-                else hi = mid;
+        pos -= local;  // start of this thread's first cell
+#pragma unroll
+        for (int c = 0; c < CELLS_PER_T; ++c) {
+            for (u32 j = hs[c]; j < he[c]; ++j, ++pos) {
+                const Rec<T> rb = rec[j];
+                const float px = (float)((double)rb.x - ox) + sx[c];
+                const float py = (float)((double)rb.y - oy) + sy[c];
+                const float pz = DIM == 3 ? (float)((double)rb.z - oz) + sz[c] : 0.0f;
+                sbr[pos] = make_float4(px, py, pz, __uint_as_float(j));
             }
-            const u32 src = hsrc[lo] + (i - off[lo]);
-            const Rec<T> rb = rec[src];
-            // periodic image of the halo cell relative to the brick
-            const int ix = x0 - 1 + lo % hx, r = lo / hx;
-            const int iy = y0 - 1 + r % hy, iz = z0 - 1 + r / hy;
-            double px = (double)rb.x - ox, py = (double)rb.y - oy, pz = DIM == 3 ? (double)rb.z - oz : 0.0;
-            px += ix < 0 ? -P.L[0] : (ix >= nx ? P.L[0] : 0.0);
-            py += iy < 0 ? -P.L[1] : (iy >= ny ? P.L[1] : 0.0);
-            if (DIM == 3) pz += iz < 0 ? -P.L[2] : (iz >= nz ? P.L[2] : 0.0);
-            sbr[i] = make_float4((float)px, (float)py, (float)pz, __uint_as_float(src));
         }
     } else if (threadIdx.x == 0) {
         atomicAdd((unsigned long long *)&C->stats[ST_LDS_FALLBACK], 1ull);
@@ -606,9 +571,13 @@ __global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__
     const u32 nA = rowpre[nr];
     const float rpre = P.rcut2f_pre;
     for (u32 i = threadIdx.x; i < nA; i += PBLOCK) {
-        int r = 0;
-        while (r + 1 < nr && rowpre[r + 1] <= i) ++r;
-        const u32 ia = rowst[r] + (i - rowpre[r]);
+        int lo = 0, hi = nr;  // rowpre[lo] <= i < rowpre[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (rowpre[mid] <= i) lo = mid;
+            else hi = mid;
+        }
+        const u32 ia = rowst[lo] + (i - rowpre[lo]);
         const Rec<T> ra = rec[ia];
         if (use_lds) {
             const int lx = cell1((double)ra.x, P.cs[0], nx) - x0 + 1;
@@ -876,7 +845,6 @@ __device__ inline void finish_step(Counters *C)
     }
     C->n_rec = ld_u32(&C->n_live) + ld_u32(&C->n_append);
     C->n_pl = C->n_append = C->n_ev = 0;
-    C->scan_tile = 0;
     C->blocks_done = 0;
     C->step += 1u;
 }
