@@ -43,6 +43,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=20, help="oracle steps timed for the CPU baseline (0 = skip)")
     ap.add_argument("--no-timing", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--pair-search", choices=["auto", "bricks", "direct"], default="auto",
+                    help="pair-search kernel (auto = the library's choice)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported", "n_gpus": args.gpus}))
@@ -57,7 +59,8 @@ def main():
     log(f"[bench] state: {len(sp)} particles, {red} redrawn overlaps, {time.time() - t0:.1f}s")
     def make(timing):
         return S.Sim(dim=3, box=box, dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
-                     k_off=cfg["k_off"], precision=cfg["precision"], seed=0, species=sp, pos=pos, timing=timing)
+                     k_off=cfg["k_off"], precision=cfg["precision"], seed=0, species=sp, pos=pos, timing=timing,
+                     pair_search={"auto": S.PAIRS_AUTO, "bricks": S.PAIRS_BRICKS, "direct": S.PAIRS_DIRECT}[args.pair_search])
 
     def timed(sim):
         sim.step(args.warmup)
@@ -135,6 +138,7 @@ def main():
                                "D=1 um^2/s, sigma=5 nm, kappa=0.1 um^3/s, k_off=10/s, dt=10 us",
                    "precision": "binary32 state and p_enc, binary64 near-contact arguments and propagation",
                    "particles": len(sp), "r_cut_um": der["rcut"], "cells": grid[:3],
+                   "pair_search": {S.PAIRS_BRICKS: "lds-bricks", S.PAIRS_DIRECT: "direct"}[grid[4]],
                    "step_launch": "one hipGraph replay per step"},
         "roofline": roof,
         "kernel_ms_per_step": {k: round(v[0] / max(args.steps, 1), 5) for k, v in kt.items()},

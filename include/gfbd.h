@@ -69,6 +69,14 @@ enum { SIM_BC_ABSORBING = 0, SIM_BC_REFLECTING = 1, SIM_BC_RADIATION = 2 };
  * Displacements, placements, the propagator and p_reac are binary64 in all modes. */
 enum { SIM_PREC_FP64 = 0, SIM_PREC_FP32 = 1, SIM_PREC_FP32_FP64NC = 2 };
 
+/* Kernel of the pair search (step 2); both find exactly the same pairs.
+ *  BRICKS  one workgroup per brick of cells stages the B records of the brick
+ *          and its one-cell halo in LDS (pays off with many B's per A);
+ *  DIRECT  one thread per A reads the neighbour buckets through L2;
+ *  AUTO    BRICKS when an A is expected to test more than 8 B's, else DIRECT.
+ * Grids with fewer than three cells along some axis always use DIRECT. */
+enum { SIM_PAIRS_AUTO = 0, SIM_PAIRS_BRICKS = 1, SIM_PAIRS_DIRECT = 2 };
+
 typedef struct {
     double D; /* diffusion constant, um^2/s, >= 0 */
 } sim_species;
@@ -92,6 +100,7 @@ typedef struct {
     double eps_cut;                /* cut-off: 1 - S(dt | r_cut) = eps_cut (0 = 1e-3) */
     double rcut;                   /* > 0: use this cut-off (um) instead of deriving it */
     double cell;                   /* > 0: requested cell edge (um, raised to >= r_cut); 0 = automatic */
+    int32_t pair_search;           /* SIM_PAIRS_* */
     int32_t n_species;             /* must be 3: A, B, C */
     const sim_species *species;    /* n_species entries; D_C is the C diffusion constant */
     int32_t n_reactions;           /* must be 1 */
@@ -134,7 +143,7 @@ enum {
     SIM_READ_DBG_DISS = 11, /* sim_dbg_diss[] (debug) */
     SIM_READ_DBG_CELLS = 12,/* uint32[n]: sort key (species * n_cells + cell) of each live slot after binning, else 0xFFFFFFFF (debug) */
     SIM_READ_TIMING = 13,   /* sim_kernel_time[SIM_K_N]: accumulated kernel times (timing) */
-    SIM_READ_GRID = 14      /* int64[4]: cells per edge x, y, z and total cells */
+    SIM_READ_GRID = 14      /* int64[5]: cells per edge x, y, z, total cells, pair-search kernel (SIM_PAIRS_BRICKS or _DIRECT) */
 };
 
 enum {

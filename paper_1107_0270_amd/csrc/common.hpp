@@ -102,6 +102,8 @@ struct Params {
     int n_terms;     // 2D expansion order
     double L[3], Lh[3];
     double cs[3];    // cells per um along each axis (n / L)
+    double ce[3];    // cell edge along each axis (L / n)
+    double reach;    // r_cut plus a rounding margin: neighbour cells farther away are skipped
     int nc[3];
     u32 n_cells, n_keys;
     double sd[3];    // sqrt(2 D dt) of A, B, C

@@ -131,9 +131,13 @@ namespace {
         if (e_ != hipSuccess) return fail(SIM_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
     } while (0)
 
+// expected B's tested per A above which the LDS brick search is chosen
+constexpr double PAIR_TESTS_TILED = 8.0;
+
 struct Model {
     int dim, prec, bc;
     double box[3], dt, D[3], sigma, kappa, k_off, eps, rcut_req, cell_req;
+    int pair_search;
     uint64_t seed;
     uint32_t replica;
     int n_terms;
@@ -148,7 +152,8 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     uint64_t n = 0, stepno = 0;
     int cur = 0;
     uint32_t maxA = 0, maxC = 0, nb_scan = 0;
-    double cell_edge = 0.0;
+    double cell_edge = 0.0, pair_tests = 0.0;
+    bool narrow = false;
     // device memory
     Rec<T> *rec[2] = {nullptr, nullptr}, *tmp = nullptr;
     u32 *rank = nullptr, *cnt = nullptr, *start = nullptr, *bsum = nullptr, *partner = nullptr;
@@ -229,6 +234,10 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             for (int k = 0; k < DIM; ++k) lmax = std::max(lmax, M.box[k]);
             const double slack = 4.0 * std::ldexp(1.0, std::ilogb(lmax) - 23) * std::sqrt((double)DIM);
             P.rcut2f_pre = (float)((P.rcut + slack) * (P.rcut + slack) * (1.0 + 1e-5));
+            // neighbour cells farther than this from an A are skipped: the
+            // margin exceeds every rounding of a binary32 coordinate below
+            // the box edge by a factor of 16 or more
+            P.reach = P.rcut * (1.0 + 1e-6) + 64.0 * std::ldexp(1.0, std::ilogb(lmax) - 23);
         }
         P.inv_af = (float)P.inv_a;
         P.inv_tauf = (float)P.inv_tau;
@@ -274,6 +283,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             P.Lf[k] = (float)P.L[k];
             P.Lhf[k] = (float)P.Lh[k];
             P.cs[k] = m_ / P.L[k];
+            P.ce[k] = P.L[k] / m_;
             ncell *= (uint64_t)m_;
         }
         if (ncell > (1ull << 28)) return fail(SIM_EUNSUPPORTED, "too many cells");
@@ -281,8 +291,24 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         P.n_keys = 3u * P.n_cells;
         P.cap = (u32)n;
         P.cap_pl = (u32)std::min<uint64_t>(std::max<uint64_t>(1u << 20, 4 * n), 1u << 30);
+        // Pair search: LDS bricks pay off where every A tests many B's (each
+        // staged B serves many A's); with few B's per A the direct kernel
+        // (neighbour buckets through L2) has no staging to amortise.
+        {
+            const double bpc0 = (double)std::max<uint64_t>(nB + nC, 1) / (double)ncell;
+            double tests = bpc0;
+            for (int k = 0; k < DIM; ++k) tests *= P.nc[k] >= 3 ? std::min(3.0, 1.0 + 2.0 * P.reach / P.ce[k]) : 1.0;
+            pair_tests = tests;
+        }
+        // an A needs at most one neighbour cell per axis when every axis with
+        // three or more cells is at least twice the reach wide
+        narrow = true;
+        for (int k = 0; k < DIM; ++k)
+            if (P.nc[k] >= 3 && !(P.ce[k] >= 2.0 * P.reach)) narrow = false;
+        const bool can_tile = P.nc[0] >= 3 && P.nc[1] >= 3 && (DIM == 2 || P.nc[2] >= 3);
+        P.tiled = can_tile && (M.pair_search == SIM_PAIRS_BRICKS ||
+                               (M.pair_search == SIM_PAIRS_AUTO && pair_tests > PAIR_TESTS_TILED));
         // LDS bricks: about 256 cells (halo <= MAX_HALO), fewer when buckets are crowded
-        P.tiled = P.nc[0] >= 3 && P.nc[1] >= 3 && (DIM == 2 || P.nc[2] >= 3);
         if (P.tiled) {
             const double bpc = (double)std::max<uint64_t>(nB + nC, 1) / (double)ncell;
             const double lcap = 1024.0;
@@ -406,7 +432,8 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         }
         launch(SIM_K_PAIRS, [&] {
             if (P.tiled) k_pair_scan<DIM, T, PM><<<n_bricks, PBLOCK, 0, st>>>(P, out, start, plist, ctr);
-            else k_pair_scan_global<DIM, T, PM><<<grid_for(maxA, 4096), BLOCK, 0, st>>>(P, out, start, plist, ctr);
+            else if (narrow) k_pair_scan_direct_narrow<DIM, T, PM><<<grid_for(maxA, 8192), BLOCK, 0, st>>>(P, out, start, plist, ctr);
+            else k_pair_scan_direct<DIM, T, PM><<<grid_for(maxA, 8192), BLOCK, 0, st>>>(P, out, start, plist, ctr);
         });
         launch(SIM_K_EVAL, [&] { k_pair_eval<DIM, T, PM><<<g_pl, BLOCK, 0, st>>>(P, out, plist, cand, flag, headA, nextA, ctr, dbg_pairs); });
         launch(SIM_K_SELECT_A, [&] { k_select_a<<<g_pl, BLOCK, 0, st>>>(P, plist, cand, flag, headA, nextA, headB, nextB, ctr, dbg_picks); });
@@ -532,7 +559,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             return SIM_OK;
         }
         case SIM_READ_GRID: {
-            const int64_t g[4] = {P.nc[0], P.nc[1], P.nc[2], (int64_t)P.n_cells};
+            const int64_t g[5] = {P.nc[0], P.nc[1], P.nc[2], (int64_t)P.n_cells, P.tiled ? SIM_PAIRS_BRICKS : SIM_PAIRS_DIRECT};
             if (cap < sizeof(g)) return fail(SIM_EINVAL, "destination buffer too small");
             std::memcpy(dst, g, sizeof(g));
             if (written) *written = sizeof(g);
@@ -599,6 +626,7 @@ int validate(const sim_config *cfg, uint64_t n, const int32_t *sp, const double 
     const double eps = cfg->eps_cut == 0.0 ? 1e-3 : cfg->eps_cut;
     if (!(eps > 0.0 && eps < 1.0)) { g_err = "eps_cut must be in (0, 1)"; return SIM_EINVAL; }
     if (!finite_nonneg(cfg->rcut) || !finite_nonneg(cfg->cell)) { g_err = "rcut and cell must be >= 0"; return SIM_EINVAL; }
+    if (cfg->pair_search < SIM_PAIRS_AUTO || cfg->pair_search > SIM_PAIRS_DIRECT) { g_err = "unknown pair_search"; return SIM_EINVAL; }
     // state
     std::vector<int> owners(n, 0);
     for (uint64_t i = 0; i < n; ++i) {
@@ -628,6 +656,7 @@ int validate(const sim_config *cfg, uint64_t n, const int32_t *sp, const double 
     M.eps = eps;
     M.rcut_req = cfg->rcut;
     M.cell_req = cfg->cell;
+    M.pair_search = cfg->pair_search;
     M.seed = cfg->seed;
     M.replica = cfg->replica;
     M.n_terms = cfg->n_terms == 0 ? 12 : cfg->n_terms;

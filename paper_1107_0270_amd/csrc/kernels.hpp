@@ -357,53 +357,100 @@ template <int DIM, class T, int PM> __device__ __forceinline__ bool in_range(con
     }
 }
 
-// Visit every B record within r_cut of the A record ra: the B buckets of the
-// 3^d cells around ra's cell (rows along x are contiguous bucket ranges).
+// Which neighbour cells of ra's cell can hold a B within r_cut.  Cells are
+// at least r_cut wide, so along each axis only the cell itself and a
+// neighbour whose shared face lies within r_cut of ra qualify.  P.reach is
+// r_cut widened by far more than the rounding of the face positions, of the
+// binning and of the pair test, so a skipped cell holds no pair; the pair
+// test itself still decides every candidate.  An axis with fewer than three
+// cells has one cell.
+template <int DIM, class T>
+__device__ __forceinline__ void reach_of(const Params &P, const Rec<T> &ra, int c[3], int lo[3], int hi[3])
+{
+    const double x[3] = {(double)ra.x, (double)ra.y, (double)ra.z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        c[k] = 0;
+        lo[k] = hi[k] = 0;
+        if (k < DIM) {
+            c[k] = cell1(x[k], P.cs[k], P.nc[k]);
+            if (P.nc[k] >= 3) {
+                const double f = x[k] - c[k] * P.ce[k];
+                lo[k] = f < P.reach ? -1 : 0;
+                hi[k] = P.ce[k] - f < P.reach ? 1 : 0;
+            }
+        }
+    }
+}
+
+// The B bucket ranges that can hold a partner of the A record ra: rows of
+// cells along x are contiguous ranges, a row split in two where it wraps
+// around the box.  With cells at least twice the reach (NARROW) an A needs
+// at most one neighbour per axis, so 2 x 2 rows (2 in 2D); otherwise up to
+// 3 x 3.  All bounds are loaded before any is used.
+template <int DIM, bool NARROW> constexpr int n_slots() { return NARROW ? (DIM == 3 ? 4 : 2) : (DIM == 3 ? 9 : 3); }
+
+template <int DIM, bool NARROW, class T>
+__device__ __forceinline__ void collect_ranges(const Params &P, const u32 *__restrict__ start, const Rec<T> &ra, u32 *b0, u32 *e0,
+                                               u32 *b1, u32 *e1)
+{
+    int c[3], lo[3], hi[3];
+    reach_of<DIM, T>(P, ra, c, lo, hi);
+    const int nx = P.nc[0], ny = P.nc[1], nz = P.nc[2];
+    const u32 bbase = P.n_cells;  // B buckets follow the A buckets
+    const int xa = c[0] + lo[0], xb = c[0] + hi[0];
+    const int sy = lo[1] + hi[1], sz = lo[2] + hi[2];  // NARROW: the one neighbour side, or 0
+#pragma unroll
+    for (int s = 0; s < n_slots<DIM, NARROW>(); ++s) {
+        int oy, oz;
+        bool use;
+        if (NARROW) {
+            oy = (s & 1) ? sy : 0;
+            oz = (s & 2) ? sz : 0;
+            use = (!(s & 1) || sy != 0) && (!(s & 2) || sz != 0);
+        } else {
+            oy = s % 3 - 1;
+            oz = DIM == 3 ? s / 3 - 1 : 0;
+            use = oy >= lo[1] && oy <= hi[1] && oz >= lo[2] && oz <= hi[2];
+        }
+        b0[s] = e0[s] = b1[s] = e1[s] = 0;
+        if (!use) continue;
+        int y = c[1] + oy, z = c[2] + oz;
+        y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+        z = z < 0 ? z + nz : (z >= nz ? z - nz : z);
+        const u32 row = bbase + ((u32)z * ny + y) * nx;
+        // bucket indices first, then the loads (branch-free, so the bounds
+        // stay in registers)
+        const bool wl = xa < 0, wh = xb >= nx;
+        const u32 ka = row + (wl ? 0 : xa), kb = row + (wh ? nx : xb + 1);
+        const u32 kc = row + (wl ? nx - 1 : 0), kd = row + (wl ? nx : 1);
+        b0[s] = start[ka];
+        e0[s] = start[kb];
+        if (wl || wh) {
+            b1[s] = start[kc];
+            e1[s] = start[kd];
+        }
+    }
+}
+
+// Visit every B record within r_cut of the A record ra, one range after the
+// other (the per-lane form; the direct kernel balances the ranges over a wave).
 template <int DIM, class T, int PM, class F>
 __device__ inline void for_pairs(const Params &P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start, const Rec<T> &ra,
                                  F &&emit)
 {
-    const int cx = cell1((double)ra.x, P.cs[0], P.nc[0]);
-    const int cy = cell1((double)ra.y, P.cs[1], P.nc[1]);
-    const int cz = DIM == 3 ? cell1((double)ra.z, P.cs[2], P.nc[2]) : 0;
-    const int nx = P.nc[0], ny = P.nc[1], nz = P.nc[2];
-    const int zlo = (DIM == 3 && nz >= 3) ? -1 : 0, zhi = -zlo;
-    const int ylo = ny >= 3 ? -1 : 0, yhi = -ylo;
-    const u32 bbase = P.n_cells;  // B buckets follow the A buckets
-    for (int oz = zlo; oz <= zhi; ++oz) {
-        int z = cz + oz;
-        z = z < 0 ? z + nz : (z >= nz ? z - nz : z);
-        for (int oy = ylo; oy <= yhi; ++oy) {
-            int y = cy + oy;
-            y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
-            const u32 row = bbase + ((u32)z * ny + y) * nx;
-            // up to three contiguous ranges along x
-            u32 r0b, r0e, r1b = 0, r1e = 0;
-            if (nx < 3) {
-                r0b = start[row];
-                r0e = start[row + nx];
-            } else if (cx >= 1 && cx <= nx - 2) {
-                r0b = start[row + cx - 1];
-                r0e = start[row + cx + 2];
-            } else if (cx == 0) {
-                r0b = start[row];
-                r0e = start[row + 2];
-                r1b = start[row + nx - 1];
-                r1e = start[row + nx];
-            } else {
-                r0b = start[row + nx - 2];
-                r0e = start[row + nx];
-                r1b = start[row];
-                r1e = start[row + 1];
-            }
-            for (u32 j = r0b; j < r0e; ++j) {
-                const Rec<T> rb = rec[j];
-                if (in_range<DIM, T, PM>(P, ra, rb)) emit(j, rb);
-            }
-            for (u32 j = r1b; j < r1e; ++j) {
-                const Rec<T> rb = rec[j];
-                if (in_range<DIM, T, PM>(P, ra, rb)) emit(j, rb);
-            }
+    constexpr int NS = n_slots<DIM, false>();
+    u32 b0[NS], e0[NS], b1[NS], e1[NS];
+    collect_ranges<DIM, false, T>(P, start, ra, b0, e0, b1, e1);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        for (u32 j = b0[s]; j < e0[s]; ++j) {
+            const Rec<T> rb = rec[j];
+            if (in_range<DIM, T, PM>(P, ra, rb)) emit(j, rb);
+        }
+        for (u32 j = b1[s]; j < e1[s]; ++j) {
+            const Rec<T> rb = rec[j];
+            if (in_range<DIM, T, PM>(P, ra, rb)) emit(j, rb);
         }
     }
 }
@@ -464,6 +511,21 @@ __device__ __forceinline__ void append_pair(PairEnt *q, u32 *nq, PairEnt *list, 
     }
 }
 
+// Append a workgroup's queued pairs to the global list with one atomic.
+template <int NT>
+__device__ __forceinline__ void flush_pairs(const PairEnt *q, const u32 &nq, u32 &qbase, PairEnt *list, Counters *C, const Params &P)
+{
+    __syncthreads();
+    const u32 n = min(nq, (u32)QCAP);
+    if (threadIdx.x == 0) qbase = n ? atomicAdd(&C->n_pl, n) : 0u;
+    __syncthreads();
+    for (u32 i = threadIdx.x; i < n; i += NT) {
+        const u32 g = qbase + i;
+        if (g < P.cap_pl) list[g] = q[i];
+        else atomicOr(&C->err, (u32)ERR_PAIRS);
+    }
+}
+
 __device__ __forceinline__ int wrapc(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
 template <int DIM, class T, int PM>
@@ -475,6 +537,10 @@ __global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__
     // the B record index in the fourth lane, in halo-cell order
     __shared__ float4 sbr[LCAP];
     __shared__ u32 off[MAX_HALO + 1];
+    // source of each staged slot: B record index and periodic-shift code
+    // (two bits per axis: 1 = -L, 2 = +L)
+    __shared__ u32 srcj[LCAP];
+    __shared__ unsigned char srcc[LCAP];
     __shared__ u32 rowpre[MAX_ROWS + 1], rowst[MAX_ROWS];
     __shared__ PairEnt q[QCAP];
     __shared__ u32 nq, qbase;
@@ -495,14 +561,12 @@ __global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__
 
     // 1. this thread's halo cells h = CELLS_PER_T * t + c: bucket ranges (all
     //    loads issued together) and the periodic shift of each cell
-    u32 hs[CELLS_PER_T], he[CELLS_PER_T];
-    float sx[CELLS_PER_T], sy[CELLS_PER_T], sz[CELLS_PER_T];
+    u32 hs[CELLS_PER_T], he[CELLS_PER_T], code[CELLS_PER_T];
     u32 local = 0;
 #pragma unroll
     for (int c = 0; c < CELLS_PER_T; ++c) {
         const int h = CELLS_PER_T * threadIdx.x + c;
-        hs[c] = he[c] = 0;
-        sx[c] = sy[c] = sz[c] = 0.0f;
+        hs[c] = he[c] = code[c] = 0;
         if (h < nh) {
             const int r = h / hx;
             const int ux = x0 - 1 + (h - r * hx), uy = y0 - 1 + r % hy, uz = z0 - 1 + r / hy;
@@ -510,9 +574,8 @@ __global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__
             const u32 k = bbase + ((u32)gz * ny + gy) * nx + gx;
             hs[c] = start[k];
             he[c] = start[k + 1];
-            sx[c] = ux < 0 ? -(float)P.L[0] : (ux >= nx ? (float)P.L[0] : 0.0f);
-            sy[c] = uy < 0 ? -(float)P.L[1] : (uy >= ny ? (float)P.L[1] : 0.0f);
-            if (DIM == 3) sz[c] = uz < 0 ? -(float)P.L[2] : (uz >= nz ? (float)P.L[2] : 0.0f);
+            code[c] = (ux < 0 ? 1u : (ux >= nx ? 2u : 0u)) | (uy < 0 ? 4u : (uy >= ny ? 8u : 0u)) |
+                      (DIM == 3 ? (uz < 0 ? 16u : (uz >= nz ? 32u : 0u)) : 0u);
         }
     }
     const int nr = ey * ez;
@@ -546,22 +609,39 @@ __global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__
         nq = 0;
     }
 
-    // 2. stage each cell's B records (the thread that owns the cell copies it)
+    // 2. stage the B records: the owner of each cell writes the sources of
+    //    its slots, then every thread converts up to LCAP / PBLOCK records
+    //    (fixed trip count, so all loads are in flight together)
     const bool use_lds = total <= (u32)LCAP;
     if (use_lds) {
         pos -= local;  // start of this thread's first cell
 #pragma unroll
-        for (int c = 0; c < CELLS_PER_T; ++c) {
+        for (int c = 0; c < CELLS_PER_T; ++c)
             for (u32 j = hs[c]; j < he[c]; ++j, ++pos) {
-                const Rec<T> rb = rec[j];
-                const float px = (float)((double)rb.x - ox) + sx[c];
-                const float py = (float)((double)rb.y - oy) + sy[c];
-                const float pz = DIM == 3 ? (float)((double)rb.z - oz) + sz[c] : 0.0f;
-                sbr[pos] = make_float4(px, py, pz, __uint_as_float(j));
+                srcj[pos] = j;
+                srcc[pos] = (unsigned char)code[c];
             }
-        }
     } else if (threadIdx.x == 0) {
         atomicAdd((unsigned long long *)&C->stats[ST_LDS_FALLBACK], 1ull);
+    }
+    __syncthreads();
+    if (use_lds) {
+        const float Lx = (float)P.L[0], Ly = (float)P.L[1], Lz = (float)P.L[2];
+#pragma unroll
+        for (int u = 0; u < LCAP / PBLOCK; ++u) {
+            const u32 k = threadIdx.x + u * PBLOCK;
+            if (k < total) {
+                const u32 j = srcj[k], cd = srcc[k];
+                const Rec<T> rb = rec[j];
+                const float sx = (cd & 1u) ? -Lx : ((cd & 2u) ? Lx : 0.0f);
+                const float sy = (cd & 4u) ? -Ly : ((cd & 8u) ? Ly : 0.0f);
+                const float sz = (cd & 16u) ? -Lz : ((cd & 32u) ? Lz : 0.0f);
+                const float px = (float)((double)rb.x - ox) + sx;
+                const float py = (float)((double)rb.y - oy) + sy;
+                const float pz = DIM == 3 ? (float)((double)rb.z - oz) + sz : 0.0f;
+                sbr[k] = make_float4(px, py, pz, __uint_as_float(j));
+            }
+        }
     }
     __syncthreads();
 
@@ -580,17 +660,16 @@ __global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__
         const u32 ia = rowst[lo] + (i - rowpre[lo]);
         const Rec<T> ra = rec[ia];
         if (use_lds) {
-            const int lx = cell1((double)ra.x, P.cs[0], nx) - x0 + 1;
-            const int ly = cell1((double)ra.y, P.cs[1], ny) - y0 + 1;
-            const int lz = DIM == 3 ? cell1((double)ra.z, P.cs[2], nz) - z0 + 1 : 0;
+            int c[3], lo[3], hi[3];
+            reach_of<DIM, T>(P, ra, c, lo, hi);
+            const int lx = c[0] - x0 + 1, ly = c[1] - y0 + 1, lz = DIM == 3 ? c[2] - z0 + 1 : 0;
             const float ax = (float)((double)ra.x - ox), ay = (float)((double)ra.y - oy);
             const float az = DIM == 3 ? (float)((double)ra.z - oz) : 0.0f;
-            const int zlo = DIM == 3 ? -1 : 0, zhi = -zlo;
-            for (int dz = zlo; dz <= zhi; ++dz)
-                for (int dy = -1; dy <= 1; ++dy) {
-                    const int h0 = ((lz + dz) * hy + (ly + dy)) * hx + (lx - 1);
-                    const u32 je = off[h0 + 3];
-                    for (u32 j = off[h0]; j < je; ++j) {
+            for (int dz = lo[2]; dz <= hi[2]; ++dz)
+                for (int dy = lo[1]; dy <= hi[1]; ++dy) {
+                    const int h0 = ((lz + dz) * hy + (ly + dy)) * hx + lx;
+                    const u32 je = off[h0 + hi[0] + 1];
+                    for (u32 j = off[h0 + lo[0]]; j < je; ++j) {
                         const float4 v = sbr[j];
                         const float ddx = v.x - ax, ddy = v.y - ay, ddz = v.z - az;
                         if (ddx * ddx + ddy * ddy + ddz * ddz < rpre) {
@@ -603,35 +682,115 @@ __global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__
             for_pairs<DIM, T, PM>(P, rec, start, ra, [&](u32 jb, const Rec<T> &) { append_pair(q, &nq, list, C, P, ia, jb); });
         }
     }
-    __syncthreads();
-    const u32 n = min(nq, (u32)QCAP);
-    if (threadIdx.x == 0) qbase = n ? atomicAdd(&C->n_pl, n) : 0u;
-    __syncthreads();
-    for (u32 i = threadIdx.x; i < n; i += PBLOCK) {
-        const u32 g = qbase + i;
-        if (g < P.cap_pl) list[g] = q[i];
-        else atomicOr(&C->err, (u32)ERR_PAIRS);
-    }
+    flush_pairs<PBLOCK>(q, nq, qbase, list, C, P);
 }
 
-// K5a for grids with fewer than three cells along some axis: one thread per A
-// record, neighbour buckets read from global memory.
+// K5b: the same pairs with one A record per thread and the neighbour
+// buckets read through L2: no staging, so it wins where an A tests few B's;
+// also the path for grids with fewer than three cells along some axis.
+// The lanes of a wave write their (B record, owner lane) tests into one LDS
+// list and the wave then works through it 2 x 64 tests at a time (loads in
+// flight together), so a lane with many tests does not hold up the other 63.
+// A wave with more than TCAP tests tests per lane instead.
+constexpr int TCAP = 512;  // tests listed per wave
+
+template <int DIM, class T, int PM, bool NARROW>
+__device__ __forceinline__ void pair_scan_direct(const Params &P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start,
+                                                 PairEnt *__restrict__ list, Counters *C)
+{
+    constexpr int NS = n_slots<DIM, NARROW>();
+    constexpr int NW = BLOCK / 64;
+    constexpr int U = 2;
+    __shared__ PairEnt q[QCAP];
+    __shared__ u32 nq, qbase;
+    __shared__ u32 tj[NW][TCAP];
+    __shared__ unsigned char town[NW][TCAP];
+    __shared__ Rec<T> sa[BLOCK];
+    if (threadIdx.x == 0) nq = 0;
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    const u32 a_end = start[P.n_cells];  // A buckets are the keys below n_cells
+    for (u32 b = blockIdx.x * BLOCK; b < a_end; b += gridDim.x * BLOCK) {
+        const u32 ia = b + threadIdx.x;
+        const bool act = ia < a_end;
+        Rec<T> ra = rec[act ? ia : b];
+        u32 b0[NS], e0[NS], b1[NS], e1[NS];
+        u32 tot = 0;
+        if (act) {
+            collect_ranges<DIM, NARROW, T>(P, start, ra, b0, e0, b1, e1);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) tot += (e0[s] - b0[s]) + (e1[s] - b1[s]);
+        } else {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) b0[s] = e0[s] = b1[s] = e1[s] = 0;
+        }
+        const u32 tinc = wave_incl_scan(tot);
+        const u32 T_ = __shfl(tinc, 63, 64);
+        const bool fits = T_ <= (u32)TCAP;  // uniform over the wave
+        if (fits) {
+            u32 k = tinc - tot;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                for (u32 j = b0[s]; j < e0[s]; ++j, ++k) {
+                    tj[w][k] = j;
+                    town[w][k] = (unsigned char)lane;
+                }
+                for (u32 j = b1[s]; j < e1[s]; ++j, ++k) {
+                    tj[w][k] = j;
+                    town[w][k] = (unsigned char)lane;
+                }
+            }
+            sa[threadIdx.x] = ra;
+        }
+        __syncthreads();
+        if (fits) {
+            for (u32 t0 = 0; t0 < T_; t0 += U * 64) {
+                u32 jb[U];
+                int own[U];
+                Rec<T> rb[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const u32 t = t0 + u * 64 + lane;
+                    jb[u] = t < T_ ? tj[w][t] : NOSLOT;
+                    own[u] = t < T_ ? town[w][t] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (jb[u] != NOSLOT) rb[u] = rec[jb[u]];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (jb[u] == NOSLOT) continue;
+                    const Rec<T> ro = sa[w * 64 + own[u]];
+                    if (in_range<DIM, T, PM>(P, ro, rb[u])) append_pair(q, &nq, list, C, P, b + w * 64 + own[u], jb[u]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                for (u32 j = b0[s]; j < e0[s]; ++j)
+                    if (in_range<DIM, T, PM>(P, ra, rec[j])) append_pair(q, &nq, list, C, P, ia, j);
+                for (u32 j = b1[s]; j < e1[s]; ++j)
+                    if (in_range<DIM, T, PM>(P, ra, rec[j])) append_pair(q, &nq, list, C, P, ia, j);
+            }
+        }
+        __syncthreads();  // the next batch reuses the LDS tables
+    }
+    flush_pairs<BLOCK>(q, nq, qbase, list, C, P);
+}
+
+// The narrow form fits 64 VGPRs: eight waves per SIMD hold all A's of a
+// typical step at once.
 template <int DIM, class T, int PM>
-__global__ __launch_bounds__(BLOCK) void k_pair_scan_global(Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void k_pair_scan_direct_narrow(
+    Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start, PairEnt *__restrict__ list, Counters *C)
+{
+    pair_scan_direct<DIM, T, PM, true>(P, rec, start, list, C);
+}
+
+template <int DIM, class T, int PM>
+__global__ __launch_bounds__(BLOCK) void k_pair_scan_direct(Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start,
                                                              PairEnt *__restrict__ list, Counters *C)
 {
-    const u32 a_beg = start[0], a_end = start[P.n_cells];
-    for (u32 ia = a_beg + gtid(); ia < a_end; ia += gstride()) {
-        const Rec<T> ra = rec[ia];
-        for_pairs<DIM, T, PM>(P, rec, start, ra, [&](u32 jb, const Rec<T> &) {
-            const u32 g = atomicAdd(&C->n_pl, 1u);
-            PairEnt e;
-            e.a_idx = ia;
-            e.b_idx = jb;
-            if (g < P.cap_pl) list[g] = e;
-            else atomicOr(&C->err, (u32)ERR_PAIRS);
-        });
-    }
+    pair_scan_direct<DIM, T, PM, false>(P, rec, start, list, C);
 }
 
 // ---------------------------------------------------------------------------

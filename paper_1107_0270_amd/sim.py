@@ -18,6 +18,7 @@ SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_ESTATE, SIM_EUNSUPPORTED, SIM_E
 SP_A, SP_B, SP_C, SP_FREE, SP_RESERVED = 0, 1, 2, 3, 4
 BC_ABSORBING, BC_REFLECTING, BC_RADIATION = 0, 1, 2
 PREC_FP64, PREC_FP32, PREC_FP32_FP64NC = 0, 1, 2
+PAIRS_AUTO, PAIRS_BRICKS, PAIRS_DIRECT = 0, 1, 2
 (READ_POS, READ_SPECIES, READ_PARTNER, READ_COUNTS, READ_STATS, READ_STATS_SUM, READ_DERIVED, READ_DBG_MOVED,
  READ_DBG_PAIRS, READ_DBG_PICKS, READ_DBG_MATCHES, READ_DBG_DISS, READ_DBG_CELLS, READ_TIMING, READ_GRID) = range(15)
 STAT_NAMES = ["pairs", "cand", "overlap", "r0clamp", "picks", "matches", "react", "decay", "geminate",
@@ -45,7 +46,7 @@ class SimReaction(C.Structure):
 class SimConfig(C.Structure):
     _fields_ = [("dim", C.c_int32), ("precision", C.c_int32), ("box", C.c_double * 3), ("dt", C.c_double),
                 ("seed", C.c_uint64), ("replica", C.c_uint32), ("n_terms", C.c_int32), ("eps_cut", C.c_double),
-                ("rcut", C.c_double), ("cell", C.c_double), ("n_species", C.c_int32),
+                ("rcut", C.c_double), ("cell", C.c_double), ("pair_search", C.c_int32), ("n_species", C.c_int32),
                 ("species", C.POINTER(SimSpecies)), ("n_reactions", C.c_int32),
                 ("reactions", C.POINTER(SimReaction)), ("debug", C.c_uint32), ("timing", C.c_uint32),
                 ("debug_cap", C.c_uint64), ("hip_stream", C.c_void_p)]
@@ -91,7 +92,7 @@ class Sim:
 
     def __init__(self, *, dim, box, dt, D, sigma, bc, species, pos, kappa=0.0, k_off=0.0,
                  precision=PREC_FP32_FP64NC, seed=0, replica=0, n_terms=12, eps_cut=1e-3, rcut=0.0, cell=0.0,
-                 partner=None, debug=False, timing=False, debug_cap=0, stream=None):
+                 pair_search=PAIRS_AUTO, partner=None, debug=False, timing=False, debug_cap=0, stream=None):
         L = lib()
         cfg = SimConfig()
         cfg.dim, cfg.precision = int(dim), int(precision)
@@ -101,6 +102,7 @@ class Sim:
             cfg.box[k] = float(bx[k])
         cfg.dt, cfg.seed, cfg.replica, cfg.n_terms = float(dt), int(seed), int(replica), int(n_terms)
         cfg.eps_cut, cfg.rcut, cfg.cell = float(eps_cut), float(rcut), float(cell)
+        cfg.pair_search = int(pair_search)
         Dl = list(D)
         if len(Dl) == 2:
             Dl.append(Dl[0] * Dl[1] / (Dl[0] + Dl[1]))
@@ -197,7 +199,8 @@ class Sim:
         return dict(zip(["Deff", "tau", "hh", "rcut", "a", "p_uni", "cell", "step"], out.tolist()))
 
     def grid(self):
-        out = np.zeros(4, np.int64)
+        """Cells per edge x, y, z, total cells, pair-search kernel (PAIRS_BRICKS or PAIRS_DIRECT)."""
+        out = np.zeros(5, np.int64)
         self._read(READ_GRID, out)
         return out.tolist()
 

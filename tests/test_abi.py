@@ -44,8 +44,9 @@ def test_struct_layouts_match_the_header(tmp_path):
 #include <stdio.h>
 #include "gfbd.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(sim_config), offsetof(sim_config, species),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(sim_config), offsetof(sim_config, species),
          offsetof(sim_config, reactions), offsetof(sim_config, debug_cap), offsetof(sim_config, hip_stream),
+         offsetof(sim_config, pair_search),
          sizeof(sim_reaction), sizeof(sim_dbg_pair), sizeof(sim_dbg_diss));
   printf("%zu %zu %zu\n", sizeof(sim_dbg_pick), sizeof(sim_dbg_match), sizeof(sim_kernel_time));
   return 0; }
@@ -55,7 +56,8 @@ int main(void) {
     a, b = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")[:2]
     got = [int(x) for x in a.split()]
     assert got == [C.sizeof(S.SimConfig), S.SimConfig.species.offset, S.SimConfig.reactions.offset,
-                   S.SimConfig.debug_cap.offset, S.SimConfig.hip_stream.offset, C.sizeof(S.SimReaction),
+                   S.SimConfig.debug_cap.offset, S.SimConfig.hip_stream.offset, S.SimConfig.pair_search.offset,
+                   C.sizeof(S.SimReaction),
                    S.PAIR_DT.itemsize, S.DISS_DT.itemsize]
     assert [int(x) for x in b.split()] == [S.PICK_DT.itemsize, S.MATCH_DT.itemsize, 16]
 
@@ -81,6 +83,8 @@ def _args(**over):
     (dict(precision=S.PREC_FP32, box=0.1), S.SIM_EINVAL),        # 0.1 is not a binary32 value
     (dict(n_terms=40), S.SIM_EINVAL),
     (dict(eps_cut=1.5), S.SIM_EINVAL),
+    (dict(pair_search=3), S.SIM_EINVAL),
+    (dict(pair_search=-1), S.SIM_EINVAL),
     # C without a reserved partner in a reversible system
     (dict(species=np.array([2, 1], np.int32), k_off=1.0), S.SIM_EINVAL),
 ])

@@ -50,21 +50,26 @@ def test_abs3d_fp64_trajectory():
     assert gpu.derived()["rcut"] == pytest.approx(orc.derived()["rcut"], rel=1e-12)
 
 
+KERNELS = [S.PAIRS_BRICKS, S.PAIRS_DIRECT]
+
+
+@pytest.mark.parametrize("pair_search", KERNELS)
 @pytest.mark.parametrize("prec,p_tol", [(S.PREC_FP32_FP64NC, 1e-6), (S.PREC_FP32, 1e-4)])
-def test_rad3d_reversible_binary32(prec, p_tol):
+def test_rad3d_reversible_binary32(prec, p_tol, pair_search):
     # radiation workload at its density (500 A + 500 B per um^3) in a 2.5 um box;
     # k_off raised so dissociation and geminate recombination occur within the run
     n = 7812
     sp, pos = _state(n, n, 2.5, 3, 0.005, 1, True)
     gpu, orc = make_pair(dim=3, bc=O.BC_RAD, box=2.5, dt=1e-5, D=(1.0, 1.0, 0.5), sigma=0.005, kappa=0.1,
-                         k_off=2000.0, precision=prec, species=sp, pos=pos, seed=3)
+                         k_off=2000.0, precision=prec, species=sp, pos=pos, seed=3, pair_search=pair_search)
     rep = run(gpu, orc, 30, p_tol=p_tol, pos_tol=0.0, box=2.5)
     _check(rep, p_tol=p_tol)
     assert rep.reactions > 20 and rep.decays > 0
 
 
+@pytest.mark.parametrize("pair_search", KERNELS)
 @pytest.mark.parametrize("cell", [0.0, 0.075])
-def test_rad3d_dense(cell):
+def test_rad3d_dense(cell, pair_search):
     # a dense, fast system: A's with up to ~16 candidates, chains of several
     # picks per B.  cell = 0.075 um puts ~160 B in every bucket, so the halo of
     # even a one-cell brick overflows LDS and the search reads global memory.
@@ -73,11 +78,11 @@ def test_rad3d_dense(cell):
     sp, pos = _state(n, n, 0.375, 3, 0.004, 2, True)
     gpu, orc = make_pair(dim=3, bc=O.BC_RAD, box=0.375, dt=2e-5, D=(5.0, 5.0, 2.5), sigma=0.004, kappa=1.0,
                          k_off=500.0, precision=S.PREC_FP32_FP64NC, species=sp, pos=pos, seed=4, eps_cut=0.05,
-                         cell=cell)
+                         cell=cell, pair_search=pair_search)
     rep = run(gpu, orc, 5, p_tol=1e-6, pos_tol=0.0, box=0.375)
     _check(rep, p_tol=1e-6, allow_near=3)
     tot = gpu.stats(total=True)
-    if cell > 0:
+    if cell > 0 and pair_search == S.PAIRS_BRICKS:
         assert tot["lds_fallback"] > 0
 
 
@@ -94,13 +99,14 @@ def test_reflecting_and_small_box_single_cell():
     assert rep.matches > 0 and rep.reactions == 0
 
 
+@pytest.mark.parametrize("pair_search", KERNELS)
 @pytest.mark.parametrize("prec,p_tol", [(S.PREC_FP64, 1e-12), (S.PREC_FP32_FP64NC, 1e-9)])
-def test_mem2d_small_tau(prec, p_tol):
+def test_mem2d_small_tau(prec, p_tol, pair_search):
     # 2D membrane workload at tau = 0.04 (dt = 5 us), its density (1,250 A and B per um^2)
     n = 7812
     sp, pos = _state(n, n, 2.5, 2, 0.005, 7, prec != S.PREC_FP64)
     gpu, orc = make_pair(dim=2, bc=O.BC_RAD, box=2.5, dt=5e-6, D=(0.1, 0.1, 0.05), sigma=0.005, kappa=0.05,
-                         k_off=2000.0, precision=prec, species=sp, pos=pos, seed=8)
+                         k_off=2000.0, precision=prec, species=sp, pos=pos, seed=8, pair_search=pair_search)
     rep = run(gpu, orc, 20, p_tol=p_tol, pos_tol=0.0 if prec != S.PREC_FP64 else 1e-12, box=2.5)
     _check(rep, p_tol=p_tol)
     assert rep.reactions > 0
@@ -116,12 +122,16 @@ def test_mem2d_as_written_tau_0p8():
     _check(rep, p_tol=1e-9)
 
 
-def test_rad3d_full_size_one_step():
-    # the benchmark workload at full size (1e6 particles, L = 10 um), one step
+@pytest.mark.parametrize("pair_search", [S.PAIRS_AUTO, S.PAIRS_BRICKS])
+def test_rad3d_full_size_one_step(pair_search):
+    # the benchmark workload at full size (1e6 particles, L = 10 um), in the
+    # launch configuration the benchmark times (automatic kernel choice) and
+    # with the other pair-search kernel
     cfg = I.workload("cfg_rad3d")
     sp, pos = _state(cfg["n_a"], cfg["n_b"], cfg["box"], 3, cfg["sigma"], 0, True)
     gpu, orc = make_pair(dim=3, bc=cfg["bc"], box=cfg["box"], dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"],
-                         kappa=cfg["kappa_a"], k_off=cfg["k_off"], precision=cfg["precision"], species=sp, pos=pos)
+                         kappa=cfg["kappa_a"], k_off=cfg["k_off"], precision=cfg["precision"], species=sp, pos=pos,
+                         pair_search=pair_search)
     rep = run(gpu, orc, 2, p_tol=1e-6, pos_tol=0.0, box=cfg["box"])
     _check(rep, p_tol=1e-6)
     assert rep.pairs > 10000
@@ -136,7 +146,7 @@ def test_cell_lists_are_consistent():
     sp0 = gpu.species()
     gpu.step()
     keys, moved = gpu.dbg_cells(), gpu.dbg_moved()
-    nx, ny, nz, ncell = gpu.grid()
+    nx, ny, nz, ncell, _ = gpu.grid()
     live = sp0 <= S.SP_C
     c = [np.clip(np.floor(moved[live, k] * (m / 1.0)).astype(np.int64), 0, m - 1) for k, m in enumerate((nx, ny, nz))]
     expect = sp0[live].astype(np.int64) * ncell + (c[2] * ny + c[1]) * nx + c[0]
