@@ -160,7 +160,7 @@ typedef struct { uint32_t c, j; int32_t decayed, recombined; uint32_t attempts, 
 /* Kernels timed with sim_config.timing: move + bucket count, bucket scan,
  * scatter into sorted order, pair search, p_enc + draw per pair, A-side
  * choice, B-side choice + decay draws, matched pairs and decays (one wave
- * each: propagation, reaction, dissociation; the last block closes the step). */
+ * each: propagation, reaction, dissociation) and the one-workgroup step close. */
 enum {
     SIM_K_MOVE = 0, SIM_K_SCAN, SIM_K_SCATTER, SIM_K_PAIRS, SIM_K_EVAL, SIM_K_SELECT_A, SIM_K_SELECT_B,
     SIM_K_EVENTS, SIM_K_N

@@ -41,13 +41,13 @@ __device__ __forceinline__ uint4 philox(u32 c0, u32 c1, u32 c2, u32 c3, Key k)
     u32 k0 = k.k0, k1 = k.k1;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const u32 hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-        const u32 hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-        const u32 n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        // one 32 x 32 -> 64-bit product gives both halves
+        const u64 p0 = (u64)0xD2511F53u * c0, p1 = (u64)0xCD9E8D57u * c2;
+        const u32 n0 = (u32)(p1 >> 32) ^ c1 ^ k0, n2 = (u32)(p0 >> 32) ^ c3 ^ k1;
         c0 = n0;
-        c1 = lo1;
+        c1 = (u32)p1;
         c2 = n2;
-        c3 = lo0;
+        c3 = (u32)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -141,8 +141,7 @@ struct Counters {
     u32 err;
     u32 n_dbg[4];   // pairs, picks, matches, dissociations logged this step
     u32 n_ev;       // events (matched pairs and decays) queued this step
-    u32 blocks_done;// blocks of the last kernel of the step that are done
-    u32 pad[4];
+    u32 pad[5];
     u64 stats[ST_N];
     u64 stats_last[ST_N];
     u64 stats_sum[ST_N];
@@ -153,10 +152,12 @@ struct PairEnt {
     u32 a_idx, b_idx;
 };
 
-// A candidate (p_enc accepted): its slots and p_enc.
+// A candidate (p_enc accepted): its slots, p_enc and the binary64 initial
+// separation R0 (clamped to >= 1) that its propagation starts from.
 struct CandEnt {
     u32 a_slot, b_slot;
     double p;
+    double R0;
 };
 
 // pair-list entry state

@@ -131,6 +131,8 @@ namespace {
         if (e_ != hipSuccess) return fail(SIM_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
     } while (0)
 
+// workgroups of the event kernel: one wave per event for up to 4 * EV_BLOCKS events
+constexpr unsigned EV_BLOCKS = 1024;
 // expected B's tested per A above which the LDS brick search is chosen
 constexpr double PAIR_TESTS_TILED = 8.0;
 
@@ -162,6 +164,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     u32 *flag = nullptr, *nextA = nullptr, *nextB = nullptr, *ev = nullptr;
     u64 *headA = nullptr, *headB = nullptr;
     Counters *ctr = nullptr;
+    Params *dparams = nullptr;  // device copy of P for kernels that call out-of-line functions
     hipStream_t own_stream = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     uint32_t n_bricks = 0;
@@ -353,6 +356,8 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         h_g2_constants(P.hh, g2h);
         HIPCHECK(hipMemcpyAsync(g2c, g2h, sizeof(g2h), hipMemcpyHostToDevice, M.stream));
         P.g2c = g2c;
+        if ((rc = alloc(dparams, 1))) return rc;
+        HIPCHECK(hipMemcpyAsync(dparams, &P, sizeof(P), hipMemcpyHostToDevice, M.stream));  // P is final here
         return load(0, sp, pos, pt);
     }
 
@@ -408,6 +413,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         ev_used.push_back(e);
     }
 
+    static u32 round8(u32 g) { return (g + 7u) & ~7u; }
     static u32 grid_for(uint64_t work, u32 maxg) { return (u32)std::max<uint64_t>(1, std::min<uint64_t>((work + BLOCK - 1) / BLOCK, maxg)); }
 
     // Launches one step reading record buffer c and writing buffer c ^ 1.
@@ -431,9 +437,12 @@ template <int DIM, class T, int PM> struct Engine final : sim {
                                                  dbg_cells);
         }
         launch(SIM_K_PAIRS, [&] {
-            if (P.tiled) k_pair_scan<DIM, T, PM><<<n_bricks, PBLOCK, 0, st>>>(P, out, start, plist, ctr);
-            else if (narrow) k_pair_scan_direct_narrow<DIM, T, PM><<<grid_for(maxA, 8192), BLOCK, 0, st>>>(P, out, start, plist, ctr);
-            else k_pair_scan_direct<DIM, T, PM><<<grid_for(maxA, 8192), BLOCK, 0, st>>>(P, out, start, plist, ctr);
+            // grids in multiples of the eight XCDs; the direct search takes no
+            // more workgroups than are resident at once (2048)
+            const u32 g_pairs = round8(grid_for(maxA, 2048));
+            if (P.tiled) k_pair_scan<DIM, T, PM><<<round8(n_bricks), PBLOCK, 0, st>>>(P, out, start, plist, ctr);
+            else if (narrow) k_pair_scan_direct_narrow<DIM, T, PM><<<g_pairs, BLOCK, 0, st>>>(P, out, start, plist, ctr);
+            else k_pair_scan_direct<DIM, T, PM><<<g_pairs, BLOCK, 0, st>>>(P, out, start, plist, ctr);
         });
         launch(SIM_K_EVAL, [&] { k_pair_eval<DIM, T, PM><<<g_pl, BLOCK, 0, st>>>(P, out, plist, cand, flag, headA, nextA, ctr, dbg_pairs); });
         launch(SIM_K_SELECT_A, [&] { k_select_a<<<g_pl, BLOCK, 0, st>>>(P, plist, cand, flag, headA, nextA, headB, nextB, ctr, dbg_picks); });
@@ -441,7 +450,10 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         launch(SIM_K_SELECT_B, [&] {
             k_select_b<T><<<nb_sel + nb_dec, BLOCK, 0, st>>>(P, plist, cand, flag, headB, nextB, out, start, ev, ctr, nb_sel);
         });
-        launch(SIM_K_EVENTS, [&] { k_events<DIM, T><<<256, BLOCK, 0, st>>>(P, out, plist, ev, partner, ctr, dbg_matches, dbg_diss); });
+        launch(SIM_K_EVENTS, [&] {
+            k_events<DIM, T><<<EV_BLOCKS, BLOCK, 0, st>>>(dparams, out, plist, cand, ev, partner, ctr, dbg_matches, dbg_diss);
+            k_close<<<1, 64, 0, st>>>(ctr);
+        });
     }
 
     int one_step()

@@ -171,23 +171,26 @@ __device__ inline double reac_prob(const Params &P, int dim, double R, double R0
 // Radial propagator sampler.
 // ---------------------------------------------------------------------------
 
-// The y >= yc with erfc(y) = u erfc(yc).  Start from erfcinv of the target
-// (or, when the target underflows, from the leading large-y form
-// erfc(y) ~ e^{-y^2}/(y sqrt(pi))), then Newton steps on
+// The y >= yc with erfc(y) = u erfc(yc).  Start from the binary32 erfcinv
+// of the target (about 1e-7 relative; where the target is below the binary32
+// range, from the leading large-y form erfc(y) ~ e^{-y^2}/(y sqrt(pi)), within
+// 1% there), then binary64 Newton steps on
 // f(y) = ln erfcx(y) - y^2 - ln(u erfc(yc)), f'(y) = -2/(sqrt(pi) erfcx(y)),
-// which converge quadratically from there.
-__device__ inline double erfc_tail_inv(double yc, double u)
+// which converge quadratically: two or three reach the root to rounding.
+// Called, not inlined: its registers would otherwise add to its callers'.
+__device__ __forceinline__ double erfc_tail_inv(double yc, double u)
 {
     const double lt = log(u) + log(erfcx(yc)) - yc * yc;  // ln of the target
     double y;
-    if (lt > -700.0) {
-        y = erfcinv(exp(lt));
+    if (lt > -80.0) {
+        y = (double)erfcinvf(expf((float)lt));
     } else {
         const double s = sqrt(-lt);
         y = sqrt(fmax(-lt - log(s * SQRTPI_D), 0.0));
     }
     if (!(y >= yc)) y = yc;
-    for (int it = 0; it < 6; ++it) {
+#pragma nounroll
+    for (int it = 0; it < 8; ++it) {
         const double ex = erfcx(y);
         const double dy = (log(ex) - y * y - lt) * ex * (0.5 * SQRTPI_D);
         double yn = y + dy;

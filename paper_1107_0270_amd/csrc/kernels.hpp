@@ -19,6 +19,13 @@ __device__ __forceinline__ u32 gtid() { return blockIdx.x * BLOCK + threadIdx.x;
 __device__ __forceinline__ u32 gstride() { return gridDim.x * BLOCK; }
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// The dispatcher deals workgroups to the eight XCDs round-robin (workgroup b
+// runs on XCD b % 8), and each XCD has its own L2.  Work items that share
+// bucket data (neighbouring cells) are given to one XCD as a contiguous
+// range: item = (b % 8) * per + b / 8 for a grid of 8 * per workgroups.
+constexpr u32 N_XCD = 8;
+__device__ __forceinline__ u32 xcd_item(u32 b, u32 per) { return (b % N_XCD) * per + b / N_XCD; }
+
 // ---------------------------------------------------------------------------
 // State updates: binary64 arithmetic, one rounding into the state precision,
 // no FMA contraction (so each rounding is the one written).
@@ -39,19 +46,33 @@ template <class T> __device__ inline T wrap_store(double y, double L)
 
 // Free displacement sqrt(2 D dt) N(0,1) of a slot (Sec. 3, step 1):
 // Box-Muller on one Philox draw {slot, -, step, MOVE}.
-template <int DIM> __device__ inline void displacement(const Params &P, u32 slot, u32 sp, u32 step, double d[3])
+// Angles 2 pi u: a binary64 state rounds the update at the level of the
+// angle's own rounding, so the angle is formed as the product 2 pi * u; for a
+// binary32 state those bits lie far below the state's resolution and
+// sincospi(2u), which needs no argument reduction, is used.
+template <class T> __device__ __forceinline__ void sincos_turn(double u, double *s, double *c)
+{
+    if (sizeof(T) == 8) sincos((2.0 * PI_D) * u, s, c);
+    else sincospi(2.0 * u, s, c);
+}
+template <class T> __device__ __forceinline__ double cos_turn(double u)
+{
+    return sizeof(T) == 8 ? cos((2.0 * PI_D) * u) : cospi(2.0 * u);
+}
+
+template <int DIM, class T> __device__ inline void displacement(const Params &P, u32 slot, u32 sp, u32 step, double d[3])
 {
 #pragma clang fp contract(off)
     const uint4 r = philox(slot, NOSLOT, step, TAG_MOVE, P.key);
     const double s = P.sd[sp];
-    const double r0 = sqrt(-2.0 * log(u01(r.x))), t0 = (2.0 * PI_D) * u01(r.y);
+    const double r0 = sqrt(-2.0 * log(u01(r.x)));
     double s0, c0;
-    sincos(t0, &s0, &c0);
+    sincos_turn<T>(u01(r.y), &s0, &c0);
     d[0] = s * (r0 * c0);
     d[1] = s * (r0 * s0);
     if (DIM == 3) {
-        const double r1 = sqrt(-2.0 * log(u01(r.z))), t1 = (2.0 * PI_D) * u01(r.w);
-        d[2] = s * (r1 * cos(t1));
+        const double r1 = sqrt(-2.0 * log(u01(r.z)));
+        d[2] = s * (r1 * cos_turn<T>(u01(r.w)));
     } else {
         d[2] = 0.0;
     }
@@ -61,7 +82,7 @@ template <int DIM, class T> __device__ inline Rec<T> moved(const Params &P, cons
 {
 #pragma clang fp contract(off)
     double d[3];
-    displacement<DIM>(P, meta_slot(meta), meta_sp(meta), step, d);
+    displacement<DIM, T>(P, meta_slot(meta), meta_sp(meta), step, d);
     Rec<T> q;
     q.x = wrap_store<T>((double)r.x + d[0], P.L[0]);
     q.y = wrap_store<T>((double)r.y + d[1], P.L[1]);
@@ -242,6 +263,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Params P, const Rec<T> *__res
 // ---------------------------------------------------------------------------
 struct PairQ {
     double R, R0, p;
+    double R0d;  // R0 in binary64 (equal to R0 unless the pair arithmetic is binary32)
     u32 draw;
     bool cand, overlap, clamped, near;
 };
@@ -273,7 +295,7 @@ __device__ inline PairQ pair_quantities(const Params &P, const Rec<T> &ra, const
 #pragma clang fp contract(off)
     PairQ q;
     double dB[3];
-    displacement<DIM>(P, sb, SP_B, step, dB);
+    displacement<DIM, T>(P, sb, SP_B, step, dB);
     if (PM == PM_F32) {
         const float rx = min_image_f((float)rb.x, (float)ra.x, P.Lf[0], P.Lhf[0]);
         const float ry = min_image_f((float)rb.y, (float)ra.y, P.Lf[1], P.Lhf[1]);
@@ -286,6 +308,19 @@ __device__ inline PairQ pair_quantities(const Params &P, const Rec<T> &ra, const
         if (q.clamped) R0f = 1.0f;
         q.R = Rf;
         q.R0 = R0f;
+        {
+            // the binary64 R0 that the propagation of a matched pair uses
+            const double xa[3] = {(double)ra.x, (double)ra.y, (double)ra.z};
+            const double xb[3] = {(double)rb.x, (double)rb.y, (double)rb.z};
+            double r02 = 0.0;
+            for (int k = 0; k < DIM; ++k) {
+                const double o = min_image_d(xb[k] - xa[k], P.L[k], P.Lh[k]) - (dB[k] - dA[k]);
+                r02 += o * o;
+            }
+            double R0 = sqrt(r02) / P.a;
+            if (R0 < 1.0) R0 = 1.0;
+            q.R0d = R0;
+        }
         q.overlap = Rf <= 1.0f;
         if (q.overlap) q.p = 1.0;
         else if (DIM == 3) q.p = penc3_args((Rf - 1.0f) * (R0f - 1.0f) * P.inv_tauf, (Rf + R0f - 1.0f) * P.inv_tauf, Rf * R0f * P.inv_tauf);
@@ -307,6 +342,7 @@ __device__ inline PairQ pair_quantities(const Params &P, const Rec<T> &ra, const
         if (q.clamped) R0 = 1.0;
         q.R = R;
         q.R0 = R0;
+        q.R0d = R0;
         q.overlap = R <= 1.0;
         if (q.overlap) {
             q.p = 1.0;
@@ -547,7 +583,9 @@ __global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__
     __shared__ u32 lds[PBLOCK / 64];
 
     const int nx = P.nc[0], ny = P.nc[1], nz = P.nc[2];
-    u32 b = blockIdx.x;
+    const u32 per = gridDim.x / N_XCD;
+    u32 b = xcd_item(blockIdx.x, per);
+    if (b >= P.nbx * P.nby * P.nbz) return;  // padding of the grid to a multiple of 8 (uniform)
     const int x0 = (int)(b % P.nbx) * P.bx;
     b /= P.nbx;
     const int y0 = (int)(b % P.nby) * P.by;
@@ -709,7 +747,12 @@ __device__ __forceinline__ void pair_scan_direct(const Params &P, const Rec<T> *
     if (threadIdx.x == 0) nq = 0;
     const int w = threadIdx.x >> 6, lane = lane_id();
     const u32 a_end = start[P.n_cells];  // A buckets are the keys below n_cells
-    for (u32 b = blockIdx.x * BLOCK; b < a_end; b += gridDim.x * BLOCK) {
+    // batches of BLOCK A records; XCD x takes the contiguous range
+    // [x * per, (x + 1) * per), its workgroups striding through it
+    const u32 nbatch = (a_end + BLOCK - 1) / BLOCK, per = (nbatch + N_XCD - 1) / N_XCD;
+    const u32 x = blockIdx.x % N_XCD, g8 = gridDim.x / N_XCD;
+    for (u32 k = blockIdx.x / N_XCD; k < per && x * per + k < nbatch; k += g8) {
+        const u32 b = (x * per + k) * BLOCK;
         const u32 ia = b + threadIdx.x;
         const bool act = ia < a_end;
         Rec<T> ra = rec[act ? ia : b];
@@ -819,7 +862,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair_eval(Params P, const Rec<T> *__r
         const Rec<T> ra = rec[e.a_idx], rb = rec[e.b_idx];
         const u32 sa = meta_slot(rec_meta(ra)), sb = meta_slot(rec_meta(rb));
         double dA[3];
-        displacement<DIM>(P, sa, SP_A, step, dA);
+        displacement<DIM, T>(P, sa, SP_A, step, dA);
         const PairQ q = pair_quantities<DIM, T, PM>(P, ra, rb, sa, sb, dA, step);
         st[0] += 1;
         st[1] += q.cand;
@@ -840,6 +883,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair_eval(Params P, const Rec<T> *__r
             c.a_slot = sa;
             c.b_slot = sb;
             c.p = q.p;
+            c.R0 = q.R0d;
             cand[k] = c;
             nextA[k] = chain_push(headA, e.a_idx, k, step);
         }
@@ -988,24 +1032,25 @@ __global__ __launch_bounds__(BLOCK) void k_select_b(Params P, const PairEnt *__r
     if (n_match) atomicAdd((unsigned long long *)&C->stats[ST_MATCHES], (unsigned long long)n_match);
 }
 
-// K9: close the step (counters are read with device-scope atomics, since the
-// other blocks of the closing kernel wrote them the same way).
-__device__ inline u32 ld_u32(u32 *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-__device__ inline u64 ld_u64(u64 *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-
-__device__ inline void finish_step(Counters *C)
+// K9: close the step (one workgroup, after the events): thread s < ST_N
+// moves counter s into the per-step and running sums; thread 0 then sets up
+// the next step.  A kernel of its own rather than a last-block test in the
+// event kernel: that test costs one same-address atomic per workgroup.
+__global__ void k_close(Counters *C)
 {
-    C->stats[ST_PAIRS] = min(ld_u32(&C->n_pl), 0xFFFFFFFFu);
-    for (int s = 0; s < ST_N; ++s) {
-        const u64 v = ld_u64(&C->stats[s]);
+    const int s = threadIdx.x;
+    if (s < ST_N) {
+        const u64 v = s == ST_PAIRS ? (u64)C->n_pl : C->stats[s];
         C->stats_last[s] = v;
         C->stats_sum[s] += v;
         C->stats[s] = 0;
     }
-    C->n_rec = ld_u32(&C->n_live) + ld_u32(&C->n_append);
-    C->n_pl = C->n_append = C->n_ev = 0;
-    C->blocks_done = 0;
-    C->step += 1u;
+    __syncthreads();
+    if (s == 0) {
+        C->n_rec = C->n_live + C->n_append;
+        C->n_pl = C->n_append = C->n_ev = 0;
+        C->step += 1u;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1020,27 +1065,20 @@ __device__ inline void finish_step(Counters *C)
 // All lanes compute the same values; lane 0 writes.
 // ---------------------------------------------------------------------------
 template <int DIM, class T>
-__device__ inline void ev_match(const Params &P, Rec<T> *__restrict__ rec, u32 ia, u32 ib, u32 *__restrict__ partner, u32 step,
-                                Counters *C, DbgMatch *dbg)
+__device__ __noinline__ void ev_match(const Params &P, Rec<T> *__restrict__ rec, u32 ia, u32 ib, double R0, u32 *__restrict__ partner,
+                                      u32 step, Counters *C, DbgMatch *dbg)
 {
 #pragma clang fp contract(off)
     Rec<T> ra = rec[ia], rb = rec[ib];
     const u32 sa = meta_slot(rec_meta(ra)), sb = meta_slot(rec_meta(rb));
-    double dA[3], dB[3];
-    displacement<DIM>(P, sa, SP_A, step, dA);
-    displacement<DIM>(P, sb, SP_B, step, dB);
     const double xa[3] = {(double)ra.x, (double)ra.y, (double)ra.z};
     const double xb[3] = {(double)rb.x, (double)rb.y, (double)rb.z};
-    double rv[3] = {0.0, 0.0, 0.0}, r2 = 0.0, r02 = 0.0;
+    double rv[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
     for (int d = 0; d < DIM; ++d) {
         rv[d] = min_image_d(xb[d] - xa[d], P.L[d], P.Lh[d]);
-        const double o = rv[d] - (dB[d] - dA[d]);
         r2 += rv[d] * rv[d];
-        r02 += o * o;
     }
     const double R = sqrt(r2) / P.a;
-    double R0 = sqrt(r02) / P.a;
-    if (R0 < 1.0) R0 = 1.0;
     bool react;
     double Rpp = R, preac = 1.0;
     u32 att = 0, hits = 0, near = 0;
@@ -1094,7 +1132,7 @@ __device__ inline void ev_match(const Params &P, Rec<T> *__restrict__ rec, u32 i
 }
 
 template <int DIM, class T>
-__device__ inline void ev_decay(const Params &P, Rec<T> *__restrict__ rec, u32 i, u32 *__restrict__ partner, u32 step,
+__device__ __noinline__ void ev_decay(const Params &P, Rec<T> *__restrict__ rec, u32 i, u32 *__restrict__ partner, u32 step,
                                 Counters *C, DbgDiss *dbg)
 {
 #pragma clang fp contract(off)
@@ -1123,14 +1161,14 @@ __device__ inline void ev_decay(const Params &P, Rec<T> *__restrict__ rec, u32 i
     const uint4 r = philox(sc, NOSLOT, step, TAG_DIR, P.key);
     double e[3] = {0.0, 0.0, 0.0};
     if (DIM == 3) {
-        const double z = 2.0 * u01(r.x) - 1.0, ph = (2.0 * PI_D) * u01(r.y), rho = sqrt(1.0 - z * z);
-        e[0] = rho * cos(ph);
-        e[1] = rho * sin(ph);
+        const double z = 2.0 * u01(r.x) - 1.0, rho = sqrt(1.0 - z * z);
+        double sp, cp;
+        sincos_turn<T>(u01(r.y), &sp, &cp);
+        e[0] = rho * cp;
+        e[1] = rho * sp;
         e[2] = z;
     } else {
-        const double ph = (2.0 * PI_D) * u01(r.x);
-        e[0] = cos(ph);
-        e[1] = sin(ph);
+        sincos_turn<T>(u01(r.x), &e[1], &e[0]);
     }
     const double X[3] = {(double)rc.x, (double)rc.y, (double)rc.z};
     Rec<T> ra = rc, rb = rc;
@@ -1152,27 +1190,24 @@ __device__ inline void ev_decay(const Params &P, Rec<T> *__restrict__ rec, u32 i
     }
 }
 
+// The handlers are called, not inlined: one inlined body for both event
+// kinds needs more registers than a wave has and spills.  They read the
+// parameters from a device-resident copy (a by-value kernel argument would be
+// copied to per-lane scratch to be passed by reference).
 template <int DIM, class T>
-__global__ __launch_bounds__(BLOCK) void k_events(Params P, Rec<T> *__restrict__ rec, const PairEnt *__restrict__ list,
+__global__ __launch_bounds__(BLOCK) void k_events(const Params *__restrict__ Pd, Rec<T> *__restrict__ rec,
+                                                   const PairEnt *__restrict__ list, const CandEnt *__restrict__ cand,
                                                    const u32 *__restrict__ ev, u32 *__restrict__ partner, Counters *C,
                                                    DbgMatch *dbg_m, DbgDiss *dbg_d)
 {
+    const Params &P = *Pd;
     const u32 step = C->step;
     const u32 n = min(C->n_ev, P.cap);
     const u32 wave = (blockIdx.x * BLOCK + threadIdx.x) >> 6, nwaves = (gridDim.x * BLOCK) >> 6;
     for (u32 w = wave; w < n; w += nwaves) {
         const u32 e = ev[w];
         if (e & EV_DECAY) ev_decay<DIM, T>(P, rec, e & ~EV_DECAY, partner, step, C, dbg_d);
-        else ev_match<DIM, T>(P, rec, list[e].a_idx, list[e].b_idx, partner, step, C, dbg_m);
-    }
-    // K9: the last block to finish closes the step
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(&C->blocks_done, 1u) == gridDim.x - 1) {
-            __threadfence();
-            finish_step(C);
-        }
+        else ev_match<DIM, T>(P, rec, list[e].a_idx, list[e].b_idx, cand[e].R0, partner, step, C, dbg_m);
     }
 }
 
