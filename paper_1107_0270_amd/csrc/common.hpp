@@ -115,6 +115,7 @@ struct Params {
     Key key;
     u32 cap;
     u32 cap_pl;          // capacity of the per-step pair list
+    u32 cnt_region;      // words per region of the bucket counters (keys padded to whole scan tiles / 16)
     int tiled;           // pair search through LDS bricks (all edges >= 3 cells)
     int bx, by, bz;      // brick edges in cells
     u32 nbx, nby, nbz;   // bricks per axis
@@ -141,7 +142,8 @@ struct Counters {
     u32 err;
     u32 n_dbg[4];   // pairs, picks, matches, dissociations logged this step
     u32 n_ev;       // events (matched pairs and decays) queued this step
-    u32 pad[5];
+    u32 n_sorted;   // leading records whose bucket keys the last binning noted
+    u32 pad[4];
     u64 stats[ST_N];
     u64 stats_last[ST_N];
     u64 stats_sum[ST_N];

@@ -158,7 +158,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     bool narrow = false;
     // device memory
     Rec<T> *rec[2] = {nullptr, nullptr}, *tmp = nullptr;
-    u32 *rank = nullptr, *cnt = nullptr, *start = nullptr, *bsum = nullptr, *partner = nullptr;
+    u32 *rank = nullptr, *cnt = nullptr, *scnt = nullptr, *okey = nullptr, *start = nullptr, *bsum = nullptr, *partner = nullptr;
     PairEnt *plist = nullptr;
     CandEnt *cand = nullptr;
     u32 *flag = nullptr, *nextA = nullptr, *nextB = nullptr, *ev = nullptr;
@@ -336,10 +336,12 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         P.debug = M.debug;
         P.dbg_cap = (u32)M.dbg_cap;
         nb_scan = (P.n_keys + SCAN_TILE - 1) / SCAN_TILE;
+        P.cnt_region = nb_scan * (SCAN_TILE / CNT_REGIONS);
         // device buffers
         int rc;
         if ((rc = alloc(rec[0], n)) || (rc = alloc(rec[1], n)) || (rc = alloc(tmp, n)) ||
             (rc = alloc(rank, n)) || (rc = alloc(cnt, (uint64_t)nb_scan * SCAN_TILE)) ||
+            (rc = alloc(scnt, (uint64_t)nb_scan * SCAN_TILE)) || (rc = alloc(okey, n)) ||
             (rc = alloc(start, (uint64_t)nb_scan * SCAN_TILE + 1)) || (rc = alloc(bsum, nb_scan)) || (rc = alloc(partner, n)) ||
             (rc = alloc(plist, P.cap_pl)) || (rc = alloc(cand, P.cap_pl)) || (rc = alloc(flag, P.cap_pl)) ||
             (rc = alloc(nextA, P.cap_pl)) || (rc = alloc(nextB, P.cap_pl)) || (rc = alloc(headA, n)) ||
@@ -352,6 +354,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
                 return rc;
         }
         HIPCHECK(hipMemsetAsync(cnt, 0, sizeof(u32) * nb_scan * SCAN_TILE, M.stream));  // padding stays zero
+        HIPCHECK(hipMemsetAsync(scnt, 0, sizeof(u32) * nb_scan * SCAN_TILE, M.stream));
         double g2h[4 * (MAXTERMS + 1)];
         h_g2_constants(P.hh, g2h);
         HIPCHECK(hipMemcpyAsync(g2c, g2h, sizeof(g2h), hipMemcpyHostToDevice, M.stream));
@@ -423,12 +426,12 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         Rec<T> *in = rec[c], *out = rec[c ^ 1];
         const u32 g_all = grid_for(n, 8192);
         const u32 g_pl = 1024;
-        launch(SIM_K_MOVE, [&] { k_move_count<DIM, T><<<g_all, BLOCK, 0, st>>>(P, in, tmp, rank, cnt, ctr); });
+        launch(SIM_K_MOVE, [&] { k_move_count<DIM, T><<<g_all, BLOCK, 0, st>>>(P, in, okey, tmp, rank, cnt, scnt, ctr); });
         launch(SIM_K_SCAN, [&] {
-            k_scan_tiles<<<nb_scan, BLOCK, 0, st>>>(cnt, bsum);
-            k_scan<<<nb_scan, BLOCK, 0, st>>>(cnt, bsum, start, ctr);
+            k_scan_tiles<<<nb_scan, BLOCK, 0, st>>>(cnt, scnt, bsum);
+            k_scan<<<nb_scan, BLOCK, 0, st>>>(cnt, scnt, bsum, start, ctr);
         });
-        launch(SIM_K_SCATTER, [&] { k_scatter<DIM, T><<<g_all, BLOCK, 0, st>>>(P, tmp, rank, start, out, ctr); });
+        launch(SIM_K_SCATTER, [&] { k_scatter<DIM, T><<<g_all, BLOCK, 0, st>>>(P, tmp, rank, start, out, okey, ctr); });
         if (M.debug) {
             k_fill<<<grid_for(n * DIM, 2048), BLOCK, 0, st>>>(dbg_moved, n * DIM, (int *)dbg_cells, (u32)n);
             k_gather<DIM, T><<<g_all, BLOCK, 0, st>>>(out, partner, ctr, 1, dbg_moved, nullptr, (u32)n);

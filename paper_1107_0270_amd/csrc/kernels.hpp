@@ -16,6 +16,13 @@ constexpr int SCAN_ITEMS = 16;   // keys per thread in the bin scan
 constexpr int SCAN_TILE = BLOCK * SCAN_ITEMS;
 
 __device__ __forceinline__ u32 gtid() { return blockIdx.x * BLOCK + threadIdx.x; }
+
+// Bucket counters: key k is kept in region k % 16 at offset k / 16 (regions
+// of region_len words).  A wave counts particles of consecutive cells, so its
+// atomics then fall on 16 cache lines with a few words each instead of on two
+// lines: same-line atomics serialise.
+constexpr u32 CNT_REGIONS = 16;
+__device__ __forceinline__ u32 cnt_index(u32 key, u32 region_len) { return (key % CNT_REGIONS) * region_len + key / CNT_REGIONS; }
 __device__ __forceinline__ u32 gstride() { return gridDim.x * BLOCK; }
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
@@ -106,34 +113,7 @@ template <int DIM, class T> __device__ inline u32 cell_of(const Params &P, const
 }
 
 // ---------------------------------------------------------------------------
-// K1: move every live record and count it into its (species, cell) bucket.
-// ---------------------------------------------------------------------------
-template <int DIM, class T>
-__global__ __launch_bounds__(BLOCK) void k_move_count(Params P, const Rec<T> *__restrict__ rec, Rec<T> *__restrict__ tmp,
-                                                       u32 *__restrict__ rank, u32 *__restrict__ cnt, Counters *C)
-{
-    const u32 step = C->step;
-    if (gtid() == 0) {
-        C->n_dbg[0] = C->n_dbg[1] = C->n_dbg[2] = C->n_dbg[3] = 0;
-    }
-    const u32 n = C->n_rec;
-    for (u32 i = gtid(); i < n; i += gstride()) {
-        const Rec<T> r = rec[i];
-        const u32 m = rec_meta(r), sp = meta_sp(m);
-        if (sp > SP_C) {
-            tmp[i] = r;  // dead record: the scatter skips it
-            continue;
-        }
-        const Rec<T> q = moved<DIM, T>(P, r, m, step);
-        tmp[i] = q;
-        const u32 key = sp * P.n_cells + cell_of<DIM, T>(P, q);
-        rank[i] = atomicAdd(&cnt[key], 1u);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// K2: exclusive scan of the bucket counts into bucket starts (and clear the
-// counts for the next step).
+// Wave and workgroup scans.
 // ---------------------------------------------------------------------------
 __device__ inline u32 wave_incl_scan(u32 v)
 {
@@ -171,31 +151,119 @@ __device__ inline u32 block_sum(u32 v, u32 *lds)
     return t;
 }
 
-// Two passes, no waiting.  Each thread owns SCAN_ITEMS consecutive keys (four
-// 16-byte loads); the count and start arrays are padded to whole tiles and
-// the padding of the counts stays zero.  Pass 1 writes tile sums; pass 2 adds
-// up the sums of the tiles before its own (a few hundred values) and scans
-// its tile.
-static_assert(SCAN_ITEMS == 16, "four uint4 per thread");
-
-__device__ __forceinline__ void load16(const u32 *p, u32 v[16])
+__device__ inline u32 block_incl_max(u32 v, u32 *lds)
 {
-    const uint4 *q = reinterpret_cast<const uint4 *>(p);
+    const int lane = lane_id(), w = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint4 t = q[k];
-        v[4 * k] = t.x;
-        v[4 * k + 1] = t.y;
-        v[4 * k + 2] = t.z;
-        v[4 * k + 3] = t.w;
+    for (int o = 1; o < 64; o <<= 1) {
+        const u32 x = __shfl_up(v, o, 64);
+        if (lane >= o) v = max(v, x);
+    }
+    if (lane == 63) lds[w] = v;
+    __syncthreads();
+    for (int k = 0; k < w; ++k) v = max(v, lds[k]);
+    __syncthreads();
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// K1: move every live record and count it into its (species, cell) bucket.
+// The records sit in the order of last step's buckets, whose keys okey[]
+// holds for the first n_sorted of them, and a step takes only a few per cent
+// of them to another bucket.  A record that keeps its bucket (a stayer) is
+// ranked among the stayers of that bucket by a segmented scan over its
+// workgroup's chunk, and the chunk stores the bucket's stayer count: no
+// atomics.  Every other live record (bucket changed, appended since the last
+// binning, or in a bucket that began in an earlier chunk) takes its rank
+// from an atomic counter.  Stayers fill a bucket from its start, the others
+// from its end.  rank[i] = STAYER | rank for a stayer, else the atomic rank.
+// ---------------------------------------------------------------------------
+constexpr u32 STAYER = 0x80000000u;
+constexpr u32 NOKEY = 0xFFFFFFFFu;
+
+template <int DIM, class T>
+__global__ __launch_bounds__(BLOCK) void k_move_count(Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ okey,
+                                                       Rec<T> *__restrict__ tmp, u32 *__restrict__ rank, u32 *__restrict__ cnt,
+                                                       u32 *__restrict__ scnt, Counters *C)
+{
+    __shared__ u32 lds[BLOCK / 64];
+    __shared__ u32 skey[BLOCK + 1];  // old bucket keys of the chunk; [BLOCK]: that of the record before it
+    __shared__ u32 sx[BLOCK];        // exclusive prefix count of stayers in the chunk
+    const u32 step = C->step;
+    if (gtid() == 0) {
+        C->n_dbg[0] = C->n_dbg[1] = C->n_dbg[2] = C->n_dbg[3] = 0;
+    }
+    const u32 n = C->n_rec, ns = min(C->n_sorted, n);
+    const u32 t = threadIdx.x;
+    for (u32 b0 = blockIdx.x * BLOCK; b0 < n; b0 += gridDim.x * BLOCK) {  // uniform over the workgroup
+        const u32 i = b0 + t;
+        const bool valid = i < n, sorted = i < ns;
+        Rec<T> r;
+        u32 m = 0, sp = SP_DEAD;
+        if (valid) {
+            r = rec[i];
+            m = rec_meta(r);
+            sp = meta_sp(m);
+        }
+        const u32 ok = sorted ? okey[i] : NOKEY;
+        skey[t] = ok;
+        if (t == 0) skey[BLOCK] = (b0 > 0 && b0 - 1 < ns) ? okey[b0 - 1] : NOKEY;
+        const bool alive = valid && sp <= SP_C;
+        u32 key = NOKEY;
+        if (alive) {
+            const Rec<T> q = moved<DIM, T>(P, r, m, step);
+            tmp[i] = q;
+            key = sp * P.n_cells + cell_of<DIM, T>(P, q);
+        } else if (valid) {
+            tmp[i] = r;  // dead record: the scatter skips it
+        }
+        __syncthreads();
+        // segments: runs of equal old keys; the first one is not this
+        // chunk's if it continues from the record before the chunk
+        const bool head = t == 0 || skey[t - 1] != ok;
+        const u32 seg0 = block_incl_max(head ? t : 0u, lds);
+        const bool cont0 = skey[BLOCK] != NOKEY && skey[BLOCK] == skey[0];
+        const bool local = sorted && !(seg0 == 0 && cont0);
+        const bool stay = alive && local && key == ok;
+        u32 total;
+        const u32 ex = block_excl_scan(stay ? 1u : 0u, lds, total);
+        sx[t] = ex;
+        __syncthreads();
+        const u32 rs = ex - sx[seg0];
+        const bool last = t == BLOCK - 1 || skey[t + 1] != ok;
+        if (local && last) scnt[cnt_index(ok, P.cnt_region)] = rs + (stay ? 1u : 0u);
+        if (alive) rank[i] = stay ? (STAYER | rs) : atomicAdd(&cnt[cnt_index(key, P.cnt_region)], 1u);
+        __syncthreads();  // the next chunk reuses skey and sx
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_scan_tiles(const u32 *__restrict__ cnt, u32 *__restrict__ tsum)
+
+// ---------------------------------------------------------------------------
+// K2: exclusive scan of the bucket counts (atomic counts plus stayer counts)
+// into bucket starts, clearing both for the next step.
+// ---------------------------------------------------------------------------
+// Two passes, no waiting.  Each thread owns SCAN_ITEMS consecutive keys; the
+// count and start arrays are padded to whole tiles and the padding of the
+// counts stays zero.  Pass 1 writes tile sums; pass 2 adds up the sums of the
+// tiles before its own (a few hundred values) and scans its tile.
+// The counts of the 16 keys of thread g sit in 16 regions at offset g
+// (cnt_index), so each of a thread's 16 loads is coalesced across the wave.
+static_assert(SCAN_ITEMS == CNT_REGIONS, "one key per region per thread");
+
+__device__ __forceinline__ void load_counts(const u32 *cnt, u32 g, u32 region_len, u32 v[16])
+{
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = cnt[(size_t)r * region_len + g];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_tiles(const u32 *__restrict__ cnt, const u32 *__restrict__ scnt, u32 *__restrict__ tsum)
 {
     __shared__ u32 lds[BLOCK / 64];
-    u32 v[16];
-    load16(cnt + (size_t)blockIdx.x * SCAN_TILE + SCAN_ITEMS * threadIdx.x, v);
+    u32 v[16], w[16];
+    load_counts(cnt, gtid(), gridDim.x * BLOCK, v);
+    load_counts(scnt, gtid(), gridDim.x * BLOCK, w);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] += w[k];
     u32 s = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) s += v[k];
@@ -203,13 +271,17 @@ __global__ __launch_bounds__(BLOCK) void k_scan_tiles(const u32 *__restrict__ cn
     if (threadIdx.x == 0) tsum[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_scan(u32 *__restrict__ cnt, const u32 *__restrict__ tsum, u32 *__restrict__ start,
-                                                 Counters *C)
+__global__ __launch_bounds__(BLOCK) void k_scan(u32 *__restrict__ cnt, u32 *__restrict__ scnt, const u32 *__restrict__ tsum,
+                                                 u32 *__restrict__ start, Counters *C)
 {
     __shared__ u32 lds[BLOCK / 64];
     const size_t base = (size_t)blockIdx.x * SCAN_TILE + SCAN_ITEMS * threadIdx.x;
-    u32 v[16];
-    load16(cnt + base, v);
+    const u32 rl = gridDim.x * BLOCK;
+    u32 v[16], w[16];
+    load_counts(cnt, gtid(), rl, v);
+    load_counts(scnt, gtid(), rl, w);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] += w[k];
     u32 before = 0;
     for (u32 t = threadIdx.x; t < blockIdx.x; t += BLOCK) before += tsum[t];
     const u32 carry = block_sum(before, lds);
@@ -219,7 +291,6 @@ __global__ __launch_bounds__(BLOCK) void k_scan(u32 *__restrict__ cnt, const u32
     u32 total;
     u32 run = carry + block_excl_scan(mine, lds, total);
     uint4 *o = reinterpret_cast<uint4 *>(start + base);
-    uint4 *z = reinterpret_cast<uint4 *>(cnt + base);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         uint4 t;
@@ -232,8 +303,11 @@ __global__ __launch_bounds__(BLOCK) void k_scan(u32 *__restrict__ cnt, const u32
         t.w = run;
         run += v[4 * k + 3];
         o[k] = t;
-        z[k] = make_uint4(0u, 0u, 0u, 0u);
     }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) cnt[(size_t)r * rl + gtid()] = 0u;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) scnt[(size_t)r * rl + gtid()] = 0u;
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == BLOCK - 1) {
         start[(size_t)gridDim.x * SCAN_TILE] = run;
         C->n_live = run;
@@ -241,11 +315,14 @@ __global__ __launch_bounds__(BLOCK) void k_scan(u32 *__restrict__ cnt, const u32
 }
 
 // ---------------------------------------------------------------------------
-// K3: write each moved record to its sorted place.
+// K3: write each moved record to its sorted place (stayers from the start of
+// the bucket, the others from its end) and note its bucket key for the next
+// step's stayer test.
 // ---------------------------------------------------------------------------
 template <int DIM, class T>
 __global__ __launch_bounds__(BLOCK) void k_scatter(Params P, const Rec<T> *__restrict__ tmp, const u32 *__restrict__ rank,
-                                                    const u32 *__restrict__ start, Rec<T> *__restrict__ out, const Counters *C)
+                                                    const u32 *__restrict__ start, Rec<T> *__restrict__ out, u32 *__restrict__ okey,
+                                                    const Counters *C)
 {
     const u32 n = C->n_rec;
     for (u32 i = gtid(); i < n; i += gstride()) {
@@ -253,8 +330,12 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Params P, const Rec<T> *__res
         const u32 sp = meta_sp(rec_meta(q));
         if (sp > SP_C) continue;
         const u32 key = sp * P.n_cells + cell_of<DIM, T>(P, q);
-        const u32 dst = start[key] + rank[i];
-        if (dst < P.cap) out[dst] = q;
+        const u32 rk = rank[i];
+        const u32 dst = (rk & STAYER) ? start[key] + (rk & ~STAYER) : start[key + 1] - 1u - rk;
+        if (dst < P.cap) {
+            out[dst] = q;
+            okey[dst] = key;
+        }
     }
 }
 
@@ -1048,6 +1129,7 @@ __global__ void k_close(Counters *C)
     __syncthreads();
     if (s == 0) {
         C->n_rec = C->n_live + C->n_append;
+        C->n_sorted = C->n_live;  // records [0, n_live) carry their bucket keys
         C->n_pl = C->n_append = C->n_ev = 0;
         C->step += 1u;
     }
