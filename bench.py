@@ -11,6 +11,7 @@ Prints one JSON line.  Kernel durations come from HIP events recorded on the
 library's stream around every kernel of the timed steps.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,14 +27,52 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kernel, n_live, n_a, n_b, n_keys, rec_bytes):
-    """HBM bytes one launch of a stage must move at least (each datum once)."""
+def algorithmic_bytes(kernel, n_live, n_a, n_b, n_keys):
+    """Bytes the method itself must move per launch of a stage (binary32 records): move 32 B per
+    particle (read and write a position), binning 36 B per particle plus 8 B per bucket, the pair
+    stage 32 B per A or B (new and old position)."""
     return {
-        "move": (2 * rec_bytes + 4) * n_live + 8 * n_keys,      # read record, write moved record + rank, count buckets
-        "scan": 12 * n_keys,                                     # read counts, write starts, clear counts
-        "scatter": (2 * rec_bytes + 8) * n_live,                 # read moved record + rank + start, write record
-        "pairs": rec_bytes * (n_a + n_b) + 4 * n_keys // 3,      # A and B records once, B bucket starts
+        "move": 32 * n_live,
+        "scan": 8 * n_keys,
+        "scatter": 36 * n_live,
+        "pairs": 32 * (n_a + n_b),
     }.get(kernel)
+
+
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE on this workload (KiB per
+# dispatch, each counter scaled by what it reads for a plain 256 MiB device copy); the table and the
+# commands are in profiles/rad3d_step_traffic.md.  Valid only for the kernel sources they were taken
+# on (hash below): after any change to them the field is reported as null.
+MEASURED_TRAFFIC = {
+    "src_hash": "11263d1d77ecf003",
+    "scale_fetch": 1.9998, "scale_write": 1.0,
+    "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
+        "move": (9816.4, 31266.3),
+        "scan": (5809.5 + 5820.5, 11.3 + 17376.1),
+        "scatter": (17027.9, 29451.3),
+        "pairs": (9598.4, 157.7),
+        "eval": (1019.8, 94.5),
+        "select_a": (146.9, 52.6),
+        "select_b": (157.9, 11.8),
+        "events": (1287.5 + 1.6, 5654.5 + 0.4),
+    },
+}
+
+
+def kernel_src_hash():
+    h = hashlib.sha256()
+    for f in ["common.hpp", "green.hpp", "kernels.hpp", "gfbd.hip"]:
+        with open(os.path.join(ROOT, "paper_1107_0270_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(stage):
+    t = MEASURED_TRAFFIC
+    if stage not in t["kib"] or kernel_src_hash() != t["src_hash"]:
+        return None
+    f, w = t["kib"][stage]
+    return int(f * 1024 * t["scale_fetch"] + w * 1024 * t["scale_write"])
 
 
 def main():
@@ -46,7 +85,19 @@ def main():
     ap.add_argument("--pair-search", choices=["auto", "bricks", "direct"], default="auto",
                     help="pair-search kernel (auto = the library's choice)")
     ap.add_argument("--cell", type=float, default=0.0, help="cell edge in um (0 = the library's choice)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB five times (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        x = torch.ones(args.copy_probe << 18, device="cuda")  # float32: MIB MiB
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": x.numel() * 4, "launches": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported", "n_gpus": args.gpus}))
         sys.exit(2)
@@ -91,19 +142,18 @@ def main():
         log(f"[bench] events: {args.steps} steps in {el_ev * 1e3:.1f} ms; kernel times {kt}")
 
     # dominant kernel and its roofline
-    rec_bytes = 16
     n_keys = 3 * grid[3]
     per = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kt.items()}
     tot = {k: v[0] for k, v in kt.items()}
     dom = max(tot, key=tot.get) if any(tot.values()) else None
     roof = None
     if dom is not None and per[dom] > 0:
-        nb = algorithmic_bytes(dom, n_live, 0.5 * (c0["A"] + c1["A"]), 0.5 * (c0["B"] + c1["B"]), n_keys, rec_bytes)
+        nb = algorithmic_bytes(dom, n_live, 0.5 * (c0["A"] + c1["A"]), 0.5 * (c0["B"] + c1["B"]), n_keys)
         if nb is not None:
             ach = nb / (per[dom] * 1e-3) / 1e9
             roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": int(nb),
-                    "avg_launch_ms": round(per[dom], 5)}
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
+                    "algorithmic_bytes_per_launch": int(nb), "avg_launch_ms": round(per[dom], 5)}
 
     cpu = None
     if args.cpu_steps > 0:
