@@ -17,6 +17,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -75,6 +77,50 @@ def measured_traffic(stage):
     return int(f * 1024 * t["scale_fetch"] + w * 1024 * t["scale_write"])
 
 
+def pair_probs(args, I, S):
+    """p_enc and p_reac of N pairs drawn from the workload's pair distribution (uniform positions:
+    R uniform in the ball of radius r_cut/a; R0 = |R + sqrt(2 tau) z| >= 1, z standard normal),
+    evaluated by sim_eval_pairs with the step's device functions on device-resident arrays."""
+    cfg = I.workload("cfg_rad3d" if args.dim == 3 else "cfg_mem2d_small_tau")
+    d = args.dim
+    sp = np.array([0, 1], np.int32)
+    pos = np.array([[0.25] * d, [0.75] * d])
+    h = S.Sim(dim=d, box=cfg["box"], dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
+              k_off=0.0, precision=cfg["precision"], seed=0, species=sp, pos=pos)
+    der = h.derived()
+    tau, rmax, n = der["tau"], der["rcut"] / der["a"], args.pair_probs
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal((n, d))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    v *= (rmax * rng.random(n) ** (1.0 / d))[:, None]
+    R = np.linalg.norm(v, axis=1)
+    v += np.sqrt(2.0 * tau) * rng.standard_normal((n, d))
+    R0 = np.maximum(np.linalg.norm(v, axis=1), 1.0)
+    del v
+    bufs = [S.DeviceBuffer(8 * n) for _ in range(4)]
+    bufs[0].upload(R)
+    bufs[1].upload(R0)
+    out = {}
+    for name, want_preac in (("penc", False), ("penc_preac", True)):
+        args4 = (n, bufs[0].ptr, bufs[1].ptr, bufs[2].ptr, bufs[3].ptr if want_preac else None)
+        h.eval_pairs_device(*args4)  # warm-up
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            h.eval_pairs_device(*args4)
+        out[name] = n * args.steps / (time.perf_counter() - t0)
+        log(f"[pair-probs] {name}: {out[name]:.3e} pair evals/s")
+    for b in bufs:
+        b.free()
+    h.close()
+    print(json.dumps({
+        "metric": "pair-probability evals/s (kernel only)", "value": round(out["penc"], 1), "unit": "pair evals/s",
+        "penc_and_preac_per_s": round(out["penc_preac"], 1), "n_gpus": 1, "pairs": n, "repeats": args.steps,
+        "dtype": {0: "f64", 1: "f32", 2: "f32+f64-args"}[cfg["precision"]], "data": "synthetic",
+        "config": {"workload": f"{d}D pair distribution of the benchmark workload: R uniform in the ball of radius "
+                               f"r_cut/a = {rmax:.3f}, R0 = |R + sqrt(2 tau) z|, tau = {tau:.4g}",
+                   "kernel": "k_eval_probs (the step's p_enc / p_reac device functions)"}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +131,10 @@ def main():
     ap.add_argument("--pair-search", choices=["auto", "bricks", "direct"], default="auto",
                     help="pair-search kernel (auto = the library's choice)")
     ap.add_argument("--cell", type=float, default=0.0, help="cell edge in um (0 = the library's choice)")
+    ap.add_argument("--pair-probs", type=int, default=0, metavar="N",
+                    help="only run the pair-probability micro-benchmark on N synthetic pairs and exit")
+    ap.add_argument("--dim", type=int, default=3, help="workload dimension for --pair-probs (2: the membrane "
+                    "workload at dt = 5 us)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -104,6 +154,10 @@ def main():
 
     from paper_1107_0270_amd import inputs as I
     from paper_1107_0270_amd import sim as S
+
+    if args.pair_probs:
+        pair_probs(args, I, S)
+        return
 
     cfg = I.workload("cfg_rad3d")
     t0 = time.time()

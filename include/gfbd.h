@@ -173,6 +173,17 @@ int sim_read(sim_t *h, int what, void *dst, uint64_t cap_bytes, uint64_t *writte
  * n must equal the handle's slot count. */
 int sim_load_state(sim_t *h, uint64_t step, const int32_t *species, const double *pos, const uint32_t *partner);
 
+/* Evaluates p_enc = 1 - g_abs/g_free (Secs. 2.2.1 and 2.2.4, with the closed forms of Sec. 4.1
+ * in 3D and the small-time expansion of Sec. 4.2 in 2D) and p_reac = (g_ref - g_rad)/(g_ref - g_abs)
+ * (Sec. 2.2.3) for n caller-given pairs, with the step's own device functions and the handle's
+ * dim, precision, boundary condition, tau, h and n_terms.  R[i] = r/a is the separation after
+ * the move and R0[i] = r0/a >= 1 the one before it (a = sigma); for p_reac R[i] is the
+ * propagated R'' >= 1.  R, R0, penc and preac are DEVICE pointers to n doubles owned by the
+ * caller; penc or preac may be NULL to skip it.  p_enc is 1 for R <= 1 (overlap); p_reac is 1
+ * for an absorbing and 0 for a reflecting surface.  Runs on the handle's stream and returns
+ * when done.  SIM_EINVAL for NULL R, R0 or n = 0; SIM_EDEVICE if a HIP call fails. */
+int sim_eval_pairs(sim_t *h, uint64_t n, const double *R, const double *R0, double *penc, double *preac);
+
 /* Releases all device memory of the handle; NULL is accepted. */
 int sim_destroy(sim_t *h);
 

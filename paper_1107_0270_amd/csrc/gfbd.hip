@@ -115,6 +115,7 @@ struct sim {
     virtual int step(uint32_t n) = 0;
     virtual int read(int what, void *dst, uint64_t cap, uint64_t *written) = 0;
     virtual int load(uint64_t step, const int32_t *sp, const double *pos, const uint32_t *partner) = 0;
+    virtual int eval_pairs(uint64_t n, const double *R, const double *R0, double *penc, double *preac) = 0;
     int fail(int code, const std::string &msg)
     {
         err = msg;
@@ -483,6 +484,15 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         return SIM_OK;
     }
 
+    int eval_pairs(uint64_t n, const double *R, const double *R0, double *penc, double *preac) override
+    {
+        const u32 g = grid_for(n, 16384);
+        k_eval_probs<DIM, PM><<<g, BLOCK, 0, M.stream>>>(P, n, R, R0, penc, preac);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipStreamSynchronize(M.stream));
+        return SIM_OK;
+    }
+
     int step(uint32_t nsteps) override
     {
         for (uint32_t i = 0; i < nsteps; ++i) {
@@ -734,6 +744,12 @@ int sim_load_state(sim_t *h, uint64_t step, const int32_t *species, const double
 {
     if (!h || !species || !pos) { g_err = "null argument"; return SIM_EINVAL; }
     return h->load(step, species, pos, partner);
+}
+
+int sim_eval_pairs(sim_t *h, uint64_t n, const double *R, const double *R0, double *penc, double *preac)
+{
+    if (!h || !R || !R0 || n == 0) { g_err = "null argument or n = 0"; return SIM_EINVAL; }
+    return h->eval_pairs(n, R, R0, penc, preac);
 }
 
 int sim_destroy(sim_t *h)

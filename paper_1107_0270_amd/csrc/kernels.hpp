@@ -369,6 +369,21 @@ __device__ __forceinline__ float min_image_f(float xb, float xa, float L, float 
 // Everything about one A-B pair within r_cut (Sec. 3, steps 2-3): separation r
 // after the move, separation r0 = r - (dB - dA) before it (R0 < 1 clamped to
 // 1), p_enc (overlap: 1) and the Bernoulli draw {a, b, step, ENC}.
+// p_enc of a pair that does not overlap (R > 1, R0 >= 1) in the pair
+// arithmetic PM: binary64; binary32 from binary32 R and R0; or binary32
+// exponentials of binary64 exponent arguments.  The 2D expansion is binary64.
+template <int DIM, int PM> __device__ __forceinline__ double penc_R(const Params &P, double R, double R0)
+{
+#pragma clang fp contract(off)
+    if (DIM == 2) return penc2(P, R, R0);
+    if (PM == PM_F32) {
+        const float Rf = (float)R, R0f = (float)R0;
+        return penc3_args((Rf - 1.0f) * (R0f - 1.0f) * P.inv_tauf, (Rf + R0f - 1.0f) * P.inv_tauf, Rf * R0f * P.inv_tauf);
+    }
+    const double e1 = (R - 1.0) * (R0 - 1.0) / P.tau, e2 = (R + R0 - 1.0) / P.tau, e3 = R * R0 / P.tau;
+    return PM == PM_F64 ? penc3_args(e1, e2, e3) : (double)penc3_args((float)e1, (float)e2, (float)e3);
+}
+
 template <int DIM, class T, int PM>
 __device__ inline PairQ pair_quantities(const Params &P, const Rec<T> &ra, const Rec<T> &rb, u32 sa, u32 sb,
                                         const double dA[3], u32 step)
@@ -403,9 +418,7 @@ __device__ inline PairQ pair_quantities(const Params &P, const Rec<T> &ra, const
             q.R0d = R0;
         }
         q.overlap = Rf <= 1.0f;
-        if (q.overlap) q.p = 1.0;
-        else if (DIM == 3) q.p = penc3_args((Rf - 1.0f) * (R0f - 1.0f) * P.inv_tauf, (Rf + R0f - 1.0f) * P.inv_tauf, Rf * R0f * P.inv_tauf);
-        else q.p = penc2(P, (double)Rf, (double)R0f);
+        q.p = q.overlap ? 1.0 : penc_R<DIM, PM>(P, (double)Rf, (double)R0f);
     } else {
         double rv[3] = {0.0, 0.0, 0.0}, r2 = 0.0, r02 = 0.0;
         const double xa[3] = {(double)ra.x, (double)ra.y, (double)ra.z};
@@ -425,14 +438,7 @@ __device__ inline PairQ pair_quantities(const Params &P, const Rec<T> &ra, const
         q.R0 = R0;
         q.R0d = R0;
         q.overlap = R <= 1.0;
-        if (q.overlap) {
-            q.p = 1.0;
-        } else if (DIM == 3) {
-            const double e1 = (R - 1.0) * (R0 - 1.0) / P.tau, e2 = (R + R0 - 1.0) / P.tau, e3 = R * R0 / P.tau;
-            q.p = PM == PM_F64 ? penc3_args(e1, e2, e3) : (double)penc3_args((float)e1, (float)e2, (float)e3);
-        } else {
-            q.p = penc2(P, R, R0);
-        }
+        q.p = q.overlap ? 1.0 : penc_R<DIM, PM>(P, R, R0);
     }
     q.draw = philox(sa, sb, step, TAG_ENC, P.key).x;
     q.cand = q.overlap || below(q.draw, q.p);
@@ -1290,6 +1296,21 @@ __global__ __launch_bounds__(BLOCK) void k_events(const Params *__restrict__ Pd,
         const u32 e = ev[w];
         if (e & EV_DECAY) ev_decay<DIM, T>(P, rec, e & ~EV_DECAY, partner, step, C, dbg_d);
         else ev_match<DIM, T>(P, rec, list[e].a_idx, list[e].b_idx, cand[e].R0, partner, step, C, dbg_m);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// p_enc and p_reac of caller-given (R, R0) pairs with the step's own device
+// functions (overlap rule included), one thread per pair.
+// ---------------------------------------------------------------------------
+template <int DIM, int PM>
+__global__ __launch_bounds__(BLOCK) void k_eval_probs(Params P, uint64_t n, const double *__restrict__ R, const double *__restrict__ R0,
+                                                       double *__restrict__ penc, double *__restrict__ preac)
+{
+    for (uint64_t i = gtid(); i < n; i += gstride()) {
+        const double r = R[i], r0 = R0[i];
+        if (penc) penc[i] = r <= 1.0 ? 1.0 : penc_R<DIM, PM>(P, r, r0);
+        if (preac) preac[i] = reac_prob(P, DIM, r, r0);
     }
 }
 

@@ -52,6 +52,51 @@ class SimConfig(C.Structure):
                 ("debug_cap", C.c_uint64), ("hip_stream", C.c_void_p)]
 
 
+_hip_rt = None
+
+
+def hip_runtime():
+    """The HIP runtime libgfbd.so is linked against (device buffers for sim_eval_pairs)."""
+    global _hip_rt
+    if _hip_rt is None:
+        lib()
+        h = C.CDLL("libamdhip64.so.7")
+        h.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
+        h.hipFree.argtypes = [C.c_void_p]
+        h.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        h.hipDeviceSynchronize.argtypes = []
+        _hip_rt = h
+    return _hip_rt
+
+
+class DeviceBuffer:
+    """A plain device allocation of the library's HIP runtime."""
+
+    def __init__(self, nbytes):
+        self.nbytes = int(nbytes)
+        p = C.c_void_p()
+        if hip_runtime().hipMalloc(C.byref(p), self.nbytes) != 0:
+            raise MemoryError(f"hipMalloc of {self.nbytes} bytes failed")
+        self.ptr = p.value
+
+    def upload(self, a):
+        a = np.ascontiguousarray(a)
+        assert a.nbytes <= self.nbytes
+        if hip_runtime().hipMemcpy(self.ptr, a.ctypes.data, a.nbytes, 1) != 0:  # host to device
+            raise RuntimeError("hipMemcpy to the device failed")
+
+    def download(self, a):
+        assert a.nbytes <= self.nbytes and a.flags["C_CONTIGUOUS"]
+        if hip_runtime().hipMemcpy(a.ctypes.data, self.ptr, a.nbytes, 2) != 0:  # device to host
+            raise RuntimeError("hipMemcpy from the device failed")
+        return a
+
+    def free(self):
+        if self.ptr:
+            hip_runtime().hipFree(self.ptr)
+            self.ptr = None
+
+
 class SimError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"gfbd error {code}: {msg}")
@@ -79,6 +124,8 @@ def lib():
     L.sim_read.restype = C.c_int
     L.sim_load_state.argtypes = [vp, u64, vp, vp, vp]
     L.sim_load_state.restype = C.c_int
+    L.sim_eval_pairs.argtypes = [vp, u64, vp, vp, vp, vp]
+    L.sim_eval_pairs.restype = C.c_int
     L.sim_destroy.argtypes = [vp]
     L.sim_destroy.restype = C.c_int
     L.sim_last_error.argtypes = [vp]
@@ -197,6 +244,32 @@ class Sim:
         out = np.zeros(8)
         self._read(READ_DERIVED, out)
         return dict(zip(["Deff", "tau", "hh", "rcut", "a", "p_uni", "cell", "step"], out.tolist()))
+
+    def eval_pairs(self, R, R0, penc=True, preac=True):
+        """p_enc and p_reac of (R, R0) pairs on the device (sim_eval_pairs).  R and R0 are host
+        arrays; they are copied to device buffers and the results back."""
+        R = np.ascontiguousarray(R, dtype=np.float64)
+        R0 = np.ascontiguousarray(R0, dtype=np.float64)
+        if R.shape != R0.shape or R.ndim != 1:
+            raise ValueError("R and R0 must be 1-D and of equal length")
+        n = R.size
+        bufs = [DeviceBuffer(8 * n) for _ in range(4)]
+        try:
+            bufs[0].upload(R)
+            bufs[1].upload(R0)
+            self.eval_pairs_device(n, bufs[0].ptr, bufs[1].ptr, bufs[2].ptr if penc else None,
+                                   bufs[3].ptr if preac else None)
+            out = []
+            for want, b in ((penc, bufs[2]), (preac, bufs[3])):
+                out.append(b.download(np.empty(n, np.float64)) if want else None)
+            return tuple(out)
+        finally:
+            for b in bufs:
+                b.free()
+
+    def eval_pairs_device(self, n, R, R0, penc, preac):
+        """sim_eval_pairs on caller-owned device pointers (ints or None)."""
+        self._check(lib().sim_eval_pairs(self._h, int(n), R, R0, penc, preac))
 
     def grid(self):
         """Cells per edge x, y, z, total cells, pair-search kernel (PAIRS_BRICKS or PAIRS_DIRECT)."""

@@ -21,7 +21,8 @@ def _declared():
 
 
 def test_header_declares_the_boundary():
-    assert _declared() == sorted(["sim_create", "sim_step", "sim_read", "sim_load_state", "sim_destroy", "sim_last_error"])
+    assert _declared() == sorted(["sim_create", "sim_step", "sim_read", "sim_load_state", "sim_eval_pairs", "sim_destroy",
+                                  "sim_last_error"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -94,3 +95,9 @@ def test_invalid_input_is_rejected_before_the_device(over, code):
     with pytest.raises(S.SimError) as e:
         S.Sim(**_args(**over))
     assert e.value.code == code
+
+
+def test_eval_pairs_rejects_null_arguments_on_the_host():
+    if not os.path.exists(S.LIB_PATH):
+        pytest.skip("libgfbd.so not built")
+    assert S.lib().sim_eval_pairs(None, 0, None, None, None, None) == S.SIM_EINVAL
