@@ -421,7 +421,17 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     static u32 grid_for(uint64_t work, u32 maxg) { return (u32)std::max<uint64_t>(1, std::min<uint64_t>((work + BLOCK - 1) / BLOCK, maxg)); }
 
     // Launches one step reading record buffer c and writing buffer c ^ 1.
+    // The kernels that evaluate the 2D expansion are compiled for its order
+    // (12, the default, or any order at run time).
     void enqueue_step(int c)
+    {
+        if constexpr (DIM == 2) {
+            if (P.n_terms == 12) return enqueue_step_n<12>(c);
+        }
+        enqueue_step_n<0>(c);
+    }
+
+    template <int NC2> void enqueue_step_n(int c)
     {
         hipStream_t st = M.stream;
         Rec<T> *in = rec[c], *out = rec[c ^ 1];
@@ -448,14 +458,14 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             else if (narrow) k_pair_scan_direct_narrow<DIM, T, PM><<<g_pairs, BLOCK, 0, st>>>(P, out, start, plist, ctr);
             else k_pair_scan_direct<DIM, T, PM><<<g_pairs, BLOCK, 0, st>>>(P, out, start, plist, ctr);
         });
-        launch(SIM_K_EVAL, [&] { k_pair_eval<DIM, T, PM><<<g_pl, BLOCK, 0, st>>>(P, out, plist, cand, flag, headA, nextA, ctr, dbg_pairs); });
+        launch(SIM_K_EVAL, [&] { k_pair_eval<DIM, T, PM, NC2><<<g_pl, BLOCK, 0, st>>>(P, out, plist, cand, flag, headA, nextA, ctr, dbg_pairs); });
         launch(SIM_K_SELECT_A, [&] { k_select_a<<<g_pl, BLOCK, 0, st>>>(P, plist, cand, flag, headA, nextA, headB, nextB, ctr, dbg_picks); });
         const u32 nb_sel = g_pl, nb_dec = P.reversible ? grid_for(maxC, 2048) : 0;
         launch(SIM_K_SELECT_B, [&] {
             k_select_b<T><<<nb_sel + nb_dec, BLOCK, 0, st>>>(P, plist, cand, flag, headB, nextB, out, start, ev, ctr, nb_sel);
         });
         launch(SIM_K_EVENTS, [&] {
-            k_events<DIM, T><<<EV_BLOCKS, BLOCK, 0, st>>>(dparams, out, plist, cand, ev, partner, ctr, dbg_matches, dbg_diss);
+            k_events<DIM, T, NC2><<<EV_BLOCKS, BLOCK, 0, st>>>(dparams, out, plist, cand, ev, partner, ctr, dbg_matches, dbg_diss);
             k_close<<<1, 64, 0, st>>>(ctr);
         });
     }
@@ -487,7 +497,14 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     int eval_pairs(uint64_t n, const double *R, const double *R0, double *penc, double *preac) override
     {
         const u32 g = grid_for(n, 16384);
-        k_eval_probs<DIM, PM><<<g, BLOCK, 0, M.stream>>>(P, n, R, R0, penc, preac);
+        bool done = false;
+        if constexpr (DIM == 2) {
+            if (P.n_terms == 12) {
+                k_eval_probs<DIM, PM, 12><<<g, BLOCK, 0, M.stream>>>(P, n, R, R0, penc, preac);
+                done = true;
+            }
+        }
+        if (!done) k_eval_probs<DIM, PM, 0><<<g, BLOCK, 0, M.stream>>>(P, n, R, R0, penc, preac);
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipStreamSynchronize(M.stream));
         return SIM_OK;

@@ -43,20 +43,12 @@ __device__ inline double preac3(const Params &P, double R, double R0)
 // 2D: e^{-x} I_0(x); scaled repeated erfc integrals; expansion coefficients.
 // ---------------------------------------------------------------------------
 
-// Ascending series up to 20, the large-argument series e^x/sqrt(2 pi x)
-// sum |a_k(0)| x^-k above (cut at its smallest term).
+// e^{-x} I_0(x): the device library's I_0 below 500, above it the
+// large-argument series e^x/sqrt(2 pi x) sum |a_k(0)| x^-k (cut at its
+// smallest term, far below rounding there).
 __device__ inline double i0e_d(double x)
 {
-    if (x <= 20.0) {
-        const double q = 0.25 * x * x;
-        double t = 1.0, s = 1.0;
-        for (int k = 1; k < 120; ++k) {
-            t *= q / (double)(k * k);
-            s += t;
-            if (t < 1e-18 * s) break;
-        }
-        return s * exp(-x);
-    }
+    if (x <= 500.0) return cyl_bessel_i0(x) * exp(-x);
     double t = 1.0, s = 1.0;
     const double ix = 1.0 / x;
     for (int k = 1; k < 80; ++k) {
@@ -69,14 +61,23 @@ __device__ inline double i0e_d(double x)
     return s * rsqrt(2.0 * PI_D * x);
 }
 
+// The expansion to order n.  NC > 0 fixes n = NC at compile time: the loops
+// unroll and the coefficient arrays stay in registers.  NC = 0 takes
+// n = P.n_terms at run time (any order up to MAXTERMS).
+template <int NC> struct Order {
+    static constexpr int M = NC > 0 ? NC : MAXTERMS;
+};
+
 // T_k = e^{x^2} i^{k-1}erfc(x) (2 sqrt tau)^k, k = 1..n, by the upward
 // recursion 2k i^k = i^{k-2} - 2x i^{k-1} (eq. iErf) started from
 // i^{-1} = 2/sqrt(pi) and i^0 = erfcx(x).
-__device__ inline void t_terms(double x, double two_st, int n, double *T)
+template <int NC> __device__ __forceinline__ void t_terms(double x, double two_st, int n, double *T)
 {
     double im2 = 2.0 / SQRTPI_D, im1 = erfcx(x), pw = two_st;
     T[1] = im1 * pw;
-    for (int k = 2; k <= n; ++k) {
+#pragma unroll
+    for (int k = 2; k <= Order<NC>::M; ++k) {
+        if (k > n) break;
         const double ik = (im2 - 2.0 * x * im1) / (2.0 * (k - 1));
         im2 = im1;
         im1 = ik;
@@ -86,59 +87,71 @@ __device__ inline void t_terms(double x, double two_st, int n, double *T)
 }
 
 // P_k: coefficients of A_0(s/R0) A_0(s/R), k = 0..n (a_k(0) from the table).
-__device__ inline void p_series(const double *a0, double R, double R0, int n, double *Pc)
+template <int NC> __device__ __forceinline__ void p_series(const double *a0, double R, double R0, int n, double *Pc)
 {
-    double x[MAXTERMS + 1], y[MAXTERMS + 1];
+    double x[Order<NC>::M + 1], y[Order<NC>::M + 1];
     const double iR = 1.0 / R, iR0 = 1.0 / R0;
     double px = 1.0, py = 1.0;
-    for (int k = 0; k <= n; ++k) {
+#pragma unroll
+    for (int k = 0; k <= Order<NC>::M; ++k) {
+        if (k > n) break;
         x[k] = a0[k] * px;
         y[k] = a0[k] * py;
         px *= iR0;
         py *= iR;
     }
-    for (int k = 0; k <= n; ++k) {
+#pragma unroll
+    for (int k = 0; k <= Order<NC>::M; ++k) {
+        if (k > n) break;
         double s = 0.0;
+#pragma unroll
         for (int m = 0; m <= k; ++m) s += x[m] * y[k - m];
         Pc[k] = s;
     }
 }
 
 // gamma_k = sum_m Q_m P_{k-m} for one boundary condition's quotient series Q.
-__device__ inline double gamma_k(const double *Q, const double *Pc, int k)
+__device__ __forceinline__ double gamma_k(const double *Q, const double *Pc, int k)
 {
     double s = 0.0;
+#pragma unroll
     for (int m = 0; m <= k; ++m) s += Q[m] * Pc[k - m];
     return s;
 }
 
 // 2D encounter probability -g_abs,bc / g_free with eq. smallTEabs:
 //   sqrt(tau/(R R0)) e^{-(R-1)(R0-1)/tau} [pi^{-1/2} + (1/2) sum gamma^abs_k T_k] / i0e(R R0/2tau).
-__device__ inline double penc2(const Params &P, double R, double R0)
+template <int NC> __device__ inline double penc2_n(const Params &P, double R, double R0)
 {
-    const int n = P.n_terms;
+    const int n = NC > 0 ? NC : P.n_terms;
     const double *a0 = P.g2c, *Qa = P.g2c + (MAXTERMS + 1);
-    double Pc[MAXTERMS + 1], T[MAXTERMS + 1];
-    p_series(a0, R, R0, n, Pc);
+    double Pc[Order<NC>::M + 1], T[Order<NC>::M + 1];
+    p_series<NC>(a0, R, R0, n, Pc);
     const double x = (R + R0 - 2.0) / (2.0 * P.sqrt_tau);
-    t_terms(x, 2.0 * P.sqrt_tau, n, T);
+    t_terms<NC>(x, 2.0 * P.sqrt_tau, n, T);
     double S = 1.0 / SQRTPI_D;
-    for (int k = 1; k <= n; ++k) S += 0.5 * gamma_k(Qa, Pc, k) * T[k];
+#pragma unroll
+    for (int k = 1; k <= Order<NC>::M; ++k) {
+        if (k > n) break;
+        S += 0.5 * gamma_k(Qa, Pc, k) * T[k];
+    }
     return sqrt(P.tau / (R * R0)) * exp(-(R - 1.0) * (R0 - 1.0) * P.inv_tau) * S / i0e_d(R * R0 * 0.5 * P.inv_tau);
 }
 
 // 2D reaction probability: free parts and the common factor cancel,
 //   sum (g^ref_k - g^rad_k) T_k / [4 pi^{-1/2} + sum (g^ref_k + g^abs_k) T_k].
-__device__ inline double preac2(const Params &P, double R, double R0)
+template <int NC> __device__ inline double preac2_n(const Params &P, double R, double R0)
 {
-    const int n = P.n_terms;
+    const int n = NC > 0 ? NC : P.n_terms;
     const double *a0 = P.g2c, *Qa = a0 + (MAXTERMS + 1), *Qf = a0 + 2 * (MAXTERMS + 1), *Qr = a0 + 3 * (MAXTERMS + 1);
-    double Pc[MAXTERMS + 1], T[MAXTERMS + 1];
-    p_series(a0, R, R0, n, Pc);
+    double Pc[Order<NC>::M + 1], T[Order<NC>::M + 1];
+    p_series<NC>(a0, R, R0, n, Pc);
     const double x = (R + R0 - 2.0) / (2.0 * P.sqrt_tau);
-    t_terms(x, 2.0 * P.sqrt_tau, n, T);
+    t_terms<NC>(x, 2.0 * P.sqrt_tau, n, T);
     double num = 0.0, den = 4.0 / SQRTPI_D;
-    for (int k = 1; k <= n; ++k) {
+#pragma unroll
+    for (int k = 1; k <= Order<NC>::M; ++k) {
+        if (k > n) break;
         const double gf = gamma_k(Qf, Pc, k);
         num += (gf - gamma_k(Qr, Pc, k)) * T[k];
         den += (gf + gamma_k(Qa, Pc, k)) * T[k];
@@ -147,24 +160,34 @@ __device__ inline double preac2(const Params &P, double R, double R0)
 }
 
 // The 2D propagator density over its leading term: 1 + (sqrt(pi)/4) sum (g^ref_k + g^abs_k) T_k.
-__device__ inline double corr2(const Params &P, double Rp, double R0)
+template <int NC> __device__ inline double corr2_n(const Params &P, double Rp, double R0)
 {
-    const int n = P.n_terms;
+    const int n = NC > 0 ? NC : P.n_terms;
     const double *a0 = P.g2c, *Qa = a0 + (MAXTERMS + 1), *Qf = a0 + 2 * (MAXTERMS + 1);
-    double Pc[MAXTERMS + 1], T[MAXTERMS + 1];
-    p_series(a0, Rp, R0, n, Pc);
+    double Pc[Order<NC>::M + 1], T[Order<NC>::M + 1];
+    p_series<NC>(a0, Rp, R0, n, Pc);
     const double x = (Rp + R0 - 2.0) / (2.0 * P.sqrt_tau);
-    t_terms(x, 2.0 * P.sqrt_tau, n, T);
+    t_terms<NC>(x, 2.0 * P.sqrt_tau, n, T);
     double s = 0.0;
-    for (int k = 1; k <= n; ++k) s += (gamma_k(Qf, Pc, k) + gamma_k(Qa, Pc, k)) * T[k];
+#pragma unroll
+    for (int k = 1; k <= Order<NC>::M; ++k) {
+        if (k > n) break;
+        s += (gamma_k(Qf, Pc, k) + gamma_k(Qa, Pc, k)) * T[k];
+    }
     return 1.0 + 0.25 * SQRTPI_D * s;
 }
 
-__device__ inline double reac_prob(const Params &P, int dim, double R, double R0)
+// The order NC (12, or 0 for any order) is a template parameter of the
+// kernels that evaluate the expansion, chosen on the host.
+template <int NC> __device__ inline double penc2(const Params &P, double R, double R0) { return penc2_n<NC>(P, R, R0); }
+template <int NC> __device__ inline double preac2(const Params &P, double R, double R0) { return preac2_n<NC>(P, R, R0); }
+template <int NC> __device__ inline double corr2(const Params &P, double Rp, double R0) { return corr2_n<NC>(P, Rp, R0); }
+
+template <int NC> __device__ inline double reac_prob(const Params &P, int dim, double R, double R0)
 {
     if (P.bc == 0) return 1.0;
     if (P.bc == 1) return 0.0;
-    return dim == 3 ? preac3(P, R, R0) : preac2(P, R, R0);
+    return dim == 3 ? preac3(P, R, R0) : preac2<NC>(P, R, R0);
 }
 
 // ---------------------------------------------------------------------------
@@ -235,7 +258,7 @@ template <int DIM> __device__ inline PropSetup prop_setup(const Params &P, doubl
 }
 
 // One attempt: the proposed R' and whether it is accepted.
-template <int DIM>
+template <int DIM, int NC>
 __device__ inline double prop_attempt(const Params &P, const PropSetup &S, double R0, u32 c0, u32 c1, u32 step, u32 tag, u32 k,
                                       bool *accepted, bool *hit)
 {
@@ -256,7 +279,7 @@ __device__ inline double prop_attempt(const Params &P, const PropSetup &S, doubl
     if (DIM == 3) {
         acc *= 1.0 - (SQRTPI_D * st) * erfcx(st + v / (2.0 * st));
     } else {
-        double corr = corr2(P, Rp, R0);
+        double corr = corr2<NC>(P, Rp, R0);
         if (corr > 1.0) {
             *hit = true;
             corr = 1.0;
@@ -272,7 +295,7 @@ __device__ inline double prop_attempt(const Params &P, const PropSetup &S, doubl
 // l, l + 64, ...; the first accepted attempt in order wins, exactly as if the
 // attempts were tried one after another.  Every lane of the wave must call it
 // with the same arguments; every lane gets the result.
-template <int DIM>
+template <int DIM, int NC>
 __device__ double sample_radius_wave(const Params &P, double R0, u32 c0, u32 c1, u32 step, u32 tag, u32 *attempts, u32 *hits)
 {
     const PropSetup S = prop_setup<DIM>(P, R0);
@@ -281,7 +304,7 @@ __device__ double sample_radius_wave(const Params &P, double R0, u32 c0, u32 c1,
     double Rp = 1.0;
     for (u32 k0 = 0; k0 < MAX_ATTEMPTS; k0 += 64) {
         bool ok, hit;
-        Rp = prop_attempt<DIM>(P, S, R0, c0, c1, step, tag, k0 + lane, &ok, &hit);
+        Rp = prop_attempt<DIM, NC>(P, S, R0, c0, c1, step, tag, k0 + lane, &ok, &hit);
         const u64 okm = __ballot(ok), hm = __ballot(hit);
         if (okm) {
             const int first = __ffsll((unsigned long long)okm) - 1;

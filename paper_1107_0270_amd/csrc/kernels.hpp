@@ -372,10 +372,10 @@ __device__ __forceinline__ float min_image_f(float xb, float xa, float L, float 
 // p_enc of a pair that does not overlap (R > 1, R0 >= 1) in the pair
 // arithmetic PM: binary64; binary32 from binary32 R and R0; or binary32
 // exponentials of binary64 exponent arguments.  The 2D expansion is binary64.
-template <int DIM, int PM> __device__ __forceinline__ double penc_R(const Params &P, double R, double R0)
+template <int DIM, int PM, int NC> __device__ __forceinline__ double penc_R(const Params &P, double R, double R0)
 {
 #pragma clang fp contract(off)
-    if (DIM == 2) return penc2(P, R, R0);
+    if (DIM == 2) return penc2<NC>(P, R, R0);
     if (PM == PM_F32) {
         const float Rf = (float)R, R0f = (float)R0;
         return penc3_args((Rf - 1.0f) * (R0f - 1.0f) * P.inv_tauf, (Rf + R0f - 1.0f) * P.inv_tauf, Rf * R0f * P.inv_tauf);
@@ -384,7 +384,7 @@ template <int DIM, int PM> __device__ __forceinline__ double penc_R(const Params
     return PM == PM_F64 ? penc3_args(e1, e2, e3) : (double)penc3_args((float)e1, (float)e2, (float)e3);
 }
 
-template <int DIM, class T, int PM>
+template <int DIM, class T, int PM, int NC>
 __device__ inline PairQ pair_quantities(const Params &P, const Rec<T> &ra, const Rec<T> &rb, u32 sa, u32 sb,
                                         const double dA[3], u32 step)
 {
@@ -418,7 +418,7 @@ __device__ inline PairQ pair_quantities(const Params &P, const Rec<T> &ra, const
             q.R0d = R0;
         }
         q.overlap = Rf <= 1.0f;
-        q.p = q.overlap ? 1.0 : penc_R<DIM, PM>(P, (double)Rf, (double)R0f);
+        q.p = q.overlap ? 1.0 : penc_R<DIM, PM, NC>(P, (double)Rf, (double)R0f);
     } else {
         double rv[3] = {0.0, 0.0, 0.0}, r2 = 0.0, r02 = 0.0;
         const double xa[3] = {(double)ra.x, (double)ra.y, (double)ra.z};
@@ -438,7 +438,7 @@ __device__ inline PairQ pair_quantities(const Params &P, const Rec<T> &ra, const
         q.R0 = R0;
         q.R0d = R0;
         q.overlap = R <= 1.0;
-        q.p = q.overlap ? 1.0 : penc_R<DIM, PM>(P, R, R0);
+        q.p = q.overlap ? 1.0 : penc_R<DIM, PM, NC>(P, R, R0);
     }
     q.draw = philox(sa, sb, step, TAG_ENC, P.key).x;
     q.cand = q.overlap || below(q.draw, q.p);
@@ -935,7 +935,7 @@ __device__ __forceinline__ u32 chain_push(u64 *head, u32 rec_idx, u32 entry, u32
     return (prev >> 32) == (u64)(step + 1u) ? (u32)prev : NOSLOT;
 }
 
-template <int DIM, class T, int PM>
+template <int DIM, class T, int PM, int NC>
 __global__ __launch_bounds__(BLOCK) void k_pair_eval(Params P, const Rec<T> *__restrict__ rec, const PairEnt *__restrict__ list,
                                                       CandEnt *__restrict__ cand, u32 *__restrict__ flag, u64 *__restrict__ headA,
                                                       u32 *__restrict__ nextA, Counters *C, DbgPair *dbg)
@@ -950,7 +950,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair_eval(Params P, const Rec<T> *__r
         const u32 sa = meta_slot(rec_meta(ra)), sb = meta_slot(rec_meta(rb));
         double dA[3];
         displacement<DIM, T>(P, sa, SP_A, step, dA);
-        const PairQ q = pair_quantities<DIM, T, PM>(P, ra, rb, sa, sb, dA, step);
+        const PairQ q = pair_quantities<DIM, T, PM, NC>(P, ra, rb, sa, sb, dA, step);
         st[0] += 1;
         st[1] += q.cand;
         st[2] += q.overlap;
@@ -1152,7 +1152,7 @@ __global__ void k_close(Counters *C)
 //    along a uniform direction around the old C, B into the reserved slot.
 // All lanes compute the same values; lane 0 writes.
 // ---------------------------------------------------------------------------
-template <int DIM, class T>
+template <int DIM, class T, int NC>
 __device__ __noinline__ void ev_match(const Params &P, Rec<T> *__restrict__ rec, u32 ia, u32 ib, double R0, u32 *__restrict__ partner,
                                       u32 step, Counters *C, DbgMatch *dbg)
 {
@@ -1173,8 +1173,8 @@ __device__ __noinline__ void ev_match(const Params &P, Rec<T> *__restrict__ rec,
     if (P.bc == 0) {
         react = true;
     } else {
-        Rpp = sample_radius_wave<DIM>(P, R0, sa, sb, step, TAG_PROP, &att, &hits);
-        preac = reac_prob(P, DIM, Rpp, R0);
+        Rpp = sample_radius_wave<DIM, NC>(P, R0, sa, sb, step, TAG_PROP, &att, &hits);
+        preac = reac_prob<NC>(P, DIM, Rpp, R0);
         const u32 w = philox(sa, sb, step, TAG_REAC, P.key).x;
         react = below(w, preac);
         near = fabs(u01(w) - preac) < 1e-6;
@@ -1219,7 +1219,7 @@ __device__ __noinline__ void ev_match(const Params &P, Rec<T> *__restrict__ rec,
     }
 }
 
-template <int DIM, class T>
+template <int DIM, class T, int NC>
 __device__ __noinline__ void ev_decay(const Params &P, Rec<T> *__restrict__ rec, u32 i, u32 *__restrict__ partner, u32 step,
                                 Counters *C, DbgDiss *dbg)
 {
@@ -1227,8 +1227,8 @@ __device__ __noinline__ void ev_decay(const Params &P, Rec<T> *__restrict__ rec,
     const Rec<T> rc = rec[i];
     const u32 sc = meta_slot(rec_meta(rc));
     u32 att = 0, hits = 0;
-    const double Rpp = sample_radius_wave<DIM>(P, 1.0, sc, NOSLOT, step, TAG_DPROP, &att, &hits);
-    const double preac = reac_prob(P, DIM, Rpp, 1.0);
+    const double Rpp = sample_radius_wave<DIM, NC>(P, 1.0, sc, NOSLOT, step, TAG_DPROP, &att, &hits);
+    const double preac = reac_prob<NC>(P, DIM, Rpp, 1.0);
     const bool gem = below(philox(sc, NOSLOT, step, TAG_GEM, P.key).x, preac);
     const u32 sb = partner[sc];
     if (lane_id() == 0) {
@@ -1282,7 +1282,7 @@ __device__ __noinline__ void ev_decay(const Params &P, Rec<T> *__restrict__ rec,
 // kinds needs more registers than a wave has and spills.  They read the
 // parameters from a device-resident copy (a by-value kernel argument would be
 // copied to per-lane scratch to be passed by reference).
-template <int DIM, class T>
+template <int DIM, class T, int NC>
 __global__ __launch_bounds__(BLOCK) void k_events(const Params *__restrict__ Pd, Rec<T> *__restrict__ rec,
                                                    const PairEnt *__restrict__ list, const CandEnt *__restrict__ cand,
                                                    const u32 *__restrict__ ev, u32 *__restrict__ partner, Counters *C,
@@ -1294,8 +1294,8 @@ __global__ __launch_bounds__(BLOCK) void k_events(const Params *__restrict__ Pd,
     const u32 wave = (blockIdx.x * BLOCK + threadIdx.x) >> 6, nwaves = (gridDim.x * BLOCK) >> 6;
     for (u32 w = wave; w < n; w += nwaves) {
         const u32 e = ev[w];
-        if (e & EV_DECAY) ev_decay<DIM, T>(P, rec, e & ~EV_DECAY, partner, step, C, dbg_d);
-        else ev_match<DIM, T>(P, rec, list[e].a_idx, list[e].b_idx, cand[e].R0, partner, step, C, dbg_m);
+        if (e & EV_DECAY) ev_decay<DIM, T, NC>(P, rec, e & ~EV_DECAY, partner, step, C, dbg_d);
+        else ev_match<DIM, T, NC>(P, rec, list[e].a_idx, list[e].b_idx, cand[e].R0, partner, step, C, dbg_m);
     }
 }
 
@@ -1303,14 +1303,14 @@ __global__ __launch_bounds__(BLOCK) void k_events(const Params *__restrict__ Pd,
 // p_enc and p_reac of caller-given (R, R0) pairs with the step's own device
 // functions (overlap rule included), one thread per pair.
 // ---------------------------------------------------------------------------
-template <int DIM, int PM>
+template <int DIM, int PM, int NC>
 __global__ __launch_bounds__(BLOCK) void k_eval_probs(Params P, uint64_t n, const double *__restrict__ R, const double *__restrict__ R0,
                                                        double *__restrict__ penc, double *__restrict__ preac)
 {
     for (uint64_t i = gtid(); i < n; i += gstride()) {
         const double r = R[i], r0 = R0[i];
-        if (penc) penc[i] = r <= 1.0 ? 1.0 : penc_R<DIM, PM>(P, r, r0);
-        if (preac) preac[i] = reac_prob(P, DIM, r, r0);
+        if (penc) penc[i] = r <= 1.0 ? 1.0 : penc_R<DIM, PM, NC>(P, r, r0);
+        if (preac) preac[i] = reac_prob<NC>(P, DIM, r, r0);
     }
 }
 

@@ -112,6 +112,16 @@ def test_mem2d_small_tau(prec, p_tol, pair_search):
     assert rep.reactions > 0
 
 
+def test_mem2d_runtime_order():
+    # the 2D step at an expansion order with no compiled form (10): the run-time-order kernels
+    n = 3000
+    sp, pos = _state(n, n, 1.5, 2, 0.005, 12, False)
+    gpu, orc = make_pair(dim=2, bc=O.BC_RAD, box=1.5, dt=5e-6, D=(0.1, 0.1, 0.05), sigma=0.005, kappa=0.05,
+                         k_off=2000.0, precision=S.PREC_FP64, species=sp, pos=pos, seed=13, n_terms=10)
+    rep = run(gpu, orc, 8, p_tol=1e-12, pos_tol=1e-12, box=1.5)
+    _check(rep, p_tol=1e-12)
+
+
 def test_mem2d_as_written_tau_0p8():
     # the membrane workload's dt = 100 us (tau = 0.8): same arithmetic on both sides
     n = 4000
