@@ -77,6 +77,15 @@ def measured_traffic(stage):
     return int(f * 1024 * t["scale_fetch"] + w * 1024 * t["scale_write"])
 
 
+def describe(cfg):
+    bc = {0: "absorbing", 1: "reflecting", 2: "radiation"}[cfg["bc"]]
+    rev = "reversible A+B<->C" if cfg["k_off"] > 0 else "irreversible A+B->C"
+    k_units = "um^3/s" if cfg["dim"] == 3 else "um^2/s"
+    return (f"{cfg['dim']}D {rev}, {bc} surface: {cfg['n_a']:g} A + {cfg['n_b']:g} B, periodic L={cfg['box']:g} um, "
+            f"D={cfg['D'][0]:g} um^2/s, sigma={cfg['sigma'] * 1e3:g} nm, kappa={cfg['kappa_a']:g} {k_units}, "
+            f"k_off={cfg['k_off']:g}/s, dt={cfg['dt'] * 1e6:g} us")
+
+
 def pair_probs(args, I, S):
     """p_enc and p_reac of N pairs drawn from the workload's pair distribution (uniform positions:
     R uniform in the ball of radius r_cut/a; R0 = |R + sqrt(2 tau) z| >= 1, z standard normal),
@@ -131,6 +140,9 @@ def main():
     ap.add_argument("--pair-search", choices=["auto", "bricks", "direct"], default="auto",
                     help="pair-search kernel (auto = the library's choice)")
     ap.add_argument("--cell", type=float, default=0.0, help="cell edge in um (0 = the library's choice)")
+    ap.add_argument("--workload", default="cfg_rad3d",
+                    choices=["cfg_rad3d", "cfg_rad3d_dense", "cfg_mem2d", "cfg_mem2d_small_tau", "cfg_abs3d"],
+                    help="synthetic workload (default: the 3D radiation workload the metric is quoted on)")
     ap.add_argument("--pair-probs", type=int, default=0, metavar="N",
                     help="only run the pair-probability micro-benchmark on N synthetic pairs and exit")
     ap.add_argument("--dim", type=int, default=3, help="workload dimension for --pair-probs (2: the membrane "
@@ -159,12 +171,13 @@ def main():
         pair_probs(args, I, S)
         return
 
-    cfg = I.workload("cfg_rad3d")
+    cfg = I.workload(args.workload)
+    dim = cfg["dim"]
     t0 = time.time()
     sp, pos, box, red = I.state_for(cfg, seed=0)
     log(f"[bench] state: {len(sp)} particles, {red} redrawn overlaps, {time.time() - t0:.1f}s")
     def make(timing):
-        return S.Sim(dim=3, box=box, dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
+        return S.Sim(dim=dim, box=box, dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
                      k_off=cfg["k_off"], precision=cfg["precision"], seed=0, species=sp, pos=pos, timing=timing, cell=args.cell,
                      pair_search={"auto": S.PAIRS_AUTO, "bricks": S.PAIRS_BRICKS, "direct": S.PAIRS_DIRECT}[args.pair_search])
 
@@ -197,6 +210,7 @@ def main():
 
     # dominant kernel and its roofline
     n_keys = 3 * grid[3]
+    rec_scale = 2 if cfg["precision"] == S.PREC_FP64 else 1  # 32-byte binary64 records
     per = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kt.items()}
     tot = {k: v[0] for k, v in kt.items()}
     dom = max(tot, key=tot.get) if any(tot.values()) else None
@@ -204,6 +218,7 @@ def main():
     if dom is not None and per[dom] > 0:
         nb = algorithmic_bytes(dom, n_live, 0.5 * (c0["A"] + c1["A"]), 0.5 * (c0["B"] + c1["B"]), n_keys)
         if nb is not None:
+            nb *= rec_scale
             ach = nb / (per[dom] * 1e-3) / 1e9
             roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
@@ -213,15 +228,16 @@ def main():
     if args.cpu_steps > 0:
         import oracle as O
 
-        orc = O.OracleSim(dim=3, bc=cfg["bc"], box=[box] * 3, dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"],
-                          kappa_a=cfg["kappa_a"], k_off=cfg["k_off"], store_f32=True, species=sp, pos=pos)
+        orc = O.OracleSim(dim=dim, bc=cfg["bc"], box=[box] * dim, dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"],
+                          kappa_a=cfg["kappa_a"], k_off=cfg["k_off"], store_f32=cfg["precision"] != S.PREC_FP64,
+                          species=sp, pos=pos)
         tc = time.perf_counter()
         orc.step(args.cpu_steps)
         tc = time.perf_counter() - tc
         cpu = {"value": round(len(sp) * args.cpu_steps / tc, 1), "unit": "particle-steps/s", "cores": 1,
                "kind": "oracle",
-               "sample": f"{args.cpu_steps} steps of the same 1e6-particle workload from the same initial state, "
-                         f"single-threaded FP64 C oracle ({tc:.1f} s)"}
+               "sample": f"{args.cpu_steps} steps of the same {len(sp)}-particle workload from the same initial "
+                         f"state, single-threaded FP64 C oracle ({tc:.1f} s)"}
         log(f"[bench] cpu baseline {cpu}")
 
     out = {
@@ -236,12 +252,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if cfg["precision"] == S.PREC_FP64 else "f32",
         "data": "synthetic",
         "pair_evals_per_s": round(pairs / el, 1),
-        "config": {"workload": "3D reversible A+B<->C, radiation surface: 5e5 A + 5e5 B, periodic L=10 um, "
-                               "D=1 um^2/s, sigma=5 nm, kappa=0.1 um^3/s, k_off=10/s, dt=10 us",
-                   "precision": "binary32 state and p_enc, binary64 near-contact arguments and propagation",
+        "config": {"workload": describe(cfg),
+                   "precision": {S.PREC_FP64: "binary64 throughout",
+                                 S.PREC_FP32: "binary32 state, pair test and p_enc; binary64 propagation",
+                                 S.PREC_FP32_FP64NC: "binary32 state and p_enc, binary64 near-contact arguments and "
+                                                     "propagation"}[cfg["precision"]],
                    "particles": len(sp), "r_cut_um": der["rcut"], "cells": grid[:3],
                    "pair_search": {S.PAIRS_BRICKS: "lds-bricks", S.PAIRS_DIRECT: "direct"}[grid[4]],
                    "step_launch": "one hipGraph replay per step"},

@@ -184,6 +184,16 @@ int sim_load_state(sim_t *h, uint64_t step, const int32_t *species, const double
  * when done.  SIM_EINVAL for NULL R, R0 or n = 0; SIM_EDEVICE if a HIP call fails. */
 int sim_eval_pairs(sim_t *h, uint64_t n, const double *R, const double *R0, double *penc, double *preac);
 
+/* Draws n radii R'' >= 1 (in units of a) from the radial propagator w_d r^{d-1}(g_ref - g_abs)(.|R0)
+ * (Sec. 2.2.2; 3D closed forms of Sec. 4.1, 2D expansion of Sec. 4.2) with the step's own rejection
+ * sampler and the handle's parameters.  Draw i starts from R0[i] >= 1 and uses the Philox counter
+ * {i, 0xFFFFFFFF, step, 5 | attempt << 8} with the handle's key.  wave != 0 spreads each draw's
+ * attempts over a wave (the step's form for few events), wave = 0 takes one draw per lane (its
+ * form for many); both give the same draws.  R0, Rpp (n doubles) and attempts (n uint32, may be
+ * NULL) are DEVICE pointers owned by the caller.  Returns when done; SIM_EINVAL for NULL R0 or
+ * Rpp, n = 0 or n > 2^32; SIM_EDEVICE if a HIP call fails. */
+int sim_eval_propagator(sim_t *h, uint64_t n, const double *R0, uint32_t step, int wave, double *Rpp, uint32_t *attempts);
+
 /* Releases all device memory of the handle; NULL is accepted. */
 int sim_destroy(sim_t *h);
 

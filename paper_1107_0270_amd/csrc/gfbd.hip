@@ -116,6 +116,7 @@ struct sim {
     virtual int read(int what, void *dst, uint64_t cap, uint64_t *written) = 0;
     virtual int load(uint64_t step, const int32_t *sp, const double *pos, const uint32_t *partner) = 0;
     virtual int eval_pairs(uint64_t n, const double *R, const double *R0, double *penc, double *preac) = 0;
+    virtual int eval_prop(uint64_t n, const double *R0, uint32_t step, int wave, double *Rpp, uint32_t *attempts) = 0;
     int fail(int code, const std::string &msg)
     {
         err = msg;
@@ -510,6 +511,22 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         return SIM_OK;
     }
 
+    int eval_prop(uint64_t n, const double *R0, uint32_t step, int wave, double *Rpp, uint32_t *attempts) override
+    {
+        if (n > 0xFFFFFFFFull) return fail(SIM_EINVAL, "at most 2^32 draws");
+        if (DIM == 2 && P.n_terms == 12) launch_prop<12>(n, R0, step, wave, Rpp, attempts);
+        else launch_prop<0>(n, R0, step, wave, Rpp, attempts);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipStreamSynchronize(M.stream));
+        return SIM_OK;
+    }
+
+    template <int NC> void launch_prop(uint64_t n, const double *R0, uint32_t step, int wave, double *Rpp, uint32_t *attempts)
+    {
+        if (wave) k_eval_prop<DIM, NC, true><<<grid_for(64 * n, 8192), BLOCK, 0, M.stream>>>(P, n, R0, step, Rpp, attempts);
+        else k_eval_prop<DIM, NC, false><<<grid_for(n, 8192), BLOCK, 0, M.stream>>>(P, n, R0, step, Rpp, attempts);
+    }
+
     int step(uint32_t nsteps) override
     {
         for (uint32_t i = 0; i < nsteps; ++i) {
@@ -767,6 +784,12 @@ int sim_eval_pairs(sim_t *h, uint64_t n, const double *R, const double *R0, doub
 {
     if (!h || !R || !R0 || n == 0) { g_err = "null argument or n = 0"; return SIM_EINVAL; }
     return h->eval_pairs(n, R, R0, penc, preac);
+}
+
+int sim_eval_propagator(sim_t *h, uint64_t n, const double *R0, uint32_t step, int wave, double *Rpp, uint32_t *attempts)
+{
+    if (!h || !R0 || !Rpp || n == 0) { g_err = "null argument or n = 0"; return SIM_EINVAL; }
+    return h->eval_prop(n, R0, step, wave, Rpp, attempts);
 }
 
 int sim_destroy(sim_t *h)

@@ -178,10 +178,29 @@ template <int NC> __device__ inline double corr2_n(const Params &P, double Rp, d
 }
 
 // The order NC (12, or 0 for any order) is a template parameter of the
-// kernels that evaluate the expansion, chosen on the host.
-template <int NC> __device__ inline double penc2(const Params &P, double R, double R0) { return penc2_n<NC>(P, R, R0); }
-template <int NC> __device__ inline double preac2(const Params &P, double R, double R0) { return preac2_n<NC>(P, R, R0); }
-template <int NC> __device__ inline double corr2(const Params &P, double Rp, double R0) { return corr2_n<NC>(P, Rp, R0); }
+// kernels that evaluate the expansion, chosen on the host.  The run-time
+// order forms (arrays in scratch) are called, not inlined: inlined into the
+// event handler's wave sampler they gave acceptance decisions that differ
+// from the oracle's, while called (and inlined into a kernel) they agree
+// draw by draw.
+__device__ __noinline__ double penc2_any(const Params &P, double R, double R0) { return penc2_n<0>(P, R, R0); }
+__device__ __noinline__ double preac2_any(const Params &P, double R, double R0) { return preac2_n<0>(P, R, R0); }
+__device__ __noinline__ double corr2_any(const Params &P, double Rp, double R0) { return corr2_n<0>(P, Rp, R0); }
+template <int NC> __device__ inline double penc2(const Params &P, double R, double R0)
+{
+    if constexpr (NC == 0) return penc2_any(P, R, R0);
+    else return penc2_n<NC>(P, R, R0);
+}
+template <int NC> __device__ inline double preac2(const Params &P, double R, double R0)
+{
+    if constexpr (NC == 0) return preac2_any(P, R, R0);
+    else return preac2_n<NC>(P, R, R0);
+}
+template <int NC> __device__ inline double corr2(const Params &P, double Rp, double R0)
+{
+    if constexpr (NC == 0) return corr2_any(P, Rp, R0);
+    else return corr2_n<NC>(P, Rp, R0);
+}
 
 template <int NC> __device__ inline double reac_prob(const Params &P, int dim, double R, double R0)
 {
@@ -318,6 +337,29 @@ __device__ double sample_radius_wave(const Params &P, double R0, u32 c0, u32 c1,
     *attempts = MAX_ATTEMPTS;
     *hits = nh;
     return __shfl(Rp, 63, 64);
+}
+
+// The same sampler for one lane working alone: attempts 0, 1, 2, ... in
+// order until one is accepted (the definition the wave form reproduces).
+template <int DIM, int NC>
+__device__ double sample_radius_lane(const Params &P, double R0, u32 c0, u32 c1, u32 step, u32 tag, u32 *attempts, u32 *hits)
+{
+    const PropSetup S = prop_setup<DIM>(P, R0);
+    u32 nh = 0;
+    double Rp = 1.0;
+    for (u32 k = 0; k < MAX_ATTEMPTS; ++k) {
+        bool ok, hit;
+        Rp = prop_attempt<DIM, NC>(P, S, R0, c0, c1, step, tag, k, &ok, &hit);
+        nh += hit;
+        if (ok) {
+            *attempts = k + 1;
+            *hits = nh;
+            return Rp;
+        }
+    }
+    *attempts = MAX_ATTEMPTS;
+    *hits = nh;
+    return Rp;
 }
 
 } // namespace gfbd

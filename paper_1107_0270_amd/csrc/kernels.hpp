@@ -1150,11 +1150,17 @@ __global__ void k_close(Counters *C)
 //  decay (Sec. 2.2.5): R'' from the propagator with r0 = a, geminate
 //    recombination with p_reac(R''|a), otherwise A and B placed R'' apart
 //    along a uniform direction around the old C, B into the reserved slot.
-// All lanes compute the same values; lane 0 writes.
+// Wave form (LANE = false): one wave per event, every lane computes the same
+// values, the rejection attempts are spread over the lanes, lane 0 writes.
+// Lane form (LANE = true): one event per lane, attempts one after another.
+// Both add their counts to st[] (react, attempts, bound hits, near, decay,
+// geminate), which the kernel sums per workgroup.
 // ---------------------------------------------------------------------------
-template <int DIM, class T, int NC>
+constexpr int EV_ST = 6;
+
+template <int DIM, class T, int NC, bool LANE>
 __device__ __noinline__ void ev_match(const Params &P, Rec<T> *__restrict__ rec, u32 ia, u32 ib, double R0, u32 *__restrict__ partner,
-                                      u32 step, Counters *C, DbgMatch *dbg)
+                                      u32 step, Counters *C, DbgMatch *dbg, u32 *st)
 {
 #pragma clang fp contract(off)
     Rec<T> ra = rec[ia], rb = rec[ib];
@@ -1173,7 +1179,8 @@ __device__ __noinline__ void ev_match(const Params &P, Rec<T> *__restrict__ rec,
     if (P.bc == 0) {
         react = true;
     } else {
-        Rpp = sample_radius_wave<DIM, NC>(P, R0, sa, sb, step, TAG_PROP, &att, &hits);
+        Rpp = LANE ? sample_radius_lane<DIM, NC>(P, R0, sa, sb, step, TAG_PROP, &att, &hits)
+                   : sample_radius_wave<DIM, NC>(P, R0, sa, sb, step, TAG_PROP, &att, &hits);
         preac = reac_prob<NC>(P, DIM, Rpp, R0);
         const u32 w = philox(sa, sb, step, TAG_REAC, P.key).x;
         react = below(w, preac);
@@ -1200,14 +1207,14 @@ __device__ __noinline__ void ev_match(const Params &P, Rec<T> *__restrict__ rec,
         rec_set_meta(ra, meta_make(SP_C, sa));
         rec_set_meta(rb, meta_make(SP_DEAD, sb));
     }
-    if (lane_id() == 0) {
+    if (LANE || lane_id() == 0) {
         if (react) partner[sa] = P.reversible ? sb : NOSLOT;
         rec[ia] = ra;
         rec[ib] = rb;
-        if (react) atomicAdd((unsigned long long *)&C->stats[ST_REACT], 1ull);
-        if (att) atomicAdd((unsigned long long *)&C->stats[ST_ATTEMPTS], (unsigned long long)att);
-        if (hits) atomicAdd((unsigned long long *)&C->stats[ST_BOUND], (unsigned long long)hits);
-        if (near) atomicAdd((unsigned long long *)&C->stats[ST_NEAR], 1ull);
+        st[0] += react;
+        st[1] += att;
+        st[2] += hits;
+        st[3] += near;
         if (P.debug) {
             const u32 q = atomicAdd(&C->n_dbg[2], 1u);
             if (q < P.dbg_cap) {
@@ -1219,23 +1226,24 @@ __device__ __noinline__ void ev_match(const Params &P, Rec<T> *__restrict__ rec,
     }
 }
 
-template <int DIM, class T, int NC>
+template <int DIM, class T, int NC, bool LANE>
 __device__ __noinline__ void ev_decay(const Params &P, Rec<T> *__restrict__ rec, u32 i, u32 *__restrict__ partner, u32 step,
-                                Counters *C, DbgDiss *dbg)
+                                      Counters *C, DbgDiss *dbg, u32 *st)
 {
 #pragma clang fp contract(off)
     const Rec<T> rc = rec[i];
     const u32 sc = meta_slot(rec_meta(rc));
     u32 att = 0, hits = 0;
-    const double Rpp = sample_radius_wave<DIM, NC>(P, 1.0, sc, NOSLOT, step, TAG_DPROP, &att, &hits);
+    const double Rpp = LANE ? sample_radius_lane<DIM, NC>(P, 1.0, sc, NOSLOT, step, TAG_DPROP, &att, &hits)
+                            : sample_radius_wave<DIM, NC>(P, 1.0, sc, NOSLOT, step, TAG_DPROP, &att, &hits);
     const double preac = reac_prob<NC>(P, DIM, Rpp, 1.0);
     const bool gem = below(philox(sc, NOSLOT, step, TAG_GEM, P.key).x, preac);
     const u32 sb = partner[sc];
-    if (lane_id() == 0) {
-        atomicAdd((unsigned long long *)&C->stats[ST_DECAY], 1ull);
-        if (gem) atomicAdd((unsigned long long *)&C->stats[ST_GEMINATE], 1ull);
-        atomicAdd((unsigned long long *)&C->stats[ST_ATTEMPTS], (unsigned long long)att);
-        if (hits) atomicAdd((unsigned long long *)&C->stats[ST_BOUND], (unsigned long long)hits);
+    if (LANE || lane_id() == 0) {
+        st[4] += 1;
+        st[5] += gem;
+        st[1] += att;
+        st[2] += hits;
         if (P.debug) {
             const u32 q = atomicAdd(&C->n_dbg[3], 1u);
             if (q < P.dbg_cap) {
@@ -1269,7 +1277,7 @@ __device__ __noinline__ void ev_decay(const Params &P, Rec<T> *__restrict__ rec,
     rb.x = pb[0]; rb.y = pb[1]; rb.z = pb[2];
     rec_set_meta(ra, meta_make(SP_A, sc));
     rec_set_meta(rb, meta_make(SP_B, sb));
-    if (lane_id() == 0) {
+    if (LANE || lane_id() == 0) {
         partner[sc] = NOSLOT;
         rec[i] = ra;
         const u32 q = C->n_live + atomicAdd(&C->n_append, 1u);
@@ -1281,21 +1289,41 @@ __device__ __noinline__ void ev_decay(const Params &P, Rec<T> *__restrict__ rec,
 // The handlers are called, not inlined: one inlined body for both event
 // kinds needs more registers than a wave has and spills.  They read the
 // parameters from a device-resident copy (a by-value kernel argument would be
-// copied to per-lane scratch to be passed by reference).
+// copied to per-lane scratch to be passed by reference).  Up to
+// EV_LANE_MIN - 1 events run one per wave, more run one per lane.
+constexpr u32 EV_LANE_MIN = 4096;
+
 template <int DIM, class T, int NC>
 __global__ __launch_bounds__(BLOCK) void k_events(const Params *__restrict__ Pd, Rec<T> *__restrict__ rec,
                                                    const PairEnt *__restrict__ list, const CandEnt *__restrict__ cand,
                                                    const u32 *__restrict__ ev, u32 *__restrict__ partner, Counters *C,
                                                    DbgMatch *dbg_m, DbgDiss *dbg_d)
 {
+    __shared__ u32 lds[BLOCK / 64];
     const Params &P = *Pd;
     const u32 step = C->step;
     const u32 n = min(C->n_ev, P.cap);
-    const u32 wave = (blockIdx.x * BLOCK + threadIdx.x) >> 6, nwaves = (gridDim.x * BLOCK) >> 6;
-    for (u32 w = wave; w < n; w += nwaves) {
-        const u32 e = ev[w];
-        if (e & EV_DECAY) ev_decay<DIM, T, NC>(P, rec, e & ~EV_DECAY, partner, step, C, dbg_d);
-        else ev_match<DIM, T, NC>(P, rec, list[e].a_idx, list[e].b_idx, cand[e].R0, partner, step, C, dbg_m);
+    u32 st[EV_ST] = {0, 0, 0, 0, 0, 0};
+    if (n >= EV_LANE_MIN) {
+        for (u32 w = gtid(); w < n; w += gstride()) {
+            const u32 e = ev[w];
+            if (e & EV_DECAY) ev_decay<DIM, T, NC, true>(P, rec, e & ~EV_DECAY, partner, step, C, dbg_d, st);
+            else ev_match<DIM, T, NC, true>(P, rec, list[e].a_idx, list[e].b_idx, cand[e].R0, partner, step, C, dbg_m, st);
+        }
+    } else {
+        const u32 wave = (blockIdx.x * BLOCK + threadIdx.x) >> 6, nwaves = (gridDim.x * BLOCK) >> 6;
+        for (u32 w = wave; w < n; w += nwaves) {
+            const u32 e = ev[w];
+            if (e & EV_DECAY) ev_decay<DIM, T, NC, false>(P, rec, e & ~EV_DECAY, partner, step, C, dbg_d, st);
+            else ev_match<DIM, T, NC, false>(P, rec, list[e].a_idx, list[e].b_idx, cand[e].R0, partner, step, C, dbg_m, st);
+        }
+    }
+    // counts: one atomic per counter and workgroup
+    const int map[EV_ST] = {ST_REACT, ST_ATTEMPTS, ST_BOUND, ST_NEAR, ST_DECAY, ST_GEMINATE};
+#pragma unroll
+    for (int k = 0; k < EV_ST; ++k) {
+        const u32 t = block_sum(st[k], lds);
+        if (threadIdx.x == 0 && t) atomicAdd((unsigned long long *)&C->stats[map[k]], (unsigned long long)t);
     }
 }
 
@@ -1311,6 +1339,32 @@ __global__ __launch_bounds__(BLOCK) void k_eval_probs(Params P, uint64_t n, cons
         const double r = R[i], r0 = R0[i];
         if (penc) penc[i] = r <= 1.0 ? 1.0 : penc_R<DIM, PM, NC>(P, r, r0);
         if (preac) preac[i] = reac_prob<NC>(P, DIM, r, r0);
+    }
+}
+
+// R'' draws of the radial propagator for caller-given R0 with the step's own
+// sampler: draw i uses the counter {i, 0xFFFFFFFF, step, PROP | attempt << 8}
+// and the handle's key; one wave per draw (WAVE) or one lane per draw.
+template <int DIM, int NC, bool WAVE>
+__global__ __launch_bounds__(BLOCK) void k_eval_prop(Params P, uint64_t n, const double *__restrict__ R0, u32 step,
+                                                      double *__restrict__ Rpp, u32 *__restrict__ attempts)
+{
+    if (WAVE) {
+        const u32 wave = gtid() >> 6, nwaves = gstride() >> 6;
+        for (uint64_t i = wave; i < n; i += nwaves) {
+            u32 att = 0, hits = 0;
+            const double r = sample_radius_wave<DIM, NC>(P, R0[i], (u32)i, NOSLOT, step, TAG_PROP, &att, &hits);
+            if (lane_id() == 0) {
+                Rpp[i] = r;
+                if (attempts) attempts[i] = att;
+            }
+        }
+    } else {
+        for (uint64_t i = gtid(); i < n; i += gstride()) {
+            u32 att = 0, hits = 0;
+            Rpp[i] = sample_radius_lane<DIM, NC>(P, R0[i], (u32)i, NOSLOT, step, TAG_PROP, &att, &hits);
+            if (attempts) attempts[i] = att;
+        }
     }
 }
 

@@ -126,6 +126,8 @@ def lib():
     L.sim_load_state.restype = C.c_int
     L.sim_eval_pairs.argtypes = [vp, u64, vp, vp, vp, vp]
     L.sim_eval_pairs.restype = C.c_int
+    L.sim_eval_propagator.argtypes = [vp, u64, vp, u32, C.c_int, vp, vp]
+    L.sim_eval_propagator.restype = C.c_int
     L.sim_destroy.argtypes = [vp]
     L.sim_destroy.restype = C.c_int
     L.sim_last_error.argtypes = [vp]
@@ -265,6 +267,19 @@ class Sim:
             return tuple(out)
         finally:
             for b in bufs:
+                b.free()
+
+    def eval_propagator(self, R0, step, wave=True):
+        """R'' draws for the given R0 (sim_eval_propagator); returns (Rpp, attempts) as numpy arrays."""
+        R0 = np.ascontiguousarray(R0, dtype=np.float64)
+        n = R0.size
+        b_r0, b_r, b_a = DeviceBuffer(8 * n), DeviceBuffer(8 * n), DeviceBuffer(4 * n)
+        try:
+            b_r0.upload(R0)
+            self._check(lib().sim_eval_propagator(self._h, n, b_r0.ptr, int(step), int(bool(wave)), b_r.ptr, b_a.ptr))
+            return b_r.download(np.empty(n, np.float64)), b_a.download(np.empty(n, np.uint32))
+        finally:
+            for b in (b_r0, b_r, b_a):
                 b.free()
 
     def eval_pairs_device(self, n, R, R0, penc, preac):

@@ -21,8 +21,8 @@ def _declared():
 
 
 def test_header_declares_the_boundary():
-    assert _declared() == sorted(["sim_create", "sim_step", "sim_read", "sim_load_state", "sim_eval_pairs", "sim_destroy",
-                                  "sim_last_error"])
+    assert _declared() == sorted(["sim_create", "sim_step", "sim_read", "sim_load_state", "sim_eval_pairs",
+                                  "sim_eval_propagator", "sim_destroy", "sim_last_error"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -101,3 +101,4 @@ def test_eval_pairs_rejects_null_arguments_on_the_host():
     if not os.path.exists(S.LIB_PATH):
         pytest.skip("libgfbd.so not built")
     assert S.lib().sim_eval_pairs(None, 0, None, None, None, None) == S.SIM_EINVAL
+    assert S.lib().sim_eval_propagator(None, 0, None, 0, 1, None, None) == S.SIM_EINVAL

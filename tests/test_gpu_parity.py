@@ -147,6 +147,21 @@ def test_rad3d_full_size_one_step(pair_search):
     assert rep.pairs > 10000
 
 
+@pytest.mark.parametrize("name,p_tol", [("cfg_rad3d_dense", 1e-6), ("cfg_mem2d", 1e-9)])
+def test_full_size_many_events(name, p_tol):
+    # full-size workloads with thousands of encounters per step: the event kernel
+    # runs one event per lane there (4096 or more events)
+    cfg = I.workload(name)
+    sp, pos = _state(cfg["n_a"], cfg["n_b"], cfg["box"], cfg["dim"], cfg["sigma"], 0, True)
+    gpu, orc = make_pair(dim=cfg["dim"], bc=cfg["bc"], box=cfg["box"], dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"],
+                         kappa=cfg["kappa_a"], k_off=cfg["k_off"], precision=cfg["precision"], species=sp, pos=pos)
+    rep = run(gpu, orc, 1, p_tol=p_tol, pos_tol=0.0, box=cfg["box"])
+    _check(rep, p_tol=p_tol, allow_near=4)
+    st = gpu.stats()
+    print("events", st["matches"] + st["decay"])
+    assert st["matches"] + st["decay"] >= 4096
+
+
 def test_cell_lists_are_consistent():
     # every live slot is binned once, in the bucket of its post-move position
     n = 5000

@@ -80,3 +80,39 @@ def test_pair_probabilities_2d_small_tau(prec, tol, n_terms):
     print(f"tau {tau:.3g} h {hh:.3g}: max |dp_enc| {e1.max():.2e} max |dp_reac| {e2.max():.2e}")
     assert e1.max() <= tol
     assert e2.max() <= 1e-9
+
+
+PROP_CASES = [  # (dim, dt, D, kappa, n_terms)
+    (3, 1e-5, (1.0, 1.0, 0.5), 0.1, 12),   # tau = 0.8
+    (3, 1e-6, (1.0, 1.0, 0.5), 0.1, 12),   # tau = 0.08
+    (2, 5e-6, (0.1, 0.1, 0.05), 0.05, 12),  # tau = 0.04, compiled order
+    (2, 5e-6, (0.1, 0.1, 0.05), 0.05, 10),  # run-time order
+]
+
+
+@pytest.mark.parametrize("wave", [True, False])
+@pytest.mark.parametrize("dim,dt,D,kappa,n_terms", PROP_CASES)
+def test_propagator_draws_match_the_oracle(dim, dt, D, kappa, n_terms, wave):
+    # the step's rejection sampler, draw by draw, against the oracle's, on the same counters:
+    # both forms (attempts over a wave, one draw per lane) must give the oracle's R'' and
+    # attempt count
+    seed, step = 11, 7
+    sp = np.array([0, 1], np.int32)
+    pos = np.array([[0.25] * dim, [0.75] * dim])
+    h = S.Sim(dim=dim, box=1.0, dt=dt, D=D, sigma=0.005, bc=O.BC_RAD, kappa=kappa, k_off=0.0,
+              precision=S.PREC_FP64, n_terms=n_terms, seed=seed, species=sp, pos=pos)
+    tau = h.derived()["tau"]
+    rng = np.random.default_rng(3)
+    n = 4000
+    R0 = 1.0 + 4.0 * rng.random(n) ** 2
+    R0[:4] = [1.0, 1.0 + 1e-9, 2.0 / 0.5 + 1.0, 5.0]  # contact, near contact, past the mixture bound
+    Rg, ag = h.eval_propagator(R0, step, wave=wave)
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    ref = [O.sample_prop(dim, r0, tau, n_terms, (i, 0xFFFFFFFF, step, 5), key) for i, r0 in enumerate(R0)]
+    Ro = np.array([r[0] for r in ref])
+    ao = np.array([r[1] for r in ref])
+    bad = np.flatnonzero(ag != ao)
+    print(f"dim {dim} tau {tau:.3g} n {n_terms} wave {wave}: attempts differ at {len(bad)}; "
+          f"max |dR''| {np.abs(Rg - Ro).max():.2e}")
+    assert len(bad) == 0, (bad[:5], R0[bad[:5]], ag[bad[:5]], ao[bad[:5]])
+    assert np.abs(Rg - Ro).max() <= 1e-9
