@@ -130,6 +130,59 @@ def pair_probs(args, I, S):
                    "kernel": "k_eval_probs (the step's p_enc / p_reac device functions)"}}), flush=True)
 
 
+def batched(args, I, S):
+    """R independent 3D replicas stepped together (sim_batch_create, one graph replay per step)
+    against the plain path: a sample of the same replicas stepped one handle at a time."""
+    shared = dict(dt=1e-5, D=(1.0, 1.0, 0.5), sigma=0.005, bc=S.BC_RADIATION, k_off=10.0, seed=0,
+                  precision=S.PREC_FP32_FP64NC)
+    t0 = time.time()
+    reps = I.ensemble(args.batch)
+    n_tot = sum(len(r["species"]) for r in reps)
+    log(f"[batch] {len(reps)} replicas, {n_tot} particles, generated in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    b = S.Sim.batch(reps, **shared)
+    log(f"[batch] created in {time.time() - t0:.1f}s")
+    b.step(args.warmup)
+    c0 = b.counts()
+    t0 = time.perf_counter()
+    b.step(args.steps)
+    el = time.perf_counter() - t0
+    c1 = b.counts()
+    b.close()
+    n_live = 0.5 * sum(c0[k] + c1[k] for k in ("A", "B", "C"))
+    rate = n_live * args.steps / el
+    log(f"[batch] {args.steps} steps in {el * 1e3:.1f} ms: {rate:.3e} particle-steps/s")
+    # plain path: the same replicas, one handle each, stepped one after another
+    rng = np.random.default_rng(1)
+    pick = rng.choice(len(reps), size=min(args.single_sample, len(reps)), replace=False)
+    t_single, ps_single = 0.0, 0.0
+    for r in pick:
+        rd = reps[r]
+        sim = S.Sim(dim=3, box=rd["box"], species=rd["species"], pos=rd["pos"], kappa=rd["kappa"],
+                    replica=rd["replica"], **shared)
+        sim.step(args.warmup)
+        t0 = time.perf_counter()
+        sim.step(args.steps)
+        t_single += time.perf_counter() - t0
+        ps_single += len(rd["species"]) * args.steps
+        sim.close()
+    rate1 = ps_single / t_single
+    log(f"[batch] single-replica path on {len(pick)} replicas: {rate1:.3e} particle-steps/s")
+    print(json.dumps({
+        "metric": "particle-steps/s (batched ensemble)", "value": round(rate, 1), "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(el * 1e3 / args.steps, 4),
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "single_replica_path": {"value": round(rate1, 1), "unit": "particle-steps/s",
+                                "sample": f"{len(pick)} replicas of the ensemble, one handle each, stepped one after "
+                                          f"another ({args.steps} steps each after {args.warmup} warm-up)"},
+        "speedup_vs_single_replica_path": round(rate / rate1, 2),
+        "config": {"workload": f"{len(reps)} independent 3D replicas, A+B<->C radiation surface, N log-uniform in "
+                               f"[1e3, 1e5] (total {n_tot}), kappa uniform in [0.01, 1] um^3/s, L = (N/1000)^(1/3) um, "
+                               "D=1 um^2/s, sigma=5 nm, k_off=10/s, dt=10 us",
+                   "precision": "binary32 state and p_enc, binary64 near-contact arguments and propagation",
+                   "step_launch": "one hipGraph replay per step for all replicas"}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +200,10 @@ def main():
                     help="only run the pair-probability micro-benchmark on N synthetic pairs and exit")
     ap.add_argument("--dim", type=int, default=3, help="workload dimension for --pair-probs (2: the membrane "
                     "workload at dt = 5 us)")
+    ap.add_argument("--batch", type=int, default=0, metavar="R",
+                    help="only run the batched-ensemble benchmark on R replicas (4096: the full ensemble) and exit")
+    ap.add_argument("--single-sample", type=int, default=32,
+                    help="replicas timed one handle at a time for the single-replica comparison (--batch)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -169,6 +226,9 @@ def main():
 
     if args.pair_probs:
         pair_probs(args, I, S)
+        return
+    if args.batch:
+        batched(args, I, S)
         return
 
     cfg = I.workload(args.workload)

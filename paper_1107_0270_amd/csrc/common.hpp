@@ -122,6 +122,13 @@ struct Params {
     u32 debug;
     u32 dbg_cap;
     const double *g2c;  // 2D constants: a_k(0), Q_abs, Q_ref, Q_rad (4 x (MAXTERMS+1))
+    // Batches of independent replicas: replica r owns slots [slot_base,
+    // slot_base + n) and cells [cell_base, cell_base + own cell count) of
+    // every species block.  A single system is replica 0 with both bases 0.
+    u32 slot_base, cell_base;
+    u32 n_rep;
+    const u32 *rep_of_slot;   // replica of every slot (batches only)
+    const Params *reps;       // per-replica parameters (batches only)
 };
 
 enum {

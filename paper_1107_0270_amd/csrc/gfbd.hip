@@ -167,6 +167,13 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     u64 *headA = nullptr, *headB = nullptr;
     Counters *ctr = nullptr;
     Params *dparams = nullptr;  // device copy of P for kernels that call out-of-line functions
+    // batches
+    bool batch = false;
+    std::vector<Params> reps_h;
+    std::vector<double> rep_box;
+    std::vector<u32> rep_of_slot_h;
+    Params *d_reps = nullptr;
+    u32 *d_rep_of_slot = nullptr;
     hipStream_t own_stream = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     uint32_t n_bricks = 0;
@@ -206,14 +213,10 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         return SIM_OK;
     }
 
-    int init(const Model &m, uint64_t nslots, const int32_t *sp, const double *pos, const uint32_t *pt)
+    // Physics, cut-off and cell grid of one system (or one replica of a
+    // batch) with n_r slots and species sp.
+    int setup_replica(const Model &M, uint64_t n, const int32_t *sp, Params &P, double &cell_edge, double &pair_tests, bool &narrow)
     {
-        M = m;
-        n = nslots;
-        if (!M.stream) {  // a stream of our own: the null stream cannot be captured into a graph
-            HIPCHECK(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
-            M.stream = own_stream;
-        }
         std::memset(&P, 0, sizeof(P));
         P.dim = DIM;
         P.bc = M.bc;
@@ -264,9 +267,6 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             nB += sp[i] == SIM_SP_B;
             nC += sp[i] == SIM_SP_C;
         }
-        // A and C counts change with reactions and state loads; size by the slot count
-        maxA = (u32)n;
-        maxC = (u32)n;
         // grid: cells of edge >= r_cut, about one B per cell unless requested
         double vol = 1.0;
         for (int k = 0; k < DIM; ++k) vol *= M.box[k];
@@ -294,8 +294,6 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         if (ncell > (1ull << 28)) return fail(SIM_EUNSUPPORTED, "too many cells");
         P.n_cells = (u32)ncell;
         P.n_keys = 3u * P.n_cells;
-        P.cap = (u32)n;
-        P.cap_pl = (u32)std::min<uint64_t>(std::max<uint64_t>(1u << 20, 4 * n), 1u << 30);
         // Pair search: LDS bricks pay off where every A tests many B's (each
         // staged B serves many A's); with few B's per A the direct kernel
         // (neighbour buckets through L2) has no staging to amortise.
@@ -310,6 +308,34 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         narrow = true;
         for (int k = 0; k < DIM; ++k)
             if (P.nc[k] >= 3 && !(P.ce[k] >= 2.0 * P.reach)) narrow = false;
+        P.debug = M.debug;
+        P.dbg_cap = (u32)M.dbg_cap;
+        return SIM_OK;
+    }
+
+    int open_stream()
+    {
+        if (!M.stream) {  // a stream of our own: the null stream cannot be captured into a graph
+            HIPCHECK(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
+            M.stream = own_stream;
+        }
+        return SIM_OK;
+    }
+
+    int init(const Model &m, uint64_t nslots, const int32_t *sp, const double *pos, const uint32_t *pt)
+    {
+        M = m;
+        n = nslots;
+        int rc;
+        if ((rc = open_stream()) || (rc = setup_replica(M, n, sp, P, cell_edge, pair_tests, narrow))) return rc;
+        P.cap = (u32)n;
+        P.cap_pl = (u32)std::min<uint64_t>(std::max<uint64_t>(1u << 20, 4 * n), 1u << 30);
+        uint64_t nB = 0, nC = 0;
+        for (uint64_t i = 0; i < n; ++i) {
+            nB += sp[i] == SIM_SP_B;
+            nC += sp[i] == SIM_SP_C;
+        }
+        const uint64_t ncell = P.n_cells;
         const bool can_tile = P.nc[0] >= 3 && P.nc[1] >= 3 && (DIM == 2 || P.nc[2] >= 3);
         P.tiled = can_tile && (M.pair_search == SIM_PAIRS_BRICKS ||
                                (M.pair_search == SIM_PAIRS_AUTO && pair_tests > PAIR_TESTS_TILED));
@@ -335,8 +361,72 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             P.nbz = DIM == 3 ? (P.nc[2] + P.bz - 1) / P.bz : 1;
             n_bricks = P.nbx * P.nby * P.nbz;
         }
-        P.debug = M.debug;
-        P.dbg_cap = (u32)M.dbg_cap;
+        return finish_init(sp, pos, pt);
+    }
+
+    // A batch of independent replicas (3D): each keeps its own box, kappa,
+    // replica key, cut-off and grid; their slots and cells are laid out one
+    // after the other.  The pair search is the direct one.
+    int init_batch(const std::vector<Model> &ms, const std::vector<uint64_t> &nr, const int32_t *sp, const double *pos,
+                   const uint32_t *pt)
+    {
+        M = ms[0];
+        n = 0;
+        for (uint64_t x : nr) n += x;
+        int rc;
+        if ((rc = open_stream())) return rc;
+        batch = true;
+        const size_t R = ms.size();
+        reps_h.resize(R);
+        rep_box.resize(3 * R);
+        rep_of_slot_h.resize(n);
+        uint64_t sbase = 0, cbase = 0;
+        narrow = true;
+        for (size_t r = 0; r < R; ++r) {
+            double ce = 0.0, tests = 0.0;
+            bool nar = true;
+            if ((rc = setup_replica(ms[r], nr[r], sp + sbase, reps_h[r], ce, tests, nar))) return rc;
+            reps_h[r].slot_base = (u32)sbase;
+            reps_h[r].cell_base = (u32)cbase;
+            for (int k = 0; k < 3; ++k) rep_box[3 * r + k] = ms[r].box[k];
+            for (uint64_t i = 0; i < nr[r]; ++i) rep_of_slot_h[sbase + i] = (u32)r;
+            narrow = narrow && nar;
+            if (r == 0) {
+                cell_edge = ce;
+                pair_tests = tests;
+            }
+            sbase += nr[r];
+            cbase += reps_h[r].n_cells;
+            if (cbase > (1ull << 28)) return fail(SIM_EUNSUPPORTED, "too many cells in the batch");
+        }
+        P = reps_h[0];  // replica 0's physics; totals below
+        P.n_cells = (u32)cbase;
+        P.n_keys = 3u * P.n_cells;
+        P.slot_base = P.cell_base = 0;
+        P.n_rep = (u32)R;
+        P.cap = (u32)n;
+        P.cap_pl = (u32)std::min<uint64_t>(std::max<uint64_t>(1u << 20, 4 * n), 1u << 30);
+        P.tiled = 0;
+        if ((rc = alloc(d_reps, R)) || (rc = alloc(d_rep_of_slot, n))) return rc;
+        P.reps = d_reps;
+        P.rep_of_slot = d_rep_of_slot;
+        for (auto &q : reps_h) {  // fields shared by the whole batch
+            q.cap = P.cap;
+            q.cap_pl = P.cap_pl;
+            q.n_rep = P.n_rep;
+            q.reps = d_reps;
+            q.rep_of_slot = d_rep_of_slot;
+        }
+        HIPCHECK(hipMemcpyAsync(d_rep_of_slot, rep_of_slot_h.data(), sizeof(u32) * n, hipMemcpyHostToDevice, M.stream));
+        return finish_init(sp, pos, pt);
+    }
+
+    // Buffers, constants and the initial state (P final apart from g2c).
+    int finish_init(const int32_t *sp, const double *pos, const uint32_t *pt)
+    {
+        // A and C counts change with reactions and state loads; size by the slot count
+        maxA = (u32)n;
+        maxC = (u32)n;
         nb_scan = (P.n_keys + SCAN_TILE - 1) / SCAN_TILE;
         P.cnt_region = nb_scan * (SCAN_TILE / CNT_REGIONS);
         // device buffers
@@ -363,6 +453,11 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         P.g2c = g2c;
         if ((rc = alloc(dparams, 1))) return rc;
         HIPCHECK(hipMemcpyAsync(dparams, &P, sizeof(P), hipMemcpyHostToDevice, M.stream));  // P is final here
+        if (batch) {
+            for (auto &q : reps_h) q.g2c = g2c;
+            HIPCHECK(hipMemcpyAsync(d_reps, reps_h.data(), sizeof(Params) * reps_h.size(), hipMemcpyHostToDevice, M.stream));
+            HIPCHECK(hipStreamSynchronize(M.stream));  // reps_h is host memory the copy reads
+        }
         return load(0, sp, pos, pt);
     }
 
@@ -374,9 +469,10 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         for (uint64_t i = 0; i < n; ++i) {
             if (sp[i] > SIM_SP_C) continue;
             Rec<T> r;
-            r.x = h_wrap_store<T>(pos[i * DIM + 0], M.box[0]);
-            r.y = h_wrap_store<T>(pos[i * DIM + 1], M.box[1]);
-            r.z = DIM == 3 ? h_wrap_store<T>(pos[i * DIM + 2], M.box[2]) : (T)0;
+            const double *bx = batch ? &rep_box[3 * rep_of_slot_h[i]] : M.box;
+            r.x = h_wrap_store<T>(pos[i * DIM + 0], bx[0]);
+            r.y = h_wrap_store<T>(pos[i * DIM + 1], bx[1]);
+            r.z = DIM == 3 ? h_wrap_store<T>(pos[i * DIM + 2], bx[2]) : (T)0;
             rec_set_meta(r, meta_make((u32)sp[i], (u32)i));
             h[live++] = r;
             if (sp[i] == SIM_SP_C) hp[i] = pt[i];
@@ -434,16 +530,24 @@ template <int DIM, class T, int PM> struct Engine final : sim {
 
     template <int NC2> void enqueue_step_n(int c)
     {
+        if constexpr (DIM == 3) {
+            if (batch) return enqueue_step_t<NC2, true>(c);
+        }
+        enqueue_step_t<NC2, false>(c);
+    }
+
+    template <int NC2, bool BATCH> void enqueue_step_t(int c)
+    {
         hipStream_t st = M.stream;
         Rec<T> *in = rec[c], *out = rec[c ^ 1];
         const u32 g_all = grid_for(n, 8192);
         const u32 g_pl = 1024;
-        launch(SIM_K_MOVE, [&] { k_move_count<DIM, T><<<g_all, BLOCK, 0, st>>>(P, in, okey, tmp, rank, cnt, scnt, ctr); });
+        launch(SIM_K_MOVE, [&] { k_move_count<DIM, T, BATCH><<<g_all, BLOCK, 0, st>>>(P, in, okey, tmp, rank, cnt, scnt, ctr); });
         launch(SIM_K_SCAN, [&] {
             k_scan_tiles<<<nb_scan, BLOCK, 0, st>>>(cnt, scnt, bsum);
             k_scan<<<nb_scan, BLOCK, 0, st>>>(cnt, scnt, bsum, start, ctr);
         });
-        launch(SIM_K_SCATTER, [&] { k_scatter<DIM, T><<<g_all, BLOCK, 0, st>>>(P, tmp, rank, start, out, okey, ctr); });
+        launch(SIM_K_SCATTER, [&] { k_scatter<DIM, T, BATCH><<<g_all, BLOCK, 0, st>>>(P, tmp, rank, start, out, okey, ctr); });
         if (M.debug) {
             k_fill<<<grid_for(n * DIM, 2048), BLOCK, 0, st>>>(dbg_moved, n * DIM, (int *)dbg_cells, (u32)n);
             k_gather<DIM, T><<<g_all, BLOCK, 0, st>>>(out, partner, ctr, 1, dbg_moved, nullptr, (u32)n);
@@ -455,18 +559,18 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             // grids in multiples of the eight XCDs; the direct search takes no
             // more workgroups than are resident at once (2048)
             const u32 g_pairs = round8(grid_for(maxA, 2048));
-            if (P.tiled) k_pair_scan<DIM, T, PM><<<round8(n_bricks), PBLOCK, 0, st>>>(P, out, start, plist, ctr);
-            else if (narrow) k_pair_scan_direct_narrow<DIM, T, PM><<<g_pairs, BLOCK, 0, st>>>(P, out, start, plist, ctr);
-            else k_pair_scan_direct<DIM, T, PM><<<g_pairs, BLOCK, 0, st>>>(P, out, start, plist, ctr);
+            if (!BATCH && P.tiled) k_pair_scan<DIM, T, PM><<<round8(n_bricks), PBLOCK, 0, st>>>(P, out, start, plist, ctr);
+            else if (narrow) k_pair_scan_direct_narrow<DIM, T, PM, BATCH><<<g_pairs, BLOCK, 0, st>>>(P, out, start, plist, ctr);
+            else k_pair_scan_direct<DIM, T, PM, BATCH><<<g_pairs, BLOCK, 0, st>>>(P, out, start, plist, ctr);
         });
-        launch(SIM_K_EVAL, [&] { k_pair_eval<DIM, T, PM, NC2><<<g_pl, BLOCK, 0, st>>>(P, out, plist, cand, flag, headA, nextA, ctr, dbg_pairs); });
-        launch(SIM_K_SELECT_A, [&] { k_select_a<<<g_pl, BLOCK, 0, st>>>(P, plist, cand, flag, headA, nextA, headB, nextB, ctr, dbg_picks); });
+        launch(SIM_K_EVAL, [&] { k_pair_eval<DIM, T, PM, NC2, BATCH><<<g_pl, BLOCK, 0, st>>>(P, out, plist, cand, flag, headA, nextA, ctr, dbg_pairs); });
+        launch(SIM_K_SELECT_A, [&] { k_select_a<BATCH><<<g_pl, BLOCK, 0, st>>>(P, plist, cand, flag, headA, nextA, headB, nextB, ctr, dbg_picks); });
         const u32 nb_sel = g_pl, nb_dec = P.reversible ? grid_for(maxC, 2048) : 0;
         launch(SIM_K_SELECT_B, [&] {
-            k_select_b<T><<<nb_sel + nb_dec, BLOCK, 0, st>>>(P, plist, cand, flag, headB, nextB, out, start, ev, ctr, nb_sel);
+            k_select_b<T, BATCH><<<nb_sel + nb_dec, BLOCK, 0, st>>>(P, plist, cand, flag, headB, nextB, out, start, ev, ctr, nb_sel);
         });
         launch(SIM_K_EVENTS, [&] {
-            k_events<DIM, T, NC2><<<EV_BLOCKS, BLOCK, 0, st>>>(dparams, out, plist, cand, ev, partner, ctr, dbg_matches, dbg_diss);
+            k_events<DIM, T, NC2, BATCH><<<EV_BLOCKS, BLOCK, 0, st>>>(dparams, out, plist, cand, ev, partner, ctr, dbg_matches, dbg_diss);
             k_close<<<1, 64, 0, st>>>(ctr);
         });
     }
@@ -741,6 +845,22 @@ int make(const Model &M, uint64_t n, const int32_t *sp, const double *pos, const
     return SIM_OK;
 }
 
+template <int DIM, class T, int PM>
+int make_batch(const std::vector<Model> &ms, const std::vector<uint64_t> &nr, const int32_t *sp, const double *pos, const uint32_t *pt,
+               sim_t **out)
+{
+    Engine<DIM, T, PM> *e = new (std::nothrow) Engine<DIM, T, PM>();
+    if (!e) { g_err = "host allocation failed"; return SIM_ENOMEM; }
+    const int rc = e->init_batch(ms, nr, sp, pos, pt);
+    if (rc) {
+        g_err = e->err;
+        delete e;
+        return rc;
+    }
+    *out = e;
+    return SIM_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -778,6 +898,49 @@ int sim_load_state(sim_t *h, uint64_t step, const int32_t *species, const double
 {
     if (!h || !species || !pos) { g_err = "null argument"; return SIM_EINVAL; }
     return h->load(step, species, pos, partner);
+}
+
+int sim_batch_create(const sim_config *cfg, uint32_t n_rep, const sim_replica *reps, sim_t **out)
+{
+    if (!out) { g_err = "null output handle"; return SIM_EINVAL; }
+    *out = nullptr;
+    if (!cfg || !reps || n_rep == 0) { g_err = "null argument or no replicas"; return SIM_EINVAL; }
+    if (cfg->dim != 3) { g_err = "batches are 3D"; return SIM_EUNSUPPORTED; }
+    std::vector<Model> ms(n_rep);
+    std::vector<uint64_t> nr(n_rep);
+    uint64_t total = 0;
+    for (uint32_t r = 0; r < n_rep; ++r) {
+        // each replica is checked as a system of its own: its box, kappa and replica key
+        sim_config c = *cfg;
+        for (int k = 0; k < 3; ++k) c.box[k] = reps[r].box[k];
+        c.replica = reps[r].replica;
+        sim_reaction rx = cfg->reactions ? cfg->reactions[0] : sim_reaction{};
+        rx.kappa = reps[r].kappa;
+        c.reactions = cfg->reactions ? &rx : nullptr;
+        const int rc = validate(&c, reps[r].n, reps[r].species, reps[r].pos, reps[r].partner, ms[r]);
+        if (rc) return rc;
+        nr[r] = reps[r].n;
+        total += reps[r].n;
+    }
+    if (total > SLOT_MASK) { g_err = "more than 2^29 slots in the batch"; return SIM_EINVAL; }
+    // global arrays: replica r's slots follow those of replicas 0..r-1; partners become global
+    std::vector<int32_t> sp(total);
+    std::vector<double> pos(total * 3);
+    std::vector<uint32_t> pt(total, 0xFFFFFFFFu);
+    uint64_t base = 0;
+    for (uint32_t r = 0; r < n_rep; ++r) {
+        for (uint64_t i = 0; i < nr[r]; ++i) {
+            sp[base + i] = reps[r].species[i];
+            for (int k = 0; k < 3; ++k) pos[3 * (base + i) + k] = reps[r].pos[3 * i + k];
+            if (reps[r].partner && reps[r].species[i] == SIM_SP_C && reps[r].partner[i] != 0xFFFFFFFFu)
+                pt[base + i] = (uint32_t)(base + reps[r].partner[i]);
+        }
+        base += nr[r];
+    }
+    const Model &M = ms[0];
+    if (M.prec == SIM_PREC_FP64) return make_batch<3, double, PM_F64>(ms, nr, sp.data(), pos.data(), pt.data(), out);
+    if (M.prec == SIM_PREC_FP32) return make_batch<3, float, PM_F32>(ms, nr, sp.data(), pos.data(), pt.data(), out);
+    return make_batch<3, float, PM_F32NC>(ms, nr, sp.data(), pos.data(), pt.data(), out);
 }
 
 int sim_eval_pairs(sim_t *h, uint64_t n, const double *R, const double *R0, double *penc, double *preac)

@@ -85,11 +85,25 @@ template <int DIM, class T> __device__ inline void displacement(const Params &P,
     }
 }
 
-template <int DIM, class T> __device__ inline Rec<T> moved(const Params &P, const Rec<T> &r, u32 meta, u32 step)
+// The parameters of the replica a slot belongs to (a single system: its own)
+// and the slot's index within its replica (what the draws are keyed on).
+template <bool BATCH> __device__ __forceinline__ const Params &rep_params(const Params &P, u32 slot)
+{
+    if constexpr (BATCH) return P.reps[P.rep_of_slot[slot]];
+    else return P;
+}
+template <bool BATCH> __device__ __forceinline__ u32 local_slot(const Params &Q, u32 slot)
+{
+    if constexpr (BATCH) return slot - Q.slot_base;
+    else return slot;
+}
+
+// x' = wrap(x + displacement) for the record of (replica-local) slot `slot`.
+template <int DIM, class T> __device__ inline Rec<T> moved(const Params &P, const Rec<T> &r, u32 slot, u32 sp, u32 step)
 {
 #pragma clang fp contract(off)
     double d[3];
-    displacement<DIM, T>(P, meta_slot(meta), meta_sp(meta), step, d);
+    displacement<DIM, T>(P, slot, sp, step, d);
     Rec<T> q;
     q.x = wrap_store<T>((double)r.x + d[0], P.L[0]);
     q.y = wrap_store<T>((double)r.y + d[1], P.L[1]);
@@ -110,6 +124,13 @@ template <int DIM, class T> __device__ inline u32 cell_of(const Params &P, const
     const int cy = cell1((double)q.y, P.cs[1], P.nc[1]);
     const int cz = DIM == 3 ? cell1((double)q.z, P.cs[2], P.nc[2]) : 0;
     return ((u32)cz * P.nc[1] + cy) * P.nc[0] + cx;
+}
+
+// Bucket key of a record of species sp at q: species block (each of
+// P.n_cells keys, over all replicas), then the replica's cells, then its cell.
+template <int DIM, class T, bool BATCH> __device__ inline u32 bucket_key(const Params &P, const Params &Q, u32 sp, const Rec<T> &q)
+{
+    return sp * P.n_cells + (BATCH ? Q.cell_base : 0u) + cell_of<DIM, T>(Q, q);
 }
 
 // ---------------------------------------------------------------------------
@@ -181,7 +202,7 @@ __device__ inline u32 block_incl_max(u32 v, u32 *lds)
 constexpr u32 STAYER = 0x80000000u;
 constexpr u32 NOKEY = 0xFFFFFFFFu;
 
-template <int DIM, class T>
+template <int DIM, class T, bool BATCH>
 __global__ __launch_bounds__(BLOCK) void k_move_count(Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ okey,
                                                        Rec<T> *__restrict__ tmp, u32 *__restrict__ rank, u32 *__restrict__ cnt,
                                                        u32 *__restrict__ scnt, Counters *C)
@@ -211,9 +232,11 @@ __global__ __launch_bounds__(BLOCK) void k_move_count(Params P, const Rec<T> *__
         const bool alive = valid && sp <= SP_C;
         u32 key = NOKEY;
         if (alive) {
-            const Rec<T> q = moved<DIM, T>(P, r, m, step);
+            const u32 slot = meta_slot(m);
+            const Params &Q = rep_params<BATCH>(P, slot);
+            const Rec<T> q = moved<DIM, T>(Q, r, local_slot<BATCH>(Q, slot), sp, step);
             tmp[i] = q;
-            key = sp * P.n_cells + cell_of<DIM, T>(P, q);
+            key = bucket_key<DIM, T, BATCH>(P, Q, sp, q);
         } else if (valid) {
             tmp[i] = r;  // dead record: the scatter skips it
         }
@@ -319,7 +342,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan(u32 *__restrict__ cnt, u32 *__re
 // the bucket, the others from its end) and note its bucket key for the next
 // step's stayer test.
 // ---------------------------------------------------------------------------
-template <int DIM, class T>
+template <int DIM, class T, bool BATCH>
 __global__ __launch_bounds__(BLOCK) void k_scatter(Params P, const Rec<T> *__restrict__ tmp, const u32 *__restrict__ rank,
                                                     const u32 *__restrict__ start, Rec<T> *__restrict__ out, u32 *__restrict__ okey,
                                                     const Counters *C)
@@ -327,9 +350,9 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Params P, const Rec<T> *__res
     const u32 n = C->n_rec;
     for (u32 i = gtid(); i < n; i += gstride()) {
         const Rec<T> q = tmp[i];
-        const u32 sp = meta_sp(rec_meta(q));
+        const u32 m = rec_meta(q), sp = meta_sp(m);
         if (sp > SP_C) continue;
-        const u32 key = sp * P.n_cells + cell_of<DIM, T>(P, q);
+        const u32 key = bucket_key<DIM, T, BATCH>(P, rep_params<BATCH>(P, meta_slot(m)), sp, q);
         const u32 rk = rank[i];
         const u32 dst = (rk & STAYER) ? start[key] + (rk & ~STAYER) : start[key + 1] - 1u - rk;
         if (dst < P.cap) {
@@ -513,14 +536,14 @@ __device__ __forceinline__ void reach_of(const Params &P, const Rec<T> &ra, int 
 // 3 x 3.  All bounds are loaded before any is used.
 template <int DIM, bool NARROW> constexpr int n_slots() { return NARROW ? (DIM == 3 ? 4 : 2) : (DIM == 3 ? 9 : 3); }
 
+// P: the grid of ra's replica; bbase: key of that replica's first B bucket.
 template <int DIM, bool NARROW, class T>
-__device__ __forceinline__ void collect_ranges(const Params &P, const u32 *__restrict__ start, const Rec<T> &ra, u32 *b0, u32 *e0,
-                                               u32 *b1, u32 *e1)
+__device__ __forceinline__ void collect_ranges(const Params &P, u32 bbase, const u32 *__restrict__ start, const Rec<T> &ra, u32 *b0,
+                                               u32 *e0, u32 *b1, u32 *e1)
 {
     int c[3], lo[3], hi[3];
     reach_of<DIM, T>(P, ra, c, lo, hi);
     const int nx = P.nc[0], ny = P.nc[1], nz = P.nc[2];
-    const u32 bbase = P.n_cells;  // B buckets follow the A buckets
     const int xa = c[0] + lo[0], xb = c[0] + hi[0];
     const int sy = lo[1] + hi[1], sz = lo[2] + hi[2];  // NARROW: the one neighbour side, or 0
 #pragma unroll
@@ -564,7 +587,7 @@ __device__ inline void for_pairs(const Params &P, const Rec<T> *__restrict__ rec
 {
     constexpr int NS = n_slots<DIM, false>();
     u32 b0[NS], e0[NS], b1[NS], e1[NS];
-    collect_ranges<DIM, false, T>(P, start, ra, b0, e0, b1, e1);
+    collect_ranges<DIM, false, T>(P, P.n_cells, start, ra, b0, e0, b1, e1);  // B buckets follow the A buckets
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         for (u32 j = b0[s]; j < e0[s]; ++j) {
@@ -819,7 +842,7 @@ __global__ __launch_bounds__(PBLOCK) void k_pair_scan(Params P, const Rec<T> *__
 // A wave with more than TCAP tests tests per lane instead.
 constexpr int TCAP = 512;  // tests listed per wave
 
-template <int DIM, class T, int PM, bool NARROW>
+template <int DIM, class T, int PM, bool NARROW, bool BATCH>
 __device__ __forceinline__ void pair_scan_direct(const Params &P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start,
                                                  PairEnt *__restrict__ list, Counters *C)
 {
@@ -846,7 +869,9 @@ __device__ __forceinline__ void pair_scan_direct(const Params &P, const Rec<T> *
         u32 b0[NS], e0[NS], b1[NS], e1[NS];
         u32 tot = 0;
         if (act) {
-            collect_ranges<DIM, NARROW, T>(P, start, ra, b0, e0, b1, e1);
+            // B buckets follow the A buckets; a replica's cells start at its cell base
+            const Params &Q = rep_params<BATCH>(P, meta_slot(rec_meta(ra)));
+            collect_ranges<DIM, NARROW, T>(Q, P.n_cells + (BATCH ? Q.cell_base : 0u), start, ra, b0, e0, b1, e1);
 #pragma unroll
             for (int s = 0; s < NS; ++s) tot += (e0[s] - b0[s]) + (e1[s] - b1[s]);
         } else {
@@ -890,16 +915,18 @@ __device__ __forceinline__ void pair_scan_direct(const Params &P, const Rec<T> *
                 for (int u = 0; u < U; ++u) {
                     if (jb[u] == NOSLOT) continue;
                     const Rec<T> ro = sa[w * 64 + own[u]];
-                    if (in_range<DIM, T, PM>(P, ro, rb[u])) append_pair(q, &nq, list, C, P, b + w * 64 + own[u], jb[u]);
+                    if (in_range<DIM, T, PM>(rep_params<BATCH>(P, meta_slot(rec_meta(ro))), ro, rb[u]))
+                        append_pair(q, &nq, list, C, P, b + w * 64 + own[u], jb[u]);
                 }
             }
         } else {
+            const Params &Q = rep_params<BATCH>(P, meta_slot(rec_meta(ra)));
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 for (u32 j = b0[s]; j < e0[s]; ++j)
-                    if (in_range<DIM, T, PM>(P, ra, rec[j])) append_pair(q, &nq, list, C, P, ia, j);
+                    if (in_range<DIM, T, PM>(Q, ra, rec[j])) append_pair(q, &nq, list, C, P, ia, j);
                 for (u32 j = b1[s]; j < e1[s]; ++j)
-                    if (in_range<DIM, T, PM>(P, ra, rec[j])) append_pair(q, &nq, list, C, P, ia, j);
+                    if (in_range<DIM, T, PM>(Q, ra, rec[j])) append_pair(q, &nq, list, C, P, ia, j);
             }
         }
         __syncthreads();  // the next batch reuses the LDS tables
@@ -909,18 +936,18 @@ __device__ __forceinline__ void pair_scan_direct(const Params &P, const Rec<T> *
 
 // The narrow form fits 64 VGPRs: eight waves per SIMD hold all A's of a
 // typical step at once.
-template <int DIM, class T, int PM>
+template <int DIM, class T, int PM, bool BATCH>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void k_pair_scan_direct_narrow(
     Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start, PairEnt *__restrict__ list, Counters *C)
 {
-    pair_scan_direct<DIM, T, PM, true>(P, rec, start, list, C);
+    pair_scan_direct<DIM, T, PM, true, BATCH>(P, rec, start, list, C);
 }
 
-template <int DIM, class T, int PM>
+template <int DIM, class T, int PM, bool BATCH>
 __global__ __launch_bounds__(BLOCK) void k_pair_scan_direct(Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start,
                                                              PairEnt *__restrict__ list, Counters *C)
 {
-    pair_scan_direct<DIM, T, PM, false>(P, rec, start, list, C);
+    pair_scan_direct<DIM, T, PM, false, BATCH>(P, rec, start, list, C);
 }
 
 // ---------------------------------------------------------------------------
@@ -935,7 +962,7 @@ __device__ __forceinline__ u32 chain_push(u64 *head, u32 rec_idx, u32 entry, u32
     return (prev >> 32) == (u64)(step + 1u) ? (u32)prev : NOSLOT;
 }
 
-template <int DIM, class T, int PM, int NC>
+template <int DIM, class T, int PM, int NC, bool BATCH>
 __global__ __launch_bounds__(BLOCK) void k_pair_eval(Params P, const Rec<T> *__restrict__ rec, const PairEnt *__restrict__ list,
                                                       CandEnt *__restrict__ cand, u32 *__restrict__ flag, u64 *__restrict__ headA,
                                                       u32 *__restrict__ nextA, Counters *C, DbgPair *dbg)
@@ -948,9 +975,10 @@ __global__ __launch_bounds__(BLOCK) void k_pair_eval(Params P, const Rec<T> *__r
         const PairEnt e = list[k];
         const Rec<T> ra = rec[e.a_idx], rb = rec[e.b_idx];
         const u32 sa = meta_slot(rec_meta(ra)), sb = meta_slot(rec_meta(rb));
+        const Params &Q = rep_params<BATCH>(P, sa);  // A and B of a pair share their replica
         double dA[3];
-        displacement<DIM, T>(P, sa, SP_A, step, dA);
-        const PairQ q = pair_quantities<DIM, T, PM, NC>(P, ra, rb, sa, sb, dA, step);
+        displacement<DIM, T>(Q, local_slot<BATCH>(Q, sa), SP_A, step, dA);
+        const PairQ q = pair_quantities<DIM, T, PM, NC>(Q, ra, rb, local_slot<BATCH>(Q, sa), local_slot<BATCH>(Q, sb), dA, step);
         st[0] += 1;
         st[1] += q.cand;
         st[2] += q.overlap;
@@ -1030,6 +1058,7 @@ __device__ inline u32 choose_in_chain(u32 head, const u32 *__restrict__ next, u3
 // chain leads; it applies the rule with U = {a, -, step, SELA} and chains
 // the chosen entry under its B record.
 // ---------------------------------------------------------------------------
+template <bool BATCH>
 __global__ __launch_bounds__(BLOCK) void k_select_a(Params P, const PairEnt *__restrict__ list, const CandEnt *__restrict__ cand,
                                                      u32 *__restrict__ flag, const u64 *__restrict__ headA,
                                                      const u32 *__restrict__ nextA, u64 *__restrict__ headB, u32 *__restrict__ nextB,
@@ -1050,7 +1079,8 @@ __global__ __launch_bounds__(BLOCK) void k_select_a(Params P, const PairEnt *__r
         if (me.b_slot != mins) continue;
         u32 win = k;
         if (count > 1) {
-            const double U = u01(philox(me.a_slot, NOSLOT, step, TAG_SELA, P.key).x);
+            const Params &Q = rep_params<BATCH>(P, me.a_slot);
+            const double U = u01(philox(local_slot<BATCH>(Q, me.a_slot), NOSLOT, step, TAG_SELA, Q.key).x);
             win = choose_in_chain(h, nextA, count, U, [&](u32 e) { return cand[e].b_slot; }, [&](u32 e) { return cand[e].p; });
             if (win == NOSLOT) win = k;
         }
@@ -1079,7 +1109,7 @@ constexpr u32 EV_DECAY = 0x80000000u;
 // Blocks [0, nb_sel) run the B-side choice over the pair list; the others
 // mark the C records (binned at the start of the step) that decay:
 // xi < 1 - e^{-k_off dt}, xi = {c, -, step, UNI} (eq. rad_prob, step 4).
-template <class T>
+template <class T, bool BATCH>
 __global__ __launch_bounds__(BLOCK) void k_select_b(Params P, const PairEnt *__restrict__ list, const CandEnt *__restrict__ cand,
                                                      const u32 *__restrict__ flag, const u64 *__restrict__ headB,
                                                      const u32 *__restrict__ nextB, const Rec<T> *__restrict__ rec,
@@ -1092,7 +1122,8 @@ __global__ __launch_bounds__(BLOCK) void k_select_b(Params P, const PairEnt *__r
         const u32 t0 = (blockIdx.x - nb_sel) * BLOCK + threadIdx.x, ts = (gridDim.x - nb_sel) * BLOCK;
         for (u32 i = beg + t0; i < end; i += ts) {
             const u32 sc = meta_slot(rec_meta(rec[i]));
-            if (below(philox(sc, NOSLOT, step, TAG_UNI, P.key).x, P.p_uni)) ev[atomicAdd(&C->n_ev, 1u)] = EV_DECAY | i;
+            const Params &Q = rep_params<BATCH>(P, sc);
+            if (below(philox(local_slot<BATCH>(Q, sc), NOSLOT, step, TAG_UNI, Q.key).x, P.p_uni)) ev[atomicAdd(&C->n_ev, 1u)] = EV_DECAY | i;
         }
         return;
     }
@@ -1109,7 +1140,8 @@ __global__ __launch_bounds__(BLOCK) void k_select_b(Params P, const PairEnt *__r
         if (cand[k].a_slot != mins) continue;
         u32 win = k;
         if (count > 1) {
-            const double U = u01(philox(cand[k].b_slot, NOSLOT, step, TAG_SELB, P.key).x);
+            const Params &Q = rep_params<BATCH>(P, cand[k].b_slot);
+            const double U = u01(philox(local_slot<BATCH>(Q, cand[k].b_slot), NOSLOT, step, TAG_SELB, Q.key).x);
             win = choose_in_chain(h, nextB, count, U, [&](u32 e) { return cand[e].a_slot; }, [&](u32 e) { return cand[e].p; });
             if (win == NOSLOT) win = k;
         }
@@ -1165,6 +1197,7 @@ __device__ __noinline__ void ev_match(const Params &P, Rec<T> *__restrict__ rec,
 #pragma clang fp contract(off)
     Rec<T> ra = rec[ia], rb = rec[ib];
     const u32 sa = meta_slot(rec_meta(ra)), sb = meta_slot(rec_meta(rb));
+    const u32 la = sa - P.slot_base, lb = sb - P.slot_base;  // the draws are keyed on replica-local slots
     const double xa[3] = {(double)ra.x, (double)ra.y, (double)ra.z};
     const double xb[3] = {(double)rb.x, (double)rb.y, (double)rb.z};
     double rv[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
@@ -1179,10 +1212,10 @@ __device__ __noinline__ void ev_match(const Params &P, Rec<T> *__restrict__ rec,
     if (P.bc == 0) {
         react = true;
     } else {
-        Rpp = LANE ? sample_radius_lane<DIM, NC>(P, R0, sa, sb, step, TAG_PROP, &att, &hits)
-                   : sample_radius_wave<DIM, NC>(P, R0, sa, sb, step, TAG_PROP, &att, &hits);
+        Rpp = LANE ? sample_radius_lane<DIM, NC>(P, R0, la, lb, step, TAG_PROP, &att, &hits)
+                   : sample_radius_wave<DIM, NC>(P, R0, la, lb, step, TAG_PROP, &att, &hits);
         preac = reac_prob<NC>(P, DIM, Rpp, R0);
-        const u32 w = philox(sa, sb, step, TAG_REAC, P.key).x;
+        const u32 w = philox(la, lb, step, TAG_REAC, P.key).x;
         react = below(w, preac);
         near = fabs(u01(w) - preac) < 1e-6;
         if (!react) {
@@ -1232,12 +1265,12 @@ __device__ __noinline__ void ev_decay(const Params &P, Rec<T> *__restrict__ rec,
 {
 #pragma clang fp contract(off)
     const Rec<T> rc = rec[i];
-    const u32 sc = meta_slot(rec_meta(rc));
+    const u32 sc = meta_slot(rec_meta(rc)), lc = sc - P.slot_base;
     u32 att = 0, hits = 0;
-    const double Rpp = LANE ? sample_radius_lane<DIM, NC>(P, 1.0, sc, NOSLOT, step, TAG_DPROP, &att, &hits)
-                            : sample_radius_wave<DIM, NC>(P, 1.0, sc, NOSLOT, step, TAG_DPROP, &att, &hits);
+    const double Rpp = LANE ? sample_radius_lane<DIM, NC>(P, 1.0, lc, NOSLOT, step, TAG_DPROP, &att, &hits)
+                            : sample_radius_wave<DIM, NC>(P, 1.0, lc, NOSLOT, step, TAG_DPROP, &att, &hits);
     const double preac = reac_prob<NC>(P, DIM, Rpp, 1.0);
-    const bool gem = below(philox(sc, NOSLOT, step, TAG_GEM, P.key).x, preac);
+    const bool gem = below(philox(lc, NOSLOT, step, TAG_GEM, P.key).x, preac);
     const u32 sb = partner[sc];
     if (LANE || lane_id() == 0) {
         st[4] += 1;
@@ -1254,7 +1287,7 @@ __device__ __noinline__ void ev_decay(const Params &P, Rec<T> *__restrict__ rec,
         }
     }
     if (gem) return;
-    const uint4 r = philox(sc, NOSLOT, step, TAG_DIR, P.key);
+    const uint4 r = philox(lc, NOSLOT, step, TAG_DIR, P.key);
     double e[3] = {0.0, 0.0, 0.0};
     if (DIM == 3) {
         const double z = 2.0 * u01(r.x) - 1.0, rho = sqrt(1.0 - z * z);
@@ -1293,7 +1326,14 @@ __device__ __noinline__ void ev_decay(const Params &P, Rec<T> *__restrict__ rec,
 // EV_LANE_MIN - 1 events run one per wave, more run one per lane.
 constexpr u32 EV_LANE_MIN = 4096;
 
-template <int DIM, class T, int NC>
+// the parameters of the replica of record i (a single system: its own)
+template <bool BATCH, class T> __device__ __forceinline__ const Params &ev_params(const Params &P, const Rec<T> *rec, u32 i)
+{
+    if constexpr (BATCH) return rep_params<true>(P, meta_slot(rec_meta(rec[i])));
+    else return P;
+}
+
+template <int DIM, class T, int NC, bool BATCH>
 __global__ __launch_bounds__(BLOCK) void k_events(const Params *__restrict__ Pd, Rec<T> *__restrict__ rec,
                                                    const PairEnt *__restrict__ list, const CandEnt *__restrict__ cand,
                                                    const u32 *__restrict__ ev, u32 *__restrict__ partner, Counters *C,
@@ -1307,15 +1347,25 @@ __global__ __launch_bounds__(BLOCK) void k_events(const Params *__restrict__ Pd,
     if (n >= EV_LANE_MIN) {
         for (u32 w = gtid(); w < n; w += gstride()) {
             const u32 e = ev[w];
-            if (e & EV_DECAY) ev_decay<DIM, T, NC, true>(P, rec, e & ~EV_DECAY, partner, step, C, dbg_d, st);
-            else ev_match<DIM, T, NC, true>(P, rec, list[e].a_idx, list[e].b_idx, cand[e].R0, partner, step, C, dbg_m, st);
+            if (e & EV_DECAY) {
+                const u32 i = e & ~EV_DECAY;
+                ev_decay<DIM, T, NC, true>(ev_params<BATCH>(P, rec, i), rec, i, partner, step, C, dbg_d, st);
+            } else {
+                ev_match<DIM, T, NC, true>(rep_params<BATCH>(P, cand[e].a_slot), rec, list[e].a_idx, list[e].b_idx, cand[e].R0,
+                                           partner, step, C, dbg_m, st);
+            }
         }
     } else {
         const u32 wave = (blockIdx.x * BLOCK + threadIdx.x) >> 6, nwaves = (gridDim.x * BLOCK) >> 6;
         for (u32 w = wave; w < n; w += nwaves) {
             const u32 e = ev[w];
-            if (e & EV_DECAY) ev_decay<DIM, T, NC, false>(P, rec, e & ~EV_DECAY, partner, step, C, dbg_d, st);
-            else ev_match<DIM, T, NC, false>(P, rec, list[e].a_idx, list[e].b_idx, cand[e].R0, partner, step, C, dbg_m, st);
+            if (e & EV_DECAY) {
+                const u32 i = e & ~EV_DECAY;
+                ev_decay<DIM, T, NC, false>(ev_params<BATCH>(P, rec, i), rec, i, partner, step, C, dbg_d, st);
+            } else {
+                ev_match<DIM, T, NC, false>(rep_params<BATCH>(P, cand[e].a_slot), rec, list[e].a_idx, list[e].b_idx, cand[e].R0,
+                                            partner, step, C, dbg_m, st);
+            }
         }
     }
     // counts: one atomic per counter and workgroup

@@ -99,3 +99,20 @@ def state_for(cfg: dict, seed: int = 0, scale: float = 1.0):
     f32 = cfg["precision"] != PREC_FP64
     sp, pos, red = uniform_state(n_a, n_b, box=box, dim=cfg["dim"], sigma=cfg["sigma"], seed=seed, f32=f32)
     return sp, pos, box, red
+
+
+def ensemble(n_rep: int = 4096, seed: int = 0, n_min: float = 1e3, n_max: float = 1e5, f32: bool = True):
+    """Replicas of the batched 3D workload: particle counts log-uniform in [n_min, n_max] and
+    kappa_a uniform in [0.01, 1] um^3/s, both drawn from PCG64(seed); half A, half B, uniform in
+    a periodic cube of edge (N/1000)^(1/3) um (rounded to binary32), every B closer than 5 nm
+    to an A redrawn; replica r is seeded 1000 + r and keyed r."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    counts = np.exp(rng.uniform(np.log(n_min), np.log(n_max), n_rep)).astype(np.int64)
+    kappas = rng.uniform(0.01, 1.0, n_rep)
+    reps = []
+    for r in range(n_rep):
+        n = int(counts[r])
+        box = float(np.float32((n / 1000.0) ** (1.0 / 3.0)))
+        sp, pos, _ = uniform_state(n // 2, n - n // 2, box=box, dim=3, sigma=0.005, seed=1000 + r, f32=f32)
+        reps.append(dict(species=sp, pos=pos, box=box, kappa=float(kappas[r]), replica=r))
+    return reps

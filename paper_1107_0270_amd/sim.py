@@ -43,6 +43,11 @@ class SimReaction(C.Structure):
                 ("sigma", C.c_double), ("kappa", C.c_double), ("k_off", C.c_double)]
 
 
+class SimReplica(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("species", C.c_void_p), ("pos", C.c_void_p), ("partner", C.c_void_p),
+                ("box", C.c_double * 3), ("kappa", C.c_double), ("replica", C.c_uint32)]
+
+
 class SimConfig(C.Structure):
     _fields_ = [("dim", C.c_int32), ("precision", C.c_int32), ("box", C.c_double * 3), ("dt", C.c_double),
                 ("seed", C.c_uint64), ("replica", C.c_uint32), ("n_terms", C.c_int32), ("eps_cut", C.c_double),
@@ -118,6 +123,8 @@ def lib():
     vp, u64, u32, i32 = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int32
     L.sim_create.argtypes = [C.POINTER(SimConfig), u64, vp, vp, vp, C.POINTER(vp)]
     L.sim_create.restype = C.c_int
+    L.sim_batch_create.argtypes = [C.POINTER(SimConfig), u32, C.POINTER(SimReplica), C.POINTER(vp)]
+    L.sim_batch_create.restype = C.c_int
     L.sim_step.argtypes = [vp, u32]
     L.sim_step.restype = C.c_int
     L.sim_read.argtypes = [vp, C.c_int, vp, u64, C.POINTER(u64)]
@@ -142,7 +149,29 @@ class Sim:
     def __init__(self, *, dim, box, dt, D, sigma, bc, species, pos, kappa=0.0, k_off=0.0,
                  precision=PREC_FP32_FP64NC, seed=0, replica=0, n_terms=12, eps_cut=1e-3, rcut=0.0, cell=0.0,
                  pair_search=PAIRS_AUTO, partner=None, debug=False, timing=False, debug_cap=0, stream=None):
+        self._config(dim=dim, box=box, dt=dt, D=D, sigma=sigma, bc=bc, species=species, pos=pos, kappa=kappa,
+                     k_off=k_off, precision=precision, seed=seed, replica=replica, n_terms=n_terms, eps_cut=eps_cut,
+                     rcut=rcut, cell=cell, pair_search=pair_search, debug=debug, timing=timing, debug_cap=debug_cap,
+                     stream=stream)
         L = lib()
+        cfg = self.cfg
+        sp = np.ascontiguousarray(species, dtype=np.int32)
+        self.n = len(sp)
+        ps = np.ascontiguousarray(pos, dtype=np.float64).ravel()
+        if self.dim in (2, 3) and ps.size != self.n * self.dim:
+            raise ValueError("pos must hold n * dim values")
+        pt = None if partner is None else np.ascontiguousarray(partner, dtype=np.uint32)
+        h = C.c_void_p()
+        rc = L.sim_create(C.byref(cfg), self.n, sp.ctypes.data, ps.ctypes.data,
+                          None if pt is None else pt.ctypes.data, C.byref(h))
+        if rc != SIM_OK:
+            raise SimError(rc, L.sim_last_error(None).decode())
+        self._h = h
+        self.slot_base = [0]
+
+    def _config(self, *, dim, box, dt, D, sigma, bc, species, pos, kappa=0.0, k_off=0.0,
+                precision=PREC_FP32_FP64NC, seed=0, replica=0, n_terms=12, eps_cut=1e-3, rcut=0.0, cell=0.0,
+                pair_search=PAIRS_AUTO, debug=False, timing=False, debug_cap=0, stream=None):
         cfg = SimConfig()
         cfg.dim, cfg.precision = int(dim), int(precision)
         bx = list(box) if np.ndim(box) else [float(box)] * int(dim)
@@ -163,18 +192,49 @@ class Sim:
         cfg.hip_stream = stream
         self.cfg = cfg
         self.dim = int(dim)
-        sp = np.ascontiguousarray(species, dtype=np.int32)
-        self.n = len(sp)
-        ps = np.ascontiguousarray(pos, dtype=np.float64).ravel()
-        if self.dim in (2, 3) and ps.size != self.n * self.dim:
-            raise ValueError("pos must hold n * dim values")
-        pt = None if partner is None else np.ascontiguousarray(partner, dtype=np.uint32)
+
+    @classmethod
+    def batch(cls, replicas, **shared):
+        """A handle stepping independent 3D replicas together (sim_batch_create).  ``replicas`` is a
+        list of dicts with ``species``, ``pos``, ``box`` and optional ``kappa``, ``replica`` and
+        ``partner`` (replica-local); ``shared`` takes the Sim keywords common to all (dim is 3).
+        Slots of replica r follow those of replicas 0..r-1 in every read (``self.slot_base``)."""
+        L = lib()
+        first = replicas[0]
+        self = cls.__new__(cls)
+        shared = dict(shared)
+        kappa0 = shared.pop("kappa", 0.0)
+        # a config exactly as the single-system constructor builds it, with replica 0's values
+        cfg_self = cls.__new__(cls)
+        cls._config(cfg_self, dim=3, box=first["box"], species=np.zeros(1, np.int32), pos=np.zeros(3),
+                    kappa=first.get("kappa", kappa0), **shared)
+        self.cfg, self._species, self._reaction = cfg_self.cfg, cfg_self._species, cfg_self._reaction
+        self.dim = 3
+        keep, reps = [], (SimReplica * len(replicas))()
+        bases, n = [], 0
+        for r, rd in enumerate(replicas):
+            sp = np.ascontiguousarray(rd["species"], dtype=np.int32)
+            ps = np.ascontiguousarray(rd["pos"], dtype=np.float64).ravel()
+            if ps.size != 3 * sp.size:
+                raise ValueError("pos must hold 3 n values")
+            pt = None if rd.get("partner") is None else np.ascontiguousarray(rd["partner"], dtype=np.uint32)
+            keep += [sp, ps, pt]
+            bx = list(rd["box"]) if np.ndim(rd["box"]) else [float(rd["box"])] * 3
+            reps[r].n = sp.size
+            reps[r].species, reps[r].pos = sp.ctypes.data, ps.ctypes.data
+            reps[r].partner = None if pt is None else pt.ctypes.data
+            for k in range(3):
+                reps[r].box[k] = float(bx[k])
+            reps[r].kappa = float(rd.get("kappa", kappa0))
+            reps[r].replica = int(rd.get("replica", r))
+            bases.append(n)
+            n += sp.size
         h = C.c_void_p()
-        rc = L.sim_create(C.byref(cfg), self.n, sp.ctypes.data, ps.ctypes.data,
-                          None if pt is None else pt.ctypes.data, C.byref(h))
+        rc = L.sim_batch_create(C.byref(self.cfg), len(replicas), reps, C.byref(h))
         if rc != SIM_OK:
             raise SimError(rc, L.sim_last_error(None).decode())
-        self._h = h
+        self._h, self.n, self.slot_base = h, n, bases
+        return self
 
     # ---- calls ------------------------------------------------------------
     def _check(self, rc):

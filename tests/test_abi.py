@@ -21,8 +21,8 @@ def _declared():
 
 
 def test_header_declares_the_boundary():
-    assert _declared() == sorted(["sim_create", "sim_step", "sim_read", "sim_load_state", "sim_eval_pairs",
-                                  "sim_eval_propagator", "sim_destroy", "sim_last_error"])
+    assert _declared() == sorted(["sim_create", "sim_batch_create", "sim_step", "sim_read", "sim_load_state",
+                                  "sim_eval_pairs", "sim_eval_propagator", "sim_destroy", "sim_last_error"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -49,7 +49,8 @@ int main(void) {
          offsetof(sim_config, reactions), offsetof(sim_config, debug_cap), offsetof(sim_config, hip_stream),
          offsetof(sim_config, pair_search),
          sizeof(sim_reaction), sizeof(sim_dbg_pair), sizeof(sim_dbg_diss));
-  printf("%zu %zu %zu\n", sizeof(sim_dbg_pick), sizeof(sim_dbg_match), sizeof(sim_kernel_time));
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(sim_dbg_pick), sizeof(sim_dbg_match), sizeof(sim_kernel_time),
+         sizeof(sim_replica), offsetof(sim_replica, box), offsetof(sim_replica, replica));
   return 0; }
 ''')
     exe = tmp_path / "probe"
@@ -60,7 +61,8 @@ int main(void) {
                    S.SimConfig.debug_cap.offset, S.SimConfig.hip_stream.offset, S.SimConfig.pair_search.offset,
                    C.sizeof(S.SimReaction),
                    S.PAIR_DT.itemsize, S.DISS_DT.itemsize]
-    assert [int(x) for x in b.split()] == [S.PICK_DT.itemsize, S.MATCH_DT.itemsize, 16]
+    assert [int(x) for x in b.split()] == [S.PICK_DT.itemsize, S.MATCH_DT.itemsize, 16, C.sizeof(S.SimReplica),
+                                          S.SimReplica.box.offset, S.SimReplica.replica.offset]
 
 
 def _args(**over):
@@ -102,3 +104,30 @@ def test_eval_pairs_rejects_null_arguments_on_the_host():
         pytest.skip("libgfbd.so not built")
     assert S.lib().sim_eval_pairs(None, 0, None, None, None, None) == S.SIM_EINVAL
     assert S.lib().sim_eval_propagator(None, 0, None, 0, 1, None, None) == S.SIM_EINVAL
+
+
+def _rep(n=4, box=1.0, kappa=0.1):
+    rng = np.random.default_rng(0)
+    return dict(species=np.array([0, 1] * (n // 2), np.int32), pos=rng.random((n, 3)) * box, box=box, kappa=kappa)
+
+
+@pytest.mark.parametrize("reps,over,code", [
+    ([], {}, S.SIM_EINVAL),                                            # no replicas
+    ([_rep(kappa=-1.0)], {}, S.SIM_EINVAL),                            # a replica's kappa
+    ([_rep(), _rep(box=0.1)], {"precision": S.PREC_FP32}, S.SIM_EINVAL),  # a replica's box not binary32
+    ([_rep(), dict(_rep(), species=np.array([0, 1, 9, 0], np.int32))], {}, S.SIM_EINVAL),
+])
+def test_batch_input_is_rejected_before_the_device(reps, over, code):
+    if not os.path.exists(S.LIB_PATH):
+        pytest.skip("libgfbd.so not built")
+    kw = dict(dt=1e-6, D=(1.0, 1.0, 0.5), sigma=0.005, bc=S.BC_RADIATION, k_off=1.0, precision=S.PREC_FP64)
+    kw.update(over)
+    if not reps:
+        cfg_holder = S.Sim.__new__(S.Sim)
+        S.Sim._config(cfg_holder, dim=3, box=1.0, species=np.zeros(1, np.int32), pos=np.zeros(3), **kw)
+        h = C.c_void_p()
+        assert S.lib().sim_batch_create(C.byref(cfg_holder.cfg), 0, None, C.byref(h)) == code
+        return
+    with pytest.raises(S.SimError) as e:
+        S.Sim.batch(reps, **kw)
+    assert e.value.code == code

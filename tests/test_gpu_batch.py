@@ -1,0 +1,73 @@
+"""Batches of independent replicas: every replica of a batch must follow exactly the trajectory
+it follows alone (same draws, same arithmetic), whatever the other replicas are.  Single-system
+trajectories are held to the oracle by test_gpu_parity.py."""
+import numpy as np
+import pytest
+
+from paper_1107_0270_amd import inputs as I
+from paper_1107_0270_amd import sim as S
+
+pytestmark = pytest.mark.gpu
+
+SHARED = dict(dt=1e-5, D=(1.0, 1.0, 0.5), sigma=0.005, bc=S.BC_RADIATION, k_off=2000.0, seed=21)
+
+
+def _replicas(counts, prec, seed=5):
+    rng = np.random.default_rng(seed)
+    reps = []
+    for r, n in enumerate(counts):
+        box = float(np.float32((n / 1000.0) ** (1.0 / 3.0)))  # the density of 500 A + 500 B per um^3
+        sp, pos, _ = I.uniform_state(n // 2, n - n // 2, box=box, dim=3, sigma=0.005, seed=100 + r,
+                                     f32=prec != S.PREC_FP64)
+        reps.append(dict(species=sp, pos=pos, box=box, kappa=float(rng.uniform(0.01, 1.0)), replica=7 + 3 * r))
+    return reps
+
+
+def _alone(rd, prec, steps, pair_search=S.PAIRS_AUTO):
+    sim = S.Sim(dim=3, box=rd["box"], species=rd["species"], pos=rd["pos"], kappa=rd["kappa"], replica=rd["replica"],
+                precision=prec, pair_search=pair_search, **SHARED)
+    sim.step(steps)
+    sp, pos, pt = sim.state()
+    st = sim.stats(total=True)
+    sim.close()
+    return sp, pos, pt, st
+
+
+@pytest.mark.parametrize("prec", [S.PREC_FP32_FP64NC, S.PREC_FP64])
+def test_each_replica_of_a_batch_runs_as_it_runs_alone(prec):
+    counts = [600, 2200, 1000, 3400, 1500]
+    reps = _replicas(counts, prec)
+    steps = 15
+    b = S.Sim.batch(reps, precision=prec, **SHARED)
+    b.step(steps)
+    sp, pos, pt = b.state()
+    tot = b.stats(total=True)
+    sums = {k: 0 for k in ("pairs", "matches", "react", "decay", "geminate")}
+    for r, rd in enumerate(reps):
+        lo, hi = b.slot_base[r], b.slot_base[r] + counts[r]
+        sp1, pos1, pt1, st1 = _alone(rd, prec, steps)
+        assert np.array_equal(sp[lo:hi], sp1), f"replica {r}: species differ"
+        live = sp1 <= S.SP_C
+        d = np.abs(pos[lo:hi][live] - pos1[live])
+        assert d.max() <= (0.0 if prec != S.PREC_FP64 else 1e-12), f"replica {r}: positions differ by {d.max()}"
+        c = sp1 == S.SP_C
+        assert np.array_equal(pt[lo:hi][c].astype(np.int64) - lo, pt1[c].astype(np.int64)), f"replica {r}: partners"
+        for k in sums:
+            sums[k] += st1[k]
+        print(f"replica {r}: n {counts[r]} kappa {rd['kappa']:.3f} reactions {st1['react']} decays {st1['decay']}")
+    for k in sums:
+        assert tot[k] == sums[k], (k, tot[k], sums[k])
+    assert sums["react"] > 0 and sums["decay"] > 0
+    b.close()
+
+
+def test_batch_of_one_is_the_single_system():
+    reps = _replicas([4000], S.PREC_FP32_FP64NC, seed=9)
+    b = S.Sim.batch(reps, precision=S.PREC_FP32_FP64NC, **SHARED)
+    b.step(10)
+    sp, pos, pt = b.state()
+    sp1, pos1, pt1, _ = _alone(reps[0], S.PREC_FP32_FP64NC, 10, pair_search=S.PAIRS_DIRECT)
+    assert np.array_equal(sp, sp1)
+    live = sp1 <= S.SP_C
+    assert np.array_equal(pos[live], pos1[live])
+    b.close()
