@@ -121,8 +121,9 @@ int sim_create(const sim_config *cfg, uint64_t n, const int32_t *species, const 
                const uint32_t *partner, sim_t **out);
 
 /* One replica of a batch: its own slots (n, species, positions, partners as in sim_create,
- * partner indices local to the replica), periodic box, intrinsic rate kappa_a and replica number
- * (folded into its Philox key). */
+ * partner indices local to the replica), periodic box, intrinsic rate kappa_a, replica number
+ * (folded into its Philox key) and own step counter (replicas may join at different points of
+ * their trajectories; a replica continued from a state read at its step s is created with s). */
 typedef struct {
     uint64_t n;
     const int32_t *species;
@@ -131,19 +132,21 @@ typedef struct {
     double box[3];
     double kappa;
     uint32_t replica;
+    uint32_t step;          /* the replica's own step counter at creation (its draws are keyed on it) */
 } sim_replica;
 
-/* Creates one handle that steps n_rep independent 3D replicas together: every step of the
+/* Creates one handle that steps n_rep independent replicas together: every step of the
  * algorithm of Sec. 3 runs once for all of them (one graph replay per step).  cfg supplies
  * what the replicas share (precision, dt, species D, sigma, boundary condition, k_off, seed,
  * eps_cut, cell, ...); cfg->box, cfg->replica and the reaction's kappa are taken per replica
- * from reps[].  Each replica gets its own r_cut, cell grid and draws, so its trajectory is the
- * one sim_create would give for it alone.  Afterwards the handle behaves like one system of
+ * from reps[].  Each replica gets its own r_cut, cell grid and draws (keyed on its replica
+ * number, local slots and own step), so its trajectory is the one sim_create would give for it
+ * alone.  Afterwards the handle behaves like one system of
  * sum(n) slots: replica r owns slots [n_0 + ... + n_{r-1}, + n_r) in every read, and partner
  * indices in sim_read / sim_load_state are global.  SIM_READ_DERIVED and SIM_READ_GRID
  * describe replica 0; sim_eval_pairs and sim_eval_propagator use replica 0's parameters.
- * Errors as sim_create (reported for the first replica that fails); SIM_EUNSUPPORTED unless
- * dim is 3. */
+ * pos of replica r holds n * dim values.  Errors as sim_create (reported for the first replica
+ * that fails). */
 int sim_batch_create(const sim_config *cfg, uint32_t n_rep, const sim_replica *reps, sim_t **out);
 
 /* Enqueues nsteps steps on the handle's stream and waits for them.  Without

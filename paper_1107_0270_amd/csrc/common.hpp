@@ -126,6 +126,7 @@ struct Params {
     // slot_base + n) and cells [cell_base, cell_base + own cell count) of
     // every species block.  A single system is replica 0 with both bases 0.
     u32 slot_base, cell_base;
+    u32 step_base;            // the replica's own step is the step counter minus this (mod 2^32)
     u32 n_rep;
     const u32 *rep_of_slot;   // replica of every slot (batches only)
     const Params *reps;       // per-replica parameters (batches only)

@@ -174,6 +174,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     std::vector<u32> rep_of_slot_h;
     Params *d_reps = nullptr;
     u32 *d_rep_of_slot = nullptr;
+    double *d_g2c_reps = nullptr;
     hipStream_t own_stream = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     uint32_t n_bricks = 0;
@@ -367,8 +368,8 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     // A batch of independent replicas (3D): each keeps its own box, kappa,
     // replica key, cut-off and grid; their slots and cells are laid out one
     // after the other.  The pair search is the direct one.
-    int init_batch(const std::vector<Model> &ms, const std::vector<uint64_t> &nr, const int32_t *sp, const double *pos,
-                   const uint32_t *pt)
+    int init_batch(const std::vector<Model> &ms, const std::vector<uint64_t> &nr, const std::vector<u32> &step0, const int32_t *sp,
+                   const double *pos, const uint32_t *pt)
     {
         M = ms[0];
         n = 0;
@@ -388,6 +389,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             if ((rc = setup_replica(ms[r], nr[r], sp + sbase, reps_h[r], ce, tests, nar))) return rc;
             reps_h[r].slot_base = (u32)sbase;
             reps_h[r].cell_base = (u32)cbase;
+            reps_h[r].step_base = 0u - step0[r];  // own step = counter (0 at creation) - base
             for (int k = 0; k < 3; ++k) rep_box[3 * r + k] = ms[r].box[k];
             for (uint64_t i = 0; i < nr[r]; ++i) rep_of_slot_h[sbase + i] = (u32)r;
             narrow = narrow && nar;
@@ -402,7 +404,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         P = reps_h[0];  // replica 0's physics; totals below
         P.n_cells = (u32)cbase;
         P.n_keys = 3u * P.n_cells;
-        P.slot_base = P.cell_base = 0;
+        P.slot_base = P.cell_base = P.step_base = 0;
         P.n_rep = (u32)R;
         P.cap = (u32)n;
         P.cap_pl = (u32)std::min<uint64_t>(std::max<uint64_t>(1u << 20, 4 * n), 1u << 30);
@@ -454,9 +456,17 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         if ((rc = alloc(dparams, 1))) return rc;
         HIPCHECK(hipMemcpyAsync(dparams, &P, sizeof(P), hipMemcpyHostToDevice, M.stream));  // P is final here
         if (batch) {
-            for (auto &q : reps_h) q.g2c = g2c;
-            HIPCHECK(hipMemcpyAsync(d_reps, reps_h.data(), sizeof(Params) * reps_h.size(), hipMemcpyHostToDevice, M.stream));
-            HIPCHECK(hipStreamSynchronize(M.stream));  // reps_h is host memory the copy reads
+            // each replica's 2D expansion constants (Q_rad depends on its h)
+            const size_t G = 4 * (MAXTERMS + 1), R = reps_h.size();
+            std::vector<double> g2all(G * R);
+            if ((rc = alloc(d_g2c_reps, G * R))) return rc;
+            for (size_t r = 0; r < R; ++r) {
+                h_g2_constants(reps_h[r].hh, &g2all[G * r]);
+                reps_h[r].g2c = d_g2c_reps + G * r;
+            }
+            HIPCHECK(hipMemcpyAsync(d_g2c_reps, g2all.data(), sizeof(double) * G * R, hipMemcpyHostToDevice, M.stream));
+            HIPCHECK(hipMemcpyAsync(d_reps, reps_h.data(), sizeof(Params) * R, hipMemcpyHostToDevice, M.stream));
+            HIPCHECK(hipStreamSynchronize(M.stream));  // g2all and reps_h are host memory the copies read
         }
         return load(0, sp, pos, pt);
     }
@@ -530,9 +540,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
 
     template <int NC2> void enqueue_step_n(int c)
     {
-        if constexpr (DIM == 3) {
-            if (batch) return enqueue_step_t<NC2, true>(c);
-        }
+        if (batch) return enqueue_step_t<NC2, true>(c);
         enqueue_step_t<NC2, false>(c);
     }
 
@@ -846,12 +854,12 @@ int make(const Model &M, uint64_t n, const int32_t *sp, const double *pos, const
 }
 
 template <int DIM, class T, int PM>
-int make_batch(const std::vector<Model> &ms, const std::vector<uint64_t> &nr, const int32_t *sp, const double *pos, const uint32_t *pt,
-               sim_t **out)
+int make_batch(const std::vector<Model> &ms, const std::vector<uint64_t> &nr, const std::vector<u32> &step0, const int32_t *sp,
+               const double *pos, const uint32_t *pt, sim_t **out)
 {
     Engine<DIM, T, PM> *e = new (std::nothrow) Engine<DIM, T, PM>();
     if (!e) { g_err = "host allocation failed"; return SIM_ENOMEM; }
-    const int rc = e->init_batch(ms, nr, sp, pos, pt);
+    const int rc = e->init_batch(ms, nr, step0, sp, pos, pt);
     if (rc) {
         g_err = e->err;
         delete e;
@@ -905,14 +913,15 @@ int sim_batch_create(const sim_config *cfg, uint32_t n_rep, const sim_replica *r
     if (!out) { g_err = "null output handle"; return SIM_EINVAL; }
     *out = nullptr;
     if (!cfg || !reps || n_rep == 0) { g_err = "null argument or no replicas"; return SIM_EINVAL; }
-    if (cfg->dim != 3) { g_err = "batches are 3D"; return SIM_EUNSUPPORTED; }
     std::vector<Model> ms(n_rep);
     std::vector<uint64_t> nr(n_rep);
+    std::vector<u32> step0(n_rep);
     uint64_t total = 0;
     for (uint32_t r = 0; r < n_rep; ++r) {
         // each replica is checked as a system of its own: its box, kappa and replica key
         sim_config c = *cfg;
         for (int k = 0; k < 3; ++k) c.box[k] = reps[r].box[k];
+        if (cfg->dim != 2 && cfg->dim != 3) { g_err = "dim must be 2 or 3"; return SIM_EINVAL; }
         c.replica = reps[r].replica;
         sim_reaction rx = cfg->reactions ? cfg->reactions[0] : sim_reaction{};
         rx.kappa = reps[r].kappa;
@@ -920,27 +929,34 @@ int sim_batch_create(const sim_config *cfg, uint32_t n_rep, const sim_replica *r
         const int rc = validate(&c, reps[r].n, reps[r].species, reps[r].pos, reps[r].partner, ms[r]);
         if (rc) return rc;
         nr[r] = reps[r].n;
+        step0[r] = reps[r].step;
         total += reps[r].n;
     }
     if (total > SLOT_MASK) { g_err = "more than 2^29 slots in the batch"; return SIM_EINVAL; }
     // global arrays: replica r's slots follow those of replicas 0..r-1; partners become global
+    const int d = cfg->dim;
     std::vector<int32_t> sp(total);
-    std::vector<double> pos(total * 3);
+    std::vector<double> pos(total * d);
     std::vector<uint32_t> pt(total, 0xFFFFFFFFu);
     uint64_t base = 0;
     for (uint32_t r = 0; r < n_rep; ++r) {
         for (uint64_t i = 0; i < nr[r]; ++i) {
             sp[base + i] = reps[r].species[i];
-            for (int k = 0; k < 3; ++k) pos[3 * (base + i) + k] = reps[r].pos[3 * i + k];
+            for (int k = 0; k < d; ++k) pos[d * (base + i) + k] = reps[r].pos[d * i + k];
             if (reps[r].partner && reps[r].species[i] == SIM_SP_C && reps[r].partner[i] != 0xFFFFFFFFu)
                 pt[base + i] = (uint32_t)(base + reps[r].partner[i]);
         }
         base += nr[r];
     }
     const Model &M = ms[0];
-    if (M.prec == SIM_PREC_FP64) return make_batch<3, double, PM_F64>(ms, nr, sp.data(), pos.data(), pt.data(), out);
-    if (M.prec == SIM_PREC_FP32) return make_batch<3, float, PM_F32>(ms, nr, sp.data(), pos.data(), pt.data(), out);
-    return make_batch<3, float, PM_F32NC>(ms, nr, sp.data(), pos.data(), pt.data(), out);
+    if (d == 3) {
+        if (M.prec == SIM_PREC_FP64) return make_batch<3, double, PM_F64>(ms, nr, step0, sp.data(), pos.data(), pt.data(), out);
+        if (M.prec == SIM_PREC_FP32) return make_batch<3, float, PM_F32>(ms, nr, step0, sp.data(), pos.data(), pt.data(), out);
+        return make_batch<3, float, PM_F32NC>(ms, nr, step0, sp.data(), pos.data(), pt.data(), out);
+    }
+    if (M.prec == SIM_PREC_FP64) return make_batch<2, double, PM_F64>(ms, nr, step0, sp.data(), pos.data(), pt.data(), out);
+    if (M.prec == SIM_PREC_FP32) return make_batch<2, float, PM_F32>(ms, nr, step0, sp.data(), pos.data(), pt.data(), out);
+    return make_batch<2, float, PM_F32NC>(ms, nr, step0, sp.data(), pos.data(), pt.data(), out);
 }
 
 int sim_eval_pairs(sim_t *h, uint64_t n, const double *R, const double *R0, double *penc, double *preac)

@@ -97,6 +97,12 @@ template <bool BATCH> __device__ __forceinline__ u32 local_slot(const Params &Q,
     if constexpr (BATCH) return slot - Q.slot_base;
     else return slot;
 }
+// The replica's own step (replicas may join a batch at different steps).
+template <bool BATCH> __device__ __forceinline__ u32 local_step(const Params &Q, u32 step)
+{
+    if constexpr (BATCH) return step - Q.step_base;
+    else return step;
+}
 
 // x' = wrap(x + displacement) for the record of (replica-local) slot `slot`.
 template <int DIM, class T> __device__ inline Rec<T> moved(const Params &P, const Rec<T> &r, u32 slot, u32 sp, u32 step)
@@ -234,7 +240,7 @@ __global__ __launch_bounds__(BLOCK) void k_move_count(Params P, const Rec<T> *__
         if (alive) {
             const u32 slot = meta_slot(m);
             const Params &Q = rep_params<BATCH>(P, slot);
-            const Rec<T> q = moved<DIM, T>(Q, r, local_slot<BATCH>(Q, slot), sp, step);
+            const Rec<T> q = moved<DIM, T>(Q, r, local_slot<BATCH>(Q, slot), sp, local_step<BATCH>(Q, step));
             tmp[i] = q;
             key = bucket_key<DIM, T, BATCH>(P, Q, sp, q);
         } else if (valid) {
@@ -977,8 +983,9 @@ __global__ __launch_bounds__(BLOCK) void k_pair_eval(Params P, const Rec<T> *__r
         const u32 sa = meta_slot(rec_meta(ra)), sb = meta_slot(rec_meta(rb));
         const Params &Q = rep_params<BATCH>(P, sa);  // A and B of a pair share their replica
         double dA[3];
-        displacement<DIM, T>(Q, local_slot<BATCH>(Q, sa), SP_A, step, dA);
-        const PairQ q = pair_quantities<DIM, T, PM, NC>(Q, ra, rb, local_slot<BATCH>(Q, sa), local_slot<BATCH>(Q, sb), dA, step);
+        const u32 ls = local_step<BATCH>(Q, step);
+        displacement<DIM, T>(Q, local_slot<BATCH>(Q, sa), SP_A, ls, dA);
+        const PairQ q = pair_quantities<DIM, T, PM, NC>(Q, ra, rb, local_slot<BATCH>(Q, sa), local_slot<BATCH>(Q, sb), dA, ls);
         st[0] += 1;
         st[1] += q.cand;
         st[2] += q.overlap;
@@ -1080,7 +1087,7 @@ __global__ __launch_bounds__(BLOCK) void k_select_a(Params P, const PairEnt *__r
         u32 win = k;
         if (count > 1) {
             const Params &Q = rep_params<BATCH>(P, me.a_slot);
-            const double U = u01(philox(local_slot<BATCH>(Q, me.a_slot), NOSLOT, step, TAG_SELA, Q.key).x);
+            const double U = u01(philox(local_slot<BATCH>(Q, me.a_slot), NOSLOT, local_step<BATCH>(Q, step), TAG_SELA, Q.key).x);
             win = choose_in_chain(h, nextA, count, U, [&](u32 e) { return cand[e].b_slot; }, [&](u32 e) { return cand[e].p; });
             if (win == NOSLOT) win = k;
         }
@@ -1123,7 +1130,8 @@ __global__ __launch_bounds__(BLOCK) void k_select_b(Params P, const PairEnt *__r
         for (u32 i = beg + t0; i < end; i += ts) {
             const u32 sc = meta_slot(rec_meta(rec[i]));
             const Params &Q = rep_params<BATCH>(P, sc);
-            if (below(philox(local_slot<BATCH>(Q, sc), NOSLOT, step, TAG_UNI, Q.key).x, P.p_uni)) ev[atomicAdd(&C->n_ev, 1u)] = EV_DECAY | i;
+            if (below(philox(local_slot<BATCH>(Q, sc), NOSLOT, local_step<BATCH>(Q, step), TAG_UNI, Q.key).x, P.p_uni))
+                ev[atomicAdd(&C->n_ev, 1u)] = EV_DECAY | i;
         }
         return;
     }
@@ -1141,7 +1149,7 @@ __global__ __launch_bounds__(BLOCK) void k_select_b(Params P, const PairEnt *__r
         u32 win = k;
         if (count > 1) {
             const Params &Q = rep_params<BATCH>(P, cand[k].b_slot);
-            const double U = u01(philox(local_slot<BATCH>(Q, cand[k].b_slot), NOSLOT, step, TAG_SELB, Q.key).x);
+            const double U = u01(philox(local_slot<BATCH>(Q, cand[k].b_slot), NOSLOT, local_step<BATCH>(Q, step), TAG_SELB, Q.key).x);
             win = choose_in_chain(h, nextB, count, U, [&](u32 e) { return cand[e].a_slot; }, [&](u32 e) { return cand[e].p; });
             if (win == NOSLOT) win = k;
         }
@@ -1198,6 +1206,7 @@ __device__ __noinline__ void ev_match(const Params &P, Rec<T> *__restrict__ rec,
     Rec<T> ra = rec[ia], rb = rec[ib];
     const u32 sa = meta_slot(rec_meta(ra)), sb = meta_slot(rec_meta(rb));
     const u32 la = sa - P.slot_base, lb = sb - P.slot_base;  // the draws are keyed on replica-local slots
+    step -= P.step_base;                                       // and on the replica's own step
     const double xa[3] = {(double)ra.x, (double)ra.y, (double)ra.z};
     const double xb[3] = {(double)rb.x, (double)rb.y, (double)rb.z};
     double rv[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
@@ -1266,6 +1275,7 @@ __device__ __noinline__ void ev_decay(const Params &P, Rec<T> *__restrict__ rec,
 #pragma clang fp contract(off)
     const Rec<T> rc = rec[i];
     const u32 sc = meta_slot(rec_meta(rc)), lc = sc - P.slot_base;
+    step -= P.step_base;
     u32 att = 0, hits = 0;
     const double Rpp = LANE ? sample_radius_lane<DIM, NC>(P, 1.0, lc, NOSLOT, step, TAG_DPROP, &att, &hits)
                             : sample_radius_wave<DIM, NC>(P, 1.0, lc, NOSLOT, step, TAG_DPROP, &att, &hits);

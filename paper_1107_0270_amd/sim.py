@@ -45,7 +45,7 @@ class SimReaction(C.Structure):
 
 class SimReplica(C.Structure):
     _fields_ = [("n", C.c_uint64), ("species", C.c_void_p), ("pos", C.c_void_p), ("partner", C.c_void_p),
-                ("box", C.c_double * 3), ("kappa", C.c_double), ("replica", C.c_uint32)]
+                ("box", C.c_double * 3), ("kappa", C.c_double), ("replica", C.c_uint32), ("step", C.c_uint32)]
 
 
 class SimConfig(C.Structure):
@@ -195,9 +195,10 @@ class Sim:
 
     @classmethod
     def batch(cls, replicas, **shared):
-        """A handle stepping independent 3D replicas together (sim_batch_create).  ``replicas`` is a
-        list of dicts with ``species``, ``pos``, ``box`` and optional ``kappa``, ``replica`` and
-        ``partner`` (replica-local); ``shared`` takes the Sim keywords common to all (dim is 3).
+        """A handle stepping independent replicas together (sim_batch_create).  ``replicas`` is a
+        list of dicts with ``species``, ``pos``, ``box`` and optional ``kappa``, ``replica``, ``step``
+        and ``partner`` (replica-local); ``shared`` takes the Sim keywords common to all (``dim``,
+        default 3).
         Slots of replica r follow those of replicas 0..r-1 in every read (``self.slot_base``)."""
         L = lib()
         first = replicas[0]
@@ -206,20 +207,22 @@ class Sim:
         kappa0 = shared.pop("kappa", 0.0)
         # a config exactly as the single-system constructor builds it, with replica 0's values
         cfg_self = cls.__new__(cls)
-        cls._config(cfg_self, dim=3, box=first["box"], species=np.zeros(1, np.int32), pos=np.zeros(3),
+        dim = int(shared.pop("dim", 3))
+        cls._config(cfg_self, dim=dim, box=first["box"], species=np.zeros(1, np.int32), pos=np.zeros(dim),
                     kappa=first.get("kappa", kappa0), **shared)
         self.cfg, self._species, self._reaction = cfg_self.cfg, cfg_self._species, cfg_self._reaction
-        self.dim = 3
+        self.dim = dim
         keep, reps = [], (SimReplica * len(replicas))()
         bases, n = [], 0
         for r, rd in enumerate(replicas):
             sp = np.ascontiguousarray(rd["species"], dtype=np.int32)
             ps = np.ascontiguousarray(rd["pos"], dtype=np.float64).ravel()
-            if ps.size != 3 * sp.size:
-                raise ValueError("pos must hold 3 n values")
+            if ps.size != dim * sp.size:
+                raise ValueError("pos must hold n * dim values")
             pt = None if rd.get("partner") is None else np.ascontiguousarray(rd["partner"], dtype=np.uint32)
             keep += [sp, ps, pt]
-            bx = list(rd["box"]) if np.ndim(rd["box"]) else [float(rd["box"])] * 3
+            bx = list(rd["box"]) if np.ndim(rd["box"]) else [float(rd["box"])] * dim
+            bx = bx + [1.0] * (3 - len(bx))
             reps[r].n = sp.size
             reps[r].species, reps[r].pos = sp.ctypes.data, ps.ctypes.data
             reps[r].partner = None if pt is None else pt.ctypes.data
@@ -227,6 +230,7 @@ class Sim:
                 reps[r].box[k] = float(bx[k])
             reps[r].kappa = float(rd.get("kappa", kappa0))
             reps[r].replica = int(rd.get("replica", r))
+            reps[r].step = int(rd.get("step", 0))
             bases.append(n)
             n += sp.size
         h = C.c_void_p()

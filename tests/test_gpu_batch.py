@@ -71,3 +71,72 @@ def test_batch_of_one_is_the_single_system():
     live = sp1 <= S.SP_C
     assert np.array_equal(pos[live], pos1[live])
     b.close()
+
+
+def test_2d_batch_replicas_run_as_alone():
+    shared2 = dict(dim=2, dt=5e-6, D=(0.1, 0.1, 0.05), sigma=0.005, bc=S.BC_RADIATION, k_off=2000.0, seed=3,
+                   precision=S.PREC_FP32_FP64NC)
+    rng = np.random.default_rng(2)
+    reps = []
+    for r, n in enumerate([1500, 4000, 2500]):
+        box = float(np.float32((n / 1250.0) ** 0.5))
+        sp, pos, _ = I.uniform_state(n // 2, n - n // 2, box=box, dim=2, sigma=0.005, seed=50 + r, f32=True)
+        reps.append(dict(species=sp, pos=pos, box=box, kappa=float(rng.uniform(0.01, 0.1)), replica=r))
+    b = S.Sim.batch(reps, **shared2)
+    b.step(12)
+    sp, pos, pt = b.state()
+    for r, rd in enumerate(reps):
+        kw = dict(shared2)
+        kw.pop("dim")
+        a = S.Sim(dim=2, box=rd["box"], species=rd["species"], pos=rd["pos"], kappa=rd["kappa"], replica=rd["replica"], **kw)
+        a.step(12)
+        sp1, pos1, pt1 = a.state()
+        a.close()
+        lo, hi = b.slot_base[r], b.slot_base[r] + len(rd["species"])
+        assert np.array_equal(sp[lo:hi], sp1)
+        live = sp1 <= S.SP_C
+        assert np.array_equal(pos[lo:hi][live], pos1[live])
+    b.close()
+
+
+def test_replicas_joining_at_their_own_steps():
+    # a replica continued inside a batch from a state read at its step s follows the
+    # uninterrupted trajectory: the draws are keyed on its own step
+    prec = S.PREC_FP32_FP64NC
+    reps = _replicas([1200, 2600, 1800], prec, seed=11)
+    # uninterrupted runs: 10 steps each
+    ref = [_alone(rd, prec, 10) for rd in reps]
+    # replica r first runs alone for s_r steps, then all continue together
+    pre = [3, 0, 7]
+    cont = []
+    for rd, s in zip(reps, pre):
+        a = S.Sim(dim=3, box=rd["box"], species=rd["species"], pos=rd["pos"], kappa=rd["kappa"], replica=rd["replica"],
+                  precision=prec, **SHARED)
+        a.step(s)
+        sp, pos, pt = a.state()
+        a.close()
+        cont.append(dict(rd, species=sp, pos=pos, partner=np.where(sp == S.SP_C, pt, 0xFFFFFFFF), step=s))
+    # the batch steps until replica 1 (no head start) has 10 steps; others get extra runs below
+    b = S.Sim.batch(cont, precision=prec, **SHARED)
+    b.step(3)
+    sp, pos, pt = b.state()
+    # replica 2 has now done 7 + 3 = 10 steps
+    lo, hi = b.slot_base[2], b.slot_base[2] + 1800
+    assert np.array_equal(sp[lo:hi], ref[2][0])
+    live = ref[2][0] <= S.SP_C
+    assert np.array_equal(pos[lo:hi][live], ref[2][1][live])
+    b.step(4)
+    sp, pos, pt = b.state()
+    lo, hi = b.slot_base[0], b.slot_base[0] + 1200  # 3 + 7 = 10 steps
+    assert np.array_equal(sp[lo:hi], ref[0][0])
+    live = ref[0][0] <= S.SP_C
+    assert np.array_equal(pos[lo:hi][live], ref[0][1][live])
+    b.step(3)
+    sp, pos, pt = b.state()
+    lo, hi = b.slot_base[1], b.slot_base[1] + 2600  # 0 + 10 steps
+    assert np.array_equal(sp[lo:hi], ref[1][0])
+    live = ref[1][0] <= S.SP_C
+    assert np.array_equal(pos[lo:hi][live], ref[1][1][live])
+    c = ref[1][0] == S.SP_C
+    assert np.array_equal(pt[lo:hi][c].astype(np.int64) - lo, ref[1][2][c].astype(np.int64))
+    b.close()
