@@ -149,6 +149,35 @@ typedef struct {
  * that fails). */
 int sim_batch_create(const sim_config *cfg, uint32_t n_rep, const sim_replica *reps, sim_t **out);
 
+/* Continuous batching.  A pool is a batch created empty, with device memory for slot_cap
+ * slots, cell_cap cells (over all members; a member takes its own cell grid, about one cell
+ * per B, at most n) and rep_cap members.  Systems join it (sim_pool_admit) and leave it
+ * (sim_pool_retire) between steps; each member owns a contiguous range of slots and of cells
+ * while it is in, and every sim_step advances all members together (one graph replay per
+ * step).  cfg supplies what the members share, as for sim_batch_create; cfg->box must be a
+ * valid box for the configuration (it is checked like a system's and otherwise unused).
+ * Returns SIM_EINVAL for capacities outside [1, 2^29) slots, [1, 2^28] cells or [1, 2^20]
+ * members, SIM_ENOMEM if the device memory cannot be had, other errors as sim_create. */
+int sim_pool_create(const sim_config *cfg, uint64_t slot_cap, uint64_t cell_cap, uint32_t rep_cap, sim_t **out);
+
+/* Adds one system to the pool: rep as for sim_batch_create (species, positions, partners local
+ * to it, box, kappa, replica number and its own step counter, all copied).  Its trajectory is
+ * the one sim_create would give it alone from that state and step, whatever else is in the
+ * pool and whenever it joins.  *member receives its entry, valid until it is retired.
+ * SIM_ECAPACITY if no member entry, no contiguous range of rep->n slots or of its cells is free
+ * (nothing changes then: retire members or wait); SIM_EINVAL for an invalid state or box;
+ * SIM_ESTATE if h is not a pool.  Synchronises the pool's stream. */
+int sim_pool_admit(sim_t *h, const sim_replica *rep, uint32_t *member);
+
+/* Removes a member; its slots and cells are free for later admissions.  SIM_EINVAL if member
+ * is not a current entry; SIM_ESTATE if h is not a pool.  Synchronises the pool's stream. */
+int sim_pool_retire(sim_t *h, uint32_t member);
+
+/* sim_read for one member: SIM_READ_POS, SIM_READ_SPECIES, SIM_READ_PARTNER (indices local to
+ * the member) or SIM_READ_COUNTS, over its own slots in the layout it was admitted with.
+ * SIM_EINVAL for another selector or an unknown member. */
+int sim_pool_read(sim_t *h, uint32_t member, int what, void *dst, uint64_t cap_bytes, uint64_t *written);
+
 /* Enqueues nsteps steps on the handle's stream and waits for them.  Without
  * debug or timing, each step is one replay of a captured HIP graph.  The
  * capacity flags are read back once at the end of the call, so SIM_ECAPACITY

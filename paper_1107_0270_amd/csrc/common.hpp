@@ -151,7 +151,8 @@ struct Counters {
     u32 n_dbg[4];   // pairs, picks, matches, dissociations logged this step
     u32 n_ev;       // events (matched pairs and decays) queued this step
     u32 n_sorted;   // leading records whose bucket keys the last binning noted
-    u32 pad[4];
+    u32 n_kept;     // records kept by a pool compaction (zero between compactions)
+    u32 pad[3];
     u64 stats[ST_N];
     u64 stats_last[ST_N];
     u64 stats_sum[ST_N];

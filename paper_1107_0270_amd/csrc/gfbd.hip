@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -117,6 +118,9 @@ struct sim {
     virtual int load(uint64_t step, const int32_t *sp, const double *pos, const uint32_t *partner) = 0;
     virtual int eval_pairs(uint64_t n, const double *R, const double *R0, double *penc, double *preac) = 0;
     virtual int eval_prop(uint64_t n, const double *R0, uint32_t step, int wave, double *Rpp, uint32_t *attempts) = 0;
+    virtual int admit(const sim_replica &, uint32_t *) { return fail(SIM_ESTATE, "not a pool"); }
+    virtual int retire(uint32_t) { return fail(SIM_ESTATE, "not a pool"); }
+    virtual int read_member(uint32_t, int, void *, uint64_t, uint64_t *) { return fail(SIM_ESTATE, "not a pool"); }
     int fail(int code, const std::string &msg)
     {
         err = msg;
@@ -150,6 +154,49 @@ struct Model {
     hipStream_t stream;
 };
 
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+int validate_box(int dim, int prec, const double *box);
+int validate_state(int dim, bool reversible, uint64_t n, const int32_t *sp, const double *pos, const uint32_t *pt);
+
+// First-fit allocator of index ranges in [0, cap) (the slots and cells of a
+// pool), merging neighbours on release.
+struct RangeAlloc {
+    std::map<uint64_t, uint64_t> free_;  // start -> length
+    void reset(uint64_t cap)
+    {
+        free_.clear();
+        if (cap) free_[0] = cap;
+    }
+    bool take(uint64_t len, uint64_t &at)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < len) continue;
+            at = it->first;
+            const uint64_t rest = it->second - len;
+            free_.erase(it);
+            if (rest) free_[at + len] = rest;
+            return true;
+        }
+        return false;
+    }
+    void give(uint64_t at, uint64_t len)
+    {
+        auto it = free_.emplace(at, len).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && at + len == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
 template <int DIM, class T, int PM> struct Engine final : sim {
     Model M;
     Params P;
@@ -175,6 +222,10 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     Params *d_reps = nullptr;
     u32 *d_rep_of_slot = nullptr;
     double *d_g2c_reps = nullptr;
+    // pools: members join and leave between steps
+    bool pool = false;
+    std::vector<uint64_t> member_n;  // slots of each member entry, 0 if the entry is free
+    RangeAlloc slot_free, cell_free;
     hipStream_t own_stream = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     uint32_t n_bricks = 0;
@@ -423,6 +474,43 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         return finish_init(sp, pos, pt);
     }
 
+    // A pool: an empty batch with room for slot_cap slots, cell_cap cells and
+    // rep_cap members.  The configuration's box stands in for the members'
+    // boxes in the shared fields; members bring their own.
+    int init_pool(const Model &m, uint64_t slot_cap, uint64_t cell_cap, uint32_t rep_cap)
+    {
+        M = m;
+        n = slot_cap;
+        int rc;
+        if ((rc = open_stream())) return rc;
+        batch = pool = true;
+        if ((rc = setup_replica(M, 0, nullptr, P, cell_edge, pair_tests, narrow))) return rc;
+        narrow = true;  // until a member needs the general pair search
+        reps_h.assign(rep_cap, P);
+        member_n.assign(rep_cap, 0);
+        rep_box.assign(3 * (size_t)rep_cap, 1.0);
+        slot_free.reset(slot_cap);
+        cell_free.reset(cell_cap);
+        P.n_cells = (u32)cell_cap;
+        P.n_keys = 3u * P.n_cells;
+        P.slot_base = P.cell_base = P.step_base = 0;
+        P.n_rep = rep_cap;
+        P.cap = (u32)n;
+        P.cap_pl = (u32)std::min<uint64_t>(std::max<uint64_t>(1u << 20, 4 * n), 1u << 30);
+        P.tiled = 0;
+        if ((rc = alloc(d_reps, rep_cap)) || (rc = alloc(d_rep_of_slot, n))) return rc;
+        P.reps = d_reps;
+        P.rep_of_slot = d_rep_of_slot;
+        for (auto &q : reps_h) {
+            q.cap = P.cap;
+            q.cap_pl = P.cap_pl;
+            q.n_rep = P.n_rep;
+            q.reps = d_reps;
+            q.rep_of_slot = d_rep_of_slot;
+        }
+        return finish_init(nullptr, nullptr, nullptr);
+    }
+
     // Buffers, constants and the initial state (P final apart from g2c).
     int finish_init(const int32_t *sp, const double *pos, const uint32_t *pt)
     {
@@ -468,11 +556,30 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             HIPCHECK(hipMemcpyAsync(d_reps, reps_h.data(), sizeof(Params) * R, hipMemcpyHostToDevice, M.stream));
             HIPCHECK(hipStreamSynchronize(M.stream));  // g2all and reps_h are host memory the copies read
         }
+        if (pool) return start_counters(0, 0);
         return load(0, sp, pos, pt);
+    }
+
+    // Counters of a freshly loaded state with `live` records at step step0.
+    int start_counters(uint64_t live, uint64_t step0)
+    {
+        Counters c;
+        std::memset(&c, 0, sizeof(c));
+        c.n_rec = (u32)live;
+        c.n_live = (u32)live;
+        c.step = (u32)step0;
+        HIPCHECK(hipMemcpyAsync(ctr, &c, sizeof(c), hipMemcpyHostToDevice, M.stream));
+        HIPCHECK(hipMemsetAsync(headA, 0, sizeof(u64) * n, M.stream));  // no chain survives a reload
+        HIPCHECK(hipMemsetAsync(headB, 0, sizeof(u64) * n, M.stream));
+        HIPCHECK(hipStreamSynchronize(M.stream));
+        cur = 0;
+        stepno = step0;
+        return SIM_OK;
     }
 
     int load(uint64_t step0, const int32_t *sp, const double *pos, const uint32_t *pt) override
     {
+        if (pool) return fail(SIM_ESTATE, "a pool's members are loaded by sim_pool_admit");
         std::vector<Rec<T>> h(n);
         std::vector<u32> hp(n, NOSLOT);
         uint64_t live = 0;
@@ -485,21 +592,168 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             r.z = DIM == 3 ? h_wrap_store<T>(pos[i * DIM + 2], bx[2]) : (T)0;
             rec_set_meta(r, meta_make((u32)sp[i], (u32)i));
             h[live++] = r;
-            if (sp[i] == SIM_SP_C) hp[i] = pt[i];
+            if (sp[i] == SIM_SP_C && pt) hp[i] = pt[i];
         }
         HIPCHECK(hipMemcpyAsync(rec[0], h.data(), sizeof(Rec<T>) * live, hipMemcpyHostToDevice, M.stream));
         HIPCHECK(hipMemcpyAsync(partner, hp.data(), sizeof(u32) * n, hipMemcpyHostToDevice, M.stream));
-        Counters c;
-        std::memset(&c, 0, sizeof(c));
-        c.n_rec = (u32)live;
-        c.n_live = (u32)live;
-        c.step = (u32)step0;
-        HIPCHECK(hipMemcpyAsync(ctr, &c, sizeof(c), hipMemcpyHostToDevice, M.stream));
-        HIPCHECK(hipMemsetAsync(headA, 0, sizeof(u64) * n, M.stream));  // no chain survives a reload
-        HIPCHECK(hipMemsetAsync(headB, 0, sizeof(u64) * n, M.stream));
+        return start_counters(live, step0);
+    }
+
+    // ---- pools ------------------------------------------------------------
+    int admit(const sim_replica &rp, uint32_t *member) override
+    {
+        if (!pool) return fail(SIM_ESTATE, "not a pool");
+        int rc;
+        if ((rc = validate_box(DIM, M.prec, rp.box)) || (rc = validate_state(DIM, M.k_off > 0.0, rp.n, rp.species, rp.pos, rp.partner)))
+            return fail(rc, g_err);
+        if (!finite_nonneg(rp.kappa)) return fail(SIM_EINVAL, "kappa must be >= 0");
+        uint32_t idx = 0;
+        while (idx < member_n.size() && member_n[idx]) ++idx;
+        if (idx == member_n.size()) return fail(SIM_ECAPACITY, "every member entry is taken");
+        Model mr = M;
+        for (int k = 0; k < 3; ++k) mr.box[k] = k < DIM ? rp.box[k] : 1.0;
+        mr.kappa = rp.kappa;
+        mr.replica = rp.replica;
+        Params Q;
+        double ce = 0.0, tests = 0.0;
+        bool nar = true;
+        if ((rc = setup_replica(mr, rp.n, rp.species, Q, ce, tests, nar))) return rc;
+        uint64_t s0 = 0, c0 = 0;
+        if (!slot_free.take(rp.n, s0)) return fail(SIM_ECAPACITY, "no free range of slots");
+        if (!cell_free.take(Q.n_cells, c0)) {
+            slot_free.give(s0, rp.n);
+            return fail(SIM_ECAPACITY, "no free range of cells");
+        }
+        rc = place(idx, rp, mr, Q, s0, c0);
+        if (rc) {
+            slot_free.give(s0, rp.n);
+            cell_free.give(c0, Q.n_cells);
+            return rc;
+        }
+        if (narrow && !nar) {  // the graphs were built for the narrow pair search
+            narrow = false;
+            for (auto &g : gexec)
+                if (g) {
+                    (void)hipGraphExecDestroy(g);
+                    g = nullptr;
+                }
+        }
+        *member = idx;
+        return SIM_OK;
+    }
+
+    // Writes member idx's parameters, slot ownership, partners and records.
+    int place(uint32_t idx, const sim_replica &rp, const Model &mr, Params &Q, uint64_t s0, uint64_t c0)
+    {
+        const uint64_t m = rp.n;
+        Q.slot_base = (u32)s0;
+        Q.cell_base = (u32)c0;
+        Q.step_base = (u32)stepno - rp.step;  // the member's own step = pool step - base
+        Q.cap = P.cap;
+        Q.cap_pl = P.cap_pl;
+        Q.n_rep = P.n_rep;
+        Q.reps = d_reps;
+        Q.rep_of_slot = d_rep_of_slot;
+        const size_t G = 4 * (MAXTERMS + 1);
+        Q.g2c = d_g2c_reps + G * idx;
+        std::vector<double> g2h(G);
+        h_g2_constants(Q.hh, g2h.data());
+        std::vector<Rec<T>> h;
+        h.reserve(m);
+        std::vector<u32> hp(m, NOSLOT), ho(m, idx);
+        for (uint64_t i = 0; i < m; ++i) {
+            const int sp = rp.species[i];
+            if (sp > SIM_SP_C) continue;
+            Rec<T> r;
+            r.x = h_wrap_store<T>(rp.pos[i * DIM + 0], mr.box[0]);
+            r.y = h_wrap_store<T>(rp.pos[i * DIM + 1], mr.box[1]);
+            r.z = DIM == 3 ? h_wrap_store<T>(rp.pos[i * DIM + 2], mr.box[2]) : (T)0;
+            rec_set_meta(r, meta_make((u32)sp, (u32)(s0 + i)));
+            h.push_back(r);
+            if (sp == SIM_SP_C && rp.partner && rp.partner[i] < m) hp[i] = (u32)(s0 + rp.partner[i]);
+        }
+        // the records go after the current ones; records of members that left
+        // stay (dead) until the next binning, so make room if they crowd the buffer
+        u32 n_rec = 0;
+        HIPCHECK(hipMemcpyAsync(&n_rec, &ctr->n_rec, sizeof(u32), hipMemcpyDeviceToHost, M.stream));
         HIPCHECK(hipStreamSynchronize(M.stream));
-        cur = 0;
-        stepno = step0;
+        if ((uint64_t)n_rec + h.size() > n) {
+            int rc;
+            if ((rc = compact())) return rc;
+            HIPCHECK(hipMemcpyAsync(&n_rec, &ctr->n_rec, sizeof(u32), hipMemcpyDeviceToHost, M.stream));
+            HIPCHECK(hipStreamSynchronize(M.stream));
+            if ((uint64_t)n_rec + h.size() > n) return fail(SIM_ECAPACITY, "record buffer full");
+        }
+        const u32 n_new = n_rec + (u32)h.size();
+        HIPCHECK(hipMemcpyAsync(d_g2c_reps + G * idx, g2h.data(), sizeof(double) * G, hipMemcpyHostToDevice, M.stream));
+        HIPCHECK(hipMemcpyAsync(d_reps + idx, &Q, sizeof(Params), hipMemcpyHostToDevice, M.stream));
+        HIPCHECK(hipMemcpyAsync(d_rep_of_slot + s0, ho.data(), sizeof(u32) * m, hipMemcpyHostToDevice, M.stream));
+        HIPCHECK(hipMemcpyAsync(partner + s0, hp.data(), sizeof(u32) * m, hipMemcpyHostToDevice, M.stream));
+        if (!h.empty()) HIPCHECK(hipMemcpyAsync(rec[cur] + n_rec, h.data(), sizeof(Rec<T>) * h.size(), hipMemcpyHostToDevice, M.stream));
+        HIPCHECK(hipMemcpyAsync(&ctr->n_rec, &n_new, sizeof(u32), hipMemcpyHostToDevice, M.stream));
+        HIPCHECK(hipStreamSynchronize(M.stream));  // the host buffers above are read by the copies
+        reps_h[idx] = Q;
+        member_n[idx] = m;
+        for (int k = 0; k < 3; ++k) rep_box[3 * idx + k] = mr.box[k];
+        return SIM_OK;
+    }
+
+    // Drops the dead records: the live ones move to the other buffer.
+    int compact()
+    {
+        k_compact<T><<<grid_for(n, 8192), BLOCK, 0, M.stream>>>(rec[cur], rec[cur ^ 1], ctr);
+        k_compact_done<<<1, 64, 0, M.stream>>>(ctr);
+        HIPCHECK(hipGetLastError());
+        cur ^= 1;
+        return SIM_OK;
+    }
+
+    int retire(uint32_t idx) override
+    {
+        if (!pool) return fail(SIM_ESTATE, "not a pool");
+        if (idx >= member_n.size() || !member_n[idx]) return fail(SIM_EINVAL, "no such member");
+        const Params &Q = reps_h[idx];
+        const uint64_t m = member_n[idx];
+        k_retire<T><<<grid_for(n, 8192), BLOCK, 0, M.stream>>>(rec[cur], ctr, Q.slot_base, (u32)(Q.slot_base + m));
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipStreamSynchronize(M.stream));
+        slot_free.give(Q.slot_base, m);
+        cell_free.give(Q.cell_base, Q.n_cells);
+        member_n[idx] = 0;
+        return SIM_OK;
+    }
+
+    // A member's positions, species, partners (member-local) or counts.
+    int read_member(uint32_t idx, int what, void *dst, uint64_t cap, uint64_t *written) override
+    {
+        if (!pool) return fail(SIM_ESTATE, "not a pool");
+        if (idx >= member_n.size() || !member_n[idx]) return fail(SIM_EINVAL, "no such member");
+        if (what != SIM_READ_POS && what != SIM_READ_SPECIES && what != SIM_READ_PARTNER && what != SIM_READ_COUNTS)
+            return fail(SIM_EINVAL, "a member reads positions, species, partners or counts");
+        hipStream_t st = M.stream;
+        const uint64_t s0 = reps_h[idx].slot_base, m = member_n[idx];
+        k_fill<<<grid_for(m * DIM, 2048), BLOCK, 0, st>>>(g_pos + s0 * DIM, m * DIM, g_sp + s0, (u32)m);
+        k_gather<DIM, T><<<grid_for(n, 8192), BLOCK, 0, st>>>(rec[cur], partner, ctr, 0, g_pos, g_sp, (u32)n);
+        HIPCHECK(hipGetLastError());
+        if (what == SIM_READ_POS) return copy_out(g_pos + s0 * DIM, sizeof(double) * m * DIM, dst, cap, written);
+        if (what == SIM_READ_SPECIES) return copy_out(g_sp + s0, sizeof(int) * m, dst, cap, written);
+        std::vector<int> hs(m);
+        std::vector<u32> hp(m);
+        HIPCHECK(hipMemcpyAsync(hs.data(), g_sp + s0, sizeof(int) * m, hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipMemcpyAsync(hp.data(), partner + s0, sizeof(u32) * m, hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        if (what == SIM_READ_COUNTS) {
+            int64_t cnts[5] = {0, 0, 0, 0, 0};
+            for (int v : hs) cnts[v] += 1;
+            if (cap < sizeof(cnts)) return fail(SIM_EINVAL, "destination buffer too small");
+            std::memcpy(dst, cnts, sizeof(cnts));
+            if (written) *written = sizeof(cnts);
+            return SIM_OK;
+        }
+        for (uint64_t i = 0; i < m; ++i) hp[i] = hs[i] == SIM_SP_C ? (u32)(hp[i] - s0) : NOSLOT;
+        if (cap < sizeof(u32) * m) return fail(SIM_EINVAL, "destination buffer too small");
+        std::memcpy(dst, hp.data(), sizeof(u32) * m);
+        if (written) *written = sizeof(u32) * m;
         return SIM_OK;
     }
 
@@ -765,12 +1019,45 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     }
 };
 
-bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
-
-int validate(const sim_config *cfg, uint64_t n, const int32_t *sp, const double *pos, const uint32_t *pt, Model &M)
+int validate_box(int dim, int prec, const double *box)
 {
-    if (!cfg || !sp || !pos) { g_err = "null argument"; return SIM_EINVAL; }
+    for (int k = 0; k < dim; ++k) {
+        if (!(std::isfinite(box[k]) && box[k] > 0.0)) { g_err = "box edges must be > 0"; return SIM_EINVAL; }
+        if (prec != SIM_PREC_FP64 && (double)(float)box[k] != box[k]) {
+            g_err = "binary32 states need box edges exactly representable in binary32";
+            return SIM_EINVAL;
+        }
+    }
+    return SIM_OK;
+}
+
+// Species codes, finite positions of the particles, and (reversible
+// reaction) one RESERVED partner slot per C.
+int validate_state(int dim, bool reversible, uint64_t n, const int32_t *sp, const double *pos, const uint32_t *pt)
+{
+    if (!sp || !pos) { g_err = "null argument"; return SIM_EINVAL; }
     if (n == 0 || n > SLOT_MASK) { g_err = "slot count must be in [1, 2^29)"; return SIM_EINVAL; }
+    std::vector<int> owners(n, 0);
+    for (uint64_t i = 0; i < n; ++i) {
+        const int s = sp[i];
+        if (s < 0 || s > SIM_SP_RESERVED) { g_err = "unknown species code"; return SIM_EINVAL; }
+        if (s <= SIM_SP_C)
+            for (int k = 0; k < dim; ++k)
+                if (!std::isfinite(pos[i * dim + k])) { g_err = "non-finite position"; return SIM_EINVAL; }
+        if (s == SIM_SP_C && reversible) {
+            if (!pt || pt[i] >= n || sp[pt[i]] != SIM_SP_RESERVED) { g_err = "each C needs a RESERVED partner slot"; return SIM_EINVAL; }
+            owners[pt[i]] += 1;
+        }
+    }
+    for (uint64_t i = 0; i < n; ++i)
+        if (sp[i] == SIM_SP_RESERVED && owners[i] != 1) { g_err = "each RESERVED slot must belong to exactly one C"; return SIM_EINVAL; }
+    return SIM_OK;
+}
+
+// Everything but the state.
+int validate_cfg(const sim_config *cfg, Model &M)
+{
+    if (!cfg) { g_err = "null argument"; return SIM_EINVAL; }
     if (cfg->dim != 2 && cfg->dim != 3) { g_err = "dim must be 2 or 3"; return SIM_EINVAL; }
     if (cfg->precision < 0 || cfg->precision > 2) { g_err = "unknown precision"; return SIM_EINVAL; }
     if (cfg->n_species != 3 || !cfg->species) { g_err = "exactly three species (A, B, C) are supported"; return SIM_EUNSUPPORTED; }
@@ -786,35 +1073,13 @@ int validate(const sim_config *cfg, uint64_t n, const int32_t *sp, const double 
         if (!finite_nonneg(cfg->species[s].D)) { g_err = "diffusion constants must be finite and >= 0"; return SIM_EINVAL; }
     if (!(cfg->species[0].D + cfg->species[1].D > 0.0)) { g_err = "D_A + D_B must be > 0"; return SIM_EINVAL; }
     if (!(std::isfinite(cfg->dt) && cfg->dt > 0.0)) { g_err = "dt must be > 0"; return SIM_EINVAL; }
-    for (int k = 0; k < cfg->dim; ++k) {
-        if (!(std::isfinite(cfg->box[k]) && cfg->box[k] > 0.0)) { g_err = "box edges must be > 0"; return SIM_EINVAL; }
-        if (cfg->precision != SIM_PREC_FP64 && (double)(float)cfg->box[k] != cfg->box[k]) {
-            g_err = "binary32 states need box edges exactly representable in binary32";
-            return SIM_EINVAL;
-        }
-    }
+    int rc;
+    if ((rc = validate_box(cfg->dim, cfg->precision, cfg->box))) return rc;
     if (cfg->n_terms < 0 || cfg->n_terms > MAXTERMS) { g_err = "n_terms must be in [0, 32]"; return SIM_EINVAL; }
     const double eps = cfg->eps_cut == 0.0 ? 1e-3 : cfg->eps_cut;
     if (!(eps > 0.0 && eps < 1.0)) { g_err = "eps_cut must be in (0, 1)"; return SIM_EINVAL; }
     if (!finite_nonneg(cfg->rcut) || !finite_nonneg(cfg->cell)) { g_err = "rcut and cell must be >= 0"; return SIM_EINVAL; }
     if (cfg->pair_search < SIM_PAIRS_AUTO || cfg->pair_search > SIM_PAIRS_DIRECT) { g_err = "unknown pair_search"; return SIM_EINVAL; }
-    // state
-    std::vector<int> owners(n, 0);
-    for (uint64_t i = 0; i < n; ++i) {
-        const int s = sp[i];
-        if (s < 0 || s > SIM_SP_RESERVED) { g_err = "unknown species code"; return SIM_EINVAL; }
-        if (s <= SIM_SP_C)
-            for (int k = 0; k < cfg->dim; ++k)
-                if (!std::isfinite(pos[i * cfg->dim + k])) { g_err = "non-finite position"; return SIM_EINVAL; }
-        if (s == SIM_SP_C) {
-            if (r.k_off > 0.0) {
-                if (!pt || pt[i] >= n || sp[pt[i]] != SIM_SP_RESERVED) { g_err = "each C needs a RESERVED partner slot"; return SIM_EINVAL; }
-                owners[pt[i]] += 1;
-            }
-        }
-    }
-    for (uint64_t i = 0; i < n; ++i)
-        if (sp[i] == SIM_SP_RESERVED && owners[i] != 1) { g_err = "each RESERVED slot must belong to exactly one C"; return SIM_EINVAL; }
     M.dim = cfg->dim;
     M.prec = cfg->precision;
     M.bc = r.bc;
@@ -836,6 +1101,15 @@ int validate(const sim_config *cfg, uint64_t n, const int32_t *sp, const double 
     M.dbg_cap = cfg->debug_cap == 0 ? (1u << 20) : cfg->debug_cap;
     M.stream = (hipStream_t)cfg->hip_stream;
     return SIM_OK;
+}
+
+int validate(const sim_config *cfg, uint64_t n, const int32_t *sp, const double *pos, const uint32_t *pt, Model &M)
+{
+    if (!cfg || !sp || !pos) { g_err = "null argument"; return SIM_EINVAL; }
+    if (n == 0 || n > SLOT_MASK) { g_err = "slot count must be in [1, 2^29)"; return SIM_EINVAL; }
+    int rc;
+    if ((rc = validate_cfg(cfg, M))) return rc;
+    return validate_state(cfg->dim, cfg->reactions[0].k_off > 0.0, n, sp, pos, pt);
 }
 
 template <int DIM, class T, int PM>
@@ -860,6 +1134,21 @@ int make_batch(const std::vector<Model> &ms, const std::vector<uint64_t> &nr, co
     Engine<DIM, T, PM> *e = new (std::nothrow) Engine<DIM, T, PM>();
     if (!e) { g_err = "host allocation failed"; return SIM_ENOMEM; }
     const int rc = e->init_batch(ms, nr, step0, sp, pos, pt);
+    if (rc) {
+        g_err = e->err;
+        delete e;
+        return rc;
+    }
+    *out = e;
+    return SIM_OK;
+}
+
+template <int DIM, class T, int PM>
+int make_pool(const Model &M, uint64_t slot_cap, uint64_t cell_cap, uint32_t rep_cap, sim_t **out)
+{
+    Engine<DIM, T, PM> *e = new (std::nothrow) Engine<DIM, T, PM>();
+    if (!e) { g_err = "host allocation failed"; return SIM_ENOMEM; }
+    const int rc = e->init_pool(M, slot_cap, cell_cap, rep_cap);
     if (rc) {
         g_err = e->err;
         delete e;
@@ -957,6 +1246,44 @@ int sim_batch_create(const sim_config *cfg, uint32_t n_rep, const sim_replica *r
     if (M.prec == SIM_PREC_FP64) return make_batch<2, double, PM_F64>(ms, nr, step0, sp.data(), pos.data(), pt.data(), out);
     if (M.prec == SIM_PREC_FP32) return make_batch<2, float, PM_F32>(ms, nr, step0, sp.data(), pos.data(), pt.data(), out);
     return make_batch<2, float, PM_F32NC>(ms, nr, step0, sp.data(), pos.data(), pt.data(), out);
+}
+
+int sim_pool_create(const sim_config *cfg, uint64_t slot_cap, uint64_t cell_cap, uint32_t rep_cap, sim_t **out)
+{
+    if (!out) { g_err = "null output handle"; return SIM_EINVAL; }
+    *out = nullptr;
+    Model M;
+    int rc;
+    if ((rc = validate_cfg(cfg, M))) return rc;
+    if (slot_cap == 0 || slot_cap > SLOT_MASK) { g_err = "slot capacity must be in [1, 2^29)"; return SIM_EINVAL; }
+    if (cell_cap == 0 || cell_cap > (1ull << 28)) { g_err = "cell capacity must be in [1, 2^28]"; return SIM_EINVAL; }
+    if (rep_cap == 0 || rep_cap > (1u << 20)) { g_err = "member capacity must be in [1, 2^20]"; return SIM_EINVAL; }
+    if (M.dim == 3) {
+        if (M.prec == SIM_PREC_FP64) return make_pool<3, double, PM_F64>(M, slot_cap, cell_cap, rep_cap, out);
+        if (M.prec == SIM_PREC_FP32) return make_pool<3, float, PM_F32>(M, slot_cap, cell_cap, rep_cap, out);
+        return make_pool<3, float, PM_F32NC>(M, slot_cap, cell_cap, rep_cap, out);
+    }
+    if (M.prec == SIM_PREC_FP64) return make_pool<2, double, PM_F64>(M, slot_cap, cell_cap, rep_cap, out);
+    if (M.prec == SIM_PREC_FP32) return make_pool<2, float, PM_F32>(M, slot_cap, cell_cap, rep_cap, out);
+    return make_pool<2, float, PM_F32NC>(M, slot_cap, cell_cap, rep_cap, out);
+}
+
+int sim_pool_admit(sim_t *h, const sim_replica *rep, uint32_t *member)
+{
+    if (!h || !rep || !member) { g_err = "null argument"; return SIM_EINVAL; }
+    return h->admit(*rep, member);
+}
+
+int sim_pool_retire(sim_t *h, uint32_t member)
+{
+    if (!h) { g_err = "null handle"; return SIM_EINVAL; }
+    return h->retire(member);
+}
+
+int sim_pool_read(sim_t *h, uint32_t member, int what, void *dst, uint64_t cap_bytes, uint64_t *written)
+{
+    if (!h || !dst) { g_err = "null argument"; return SIM_EINVAL; }
+    return h->read_member(member, what, dst, cap_bytes, written);
 }
 
 int sim_eval_pairs(sim_t *h, uint64_t n, const double *R, const double *R0, double *penc, double *preac)

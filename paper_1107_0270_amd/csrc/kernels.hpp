@@ -1476,4 +1476,57 @@ __global__ void k_dbg_cells(Params P, const Rec<float> *recf, const Rec<double> 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Pool membership (between steps).  A member that leaves has its records
+// marked dead in place, which keeps the buffer's order of bucket keys, and
+// the next binning drops them.  A compaction moves the live records to the
+// front of the other buffer in any order (no result depends on the order of
+// records: every choice among candidates goes by slot) and makes the next
+// binning treat every record as moved.
+// ---------------------------------------------------------------------------
+template <class T> __global__ __launch_bounds__(BLOCK) void k_retire(Rec<T> *__restrict__ rec, const Counters *C, u32 lo, u32 hi)
+{
+    const u32 n = C->n_rec;
+    for (u32 i = gtid(); i < n; i += gstride()) {
+        Rec<T> r = rec[i];
+        const u32 m = rec_meta(r), s = meta_slot(m);
+        if (meta_sp(m) <= SP_C && s >= lo && s < hi) {
+            rec_set_meta(r, meta_make(SP_DEAD, s));
+            rec[i] = r;
+        }
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_compact(const Rec<T> *__restrict__ in, Rec<T> *__restrict__ out, Counters *C)
+{
+    __shared__ u32 lds[BLOCK / 64];
+    __shared__ u32 base;
+    const u32 n = C->n_rec;
+    for (u32 b0 = blockIdx.x * BLOCK; b0 < n; b0 += gridDim.x * BLOCK) {  // uniform over the workgroup
+        const u32 i = b0 + threadIdx.x;
+        Rec<T> r;
+        bool keep = false;
+        if (i < n) {
+            r = in[i];
+            keep = meta_sp(rec_meta(r)) <= SP_C;
+        }
+        u32 total;
+        const u32 ex = block_excl_scan(keep ? 1u : 0u, lds, total);
+        if (threadIdx.x == 0) base = total ? atomicAdd(&C->n_kept, total) : 0u;
+        __syncthreads();
+        if (keep) out[base + ex] = r;
+        __syncthreads();  // base is rewritten by the next chunk
+    }
+}
+
+__global__ void k_compact_done(Counters *C)
+{
+    if (gtid() == 0) {
+        C->n_rec = C->n_live = C->n_kept;
+        C->n_sorted = 0;  // the old bucket keys no longer line up with the records
+        C->n_kept = 0;
+    }
+}
+
 } // namespace gfbd

@@ -1,0 +1,207 @@
+"""Serving loop: continuous batching of simulation requests on one GPU.
+
+Requests (a 2D or 3D system of N particles to run for S steps) arrive over time.  Each
+dimension has a worker thread that owns one pool (sim_pool_create) on its own stream, so 2D
+and 3D work proceeds on the device at the same time.  A worker repeatedly
+
+  1. admits waiting requests of its dimension in arrival order while the pool has a free range
+     of slots and cells for them (sim_pool_admit; a request that does not fit waits for
+     members to leave),
+  2. steps the pool up to the next completion (at most `tick` steps), and
+  3. reads each finished request's final state and retires it, which frees its slots.
+
+A request's result is the one it gets alone: the same draws (keyed on its replica number =
+request id, its own slots and its own steps) and the same arithmetic, whoever shares the pool.
+"""
+from __future__ import annotations
+
+import dataclasses
+import threading
+import time
+
+import numpy as np
+
+from . import inputs as I
+from . import sim as S
+
+BYTES_PER_PARTICLE = 400  # device memory per slot: records, sort buffers, pair and event lists
+
+
+@dataclasses.dataclass
+class Request:
+    id: int
+    dim: int
+    n: int
+    steps: int
+    arrival: float                     # seconds after the start of the run
+    species: np.ndarray = None
+    pos: np.ndarray = None
+    box: float = 0.0
+    # filled by the server
+    admitted: float = None
+    finished: float = None
+    result: tuple = None               # (species, positions, partner) when kept
+
+
+# Shared parameters of each dimension (3D: the radiation workload; 2D: the membrane workload at
+# dt = 5 us).  Per request: N, the box at the workload's density, the steps and the key.
+GROUP_PARAMS = {
+    3: dict(dim=3, dt=1e-5, D=(1.0, 1.0, 0.5), sigma=0.005, bc=S.BC_RADIATION, kappa=0.1, k_off=10.0, seed=0,
+            precision=S.PREC_FP32_FP64NC),
+    2: dict(dim=2, dt=5e-6, D=(0.1, 0.1, 0.05), sigma=0.005, bc=S.BC_RADIATION, kappa=0.05, k_off=10.0, seed=0,
+            precision=S.PREC_FP32_FP64NC),
+}
+DENSITY = {3: 1000.0, 2: 2500.0}  # particles per um^3 / um^2
+
+
+def request_box(dim, n):
+    return float(np.float32((n / DENSITY[dim]) ** (1.0 / dim)))
+
+
+def make_trace(count, rate, seed=0, n_range=(1e3, 1e6), step_range=(100, 10_000), p3=0.5):
+    """Poisson arrivals at `rate` per second; dimension 3 with probability p3; N and steps
+    log-uniform in the given ranges; all draws from PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = np.cumsum(rng.exponential(1.0 / rate, count))
+    dims = np.where(rng.random(count) < p3, 3, 2)
+    ns = np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1]), count)).astype(np.int64)
+    steps = np.exp(rng.uniform(np.log(step_range[0]), np.log(step_range[1]), count)).astype(np.int64)
+    return [Request(id=i, dim=int(dims[i]), n=int(ns[i]), steps=int(steps[i]), arrival=float(t[i])) for i in range(count)]
+
+
+def initial_state(req):
+    """Uniform A and B (half each) at the workload density; seeded by the request id."""
+    req.box = request_box(req.dim, req.n)
+    sp, pos, _ = I.uniform_state(req.n // 2, req.n - req.n // 2, box=req.box, dim=req.dim, sigma=0.005,
+                                 seed=10_000 + req.id, f32=True)
+    req.species, req.pos = sp, pos
+    return req
+
+
+def run_alone(req, keep=True):
+    """The request on a handle of its own (the reference for 'the same alone and in the mix')."""
+    p = dict(GROUP_PARAMS[req.dim])
+    dim = p.pop("dim")
+    sim = S.Sim(dim=dim, box=req.box, species=req.species, pos=req.pos, replica=req.id, **p)
+    sim.step(req.steps)
+    out = sim.state()
+    sim.close()
+    return out
+
+
+class _Running:
+    def __init__(self, req):
+        self.req = req
+        self.done = 0  # steps taken
+
+
+class Server:
+    """Continuous-batching server: one pool per dimension with room for `slot_cap[dim]` slots
+    (its cells: half as many, which covers about one cell per B) and `rep_cap` members."""
+
+    def __init__(self, slot_cap=None, rep_cap=4096, tick=200, keep_results=False):
+        self.slot_cap = dict(slot_cap or {3: 1 << 24, 2: 1 << 24})
+        self.rep_cap = rep_cap
+        self.tick = tick
+        self.keep = keep_results
+        self.lock = threading.Lock()
+        self.admissions = 0
+        self.step_calls = 0
+        self.admit_s = 0.0
+        self.step_s = 0.0
+
+    def run(self, requests, realtime=True):
+        """Serve `requests` (with initial states) in arrival order; returns them completed."""
+        for r in requests:
+            if r.n > self.slot_cap[r.dim]:
+                raise ValueError(f"request {r.id} needs {r.n} slots, the {r.dim}D pool has {self.slot_cap[r.dim]}")
+        self.realtime = realtime
+        ordered = sorted(requests, key=lambda r: r.arrival)
+        self.pending = {d: [r for r in ordered if r.dim == d] for d in (2, 3)}
+        self.errors = []
+        # pools are created before the clock starts
+        self.pools = {d: self._pool(d) for d in (2, 3) if self.pending[d]}
+        workers = [threading.Thread(target=self._worker, args=(d,)) for d in self.pools]
+        self.t0 = time.perf_counter()
+        for w in workers:
+            w.start()
+        for w in workers:
+            w.join()
+        self.t_end = time.perf_counter() - self.t0
+        for p in self.pools.values():
+            p.close()
+        if self.errors:
+            raise self.errors[0]
+        return requests
+
+    def now(self):
+        return time.perf_counter() - self.t0
+
+    def _pool(self, dim):
+        p = dict(GROUP_PARAMS[dim])
+        p.pop("dim")
+        cap = self.slot_cap[dim]
+        return S.Pool(dim=dim, box=request_box(dim, 1000), slot_cap=cap, cell_cap=cap // 2 + 4096,
+                      rep_cap=self.rep_cap, **p)
+
+    def _count(self, attr, dt, n=1):
+        with self.lock:
+            setattr(self, attr, getattr(self, attr) + dt)
+            if attr == "admit_s":
+                self.admissions += n
+            else:
+                self.step_calls += n
+
+    def _worker(self, dim):
+        try:
+            pool, q = self.pools[dim], self.pending[dim]
+            running = {}  # member entry -> _Running
+            while running or q:
+                t = time.perf_counter()
+                admitted = 0
+                while q and (not self.realtime or q[0].arrival <= self.now()):
+                    r = q[0]
+                    m = pool.try_admit(r.species, r.pos, r.box, replica=r.id)
+                    if m is None:
+                        break  # no room: wait for members to leave
+                    q.pop(0)
+                    r.admitted = self.now()
+                    running[m] = _Running(r)
+                    admitted += 1
+                if admitted:
+                    self._count("admit_s", time.perf_counter() - t, admitted)
+                if not running:
+                    if q and self.realtime:
+                        time.sleep(max(0.0, min(0.02, q[0].arrival - self.now())))
+                    continue
+                k = min(self.tick, min(x.req.steps - x.done for x in running.values()))
+                t = time.perf_counter()
+                pool.step(k)
+                self._count("step_s", time.perf_counter() - t)
+                for x in running.values():
+                    x.done += k
+                for m in [m for m, x in running.items() if x.done >= x.req.steps]:
+                    x = running.pop(m)
+                    if self.keep:
+                        x.req.result = pool.member_state(m)
+                    pool.retire(m)
+                    x.req.finished = self.now()
+        except Exception as e:  # surfaced by run()
+            self.errors.append(e)
+
+    def summary(self, requests):
+        lat = np.array([r.finished - r.arrival for r in requests])
+        work = sum(r.n * r.steps for r in requests)
+        return {
+            "requests": len(requests),
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "mean_queue_s": float(np.mean([r.admitted - r.arrival for r in requests])),
+            "particle_steps": int(work),
+            "wall_s": self.t_end,
+            "particle_steps_per_s": work / self.t_end,
+            "admissions": self.admissions,
+            "admit_s": self.admit_s,
+            "step_calls": self.step_calls,
+            "step_s": self.step_s,
+        }

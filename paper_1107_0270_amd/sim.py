@@ -125,6 +125,14 @@ def lib():
     L.sim_create.restype = C.c_int
     L.sim_batch_create.argtypes = [C.POINTER(SimConfig), u32, C.POINTER(SimReplica), C.POINTER(vp)]
     L.sim_batch_create.restype = C.c_int
+    L.sim_pool_create.argtypes = [C.POINTER(SimConfig), u64, u64, u32, C.POINTER(vp)]
+    L.sim_pool_create.restype = C.c_int
+    L.sim_pool_admit.argtypes = [vp, C.POINTER(SimReplica), C.POINTER(u32)]
+    L.sim_pool_admit.restype = C.c_int
+    L.sim_pool_retire.argtypes = [vp, u32]
+    L.sim_pool_retire.restype = C.c_int
+    L.sim_pool_read.argtypes = [vp, u32, C.c_int, vp, u64, C.POINTER(u64)]
+    L.sim_pool_read.restype = C.c_int
     L.sim_step.argtypes = [vp, u32]
     L.sim_step.restype = C.c_int
     L.sim_read.argtypes = [vp, C.c_int, vp, u64, C.POINTER(u64)]
@@ -141,6 +149,27 @@ def lib():
     L.sim_last_error.restype = C.c_char_p
     _lib = L
     return L
+
+
+def _fill_replica(rep, rd, dim, kappa0, default_replica):
+    """Fill a SimReplica from a dict (species, pos, box; optional kappa, replica, step, partner).
+    Returns the arrays the struct points into (to be kept alive by the caller)."""
+    sp = np.ascontiguousarray(rd["species"], dtype=np.int32)
+    ps = np.ascontiguousarray(rd["pos"], dtype=np.float64).ravel()
+    if ps.size != dim * sp.size:
+        raise ValueError("pos must hold n * dim values")
+    pt = None if rd.get("partner") is None else np.ascontiguousarray(rd["partner"], dtype=np.uint32)
+    bx = list(rd["box"]) if np.ndim(rd["box"]) else [float(rd["box"])] * dim
+    bx = bx + [1.0] * (3 - len(bx))
+    rep.n = sp.size
+    rep.species, rep.pos = sp.ctypes.data, ps.ctypes.data
+    rep.partner = None if pt is None else pt.ctypes.data
+    for k in range(3):
+        rep.box[k] = float(bx[k])
+    rep.kappa = float(rd.get("kappa", kappa0))
+    rep.replica = int(rd.get("replica", default_replica))
+    rep.step = int(rd.get("step", 0))
+    return (sp, ps, pt)
 
 
 class Sim:
@@ -215,24 +244,9 @@ class Sim:
         keep, reps = [], (SimReplica * len(replicas))()
         bases, n = [], 0
         for r, rd in enumerate(replicas):
-            sp = np.ascontiguousarray(rd["species"], dtype=np.int32)
-            ps = np.ascontiguousarray(rd["pos"], dtype=np.float64).ravel()
-            if ps.size != dim * sp.size:
-                raise ValueError("pos must hold n * dim values")
-            pt = None if rd.get("partner") is None else np.ascontiguousarray(rd["partner"], dtype=np.uint32)
-            keep += [sp, ps, pt]
-            bx = list(rd["box"]) if np.ndim(rd["box"]) else [float(rd["box"])] * dim
-            bx = bx + [1.0] * (3 - len(bx))
-            reps[r].n = sp.size
-            reps[r].species, reps[r].pos = sp.ctypes.data, ps.ctypes.data
-            reps[r].partner = None if pt is None else pt.ctypes.data
-            for k in range(3):
-                reps[r].box[k] = float(bx[k])
-            reps[r].kappa = float(rd.get("kappa", kappa0))
-            reps[r].replica = int(rd.get("replica", r))
-            reps[r].step = int(rd.get("step", 0))
+            keep.append(_fill_replica(reps[r], rd, dim, kappa0, r))
             bases.append(n)
-            n += sp.size
+            n += reps[r].n
         h = C.c_void_p()
         rc = L.sim_batch_create(C.byref(self.cfg), len(replicas), reps, C.byref(h))
         if rc != SIM_OK:
@@ -382,3 +396,65 @@ class Sim:
 
     def dbg_diss(self):
         return self._read_log(READ_DBG_DISS, DISS_DT)
+
+
+class Pool(Sim):
+    """Continuous batching (sim_pool_create): systems join (``admit``) and leave (``retire``)
+    between steps; ``step`` advances every member.  ``box`` is any valid box of the shared
+    configuration (members bring their own); the other keywords are those of Sim."""
+
+    def __init__(self, *, dim, box, slot_cap, cell_cap=None, rep_cap=4096, kappa=0.0, **shared):
+        self._config(dim=dim, box=box, species=np.zeros(1, np.int32), pos=np.zeros(dim), kappa=kappa, **shared)
+        self.kappa = float(kappa)
+        cell_cap = slot_cap if cell_cap is None else cell_cap
+        h = C.c_void_p()
+        L = lib()
+        rc = L.sim_pool_create(C.byref(self.cfg), int(slot_cap), int(cell_cap), int(rep_cap), C.byref(h))
+        if rc != SIM_OK:
+            raise SimError(rc, L.sim_last_error(None).decode())
+        self._h, self.n, self.slot_base = h, int(slot_cap), [0]
+        self.members = {}
+
+    def admit(self, species, pos, box, kappa=None, replica=0, step=0, partner=None):
+        """Add a system; returns its member entry.  Raises SimError (code SIM_ECAPACITY when
+        there is no room: nothing changed)."""
+        rep = SimReplica()
+        rd = dict(species=species, pos=pos, box=box, replica=replica, step=step, partner=partner)
+        if kappa is not None:
+            rd["kappa"] = kappa
+        keep = _fill_replica(rep, rd, self.dim, self.kappa, replica)
+        m = C.c_uint32(0)
+        self._check(lib().sim_pool_admit(self._h, C.byref(rep), C.byref(m)))
+        del keep
+        self.members[m.value] = rep.n
+        return m.value
+
+    def try_admit(self, *args, **kw):
+        """admit, or None when the pool has no room."""
+        try:
+            return self.admit(*args, **kw)
+        except SimError as e:
+            if e.code == SIM_ECAPACITY:
+                return None
+            raise
+
+    def retire(self, member):
+        self._check(lib().sim_pool_retire(self._h, int(member)))
+        self.members.pop(member, None)
+
+    def _read_member(self, member, what, out):
+        w = C.c_uint64(0)
+        self._check(lib().sim_pool_read(self._h, int(member), what, out.ctypes.data, out.nbytes, C.byref(w)))
+        return out
+
+    def member_state(self, member):
+        """(species, positions, partners) of a member, in its own slot order."""
+        n = self.members[member]
+        sp = self._read_member(member, READ_SPECIES, np.zeros(n, np.int32))
+        pos = self._read_member(member, READ_POS, np.zeros((n, self.dim)))
+        pt = self._read_member(member, READ_PARTNER, np.zeros(n, np.uint32))
+        return sp, pos, pt
+
+    def member_counts(self, member):
+        out = self._read_member(member, READ_COUNTS, np.zeros(5, np.int64))
+        return dict(zip(["A", "B", "C", "FREE", "RESERVED"], out.tolist()))

@@ -21,7 +21,8 @@ def _declared():
 
 
 def test_header_declares_the_boundary():
-    assert _declared() == sorted(["sim_create", "sim_batch_create", "sim_step", "sim_read", "sim_load_state",
+    assert _declared() == sorted(["sim_create", "sim_batch_create", "sim_pool_create", "sim_pool_admit",
+                                  "sim_pool_retire", "sim_pool_read", "sim_step", "sim_read", "sim_load_state",
                                   "sim_eval_pairs", "sim_eval_propagator", "sim_destroy", "sim_last_error"])
 
 
@@ -131,3 +132,36 @@ def test_batch_input_is_rejected_before_the_device(reps, over, code):
     with pytest.raises(S.SimError) as e:
         S.Sim.batch(reps, **kw)
     assert e.value.code == code
+
+
+@pytest.mark.parametrize("caps,over,code", [
+    ((0, 10, 1), {}, S.SIM_EINVAL),                   # no slots
+    ((1 << 29, 10, 1), {}, S.SIM_EINVAL),             # more slots than a slot index holds
+    ((100, 0, 1), {}, S.SIM_EINVAL),                  # no cells
+    ((100, (1 << 28) + 1, 1), {}, S.SIM_EINVAL),      # too many cells
+    ((100, 10, 0), {}, S.SIM_EINVAL),                 # no member entries
+    ((100, 10, (1 << 20) + 1), {}, S.SIM_EINVAL),     # too many member entries
+    ((100, 10, 1), {"dt": -1.0}, S.SIM_EINVAL),       # the shared configuration is checked
+    ((100, 10, 1), {"precision": 7}, S.SIM_EINVAL),
+])
+def test_pool_arguments_are_rejected_before_the_device(caps, over, code):
+    if not os.path.exists(S.LIB_PATH):
+        pytest.skip("libgfbd.so not built")
+    kw = dict(dt=1e-6, D=(1.0, 1.0, 0.5), sigma=0.005, bc=S.BC_RADIATION, k_off=1.0, precision=S.PREC_FP64)
+    kw.update(over)
+    with pytest.raises(S.SimError) as e:
+        S.Pool(dim=3, box=1.0, slot_cap=caps[0], cell_cap=caps[1], rep_cap=caps[2], **kw)
+    assert e.value.code == code
+
+
+def test_pool_calls_reject_null_arguments_on_the_host():
+    if not os.path.exists(S.LIB_PATH):
+        pytest.skip("libgfbd.so not built")
+    L = S.lib()
+    m = C.c_uint32(0)
+    assert L.sim_pool_create(None, 10, 10, 1, None) == S.SIM_EINVAL
+    h = C.c_void_p()
+    assert L.sim_pool_create(None, 10, 10, 1, C.byref(h)) == S.SIM_EINVAL
+    assert L.sim_pool_admit(None, None, C.byref(m)) == S.SIM_EINVAL
+    assert L.sim_pool_retire(None, 0) == S.SIM_EINVAL
+    assert L.sim_pool_read(None, 0, S.READ_POS, None, 0, None) == S.SIM_EINVAL
