@@ -183,6 +183,69 @@ def batched(args, I, S):
                    "step_launch": "one hipGraph replay per step for all replicas"}}), flush=True)
 
 
+def served(args, S):
+    """The served stream: Poisson arrivals of 2D/3D reversible simulations (N and steps
+    log-uniform), continuous batching in one pool per dimension; p50/p99 latency and aggregate
+    particle-steps/s, against the plain path (requests run alone, one after another)."""
+    from paper_1107_0270_amd import serve as V
+    trace = V.make_trace(args.serve_requests, args.serve, seed=0)
+    t0 = time.time()
+    for r in trace:
+        V.initial_state(r)
+    n_tot = sum(r.n for r in trace)
+    work = sum(r.n * r.steps for r in trace)
+    log(f"[serve] {len(trace)} requests at {args.serve}/s: {n_tot} particles, {work:.3e} particle-steps, "
+        f"states in {time.time() - t0:.1f}s")
+    # plain path first (also warms the library): a sample of the requests, one handle each
+    rng = np.random.default_rng(1)
+    pick = rng.choice(len(trace), size=min(args.single_sample, len(trace)), replace=False)
+    t_single, ps_single = 0.0, 0
+    for i in pick:
+        r = trace[i]
+        p = dict(V.GROUP_PARAMS[r.dim])
+        dim = p.pop("dim")
+        sim = S.Sim(dim=dim, box=r.box, species=r.species, pos=r.pos, replica=r.id, **p)
+        k = min(r.steps, 200)
+        t1 = time.perf_counter()
+        sim.step(k)
+        t_single += time.perf_counter() - t1
+        ps_single += r.n * k
+        sim.close()
+    rate1 = ps_single / t_single
+    log(f"[serve] plain path on {len(pick)} requests: {rate1:.3e} particle-steps/s")
+    srv = V.Server(slot_cap={3: args.pool_slots, 2: args.pool_slots}, tick=args.tick, keep_results=False,
+                   read_results=True, progress=log)
+    srv.run(trace)
+    summ = srv.summary(trace)
+    log(f"[serve] {summ}")
+    lat = np.array([r.finished - r.arrival for r in trace])
+    print(json.dumps({
+        "metric": "p50/p99 request latency; aggregate particle-steps/s (served stream)",
+        "value": round(summ["particle_steps_per_s"], 1), "unit": "particle-steps/s",
+        "p50_latency_s": round(summ["p50_latency_s"], 4), "p99_latency_s": round(summ["p99_latency_s"], 4),
+        "mean_queue_s": round(summ["mean_queue_s"], 4),
+        "mean_service_s": round(float(np.mean([r.finished - r.admitted for r in trace])), 4),
+        "wall_s": round(summ["wall_s"], 3), "last_arrival_s": round(trace[-1].arrival, 3),
+        "offered_particle_steps_per_s": round(work / trace[-1].arrival, 1),
+        "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "plain_path": {"value": round(rate1, 1), "unit": "particle-steps/s",
+                       "sample": f"{len(pick)} requests of the trace, one handle each, run one after another "
+                                 "(at most 200 steps each)"},
+        "speedup_vs_plain_path": round(summ["particle_steps_per_s"] / rate1, 2),
+        "latency_quantiles_s": {q: round(float(np.percentile(lat, q)), 4) for q in (10, 25, 50, 75, 90, 99)},
+        "server": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()},
+        "config": {"workload": f"{len(trace)} requests, Poisson arrivals at {args.serve}/s (seed 0); 3D or 2D with "
+                               "p = 1/2; N log-uniform in [1e3, 1e6]; steps log-uniform in [100, 1e4]; 3D: D=1 um^2/s, "
+                               "sigma=5 nm, kappa=0.1 um^3/s, k_off=10/s, dt=10 us, 1000 particles/um^3; 2D: D=0.1 "
+                               "um^2/s, kappa=0.05 um^2/s, k_off=10/s, dt=5 us, 2500 particles/um^2",
+                   "admission": f"first come first served into one pool per dimension of {args.pool_slots} slots "
+                                "(the device-memory ledger); each request occupies its own slot and cell ranges "
+                                "until it finishes",
+                   "tick": f"each pool steps to its next completion, at most {args.tick} steps per call",
+                   "precision": "binary32 state and p_enc, binary64 near-contact arguments and propagation"}}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +267,11 @@ def main():
                     help="only run the batched-ensemble benchmark on R replicas (4096: the full ensemble) and exit")
     ap.add_argument("--single-sample", type=int, default=32,
                     help="replicas timed one handle at a time for the single-replica comparison (--batch)")
+    ap.add_argument("--serve", type=float, default=0.0, metavar="RATE",
+                    help="only run the served stream at RATE requests/s (200: the stated stream) and exit")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests in the served trace (--serve)")
+    ap.add_argument("--pool-slots", type=int, default=1 << 26, help="slots of each pool (--serve)")
+    ap.add_argument("--tick", type=int, default=200, help="most steps per pool call (--serve)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -229,6 +297,9 @@ def main():
         return
     if args.batch:
         batched(args, I, S)
+        return
+    if args.serve:
+        served(args, S)
         return
 
     cfg = I.workload(args.workload)

@@ -69,11 +69,21 @@ def make_trace(count, rate, seed=0, n_range=(1e3, 1e6), step_range=(100, 10_000)
     return [Request(id=i, dim=int(dims[i]), n=int(ns[i]), steps=int(steps[i]), arrival=float(t[i])) for i in range(count)]
 
 
-def initial_state(req):
-    """Uniform A and B (half each) at the workload density; seeded by the request id."""
+def initial_state(req, redraw=False):
+    """Uniform A and B (half each) at the workload density, binary32-exact, from PCG64(10000 + id).
+    Overlapping A-B pairs are left as drawn unless `redraw` (at these densities about 3 in 10^4 B's
+    start within sigma of an A; the step treats them as overlaps)."""
     req.box = request_box(req.dim, req.n)
-    sp, pos, _ = I.uniform_state(req.n // 2, req.n - req.n // 2, box=req.box, dim=req.dim, sigma=0.005,
-                                 seed=10_000 + req.id, f32=True)
+    n_a = req.n // 2
+    if redraw:
+        sp, pos, _ = I.uniform_state(n_a, req.n - n_a, box=req.box, dim=req.dim, sigma=0.005, seed=10_000 + req.id,
+                                     f32=True)
+    else:
+        rng = np.random.Generator(np.random.PCG64(10_000 + req.id))
+        pos = rng.random((req.n, req.dim), dtype=np.float32).astype(np.float64) * np.float32(req.box)
+        pos = pos.astype(np.float32).astype(np.float64)
+        pos[pos >= req.box] = 0.0
+        sp = np.concatenate([np.full(n_a, S.SP_A, np.int32), np.full(req.n - n_a, S.SP_B, np.int32)])
     req.species, req.pos = sp, pos
     return req
 
@@ -99,8 +109,11 @@ class Server:
     """Continuous-batching server: one pool per dimension with room for `slot_cap[dim]` slots
     (its cells: half as many, which covers about one cell per B) and `rep_cap` members."""
 
-    def __init__(self, slot_cap=None, rep_cap=4096, tick=200, keep_results=False):
+    def __init__(self, slot_cap=None, rep_cap=4096, tick=200, keep_results=False, read_results=None, progress=None):
         self.slot_cap = dict(slot_cap or {3: 1 << 24, 2: 1 << 24})
+        self.read = keep_results if read_results is None else read_results  # read each final state
+        self.progress = progress  # called with a line after every 100th completed request
+        self.completed = 0
         self.rep_cap = rep_cap
         self.tick = tick
         self.keep = keep_results
@@ -182,10 +195,18 @@ class Server:
                     x.done += k
                 for m in [m for m, x in running.items() if x.done >= x.req.steps]:
                     x = running.pop(m)
-                    if self.keep:
-                        x.req.result = pool.member_state(m)
+                    if self.read:
+                        out = pool.member_state(m)
+                        if self.keep:
+                            x.req.result = out
                     pool.retire(m)
                     x.req.finished = self.now()
+                    with self.lock:
+                        self.completed += 1
+                        done = self.completed
+                    if self.progress and done % 100 == 0:
+                        self.progress(f"[serve] {done} requests done at t = {x.req.finished:.1f} s, "
+                                      f"{len(running)} running in the {dim}D pool, {len(q)} waiting")
         except Exception as e:  # surfaced by run()
             self.errors.append(e)
 
