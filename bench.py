@@ -139,6 +139,24 @@ def batched(args, I, S):
     reps = I.ensemble(args.batch)
     n_tot = sum(len(r["species"]) for r in reps)
     log(f"[batch] {len(reps)} replicas, {n_tot} particles, generated in {time.time() - t0:.1f}s")
+    tuned = None
+    if args.autotune:
+        # replicas share the density, so a sub-batch picks the shared cell edge (batches use the
+        # direct pair search)
+        from paper_1107_0270_amd import autotune as AT
+        rng0 = np.random.default_rng(2)
+        sub = [reps[i] for i in rng0.choice(len(reps), size=min(256, len(reps)), replace=False)]
+        probe = S.Sim.batch(sub[:1], **shared)
+        d0 = probe.derived()
+        probe.close()
+        t0 = time.time()
+        best, table = AT.tune(lambda c, p: S.Sim.batch(sub, cell=c, **shared), box=sub[0]["box"], dim=3,
+                              rcut=d0["rcut"], cell0=d0["cell"], searches=(S.PAIRS_DIRECT,), log=log)
+        shared["cell"] = best["cell"]
+        tuned = {"choice": best, "tuned_on": f"{len(sub)} replicas of the ensemble", "candidates": len(table),
+                 "seconds": round(time.time() - t0, 1),
+                 "table": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()} for r in table]}
+        log(f"[batch] autotuned in {tuned['seconds']} s: {best}")
     t0 = time.time()
     b = S.Sim.batch(reps, **shared)
     log(f"[batch] created in {time.time() - t0:.1f}s")
@@ -176,6 +194,7 @@ def batched(args, I, S):
                                 "sample": f"{len(pick)} replicas of the ensemble, one handle each, stepped one after "
                                           f"another ({args.steps} steps each after {args.warmup} warm-up)"},
         "speedup_vs_single_replica_path": round(rate / rate1, 2),
+        "autotune": tuned,
         "config": {"workload": f"{len(reps)} independent 3D replicas, A+B<->C radiation surface, N log-uniform in "
                                f"[1e3, 1e5] (total {n_tot}), kappa uniform in [0.01, 1] um^3/s, L = (N/1000)^(1/3) um, "
                                "D=1 um^2/s, sigma=5 nm, k_off=10/s, dt=10 us",
@@ -272,6 +291,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests in the served trace (--serve)")
     ap.add_argument("--pool-slots", type=int, default=1 << 26, help="slots of each pool (--serve)")
     ap.add_argument("--tick", type=int, default=200, help="most steps per pool call (--serve)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the cell edge and pair-search kernel by timing candidates on the workload first")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -307,10 +328,29 @@ def main():
     t0 = time.time()
     sp, pos, box, red = I.state_for(cfg, seed=0)
     log(f"[bench] state: {len(sp)} particles, {red} redrawn overlaps, {time.time() - t0:.1f}s")
-    def make(timing):
+    search = {"auto": S.PAIRS_AUTO, "bricks": S.PAIRS_BRICKS, "direct": S.PAIRS_DIRECT}[args.pair_search]
+
+    def make_with(timing, cell, pair_search):
         return S.Sim(dim=dim, box=box, dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
-                     k_off=cfg["k_off"], precision=cfg["precision"], seed=0, species=sp, pos=pos, timing=timing, cell=args.cell,
-                     pair_search={"auto": S.PAIRS_AUTO, "bricks": S.PAIRS_BRICKS, "direct": S.PAIRS_DIRECT}[args.pair_search])
+                     k_off=cfg["k_off"], precision=cfg["precision"], seed=0, species=sp, pos=pos, timing=timing, cell=cell,
+                     pair_search=pair_search)
+
+    tuned = None
+    if args.autotune:
+        from paper_1107_0270_amd import autotune as AT
+        probe = make_with(False, 0.0, S.PAIRS_AUTO)
+        d0 = probe.derived()
+        probe.close()
+        t0 = time.time()
+        best, table = AT.tune(lambda c, p: make_with(False, c, p), box=box, dim=dim, rcut=d0["rcut"], cell0=d0["cell"],
+                              log=log)
+        args.cell, search = best["cell"], best["pair_search"]
+        tuned = {"choice": best, "candidates": len(table), "seconds": round(time.time() - t0, 1),
+                 "table": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()} for r in table]}
+        log(f"[bench] autotuned in {tuned['seconds']} s: {best}")
+
+    def make(timing):
+        return make_with(timing, args.cell, search)
 
     def timed(sim):
         sim.step(args.warmup)
@@ -393,7 +433,9 @@ def main():
                                                      "propagation"}[cfg["precision"]],
                    "particles": len(sp), "r_cut_um": der["rcut"], "cells": grid[:3],
                    "pair_search": {S.PAIRS_BRICKS: "lds-bricks", S.PAIRS_DIRECT: "direct"}[grid[4]],
-                   "step_launch": "one hipGraph replay per step"},
+                   "step_launch": "one hipGraph replay per step",
+                   "cell_edge_um": der["cell"]},
+        "autotune": tuned,
         "roofline": roof,
         "kernel_ms_per_step": {k: round(v[0] / max(args.steps, 1), 5) for k, v in kt.items()},
         "cpu_baseline": cpu,

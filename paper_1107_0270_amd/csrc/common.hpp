@@ -129,6 +129,7 @@ struct Params {
     u32 step_base;            // the replica's own step is the step counter minus this (mod 2^32)
     u32 n_rep;
     const u32 *rep_of_slot;   // replica of every slot (batches only)
+    const u32 *cell_rep;      // replica of every cell (batches only)
     const Params *reps;       // per-replica parameters (batches only)
 };
 

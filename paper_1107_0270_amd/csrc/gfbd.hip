@@ -208,6 +208,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     // device memory
     Rec<T> *rec[2] = {nullptr, nullptr}, *tmp = nullptr;
     u32 *rank = nullptr, *cnt = nullptr, *scnt = nullptr, *okey = nullptr, *start = nullptr, *bsum = nullptr, *partner = nullptr;
+    u32 *nkey = nullptr;  // batches: each moved record's new bucket key
     PairEnt *plist = nullptr;
     CandEnt *cand = nullptr;
     u32 *flag = nullptr, *nextA = nullptr, *nextB = nullptr, *ev = nullptr;
@@ -220,7 +221,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     std::vector<double> rep_box;
     std::vector<u32> rep_of_slot_h;
     Params *d_reps = nullptr;
-    u32 *d_rep_of_slot = nullptr;
+    u32 *d_rep_of_slot = nullptr, *d_cell_rep = nullptr;
     double *d_g2c_reps = nullptr;
     // pools: members join and leave between steps
     bool pool = false;
@@ -460,17 +461,24 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         P.cap = (u32)n;
         P.cap_pl = (u32)std::min<uint64_t>(std::max<uint64_t>(1u << 20, 4 * n), 1u << 30);
         P.tiled = 0;
-        if ((rc = alloc(d_reps, R)) || (rc = alloc(d_rep_of_slot, n))) return rc;
+        if ((rc = alloc(d_reps, R)) || (rc = alloc(d_rep_of_slot, n)) || (rc = alloc(d_cell_rep, cbase))) return rc;
         P.reps = d_reps;
         P.rep_of_slot = d_rep_of_slot;
+        P.cell_rep = d_cell_rep;
+        std::vector<u32> cell_rep_h(cbase);
+        for (size_t r = 0; r < R; ++r)
+            for (u32 c = 0; c < reps_h[r].n_cells; ++c) cell_rep_h[reps_h[r].cell_base + c] = (u32)r;
         for (auto &q : reps_h) {  // fields shared by the whole batch
             q.cap = P.cap;
             q.cap_pl = P.cap_pl;
             q.n_rep = P.n_rep;
             q.reps = d_reps;
             q.rep_of_slot = d_rep_of_slot;
+            q.cell_rep = d_cell_rep;
         }
         HIPCHECK(hipMemcpyAsync(d_rep_of_slot, rep_of_slot_h.data(), sizeof(u32) * n, hipMemcpyHostToDevice, M.stream));
+        HIPCHECK(hipMemcpyAsync(d_cell_rep, cell_rep_h.data(), sizeof(u32) * cbase, hipMemcpyHostToDevice, M.stream));
+        HIPCHECK(hipStreamSynchronize(M.stream));  // cell_rep_h is host memory the copy reads
         return finish_init(sp, pos, pt);
     }
 
@@ -498,15 +506,17 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         P.cap = (u32)n;
         P.cap_pl = (u32)std::min<uint64_t>(std::max<uint64_t>(1u << 20, 4 * n), 1u << 30);
         P.tiled = 0;
-        if ((rc = alloc(d_reps, rep_cap)) || (rc = alloc(d_rep_of_slot, n))) return rc;
+        if ((rc = alloc(d_reps, rep_cap)) || (rc = alloc(d_rep_of_slot, n)) || (rc = alloc(d_cell_rep, cell_cap))) return rc;
         P.reps = d_reps;
         P.rep_of_slot = d_rep_of_slot;
+        P.cell_rep = d_cell_rep;
         for (auto &q : reps_h) {
             q.cap = P.cap;
             q.cap_pl = P.cap_pl;
             q.n_rep = P.n_rep;
             q.reps = d_reps;
             q.rep_of_slot = d_rep_of_slot;
+            q.cell_rep = d_cell_rep;
         }
         return finish_init(nullptr, nullptr, nullptr);
     }
@@ -528,7 +538,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             (rc = alloc(plist, P.cap_pl)) || (rc = alloc(cand, P.cap_pl)) || (rc = alloc(flag, P.cap_pl)) ||
             (rc = alloc(nextA, P.cap_pl)) || (rc = alloc(nextB, P.cap_pl)) || (rc = alloc(headA, n)) ||
             (rc = alloc(headB, n)) || (rc = alloc(ev, n)) || (rc = alloc(ctr, 1)) || (rc = alloc(g2c, 4 * (MAXTERMS + 1))) ||
-            (rc = alloc(g_pos, n * DIM)) || (rc = alloc(g_sp, n)))
+            (rc = alloc(g_pos, n * DIM)) || (rc = alloc(g_sp, n)) || (batch && (rc = alloc(nkey, n))))
             return rc;
         if (M.debug) {
             if ((rc = alloc(dbg_moved, n * DIM)) || (rc = alloc(dbg_cells, n)) || (rc = alloc(dbg_pairs, M.dbg_cap)) ||
@@ -654,6 +664,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         Q.n_rep = P.n_rep;
         Q.reps = d_reps;
         Q.rep_of_slot = d_rep_of_slot;
+        Q.cell_rep = d_cell_rep;
         const size_t G = 4 * (MAXTERMS + 1);
         Q.g2c = d_g2c_reps + G * idx;
         std::vector<double> g2h(G);
@@ -688,6 +699,8 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         HIPCHECK(hipMemcpyAsync(d_g2c_reps + G * idx, g2h.data(), sizeof(double) * G, hipMemcpyHostToDevice, M.stream));
         HIPCHECK(hipMemcpyAsync(d_reps + idx, &Q, sizeof(Params), hipMemcpyHostToDevice, M.stream));
         HIPCHECK(hipMemcpyAsync(d_rep_of_slot + s0, ho.data(), sizeof(u32) * m, hipMemcpyHostToDevice, M.stream));
+        std::vector<u32> hc(Q.n_cells, idx);
+        HIPCHECK(hipMemcpyAsync(d_cell_rep + c0, hc.data(), sizeof(u32) * Q.n_cells, hipMemcpyHostToDevice, M.stream));
         HIPCHECK(hipMemcpyAsync(partner + s0, hp.data(), sizeof(u32) * m, hipMemcpyHostToDevice, M.stream));
         if (!h.empty()) HIPCHECK(hipMemcpyAsync(rec[cur] + n_rec, h.data(), sizeof(Rec<T>) * h.size(), hipMemcpyHostToDevice, M.stream));
         HIPCHECK(hipMemcpyAsync(&ctr->n_rec, &n_new, sizeof(u32), hipMemcpyHostToDevice, M.stream));
@@ -804,12 +817,12 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         Rec<T> *in = rec[c], *out = rec[c ^ 1];
         const u32 g_all = grid_for(n, 8192);
         const u32 g_pl = 1024;
-        launch(SIM_K_MOVE, [&] { k_move_count<DIM, T, BATCH><<<g_all, BLOCK, 0, st>>>(P, in, okey, tmp, rank, cnt, scnt, ctr); });
+        launch(SIM_K_MOVE, [&] { k_move_count<DIM, T, BATCH><<<g_all, BLOCK, 0, st>>>(P, in, okey, tmp, rank, cnt, scnt, nkey, ctr); });
         launch(SIM_K_SCAN, [&] {
             k_scan_tiles<<<nb_scan, BLOCK, 0, st>>>(cnt, scnt, bsum);
             k_scan<<<nb_scan, BLOCK, 0, st>>>(cnt, scnt, bsum, start, ctr);
         });
-        launch(SIM_K_SCATTER, [&] { k_scatter<DIM, T, BATCH><<<g_all, BLOCK, 0, st>>>(P, tmp, rank, start, out, okey, ctr); });
+        launch(SIM_K_SCATTER, [&] { k_scatter<DIM, T, BATCH><<<g_all, BLOCK, 0, st>>>(P, tmp, rank, start, out, okey, nkey, ctr); });
         if (M.debug) {
             k_fill<<<grid_for(n * DIM, 2048), BLOCK, 0, st>>>(dbg_moved, n * DIM, (int *)dbg_cells, (u32)n);
             k_gather<DIM, T><<<g_all, BLOCK, 0, st>>>(out, partner, ctr, 1, dbg_moved, nullptr, (u32)n);
@@ -822,14 +835,14 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             // more workgroups than are resident at once (2048)
             const u32 g_pairs = round8(grid_for(maxA, 2048));
             if (!BATCH && P.tiled) k_pair_scan<DIM, T, PM><<<round8(n_bricks), PBLOCK, 0, st>>>(P, out, start, plist, ctr);
-            else if (narrow) k_pair_scan_direct_narrow<DIM, T, PM, BATCH><<<g_pairs, BLOCK, 0, st>>>(P, out, start, plist, ctr);
-            else k_pair_scan_direct<DIM, T, PM, BATCH><<<g_pairs, BLOCK, 0, st>>>(P, out, start, plist, ctr);
+            else if (narrow) k_pair_scan_direct_narrow<DIM, T, PM, BATCH><<<g_pairs, BLOCK, 0, st>>>(P, out, start, okey, plist, ctr);
+            else k_pair_scan_direct<DIM, T, PM, BATCH><<<g_pairs, BLOCK, 0, st>>>(P, out, start, okey, plist, ctr);
         });
-        launch(SIM_K_EVAL, [&] { k_pair_eval<DIM, T, PM, NC2, BATCH><<<g_pl, BLOCK, 0, st>>>(P, out, plist, cand, flag, headA, nextA, ctr, dbg_pairs); });
+        launch(SIM_K_EVAL, [&] { k_pair_eval<DIM, T, PM, NC2, BATCH><<<g_pl, BLOCK, 0, st>>>(P, out, okey, plist, cand, flag, headA, nextA, ctr, dbg_pairs); });
         launch(SIM_K_SELECT_A, [&] { k_select_a<BATCH><<<g_pl, BLOCK, 0, st>>>(P, plist, cand, flag, headA, nextA, headB, nextB, ctr, dbg_picks); });
         const u32 nb_sel = g_pl, nb_dec = P.reversible ? grid_for(maxC, 2048) : 0;
         launch(SIM_K_SELECT_B, [&] {
-            k_select_b<T, BATCH><<<nb_sel + nb_dec, BLOCK, 0, st>>>(P, plist, cand, flag, headB, nextB, out, start, ev, ctr, nb_sel);
+            k_select_b<T, BATCH><<<nb_sel + nb_dec, BLOCK, 0, st>>>(P, plist, cand, flag, headB, nextB, out, start, okey, ev, ctr, nb_sel);
         });
         launch(SIM_K_EVENTS, [&] {
             k_events<DIM, T, NC2, BATCH><<<EV_BLOCKS, BLOCK, 0, st>>>(dparams, out, plist, cand, ev, partner, ctr, dbg_matches, dbg_diss);

@@ -97,6 +97,16 @@ template <bool BATCH> __device__ __forceinline__ u32 local_slot(const Params &Q,
     if constexpr (BATCH) return slot - Q.slot_base;
     else return slot;
 }
+// The replica owning a bucket key (batches): a bucket lies in one replica's
+// cells, and sorted records know their keys, so this table lookup follows the
+// record order where a lookup by slot would gather at random.
+__device__ __forceinline__ u32 rep_of_key(const Params &P, u32 key)
+{
+    u32 c = key;
+    if (c >= P.n_cells) c -= P.n_cells;
+    if (c >= P.n_cells) c -= P.n_cells;
+    return P.cell_rep[c];
+}
 // The replica's own step (replicas may join a batch at different steps).
 template <bool BATCH> __device__ __forceinline__ u32 local_step(const Params &Q, u32 step)
 {
@@ -211,7 +221,7 @@ constexpr u32 NOKEY = 0xFFFFFFFFu;
 template <int DIM, class T, bool BATCH>
 __global__ __launch_bounds__(BLOCK) void k_move_count(Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ okey,
                                                        Rec<T> *__restrict__ tmp, u32 *__restrict__ rank, u32 *__restrict__ cnt,
-                                                       u32 *__restrict__ scnt, Counters *C)
+                                                       u32 *__restrict__ scnt, u32 *__restrict__ nkey, Counters *C)
 {
     __shared__ u32 lds[BLOCK / 64];
     __shared__ u32 skey[BLOCK + 1];  // old bucket keys of the chunk; [BLOCK]: that of the record before it
@@ -239,10 +249,12 @@ __global__ __launch_bounds__(BLOCK) void k_move_count(Params P, const Rec<T> *__
         u32 key = NOKEY;
         if (alive) {
             const u32 slot = meta_slot(m);
-            const Params &Q = rep_params<BATCH>(P, slot);
+            // a batch record's replica: from its old bucket if it has one, else by slot
+            const Params &Q = BATCH ? P.reps[sorted ? rep_of_key(P, ok) : P.rep_of_slot[slot]] : P;
             const Rec<T> q = moved<DIM, T>(Q, r, local_slot<BATCH>(Q, slot), sp, local_step<BATCH>(Q, step));
             tmp[i] = q;
             key = bucket_key<DIM, T, BATCH>(P, Q, sp, q);
+            if constexpr (BATCH) nkey[i] = key;  // the scatter needs no replica lookup
         } else if (valid) {
             tmp[i] = r;  // dead record: the scatter skips it
         }
@@ -351,14 +363,16 @@ __global__ __launch_bounds__(BLOCK) void k_scan(u32 *__restrict__ cnt, u32 *__re
 template <int DIM, class T, bool BATCH>
 __global__ __launch_bounds__(BLOCK) void k_scatter(Params P, const Rec<T> *__restrict__ tmp, const u32 *__restrict__ rank,
                                                     const u32 *__restrict__ start, Rec<T> *__restrict__ out, u32 *__restrict__ okey,
-                                                    const Counters *C)
+                                                    const u32 *__restrict__ nkey, const Counters *C)
 {
     const u32 n = C->n_rec;
     for (u32 i = gtid(); i < n; i += gstride()) {
         const Rec<T> q = tmp[i];
         const u32 m = rec_meta(q), sp = meta_sp(m);
         if (sp > SP_C) continue;
-        const u32 key = bucket_key<DIM, T, BATCH>(P, rep_params<BATCH>(P, meta_slot(m)), sp, q);
+        u32 key;
+        if constexpr (BATCH) key = nkey[i];
+        else key = bucket_key<DIM, T, false>(P, P, sp, q);
         const u32 rk = rank[i];
         const u32 dst = (rk & STAYER) ? start[key] + (rk & ~STAYER) : start[key + 1] - 1u - rk;
         if (dst < P.cap) {
@@ -850,7 +864,7 @@ constexpr int TCAP = 512;  // tests listed per wave
 
 template <int DIM, class T, int PM, bool NARROW, bool BATCH>
 __device__ __forceinline__ void pair_scan_direct(const Params &P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start,
-                                                 PairEnt *__restrict__ list, Counters *C)
+                                                 const u32 *__restrict__ okey, PairEnt *__restrict__ list, Counters *C)
 {
     constexpr int NS = n_slots<DIM, NARROW>();
     constexpr int NW = BLOCK / 64;
@@ -860,6 +874,7 @@ __device__ __forceinline__ void pair_scan_direct(const Params &P, const Rec<T> *
     __shared__ u32 tj[NW][TCAP];
     __shared__ unsigned char town[NW][TCAP];
     __shared__ Rec<T> sa[BLOCK];
+    __shared__ u32 srep[BATCH ? BLOCK : 1];  // replica of each staged A
     if (threadIdx.x == 0) nq = 0;
     const int w = threadIdx.x >> 6, lane = lane_id();
     const u32 a_end = start[P.n_cells];  // A buckets are the keys below n_cells
@@ -874,9 +889,11 @@ __device__ __forceinline__ void pair_scan_direct(const Params &P, const Rec<T> *
         Rec<T> ra = rec[act ? ia : b];
         u32 b0[NS], e0[NS], b1[NS], e1[NS];
         u32 tot = 0;
+        // an A's replica from its bucket (A keys are its cells)
+        const u32 rep = BATCH && act ? P.cell_rep[okey[ia]] : 0u;
         if (act) {
             // B buckets follow the A buckets; a replica's cells start at its cell base
-            const Params &Q = rep_params<BATCH>(P, meta_slot(rec_meta(ra)));
+            const Params &Q = BATCH ? P.reps[rep] : P;
             collect_ranges<DIM, NARROW, T>(Q, P.n_cells + (BATCH ? Q.cell_base : 0u), start, ra, b0, e0, b1, e1);
 #pragma unroll
             for (int s = 0; s < NS; ++s) tot += (e0[s] - b0[s]) + (e1[s] - b1[s]);
@@ -901,6 +918,7 @@ __device__ __forceinline__ void pair_scan_direct(const Params &P, const Rec<T> *
                 }
             }
             sa[threadIdx.x] = ra;
+            if constexpr (BATCH) srep[threadIdx.x] = rep;
         }
         __syncthreads();
         if (fits) {
@@ -921,12 +939,12 @@ __device__ __forceinline__ void pair_scan_direct(const Params &P, const Rec<T> *
                 for (int u = 0; u < U; ++u) {
                     if (jb[u] == NOSLOT) continue;
                     const Rec<T> ro = sa[w * 64 + own[u]];
-                    if (in_range<DIM, T, PM>(rep_params<BATCH>(P, meta_slot(rec_meta(ro))), ro, rb[u]))
+                    if (in_range<DIM, T, PM>(BATCH ? P.reps[srep[w * 64 + own[u]]] : P, ro, rb[u]))
                         append_pair(q, &nq, list, C, P, b + w * 64 + own[u], jb[u]);
                 }
             }
         } else {
-            const Params &Q = rep_params<BATCH>(P, meta_slot(rec_meta(ra)));
+            const Params &Q = BATCH ? P.reps[rep] : P;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 for (u32 j = b0[s]; j < e0[s]; ++j)
@@ -944,16 +962,17 @@ __device__ __forceinline__ void pair_scan_direct(const Params &P, const Rec<T> *
 // typical step at once.
 template <int DIM, class T, int PM, bool BATCH>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void k_pair_scan_direct_narrow(
-    Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start, PairEnt *__restrict__ list, Counters *C)
+    Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start, const u32 *__restrict__ okey, PairEnt *__restrict__ list,
+    Counters *C)
 {
-    pair_scan_direct<DIM, T, PM, true, BATCH>(P, rec, start, list, C);
+    pair_scan_direct<DIM, T, PM, true, BATCH>(P, rec, start, okey, list, C);
 }
 
 template <int DIM, class T, int PM, bool BATCH>
 __global__ __launch_bounds__(BLOCK) void k_pair_scan_direct(Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ start,
-                                                             PairEnt *__restrict__ list, Counters *C)
+                                                             const u32 *__restrict__ okey, PairEnt *__restrict__ list, Counters *C)
 {
-    pair_scan_direct<DIM, T, PM, false, BATCH>(P, rec, start, list, C);
+    pair_scan_direct<DIM, T, PM, false, BATCH>(P, rec, start, okey, list, C);
 }
 
 // ---------------------------------------------------------------------------
@@ -969,9 +988,10 @@ __device__ __forceinline__ u32 chain_push(u64 *head, u32 rec_idx, u32 entry, u32
 }
 
 template <int DIM, class T, int PM, int NC, bool BATCH>
-__global__ __launch_bounds__(BLOCK) void k_pair_eval(Params P, const Rec<T> *__restrict__ rec, const PairEnt *__restrict__ list,
-                                                      CandEnt *__restrict__ cand, u32 *__restrict__ flag, u64 *__restrict__ headA,
-                                                      u32 *__restrict__ nextA, Counters *C, DbgPair *dbg)
+__global__ __launch_bounds__(BLOCK) void k_pair_eval(Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ okey,
+                                                      const PairEnt *__restrict__ list, CandEnt *__restrict__ cand,
+                                                      u32 *__restrict__ flag, u64 *__restrict__ headA, u32 *__restrict__ nextA,
+                                                      Counters *C, DbgPair *dbg)
 {
     __shared__ u32 lds[BLOCK / 64];
     const u32 step = C->step;
@@ -981,7 +1001,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair_eval(Params P, const Rec<T> *__r
         const PairEnt e = list[k];
         const Rec<T> ra = rec[e.a_idx], rb = rec[e.b_idx];
         const u32 sa = meta_slot(rec_meta(ra)), sb = meta_slot(rec_meta(rb));
-        const Params &Q = rep_params<BATCH>(P, sa);  // A and B of a pair share their replica
+        const Params &Q = BATCH ? P.reps[P.cell_rep[okey[e.a_idx]]] : P;  // the A's bucket; A and B share their replica
         double dA[3];
         const u32 ls = local_step<BATCH>(Q, step);
         displacement<DIM, T>(Q, local_slot<BATCH>(Q, sa), SP_A, ls, dA);
@@ -1120,7 +1140,8 @@ template <class T, bool BATCH>
 __global__ __launch_bounds__(BLOCK) void k_select_b(Params P, const PairEnt *__restrict__ list, const CandEnt *__restrict__ cand,
                                                      const u32 *__restrict__ flag, const u64 *__restrict__ headB,
                                                      const u32 *__restrict__ nextB, const Rec<T> *__restrict__ rec,
-                                                     const u32 *__restrict__ start, u32 *__restrict__ ev, Counters *C, u32 nb_sel)
+                                                     const u32 *__restrict__ start, const u32 *__restrict__ okey, u32 *__restrict__ ev,
+                                                     Counters *C, u32 nb_sel)
 {
     const u32 step = C->step;
     if (blockIdx.x >= nb_sel) {
@@ -1129,7 +1150,7 @@ __global__ __launch_bounds__(BLOCK) void k_select_b(Params P, const PairEnt *__r
         const u32 t0 = (blockIdx.x - nb_sel) * BLOCK + threadIdx.x, ts = (gridDim.x - nb_sel) * BLOCK;
         for (u32 i = beg + t0; i < end; i += ts) {
             const u32 sc = meta_slot(rec_meta(rec[i]));
-            const Params &Q = rep_params<BATCH>(P, sc);
+            const Params &Q = BATCH ? P.reps[rep_of_key(P, okey[i])] : P;  // C records binned this step
             if (below(philox(local_slot<BATCH>(Q, sc), NOSLOT, local_step<BATCH>(Q, step), TAG_UNI, Q.key).x, P.p_uni))
                 ev[atomicAdd(&C->n_ev, 1u)] = EV_DECAY | i;
         }
