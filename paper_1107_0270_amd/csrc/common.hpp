@@ -114,7 +114,8 @@ struct Params {
     double p_uni;    // 1 - exp(-k_off dt)
     Key key;
     u32 cap;
-    u32 cap_pl;          // capacity of the per-step pair list
+    u32 cap_pl;          // capacity of the per-step pair list (PL_SEGS segments of seg_cap)
+    u32 seg_cap;
     u32 cnt_region;      // words per region of the bucket counters (keys padded to whole scan tiles / 16)
     int tiled;           // pair search through LDS bricks (all edges >= 3 cells)
     int bx, by, bz;      // brick edges in cells
@@ -140,12 +141,21 @@ enum {
 
 enum { ERR_PAIRS = 1, ERR_APPEND = 8 };
 
+// The per-step pair list is cut into PL_SEGS segments of cap_pl / PL_SEGS
+// entries, each with its own counter on its own 256-byte line: workgroup b
+// appends to segment b mod PL_SEGS, so the appends of a step spread over
+// PL_SEGS addresses (atomics on one address are serialised).  Pair k of the
+// step (0 <= k < the sum of the counts) is entry k - (pairs in earlier
+// segments) of its segment.
+constexpr u32 PL_SEGS = 16;
+constexpr u32 PL_STRIDE = 64;  // words between segment counters
+
 // Device-resident counters; the work sizes of the data-dependent stages live
 // here so that no stage needs the host to learn a count.
 struct Counters {
     u32 n_rec;      // records in the current buffer (sorted + appended)
     u32 n_live;     // records placed by the last binning
-    u32 n_pl;       // A-B pairs within r_cut found this step
+    u32 n_pl;       // A-B pairs within r_cut found by the last step (its segments summed)
     u32 n_append;
     u32 step;       // step number used by every draw of this step
     u32 err;
@@ -157,6 +167,7 @@ struct Counters {
     u64 stats[ST_N];
     u64 stats_last[ST_N];
     u64 stats_sum[ST_N];
+    u32 pl_seg[PL_SEGS * PL_STRIDE];  // pairs appended to each segment (count at [x * PL_STRIDE])
 };
 
 // An A-B pair within r_cut (record indices in the sorted buffer).

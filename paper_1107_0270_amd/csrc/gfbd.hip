@@ -366,6 +366,13 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         return SIM_OK;
     }
 
+    // pair list: four entries per slot, at least 2^20, at most 2^30, in whole segments
+    void set_pair_cap(Params &Q) const
+    {
+        Q.cap_pl = (u32)std::min<uint64_t>(std::max<uint64_t>(1u << 20, 4 * n), 1u << 30) & ~(PL_SEGS - 1);
+        Q.seg_cap = Q.cap_pl / PL_SEGS;
+    }
+
     int open_stream()
     {
         if (!M.stream) {  // a stream of our own: the null stream cannot be captured into a graph
@@ -382,7 +389,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         int rc;
         if ((rc = open_stream()) || (rc = setup_replica(M, n, sp, P, cell_edge, pair_tests, narrow))) return rc;
         P.cap = (u32)n;
-        P.cap_pl = (u32)std::min<uint64_t>(std::max<uint64_t>(1u << 20, 4 * n), 1u << 30);
+        set_pair_cap(P);
         uint64_t nB = 0, nC = 0;
         for (uint64_t i = 0; i < n; ++i) {
             nB += sp[i] == SIM_SP_B;
@@ -459,7 +466,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         P.slot_base = P.cell_base = P.step_base = 0;
         P.n_rep = (u32)R;
         P.cap = (u32)n;
-        P.cap_pl = (u32)std::min<uint64_t>(std::max<uint64_t>(1u << 20, 4 * n), 1u << 30);
+        set_pair_cap(P);
         P.tiled = 0;
         if ((rc = alloc(d_reps, R)) || (rc = alloc(d_rep_of_slot, n)) || (rc = alloc(d_cell_rep, cbase))) return rc;
         P.reps = d_reps;
@@ -471,6 +478,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         for (auto &q : reps_h) {  // fields shared by the whole batch
             q.cap = P.cap;
             q.cap_pl = P.cap_pl;
+            q.seg_cap = P.seg_cap;
             q.n_rep = P.n_rep;
             q.reps = d_reps;
             q.rep_of_slot = d_rep_of_slot;
@@ -504,7 +512,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         P.slot_base = P.cell_base = P.step_base = 0;
         P.n_rep = rep_cap;
         P.cap = (u32)n;
-        P.cap_pl = (u32)std::min<uint64_t>(std::max<uint64_t>(1u << 20, 4 * n), 1u << 30);
+        set_pair_cap(P);
         P.tiled = 0;
         if ((rc = alloc(d_reps, rep_cap)) || (rc = alloc(d_rep_of_slot, n)) || (rc = alloc(d_cell_rep, cell_cap))) return rc;
         P.reps = d_reps;
@@ -513,6 +521,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         for (auto &q : reps_h) {
             q.cap = P.cap;
             q.cap_pl = P.cap_pl;
+            q.seg_cap = P.seg_cap;
             q.n_rep = P.n_rep;
             q.reps = d_reps;
             q.rep_of_slot = d_rep_of_slot;
@@ -661,6 +670,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         Q.step_base = (u32)stepno - rp.step;  // the member's own step = pool step - base
         Q.cap = P.cap;
         Q.cap_pl = P.cap_pl;
+        Q.seg_cap = P.seg_cap;
         Q.n_rep = P.n_rep;
         Q.reps = d_reps;
         Q.rep_of_slot = d_rep_of_slot;

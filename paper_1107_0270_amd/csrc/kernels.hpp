@@ -662,6 +662,9 @@ template <int NT> __device__ inline u32 group_excl_scan(u32 v, u32 *lds, u32 &to
     return off + inc - v;
 }
 
+// This workgroup's segment of the pair list and its counter.
+__device__ __forceinline__ u32 pl_segment() { return blockIdx.x % PL_SEGS; }
+
 __device__ __forceinline__ void append_pair(PairEnt *q, u32 *nq, PairEnt *list, Counters *C, const Params &P, u32 a, u32 b)
 {
     const u32 k = atomicAdd(nq, 1u);
@@ -671,26 +674,56 @@ __device__ __forceinline__ void append_pair(PairEnt *q, u32 *nq, PairEnt *list, 
     if (k < (u32)QCAP) {
         q[k] = e;
     } else {
-        const u32 g = atomicAdd(&C->n_pl, 1u);
-        if (g < P.cap_pl) list[g] = e;
+        const u32 x = pl_segment();
+        const u32 g = atomicAdd(&C->pl_seg[x * PL_STRIDE], 1u);
+        if (g < P.seg_cap) list[x * P.seg_cap + g] = e;
         else atomicOr(&C->err, (u32)ERR_PAIRS);
     }
 }
 
-// Append a workgroup's queued pairs to the global list with one atomic.
+// Append a workgroup's queued pairs to its segment with one atomic.
 template <int NT>
 __device__ __forceinline__ void flush_pairs(const PairEnt *q, const u32 &nq, u32 &qbase, PairEnt *list, Counters *C, const Params &P)
 {
     __syncthreads();
-    const u32 n = min(nq, (u32)QCAP);
-    if (threadIdx.x == 0) qbase = n ? atomicAdd(&C->n_pl, n) : 0u;
+    const u32 n = min(nq, (u32)QCAP), x = pl_segment();
+    if (threadIdx.x == 0) qbase = n ? atomicAdd(&C->pl_seg[x * PL_STRIDE], n) : 0u;
     __syncthreads();
     for (u32 i = threadIdx.x; i < n; i += NT) {
         const u32 g = qbase + i;
-        if (g < P.cap_pl) list[g] = q[i];
+        if (g < P.seg_cap) list[x * P.seg_cap + g] = q[i];
         else atomicOr(&C->err, (u32)ERR_PAIRS);
     }
 }
+
+// The pairs of the step across the segments: pre[x] = pairs in segments
+// before x (wave-uniform values); returns the total.
+struct PairIndex {
+    u32 pre[PL_SEGS];
+    u32 total, seg_cap;
+    __device__ __forceinline__ PairIndex(const Counters *C, const Params &P) : seg_cap(P.seg_cap)
+    {
+        u32 s = 0;
+#pragma unroll
+        for (u32 x = 0; x < PL_SEGS; ++x) {
+            pre[x] = s;
+            s += min(C->pl_seg[x * PL_STRIDE], seg_cap);
+        }
+        total = s;
+    }
+    // the list entry of pair k < total
+    __device__ __forceinline__ u32 entry(u32 k) const
+    {
+        u32 seg = 0, off = 0;
+#pragma unroll
+        for (u32 x = 1; x < PL_SEGS; ++x)
+            if (k >= pre[x]) {
+                seg = x;
+                off = pre[x];
+            }
+        return seg * seg_cap + (k - off);
+    }
+};
 
 __device__ __forceinline__ int wrapc(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
@@ -995,9 +1028,10 @@ __global__ __launch_bounds__(BLOCK) void k_pair_eval(Params P, const Rec<T> *__r
 {
     __shared__ u32 lds[BLOCK / 64];
     const u32 step = C->step;
-    const u32 n = min(C->n_pl, P.cap_pl);
+    const PairIndex pi(C, P);
     u32 st[5] = {0, 0, 0, 0, 0};  // pairs, cand, overlap, r0clamp, near
-    for (u32 k = gtid(); k < n; k += gstride()) {
+    for (u32 kk = gtid(); kk < pi.total; kk += gstride()) {
+        const u32 k = pi.entry(kk);
         const PairEnt e = list[k];
         const Rec<T> ra = rec[e.a_idx], rb = rec[e.b_idx];
         const u32 sa = meta_slot(rec_meta(ra)), sb = meta_slot(rec_meta(rb));
@@ -1092,9 +1126,10 @@ __global__ __launch_bounds__(BLOCK) void k_select_a(Params P, const PairEnt *__r
                                                      Counters *C, DbgPick *dbg)
 {
     const u32 step = C->step;
-    const u32 n = min(C->n_pl, P.cap_pl);
+    const PairIndex pi(C, P);
     u32 picks = 0;
-    for (u32 k = gtid(); k < n; k += gstride()) {
+    for (u32 kk = gtid(); kk < pi.total; kk += gstride()) {
+        const u32 k = pi.entry(kk);
         if (flag[k] == PE_PAIR) continue;
         const CandEnt me = cand[k];
         const u32 h = (u32)headA[list[k].a_idx];
@@ -1156,9 +1191,10 @@ __global__ __launch_bounds__(BLOCK) void k_select_b(Params P, const PairEnt *__r
         }
         return;
     }
-    const u32 n = min(C->n_pl, P.cap_pl);
+    const PairIndex pi(C, P);
     u32 n_match = 0;
-    for (u32 k = blockIdx.x * BLOCK + threadIdx.x; k < n; k += nb_sel * BLOCK) {
+    for (u32 kk = blockIdx.x * BLOCK + threadIdx.x; kk < pi.total; kk += nb_sel * BLOCK) {
+        const u32 k = pi.entry(kk);
         if (flag[k] != PE_PICKED) continue;
         const u32 h = (u32)headB[list[k].b_idx];
         u32 mins = NOSLOT, count = 0;
@@ -1187,17 +1223,26 @@ __global__ __launch_bounds__(BLOCK) void k_select_b(Params P, const PairEnt *__r
 __global__ void k_close(Counters *C)
 {
     const int s = threadIdx.x;
+    __shared__ u32 n_pl;
+    if (s == 0) {
+        u32 t = 0;
+        for (u32 x = 0; x < PL_SEGS; ++x) t += C->pl_seg[x * PL_STRIDE];
+        n_pl = t;
+    }
+    __syncthreads();
     if (s < ST_N) {
-        const u64 v = s == ST_PAIRS ? (u64)C->n_pl : C->stats[s];
+        const u64 v = s == ST_PAIRS ? (u64)n_pl : C->stats[s];
         C->stats_last[s] = v;
         C->stats_sum[s] += v;
         C->stats[s] = 0;
     }
+    if (s < (int)PL_SEGS) C->pl_seg[s * PL_STRIDE] = 0;
     __syncthreads();
     if (s == 0) {
         C->n_rec = C->n_live + C->n_append;
         C->n_sorted = C->n_live;  // records [0, n_live) carry their bucket keys
-        C->n_pl = C->n_append = C->n_ev = 0;
+        C->n_pl = n_pl;
+        C->n_append = C->n_ev = 0;
         C->step += 1u;
     }
 }
