@@ -291,6 +291,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests in the served trace (--serve)")
     ap.add_argument("--pool-slots", type=int, default=1 << 26, help="slots of each pool (--serve)")
     ap.add_argument("--tick", type=int, default=200, help="most steps per pool call (--serve)")
+    ap.add_argument("--precision", choices=["workload", "fp64", "fp32", "fp32nc"], default="workload",
+                    help="precision mode (default: the workload's; fp32 = plain binary32, fp32nc = binary32 with "
+                         "binary64 near-contact arguments and displacements)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the cell edge and pair-search kernel by timing candidates on the workload first")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -324,6 +327,8 @@ def main():
         return
 
     cfg = I.workload(args.workload)
+    if args.precision != "workload":
+        cfg["precision"] = {"fp64": S.PREC_FP64, "fp32": S.PREC_FP32, "fp32nc": S.PREC_FP32_FP64NC}[args.precision]
     dim = cfg["dim"]
     t0 = time.time()
     sp, pos, box, red = I.state_for(cfg, seed=0)
@@ -349,8 +354,12 @@ def main():
                  "table": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()} for r in table]}
         log(f"[bench] autotuned in {tuned['seconds']} s: {best}")
 
-    def make(timing):
-        return make_with(timing, args.cell, search)
+    def make(timing, precision=None):
+        if precision is None:
+            return make_with(timing, args.cell, search)
+        return S.Sim(dim=dim, box=box, dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
+                     k_off=cfg["k_off"], precision=precision, seed=0, species=sp, pos=pos, timing=timing, cell=args.cell,
+                     pair_search=search)
 
     def timed(sim):
         sim.step(args.warmup)
@@ -371,6 +380,16 @@ def main():
     sim.close()
     ps = n_live * args.steps / el
     log(f"[bench] graph: {args.steps} steps in {el * 1e3:.1f} ms; {ps:.3e} particle-steps/s; {pairs / el:.3e} pair evals/s")
+    # the same workload in the plain binary32 mode (binary32 displacements and p_enc)
+    plain = None
+    if cfg["precision"] == S.PREC_FP32_FP64NC:
+        sim = make(False, S.PREC_FP32)
+        el32, n32, pairs32, _, _, _ = timed(sim)
+        sim.close()
+        plain = {"value": round(n32 * args.steps / el32, 1), "unit": "particle-steps/s",
+                 "ms_per_step": round(el32 * 1e3 / args.steps, 5), "pair_evals_per_s": round(pairs32 / el32, 1),
+                 "precision": "binary32 state, displacements, pair test and p_enc; binary64 propagation"}
+        log(f"[bench] plain binary32: {plain}")
     # pass 2: the same steps with HIP events around every kernel -> kernel durations
     kt, el_ev = {}, None
     if not args.no_timing:
@@ -436,6 +455,7 @@ def main():
                    "step_launch": "one hipGraph replay per step",
                    "cell_edge_um": der["cell"]},
         "autotune": tuned,
+        "plain_fp32": plain,
         "roofline": roof,
         "kernel_ms_per_step": {k: round(v[0] / max(args.steps, 1), 5) for k, v in kt.items()},
         "cpu_baseline": cpu,

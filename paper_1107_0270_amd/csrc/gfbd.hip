@@ -827,7 +827,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         Rec<T> *in = rec[c], *out = rec[c ^ 1];
         const u32 g_all = grid_for(n, 8192);
         const u32 g_pl = 1024;
-        launch(SIM_K_MOVE, [&] { k_move_count<DIM, T, BATCH><<<g_all, BLOCK, 0, st>>>(P, in, okey, tmp, rank, cnt, scnt, nkey, ctr); });
+        launch(SIM_K_MOVE, [&] { k_move_count<DIM, T, PM, BATCH><<<g_all, BLOCK, 0, st>>>(P, in, okey, tmp, rank, cnt, scnt, nkey, ctr); });
         launch(SIM_K_SCAN, [&] {
             k_scan_tiles<<<nb_scan, BLOCK, 0, st>>>(cnt, scnt, bsum);
             k_scan<<<nb_scan, BLOCK, 0, st>>>(cnt, scnt, bsum, start, ctr);

@@ -67,10 +67,25 @@ template <class T> __device__ __forceinline__ double cos_turn(double u)
     return sizeof(T) == 8 ? cos((2.0 * PI_D) * u) : cospi(2.0 * u);
 }
 
-template <int DIM, class T> __device__ inline void displacement(const Params &P, u32 slot, u32 sp, u32 step, double d[3])
+// The plain binary32 mode (PM_F32) takes the same draws through a binary32
+// Box-Muller: its displacements differ from the binary64 ones by a few
+// binary32 rounding errors of the displacement.
+__device__ __forceinline__ float u01f(u32 w) { return ((float)w + 0.5f) * 0x1p-32f; }
+
+template <int DIM, class T, int PM> __device__ inline void displacement(const Params &P, u32 slot, u32 sp, u32 step, double d[3])
 {
 #pragma clang fp contract(off)
     const uint4 r = philox(slot, NOSLOT, step, TAG_MOVE, P.key);
+    if constexpr (PM == PM_F32) {
+        const float s = (float)P.sd[sp];
+        const float r0 = sqrtf(-2.0f * logf(u01f(r.x)));
+        float s0, c0;
+        sincospif(2.0f * u01f(r.y), &s0, &c0);
+        d[0] = (double)(s * (r0 * c0));
+        d[1] = (double)(s * (r0 * s0));
+        d[2] = DIM == 3 ? (double)(s * (sqrtf(-2.0f * logf(u01f(r.z))) * cospif(2.0f * u01f(r.w)))) : 0.0;
+        return;
+    }
     const double s = P.sd[sp];
     const double r0 = sqrt(-2.0 * log(u01(r.x)));
     double s0, c0;
@@ -115,11 +130,11 @@ template <bool BATCH> __device__ __forceinline__ u32 local_step(const Params &Q,
 }
 
 // x' = wrap(x + displacement) for the record of (replica-local) slot `slot`.
-template <int DIM, class T> __device__ inline Rec<T> moved(const Params &P, const Rec<T> &r, u32 slot, u32 sp, u32 step)
+template <int DIM, class T, int PM> __device__ inline Rec<T> moved(const Params &P, const Rec<T> &r, u32 slot, u32 sp, u32 step)
 {
 #pragma clang fp contract(off)
     double d[3];
-    displacement<DIM, T>(P, slot, sp, step, d);
+    displacement<DIM, T, PM>(P, slot, sp, step, d);
     Rec<T> q;
     q.x = wrap_store<T>((double)r.x + d[0], P.L[0]);
     q.y = wrap_store<T>((double)r.y + d[1], P.L[1]);
@@ -218,7 +233,7 @@ __device__ inline u32 block_incl_max(u32 v, u32 *lds)
 constexpr u32 STAYER = 0x80000000u;
 constexpr u32 NOKEY = 0xFFFFFFFFu;
 
-template <int DIM, class T, bool BATCH>
+template <int DIM, class T, int PM, bool BATCH>
 __global__ __launch_bounds__(BLOCK) void k_move_count(Params P, const Rec<T> *__restrict__ rec, const u32 *__restrict__ okey,
                                                        Rec<T> *__restrict__ tmp, u32 *__restrict__ rank, u32 *__restrict__ cnt,
                                                        u32 *__restrict__ scnt, u32 *__restrict__ nkey, Counters *C)
@@ -251,7 +266,7 @@ __global__ __launch_bounds__(BLOCK) void k_move_count(Params P, const Rec<T> *__
             const u32 slot = meta_slot(m);
             // a batch record's replica: from its old bucket if it has one, else by slot
             const Params &Q = BATCH ? P.reps[sorted ? rep_of_key(P, ok) : P.rep_of_slot[slot]] : P;
-            const Rec<T> q = moved<DIM, T>(Q, r, local_slot<BATCH>(Q, slot), sp, local_step<BATCH>(Q, step));
+            const Rec<T> q = moved<DIM, T, PM>(Q, r, local_slot<BATCH>(Q, slot), sp, local_step<BATCH>(Q, step));
             tmp[i] = q;
             key = bucket_key<DIM, T, BATCH>(P, Q, sp, q);
             if constexpr (BATCH) nkey[i] = key;  // the scatter needs no replica lookup
@@ -434,7 +449,7 @@ __device__ inline PairQ pair_quantities(const Params &P, const Rec<T> &ra, const
 #pragma clang fp contract(off)
     PairQ q;
     double dB[3];
-    displacement<DIM, T>(P, sb, SP_B, step, dB);
+    displacement<DIM, T, PM>(P, sb, SP_B, step, dB);
     if (PM == PM_F32) {
         const float rx = min_image_f((float)rb.x, (float)ra.x, P.Lf[0], P.Lhf[0]);
         const float ry = min_image_f((float)rb.y, (float)ra.y, P.Lf[1], P.Lhf[1]);
@@ -1038,7 +1053,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair_eval(Params P, const Rec<T> *__r
         const Params &Q = BATCH ? P.reps[P.cell_rep[okey[e.a_idx]]] : P;  // the A's bucket; A and B share their replica
         double dA[3];
         const u32 ls = local_step<BATCH>(Q, step);
-        displacement<DIM, T>(Q, local_slot<BATCH>(Q, sa), SP_A, ls, dA);
+        displacement<DIM, T, PM>(Q, local_slot<BATCH>(Q, sa), SP_A, ls, dA);
         const PairQ q = pair_quantities<DIM, T, PM, NC>(Q, ra, rb, local_slot<BATCH>(Q, sa), local_slot<BATCH>(Q, sb), dA, ls);
         st[0] += 1;
         st[1] += q.cand;

@@ -7,6 +7,11 @@ radius, p_reac, reaction flag), the dissociations, and the final state.  A
 decision may legitimately differ only where the draw lies within 1e-6 of the
 probability; such steps are counted, and the GPU is then reloaded with the
 oracle's state (oracle -> GPU only) so the comparison can go on.
+
+In lock-step mode (for a mode whose move is not bit-identical to the oracle's,
+the plain binary32 one) positions within pos_tol are accepted and the GPU is
+reloaded with the oracle's state after every step that differs, so each step
+is compared from identical states; such reloads are counted apart.
 """
 from __future__ import annotations
 
@@ -38,6 +43,8 @@ class Report:
     near_decisions: int = 0
     unexplained: int = 0
     resyncs: int = 0
+    pos_resyncs: int = 0
+    max_dmove: float = 0.0
     notes: list = dataclasses.field(default_factory=list)
 
 
@@ -58,7 +65,7 @@ def _key(a, b):
     return (a.astype(np.uint64) << np.uint64(32)) | b.astype(np.uint64)
 
 
-def compare_step(gpu, orc, rep: Report, *, p_tol, pos_tol, box, rcut, sp_before):
+def compare_step(gpu, orc, rep: Report, *, p_tol, pos_tol, box, rcut, sp_before, lockstep=False):
     """Advance both sides one step and compare; returns True if the states agree afterwards."""
     gpu.step()
     orc.step()
@@ -70,6 +77,7 @@ def compare_step(gpu, orc, rep: Report, *, p_tol, pos_tol, box, rcut, sp_before)
         d = np.abs(gm[live] - om[live])
         d = np.minimum(d, box - d)
         rep.max_dpos = max(rep.max_dpos, float(d.max()))
+        rep.max_dmove = max(rep.max_dmove, float(d.max()))
     # 2.-3. pairs, p_enc, draws, candidates
     gp, op = gpu.dbg_pairs(), orc.pairs()
     rep.pairs += len(op)
@@ -140,6 +148,7 @@ def compare_step(gpu, orc, rep: Report, *, p_tol, pos_tol, box, rcut, sp_before)
     gsp, gpos, gpt = gpu.state()
     osp, opos, opt = orc.state()
     same = np.array_equal(gsp, osp)
+    drift = False
     if same:
         lv = osp <= O.SP_C
         if lv.any():
@@ -147,8 +156,12 @@ def compare_step(gpu, orc, rep: Report, *, p_tol, pos_tol, box, rcut, sp_before)
             d = np.minimum(d, box - d)
             rep.max_dpos = max(rep.max_dpos, float(d.max()))
             same = float(d.max()) <= pos_tol
+            drift = float(d.max()) > 0.0
         cs = osp == O.SP_C
         same = same and np.array_equal(gpt[cs], opt[cs])
+    if same and drift and lockstep:
+        rep.pos_resyncs += 1
+        gpu.load_state(orc.stepno, osp, opos, opt)
     if not same:
         if decisions_ok:
             rep.notes.append(f"step {rep.steps}: state differs without a decision difference")
@@ -158,12 +171,13 @@ def compare_step(gpu, orc, rep: Report, *, p_tol, pos_tol, box, rcut, sp_before)
     return osp
 
 
-def run(gpu, orc, steps, *, p_tol, pos_tol, box):
+def run(gpu, orc, steps, *, p_tol, pos_tol, box, lockstep=False):
     rep = Report()
     rcut = orc.derived()["rcut"]
     sp, _, _ = orc.state()
     for k in range(steps):
-        sp = compare_step(gpu, orc, rep, p_tol=p_tol, pos_tol=pos_tol, box=box, rcut=rcut, sp_before=sp)
+        sp = compare_step(gpu, orc, rep, p_tol=p_tol, pos_tol=pos_tol, box=box, rcut=rcut, sp_before=sp,
+                          lockstep=lockstep)
         print(f"  step {k}: pairs {rep.pairs} matches {rep.matches} reactions {rep.reactions} "
               f"max|dp| {rep.max_dp:.2e} resyncs {rep.resyncs}", flush=True)
     return rep

@@ -1,13 +1,20 @@
 """Parity of the HIP path (through the C-ABI) with the FP64 oracle, step by step.
 
 Tolerances (written out here, derived in the design doc):
-  * positions: binary32 states are bit-identical to the oracle's (both round the
-    same binary64 update once); binary64 states agree to 1e-12 of the box.
+  * positions: binary32 states with binary64 displacements are bit-identical to
+    the oracle's (both round the same binary64 update once); binary64 states
+    agree to 1e-12 of the box.  The plain binary32 mode draws its displacements
+    through binary32 arithmetic: a coordinate may then round to the binary32
+    neighbour of the oracle's, so its moves are held to one binary32 unit of
+    the box edge and compared in lock step.
   * pair lists: identical sets; draws bit-identical.
   * p_enc: 1e-12 (FP64), 1e-6 (FP32 with binary64 near-contact arguments);
     the plain FP32 mode reports its error and is held to 1e-4.
   * decisions: identical except draws within 1e-6 of p (counted).
-  * propagated radius and p_reac (binary64 on both sides): 1e-9.
+  * propagated radius and p_reac (binary64 on both sides): 1e-9 from identical
+    inputs.  In the plain binary32 mode the inputs may differ by one binary32
+    unit of a coordinate, i.e. 2^-22 um / sigma = 4.8e-5 in units of sigma at a
+    2.5 um box and sigma = 5 nm; R'' and p_reac are then held to 1e-4.
 """
 import math
 
@@ -28,13 +35,13 @@ def _state(n_a, n_b, box, dim, sigma, seed, f32):
     return sp, pos
 
 
-def _check(rep, *, p_tol, allow_near=2):
+def _check(rep, *, p_tol, allow_near=2, rpp_tol=1e-9):
     print(rep)
     assert rep.pair_set_mismatch == 0
     assert rep.draw_mismatch == 0
     assert rep.unexplained == 0, rep.notes
     assert rep.max_dp <= p_tol
-    assert rep.max_dRpp <= 1e-9 and rep.max_dpreac <= 1e-9
+    assert rep.max_dRpp <= rpp_tol and rep.max_dpreac <= rpp_tol
     assert rep.near_decisions <= allow_near
 
 
@@ -53,6 +60,9 @@ def test_abs3d_fp64_trajectory():
 KERNELS = [S.PAIRS_BRICKS, S.PAIRS_DIRECT]
 
 
+F32_ULP_2_5 = 2.0 ** -22  # one binary32 unit in [2, 4): the coordinates of a 2.5 um box
+
+
 @pytest.mark.parametrize("pair_search", KERNELS)
 @pytest.mark.parametrize("prec,p_tol", [(S.PREC_FP32_FP64NC, 1e-6), (S.PREC_FP32, 1e-4)])
 def test_rad3d_reversible_binary32(prec, p_tol, pair_search):
@@ -62,9 +72,15 @@ def test_rad3d_reversible_binary32(prec, p_tol, pair_search):
     sp, pos = _state(n, n, 2.5, 3, 0.005, 1, True)
     gpu, orc = make_pair(dim=3, bc=O.BC_RAD, box=2.5, dt=1e-5, D=(1.0, 1.0, 0.5), sigma=0.005, kappa=0.1,
                          k_off=2000.0, precision=prec, species=sp, pos=pos, seed=3, pair_search=pair_search)
-    rep = run(gpu, orc, 30, p_tol=p_tol, pos_tol=0.0, box=2.5)
-    _check(rep, p_tol=p_tol)
+    plain = prec == S.PREC_FP32
+    rep = run(gpu, orc, 30, p_tol=p_tol, pos_tol=F32_ULP_2_5 if plain else 0.0, box=2.5, lockstep=plain)
+    _check(rep, p_tol=p_tol, rpp_tol=1e-4 if plain else 1e-9)
     assert rep.reactions > 20 and rep.decays > 0
+    if plain:
+        assert rep.max_dmove <= F32_ULP_2_5
+        print(f"plain binary32 moves: max |dx| {rep.max_dmove:.3e} um, {rep.pos_resyncs} lock-step reloads in 30 steps")
+    else:
+        assert rep.max_dmove == 0.0 and rep.pos_resyncs == 0
 
 
 @pytest.mark.parametrize("pair_search", KERNELS)
