@@ -46,17 +46,17 @@ def algorithmic_bytes(kernel, n_live, n_a, n_b, n_keys):
 # commands are in profiles/rad3d_step_traffic.md.  Valid only for the kernel sources they were taken
 # on (hash below): after any change to them the field is reported as null.
 MEASURED_TRAFFIC = {
-    "src_hash": "11263d1d77ecf003",
+    "src_hash": "5492d80a6ab44abd",
     "scale_fetch": 1.9998, "scale_write": 1.0,
     "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
-        "move": (9816.4, 31266.3),
-        "scan": (5809.5 + 5820.5, 11.3 + 17376.1),
-        "scatter": (17027.9, 29451.3),
-        "pairs": (9598.4, 157.7),
-        "eval": (1019.8, 94.5),
-        "select_a": (146.9, 52.6),
-        "select_b": (157.9, 11.8),
-        "events": (1287.5 + 1.6, 5654.5 + 0.4),
+        "move": (9830.1, 31266.3),
+        "scan": (5806.6 + 5824.0, 11.3 + 17376.1),
+        "scatter": (17020.8, 29458.7),
+        "pairs": (9597.7, 119.4),
+        "eval": (1035.0, 95.7),
+        "select_a": (163.8, 52.7),
+        "select_b": (170.0, 11.4),
+        "events": (563.5 + 2.8, 3279.2 + 0.8),
     },
 }
 
@@ -294,6 +294,7 @@ def main():
     ap.add_argument("--precision", choices=["workload", "fp64", "fp32", "fp32nc"], default="workload",
                     help="precision mode (default: the workload's; fp32 = plain binary32, fp32nc = binary32 with "
                          "binary64 near-contact arguments and displacements)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain binary32 comparison run")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the cell edge and pair-search kernel by timing candidates on the workload first")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -382,7 +383,7 @@ def main():
     log(f"[bench] graph: {args.steps} steps in {el * 1e3:.1f} ms; {ps:.3e} particle-steps/s; {pairs / el:.3e} pair evals/s")
     # the same workload in the plain binary32 mode (binary32 displacements and p_enc)
     plain = None
-    if cfg["precision"] == S.PREC_FP32_FP64NC:
+    if cfg["precision"] == S.PREC_FP32_FP64NC and not args.no_plain:
         sim = make(False, S.PREC_FP32)
         el32, n32, pairs32, _, _, _ = timed(sim)
         sim.close()
