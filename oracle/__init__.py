@@ -36,7 +36,7 @@ class Params(C.Structure):
     _fields_ = [("dim", C.c_int32), ("bc", C.c_int32), ("store_f32", C.c_int32), ("n_terms", C.c_int32),
                 ("box", C.c_double * 3), ("dt", C.c_double), ("D", C.c_double * 3), ("sigma", C.c_double),
                 ("kappa_a", C.c_double), ("k_off", C.c_double), ("eps_cut", C.c_double), ("rcut", C.c_double),
-                ("seed", C.c_uint64), ("replica", C.c_uint32), ("pad", C.c_uint32)]
+                ("seed", C.c_uint64), ("replica", C.c_uint32), ("exact2d", C.c_int32)]
 
 
 PAIR_DT = np.dtype([("i", "<u4"), ("j", "<u4"), ("R", "<f8"), ("R0", "<f8"), ("p", "<f8"),
@@ -82,6 +82,11 @@ def lib():
         "orc_preac2": (d, [d, d, d, d, i]),
         "orc_prop2_density": (d, [d, d, d, i]),
         "orc_sample_prop": (d, [i, d, d, i, P(u32), P(u32), P(u32), P(u32)]),
+        "orc_g2x": (None, [d, d, d, d, P(d)]),
+        "orc_m2x": (None, [d, d, d, P(d)]),
+        "orc_penc2x": (d, [d, d, d]),
+        "orc_preac2x": (d, [d, d, d, d]),
+        "orc_sample_prop2x": (d, [d, d, d]),
         "orc_rcut": (d, [i, i, d, d, d, d, d]),
         "orc_sim_create": (vp, [P(Params), u64, vp, vp, vp]),
         "orc_sim_destroy": (None, [vp]),
@@ -217,6 +222,32 @@ def sample_prop(dim, R0, tau, n_terms, ctr, key):
     return Rp, att.value, hits.value
 
 
+def g2x(R, R0, tau, hh):
+    """Exact 2D radial Green's functions (a^2 g_abs, g_ref, g_rad) by quadrature."""
+    out = np.zeros(3)
+    lib().orc_g2x(float(R), float(R0), float(tau), float(hh), _dp(out))
+    return out
+
+
+def m2x(R, R0, tau):
+    """int_1^R 2 pi R' g(R'|R0) dR' of the absorbing and reflecting functions."""
+    out = np.zeros(2)
+    lib().orc_m2x(float(R), float(R0), float(tau), _dp(out))
+    return out
+
+
+def penc2x(R, R0, tau):
+    return lib().orc_penc2x(float(R), float(R0), float(tau))
+
+
+def preac2x(R, R0, tau, hh):
+    return lib().orc_preac2x(float(R), float(R0), float(tau), float(hh))
+
+
+def sample_prop2x(R0, tau, u):
+    return lib().orc_sample_prop2x(float(R0), float(tau), float(u))
+
+
 def rcut(dim, bc, a, Deff, dt, kappa_a, eps):
     return lib().orc_rcut(int(dim), int(bc), a, Deff, dt, kappa_a, eps)
 
@@ -227,10 +258,11 @@ class OracleSim:
     """The step of Sec. 3 on a slot-indexed state, in FP64."""
 
     def __init__(self, *, dim, bc, box, dt, D, sigma, kappa_a=0.0, k_off=0.0, eps_cut=1e-3, rcut=0.0,
-                 seed=0, replica=0, store_f32=False, n_terms=12, species, pos, partner=None):
+                 seed=0, replica=0, store_f32=False, n_terms=12, exact2d=False, species, pos, partner=None):
         L = lib()
         p = Params()
         p.dim, p.bc, p.store_f32, p.n_terms = int(dim), int(bc), int(bool(store_f32)), int(n_terms)
+        p.exact2d = int(bool(exact2d))
         bx = list(box) + [1.0] * (3 - len(box))
         for k in range(3):
             p.box[k] = float(bx[k])

@@ -23,6 +23,7 @@
  *   - the product C is placed at the diffusion-weighted centre (eq. Rcoo);
  *   - C diffuses with D_C; a C made in this step does not decay in it.
  */
+#define _DEFAULT_SOURCE /* the Bessel functions j0, j1, y0, y1 of the C library */
 #include "gfbd_oracle.h"
 
 #include <math.h>
@@ -389,6 +390,175 @@ static double prop2_corr(double Rp, double R0, double tau, int n)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Exact 2D radial Green's functions, beyond the small-time regime: the       */
+/* n = 0 term of the 2D Green's function (eq. genericGF) with the radial      */
+/* function of eq. fRad, by quadrature of its integral over x (times a^2):    */
+/*   g(R, tau | R0) = (1/2 pi) int_0^inf e^{-tau x^2} C0(R,x) C0(R0,x) x dx,  */
+/*   C0(R, x) = [J0(Rx) A(x) - Y0(Rx) B(x)] / sqrt(A^2 + B^2),               */
+/* radiation A = x Y0'(x) - h Y0(x), B = x J0'(x) - h J0(x) (reflecting:     */
+/* h = 0); absorbing A = Y0(x), B = J0(x) (the limit h -> inf, up to a sign   */
+/* common to both factors).  The mass within R of the boundary, used by the   */
+/* propagator, integrates the R' factor in closed form:                       */
+/*   int_1^R 2 pi R' g(R'|R0) dR' = int_0^inf e^{-tau x^2} C0(R0,x) K(R,x) x dx,*/
+/*   K(R, x) = [A (R J1(Rx) - J1(x)) - B (R Y1(Rx) - Y1(x))] / (x sqrt(A^2+B^2)).*/
+/* Quadrature: 16-point Gauss-Legendre panels, geometric (ratio 2) from       */
+/* 2^-30/4 up to 1/4 where the absorbing and radiation kernels vary like      */
+/* 1/ln x, then of width <= min(1/4, pi/f) with f = R + R0 + 1 (the fastest   */
+/* oscillation of the integrand), up to x = sqrt(50/tau) (e^{-50}).           */
+/* ------------------------------------------------------------------------ */
+#define GLN 16
+static double gl_x[GLN], gl_w[GLN];
+static int gl_ready;
+
+static void gl_init(void)
+{
+    if (gl_ready) return;
+    for (int i = 0; i < GLN; ++i) {
+        double z = cos(PI * (i + 0.75) / (GLN + 0.5)), p0 = 1.0, p1 = z, dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            p0 = 1.0;
+            p1 = z;
+            for (int k = 2; k <= GLN; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = GLN * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        gl_x[i] = z;
+        gl_w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+    gl_ready = 1;
+}
+
+/* A, B of C0 for kind 0 (absorbing), 1 (reflecting), 2 (radiation) */
+static void c0_ab(int kind, double x, double hh, double j0x, double y0x, double j1x, double y1x, double *A, double *B)
+{
+    if (kind == 0) {
+        *A = y0x;
+        *B = j0x;
+        return;
+    }
+    double h = kind == 1 ? 0.0 : hh;
+    *A = -x * y1x - h * y0x;
+    *B = -x * j1x - h * j0x;
+}
+
+/* The integrals at one node x: g-integrands of the three kinds at (R, R0)
+ * (mode 0), or the mass integrands of the absorbing and reflecting kinds
+ * together with their g-integrands at (R, R0) (mode 1). */
+static void x_terms(int mode, double x, double R, double R0, double hh, double out[4])
+{
+    double j0x = j0(x), y0x = y0(x), j1x = j1(x), y1x = y1(x);
+    double jr = j0(R * x), yr = y0(R * x), jq = j0(R0 * x), yq = y0(R0 * x);
+    if (mode == 0) {
+        for (int kind = 0; kind < 3; ++kind) {
+            double A, B;
+            c0_ab(kind, x, hh, j0x, y0x, j1x, y1x, &A, &B);
+            double N2 = A * A + B * B;
+            out[kind] = (jr * A - yr * B) * (jq * A - yq * B) / N2 * x;
+        }
+        return;
+    }
+    double j1r = j1(R * x), y1r = y1(R * x);
+    for (int kind = 0; kind < 2; ++kind) {
+        double A, B;
+        c0_ab(kind, x, hh, j0x, y0x, j1x, y1x, &A, &B);
+        double N2 = A * A + B * B, cq = jq * A - yq * B;
+        out[kind] = cq * (A * (R * j1r - j1x) - B * (R * y1r - y1x)) / N2;        /* x C0(R0) K(R) */
+        out[2 + kind] = (jr * A - yr * B) * cq / N2 * x;                           /* x C0(R0) C0(R) */
+    }
+}
+
+static void x_integrate(int mode, double R, double R0, double tau, double hh, double freq, double acc[4])
+{
+    gl_init();
+    for (int k = 0; k < 4; ++k) acc[k] = 0.0;
+    double xmax = sqrt(50.0 / tau), x1 = xmax < 0.25 ? xmax : 0.25;
+    double wmax = PI / freq;
+    if (wmax > 0.25) wmax = 0.25;
+    int ngeo = 30, nuni = (int)ceil((xmax - x1) / wmax);
+    double wuni = nuni > 0 ? (xmax - x1) / nuni : 0.0;
+    for (int p = 0; p < ngeo + nuni; ++p) {
+        double lo, hi;
+        if (p < ngeo) {
+            lo = ldexp(x1, p - ngeo);
+            hi = 2.0 * lo;
+        } else {
+            lo = x1 + (p - ngeo) * wuni;
+            hi = lo + wuni;
+        }
+        double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+        for (int i = 0; i < GLN; ++i) {
+            double x = c + h * gl_x[i], t[4];
+            x_terms(mode, x, R, R0, hh, t);
+            double wgt = h * gl_w[i] * exp(-tau * x * x);
+            for (int k = 0; k < 4; ++k) acc[k] += wgt * t[k];
+        }
+    }
+}
+
+void orc_g2x(double R, double R0, double tau, double hh, double out[3])
+{
+    double acc[4];
+    x_integrate(0, R, R0, tau, hh, R + R0 + 1.0, acc);
+    for (int k = 0; k < 3; ++k) out[k] = acc[k] / (2.0 * PI);
+}
+
+void orc_m2x(double R, double R0, double tau, double out[2])
+{
+    double acc[4];
+    x_integrate(1, R, R0, tau, 0.0, R + R0 + 1.0, acc);
+    out[0] = acc[0];
+    out[1] = acc[1];
+}
+
+/* p_enc = 1 - g_abs/g_free (eq. laplaceAnsatz) with the exact g_abs */
+double orc_penc2x(double R, double R0, double tau)
+{
+    if (R <= 1.0) return 1.0;
+    double g[3];
+    orc_g2x(R, R0, tau, 0.0, g);
+    return 1.0 - g[0] / orc_g2_free(R, R0, tau);
+}
+
+/* p_reac = (g_ref - g_rad)/(g_ref - g_abs) (eq. psurv_radII) with the exact functions */
+double orc_preac2x(double R, double R0, double tau, double hh)
+{
+    double g[3];
+    orc_g2x(R, R0, tau, hh, g);
+    return (g[1] - g[2]) / (g[1] - g[0]);
+}
+
+/* R'' >= 1 from w_2 r (g_ref - g_abs)(.|R0) by inversion with one uniform u:
+ * the root of M(R) = u M(R_top), M(R) = int_1^R 2 pi R'(g_ref - g_abs) dR',
+ * R_top = R0 + 12 sqrt(tau) + 1 (the mass beyond it is below e^{-36}).
+ * Newton steps on M with its derivative 2 pi R (g_ref - g_abs), kept inside
+ * a bracket that bisection takes over whenever a step leaves it. */
+double orc_sample_prop2x(double R0, double tau, double u)
+{
+    double top = R0 + 12.0 * sqrt(tau) + 1.0, acc[4];
+    double freq = top + R0 + 1.0;
+    x_integrate(1, top, R0, tau, 0.0, freq, acc);
+    double target = u * (acc[1] - acc[0]);
+    double lo = 1.0, hi = top, x = R0 > 1.0 ? R0 : 1.0 + sqrt(tau);
+    for (int it = 0; it < 200; ++it) {
+        x_integrate(1, x, R0, tau, 0.0, freq, acc);
+        double f = (acc[1] - acc[0]) - target, df = (acc[3] - acc[2]) * x;
+        if (f < 0.0) lo = x;
+        else hi = x;
+        double nx = df > 0.0 ? x - f / df : 0.5 * (lo + hi);
+        if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
+        if (fabs(nx - x) <= 1e-13 * x || hi - lo <= 1e-13 * x) return nx;
+        x = nx;
+    }
+    return x;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Radial propagator sampler.  With c = R0 - 1 and v = R' + R0 - 2 >= c:     */
 /*   3D: density ~ (1 + v - c) e^{-v^2/4tau} [1 - sqrt(pi tau) erfcx(z1)],   */
 /*       z1 = sqrt(tau) + v/(2 sqrt(tau))  (ref minus abs closed forms);     */
@@ -592,14 +762,30 @@ static int cmp_pick_bj(const void *a, const void *b)
 static double pair_prob(const orc_sim *s, double R, double R0)
 {
     if (R <= 1.0) return 1.0;
-    return s->p.dim == 3 ? orc_penc3(R, R0, s->tau) : orc_penc2(R, R0, s->tau, s->p.n_terms);
+    if (s->p.dim == 3) return orc_penc3(R, R0, s->tau);
+    return s->p.exact2d ? orc_penc2x(R, R0, s->tau) : orc_penc2(R, R0, s->tau, s->p.n_terms);
 }
 
 static double reac_prob(const orc_sim *s, double R, double R0)
 {
     if (s->p.bc == ORC_BC_ABS) return 1.0;
     if (s->p.bc == ORC_BC_REF) return 0.0;
-    return s->p.dim == 3 ? orc_preac3(R, R0, s->tau, s->hh) : orc_preac2(R, R0, s->tau, s->hh, s->p.n_terms);
+    if (s->p.dim == 3) return orc_preac3(R, R0, s->tau, s->hh);
+    return s->p.exact2d ? orc_preac2x(R, R0, s->tau, s->hh) : orc_preac2(R, R0, s->tau, s->hh, s->p.n_terms);
+}
+
+/* R'' of a propagation: keyed rejection, or in the exact 2D form inversion
+ * with word 0 of the counter's attempt 0 */
+static double propagate(const orc_sim *s, double R0, const uint32_t ctr[4], uint32_t *att, uint32_t *hits)
+{
+    if (s->p.dim == 2 && s->p.exact2d) {
+        uint32_t w[4];
+        uint32_t ct[4] = {ctr[0], ctr[1], ctr[2], ctr[3] & 0xFFu};
+        orc_philox4x32_10(ct, s->key, w);
+        *att = 1;
+        return orc_sample_prop2x(R0, s->tau, orc_u01(w[0]));
+    }
+    return orc_sample_prop(s->p.dim, R0, s->tau, s->p.n_terms, ctr, s->key, att, hits);
 }
 
 /* post-move separation vector of (i, j) and the pre-step one, and their
@@ -815,7 +1001,7 @@ void orc_sim_step(orc_sim *s)
             mt->preac = 1.0;
         } else {
             uint32_t ctr[4] = {i, j, stp, TAG_PROP}, att = 0, hits = 0;
-            double Rpp = orc_sample_prop(d, R0, s->tau, s->p.n_terms, ctr, s->key, &att, &hits);
+            double Rpp = propagate(s, R0, ctr, &att, &hits);
             s->st[ORC_ST_ATTEMPTS] += att;
             s->st[ORC_ST_BOUND] += hits;
             mt->attempts = att;
@@ -873,7 +1059,7 @@ void orc_sim_step(orc_sim *s)
             ds->decayed = 1;
             s->st[ORC_ST_DECAY]++;
             uint32_t cp[4] = {(uint32_t)c, NOSLOT, stp, TAG_DPROP}, att = 0, hits = 0;
-            double Rpp = orc_sample_prop(d, 1.0, s->tau, s->p.n_terms, cp, s->key, &att, &hits);
+            double Rpp = propagate(s, 1.0, cp, &att, &hits);
             s->st[ORC_ST_ATTEMPTS] += att;
             s->st[ORC_ST_BOUND] += hits;
             ds->attempts = att;

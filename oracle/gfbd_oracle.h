@@ -51,6 +51,12 @@ double orc_penc2(double R, double R0, double tau, int n);
 double orc_preac2(double R, double R0, double tau, double hh, int n);
 double orc_prop2_density(double Rp, double R0, double tau, int n);
 
+/* ---- exact 2D radial functions (n = 0 term of eq. genericGF, by quadrature) ---- */
+void orc_g2x(double R, double R0, double tau, double hh, double out[3]); /* a^2 g_abs, g_ref, g_rad */
+void orc_m2x(double R, double R0, double tau, double out[2]);             /* int_1^R 2 pi R' g dR': abs, ref */
+double orc_penc2x(double R, double R0, double tau);
+double orc_preac2x(double R, double R0, double tau, double hh);
+double orc_sample_prop2x(double R0, double tau, double u);                /* inversion, one uniform */
 /* ---- radial propagator sampler (Sec. 3, Details; Sec. 2.2.2) ---- */
 /* Draws R'' >= 1 from w_d r^{d-1}(g_ref - g_abs)(.|R0) by keyed rejection.
  * ctr[3] low byte is the tag; the attempt index is put in its upper 24 bits. */
@@ -79,7 +85,7 @@ typedef struct {
     double rcut;        /* > 0: use this cut-off instead of deriving it */
     uint64_t seed;
     uint32_t replica;
-    uint32_t pad;
+    int32_t exact2d;    /* 2D: 1 = exact radial functions by quadrature, 0 = small-time expansions */
 } orc_params;
 
 typedef struct { uint32_t i, j; double R, R0, p; uint32_t draw; int32_t cand; } orc_pair;

@@ -195,3 +195,59 @@ def test_conservation_reversible():
         assert sorted(pt[cs].tolist()) == sorted(np.where(sp == O.SP_RESERVED)[0].tolist())
         seen_c = max(seen_c, nC)
     assert seen_c > 0
+
+
+def _loss2_rad_scipy(R0, tau, hh):
+    """1 - S_rad(tau | R0) in 2D with scipy: 1 - int_1^inf 2 pi R g_rad dR, the R integral of the
+    Weber form taken in closed form (int R C0(R, x) dR = R [J1(Rx) A - Y1(Rx) B] / (x N))."""
+    from scipy import integrate, special as Sp
+    top = R0 + 12 * math.sqrt(tau) + 1
+
+    def f(x):
+        A = -x * Sp.y1(x) - hh * Sp.y0(x)
+        B = -x * Sp.j1(x) - hh * Sp.j0(x)
+        N2 = A * A + B * B
+        c0 = Sp.j0(R0 * x) * A - Sp.y0(R0 * x) * B
+        K = A * (top * Sp.j1(top * x) - Sp.j1(x)) - B * (top * Sp.y1(top * x) - Sp.y1(x))
+        return math.exp(-tau * x * x) * c0 * K / N2
+
+    xmax = math.sqrt(50 / tau)
+    edges = np.concatenate([[0.0], np.geomspace(1e-9, 0.25, 30), np.linspace(0.25, xmax, 200)[1:]])
+    mass = sum(integrate.quad(f, a, b, limit=200, epsabs=1e-14, epsrel=1e-12)[0] for a, b in zip(edges[:-1], edges[1:]))
+    return 1.0 - mass
+
+
+def test_exact_2d_isolated_pairs_and_geminate_recombination():
+    # 2D beyond the small-time regime (tau = 0.8, where the expansions fail): an isolated pair
+    # from R0 reacts in one step with probability 1 - S_rad(tau | R0) (Secs. 2.2.1-2.2.3 with the
+    # exact functions); a C at contact that decays recombines with probability 1 - S_rad(tau | 1)
+    M, a, Deff, dt, ka = 6000, 0.005, 0.2, 1e-4, 1.0
+    tau, hh, R0 = Deff * dt / a ** 2, ka / (2 * math.pi * Deff), 1.2
+    rng = np.random.default_rng(2)
+    side = int(math.ceil(math.sqrt(M)))
+    grid = np.stack(np.meshgrid(*[np.arange(side)] * 2, indexing="ij"), -1).reshape(-1, 2)[:M] * 0.25
+    th = rng.uniform(0, 2 * math.pi, M)
+    pos = np.concatenate([grid, grid + R0 * a * np.stack([np.cos(th), np.sin(th)], 1)])
+    sp = np.concatenate([np.zeros(M, np.int32), np.ones(M, np.int32)])
+    s = O.OracleSim(dim=2, bc=O.BC_RAD, box=[side * 0.25] * 2, dt=dt, D=(0.1, 0.1, 0.05), sigma=a, kappa_a=ka,
+                    eps_cut=1e-12, species=sp, pos=pos, seed=17, exact2d=True)
+    assert s.derived()["tau"] == pytest.approx(tau) and s.derived()["rcut"] < 0.1
+    s.step()
+    frac = np.mean(s.state()[0][:M] == O.SP_C)
+    P = _loss2_rad_scipy(R0, tau, hh)
+    assert abs(frac - P) < 4.5 * math.sqrt(P * (1 - P) / M), (frac, P)
+    # geminate recombination of decaying C's
+    koff = 5e4
+    Mc = 4000
+    gridc = np.stack(np.meshgrid(*[np.arange(64)] * 2, indexing="ij"), -1).reshape(-1, 2)[:Mc] * 0.25
+    posc = np.concatenate([gridc, np.zeros((Mc, 2))])
+    spc = np.concatenate([np.full(Mc, O.SP_C, np.int32), np.full(Mc, O.SP_RESERVED, np.int32)])
+    pt = np.concatenate([np.arange(Mc, 2 * Mc, dtype=np.uint32), np.full(Mc, 0xFFFFFFFF, np.uint32)])
+    s = O.OracleSim(dim=2, bc=O.BC_RAD, box=[16.0] * 2, dt=dt, D=(0.1, 0.1, 0.05), sigma=a, kappa_a=ka, k_off=koff,
+                    species=spc, pos=posc, partner=pt, seed=5, exact2d=True)
+    s.step()
+    ds = s.dissociations()
+    Pg = _loss2_rad_scipy(1.0, tau, hh)
+    n = len(ds)
+    assert n > 3000
+    assert abs(ds["recombined"].sum() - Pg * n) < 4.5 * math.sqrt(n * Pg * (1 - Pg)), (ds["recombined"].sum() / n, Pg)
