@@ -295,6 +295,8 @@ def main():
                     help="precision mode (default: the workload's; fp32 = plain binary32, fp32nc = binary32 with "
                          "binary64 near-contact arguments and displacements)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain binary32 comparison run")
+    ap.add_argument("--green2d", choices=["expansion", "exact"], default="expansion",
+                    help="2D radial functions: small-time expansions, or exact (tables by quadrature)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the cell edge and pair-search kernel by timing candidates on the workload first")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -336,10 +338,12 @@ def main():
     log(f"[bench] state: {len(sp)} particles, {red} redrawn overlaps, {time.time() - t0:.1f}s")
     search = {"auto": S.PAIRS_AUTO, "bricks": S.PAIRS_BRICKS, "direct": S.PAIRS_DIRECT}[args.pair_search]
 
+    g2 = S.G2_EXACT if args.green2d == "exact" else S.G2_EXPANSION
+
     def make_with(timing, cell, pair_search):
         return S.Sim(dim=dim, box=box, dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
                      k_off=cfg["k_off"], precision=cfg["precision"], seed=0, species=sp, pos=pos, timing=timing, cell=cell,
-                     pair_search=pair_search)
+                     pair_search=pair_search, green2d=g2)
 
     tuned = None
     if args.autotune:
@@ -360,7 +364,7 @@ def main():
             return make_with(timing, args.cell, search)
         return S.Sim(dim=dim, box=box, dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
                      k_off=cfg["k_off"], precision=precision, seed=0, species=sp, pos=pos, timing=timing, cell=args.cell,
-                     pair_search=search)
+                     pair_search=search, green2d=g2)
 
     def timed(sim):
         sim.step(args.warmup)
@@ -374,7 +378,9 @@ def main():
         return el, n_live, s1["pairs"] - s0["pairs"], c0, c1, sim.kernel_times()
 
     # pass 1: the step as one HIP graph replay (no per-kernel events) -> value
+    t_create = time.perf_counter()
     sim = make(False)
+    t_create = time.perf_counter() - t_create
     der, grid = sim.derived(), sim.grid()
     log(f"[bench] derived {der} grid {grid}")
     el, n_live, pairs, c0, c1, _ = timed(sim)
@@ -454,7 +460,9 @@ def main():
                    "particles": len(sp), "r_cut_um": der["rcut"], "cells": grid[:3],
                    "pair_search": {S.PAIRS_BRICKS: "lds-bricks", S.PAIRS_DIRECT: "direct"}[grid[4]],
                    "step_launch": "one hipGraph replay per step",
-                   "cell_edge_um": der["cell"]},
+                   "cell_edge_um": der["cell"],
+                   "green2d": args.green2d if dim == 2 else None,
+                   "handle_creation_s": round(t_create, 3)},
         "autotune": tuned,
         "plain_fp32": plain,
         "roofline": roof,

@@ -63,10 +63,10 @@ enum { SIM_BC_ABSORBING = 0, SIM_BC_REFLECTING = 1, SIM_BC_RADIATION = 2 };
 
 /* Precision of the state and of the pair probabilities:
  *  FP64          state and all arithmetic in binary64;
- *  FP32          binary32 state, pair search and p_enc in binary32;
- *  FP32_FP64NC   binary32 state, binary32 p_enc whose arguments (r, r - a,
+ *  FP32          binary32 state; displacements (Box-Muller), pair search and p_enc in binary32;
+ *  FP32_FP64NC   binary32 state, binary64 displacements, binary32 p_enc whose arguments (r, r - a,
  *                r0 - a and the exponent arguments) are formed in binary64.
- * Displacements, placements, the propagator and p_reac are binary64 in all modes. */
+ * Placements, the propagator and p_reac are binary64 in all modes. */
 enum { SIM_PREC_FP64 = 0, SIM_PREC_FP32 = 1, SIM_PREC_FP32_FP64NC = 2 };
 
 /* Kernel of the pair search (step 2); both find exactly the same pairs.
@@ -109,7 +109,18 @@ typedef struct {
     uint32_t timing;               /* 1: time every kernel with HIP events (sim_read SIM_READ_TIMING) */
     uint64_t debug_cap;            /* entries per stage log (0 = 1 << 20) */
     void *hip_stream;              /* hipStream_t to run on; NULL = the null stream */
+    int32_t green2d;               /* 2D radial functions: SIM_G2_EXPANSION or SIM_G2_EXACT (2D only) */
+    int32_t reserved;              /* must be 0 */
 } sim_config;
+
+/* sim_config.green2d.  EXPANSION: the small-time expansions of Sec. 4.2 to order n_terms (valid for
+ * tau = D_eff dt / a^2 up to about 0.04 at 1e-6).  EXACT: the n = 0 term of the 2D Green's function
+ * (Sec. 4.2, its Bessel-function form) by quadrature, tabulated on the device when the handle is
+ * created (a grid of step sqrt(tau)/40 in R and R0, read by bicubic interpolation): p_enc, p_reac
+ * and the propagator's distribution function, R'' then drawn by inversion of one uniform, word 0
+ * of the counter of attempt 0.  EXACT is for any tau; it is refused in 3D (SIM_EINVAL) and in
+ * batches and pools (SIM_EUNSUPPORTED), and SIM_EUNSUPPORTED if its tables would exceed 2^26 entries. */
+enum { SIM_G2_EXPANSION = 0, SIM_G2_EXACT = 1 };
 
 /* Creates a simulation with n slots.  species[i] in {A, B, C, FREE, RESERVED};
  * pos is n*dim doubles (slot-major, ignored for FREE/RESERVED); partner[i] is

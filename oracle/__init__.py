@@ -87,6 +87,7 @@ def lib():
         "orc_penc2x": (d, [d, d, d]),
         "orc_preac2x": (d, [d, d, d, d]),
         "orc_sample_prop2x": (d, [d, d, d]),
+        "orc_x2_switch": (d, [d]),
         "orc_rcut": (d, [i, i, d, d, d, d, d]),
         "orc_sim_create": (vp, [P(Params), u64, vp, vp, vp]),
         "orc_sim_destroy": (None, [vp]),
@@ -246,6 +247,10 @@ def preac2x(R, R0, tau, hh):
 
 def sample_prop2x(R0, tau, u):
     return lib().orc_sample_prop2x(float(R0), float(tau), float(u))
+
+
+def x2_switch(tau):
+    return lib().orc_x2_switch(float(tau))
 
 
 def rcut(dim, bc, a, Deff, dt, kappa_a, eps):

@@ -759,11 +759,19 @@ static int cmp_pick_bj(const void *a, const void *b)
     return 0;
 }
 
+/* The exact 2D functions serve pairs with R0 <= 1 + 8.4 sqrt(tau): there the
+ * propagator's mass 1 - S_abs(R0) exceeds erfc(4.2) ~ 3e-9 and is resolved by
+ * the quadrature.  Farther out every argument x = (R + R0 - 2)/(2 sqrt tau) of
+ * the pair is >= 4.2, where the small-time expansions hold, and they are used. */
+double orc_x2_switch(double tau) { return 1.0 + 8.4 * sqrt(tau); }
+
+static int use_x2(const orc_sim *s, double R0) { return s->p.dim == 2 && s->p.exact2d && R0 <= orc_x2_switch(s->tau); }
+
 static double pair_prob(const orc_sim *s, double R, double R0)
 {
     if (R <= 1.0) return 1.0;
     if (s->p.dim == 3) return orc_penc3(R, R0, s->tau);
-    return s->p.exact2d ? orc_penc2x(R, R0, s->tau) : orc_penc2(R, R0, s->tau, s->p.n_terms);
+    return use_x2(s, R0) ? orc_penc2x(R, R0, s->tau) : orc_penc2(R, R0, s->tau, s->p.n_terms);
 }
 
 static double reac_prob(const orc_sim *s, double R, double R0)
@@ -771,14 +779,14 @@ static double reac_prob(const orc_sim *s, double R, double R0)
     if (s->p.bc == ORC_BC_ABS) return 1.0;
     if (s->p.bc == ORC_BC_REF) return 0.0;
     if (s->p.dim == 3) return orc_preac3(R, R0, s->tau, s->hh);
-    return s->p.exact2d ? orc_preac2x(R, R0, s->tau, s->hh) : orc_preac2(R, R0, s->tau, s->hh, s->p.n_terms);
+    return use_x2(s, R0) ? orc_preac2x(R, R0, s->tau, s->hh) : orc_preac2(R, R0, s->tau, s->hh, s->p.n_terms);
 }
 
-/* R'' of a propagation: keyed rejection, or in the exact 2D form inversion
- * with word 0 of the counter's attempt 0 */
+/* R'' of a propagation: keyed rejection, or with the exact 2D functions
+ * inversion with word 0 of the counter's attempt 0 */
 static double propagate(const orc_sim *s, double R0, const uint32_t ctr[4], uint32_t *att, uint32_t *hits)
 {
-    if (s->p.dim == 2 && s->p.exact2d) {
+    if (use_x2(s, R0)) {
         uint32_t w[4];
         uint32_t ct[4] = {ctr[0], ctr[1], ctr[2], ctr[3] & 0xFFu};
         orc_philox4x32_10(ct, s->key, w);

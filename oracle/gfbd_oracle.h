@@ -57,6 +57,7 @@ void orc_m2x(double R, double R0, double tau, double out[2]);             /* int
 double orc_penc2x(double R, double R0, double tau);
 double orc_preac2x(double R, double R0, double tau, double hh);
 double orc_sample_prop2x(double R0, double tau, double u);                /* inversion, one uniform */
+double orc_x2_switch(double tau);  /* R0 above which the exact 2D mode uses the small-time expansions */
 /* ---- radial propagator sampler (Sec. 3, Details; Sec. 2.2.2) ---- */
 /* Draws R'' >= 1 from w_d r^{d-1}(g_ref - g_abs)(.|R0) by keyed rejection.
  * ctr[3] low byte is the tag; the attempt index is put in its upper 24 bits. */

@@ -146,6 +146,7 @@ struct Model {
     int dim, prec, bc;
     double box[3], dt, D[3], sigma, kappa, k_off, eps, rcut_req, cell_req;
     int pair_search;
+    int green2d;
     uint64_t seed;
     uint32_t replica;
     int n_terms;
@@ -227,6 +228,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     bool pool = false;
     std::vector<uint64_t> member_n;  // slots of each member entry, 0 if the entry is free
     RangeAlloc slot_free, cell_free;
+    std::vector<double> x2_build;  // exact 2D tables: quadrature nodes, rows, columns
     hipStream_t own_stream = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     uint32_t n_bricks = 0;
@@ -421,7 +423,120 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             P.nbz = DIM == 3 ? (P.nc[2] + P.bz - 1) / P.bz : 1;
             n_bricks = P.nbx * P.nby * P.nbz;
         }
+        if (DIM == 2 && M.green2d == SIM_G2_EXACT && (rc = build_x2())) return rc;
         return finish_init(sp, pos, pt);
+    }
+
+    // 16-point Gauss-Legendre rule on [-1, 1]: the roots of P_16 by Newton's
+    // method from Tricomi's estimate, weights 2 / ((1 - x^2) P_16'(x)^2).
+    static void gauss_legendre16(double *x, double *w)
+    {
+        const int n = 16;
+        for (int i = 0; i < n; ++i) {
+            const double th = M_PI * (4.0 * i + 3.0) / (4.0 * n + 2.0);
+            double t = (1.0 - (n - 1.0) / (8.0 * n * n * n)) * std::cos(th), d = 1.0;
+            for (int it = 0; it < 60; ++it) {
+                double pm = 1.0, p = t;  // P_0, P_1
+                for (int k = 2; k <= n; ++k) {
+                    const double pn = ((2 * k - 1) * t * p - (k - 1) * pm) / k;
+                    pm = p;
+                    p = pn;
+                }
+                d = n * (pm - t * p) / (1.0 - t * t);
+                const double step = p / d;
+                t -= step;
+                if (std::fabs(step) < 1e-17) break;
+            }
+            x[i] = t;
+            w[i] = 2.0 / ((1.0 - t * t) * d * d);
+        }
+    }
+
+    // Tables of the exact 2D radial functions (green2x.hpp): R steps of
+    // h = sqrt(tau)/160 and R0 steps of 2h, R0 up to the switch 1 + 8.4
+    // sqrt(tau) (plus the interpolation stencil), R up to the larger of
+    // r_cut/a and the switch plus L = 12 sqrt(tau) + 1, the top of the
+    // propagator's distribution function.  Quadrature nodes: 16-point
+    // Gauss-Legendre panels, geometric (ratio 2) from 2^-30/4 to 1/4 where the
+    // absorbing and radiation kernels vary like 1/ln x, then of width at most
+    // min(1/4, pi / (R_top + R0_top + 1)) up to x = sqrt(50/tau).
+    int build_x2()
+    {
+        const double tau = P.tau, st = P.sqrt_tau, h = st / 160.0, h0 = X2S * h;
+        if (!(tau <= 1.0)) return fail(SIM_EUNSUPPORTED, "exact 2D functions need tau = D_eff dt / a^2 <= 1");
+        const double r0sw = 1.0 + 8.4 * st, L = 12.0 * st + 1.0;
+        const u32 n0 = (u32)std::ceil((r0sw - 1.0) / h0) + 4;
+        const double r0top = 1.0 + (n0 - 1) * h0;
+        const double rtop = std::max(P.rcut / P.a, r0top + L) + 4.0 * h;
+        const u32 nr = (u32)std::ceil((rtop - 1.0) / h) + 1;
+        const u32 top = (u32)std::ceil(L / h);
+        if ((uint64_t)nr * n0 > (1ull << 26) || nr > 65535u * X2T)
+            return fail(SIM_EUNSUPPORTED, "exact 2D tables would exceed 2^26 entries");
+        double gx[16], gw[16];
+        gauss_legendre16(gx, gw);
+        std::vector<double> xs, s1, s2;
+        const double xmax = std::sqrt(50.0 / tau), x1 = std::min(0.25, xmax);
+        const double wmax = std::min(0.25, M_PI / (rtop + r0top + 1.0));
+        const int ngeo = 30, nuni = (int)std::ceil((xmax - x1) / wmax);
+        for (int p = 0; p < ngeo + nuni; ++p) {
+            const double lo = p < ngeo ? std::ldexp(x1, p - ngeo) : x1 + (p - ngeo) * ((xmax - x1) / nuni);
+            const double hi = p < ngeo ? 2.0 * lo : lo + (xmax - x1) / nuni;
+            for (int q = 0; q < 16; ++q) {
+                const double x = 0.5 * (lo + hi) + 0.5 * (hi - lo) * gx[q];
+                const double wk = 0.5 * (hi - lo) * gw[q] * std::exp(-tau * x * x);
+                xs.push_back(x);
+                s1.push_back(wk * x / (2.0 * M_PI));  // G: x w / 2 pi
+                s2.push_back(wk);                     // M: w
+            }
+        }
+        const u32 K = (u32)xs.size();
+        const size_t NK = (size_t)nr * K, NT = (size_t)nr * n0;
+        if (NK > (1ull << 31)) return fail(SIM_EUNSUPPORTED, "exact 2D quadrature matrices too large");
+        // scratch (freed below) and the tables (kept)
+        double *tmp_buf = nullptr;
+        const size_t n_tmp = 3 * (size_t)K + 8 * (size_t)K + 5 * NK + 5 * NT;
+        if (hipMalloc(&tmp_buf, sizeof(double) * n_tmp) != hipSuccess) return fail(SIM_ENOMEM, "device allocation failed (exact 2D scratch)");
+        double *d_x = tmp_buf, *d_s1 = d_x + K, *d_s2 = d_s1 + K, *d_nd = d_s2 + K;
+        double *Cabs = d_nd + 8 * (size_t)K, *Cref = Cabs + NK, *Crad = Cref + NK, *Kabs = Crad + NK, *Kref = Kabs + NK;
+        double *Gabs = Kref + NK, *Gref = Gabs + NT, *Grad = Gref + NT, *Mabs = Grad + NT, *Mref = Mabs + NT;
+        double *enc = nullptr, *reac = nullptr, *cdf = nullptr;
+        int rc;
+        if ((rc = alloc(enc, NT)) || (rc = alloc(reac, NT)) || (rc = alloc(cdf, NT))) {
+            (void)hipFree(tmp_buf);
+            return rc;
+        }
+        hipStream_t sm = M.stream;
+        auto run = [&]() -> hipError_t {
+            hipError_t e;
+            if ((e = hipMemcpyAsync(d_x, xs.data(), sizeof(double) * K, hipMemcpyHostToDevice, sm)) != hipSuccess) return e;
+            if ((e = hipMemcpyAsync(d_s1, s1.data(), sizeof(double) * K, hipMemcpyHostToDevice, sm)) != hipSuccess) return e;
+            if ((e = hipMemcpyAsync(d_s2, s2.data(), sizeof(double) * K, hipMemcpyHostToDevice, sm)) != hipSuccess) return e;
+            k_x2_nodes<<<(K + 255) / 256, 256, 0, sm>>>(d_x, K, P.hh, d_nd);
+            k_x2_rows<<<(u32)((NK + 255) / 256), 256, 0, sm>>>(d_x, d_nd, K, nr, h, Cabs, Cref, Crad, Kabs, Kref);
+            const dim3 g((n0 + X2T - 1) / X2T, (nr + X2T - 1) / X2T);
+            k_x2_gemm<<<g, 256, 0, sm>>>(Cabs, Cabs, d_s1, nr, n0, K, Gabs);
+            k_x2_gemm<<<g, 256, 0, sm>>>(Cref, Cref, d_s1, nr, n0, K, Gref);
+            k_x2_gemm<<<g, 256, 0, sm>>>(Crad, Crad, d_s1, nr, n0, K, Grad);
+            k_x2_gemm<<<g, 256, 0, sm>>>(Kabs, Cabs, d_s2, nr, n0, K, Mabs);
+            k_x2_gemm<<<g, 256, 0, sm>>>(Kref, Cref, d_s2, nr, n0, K, Mref);
+            k_x2_tables<<<(u32)((NT + 255) / 256), 256, 0, sm>>>(Gabs, Gref, Grad, Mabs, Mref, nr, n0, h, tau, top, enc, reac, cdf);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            return hipStreamSynchronize(sm);  // the host vectors are read by the copies
+        };
+        const hipError_t e = run();
+        (void)hipFree(tmp_buf);
+        if (e != hipSuccess) return fail(SIM_EDEVICE, std::string("exact 2D tables: ") + hipGetErrorString(e));
+        P.x2_enc = enc;
+        P.x2_reac = reac;
+        P.x2_cdf = cdf;
+        P.x2_h = h;
+        P.x2_inv_h = 1.0 / h;
+        P.x2_inv_h0 = 1.0 / h0;
+        P.x2_r0sw = r0sw;
+        P.x2_nr = nr;
+        P.x2_n0 = n0;
+        x2_build = {(double)K, (double)nr, (double)n0};
+        return SIM_OK;
     }
 
     // A batch of independent replicas (3D): each keeps its own box, kappa,
@@ -810,6 +925,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     void enqueue_step(int c)
     {
         if constexpr (DIM == 2) {
+            if (P.x2_enc) return enqueue_step_n<NC_EXACT>(c);
             if (P.n_terms == 12) return enqueue_step_n<12>(c);
         }
         enqueue_step_n<0>(c);
@@ -889,7 +1005,10 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         const u32 g = grid_for(n, 16384);
         bool done = false;
         if constexpr (DIM == 2) {
-            if (P.n_terms == 12) {
+            if (P.x2_enc) {
+                k_eval_probs<DIM, PM, NC_EXACT><<<g, BLOCK, 0, M.stream>>>(P, n, R, R0, penc, preac);
+                done = true;
+            } else if (P.n_terms == 12) {
                 k_eval_probs<DIM, PM, 12><<<g, BLOCK, 0, M.stream>>>(P, n, R, R0, penc, preac);
                 done = true;
             }
@@ -903,7 +1022,8 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     int eval_prop(uint64_t n, const double *R0, uint32_t step, int wave, double *Rpp, uint32_t *attempts) override
     {
         if (n > 0xFFFFFFFFull) return fail(SIM_EINVAL, "at most 2^32 draws");
-        if (DIM == 2 && P.n_terms == 12) launch_prop<12>(n, R0, step, wave, Rpp, attempts);
+        if (DIM == 2 && P.x2_enc) launch_prop<NC_EXACT>(n, R0, step, wave, Rpp, attempts);
+        else if (DIM == 2 && P.n_terms == 12) launch_prop<12>(n, R0, step, wave, Rpp, attempts);
         else launch_prop<0>(n, R0, step, wave, Rpp, attempts);
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipStreamSynchronize(M.stream));
@@ -1103,6 +1223,8 @@ int validate_cfg(const sim_config *cfg, Model &M)
     if (!(eps > 0.0 && eps < 1.0)) { g_err = "eps_cut must be in (0, 1)"; return SIM_EINVAL; }
     if (!finite_nonneg(cfg->rcut) || !finite_nonneg(cfg->cell)) { g_err = "rcut and cell must be >= 0"; return SIM_EINVAL; }
     if (cfg->pair_search < SIM_PAIRS_AUTO || cfg->pair_search > SIM_PAIRS_DIRECT) { g_err = "unknown pair_search"; return SIM_EINVAL; }
+    if (cfg->green2d != SIM_G2_EXPANSION && cfg->green2d != SIM_G2_EXACT) { g_err = "unknown green2d"; return SIM_EINVAL; }
+    if (cfg->green2d == SIM_G2_EXACT && cfg->dim != 2) { g_err = "green2d = SIM_G2_EXACT is for 2D"; return SIM_EINVAL; }
     M.dim = cfg->dim;
     M.prec = cfg->precision;
     M.bc = r.bc;
@@ -1116,6 +1238,7 @@ int validate_cfg(const sim_config *cfg, Model &M)
     M.rcut_req = cfg->rcut;
     M.cell_req = cfg->cell;
     M.pair_search = cfg->pair_search;
+    M.green2d = cfg->green2d;
     M.seed = cfg->seed;
     M.replica = cfg->replica;
     M.n_terms = cfg->n_terms == 0 ? 12 : cfg->n_terms;
@@ -1225,6 +1348,7 @@ int sim_batch_create(const sim_config *cfg, uint32_t n_rep, const sim_replica *r
     if (!out) { g_err = "null output handle"; return SIM_EINVAL; }
     *out = nullptr;
     if (!cfg || !reps || n_rep == 0) { g_err = "null argument or no replicas"; return SIM_EINVAL; }
+    if (cfg->green2d == SIM_G2_EXACT) { g_err = "exact 2D tables are per system: not in batches"; return SIM_EUNSUPPORTED; }
     std::vector<Model> ms(n_rep);
     std::vector<uint64_t> nr(n_rep);
     std::vector<u32> step0(n_rep);
@@ -1278,6 +1402,7 @@ int sim_pool_create(const sim_config *cfg, uint64_t slot_cap, uint64_t cell_cap,
     Model M;
     int rc;
     if ((rc = validate_cfg(cfg, M))) return rc;
+    if (M.green2d == SIM_G2_EXACT) { g_err = "exact 2D tables are per system: not in pools"; return SIM_EUNSUPPORTED; }
     if (slot_cap == 0 || slot_cap > SLOT_MASK) { g_err = "slot capacity must be in [1, 2^29)"; return SIM_EINVAL; }
     if (cell_cap == 0 || cell_cap > (1ull << 28)) { g_err = "cell capacity must be in [1, 2^28]"; return SIM_EINVAL; }
     if (rep_cap == 0 || rep_cap > (1u << 20)) { g_err = "member capacity must be in [1, 2^20]"; return SIM_EINVAL; }

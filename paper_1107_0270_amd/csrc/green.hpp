@@ -177,7 +177,9 @@ template <int NC> __device__ inline double corr2_n(const Params &P, double Rp, d
     return 1.0 + 0.25 * SQRTPI_D * s;
 }
 
-// The order NC (12, or 0 for any order) is a template parameter of the
+#include "green2x.hpp"
+
+// The order NC (12, or 0 for any order; NC_EXACT: the tables of green2x.hpp) is a template parameter of the
 // kernels that evaluate the expansion, chosen on the host.  The run-time
 // order forms (arrays in scratch) are called, not inlined: inlined into the
 // event handler's wave sampler they gave acceptance decisions that differ
@@ -188,17 +190,20 @@ __device__ __noinline__ double preac2_any(const Params &P, double R, double R0) 
 __device__ __noinline__ double corr2_any(const Params &P, double Rp, double R0) { return corr2_n<0>(P, Rp, R0); }
 template <int NC> __device__ inline double penc2(const Params &P, double R, double R0)
 {
-    if constexpr (NC == 0) return penc2_any(P, R, R0);
+    if constexpr (NC == NC_EXACT) return R0 <= P.x2_r0sw ? penc2x(P, R, R0) : penc2_any(P, R, R0);
+    else if constexpr (NC == 0) return penc2_any(P, R, R0);
     else return penc2_n<NC>(P, R, R0);
 }
 template <int NC> __device__ inline double preac2(const Params &P, double R, double R0)
 {
-    if constexpr (NC == 0) return preac2_any(P, R, R0);
+    if constexpr (NC == NC_EXACT) return R0 <= P.x2_r0sw ? preac2x(P, R, R0) : preac2_any(P, R, R0);
+    else if constexpr (NC == 0) return preac2_any(P, R, R0);
     else return preac2_n<NC>(P, R, R0);
 }
 template <int NC> __device__ inline double corr2(const Params &P, double Rp, double R0)
 {
-    if constexpr (NC == 0) return corr2_any(P, Rp, R0);
+    if constexpr (NC == NC_EXACT) return 1.0;  // not reached: the exact form samples by inversion
+    else if constexpr (NC == 0) return corr2_any(P, Rp, R0);
     else return corr2_n<NC>(P, Rp, R0);
 }
 
@@ -314,9 +319,24 @@ __device__ inline double prop_attempt(const Params &P, const PropSetup &S, doubl
 // l, l + 64, ...; the first accepted attempt in order wins, exactly as if the
 // attempts were tried one after another.  Every lane of the wave must call it
 // with the same arguments; every lane gets the result.
+// The exact 2D form (tables, R0 up to the switch) draws by inversion with
+// word 0 of attempt 0; beyond the switch it samples by rejection from the
+// small-time expansions.
+__device__ inline double sample_radius_x2(const Params &P, double R0, u32 c0, u32 c1, u32 step, u32 tag, u32 *attempts, u32 *hits)
+{
+    const uint4 r = philox(c0, c1, step, tag & 0xFFu, P.key);
+    *attempts = 1;
+    *hits = 0;
+    return sample2x(P, R0, u01(r.x));
+}
+
 template <int DIM, int NC>
 __device__ double sample_radius_wave(const Params &P, double R0, u32 c0, u32 c1, u32 step, u32 tag, u32 *attempts, u32 *hits)
 {
+    if constexpr (DIM == 2 && NC == NC_EXACT) {
+        if (R0 > P.x2_r0sw) return sample_radius_wave<DIM, 0>(P, R0, c0, c1, step, tag, attempts, hits);
+        return sample_radius_x2(P, R0, c0, c1, step, tag, attempts, hits);
+    }
     const PropSetup S = prop_setup<DIM>(P, R0);
     const int lane = threadIdx.x & 63;
     u32 nh = 0;
@@ -344,6 +364,10 @@ __device__ double sample_radius_wave(const Params &P, double R0, u32 c0, u32 c1,
 template <int DIM, int NC>
 __device__ double sample_radius_lane(const Params &P, double R0, u32 c0, u32 c1, u32 step, u32 tag, u32 *attempts, u32 *hits)
 {
+    if constexpr (DIM == 2 && NC == NC_EXACT) {
+        if (R0 > P.x2_r0sw) return sample_radius_lane<DIM, 0>(P, R0, c0, c1, step, tag, attempts, hits);
+        return sample_radius_x2(P, R0, c0, c1, step, tag, attempts, hits);
+    }
     const PropSetup S = prop_setup<DIM>(P, R0);
     u32 nh = 0;
     double Rp = 1.0;

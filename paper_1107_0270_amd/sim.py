@@ -19,6 +19,7 @@ SP_A, SP_B, SP_C, SP_FREE, SP_RESERVED = 0, 1, 2, 3, 4
 BC_ABSORBING, BC_REFLECTING, BC_RADIATION = 0, 1, 2
 PREC_FP64, PREC_FP32, PREC_FP32_FP64NC = 0, 1, 2
 PAIRS_AUTO, PAIRS_BRICKS, PAIRS_DIRECT = 0, 1, 2
+G2_EXPANSION, G2_EXACT = 0, 1
 (READ_POS, READ_SPECIES, READ_PARTNER, READ_COUNTS, READ_STATS, READ_STATS_SUM, READ_DERIVED, READ_DBG_MOVED,
  READ_DBG_PAIRS, READ_DBG_PICKS, READ_DBG_MATCHES, READ_DBG_DISS, READ_DBG_CELLS, READ_TIMING, READ_GRID) = range(15)
 STAT_NAMES = ["pairs", "cand", "overlap", "r0clamp", "picks", "matches", "react", "decay", "geminate",
@@ -54,7 +55,8 @@ class SimConfig(C.Structure):
                 ("rcut", C.c_double), ("cell", C.c_double), ("pair_search", C.c_int32), ("n_species", C.c_int32),
                 ("species", C.POINTER(SimSpecies)), ("n_reactions", C.c_int32),
                 ("reactions", C.POINTER(SimReaction)), ("debug", C.c_uint32), ("timing", C.c_uint32),
-                ("debug_cap", C.c_uint64), ("hip_stream", C.c_void_p)]
+                ("debug_cap", C.c_uint64), ("hip_stream", C.c_void_p), ("green2d", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 _hip_rt = None
@@ -177,11 +179,12 @@ class Sim:
 
     def __init__(self, *, dim, box, dt, D, sigma, bc, species, pos, kappa=0.0, k_off=0.0,
                  precision=PREC_FP32_FP64NC, seed=0, replica=0, n_terms=12, eps_cut=1e-3, rcut=0.0, cell=0.0,
-                 pair_search=PAIRS_AUTO, partner=None, debug=False, timing=False, debug_cap=0, stream=None):
+                 pair_search=PAIRS_AUTO, partner=None, debug=False, timing=False, debug_cap=0, stream=None,
+                 green2d=G2_EXPANSION):
         self._config(dim=dim, box=box, dt=dt, D=D, sigma=sigma, bc=bc, species=species, pos=pos, kappa=kappa,
                      k_off=k_off, precision=precision, seed=seed, replica=replica, n_terms=n_terms, eps_cut=eps_cut,
                      rcut=rcut, cell=cell, pair_search=pair_search, debug=debug, timing=timing, debug_cap=debug_cap,
-                     stream=stream)
+                     stream=stream, green2d=green2d)
         L = lib()
         cfg = self.cfg
         sp = np.ascontiguousarray(species, dtype=np.int32)
@@ -200,7 +203,7 @@ class Sim:
 
     def _config(self, *, dim, box, dt, D, sigma, bc, species, pos, kappa=0.0, k_off=0.0,
                 precision=PREC_FP32_FP64NC, seed=0, replica=0, n_terms=12, eps_cut=1e-3, rcut=0.0, cell=0.0,
-                pair_search=PAIRS_AUTO, debug=False, timing=False, debug_cap=0, stream=None):
+                pair_search=PAIRS_AUTO, debug=False, timing=False, debug_cap=0, stream=None, green2d=G2_EXPANSION):
         cfg = SimConfig()
         cfg.dim, cfg.precision = int(dim), int(precision)
         bx = list(box) if np.ndim(box) else [float(box)] * int(dim)
@@ -219,6 +222,7 @@ class Sim:
         cfg.n_reactions, cfg.reactions = 1, self._reaction
         cfg.debug, cfg.timing, cfg.debug_cap = int(bool(debug)), int(bool(timing)), int(debug_cap)
         cfg.hip_stream = stream
+        cfg.green2d = int(green2d)
         self.cfg = cfg
         self.dim = int(dim)
 

@@ -49,15 +49,16 @@ class Report:
 
 
 def make_pair(*, dim, bc, box, dt, D, sigma, kappa, k_off, precision, species, pos, partner=None, seed=0,
-              n_terms=12, eps_cut=1e-3, rcut=0.0, cell=0.0, debug_cap=1 << 21, pair_search=S.PAIRS_AUTO):
+              n_terms=12, eps_cut=1e-3, rcut=0.0, cell=0.0, debug_cap=1 << 21, pair_search=S.PAIRS_AUTO, exact2d=False):
     gpu = S.Sim(dim=dim, box=box, dt=dt, D=D, sigma=sigma, bc=bc, kappa=kappa, k_off=k_off, precision=precision,
                 seed=seed, n_terms=n_terms, eps_cut=eps_cut, rcut=rcut, cell=cell, species=species, pos=pos,
-                partner=partner, debug=True, debug_cap=debug_cap, pair_search=pair_search)
+                partner=partner, debug=True, debug_cap=debug_cap, pair_search=pair_search,
+                green2d=S.G2_EXACT if exact2d else S.G2_EXPANSION)
     if pair_search != S.PAIRS_AUTO and min(gpu.grid()[:dim]) >= 3:
         assert gpu.grid()[4] == pair_search
     orc = O.OracleSim(dim=dim, bc=bc, box=[box] * dim, dt=dt, D=D, sigma=sigma, kappa_a=kappa, k_off=k_off,
                       eps_cut=eps_cut, rcut=rcut, seed=seed, store_f32=precision != S.PREC_FP64, n_terms=n_terms,
-                      species=species, pos=pos, partner=partner)
+                      exact2d=exact2d, species=species, pos=pos, partner=partner)
     return gpu, orc
 
 
