@@ -203,32 +203,18 @@ __device__ inline u32 block_sum(u32 v, u32 *lds)
     return t;
 }
 
-__device__ inline u32 block_incl_max(u32 v, u32 *lds)
-{
-    const int lane = lane_id(), w = threadIdx.x >> 6;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const u32 x = __shfl_up(v, o, 64);
-        if (lane >= o) v = max(v, x);
-    }
-    if (lane == 63) lds[w] = v;
-    __syncthreads();
-    for (int k = 0; k < w; ++k) v = max(v, lds[k]);
-    __syncthreads();
-    return v;
-}
-
 // ---------------------------------------------------------------------------
 // K1: move every live record and count it into its (species, cell) bucket.
 // The records sit in the order of last step's buckets, whose keys okey[]
 // holds for the first n_sorted of them, and a step takes only a few per cent
-// of them to another bucket.  A record that keeps its bucket (a stayer) is
-// ranked among the stayers of that bucket by a segmented scan over its
-// workgroup's chunk, and the chunk stores the bucket's stayer count: no
+// of them to another bucket.  Each wave takes a chunk of 64 sorted records.
+// A record that keeps its bucket (a stayer) is ranked among the stayers of
+// that bucket in the chunk by a segmented scan across the wave (shuffles, no
+// LDS and no barrier), and the chunk stores the bucket's stayer count: no
 // atomics.  Every other live record (bucket changed, appended since the last
-// binning, or in a bucket that began in an earlier chunk) takes its rank
-// from an atomic counter.  Stayers fill a bucket from its start, the others
-// from its end.  rank[i] = STAYER | rank for a stayer, else the atomic rank.
+// binning, or in a bucket that began in an earlier chunk) takes its rank from
+// an atomic counter.  Stayers fill a bucket from its start, the others from
+// its end.  rank[i] = STAYER | rank for a stayer, else the atomic rank.
 // ---------------------------------------------------------------------------
 constexpr u32 STAYER = 0x80000000u;
 constexpr u32 NOKEY = 0xFFFFFFFFu;
@@ -238,17 +224,15 @@ __global__ __launch_bounds__(BLOCK) void k_move_count(Params P, const Rec<T> *__
                                                        Rec<T> *__restrict__ tmp, u32 *__restrict__ rank, u32 *__restrict__ cnt,
                                                        u32 *__restrict__ scnt, u32 *__restrict__ nkey, Counters *C)
 {
-    __shared__ u32 lds[BLOCK / 64];
-    __shared__ u32 skey[BLOCK + 1];  // old bucket keys of the chunk; [BLOCK]: that of the record before it
-    __shared__ u32 sx[BLOCK];        // exclusive prefix count of stayers in the chunk
     const u32 step = C->step;
     if (gtid() == 0) {
         C->n_dbg[0] = C->n_dbg[1] = C->n_dbg[2] = C->n_dbg[3] = 0;
     }
     const u32 n = C->n_rec, ns = min(C->n_sorted, n);
-    const u32 t = threadIdx.x;
-    for (u32 b0 = blockIdx.x * BLOCK; b0 < n; b0 += gridDim.x * BLOCK) {  // uniform over the workgroup
-        const u32 i = b0 + t;
+    const int lane = lane_id();
+    const u32 nw = gstride() >> 6;
+    for (u32 b0 = (gtid() >> 6) * 64; b0 < n; b0 += nw * 64) {  // uniform over the wave
+        const u32 i = b0 + lane;
         const bool valid = i < n, sorted = i < ns;
         Rec<T> r;
         u32 m = 0, sp = SP_DEAD;
@@ -258,8 +242,7 @@ __global__ __launch_bounds__(BLOCK) void k_move_count(Params P, const Rec<T> *__
             sp = meta_sp(m);
         }
         const u32 ok = sorted ? okey[i] : NOKEY;
-        skey[t] = ok;
-        if (t == 0) skey[BLOCK] = (b0 > 0 && b0 - 1 < ns) ? okey[b0 - 1] : NOKEY;
+        const u32 before = (b0 > 0 && b0 - 1 < ns) ? okey[b0 - 1] : NOKEY;  // the record before the chunk
         const bool alive = valid && sp <= SP_C;
         u32 key = NOKEY;
         if (alive) {
@@ -273,23 +256,25 @@ __global__ __launch_bounds__(BLOCK) void k_move_count(Params P, const Rec<T> *__
         } else if (valid) {
             tmp[i] = r;  // dead record: the scatter skips it
         }
-        __syncthreads();
-        // segments: runs of equal old keys; the first one is not this
-        // chunk's if it continues from the record before the chunk
-        const bool head = t == 0 || skey[t - 1] != ok;
-        const u32 seg0 = block_incl_max(head ? t : 0u, lds);
-        const bool cont0 = skey[BLOCK] != NOKEY && skey[BLOCK] == skey[0];
+        // segments: runs of equal old keys; the first one is not this chunk's
+        // if it continues from the record before the chunk.  Every lane takes
+        // part in every shuffle (a lane left out of one gives no value).
+        const u32 left = __shfl_up(ok, 1, 64), right = __shfl_down(ok, 1, 64), first = __shfl(ok, 0, 64);
+        const bool head = lane == 0 || left != ok;
+        u32 seg0 = head ? (u32)lane : 0u;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const u32 x = __shfl_up(seg0, o, 64);
+            if (lane >= o) seg0 = max(seg0, x);
+        }
+        const bool cont0 = before != NOKEY && before == first;
         const bool local = sorted && !(seg0 == 0 && cont0);
         const bool stay = alive && local && key == ok;
-        u32 total;
-        const u32 ex = block_excl_scan(stay ? 1u : 0u, lds, total);
-        sx[t] = ex;
-        __syncthreads();
-        const u32 rs = ex - sx[seg0];
-        const bool last = t == BLOCK - 1 || skey[t + 1] != ok;
+        const u32 ex = wave_incl_scan(stay ? 1u : 0u) - (stay ? 1u : 0u);
+        const u32 rs = ex - (u32)__shfl((int)ex, (int)seg0, 64);
+        const bool last = lane == 63 || right != ok;
         if (local && last) scnt[cnt_index(ok, P.cnt_region)] = rs + (stay ? 1u : 0u);
         if (alive) rank[i] = stay ? (STAYER | rs) : atomicAdd(&cnt[cnt_index(key, P.cnt_region)], 1u);
-        __syncthreads();  // the next chunk reuses skey and sx
     }
 }
 
