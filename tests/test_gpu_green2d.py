@@ -117,3 +117,30 @@ def test_mem2d_as_written_exact_step_parity():
     assert rep.max_dRpp <= 1e-4 and rep.max_dpreac <= 1e-6
     assert rep.near_decisions <= 2
     assert rep.reactions > 0 and rep.matches > 0
+
+
+def test_exact_tables_at_large_intrinsic_rate():
+    # h = 20 (kappa_2D = 2 pi D_eff h): the expansion's p_reac diverges there, the tables hold
+    kw = dict(MEM2D)
+    kw["kappa"] = 2 * math.pi * 0.2 * 20.0
+    sp = np.array([0, 1], np.int32)
+    pos = np.array([[0.25, 0.25], [0.75, 0.75]])
+    h = S.Sim(dim=2, box=1.0, dt=5e-6, bc=O.BC_RAD, k_off=0.0, precision=S.PREC_FP64, species=sp, pos=pos,
+              green2d=S.G2_EXACT, **kw)
+    d = h.derived()
+    tau, hh, Rc = d["tau"], d["hh"], d["rcut"] / d["a"]
+    assert hh == pytest.approx(20.0)
+    sw = O.x2_switch(tau)
+    rng = np.random.default_rng(9)
+    R = 1.0 + (Rc - 1.0) * rng.random(200)
+    R0 = 1.0 + (sw - 1.0) * rng.random(200)
+    _, pr = h.eval_pairs(R, R0)
+    g = np.array([O.g2x(a, b, tau, hh) for a, b in zip(R, R0)])
+    gf = np.array([O.g2_free(a, b, tau) for a, b in zip(R, R0)])
+    cond = (g[:, 1] - g[:, 0]) > 1e-4 * gf
+    orr = np.array([O.preac2x(a, b, tau, hh) for a, b in zip(R, R0)])
+    dr = np.abs(pr - orr)[cond]
+    print(f"h {hh}: max |dp_reac| {dr.max():.2e} over {cond.sum()} of 200; p_reac in [{pr.min():.3f}, {pr.max():.3f}]")
+    assert cond.sum() > 50 and dr.max() <= 1e-6
+    assert (pr >= 0).all() and (pr <= 1).all()
+    h.close()

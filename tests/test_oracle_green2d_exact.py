@@ -113,3 +113,19 @@ def test_inversion_sampler(R0):
         m = O.m2x(Rp, R0, tau)
         assert (m[1] - m[0]) == pytest.approx(u * (mt[1] - mt[0]), rel=1e-10, abs=1e-12)
         prev = Rp
+
+
+def test_large_h_reaction_probability():
+    # large intrinsic rates, where the q^-1 small-time series fails (p_reac from it is ~1e4 at
+    # h = 20): the exact p_reac is a probability, rises with h towards 1 (the absorbing limit)
+    # and equals the Bayes ratio of scipy's Weber integrals
+    tau, R, R0 = 0.04, 1.05, 1.1
+    prev = 0.0
+    for hh in (0.5, 2.0, 20.0, 200.0):
+        p = O.preac2x(R, R0, tau, hh)
+        assert prev < p <= 1.0
+        prev = p
+    gabs, gref, grad = g2_exact(R, R0, tau, np.inf), g2_exact(R, R0, tau, 0.0), g2_exact(R, R0, tau, 20.0)
+    assert O.preac2x(R, R0, tau, 20.0) == pytest.approx((gref - grad) / (gref - gabs), rel=1e-7)
+    assert O.preac2x(R, R0, tau, 1e7) == pytest.approx(1.0, abs=1e-5)
+    assert abs(O.preac2(R, R0, tau, 20.0, 12)) > 10  # the expansion is useless there
