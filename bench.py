@@ -46,17 +46,17 @@ def algorithmic_bytes(kernel, n_live, n_a, n_b, n_keys):
 # commands are in profiles/rad3d_step_traffic.md.  Valid only for the kernel sources they were taken
 # on (hash below): after any change to them the field is reported as null.
 MEASURED_TRAFFIC = {
-    "src_hash": "5492d80a6ab44abd",
+    "src_hash": "0501a0d1c5c613a4",
     "scale_fetch": 1.9998, "scale_write": 1.0,
     "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
-        "move": (9830.1, 31266.3),
-        "scan": (5806.6 + 5824.0, 11.3 + 17376.1),
-        "scatter": (17020.8, 29458.7),
-        "pairs": (9597.7, 119.4),
-        "eval": (1035.0, 95.7),
-        "select_a": (163.8, 52.7),
-        "select_b": (170.0, 11.4),
-        "events": (563.5 + 2.8, 3279.2 + 0.8),
+        "move": (9814.6, 31395.2),
+        "scan": (5809.9 + 5824.3, 11.3 + 17376.1),
+        "scatter": (17002.1, 29452.5),
+        "pairs": (9602.9, 119.4),
+        "eval": (1035.0, 95.8),
+        "select_a": (158.2, 52.7),
+        "select_b": (167.4, 11.4),
+        "events": (574.6 + 2.8, 3279.2 + 0.8),
     },
 }
 
