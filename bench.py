@@ -150,9 +150,9 @@ def batched(args, I, S):
         d0 = probe.derived()
         probe.close()
         t0 = time.time()
-        best, table = AT.tune(lambda c, p: S.Sim.batch(sub, cell=c, **shared), box=sub[0]["box"], dim=3,
-                              rcut=d0["rcut"], cell0=d0["cell"], searches=(S.PAIRS_DIRECT,), log=log)
-        shared["cell"] = best["cell"]
+        best, table = AT.tune(lambda c, p, **launch: S.Sim.batch(sub, cell=c, **launch, **shared), box=sub[0]["box"],
+                              dim=3, rcut=d0["rcut"], cell0=d0["cell"], searches=(S.PAIRS_DIRECT,), log=log)
+        shared.update(cell=best["cell"], pair_blocks=best["pair_blocks"], event_blocks=best["event_blocks"])
         tuned = {"choice": best, "tuned_on": f"{len(sub)} replicas of the ensemble", "candidates": len(table),
                  "seconds": round(time.time() - t0, 1),
                  "table": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()} for r in table]}
@@ -340,10 +340,12 @@ def main():
 
     g2 = S.G2_EXACT if args.green2d == "exact" else S.G2_EXPANSION
 
-    def make_with(timing, cell, pair_search):
+    launch = {}  # pair-stage and event workgroups (the library's defaults unless tuned)
+
+    def make_with(timing, cell, pair_search, **shape):
         return S.Sim(dim=dim, box=box, dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
                      k_off=cfg["k_off"], precision=cfg["precision"], seed=0, species=sp, pos=pos, timing=timing, cell=cell,
-                     pair_search=pair_search, green2d=g2)
+                     pair_search=pair_search, green2d=g2, **shape)
 
     tuned = None
     if args.autotune:
@@ -352,19 +354,20 @@ def main():
         d0 = probe.derived()
         probe.close()
         t0 = time.time()
-        best, table = AT.tune(lambda c, p: make_with(False, c, p), box=box, dim=dim, rcut=d0["rcut"], cell0=d0["cell"],
-                              log=log)
+        best, table = AT.tune(lambda c, p, **shape: make_with(False, c, p, **shape), box=box, dim=dim, rcut=d0["rcut"],
+                              cell0=d0["cell"], log=log)
         args.cell, search = best["cell"], best["pair_search"]
+        launch.update(pair_blocks=best["pair_blocks"], event_blocks=best["event_blocks"])
         tuned = {"choice": best, "candidates": len(table), "seconds": round(time.time() - t0, 1),
                  "table": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()} for r in table]}
         log(f"[bench] autotuned in {tuned['seconds']} s: {best}")
 
     def make(timing, precision=None):
         if precision is None:
-            return make_with(timing, args.cell, search)
+            return make_with(timing, args.cell, search, **launch)
         return S.Sim(dim=dim, box=box, dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
                      k_off=cfg["k_off"], precision=precision, seed=0, species=sp, pos=pos, timing=timing, cell=args.cell,
-                     pair_search=search, green2d=g2)
+                     pair_search=search, green2d=g2, **launch)
 
     def timed(sim):
         sim.step(args.warmup)

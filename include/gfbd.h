@@ -110,6 +110,8 @@ typedef struct {
     uint64_t debug_cap;            /* entries per stage log (0 = 1 << 20) */
     void *hip_stream;              /* hipStream_t to run on; NULL = the null stream */
     int32_t green2d;               /* 2D radial functions: SIM_G2_EXPANSION or SIM_G2_EXACT (2D only) */
+    int32_t pair_blocks;           /* workgroups of the pair-evaluation and selection kernels, 8..65536 (0 = 1024) */
+    int32_t event_blocks;          /* workgroups of the event kernel, 1..65536 (0 = 1024) */
     int32_t reserved;              /* must be 0 */
 } sim_config;
 

@@ -1,12 +1,14 @@
-"""Autotuner for the run-time choices of a step: the cell edge of the cell list and the
-pair-search kernel (direct neighbour-bucket search or LDS bricks).
+"""Autotuner for the run-time choices of a step: the cell edge of the cell list, the
+pair-search kernel (direct neighbour-bucket search or LDS bricks) and the launch shapes of the
+pair stage and of the event kernel (workgroups per launch).
 
 The choices change only how fast a step runs, never what it computes: whatever the grid, the
-pair list is the set of all A-B pairs within r_cut, and every choice among candidates goes by
-slot.  So the tuner times candidates on the caller's own state and keeps the fastest.
+pair list is the set of all A-B pairs within r_cut, every choice among candidates goes by
+slot, and the pair-stage and event kernels stride over their work whatever their grid.  So the
+tuner times candidates on the caller's own state and keeps the fastest.
 
 Usage:
-    best, table = tune(lambda cell, pair_search: Sim(..., cell=cell, pair_search=pair_search),
+    best, table = tune(lambda cell, pair_search, **launch: Sim(..., cell=cell, pair_search=pair_search, **launch),
                        box=..., dim=..., rcut=...)
     sim = Sim(..., **best)
 
@@ -27,6 +29,10 @@ from . import sim as S
 CELL_FACTORS = (1.0, 1.25, 1.5, 2.0, 3.0)
 DEFAULT_FACTORS = (0.6, 0.75, 0.9, 1.15, 1.35, 1.6, 2.0)
 SEARCHES = (S.PAIRS_DIRECT, S.PAIRS_BRICKS)
+# workgroups per launch tried for the pair-evaluation/selection kernels and for the event kernel
+# (the library's default is 1024 for both)
+PAIR_BLOCKS = (256, 512, 1024, 2048)
+EVENT_BLOCKS = (256, 512, 1024, 2048)
 
 
 def grid_of(box, dim, cell, rcut):
@@ -75,34 +81,55 @@ def time_steps(sim, steps, warmup, repeats=2):
 
 
 def tune(make, *, box, dim, rcut, cell0=None, steps=30, warmup=10, factors=CELL_FACTORS,
-         default_factors=DEFAULT_FACTORS, searches=SEARCHES, log=None):
-    """Time every candidate; returns ({'cell': c, 'pair_search': p}, table).  `make(cell,
-    pair_search)` returns a fresh handle on the workload's initial state; cell0 is the edge the
-    library picks by itself (sim.derived()['cell']); candidates for which the library picks the
-    same kernel and grid as one already timed are skipped."""
+         default_factors=DEFAULT_FACTORS, searches=SEARCHES, pair_blocks=PAIR_BLOCKS, event_blocks=EVENT_BLOCKS,
+         log=None):
+    """Time every candidate; returns (choice, table) with choice = {'cell', 'pair_search',
+    'pair_blocks', 'event_blocks'}.  `make(cell, pair_search, **launch)` returns a fresh handle on
+    the workload's initial state (launch: pair_blocks and event_blocks, absent = the library's
+    default); cell0 is the edge the library picks by itself (sim.derived()['cell']).
+
+    Stage 1 times every (cell, pair_search) candidate at the default launch shapes, skipping
+    those for which the library picks a kernel and grid already timed.  Stage 2 then times, on
+    the best of stage 1, each pair-stage workgroup count and, on the best of those, each event
+    workgroup count (empty tuples skip stage 2)."""
     table, done = [], set()
-    for cell, ps in candidates(box, dim, rcut, cell0, factors, default_factors, searches):
-        try:
-            sim = make(cell, ps)
-        except S.SimError as e:  # a grid the library does not take for this state (e.g. a brick too large)
-            if e.code != S.SIM_EUNSUPPORTED:
-                raise
-            continue
+
+    def timed(cell, ps, **launch):
+        sim = make(cell, ps, **launch)
         try:
             g = tuple(int(x) for x in sim.grid())
-            if g in done:
-                continue
-            done.add(g)
+            if not launch:
+                if g in done:
+                    return None
+                done.add(g)
             t = time_steps(sim, steps, warmup)
         finally:
             sim.close()
         row = {"cell": cell, "pair_search": ps, "grid": list(g[:3]), "kernel": "bricks" if g[4] == S.PAIRS_BRICKS
-               else "direct", "ms_per_step": t * 1e3}
+               else "direct", "pair_blocks": launch.get("pair_blocks", 0), "event_blocks": launch.get("event_blocks", 0),
+               "ms_per_step": t * 1e3}
         table.append(row)
         if log:
-            log(f"[autotune] cell {cell:.5f} ({'x'.join(map(str, g[:dim]))}) {row['kernel']}: {t * 1e3:.4f} ms/step")
+            log(f"[autotune] cell {cell:.5f} ({'x'.join(map(str, g[:dim]))}) {row['kernel']} pair_blocks "
+                f"{row['pair_blocks'] or 'default'} event_blocks {row['event_blocks'] or 'default'}: {t * 1e3:.4f} ms/step")
+        return row
+
+    for cell, ps in candidates(box, dim, rcut, cell0, factors, default_factors, searches):
+        try:
+            timed(cell, ps)
+        except S.SimError as e:  # a grid the library does not take for this state (e.g. a brick too large)
+            if e.code != S.SIM_EUNSUPPORTED:
+                raise
     best = min(table, key=lambda r: r["ms_per_step"])
-    return {"cell": best["cell"], "pair_search": best["pair_search"]}, table
+    choice = {"cell": best["cell"], "pair_search": best["pair_search"], "pair_blocks": 0, "event_blocks": 0}
+    for key, values in (("pair_blocks", pair_blocks), ("event_blocks", event_blocks)):
+        for v in values:
+            row = timed(choice["cell"], choice["pair_search"], **dict(
+                {k: choice[k] for k in ("pair_blocks", "event_blocks") if choice[k]}, **{key: v}))
+            if row["ms_per_step"] < best["ms_per_step"]:
+                best = row
+                choice[key] = v
+    return choice, table
 
 
 def signature(*, dim, precision, bc, n, box, tau):

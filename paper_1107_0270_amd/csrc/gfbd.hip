@@ -137,7 +137,7 @@ namespace {
         if (e_ != hipSuccess) return fail(SIM_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
     } while (0)
 
-// workgroups of the event kernel: one wave per event for up to 4 * EV_BLOCKS events
+// default workgroups of the event kernel (sim_config.event_blocks)
 constexpr unsigned EV_BLOCKS = 1024;
 // expected B's tested per A above which the LDS brick search is chosen
 constexpr double PAIR_TESTS_TILED = 8.0;
@@ -147,6 +147,7 @@ struct Model {
     double box[3], dt, D[3], sigma, kappa, k_off, eps, rcut_req, cell_req;
     int pair_search;
     int green2d;
+    u32 pair_blocks, event_blocks;  // launch shapes of the pair stage and the event kernel
     uint64_t seed;
     uint32_t replica;
     int n_terms;
@@ -942,7 +943,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         hipStream_t st = M.stream;
         Rec<T> *in = rec[c], *out = rec[c ^ 1];
         const u32 g_all = grid_for(n, 8192);
-        const u32 g_pl = 1024;
+        const u32 g_pl = M.pair_blocks;
         launch(SIM_K_MOVE, [&] { k_move_count<DIM, T, PM, BATCH><<<g_all, BLOCK, 0, st>>>(P, in, okey, tmp, rank, cnt, scnt, nkey, ctr); });
         launch(SIM_K_SCAN, [&] {
             k_scan_tiles<<<nb_scan, BLOCK, 0, st>>>(cnt, scnt, bsum);
@@ -971,7 +972,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             k_select_b<T, BATCH><<<nb_sel + nb_dec, BLOCK, 0, st>>>(P, plist, cand, flag, headB, nextB, out, start, okey, ev, ctr, nb_sel);
         });
         launch(SIM_K_EVENTS, [&] {
-            k_events<DIM, T, NC2, BATCH><<<EV_BLOCKS, BLOCK, 0, st>>>(dparams, out, plist, cand, ev, partner, ctr, dbg_matches, dbg_diss);
+            k_events<DIM, T, NC2, BATCH><<<M.event_blocks, BLOCK, 0, st>>>(dparams, out, plist, cand, ev, partner, ctr, dbg_matches, dbg_diss);
             k_close<<<1, 64, 0, st>>>(ctr);
         });
     }
@@ -1225,6 +1226,8 @@ int validate_cfg(const sim_config *cfg, Model &M)
     if (cfg->pair_search < SIM_PAIRS_AUTO || cfg->pair_search > SIM_PAIRS_DIRECT) { g_err = "unknown pair_search"; return SIM_EINVAL; }
     if (cfg->green2d != SIM_G2_EXPANSION && cfg->green2d != SIM_G2_EXACT) { g_err = "unknown green2d"; return SIM_EINVAL; }
     if (cfg->green2d == SIM_G2_EXACT && cfg->dim != 2) { g_err = "green2d = SIM_G2_EXACT is for 2D"; return SIM_EINVAL; }
+    if (cfg->pair_blocks != 0 && (cfg->pair_blocks < 8 || cfg->pair_blocks > 65536)) { g_err = "pair_blocks must be 0 or in [8, 65536]"; return SIM_EINVAL; }
+    if (cfg->event_blocks < 0 || cfg->event_blocks > 65536) { g_err = "event_blocks must be in [0, 65536]"; return SIM_EINVAL; }
     M.dim = cfg->dim;
     M.prec = cfg->precision;
     M.bc = r.bc;
@@ -1239,6 +1242,8 @@ int validate_cfg(const sim_config *cfg, Model &M)
     M.cell_req = cfg->cell;
     M.pair_search = cfg->pair_search;
     M.green2d = cfg->green2d;
+    M.pair_blocks = cfg->pair_blocks ? (u32)cfg->pair_blocks : 1024u;
+    M.event_blocks = cfg->event_blocks ? (u32)cfg->event_blocks : EV_BLOCKS;
     M.seed = cfg->seed;
     M.replica = cfg->replica;
     M.n_terms = cfg->n_terms == 0 ? 12 : cfg->n_terms;

@@ -56,7 +56,7 @@ class SimConfig(C.Structure):
                 ("species", C.POINTER(SimSpecies)), ("n_reactions", C.c_int32),
                 ("reactions", C.POINTER(SimReaction)), ("debug", C.c_uint32), ("timing", C.c_uint32),
                 ("debug_cap", C.c_uint64), ("hip_stream", C.c_void_p), ("green2d", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("pair_blocks", C.c_int32), ("event_blocks", C.c_int32), ("reserved", C.c_int32)]
 
 
 _hip_rt = None
@@ -180,11 +180,11 @@ class Sim:
     def __init__(self, *, dim, box, dt, D, sigma, bc, species, pos, kappa=0.0, k_off=0.0,
                  precision=PREC_FP32_FP64NC, seed=0, replica=0, n_terms=12, eps_cut=1e-3, rcut=0.0, cell=0.0,
                  pair_search=PAIRS_AUTO, partner=None, debug=False, timing=False, debug_cap=0, stream=None,
-                 green2d=G2_EXPANSION):
+                 green2d=G2_EXPANSION, pair_blocks=0, event_blocks=0):
         self._config(dim=dim, box=box, dt=dt, D=D, sigma=sigma, bc=bc, species=species, pos=pos, kappa=kappa,
                      k_off=k_off, precision=precision, seed=seed, replica=replica, n_terms=n_terms, eps_cut=eps_cut,
                      rcut=rcut, cell=cell, pair_search=pair_search, debug=debug, timing=timing, debug_cap=debug_cap,
-                     stream=stream, green2d=green2d)
+                     stream=stream, green2d=green2d, pair_blocks=pair_blocks, event_blocks=event_blocks)
         L = lib()
         cfg = self.cfg
         sp = np.ascontiguousarray(species, dtype=np.int32)
@@ -203,7 +203,8 @@ class Sim:
 
     def _config(self, *, dim, box, dt, D, sigma, bc, species, pos, kappa=0.0, k_off=0.0,
                 precision=PREC_FP32_FP64NC, seed=0, replica=0, n_terms=12, eps_cut=1e-3, rcut=0.0, cell=0.0,
-                pair_search=PAIRS_AUTO, debug=False, timing=False, debug_cap=0, stream=None, green2d=G2_EXPANSION):
+                pair_search=PAIRS_AUTO, debug=False, timing=False, debug_cap=0, stream=None, green2d=G2_EXPANSION,
+                pair_blocks=0, event_blocks=0):
         cfg = SimConfig()
         cfg.dim, cfg.precision = int(dim), int(precision)
         bx = list(box) if np.ndim(box) else [float(box)] * int(dim)
@@ -223,6 +224,7 @@ class Sim:
         cfg.debug, cfg.timing, cfg.debug_cap = int(bool(debug)), int(bool(timing)), int(debug_cap)
         cfg.hip_stream = stream
         cfg.green2d = int(green2d)
+        cfg.pair_blocks, cfg.event_blocks = int(pair_blocks), int(event_blocks)
         self.cfg = cfg
         self.dim = int(dim)
 

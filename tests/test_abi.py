@@ -50,18 +50,22 @@ int main(void) {
          offsetof(sim_config, reactions), offsetof(sim_config, debug_cap), offsetof(sim_config, hip_stream),
          offsetof(sim_config, pair_search),
          sizeof(sim_reaction), sizeof(sim_dbg_pair), sizeof(sim_dbg_diss));
+  printf("%zu %zu %zu %zu\n", offsetof(sim_config, green2d), offsetof(sim_config, pair_blocks),
+         offsetof(sim_config, event_blocks), offsetof(sim_config, reserved));
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(sim_dbg_pick), sizeof(sim_dbg_match), sizeof(sim_kernel_time),
          sizeof(sim_replica), offsetof(sim_replica, box), offsetof(sim_replica, replica));
   return 0; }
 ''')
     exe = tmp_path / "probe"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
-    a, b = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")[:2]
+    a, g, b = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")[:3]
     got = [int(x) for x in a.split()]
     assert got == [C.sizeof(S.SimConfig), S.SimConfig.species.offset, S.SimConfig.reactions.offset,
                    S.SimConfig.debug_cap.offset, S.SimConfig.hip_stream.offset, S.SimConfig.pair_search.offset,
                    C.sizeof(S.SimReaction),
                    S.PAIR_DT.itemsize, S.DISS_DT.itemsize]
+    assert [int(x) for x in g.split()] == [S.SimConfig.green2d.offset, S.SimConfig.pair_blocks.offset,
+                                          S.SimConfig.event_blocks.offset, S.SimConfig.reserved.offset]
     assert [int(x) for x in b.split()] == [S.PICK_DT.itemsize, S.MATCH_DT.itemsize, 16, C.sizeof(S.SimReplica),
                                           S.SimReplica.box.offset, S.SimReplica.replica.offset]
 
@@ -89,6 +93,10 @@ def _args(**over):
     (dict(eps_cut=1.5), S.SIM_EINVAL),
     (dict(pair_search=3), S.SIM_EINVAL),
     (dict(pair_search=-1), S.SIM_EINVAL),
+    (dict(pair_blocks=7), S.SIM_EINVAL),
+    (dict(pair_blocks=65537), S.SIM_EINVAL),
+    (dict(event_blocks=-1), S.SIM_EINVAL),
+    (dict(event_blocks=65537), S.SIM_EINVAL),
     # C without a reserved partner in a reversible system
     (dict(species=np.array([2, 1], np.int32), k_off=1.0), S.SIM_EINVAL),
 ])

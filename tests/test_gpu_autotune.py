@@ -1,5 +1,5 @@
-"""The autotuner's choices change only the speed: every candidate cell edge and pair-search
-kernel gives the same trajectory, bit for bit."""
+"""The autotuner's choices change only the speed: every candidate cell edge, pair-search kernel
+and launch shape gives the same trajectory, bit for bit."""
 import numpy as np
 import pytest
 
@@ -26,8 +26,9 @@ def test_every_candidate_gives_the_same_trajectory(name):
     box = float(np.float32((n / density) ** (1.0 / dim)))
     sp, pos, _ = I.uniform_state(n // 2, n - n // 2, box=box, dim=dim, sigma=c["sigma"], seed=8, f32=prec != S.PREC_FP64)
 
-    def make(cell, ps):
-        return S.Sim(dim=dim, box=box, species=sp, pos=pos, precision=prec, seed=2, cell=cell, pair_search=ps, **c)
+    def make(cell, ps, **launch):
+        return S.Sim(dim=dim, box=box, species=sp, pos=pos, precision=prec, seed=2, cell=cell, pair_search=ps,
+                     **launch, **c)
 
     ref = make(0.0, S.PAIRS_AUTO)
     rcut, cell0 = ref.derived()["rcut"], ref.derived()["cell"]
@@ -36,21 +37,25 @@ def test_every_candidate_gives_the_same_trajectory(name):
     want_stats = ref.stats(total=True)
     ref.close()
     seen = set()
-    for cell, ps in AT.candidates(box, dim, rcut, cell0):
-        sim = make(cell, ps)
+    # every cell/search candidate at the default launch shapes, then the default grid at launch
+    # shapes from one workgroup per XCD to far more workgroups than pairs or events
+    shapes = [(cell, ps, {}) for cell, ps in AT.candidates(box, dim, rcut, cell0)]
+    shapes += [(0.0, S.PAIRS_AUTO, dict(pair_blocks=pb, event_blocks=eb)) for pb, eb in ((8, 1), (200, 77), (4096, 4096))]
+    for cell, ps, launch in shapes:
+        sim = make(cell, ps, **launch)
         g = tuple(sim.grid())
         sim.step(12)
         got = sim.state()
         st = sim.stats(total=True)
         sim.close()
         seen.add(g)
-        assert np.array_equal(got[0], want[0]), (cell, ps, g)
+        assert np.array_equal(got[0], want[0]), (cell, ps, g, launch)
         live = want[0] <= S.SP_C
-        assert np.array_equal(got[1][live], want[1][live]), (cell, ps, g)
+        assert np.array_equal(got[1][live], want[1][live]), (cell, ps, g, launch)
         cc = want[0] == S.SP_C
-        assert np.array_equal(got[2][cc], want[2][cc]), (cell, ps, g)
+        assert np.array_equal(got[2][cc], want[2][cc]), (cell, ps, g, launch)
         for k in ("pairs", "cand", "matches", "react", "decay", "geminate"):
-            assert st[k] == want_stats[k], (k, cell, ps, g)
+            assert st[k] == want_stats[k], (k, cell, ps, g, launch)
     assert len(seen) >= 4  # several grids and both kernels were exercised
     assert want_stats["react"] > 0
 
@@ -62,7 +67,10 @@ def test_tune_returns_a_timed_choice():
     probe = S.Sim(box=box, species=sp, pos=pos, **kw)
     rcut = probe.derived()["rcut"]
     probe.close()
-    best, table = AT.tune(lambda cell, ps: S.Sim(box=box, species=sp, pos=pos, cell=cell, pair_search=ps, **kw),
-                          box=box, dim=3, rcut=rcut, steps=5, warmup=2)
-    assert table and min(r["ms_per_step"] for r in table) == [r for r in table if r["cell"] == best["cell"] and
-                                                              r["pair_search"] == best["pair_search"]][0]["ms_per_step"]
+    best, table = AT.tune(lambda cell, ps, **launch: S.Sim(box=box, species=sp, pos=pos, cell=cell, pair_search=ps,
+                                                           **launch, **kw),
+                          box=box, dim=3, rcut=rcut, steps=5, warmup=2, pair_blocks=(256, 2048), event_blocks=(512,))
+    keys = ("cell", "pair_search", "pair_blocks", "event_blocks")
+    fastest = min(table, key=lambda r: r["ms_per_step"])
+    assert {k: fastest[k] for k in keys} == best
+    assert sum(1 for r in table if r["pair_blocks"] or r["event_blocks"]) == 3  # stage 2 timed each launch shape
