@@ -166,7 +166,7 @@ struct Counters {
     u32 step;       // step number used by every draw of this step
     u32 err;
     u32 n_dbg[4];   // pairs, picks, matches, dissociations logged this step
-    u32 n_ev;       // events (matched pairs and decays) queued this step
+    u32 unused0;
     u32 n_sorted;   // leading records whose bucket keys the last binning noted
     u32 n_kept;     // records kept by a pool compaction (zero between compactions)
     u32 pad[3];
@@ -174,6 +174,10 @@ struct Counters {
     u64 stats_last[ST_N];
     u64 stats_sum[ST_N];
     u32 pl_seg[PL_SEGS * PL_STRIDE];  // pairs appended to each segment (count at [x * PL_STRIDE])
+    // events (matched pairs and decays) queued this step, on a cache line of its
+    // own (the preceding words are segment padding, the following ones padding)
+    u32 n_ev;
+    u32 pad_ev[PL_STRIDE - 1];
 };
 
 // An A-B pair within r_cut (record indices in the sorted buffer).

@@ -203,6 +203,20 @@ __device__ inline u32 block_sum(u32 v, u32 *lds)
     return t;
 }
 
+// Append `val` to buf for every thread with `has`, one atomic on *counter per
+// workgroup: a same-address atomic per entry would serialise.  Every thread
+// of the workgroup calls it; the order of entries within the list is free.
+__device__ inline void block_append(u32 *__restrict__ buf, u32 *counter, bool has, u32 val, u32 *lds, u32 *base)
+{
+    u32 total;
+    const u32 r = block_excl_scan(has ? 1u : 0u, lds, total);
+    if (total == 0) return;  // uniform: total is the workgroup's
+    if (threadIdx.x == 0) *base = atomicAdd(counter, total);
+    __syncthreads();
+    if (has) buf[*base + r] = val;
+    __syncthreads();  // *base is read before the next call writes it
+}
+
 // ---------------------------------------------------------------------------
 // K1: move every live record and count it into its (species, cell) bucket.
 // The records sit in the order of last step's buckets, whose keys okey[]
@@ -1029,6 +1043,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair_eval(Params P, const Rec<T> *__r
     __shared__ u32 lds[BLOCK / 64];
     const u32 step = C->step;
     const PairIndex pi(C, P);
+    if (blockIdx.x * BLOCK >= pi.total) return;  // no pair for this workgroup (uniform): nothing to count
     u32 st[5] = {0, 0, 0, 0, 0};  // pairs, cand, overlap, r0clamp, near
     for (u32 kk = gtid(); kk < pi.total; kk += gstride()) {
         const u32 k = pi.entry(kk);
@@ -1125,8 +1140,10 @@ __global__ __launch_bounds__(BLOCK) void k_select_a(Params P, const PairEnt *__r
                                                      const u32 *__restrict__ nextA, u64 *__restrict__ headB, u32 *__restrict__ nextB,
                                                      Counters *C, DbgPick *dbg)
 {
+    __shared__ u32 lds[BLOCK / 64];
     const u32 step = C->step;
     const PairIndex pi(C, P);
+    if (blockIdx.x * BLOCK >= pi.total) return;  // no pair for this workgroup (uniform)
     u32 picks = 0;
     for (u32 kk = gtid(); kk < pi.total; kk += gstride()) {
         const u32 k = pi.entry(kk);
@@ -1158,7 +1175,7 @@ __global__ __launch_bounds__(BLOCK) void k_select_a(Params P, const PairEnt *__r
             }
         }
     }
-    if (picks) atomicAdd((unsigned long long *)&C->stats[ST_PICKS], (unsigned long long)picks);
+    block_add_stats(&picks, 1, &C->stats[ST_PICKS], lds);
 }
 
 constexpr u32 EV_DECAY = 0x80000000u;
@@ -1178,42 +1195,57 @@ __global__ __launch_bounds__(BLOCK) void k_select_b(Params P, const PairEnt *__r
                                                      const u32 *__restrict__ start, const u32 *__restrict__ okey, u32 *__restrict__ ev,
                                                      Counters *C, u32 nb_sel)
 {
+    __shared__ u32 lds[BLOCK / 64];
+    __shared__ u32 base;
     const u32 step = C->step;
     if (blockIdx.x >= nb_sel) {
         if (!P.reversible) return;
         const u32 beg = start[2 * P.n_cells], end = start[3 * P.n_cells];
-        const u32 t0 = (blockIdx.x - nb_sel) * BLOCK + threadIdx.x, ts = (gridDim.x - nb_sel) * BLOCK;
-        for (u32 i = beg + t0; i < end; i += ts) {
-            const u32 sc = meta_slot(rec_meta(rec[i]));
-            const Params &Q = BATCH ? P.reps[rep_of_key(P, okey[i])] : P;  // C records binned this step
-            if (below(philox(local_slot<BATCH>(Q, sc), NOSLOT, local_step<BATCH>(Q, step), TAG_UNI, Q.key).x, P.p_uni))
-                ev[atomicAdd(&C->n_ev, 1u)] = EV_DECAY | i;
+        const u32 ts = (gridDim.x - nb_sel) * BLOCK;
+        for (u32 b0 = beg + (blockIdx.x - nb_sel) * BLOCK; b0 < end; b0 += ts) {  // uniform over the workgroup
+            const u32 i = b0 + threadIdx.x;
+            bool dec = false;
+            if (i < end) {
+                const u32 sc = meta_slot(rec_meta(rec[i]));
+                const Params &Q = BATCH ? P.reps[rep_of_key(P, okey[i])] : P;  // C records binned this step
+                dec = below(philox(local_slot<BATCH>(Q, sc), NOSLOT, local_step<BATCH>(Q, step), TAG_UNI, Q.key).x, P.p_uni);
+            }
+            block_append(ev, &C->n_ev, dec, EV_DECAY | i, lds, &base);
         }
         return;
     }
     const PairIndex pi(C, P);
+    if (blockIdx.x * BLOCK >= pi.total) return;  // no pair for this workgroup (uniform)
     u32 n_match = 0;
-    for (u32 kk = blockIdx.x * BLOCK + threadIdx.x; kk < pi.total; kk += nb_sel * BLOCK) {
-        const u32 k = pi.entry(kk);
-        if (flag[k] != PE_PICKED) continue;
-        const u32 h = (u32)headB[list[k].b_idx];
-        u32 mins = NOSLOT, count = 0;
-        for (u32 e = h; e != NOSLOT; e = nextB[e]) {
-            mins = min(mins, cand[e].a_slot);
-            ++count;
+    for (u32 b0 = blockIdx.x * BLOCK; b0 < pi.total; b0 += nb_sel * BLOCK) {  // uniform over the workgroup
+        const u32 kk = b0 + threadIdx.x;
+        u32 win = NOSLOT;
+        if (kk < pi.total) {
+            const u32 k = pi.entry(kk);
+            if (flag[k] == PE_PICKED) {
+                const u32 h = (u32)headB[list[k].b_idx];
+                u32 mins = NOSLOT, count = 0;
+                for (u32 e = h; e != NOSLOT; e = nextB[e]) {
+                    mins = min(mins, cand[e].a_slot);
+                    ++count;
+                }
+                if (cand[k].a_slot == mins) {
+                    win = k;
+                    if (count > 1) {
+                        const Params &Q = rep_params<BATCH>(P, cand[k].b_slot);
+                        const double U =
+                            u01(philox(local_slot<BATCH>(Q, cand[k].b_slot), NOSLOT, local_step<BATCH>(Q, step), TAG_SELB, Q.key).x);
+                        win = choose_in_chain(h, nextB, count, U, [&](u32 e) { return cand[e].a_slot; },
+                                              [&](u32 e) { return cand[e].p; });
+                        if (win == NOSLOT) win = k;
+                    }
+                }
+            }
         }
-        if (cand[k].a_slot != mins) continue;
-        u32 win = k;
-        if (count > 1) {
-            const Params &Q = rep_params<BATCH>(P, cand[k].b_slot);
-            const double U = u01(philox(local_slot<BATCH>(Q, cand[k].b_slot), NOSLOT, local_step<BATCH>(Q, step), TAG_SELB, Q.key).x);
-            win = choose_in_chain(h, nextB, count, U, [&](u32 e) { return cand[e].a_slot; }, [&](u32 e) { return cand[e].p; });
-            if (win == NOSLOT) win = k;
-        }
-        ++n_match;
-        ev[atomicAdd(&C->n_ev, 1u)] = win;
+        n_match += win != NOSLOT;
+        block_append(ev, &C->n_ev, win != NOSLOT, win, lds, &base);
     }
-    if (n_match) atomicAdd((unsigned long long *)&C->stats[ST_MATCHES], (unsigned long long)n_match);
+    block_add_stats(&n_match, 1, &C->stats[ST_MATCHES], lds);
 }
 
 // K9: close the step (one workgroup, after the events): thread s < ST_N
@@ -1259,14 +1291,18 @@ __global__ void k_close(Counters *C)
 // Wave form (LANE = false): one wave per event, every lane computes the same
 // values, the rejection attempts are spread over the lanes, lane 0 writes.
 // Lane form (LANE = true): one event per lane, attempts one after another.
-// Both add their counts to st[] (react, attempts, bound hits, near, decay,
-// geminate), which the kernel sums per workgroup.
+// Both return their counts (react, attempts, bound hits, near, decay,
+// geminate; zero on lanes other than 0 in the wave form), which the kernel
+// sums per workgroup.
 // ---------------------------------------------------------------------------
 constexpr int EV_ST = 6;
+struct EvCount {
+    u32 v[EV_ST];
+};
 
 template <int DIM, class T, int NC, bool LANE>
-__device__ __noinline__ void ev_match(const Params &P, Rec<T> *__restrict__ rec, u32 ia, u32 ib, double R0, u32 *__restrict__ partner,
-                                      u32 step, Counters *C, DbgMatch *dbg, u32 *st)
+__device__ __forceinline__ EvCount ev_match(const Params &P, Rec<T> *__restrict__ rec, u32 ia, u32 ib, double R0,
+                                         u32 *__restrict__ partner, u32 step, Counters *C, DbgMatch *dbg)
 {
 #pragma clang fp contract(off)
     Rec<T> ra = rec[ia], rb = rec[ib];
@@ -1315,14 +1351,15 @@ __device__ __noinline__ void ev_match(const Params &P, Rec<T> *__restrict__ rec,
         rec_set_meta(ra, meta_make(SP_C, sa));
         rec_set_meta(rb, meta_make(SP_DEAD, sb));
     }
+    EvCount cnt = {{0, 0, 0, 0, 0, 0}};
     if (LANE || lane_id() == 0) {
         if (react) partner[sa] = P.reversible ? sb : NOSLOT;
         rec[ia] = ra;
         rec[ib] = rb;
-        st[0] += react;
-        st[1] += att;
-        st[2] += hits;
-        st[3] += near;
+        cnt.v[0] = react;
+        cnt.v[1] = att;
+        cnt.v[2] = hits;
+        cnt.v[3] = near;
         if (P.debug) {
             const u32 q = atomicAdd(&C->n_dbg[2], 1u);
             if (q < P.dbg_cap) {
@@ -1332,11 +1369,12 @@ __device__ __noinline__ void ev_match(const Params &P, Rec<T> *__restrict__ rec,
             }
         }
     }
+    return cnt;
 }
 
 template <int DIM, class T, int NC, bool LANE>
-__device__ __noinline__ void ev_decay(const Params &P, Rec<T> *__restrict__ rec, u32 i, u32 *__restrict__ partner, u32 step,
-                                      Counters *C, DbgDiss *dbg, u32 *st)
+__device__ __forceinline__ EvCount ev_decay(const Params &P, Rec<T> *__restrict__ rec, u32 i, u32 *__restrict__ partner, u32 step,
+                                         Counters *C, DbgDiss *dbg)
 {
 #pragma clang fp contract(off)
     const Rec<T> rc = rec[i];
@@ -1348,11 +1386,12 @@ __device__ __noinline__ void ev_decay(const Params &P, Rec<T> *__restrict__ rec,
     const double preac = reac_prob<NC>(P, DIM, Rpp, 1.0);
     const bool gem = below(philox(lc, NOSLOT, step, TAG_GEM, P.key).x, preac);
     const u32 sb = partner[sc];
+    EvCount cnt = {{0, 0, 0, 0, 0, 0}};
     if (LANE || lane_id() == 0) {
-        st[4] += 1;
-        st[5] += gem;
-        st[1] += att;
-        st[2] += hits;
+        cnt.v[4] = 1;
+        cnt.v[5] = gem;
+        cnt.v[1] = att;
+        cnt.v[2] = hits;
         if (P.debug) {
             const u32 q = atomicAdd(&C->n_dbg[3], 1u);
             if (q < P.dbg_cap) {
@@ -1362,7 +1401,7 @@ __device__ __noinline__ void ev_decay(const Params &P, Rec<T> *__restrict__ rec,
             }
         }
     }
-    if (gem) return;
+    if (gem) return cnt;
     const uint4 r = philox(lc, NOSLOT, step, TAG_DIR, P.key);
     double e[3] = {0.0, 0.0, 0.0};
     if (DIM == 3) {
@@ -1393,13 +1432,15 @@ __device__ __noinline__ void ev_decay(const Params &P, Rec<T> *__restrict__ rec,
         if (q < P.cap) rec[q] = rb;
         else atomicOr(&C->err, (u32)ERR_APPEND);
     }
+    return cnt;
 }
 
-// The handlers are called, not inlined: one inlined body for both event
-// kinds needs more registers than a wave has and spills.  They read the
-// parameters from a device-resident copy (a by-value kernel argument would be
-// copied to per-lane scratch to be passed by reference).  Up to
-// EV_LANE_MIN - 1 events run one per wave, more run one per lane.
+// The handlers are inlined: called, they keep their frames and the registers
+// saved around the calls in per-lane scratch memory, whose loads then sit on
+// each event's chain of dependent operations.  They read the parameters from
+// a device-resident copy (a by-value kernel argument would be copied to
+// per-lane scratch to be passed by reference).  Up to EV_LANE_MIN - 1 events
+// run one per wave, more run one per lane.
 constexpr u32 EV_LANE_MIN = 4096;
 
 // the parameters of the replica of record i (a single system: its own)
@@ -1419,16 +1460,22 @@ __global__ __launch_bounds__(BLOCK) void k_events(const Params *__restrict__ Pd,
     const Params &P = *Pd;
     const u32 step = C->step;
     const u32 n = min(C->n_ev, P.cap);
+    // a workgroup with no event (uniform) has nothing to count either
+    if (blockIdx.x * (n >= EV_LANE_MIN ? BLOCK : BLOCK / 64) >= n) return;
     u32 st[EV_ST] = {0, 0, 0, 0, 0, 0};
+    auto add = [&](const EvCount &c) {
+#pragma unroll
+        for (int k = 0; k < EV_ST; ++k) st[k] += c.v[k];
+    };
     if (n >= EV_LANE_MIN) {
         for (u32 w = gtid(); w < n; w += gstride()) {
             const u32 e = ev[w];
             if (e & EV_DECAY) {
                 const u32 i = e & ~EV_DECAY;
-                ev_decay<DIM, T, NC, true>(ev_params<BATCH>(P, rec, i), rec, i, partner, step, C, dbg_d, st);
+                add(ev_decay<DIM, T, NC, true>(ev_params<BATCH>(P, rec, i), rec, i, partner, step, C, dbg_d));
             } else {
-                ev_match<DIM, T, NC, true>(rep_params<BATCH>(P, cand[e].a_slot), rec, list[e].a_idx, list[e].b_idx, cand[e].R0,
-                                           partner, step, C, dbg_m, st);
+                add(ev_match<DIM, T, NC, true>(rep_params<BATCH>(P, cand[e].a_slot), rec, list[e].a_idx, list[e].b_idx,
+                                               cand[e].R0, partner, step, C, dbg_m));
             }
         }
     } else {
@@ -1437,10 +1484,10 @@ __global__ __launch_bounds__(BLOCK) void k_events(const Params *__restrict__ Pd,
             const u32 e = ev[w];
             if (e & EV_DECAY) {
                 const u32 i = e & ~EV_DECAY;
-                ev_decay<DIM, T, NC, false>(ev_params<BATCH>(P, rec, i), rec, i, partner, step, C, dbg_d, st);
+                add(ev_decay<DIM, T, NC, false>(ev_params<BATCH>(P, rec, i), rec, i, partner, step, C, dbg_d));
             } else {
-                ev_match<DIM, T, NC, false>(rep_params<BATCH>(P, cand[e].a_slot), rec, list[e].a_idx, list[e].b_idx, cand[e].R0,
-                                            partner, step, C, dbg_m, st);
+                add(ev_match<DIM, T, NC, false>(rep_params<BATCH>(P, cand[e].a_slot), rec, list[e].a_idx, list[e].b_idx,
+                                                cand[e].R0, partner, step, C, dbg_m));
             }
         }
     }
