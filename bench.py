@@ -46,17 +46,28 @@ def algorithmic_bytes(kernel, n_live, n_a, n_b, n_keys):
 # commands are in profiles/rad3d_step_traffic.md.  Valid only for the kernel sources they were taken
 # on (hash below): after any change to them the field is reported as null.
 MEASURED_TRAFFIC = {
-    "src_hash": "0501a0d1c5c613a4",
+    "src_hash": "9b34e01bc6bd27c0",
     "scale_fetch": 1.9998, "scale_write": 1.0,
     "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
-        "move": (9814.6, 31395.2),
-        "scan": (5809.9 + 5824.3, 11.3 + 17376.1),
-        "scatter": (17002.1, 29452.5),
-        "pairs": (9602.9, 119.4),
-        "eval": (1035.0, 95.8),
-        "select_a": (158.2, 52.7),
-        "select_b": (167.4, 11.4),
-        "events": (574.6 + 2.8, 3279.2 + 0.8),
+        "move": (9819.4, 31395.4),
+        "scan": (5809.6 + 5824.3, 11.3 + 17376.1),
+        "scatter": (17008.7, 29449.3),
+        "pairs": (9602.8, 119.4),
+        "eval": (1035.9, 95.8),
+        "select_a": (164.3, 50.0),
+        "select_b": (183.6, 4.9),
+        "events": (322.5 + 2.8, 52.1 + 0.9),
+    },
+    # stage -> VALU wave-instructions per launch (SQ_INSTS_VALU summed over the stage's kernels)
+    "valu": {
+        "move": 9487370,
+        "scan": 144800 + 271542,
+        "scatter": 723660,
+        "pairs": 4398462,
+        "eval": 233629,
+        "select_a": 18402,
+        "select_b": 159702,
+        "events": 1175650 + 21,
     },
 }
 
@@ -75,6 +86,22 @@ def measured_traffic(stage):
         return None
     f, w = t["kib"][stage]
     return int(f * 1024 * t["scale_fetch"] + w * 1024 * t["scale_write"])
+
+
+# VALU issue peak: a wave64 VALU instruction occupies one of 256 CUs x 4 SIMDs for 4 cycles at 2.4 GHz
+VALU_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
+
+
+def valu_issue(stage, launch_ms):
+    """The stage's measured VALU wave-instructions per launch (profiles/rad3d_step_valu.md), the
+    time they take at the issue peak, and that time over the live launch duration."""
+    t = MEASURED_TRAFFIC
+    if stage not in t["valu"] or kernel_src_hash() != t["src_hash"]:
+        return None
+    n = t["valu"][stage]
+    at_peak = n / VALU_WAVE_INSTR_PER_S * 1e3
+    return {"wave_instructions_per_launch": n, "issue_ms_at_peak": round(at_peak, 5),
+            "frac": round(at_peak / launch_ms, 4), "peak_wave_instr_per_s": VALU_WAVE_INSTR_PER_S}
 
 
 def describe(cfg):
@@ -414,6 +441,9 @@ def main():
     per = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kt.items()}
     tot = {k: v[0] for k, v in kt.items()}
     dom = max(tot, key=tot.get) if any(tot.values()) else None
+    # the rocprofv3 counts were taken on the default run of this workload
+    profiled = (args.workload == "cfg_rad3d" and args.precision == "workload" and args.pair_search == "auto"
+                and args.cell == 0.0 and not args.autotune)
     roof = None
     if dom is not None and per[dom] > 0:
         nb = algorithmic_bytes(dom, n_live, 0.5 * (c0["A"] + c1["A"]), 0.5 * (c0["B"] + c1["B"]), n_keys)
@@ -421,8 +451,9 @@ def main():
             nb *= rec_scale
             ach = nb / (per[dom] * 1e-3) / 1e9
             roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
-                    "algorithmic_bytes_per_launch": int(nb), "avg_launch_ms": round(per[dom], 5)}
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom) if profiled else None,
+                    "algorithmic_bytes_per_launch": int(nb), "avg_launch_ms": round(per[dom], 5),
+                    "valu_issue": valu_issue(dom, per[dom]) if profiled else None}
 
     cpu = None
     if args.cpu_steps > 0:
