@@ -88,6 +88,7 @@ def lib():
         "orc_preac2x": (d, [d, d, d, d]),
         "orc_sample_prop2x": (d, [d, d, d]),
         "orc_x2_switch": (d, [d]),
+        "orc_first_passage": (u64, [i, P(d), P(d), d, i, i, u32, u32, P(u32), P(u32)]),
         "orc_rcut": (d, [i, i, d, d, d, d, d]),
         "orc_sim_create": (vp, [P(Params), u64, vp, vp, vp]),
         "orc_sim_destroy": (None, [vp]),
@@ -251,6 +252,20 @@ def sample_prop2x(R0, tau, u):
 
 def x2_switch(tau):
     return lib().orc_x2_switch(float(tau))
+
+
+def first_passage(dim, xi, xf, tau, levels, c0, step, key, n_terms=12):
+    """First contact of a pair by bisection (Appendix): the index lo of the interval
+    [lo, lo + 1) * dt / 2^levels, and the midpoint proposals drawn."""
+    a = np.zeros(3)
+    b = np.zeros(3)
+    a[:dim] = np.asarray(xi, dtype=np.float64).reshape(-1)[:dim]
+    b[:dim] = np.asarray(xf, dtype=np.float64).reshape(-1)[:dim]
+    k = (C.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    att = C.c_uint32(0)
+    lo = lib().orc_first_passage(int(dim), _dp(a), _dp(b), float(tau), int(levels), int(n_terms),
+                                 int(c0) & 0xFFFFFFFF, int(step) & 0xFFFFFFFF, k, C.byref(att))
+    return int(lo), att.value
 
 
 def rcut(dim, bc, a, Deff, dt, kappa_a, eps):

@@ -654,7 +654,7 @@ double orc_rcut(int dim, int bc, double a, double Deff, double dt, double kappa_
 /* {slot i, partner j or 0xFFFFFFFF, step, tag | attempt << 8}.             */
 /* ------------------------------------------------------------------------ */
 enum { TAG_MOVE = 1, TAG_ENC = 2, TAG_SELA = 3, TAG_SELB = 4, TAG_PROP = 5, TAG_REAC = 6,
-       TAG_UNI = 7, TAG_DPROP = 8, TAG_DIR = 9, TAG_GEM = 10 };
+       TAG_UNI = 7, TAG_DPROP = 8, TAG_DIR = 9, TAG_GEM = 10, TAG_FPT = 11, TAG_FPTU = 12 };
 #define NOSLOT 0xFFFFFFFFu
 
 struct orc_sim {
@@ -1142,3 +1142,88 @@ void orc_sim_pairs(const orc_sim *s, orc_pair *out) { memcpy(out, s->pairs, s->n
 void orc_sim_picks(const orc_sim *s, orc_pick *out) { memcpy(out, s->picks, s->n_picks * sizeof(orc_pick)); }
 void orc_sim_matches(const orc_sim *s, orc_match *out) { memcpy(out, s->matches, s->n_matches * sizeof(orc_match)); }
 void orc_sim_diss(const orc_sim *s, orc_diss *out) { memcpy(out, s->diss, s->n_diss * sizeof(orc_diss)); }
+
+/* ------------------------------------------------------------------------ */
+/* First-passage time by bisection (Appendix).  A pair whose separation went */
+/* from x_i to x_f over one step of tau = D_eff dt / a^2, with at least one  */
+/* encounter, has its first contact time located by halving the interval:   */
+/* the separation at the midpoint is drawn from the Brownian bridge (eq.     */
+/* midPGauss, per coordinate mean (x_a + x_b)/2 and variance tau_h, the      */
+/* dimensionless half-interval), and p_enc of each half decides where the    */
+/* first encounter lies.  Reading: both the midpoint and the choice are      */
+/* conditioned on the encounter known to lie in the interval.  Given x_m the */
+/* halves are independent, so that encounter has probability                 */
+/* q = 1 - (1 - p1)(1 - p2): the midpoint is drawn from the bridge times q   */
+/* (a bridge proposal accepted with probability q), and the first half is    */
+/* chosen with probability p1 / q.  The located interval is then distributed */
+/* as the first-passage time given the end points and the encounter.        */
+/* Lengths are in units of a (contact at |x| = 1).  dim = 1 is the half line */
+/* x > 1 with eq. bayes1D, p_enc = e^{-(x-1)(x0-1)/tau}; dim = 2 and 3 use    */
+/* the radial encounter probabilities of Sec. 2.2.4 (3D: the closed form,   */
+/* 2D: the expansion of order n_terms).                                      */
+/* Draws per attempt k at level l: {c0, l, step, FPT | k << 8} gives the     */
+/* normals (Box-Muller on words 0, 1 and 2, 3: z0 = r0 cos, z1 = r0 sin,     */
+/* z2 = r1 cos), {c0, l, step, FPTU | k << 8} the uniforms (word 0 accepts,  */
+/* word 1 chooses the half).                                                 */
+/* ------------------------------------------------------------------------ */
+static double fp_penc(int dim, double R, double R0, double tau, int n_terms)
+{
+    if (R <= 1.0 || R0 <= 1.0) return 1.0;
+    if (dim == 1) return exp(-(R - 1.0) * (R0 - 1.0) / tau);
+    if (dim == 2) return orc_penc2(R, R0, tau, n_terms);
+    return orc_penc3(R, R0, tau);
+}
+
+static double fp_norm(int dim, const double *x)
+{
+    if (dim == 1) return x[0];
+    double s = 0.0;
+    for (int k = 0; k < dim; ++k) s += x[k] * x[k];
+    return sqrt(s);
+}
+
+uint64_t orc_first_passage(int dim, const double *xi, const double *xf, double tau, int levels, int n_terms,
+                           uint32_t c0, uint32_t step, const uint32_t key[2], uint32_t *attempts)
+{
+    double xa[3] = {0, 0, 0}, xb[3] = {0, 0, 0}, xm[3] = {0, 0, 0};
+    for (int k = 0; k < dim; ++k) {
+        xa[k] = xi[k];
+        xb[k] = xf[k];
+    }
+    uint64_t lo = 0;  /* the interval is [lo, lo + 1) in units of dt / 2^level */
+    uint32_t att = 0;
+    for (int l = 0; l < levels; ++l) {
+        double th = tau / (double)(2ull << l);  /* the half-interval */
+        double sd = sqrt(th), ra = fp_norm(dim, xa), rb = fp_norm(dim, xb);
+        double p1 = 1.0, q = 1.0;
+        double V = 0.0;
+        for (uint32_t k = 0; k < MAX_ATTEMPTS; ++k) {
+            uint32_t cz[4] = {c0, (uint32_t)l, step, TAG_FPT | (k << 8)}, cu[4] = {c0, (uint32_t)l, step, TAG_FPTU | (k << 8)};
+            double u[4], v[4], z[3];
+            uint32_t w[4];
+            draw(cz, key, u, w);
+            double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
+            z[0] = r0 * cos(2.0 * PI * u[1]);
+            z[1] = r0 * sin(2.0 * PI * u[1]);
+            z[2] = r1 * cos(2.0 * PI * u[3]);
+            for (int d = 0; d < dim; ++d) xm[d] = 0.5 * (xa[d] + xb[d]) + sd * z[d];
+            double rm = fp_norm(dim, xm);
+            p1 = fp_penc(dim, rm, ra, th, n_terms);
+            double p2 = fp_penc(dim, rb, rm, th, n_terms);
+            q = 1.0 - (1.0 - p1) * (1.0 - p2);
+            draw(cu, key, v, w);
+            ++att;
+            V = v[1];
+            if (v[0] < q) break;
+        }
+        lo *= 2;
+        if (V * q < p1) {  /* first half: the end point becomes the midpoint */
+            for (int d = 0; d < dim; ++d) xb[d] = xm[d];
+        } else {           /* second half: the start point becomes the midpoint */
+            for (int d = 0; d < dim; ++d) xa[d] = xm[d];
+            lo += 1;
+        }
+    }
+    if (attempts) *attempts = att;
+    return lo;
+}

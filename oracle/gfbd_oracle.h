@@ -99,6 +99,14 @@ enum {
     ORC_ST_REACT, ORC_ST_DECAY, ORC_ST_GEMINATE, ORC_ST_ATTEMPTS, ORC_ST_BOUND, ORC_ST_N
 };
 
+/* First-passage time by bisection (Appendix): the index lo of the interval
+ * [lo, lo + 1) * dt / 2^levels that holds the first contact of a pair whose
+ * separation (units of a) went from xi to xf over tau = D_eff dt / a^2 with at
+ * least one encounter; dim 1 (half line x > 1), 2 or 3.  *attempts: midpoint
+ * proposals drawn. */
+uint64_t orc_first_passage(int dim, const double *xi, const double *xf, double tau, int levels, int n_terms,
+                           uint32_t c0, uint32_t step, const uint32_t key[2], uint32_t *attempts);
+
 typedef struct orc_sim orc_sim;
 
 orc_sim *orc_sim_create(const orc_params *p, uint64_t n, const int32_t *species, const double *pos,
