@@ -157,6 +157,88 @@ def pair_probs(args, I, S):
                    "kernel": "k_eval_probs (the step's p_enc / p_reac device functions)"}}), flush=True)
 
 
+def first_passage(args, I, S):
+    """First contact of N candidate pairs of the benchmark workload located by bisection
+    (sim_eval_first_passage, the paper's Appendix) to dt / 2^levels, on device-resident arrays.
+    Candidates: a pre-step separation uniform in the shell 1 < R0 < r_cut/a, a free step of
+    sqrt(2 tau) z, kept with the encounter probability that the step's own device function gives
+    (sim_eval_pairs), as the step keeps its candidates."""
+    cfg = I.workload("cfg_rad3d")
+    sp = np.array([0, 1], np.int32)
+    pos = np.array([[0.25] * 3, [0.75] * 3])
+    h = S.Sim(dim=3, box=cfg["box"], dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
+              k_off=0.0, precision=S.PREC_FP64, seed=0, species=sp, pos=pos)
+    der = h.derived()
+    tau, rmax, n, levels = der["tau"], der["rcut"] / der["a"], args.first_passage, args.fp_levels
+    rng = np.random.default_rng(0)
+    xi_all, xf_all, have = [], [], 0
+    while have < n:
+        m = 4 * n
+        d = rng.standard_normal((m, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        xi = d * ((1.0 + (rmax ** 3 - 1.0) * rng.random(m)) ** (1.0 / 3.0))[:, None]
+        xf = xi + np.sqrt(2.0 * tau) * rng.standard_normal((m, 3))
+        R, R0 = np.ascontiguousarray(np.linalg.norm(xf, axis=1)), np.ascontiguousarray(np.linalg.norm(xi, axis=1))
+        bR, bR0, bp = S.DeviceBuffer(8 * m), S.DeviceBuffer(8 * m), S.DeviceBuffer(8 * m)
+        bR.upload(R)
+        bR0.upload(R0)
+        h.eval_pairs_device(m, bR.ptr, bR0.ptr, bp.ptr, None)
+        p = bp.download(np.empty(m, np.float64))
+        for b in (bR, bR0, bp):
+            b.free()
+        keep = rng.random(m) < p
+        xi_all.append(xi[keep])
+        xf_all.append(xf[keep])
+        have += int(keep.sum())
+    xi = np.ascontiguousarray(np.concatenate(xi_all)[:n])
+    xf = np.ascontiguousarray(np.concatenate(xf_all)[:n])
+    bi, bf, blo, ba = S.DeviceBuffer(24 * n), S.DeviceBuffer(24 * n), S.DeviceBuffer(8 * n), S.DeviceBuffer(4 * n)
+    bi.upload(xi)
+    bf.upload(xf)
+    call = (n, bi.ptr, bf.ptr, levels, 1, blo.ptr, ba.ptr)
+    h.eval_first_passage_device(*call)  # warm-up
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        h.eval_first_passage_device(*call)
+    el = time.perf_counter() - t0
+    att = ba.download(np.empty(n, np.uint32))
+    lo = blo.download(np.empty(n, np.uint64))
+    for b in (bi, bf, blo, ba):
+        b.free()
+    h.close()
+    rate = n * args.steps / el
+    cpu = None
+    if args.cpu_steps > 0:
+        import oracle as O
+
+        m = min(n, 20000)
+        key = (0, 0)  # seed 0, replica 0
+        tc = time.perf_counter()
+        for k in range(m):
+            O.first_passage(3, xi[k], xf[k], tau, levels, k, 1, key)
+        tc = time.perf_counter() - tc
+        cpu = {"value": round(m / tc, 1), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+               "sample": f"the first {m} of the same candidates, one call of the single-threaded FP64 C oracle each "
+                         f"({tc:.1f} s)"}
+        log(f"[first-passage] cpu baseline {cpu}")
+    frac_first = float(np.mean(lo < (1 << (levels - 1))))
+    exhausted = (att & 0x80000000) != 0
+    props = float(np.mean(att & 0x7FFFFFFF))
+    log(f"[first-passage] {n} pairs x {levels} levels: {rate:.3e} pairs/s, {props:.2f} proposals per pair, "
+        f"{exhausted.mean():.2e} of the pairs exhausted a level, first contact in the first half of the step "
+        f"for {frac_first:.3f}")
+    print(json.dumps({
+        "metric": "first-passage refinements/s (kernel only)", "value": round(rate, 1), "unit": "pairs/s",
+        "levels_per_s": round(rate * levels, 1), "proposals_per_pair": round(props, 3),
+        "exhausted_fraction": float(exhausted.mean()), "cpu_baseline": cpu,
+        "n_gpus": 1, "pairs": n, "levels": levels, "repeats": args.steps, "ms_per_call": round(el * 1e3 / args.steps, 4),
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"3D candidates of the benchmark workload: R0 uniform in the shell 1 < R0 < r_cut/a = "
+                               f"{rmax:.3f}, R = R0 + sqrt(2 tau) z, kept with p_enc(R, R0), tau = {tau:.4g}; first "
+                               f"contact located to dt / 2^{levels}",
+                   "kernel": "k_first_passage (bisection of the Appendix, 16 lanes per pair)"}}), flush=True)
+
+
 def batched(args, I, S):
     """R independent 3D replicas stepped together (sim_batch_create, one graph replay per step)
     against the plain path: a sample of the same replicas stepped one handle at a time."""
@@ -305,6 +387,9 @@ def main():
     ap.add_argument("--workload", default="cfg_rad3d",
                     choices=["cfg_rad3d", "cfg_rad3d_dense", "cfg_mem2d", "cfg_mem2d_small_tau", "cfg_abs3d"],
                     help="synthetic workload (default: the 3D radiation workload the metric is quoted on)")
+    ap.add_argument("--first-passage", type=int, default=0, metavar="N",
+                    help="time the first-passage bisection on N candidate pairs instead of the step")
+    ap.add_argument("--fp-levels", type=int, default=20, help="bisection levels for --first-passage")
     ap.add_argument("--pair-probs", type=int, default=0, metavar="N",
                     help="only run the pair-probability micro-benchmark on N synthetic pairs and exit")
     ap.add_argument("--dim", type=int, default=3, help="workload dimension for --pair-probs (2: the membrane "
@@ -348,6 +433,9 @@ def main():
 
     if args.pair_probs:
         pair_probs(args, I, S)
+        return
+    if args.first_passage:
+        first_passage(args, I, S)
         return
     if args.batch:
         batched(args, I, S)

@@ -1164,7 +1164,10 @@ void orc_sim_diss(const orc_sim *s, orc_diss *out) { memcpy(out, s->diss, s->n_d
 /* Draws per attempt k at level l: {c0, l, step, FPT | k << 8} gives the     */
 /* normals (Box-Muller on words 0, 1 and 2, 3: z0 = r0 cos, z1 = r0 sin,     */
 /* z2 = r1 cos), {c0, l, step, FPTU | k << 8} the uniforms (word 0 accepts,  */
-/* word 1 chooses the half).                                                 */
+/* word 1 chooses the half).  A level whose MAX_ATTEMPTS proposals are all   */
+/* rejected (an interval whose encounter probability is far below their     */
+/* inverse) ends the refinement: the interval reached is returned at the     */
+/* requested resolution (its lower end) and bit 31 of *attempts is set.      */
 /* ------------------------------------------------------------------------ */
 static double fp_penc(int dim, double R, double R0, double tau, int n_terms)
 {
@@ -1197,6 +1200,7 @@ uint64_t orc_first_passage(int dim, const double *xi, const double *xf, double t
         double sd = sqrt(th), ra = fp_norm(dim, xa), rb = fp_norm(dim, xb);
         double p1 = 1.0, q = 1.0;
         double V = 0.0;
+        int accepted = 0;
         for (uint32_t k = 0; k < MAX_ATTEMPTS; ++k) {
             uint32_t cz[4] = {c0, (uint32_t)l, step, TAG_FPT | (k << 8)}, cu[4] = {c0, (uint32_t)l, step, TAG_FPTU | (k << 8)};
             double u[4], v[4], z[3];
@@ -1214,7 +1218,15 @@ uint64_t orc_first_passage(int dim, const double *xi, const double *xf, double t
             draw(cu, key, v, w);
             ++att;
             V = v[1];
-            if (v[0] < q) break;
+            if (v[0] < q) {
+                accepted = 1;
+                break;
+            }
+        }
+        if (!accepted) {  /* exhausted: keep the interval reached */
+            lo <<= (levels - l);
+            att |= 0x80000000u;
+            break;
         }
         lo *= 2;
         if (V * q < p1) {  /* first half: the end point becomes the midpoint */

@@ -103,7 +103,8 @@ enum {
  * [lo, lo + 1) * dt / 2^levels that holds the first contact of a pair whose
  * separation (units of a) went from xi to xf over tau = D_eff dt / a^2 with at
  * least one encounter; dim 1 (half line x > 1), 2 or 3.  *attempts: midpoint
- * proposals drawn. */
+ * proposals drawn, bit 31 set if a level exhausted its proposals (the
+ * refinement then stops at that level's interval). */
 uint64_t orc_first_passage(int dim, const double *xi, const double *xf, double tau, int levels, int n_terms,
                            uint32_t c0, uint32_t step, const uint32_t key[2], uint32_t *attempts);
 

@@ -23,7 +23,7 @@ __host__ __device__ inline u32 meta_slot(u32 m) { return m & SLOT_MASK; }
 // Counter word 3: tag in the low byte, rejection-attempt index above it.
 enum : u32 {
     TAG_MOVE = 1, TAG_ENC = 2, TAG_SELA = 3, TAG_SELB = 4, TAG_PROP = 5, TAG_REAC = 6,
-    TAG_UNI = 7, TAG_DPROP = 8, TAG_DIR = 9, TAG_GEM = 10
+    TAG_UNI = 7, TAG_DPROP = 8, TAG_DIR = 9, TAG_GEM = 10, TAG_FPT = 11, TAG_FPTU = 12
 };
 
 // Arithmetic of the pair probability: binary64 throughout, binary32, or

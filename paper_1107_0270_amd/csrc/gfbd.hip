@@ -118,6 +118,8 @@ struct sim {
     virtual int load(uint64_t step, const int32_t *sp, const double *pos, const uint32_t *partner) = 0;
     virtual int eval_pairs(uint64_t n, const double *R, const double *R0, double *penc, double *preac) = 0;
     virtual int eval_prop(uint64_t n, const double *R0, uint32_t step, int wave, double *Rpp, uint32_t *attempts) = 0;
+    virtual int eval_first_passage(uint64_t n, const double *xi, const double *xf, int levels, uint32_t step, uint64_t *lo,
+                                   uint32_t *attempts) = 0;
     virtual int admit(const sim_replica &, uint32_t *) { return fail(SIM_ESTATE, "not a pool"); }
     virtual int retire(uint32_t) { return fail(SIM_ESTATE, "not a pool"); }
     virtual int read_member(uint32_t, int, void *, uint64_t, uint64_t *) { return fail(SIM_ESTATE, "not a pool"); }
@@ -1031,6 +1033,18 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         return SIM_OK;
     }
 
+    int eval_first_passage(uint64_t n, const double *xi, const double *xf, int levels, uint32_t step, uint64_t *lo,
+                           uint32_t *attempts) override
+    {
+        if (DIM != 3) return fail(SIM_EUNSUPPORTED, "the first-passage bisection is built for 3D handles");
+        if (n > 0xFFFFFFFFull) return fail(SIM_EINVAL, "at most 2^32 pairs");
+        if (levels < 1 || levels > 52) return fail(SIM_EINVAL, "levels must be in [1, 52]");
+        k_first_passage<<<grid_for(n * FP_GROUP, 16384), BLOCK, 0, M.stream>>>(P, n, xi, xf, levels, step, lo, attempts);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipStreamSynchronize(M.stream));
+        return SIM_OK;
+    }
+
     template <int NC> void launch_prop(uint64_t n, const double *R0, uint32_t step, int wave, double *Rpp, uint32_t *attempts)
     {
         if (wave) k_eval_prop<DIM, NC, true><<<grid_for(64 * n, 8192), BLOCK, 0, M.stream>>>(P, n, R0, step, Rpp, attempts);
@@ -1449,6 +1463,13 @@ int sim_eval_propagator(sim_t *h, uint64_t n, const double *R0, uint32_t step, i
 {
     if (!h || !R0 || !Rpp || n == 0) { g_err = "null argument or n = 0"; return SIM_EINVAL; }
     return h->eval_prop(n, R0, step, wave, Rpp, attempts);
+}
+
+int sim_eval_first_passage(sim_t *h, uint64_t n, const double *xi, const double *xf, int32_t levels, uint32_t step,
+                           uint64_t *lo, uint32_t *attempts)
+{
+    if (!h || !xi || !xf || !lo || n == 0) { g_err = "null argument or n = 0"; return SIM_EINVAL; }
+    return h->eval_first_passage(n, xi, xf, levels, step, lo, attempts);
 }
 
 int sim_destroy(sim_t *h)

@@ -1542,6 +1542,106 @@ __global__ __launch_bounds__(BLOCK) void k_eval_prop(Params P, uint64_t n, const
 }
 
 // ---------------------------------------------------------------------------
+// First contact of a pair by bisection of the step (Appendix).  The pair's
+// separation (units of a) went from xi to xf over tau = D_eff dt / a^2 with
+// at least one encounter.  Each level halves the interval that holds the
+// first contact: the midpoint separation is drawn from the Brownian bridge
+// (eq. midPGauss: per coordinate mean (x_a + x_b)/2, variance tau_h for the
+// half interval tau_h) conditioned on the encounter in the interval, i.e. a
+// bridge proposal accepted with q = 1 - (1 - p1)(1 - p2), p1 and p2 the
+// encounter probabilities of the halves (given the midpoint they are
+// independent); the first half is kept with probability p1 / q.  Attempt k of
+// level l draws {i, l, step, FPT | k << 8} (normals, by Box-Muller on words
+// 0-1 and 2-3) and {i, l, step, FPTU | k << 8} (word 0 accepts, word 1
+// chooses).  A level whose MAX_ATTEMPTS proposals are all rejected ends the
+// refinement: the interval reached is kept (its lower end at the requested
+// resolution) and bit 31 of the attempt count is set.  3D: the closed-form
+// encounter probability.
+// The acceptance of the first level is the pair's whole encounter
+// probability, which for some candidates is small, so one lane per pair would
+// leave most lanes of a wave waiting for its slowest pair.  FP_GROUP lanes
+// share a pair instead: lane s of the group evaluates attempts s, s + G, ...
+// and the first accepted attempt in order wins, exactly as if the attempts
+// were tried one after another.
+// ---------------------------------------------------------------------------
+constexpr u32 FP_GROUP = 16;
+
+__device__ __forceinline__ double penc3_fp(double R, double R0, double tau)
+{
+    if (R <= 1.0 || R0 <= 1.0) return 1.0;
+    return penc3_args((R - 1.0) * (R0 - 1.0) / tau, (R + R0 - 1.0) / tau, R * R0 / tau);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_first_passage(Params P, uint64_t n, const double *__restrict__ xi,
+                                                          const double *__restrict__ xf, int levels, u32 step,
+                                                          uint64_t *__restrict__ lo_out, u32 *__restrict__ att_out)
+{
+#pragma clang fp contract(off)
+    const u32 lane = lane_id(), sub = lane % FP_GROUP, gbase = lane - sub;
+    const uint64_t stride = gstride() / FP_GROUP;
+    for (uint64_t i = gtid() / FP_GROUP; i < n; i += stride) {  // uniform over the group
+        double xa[3], xb[3];
+        for (int d = 0; d < 3; ++d) {
+            xa[d] = xi[3 * i + d];
+            xb[d] = xf[3 * i + d];
+        }
+        uint64_t lo = 0;
+        u32 att = 0;
+        for (int l = 0; l < levels; ++l) {
+            const double th = P.tau / (double)(2ull << l);
+            const double sd = sqrt(th);
+            const double ra = sqrt(xa[0] * xa[0] + xa[1] * xa[1] + xa[2] * xa[2]);
+            const double rb = sqrt(xb[0] * xb[0] + xb[1] * xb[1] + xb[2] * xb[2]);
+            double xm[3], p1 = 1.0, q = 1.0, V = 0.0;
+            int win = -1;
+            for (u32 k0 = 0; k0 < MAX_ATTEMPTS; k0 += FP_GROUP) {  // uniform over the group
+                const u32 k = k0 + sub;
+                const uint4 rz = philox((u32)i, (u32)l, step, TAG_FPT | (k << 8), P.key);
+                const uint4 ru = philox((u32)i, (u32)l, step, TAG_FPTU | (k << 8), P.key);
+                const double r0 = sqrt(-2.0 * log(u01(rz.x))), r1 = sqrt(-2.0 * log(u01(rz.z)));
+                double s0, c0;
+                sincos((2.0 * PI_D) * u01(rz.y), &s0, &c0);
+                const double z[3] = {r0 * c0, r0 * s0, r1 * cos((2.0 * PI_D) * u01(rz.w))};
+                for (int d = 0; d < 3; ++d) xm[d] = 0.5 * (xa[d] + xb[d]) + sd * z[d];
+                const double rm = sqrt(xm[0] * xm[0] + xm[1] * xm[1] + xm[2] * xm[2]);
+                p1 = penc3_fp(rm, ra, th);
+                const double p2 = penc3_fp(rb, rm, th);
+                q = 1.0 - (1.0 - p1) * (1.0 - p2);
+                V = u01(ru.y);
+                const u64 m = __ballot(u01(ru.x) < q);
+                const u64 gm = (m >> gbase) & (FP_GROUP == 64 ? ~0ull : ((1ull << (FP_GROUP % 64)) - 1ull));
+                if (gm) {  // uniform over the group
+                    win = __ffsll((unsigned long long)gm) - 1;
+                    att += k0 + (u32)win + 1u;
+                    break;
+                }
+            }
+            if (win < 0) {  // exhausted: keep the interval reached
+                lo <<= (levels - l);
+                att = (att + MAX_ATTEMPTS) | 0x80000000u;
+                break;
+            }
+            const int src = (int)gbase + win;
+            for (int d = 0; d < 3; ++d) xm[d] = __shfl(xm[d], src, 64);
+            p1 = __shfl(p1, src, 64);
+            q = __shfl(q, src, 64);
+            V = __shfl(V, src, 64);
+            lo *= 2;
+            if (V * q < p1) {
+                for (int d = 0; d < 3; ++d) xb[d] = xm[d];
+            } else {
+                for (int d = 0; d < 3; ++d) xa[d] = xm[d];
+                lo += 1;
+            }
+        }
+        if (sub == 0) {
+            lo_out[i] = lo;
+            if (att_out) att_out[i] = att;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Reads and debug captures.
 // ---------------------------------------------------------------------------
 template <int DIM, class T>

@@ -145,6 +145,8 @@ def lib():
     L.sim_eval_pairs.restype = C.c_int
     L.sim_eval_propagator.argtypes = [vp, u64, vp, u32, C.c_int, vp, vp]
     L.sim_eval_propagator.restype = C.c_int
+    L.sim_eval_first_passage.argtypes = [vp, u64, vp, vp, C.c_int32, u32, vp, vp]
+    L.sim_eval_first_passage.restype = C.c_int
     L.sim_destroy.argtypes = [vp]
     L.sim_destroy.restype = C.c_int
     L.sim_last_error.argtypes = [vp]
@@ -365,6 +367,30 @@ class Sim:
         finally:
             for b in (b_r0, b_r, b_a):
                 b.free()
+
+    def eval_first_passage(self, xi, xf, levels, step=0):
+        """First contact of pairs by bisection (sim_eval_first_passage): xi, xf are (n, 3)
+        separations in units of a before and after the step; returns (lo, attempts), the contact
+        lying in [lo, lo + 1) * dt / 2^levels."""
+        xi = np.ascontiguousarray(xi, dtype=np.float64).reshape(-1, 3)
+        xf = np.ascontiguousarray(xf, dtype=np.float64).reshape(-1, 3)
+        if xi.shape != xf.shape:
+            raise ValueError("xi and xf differ in shape")
+        n = xi.shape[0]
+        b_i, b_f, b_lo, b_a = DeviceBuffer(24 * n), DeviceBuffer(24 * n), DeviceBuffer(8 * n), DeviceBuffer(4 * n)
+        try:
+            b_i.upload(xi)
+            b_f.upload(xf)
+            self._check(lib().sim_eval_first_passage(self._h, n, b_i.ptr, b_f.ptr, int(levels), int(step), b_lo.ptr,
+                                                     b_a.ptr))
+            return b_lo.download(np.empty(n, np.uint64)), b_a.download(np.empty(n, np.uint32))
+        finally:
+            for b in (b_i, b_f, b_lo, b_a):
+                b.free()
+
+    def eval_first_passage_device(self, n, xi, xf, levels, step, lo, attempts):
+        """sim_eval_first_passage on caller-owned device pointers (ints; attempts may be None)."""
+        self._check(lib().sim_eval_first_passage(self._h, int(n), xi, xf, int(levels), int(step), lo, attempts))
 
     def eval_pairs_device(self, n, R, R0, penc, preac):
         """sim_eval_pairs on caller-owned device pointers (ints or None)."""

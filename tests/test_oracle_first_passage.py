@@ -139,3 +139,14 @@ def test_deeper_levels_refine_the_same_interval():
         lo8, _ = O.first_passage(3, [1.1, 0.2, 0.0], [1.0, 0.6, 0.2], 0.5, 8, c, 1, KEY)
         lo12, _ = O.first_passage(3, [1.1, 0.2, 0.0], [1.0, 0.6, 0.2], 0.5, 12, c, 1, KEY)
         assert lo12 >> 4 == lo8
+
+
+def test_exhausted_level_ends_the_refinement():
+    # an interval with no realistic encounter (p_enc ~ e^-841): every proposal of the first
+    # level is rejected; the refinement stops there with the flag set
+    lo, att = O.first_passage(3, [3.9, 0.0, 0.0], [3.9, 0.0, 0.0], 0.01, 10, 0, 0, KEY)
+    assert lo == 0 and att == (4096 | 0x80000000)
+    # a pair that exhausts a later level keeps the interval it reached, at the full resolution
+    for c in range(200):
+        lo, att = O.first_passage(1, [1.0 + 0.02], [1.0 + 0.02], 1e-3, 16, c, 0, KEY)
+        assert att & 0x80000000 == 0 or lo % 2 == 0
