@@ -158,15 +158,17 @@ def pair_probs(args, I, S):
 
 
 def first_passage(args, I, S):
-    """First contact of N candidate pairs of the benchmark workload located by bisection
+    """First contact of N candidate pairs of the benchmark workload (3D, or the 2D membrane
+    workload at tau = 0.04 with --dim 2) located by bisection
     (sim_eval_first_passage, the paper's Appendix) to dt / 2^levels, on device-resident arrays.
     Candidates: a pre-step separation uniform in the shell 1 < R0 < r_cut/a, a free step of
     sqrt(2 tau) z, kept with the encounter probability that the step's own device function gives
     (sim_eval_pairs), as the step keeps its candidates."""
-    cfg = I.workload("cfg_rad3d")
+    dim = args.dim
+    cfg = I.workload("cfg_rad3d" if dim == 3 else "cfg_mem2d_small_tau")
     sp = np.array([0, 1], np.int32)
-    pos = np.array([[0.25] * 3, [0.75] * 3])
-    h = S.Sim(dim=3, box=cfg["box"], dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
+    pos = np.array([[0.25] * dim, [0.75] * dim])
+    h = S.Sim(dim=dim, box=cfg["box"], dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
               k_off=0.0, precision=S.PREC_FP64, seed=0, species=sp, pos=pos)
     der = h.derived()
     tau, rmax, n, levels = der["tau"], der["rcut"] / der["a"], args.first_passage, args.fp_levels
@@ -174,10 +176,12 @@ def first_passage(args, I, S):
     xi_all, xf_all, have = [], [], 0
     while have < n:
         m = 4 * n
-        d = rng.standard_normal((m, 3))
+        d = rng.standard_normal((m, dim))
         d /= np.linalg.norm(d, axis=1, keepdims=True)
-        xi = d * ((1.0 + (rmax ** 3 - 1.0) * rng.random(m)) ** (1.0 / 3.0))[:, None]
-        xf = xi + np.sqrt(2.0 * tau) * rng.standard_normal((m, 3))
+        xi = d * ((1.0 + (rmax ** dim - 1.0) * rng.random(m)) ** (1.0 / dim))[:, None]
+        xf = xi + np.sqrt(2.0 * tau) * rng.standard_normal((m, dim))
+        if dim == 2:  # the boundary takes three components per pair
+            xi, xf = np.pad(xi, ((0, 0), (0, 1))), np.pad(xf, ((0, 0), (0, 1)))
         R, R0 = np.ascontiguousarray(np.linalg.norm(xf, axis=1)), np.ascontiguousarray(np.linalg.norm(xi, axis=1))
         bR, bR0, bp = S.DeviceBuffer(8 * m), S.DeviceBuffer(8 * m), S.DeviceBuffer(8 * m)
         bR.upload(R)
@@ -215,7 +219,7 @@ def first_passage(args, I, S):
         key = (0, 0)  # seed 0, replica 0
         tc = time.perf_counter()
         for k in range(m):
-            O.first_passage(3, xi[k], xf[k], tau, levels, k, 1, key)
+            O.first_passage(dim, xi[k][:dim], xf[k][:dim], tau, levels, k, 1, key)
         tc = time.perf_counter() - tc
         cpu = {"value": round(m / tc, 1), "unit": "pairs/s", "cores": 1, "kind": "oracle",
                "sample": f"the first {m} of the same candidates, one call of the single-threaded FP64 C oracle each "
@@ -233,7 +237,7 @@ def first_passage(args, I, S):
         "exhausted_fraction": float(exhausted.mean()), "cpu_baseline": cpu,
         "n_gpus": 1, "pairs": n, "levels": levels, "repeats": args.steps, "ms_per_call": round(el * 1e3 / args.steps, 4),
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"3D candidates of the benchmark workload: R0 uniform in the shell 1 < R0 < r_cut/a = "
+        "config": {"workload": f"{dim}D candidates of the benchmark workload: R0 uniform in the shell 1 < R0 < r_cut/a = "
                                f"{rmax:.3f}, R = R0 + sqrt(2 tau) z, kept with p_enc(R, R0), tau = {tau:.4g}; first "
                                f"contact located to dt / 2^{levels}",
                    "kernel": "k_first_passage (bisection of the Appendix, 16 lanes per pair)"}}), flush=True)

@@ -266,13 +266,15 @@ int sim_eval_pairs(sim_t *h, uint64_t n, const double *R, const double *R0, doub
 int sim_eval_propagator(sim_t *h, uint64_t n, const double *R0, uint32_t step, int wave, double *Rpp, uint32_t *attempts);
 
 /* Locates the first contact of n pairs within one step by bisection (the paper's Appendix).
- * Pair i's separation vector went from xi[3i..3i+2] to xf[3i..3i+2] (units of a = sigma) over the
+ * Pair i's separation vector went from xi[3i..3i+2] to xf[3i..3i+2] (units of a = sigma; a 2D
+ * handle reads the first two components) over the
  * handle's dt (tau = D_eff dt / a^2), with at least one encounter in that step (a candidate of
  * the step is one).  Each of `levels` halvings draws the separation at the midpoint of the
  * interval from the Brownian bridge (eq. midPGauss: mean the end points' average, variance
  * tau_h per coordinate for the half interval tau_h), conditioned on the encounter known to lie
  * in the interval: a proposal is accepted with q = 1 - (1 - p1)(1 - p2), p1 and p2 the encounter
- * probabilities (Sec. 2.2.1 in the radial 3D form of Secs. 2.2.4 and 4.1) of the two halves;
+ * probabilities (Sec. 2.2.1 in the radial form of Sec. 2.2.4: the closed form of Sec. 4.1 in 3D,
+ * the expansion of Sec. 4.2 in 2D, evaluated at each half interval's tau) of the two halves;
  * the first half is kept with probability p1 / q.  lo[i] receives the index of the final
  * interval: the first contact lies in [lo, lo + 1) * dt / 2^levels.  attempts[i] (may be NULL)
  * receives the midpoint proposals drawn (at most 4096 per level).  A level whose 4096 proposals
@@ -283,7 +285,8 @@ int sim_eval_propagator(sim_t *h, uint64_t n, const double *R0, uint32_t step, i
  * (acceptance and choice) with the handle's key.  xi, xf (3n doubles), lo (n uint64) and
  * attempts (n uint32) are DEVICE pointers owned by the caller.  Runs on the handle's stream and
  * returns when done.  SIM_EINVAL for NULL xi, xf or lo, n = 0, n > 2^32 or levels outside
- * [1, 52]; SIM_EUNSUPPORTED for a 2D handle; SIM_EDEVICE if a HIP call fails. */
+ * [1, 52]; SIM_EUNSUPPORTED for a 2D handle with the exact functions (green2d) or an expansion
+ * order other than 12; SIM_EDEVICE if a HIP call fails. */
 int sim_eval_first_passage(sim_t *h, uint64_t n, const double *xi, const double *xf, int32_t levels, uint32_t step,
                            uint64_t *lo, uint32_t *attempts);
 

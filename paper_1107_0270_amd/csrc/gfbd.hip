@@ -1036,10 +1036,13 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     int eval_first_passage(uint64_t n, const double *xi, const double *xf, int levels, uint32_t step, uint64_t *lo,
                            uint32_t *attempts) override
     {
-        if (DIM != 3) return fail(SIM_EUNSUPPORTED, "the first-passage bisection is built for 3D handles");
+        if (DIM == 2 && (P.x2_enc || P.n_terms != 12))
+            return fail(SIM_EUNSUPPORTED, "the 2D first-passage bisection takes the expansion of order 12");
         if (n > 0xFFFFFFFFull) return fail(SIM_EINVAL, "at most 2^32 pairs");
         if (levels < 1 || levels > 52) return fail(SIM_EINVAL, "levels must be in [1, 52]");
-        k_first_passage<<<grid_for(n * FP_GROUP, 16384), BLOCK, 0, M.stream>>>(P, n, xi, xf, levels, step, lo, attempts);
+        const u32 g = grid_for(n * FP_GROUP, 16384);
+        if constexpr (DIM == 3) k_first_passage<3, 0><<<g, BLOCK, 0, M.stream>>>(P, n, xi, xf, levels, step, lo, attempts);
+        else k_first_passage<2, 12><<<g, BLOCK, 0, M.stream>>>(P, n, xi, xf, levels, step, lo, attempts);
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipStreamSynchronize(M.stream));
         return SIM_OK;

@@ -121,21 +121,28 @@ __device__ __forceinline__ double gamma_k(const double *Q, const double *Pc, int
 
 // 2D encounter probability -g_abs,bc / g_free with eq. smallTEabs:
 //   sqrt(tau/(R R0)) e^{-(R-1)(R0-1)/tau} [pi^{-1/2} + (1/2) sum gamma^abs_k T_k] / i0e(R R0/2tau).
-template <int NC> __device__ inline double penc2_n(const Params &P, double R, double R0)
+// At a given tau (sqrt_tau and inv_tau its root and inverse): the step uses the
+// handle's, the first-passage bisection those of its half intervals.
+template <int NC>
+__device__ inline double penc2_at(const Params &P, double R, double R0, double tau, double sqrt_tau, double inv_tau)
 {
     const int n = NC > 0 ? NC : P.n_terms;
     const double *a0 = P.g2c, *Qa = P.g2c + (MAXTERMS + 1);
     double Pc[Order<NC>::M + 1], T[Order<NC>::M + 1];
     p_series<NC>(a0, R, R0, n, Pc);
-    const double x = (R + R0 - 2.0) / (2.0 * P.sqrt_tau);
-    t_terms<NC>(x, 2.0 * P.sqrt_tau, n, T);
+    const double x = (R + R0 - 2.0) / (2.0 * sqrt_tau);
+    t_terms<NC>(x, 2.0 * sqrt_tau, n, T);
     double S = 1.0 / SQRTPI_D;
 #pragma unroll
     for (int k = 1; k <= Order<NC>::M; ++k) {
         if (k > n) break;
         S += 0.5 * gamma_k(Qa, Pc, k) * T[k];
     }
-    return sqrt(P.tau / (R * R0)) * exp(-(R - 1.0) * (R0 - 1.0) * P.inv_tau) * S / i0e_d(R * R0 * 0.5 * P.inv_tau);
+    return sqrt(tau / (R * R0)) * exp(-(R - 1.0) * (R0 - 1.0) * inv_tau) * S / i0e_d(R * R0 * 0.5 * inv_tau);
+}
+template <int NC> __device__ inline double penc2_n(const Params &P, double R, double R0)
+{
+    return penc2_at<NC>(P, R, R0, P.tau, P.sqrt_tau, P.inv_tau);
 }
 
 // 2D reaction probability: free parts and the common factor cancel,

@@ -1556,7 +1556,7 @@ __global__ __launch_bounds__(BLOCK) void k_eval_prop(Params P, uint64_t n, const
 // chooses).  A level whose MAX_ATTEMPTS proposals are all rejected ends the
 // refinement: the interval reached is kept (its lower end at the requested
 // resolution) and bit 31 of the attempt count is set.  3D: the closed-form
-// encounter probability.
+// encounter probability; 2D: the expansion of compile-time order NC.
 // The acceptance of the first level is the pair's whole encounter
 // probability, which for some candidates is small, so one lane per pair would
 // leave most lanes of a wave waiting for its slowest pair.  FP_GROUP lanes
@@ -1572,6 +1572,14 @@ __device__ __forceinline__ double penc3_fp(double R, double R0, double tau)
     return penc3_args((R - 1.0) * (R0 - 1.0) / tau, (R + R0 - 1.0) / tau, R * R0 / tau);
 }
 
+template <int DIM, int NC> __device__ __forceinline__ double penc_fp(const Params &P, double R, double R0, double tau)
+{
+    if constexpr (DIM == 3) return penc3_fp(R, R0, tau);
+    if (R <= 1.0 || R0 <= 1.0) return 1.0;
+    return penc2_at<NC>(P, R, R0, tau, sqrt(tau), 1.0 / tau);
+}
+
+template <int DIM, int NC>
 __global__ __launch_bounds__(BLOCK) void k_first_passage(Params P, uint64_t n, const double *__restrict__ xi,
                                                           const double *__restrict__ xf, int levels, u32 step,
                                                           uint64_t *__restrict__ lo_out, u32 *__restrict__ att_out)
@@ -1582,16 +1590,16 @@ __global__ __launch_bounds__(BLOCK) void k_first_passage(Params P, uint64_t n, c
     for (uint64_t i = gtid() / FP_GROUP; i < n; i += stride) {  // uniform over the group
         double xa[3], xb[3];
         for (int d = 0; d < 3; ++d) {
-            xa[d] = xi[3 * i + d];
-            xb[d] = xf[3 * i + d];
+            xa[d] = d < DIM ? xi[3 * i + d] : 0.0;
+            xb[d] = d < DIM ? xf[3 * i + d] : 0.0;
         }
         uint64_t lo = 0;
         u32 att = 0;
         for (int l = 0; l < levels; ++l) {
             const double th = P.tau / (double)(2ull << l);
             const double sd = sqrt(th);
-            const double ra = sqrt(xa[0] * xa[0] + xa[1] * xa[1] + xa[2] * xa[2]);
-            const double rb = sqrt(xb[0] * xb[0] + xb[1] * xb[1] + xb[2] * xb[2]);
+            const double ra = sqrt(DIM == 3 ? xa[0] * xa[0] + xa[1] * xa[1] + xa[2] * xa[2] : xa[0] * xa[0] + xa[1] * xa[1]);
+            const double rb = sqrt(DIM == 3 ? xb[0] * xb[0] + xb[1] * xb[1] + xb[2] * xb[2] : xb[0] * xb[0] + xb[1] * xb[1]);
             double xm[3], p1 = 1.0, q = 1.0, V = 0.0;
             int win = -1;
             for (u32 k0 = 0; k0 < MAX_ATTEMPTS; k0 += FP_GROUP) {  // uniform over the group
@@ -1602,10 +1610,10 @@ __global__ __launch_bounds__(BLOCK) void k_first_passage(Params P, uint64_t n, c
                 double s0, c0;
                 sincos((2.0 * PI_D) * u01(rz.y), &s0, &c0);
                 const double z[3] = {r0 * c0, r0 * s0, r1 * cos((2.0 * PI_D) * u01(rz.w))};
-                for (int d = 0; d < 3; ++d) xm[d] = 0.5 * (xa[d] + xb[d]) + sd * z[d];
-                const double rm = sqrt(xm[0] * xm[0] + xm[1] * xm[1] + xm[2] * xm[2]);
-                p1 = penc3_fp(rm, ra, th);
-                const double p2 = penc3_fp(rb, rm, th);
+                for (int d = 0; d < 3; ++d) xm[d] = d < DIM ? 0.5 * (xa[d] + xb[d]) + sd * z[d] : 0.0;
+                const double rm = sqrt(DIM == 3 ? xm[0] * xm[0] + xm[1] * xm[1] + xm[2] * xm[2] : xm[0] * xm[0] + xm[1] * xm[1]);
+                p1 = penc_fp<DIM, NC>(P, rm, ra, th);
+                const double p2 = penc_fp<DIM, NC>(P, rb, rm, th);
                 q = 1.0 - (1.0 - p1) * (1.0 - p2);
                 V = u01(ru.y);
                 const u64 m = __ballot(u01(ru.x) < q);
