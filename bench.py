@@ -415,6 +415,8 @@ def main():
                     help="2D radial functions: small-time expansions, or exact (tables by quadrature)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the cell edge and pair-search kernel by timing candidates on the workload first")
+    ap.add_argument("--scale", type=float, default=1.0,
+                    help="particle count and box volume times this factor (same density; the metric is quoted at 1)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -453,7 +455,9 @@ def main():
         cfg["precision"] = {"fp64": S.PREC_FP64, "fp32": S.PREC_FP32, "fp32nc": S.PREC_FP32_FP64NC}[args.precision]
     dim = cfg["dim"]
     t0 = time.time()
-    sp, pos, box, red = I.state_for(cfg, seed=0)
+    sp, pos, box, red = I.state_for(cfg, seed=0, scale=args.scale)
+    if args.scale != 1.0:  # the same density in a box scaled with the particle count
+        cfg = dict(cfg, n_a=int(np.sum(sp == S.SP_A)), n_b=int(np.sum(sp == S.SP_B)), box=box)
     log(f"[bench] state: {len(sp)} particles, {red} redrawn overlaps, {time.time() - t0:.1f}s")
     search = {"auto": S.PAIRS_AUTO, "bricks": S.PAIRS_BRICKS, "direct": S.PAIRS_DIRECT}[args.pair_search]
 
@@ -535,7 +539,7 @@ def main():
     dom = max(tot, key=tot.get) if any(tot.values()) else None
     # the rocprofv3 counts were taken on the default run of this workload
     profiled = (args.workload == "cfg_rad3d" and args.precision == "workload" and args.pair_search == "auto"
-                and args.cell == 0.0 and not args.autotune)
+                and args.cell == 0.0 and not args.autotune and args.scale == 1.0)
     roof = None
     if dom is not None and per[dom] > 0:
         nb = algorithmic_bytes(dom, n_live, 0.5 * (c0["A"] + c1["A"]), 0.5 * (c0["B"] + c1["B"]), n_keys)

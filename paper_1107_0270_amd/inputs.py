@@ -95,8 +95,10 @@ def state_for(cfg: dict, seed: int = 0, scale: float = 1.0):
     volume together so the density stays that of the workload."""
     n_a = max(1, int(round(cfg["n_a"] * scale)))
     n_b = max(1, int(round(cfg["n_b"] * scale)))
-    box = cfg["box"] * scale ** (1.0 / cfg["dim"])
     f32 = cfg["precision"] != PREC_FP64
+    box = cfg["box"] * scale ** (1.0 / cfg["dim"])
+    if f32:  # a binary32 state needs a binary32 box edge
+        box = float(np.float32(box))
     sp, pos, red = uniform_state(n_a, n_b, box=box, dim=cfg["dim"], sigma=cfg["sigma"], seed=seed, f32=f32)
     return sp, pos, box, red
 
