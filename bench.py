@@ -46,28 +46,28 @@ def algorithmic_bytes(kernel, n_live, n_a, n_b, n_keys):
 # commands are in profiles/rad3d_step_traffic.md.  Valid only for the kernel sources they were taken
 # on (hash below): after any change to them the field is reported as null.
 MEASURED_TRAFFIC = {
-    "src_hash": "94396032b6ff9c25",
+    "src_hash": "9d9e311fac32f04e",
     "scale_fetch": 1.9998, "scale_write": 1.0,
     "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
-        "move": (9818.3, 31395.1),
+        "move": (9885.4, 31395.4),
         "scan": (5809.6 + 5824.3, 11.3 + 17376.1),
-        "scatter": (16994.6, 29451.1),
-        "pairs": (9595.6, 119.4),
-        "eval": (1035.6, 95.7),
-        "select_a": (165.9, 50.1),
-        "select_b": (182.1, 4.8),
-        "events": (336.8 + 2.8, 52.1 + 0.9),
+        "scatter": (16997.2, 29459.7),
+        "pairs": (9595.9, 119.5),
+        "eval": (1027.4, 95.8),
+        "select_a": (162.6, 49.9),
+        "select_b": (183.5, 4.8),
+        "events": (318.6 + 2.8, 52.1 + 0.9),
     },
     # stage -> VALU wave-instructions per launch (SQ_INSTS_VALU summed over the stage's kernels)
     "valu": {
-        "move": 9487370,
+        "move": 8175192,
         "scan": 144800 + 271542,
         "scatter": 723660,
-        "pairs": 4398294,
-        "eval": 233636,
-        "select_a": 18411,
-        "select_b": 159710,
-        "events": 1175648 + 21,
+        "pairs": 4398352,
+        "eval": 221479,
+        "select_a": 18394,
+        "select_b": 159693,
+        "events": 1175478 + 21,
     },
 }
 
