@@ -383,7 +383,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-steps", type=int, default=20, help="oracle steps timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=60, help="oracle steps timed for the CPU baseline (0 = skip)")
     ap.add_argument("--no-timing", action="store_true", help="time without per-kernel events")
     ap.add_argument("--pair-search", choices=["auto", "bricks", "direct"], default="auto",
                     help="pair-search kernel (auto = the library's choice)")
