@@ -118,3 +118,23 @@ def ensemble(n_rep: int = 4096, seed: int = 0, n_min: float = 1e3, n_max: float 
         sp, pos, _ = uniform_state(n // 2, n - n // 2, box=box, dim=3, sigma=0.005, seed=1000 + r, f32=f32)
         reps.append(dict(species=sp, pos=pos, box=box, kappa=float(kappas[r]), replica=r))
     return reps
+
+
+def lattice_targets(m: int, spacing: float, n_b: int, sigma: float, seed: int = 0):
+    """m^3 targets (species 0) at ((i, j, k) + 1/4) * spacing and n_b B's (species 1) uniform in
+    the periodic box of edge m * spacing, each B closer than sigma to a target redrawn."""
+    L = m * spacing
+    g = (np.arange(m) + 0.25) * spacing
+    a = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    b = rng.random((n_b, 3)) * L
+    for _ in range(100):
+        d = b - (np.floor(b / spacing - 0.25 + 0.5) + 0.25) * spacing  # to the nearest lattice point
+        bad = np.flatnonzero(np.sum(d * d, axis=1) < sigma * sigma)
+        if bad.size == 0:
+            break
+        b[bad] = rng.random((bad.size, 3)) * L
+    b = b.astype(np.float32).astype(np.float64)
+    b[b >= L] = 0.0
+    sp = np.concatenate([np.zeros(len(a), np.int32), np.ones(n_b, np.int32)])
+    return sp, np.concatenate([a, b]), L
