@@ -157,7 +157,8 @@ typedef struct {
  * alone.  Afterwards the handle behaves like one system of
  * sum(n) slots: replica r owns slots [n_0 + ... + n_{r-1}, + n_r) in every read, and partner
  * indices in sim_read / sim_load_state are global.  SIM_READ_DERIVED and SIM_READ_GRID
- * describe replica 0; sim_eval_pairs and sim_eval_propagator use replica 0's parameters.
+ * describe replica 0; sim_eval_pairs, sim_eval_propagator and sim_eval_first_passage use replica 0's
+ * parameters.
  * pos of replica r holds n * dim values.  Errors as sim_create (reported for the first replica
  * that fails). */
 int sim_batch_create(const sim_config *cfg, uint32_t n_rep, const sim_replica *reps, sim_t **out);
