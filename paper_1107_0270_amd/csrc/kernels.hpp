@@ -1115,9 +1115,70 @@ __global__ __launch_bounds__(BLOCK) void k_pair_eval(Params P, const Rec<T> *__r
 // The cumulative rule of Sec. 3 (Details) over one chain, members in
 // ascending order of `key` (a slot): the first member k with
 // U * sum(p) <= p_1 + ... + p_k.  `key_of(e)` and `p_of(e)` read member e.
+// A chain of up to CHAIN_REGS members is read once into registers and put in
+// key order by a sorting network (Batcher's odd-even merge, 19 comparators;
+// static indices only, so nothing goes to per-lane scratch): one pass of
+// dependent loads instead of one per member and rank.  The sums run in the
+// same order either way.
+constexpr u32 CHAIN_REGS = 8;
+
+template <class V> __device__ __forceinline__ void chain_cas(u32 *key, V *p, u32 *ent, int i, int j)
+{
+    if (key[j] < key[i]) {
+        const u32 k = key[i], e = ent[i];
+        const V v = p[i];
+        key[i] = key[j];
+        p[i] = p[j];
+        ent[i] = ent[j];
+        key[j] = k;
+        p[j] = v;
+        ent[j] = e;
+    }
+}
+
 template <class K, class Pf>
 __device__ inline u32 choose_in_chain(u32 head, const u32 *__restrict__ next, u32 count, double U, K &&key_of, Pf &&p_of)
 {
+    if (count <= CHAIN_REGS) {
+        u32 key[CHAIN_REGS], ent[CHAIN_REGS];
+        double p[CHAIN_REGS];
+        u32 e = head;
+#pragma unroll
+        for (int j = 0; j < (int)CHAIN_REGS; ++j) {
+            if ((u32)j < count && e != NOSLOT) {
+                key[j] = key_of(e);
+                p[j] = p_of(e);
+                ent[j] = e;
+                e = next[e];
+            } else {
+                key[j] = NOSLOT;
+                p[j] = 0.0;
+                ent[j] = NOSLOT;
+            }
+        }
+        chain_cas(key, p, ent, 0, 1); chain_cas(key, p, ent, 2, 3); chain_cas(key, p, ent, 4, 5); chain_cas(key, p, ent, 6, 7);
+        chain_cas(key, p, ent, 0, 2); chain_cas(key, p, ent, 1, 3); chain_cas(key, p, ent, 4, 6); chain_cas(key, p, ent, 5, 7);
+        chain_cas(key, p, ent, 1, 2); chain_cas(key, p, ent, 5, 6);
+        chain_cas(key, p, ent, 0, 4); chain_cas(key, p, ent, 1, 5); chain_cas(key, p, ent, 2, 6); chain_cas(key, p, ent, 3, 7);
+        chain_cas(key, p, ent, 2, 4); chain_cas(key, p, ent, 3, 5);
+        chain_cas(key, p, ent, 1, 2); chain_cas(key, p, ent, 3, 4); chain_cas(key, p, ent, 5, 6);
+        double T_ = 0.0;
+#pragma unroll
+        for (int j = 0; j < (int)CHAIN_REGS; ++j)
+            if (key[j] != NOSLOT) T_ += p[j];
+        const double tgt = U * T_;
+        double acc = 0.0;
+        u32 win = NOSLOT;
+        bool done = false;
+#pragma unroll
+        for (int j = 0; j < (int)CHAIN_REGS; ++j)
+            if (!done && key[j] != NOSLOT) {
+                acc += p[j];
+                win = ent[j];
+                done = tgt <= acc;
+            }
+        return win;
+    }
     double T_ = 0.0;
     u32 prev = 0;
     bool first = true;
