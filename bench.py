@@ -434,7 +434,7 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": x.numel() * 4, "launches": 5}), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not supported", "n_gpus": args.gpus}))
         sys.exit(2)
 
     from paper_1107_0270_amd import inputs as I

@@ -54,7 +54,7 @@ enum {
     SIM_ENOMEM = -2,      /* device or host allocation failed */
     SIM_EDEVICE = -3,     /* a HIP call failed; the handle should be destroyed */
     SIM_ESTATE = -4,      /* call not valid in the handle's current state */
-    SIM_EUNSUPPORTED = -5,/* valid input outside what this build supports */
+    SIM_EUNSUPPORTED = -5,/* valid input outside what this library supports */
     SIM_ECAPACITY = -6    /* a per-step buffer overflowed; the step's results are invalid */
 };
 
