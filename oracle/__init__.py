@@ -90,6 +90,11 @@ def lib():
         "orc_x2_switch": (d, [d]),
         "orc_first_passage": (u64, [i, P(d), P(d), d, i, i, u32, u32, P(u32), P(u32)]),
         "orc_rcut": (d, [i, i, d, d, d, d, d]),
+        "orc_angle3_terms": (i, [d, d, d]),
+        "orc_bessel_half": (None, [i, d, P(d), P(d)]),
+        "orc_angle3_coef": (None, [i, d, d, d, i, P(d)]),
+        "orc_angle3_cdf": (d, [P(d), i, d]),
+        "orc_sample_angle3": (d, [d, d, d, d]),
         "orc_sim_create": (vp, [P(Params), u64, vp, vp, vp]),
         "orc_sim_destroy": (None, [vp]),
         "orc_sim_step": (None, [vp]),
@@ -266,6 +271,40 @@ def first_passage(dim, xi, xf, tau, levels, c0, step, key, n_terms=12):
     lo = lib().orc_first_passage(int(dim), _dp(a), _dp(b), float(tau), int(levels), int(n_terms),
                                  int(c0) & 0xFFFFFFFF, int(step) & 0xFFFFFFFF, k, C.byref(att))
     return int(lo), att.value
+
+
+def angle3_terms(R, R0, tau):
+    """Legendre terms kept by the 3D angular propagator."""
+    return lib().orc_angle3_terms(float(R), float(R0), float(tau))
+
+
+def bessel_half(kmax, z):
+    """(J, Y): J[k] = J_{k-1/2}(z), Y[k] = Y_{k-1/2}(z) for k = 0 .. kmax."""
+    J = np.zeros(kmax + 1)
+    Y = np.zeros(kmax + 1)
+    lib().orc_bessel_half(int(kmax), float(z), _dp(J), _dp(Y))
+    return J, Y
+
+
+def angle3_coef(kind, R, R0, tau, N=None):
+    """Legendre coefficients w_0..w_N of G_ref - G_abs (kind 0) or of the free
+    Green's function (kind 1), eq. genericGF3D in units a = 1, D_eff = 1."""
+    if N is None:
+        N = angle3_terms(R, R0, tau)
+    w = np.zeros(N + 1)
+    lib().orc_angle3_coef(int(kind), float(R), float(R0), float(tau), int(N), _dp(w))
+    return w
+
+
+def angle3_cdf(w, c):
+    """Distribution function of cos Theta given R from the coefficients w."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    return lib().orc_angle3_cdf(_dp(w), len(w) - 1, float(c))
+
+
+def sample_angle3(R, R0, tau, u):
+    """cos Theta drawn from J (G_ref - G_abs) given R by inversion at u."""
+    return lib().orc_sample_angle3(float(R), float(R0), float(tau), float(u))
 
 
 def rcut(dim, bc, a, Deff, dt, kappa_a, eps):

@@ -1239,3 +1239,134 @@ uint64_t orc_first_passage(int dim, const double *xi, const double *xf, double t
     if (attempts) *attempts = att;
     return lo;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Angular propagator in 3D (Sec. 3, Details: the angle between the pair's   */
+/* separations before and after the step is drawn from J(G_ref - G_abs),    */
+/* J = 2 pi sin(Theta) r^2, given the radius already drawn).                */
+/*                                                                          */
+/* With eq. genericGF3D for h -> 0 (reflecting) and h -> infinity           */
+/* (absorbing), units a = 1 and D_eff = 1:                                   */
+/*   G_ref - G_abs = sum_n (2n+1) P_n(cos Theta) w_n / (4 pi sqrt(R R0)),    */
+/*   w_n = int_0^inf e^{-tau x^2} [F^r(R,x) F^r(R0,x) - F^a(R,x) F^a(R0,x)] x dx,*/
+/* F^{r,a} the functions F_{n+1/2} of that equation.  Writing F as          */
+/* [J(Rx) A - Y(Rx) B] / sqrt(A^2 + B^2) with A = (2h+1) Y(x) - 2x Y'(x),    */
+/* B = (2h+1) J(x) - 2x J'(x) and C'_nu = C_{nu-1} - (nu/x) C_nu:           */
+/*   reflecting: A = (2n+2) Y_nu(x) - 2x Y_{nu-1}(x), B likewise with J;    */
+/*   absorbing (divide by 2h+1, h -> inf): A = Y_nu(x), B = J_nu(x).        */
+/* Integrating over the sphere, the Legendre orthogonality leaves w_0:      */
+/*   w_0 = 4 pi sqrt(R R0) (g_ref - g_abs)(R | R0), and the density of       */
+/* c = cos Theta given R is sum_n (2n+1) P_n(c) w_n / (2 w_0), whose         */
+/* integral from -1 (int P_n = (P_{n+1} - P_{n-1}) / (2n+1), n >= 1) is      */
+/*   F(c) = [1 + c + sum_{n>=1} (w_n / w_0)(P_{n+1}(c) - P_{n-1}(c))] / 2.   */
+/* The draw is the root of F(c) = u, located by bisection.                  */
+/*                                                                          */
+/* Bessel functions of half-integer order (Sec. 4.1, eq. 3termBessel):      */
+/* J by the downward recurrence from a start above both the highest order   */
+/* and the turning point (Miller's method), normalised to the elementary    */
+/* J_{1/2} and J_{-1/2}; Y by the upward recurrence from Y_{-1/2} and        */
+/* Y_{1/2}.  The integral over x: 16-point Gauss-Legendre panels of equal   */
+/* width, at most min(1, 2 pi / f) with f = R + R0 - 1 (the fastest          */
+/* oscillation of the integrand is at R + R0 - 2), over [0, sqrt(50/tau)].  */
+/* Terms n = 0 .. N, N = min(160, 8 + ceil(sqrt(45 R R0 / tau))): the       */
+/* coefficients fall like e^{-n(n+1) tau / (R R0)} (angular diffusion at    */
+/* radius about sqrt(R R0)).  A node stops adding orders once |Y_nu(x)|      */
+/* exceeds 2^600: there the products are below 1e-150.                      */
+/* kind 1 replaces the bracket by J_nu(Rx) J_nu(R0x) (the free-space terms,   */
+/* a check of the Bessel functions and the rule against Weber's integral)   */
+/* and takes f = R + R0 + 1.                                                */
+/* ------------------------------------------------------------------------ */
+#define ANG_NCAP 160
+
+int orc_angle3_terms(double R, double R0, double tau)
+{
+    int n = 8 + (int)ceil(sqrt(45.0 * R * R0 / tau));
+    return n < ANG_NCAP ? n : ANG_NCAP;
+}
+
+/* J[k] = J_{k-1/2}(z), Y[k] = Y_{k-1/2}(z), k = 0 .. kmax (z > 0). */
+void orc_bessel_half(int kmax, double z, double *J, double *Y)
+{
+    double zc = ceil(z);
+    int m = (kmax > (int)zc + (int)ceil(12.0 * cbrt(z)) ? kmax : (int)zc + (int)ceil(12.0 * cbrt(z))) + 20;
+    double *t = (double *)calloc((size_t)m + 2, sizeof(double));
+    t[m + 1] = 0.0;
+    t[m] = 1.0;
+    for (int k = m; k >= 1; --k) {  /* C_{nu-1} = (2 nu / z) C_nu - C_{nu+1}, nu = k - 1/2 */
+        t[k - 1] = (2.0 * k - 1.0) / z * t[k] - t[k + 1];
+        if (fabs(t[k - 1]) > 1e250)
+            for (int j = k - 1; j <= m + 1; ++j) t[j] *= 1e-250;
+    }
+    double s = sqrt(2.0 / (PI * z)), sz = sin(z), cz = cos(z);
+    double M = fmax(fabs(t[0]), fabs(t[1])), a0 = t[0] / M, a1 = t[1] / M;
+    double lam = s * (sz * a1 + cz * a0) / (a1 * a1 + a0 * a0) / M;
+    for (int k = 0; k <= kmax; ++k) J[k] = lam * t[k];
+    free(t);
+    Y[0] = s * sz;
+    if (kmax >= 1) Y[1] = -s * cz;
+    for (int k = 1; k < kmax; ++k) Y[k + 1] = (2.0 * k - 1.0) / z * Y[k] - Y[k - 1];
+}
+
+void orc_angle3_coef(int kind, double R, double R0, double tau, int N, double *w)
+{
+    gl_init();
+    double X = sqrt(50.0 / tau), f = R + R0 + (kind == 1 ? 1.0 : -1.0);
+    double hmax = fmin(1.0, 2.0 * PI / f);
+    int P = (int)ceil(X / hmax);
+    double h = X / P;
+    double *Jx = (double *)malloc(sizeof(double) * (size_t)(N + 2) * 6);
+    double *Yx = Jx + (N + 2), *Jr = Yx + (N + 2), *Yr = Jr + (N + 2), *Jq = Yr + (N + 2), *Yq = Jq + (N + 2);
+    for (int n = 0; n <= N; ++n) w[n] = 0.0;
+    for (int p = 0; p < P; ++p) {
+        for (int i = 0; i < GLN; ++i) {
+            double x = h * (p + 0.5 + 0.5 * gl_x[i]);
+            double g = 0.5 * h * gl_w[i] * exp(-tau * x * x) * x;
+            orc_bessel_half(N + 1, x, Jx, Yx);
+            orc_bessel_half(N + 1, R * x, Jr, Yr);
+            orc_bessel_half(N + 1, R0 * x, Jq, Yq);
+            for (int n = 0; n <= N; ++n) {
+                int k = n + 1;  /* nu = n + 1/2 */
+                if (kind == 1) {
+                    w[n] += g * Jr[k] * Jq[k];
+                    continue;
+                }
+                if (fabs(Yx[k]) > 0x1p600) break;
+                double Ar = (2.0 * n + 2.0) * Yx[k] - 2.0 * x * Yx[k - 1];
+                double Br = (2.0 * n + 2.0) * Jx[k] - 2.0 * x * Jx[k - 1];
+                double Aa = Yx[k], Ba = Jx[k];
+                double nr = sqrt(Ar * Ar + Br * Br), na = sqrt(Aa * Aa + Ba * Ba);
+                double frR = (Jr[k] * Ar - Yr[k] * Br) / nr, frQ = (Jq[k] * Ar - Yq[k] * Br) / nr;
+                double faR = (Jr[k] * Aa - Yr[k] * Ba) / na, faQ = (Jq[k] * Aa - Yq[k] * Ba) / na;
+                w[n] += g * (frR * frQ - faR * faQ);
+            }
+        }
+    }
+    free(Jx);
+}
+
+double orc_angle3_cdf(const double *w, int N, double c)
+{
+    double s = 1.0 + c, pm = 1.0, p = c;  /* P_{n-1}, P_n at n = 1 */
+    for (int n = 1; n <= N; ++n) {
+        double pn1 = ((2.0 * n + 1.0) * c * p - n * pm) / (n + 1.0);
+        s += w[n] / w[0] * (pn1 - pm);
+        pm = p;
+        p = pn1;
+    }
+    return 0.5 * s;
+}
+
+double orc_sample_angle3(double R, double R0, double tau, double u)
+{
+    int N = orc_angle3_terms(R, R0, tau);
+    double *w = (double *)malloc(sizeof(double) * (size_t)(N + 1));
+    orc_angle3_coef(0, R, R0, tau, N, w);
+    double lo = -1.0, hi = 1.0;
+    for (int it = 0; it < 200 && hi - lo > 4e-16; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (orc_angle3_cdf(w, N, mid) < u) lo = mid;
+        else hi = mid;
+    }
+    free(w);
+    return 0.5 * (lo + hi);
+}

@@ -108,6 +108,18 @@ enum {
 uint64_t orc_first_passage(int dim, const double *xi, const double *xf, double tau, int levels, int n_terms,
                            uint32_t c0, uint32_t step, const uint32_t key[2], uint32_t *attempts);
 
+/* Angular propagator in 3D (Sec. 3, Details; eq. genericGF3D): the number of
+ * Legendre terms, the half-integer Bessel functions J[k] = J_{k-1/2}(z),
+ * Y[k] = Y_{k-1/2}(z) (k = 0 .. kmax), the coefficients w[0..N] of
+ * G_ref - G_abs (kind 0) or of the free Green's function (kind 1), the
+ * conditional distribution function of cos Theta given R, and one draw of
+ * cos Theta by its inverse at u. */
+int orc_angle3_terms(double R, double R0, double tau);
+void orc_bessel_half(int kmax, double z, double *J, double *Y);
+void orc_angle3_coef(int kind, double R, double R0, double tau, int N, double *w);
+double orc_angle3_cdf(const double *w, int N, double c);
+double orc_sample_angle3(double R, double R0, double tau, double u);
+
 typedef struct orc_sim orc_sim;
 
 orc_sim *orc_sim_create(const orc_params *p, uint64_t n, const int32_t *species, const double *pos,
