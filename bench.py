@@ -243,6 +243,63 @@ def first_passage(args, I, S):
                    "kernel": "k_first_passage (bisection of the Appendix, 16 lanes per pair)"}}), flush=True)
 
 
+def angle(args, I, S):
+    """Angles of N propagated pairs of the benchmark workload (sim_eval_angle: cos Theta from
+    J (G_ref - G_abs) given the radii, Sec. 3, Details, eq. genericGF3D), on device-resident
+    arrays.  Pairs: a pre-step separation uniform in the shell 1 < R0 < r_cut/a, the new radius
+    drawn from the radial propagator by the step's own sampler (sim_eval_propagator), a uniform u."""
+    cfg = I.workload("cfg_rad3d")
+    sp = np.array([0, 1], np.int32)
+    pos = np.array([[0.25] * 3, [0.75] * 3])
+    h = S.Sim(dim=3, box=cfg["box"], dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
+              k_off=0.0, precision=S.PREC_FP64, seed=0, species=sp, pos=pos)
+    der = h.derived()
+    tau, rmax, n = der["tau"], der["rcut"] / der["a"], args.angle
+    rng = np.random.default_rng(0)
+    R0 = np.ascontiguousarray((1.0 + (rmax ** 3 - 1.0) * rng.random(n)) ** (1.0 / 3.0))
+    u = rng.random(n)
+    bR, bR0, bu, bc = (S.DeviceBuffer(8 * n) for _ in range(4))
+    bR0.upload(R0)
+    bu.upload(u)
+    h.eval_propagator_device(n, bR0.ptr, 1, 0, bR.ptr, None)
+    call = (n, bR.ptr, bR0.ptr, bu.ptr, bc.ptr)
+    h.eval_angle_device(*call)  # warm-up
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        h.eval_angle_device(*call)
+    el = time.perf_counter() - t0
+    R = bR.download(np.empty(n))
+    c = bc.download(np.empty(n))
+    for b in (bR, bR0, bu, bc):
+        b.free()
+    h.close()
+    rate = n * args.steps / el
+    cpu = None
+    if args.cpu_steps > 0:
+        import oracle as O
+
+        m = min(n, 20000)
+        tc = time.perf_counter()
+        k = 0
+        while k < m and time.perf_counter() - tc < 20.0:
+            O.sample_angle3(R[k], R0[k], tau, u[k])
+            k += 1
+        tc = time.perf_counter() - tc
+        cpu = {"value": round(k / tc, 1), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+               "sample": f"the first {k} of the same pairs, one call of the single-threaded FP64 C oracle each "
+                         f"({tc:.1f} s)"}
+        log(f"[angle] cpu baseline {cpu}")
+    log(f"[angle] {n} pairs: {rate:.3e} pairs/s, mean cos Theta {c.mean():.4f}, mean R'' {R.mean():.4f}")
+    print(json.dumps({
+        "metric": "propagated-pair angles/s (kernel only)", "value": round(rate, 1), "unit": "pairs/s",
+        "mean_cos_theta": round(float(c.mean()), 6), "cpu_baseline": cpu,
+        "n_gpus": 1, "pairs": n, "repeats": args.steps, "ms_per_call": round(el * 1e3 / args.steps, 4),
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"3D propagated pairs of the benchmark workload: R0 uniform in the shell 1 < R0 < "
+                               f"r_cut/a = {rmax:.3f}, R'' from the radial propagator, tau = {tau:.4g}",
+                   "kernel": "k_angle3 (Legendre series of G_ref - G_abs, one wave per pair)"}}), flush=True)
+
+
 def batched(args, I, S):
     """R independent 3D replicas stepped together (sim_batch_create, one graph replay per step)
     against the plain path: a sample of the same replicas stepped one handle at a time."""
@@ -394,6 +451,8 @@ def main():
     ap.add_argument("--first-passage", type=int, default=0, metavar="N",
                     help="time the first-passage bisection on N candidate pairs instead of the step")
     ap.add_argument("--fp-levels", type=int, default=20, help="bisection levels for --first-passage")
+    ap.add_argument("--angle", type=int, default=0, metavar="N",
+                    help="time the 3D angular propagator on N propagated pairs instead of the step")
     ap.add_argument("--pair-probs", type=int, default=0, metavar="N",
                     help="only run the pair-probability micro-benchmark on N synthetic pairs and exit")
     ap.add_argument("--dim", type=int, default=3, help="workload dimension for --pair-probs (2: the membrane "
@@ -445,6 +504,9 @@ def main():
         return
     if args.first_passage:
         first_passage(args, I, S)
+        return
+    if args.angle:
+        angle(args, I, S)
         return
     if args.batch:
         batched(args, I, S)

@@ -1358,6 +1358,9 @@ double orc_angle3_cdf(const double *w, int N, double c)
 
 double orc_sample_angle3(double R, double R0, double tau, double u)
 {
+    if (!(R + R0 - 2.0 <= 40.0 * sqrt(tau))) return NAN;  /* beyond any encounter (e^{-400}), or not a number */
+    R = fmax(R, 1.0);  /* a separation below contact is taken at contact */
+    R0 = fmax(R0, 1.0);
     int N = orc_angle3_terms(R, R0, tau);
     double *w = (double *)malloc(sizeof(double) * (size_t)(N + 1));
     orc_angle3_coef(0, R, R0, tau, N, w);

@@ -147,6 +147,8 @@ def lib():
     L.sim_eval_propagator.restype = C.c_int
     L.sim_eval_first_passage.argtypes = [vp, u64, vp, vp, C.c_int32, u32, vp, vp]
     L.sim_eval_first_passage.restype = C.c_int
+    L.sim_eval_angle.argtypes = [vp, u64, vp, vp, vp, vp]
+    L.sim_eval_angle.restype = C.c_int
     L.sim_destroy.argtypes = [vp]
     L.sim_destroy.restype = C.c_int
     L.sim_last_error.argtypes = [vp]
@@ -368,6 +370,10 @@ class Sim:
             for b in (b_r0, b_r, b_a):
                 b.free()
 
+    def eval_propagator_device(self, n, R0, step, wave, Rpp, attempts):
+        """sim_eval_propagator on caller-owned device pointers (ints; attempts may be None)."""
+        self._check(lib().sim_eval_propagator(self._h, int(n), R0, int(step), int(bool(wave)), Rpp, attempts))
+
     def eval_first_passage(self, xi, xf, levels, step=0):
         """First contact of pairs by bisection (sim_eval_first_passage): xi, xf are (n, 3)
         separations in units of a before and after the step; returns (lo, attempts), the contact
@@ -391,6 +397,29 @@ class Sim:
     def eval_first_passage_device(self, n, xi, xf, levels, step, lo, attempts):
         """sim_eval_first_passage on caller-owned device pointers (ints; attempts may be None)."""
         self._check(lib().sim_eval_first_passage(self._h, int(n), xi, xf, int(levels), int(step), lo, attempts))
+
+    def eval_angle(self, R, R0, u):
+        """cos Theta of propagated pairs (sim_eval_angle): R, R0 the new and old separations in
+        units of a, u the uniforms of the draws (3D handles)."""
+        R = np.ascontiguousarray(R, dtype=np.float64).ravel()
+        R0 = np.ascontiguousarray(R0, dtype=np.float64).ravel()
+        u = np.ascontiguousarray(u, dtype=np.float64).ravel()
+        if not (R.size == R0.size == u.size):
+            raise ValueError("R, R0 and u differ in length")
+        n = R.size
+        bufs = [DeviceBuffer(8 * n) for _ in range(4)]
+        try:
+            for b, a in zip(bufs, (R, R0, u)):
+                b.upload(a)
+            self._check(lib().sim_eval_angle(self._h, n, bufs[0].ptr, bufs[1].ptr, bufs[2].ptr, bufs[3].ptr))
+            return bufs[3].download(np.empty(n))
+        finally:
+            for b in bufs:
+                b.free()
+
+    def eval_angle_device(self, n, R, R0, u, cos_theta):
+        """sim_eval_angle on caller-owned device pointers (ints)."""
+        self._check(lib().sim_eval_angle(self._h, int(n), R, R0, u, cos_theta))
 
     def eval_pairs_device(self, n, R, R0, penc, preac):
         """sim_eval_pairs on caller-owned device pointers (ints or None)."""

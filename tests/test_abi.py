@@ -23,7 +23,7 @@ def _declared():
 def test_header_declares_the_boundary():
     assert _declared() == sorted(["sim_create", "sim_batch_create", "sim_pool_create", "sim_pool_admit",
                                   "sim_pool_retire", "sim_pool_read", "sim_step", "sim_read", "sim_load_state",
-                                  "sim_eval_pairs", "sim_eval_propagator", "sim_eval_first_passage", "sim_destroy",
+                                  "sim_eval_pairs", "sim_eval_propagator", "sim_eval_first_passage", "sim_eval_angle", "sim_destroy",
                                   "sim_last_error"])
 
 
@@ -115,6 +115,7 @@ def test_eval_pairs_rejects_null_arguments_on_the_host():
     assert S.lib().sim_eval_pairs(None, 0, None, None, None, None) == S.SIM_EINVAL
     assert S.lib().sim_eval_propagator(None, 0, None, 0, 1, None, None) == S.SIM_EINVAL
     assert S.lib().sim_eval_first_passage(None, 0, None, None, 8, 0, None, None) == S.SIM_EINVAL
+    assert S.lib().sim_eval_angle(None, 0, None, None, None, None) == S.SIM_EINVAL
 
 
 def _rep(n=4, box=1.0, kappa=0.1):
