@@ -104,6 +104,38 @@ def valu_issue(stage, launch_ms):
             "frac": round(at_peak / launch_ms, 4), "peak_wave_instr_per_s": VALU_WAVE_INSTR_PER_S}
 
 
+# k_angle3 on the --angle workload (10^6 pairs, tau = 0.8): fp64 operations and VALU wave-
+# instructions per launch from rocprofv3 (SQ_INSTS_VALU_{ADD,MUL,FMA}_F64 x 64 lanes, an FMA
+# counting two; SQ_INSTS_VALU), profiles/angle3_kernels.md.  Valid for the source it was taken on.
+ANGLE_COUNTERS = {
+    "src_hash": "77752e75850f63b7",
+    "pairs": 1000000,
+    "f64_flop": 5.994743e+11,  # 64 x (ADD 999569215 + MUL 2386729574 + 2 x FMA 2990243945)
+    "valu": 13138793499,
+}
+FP64_VECTOR_PEAK = 78.6e12  # MI355X dense fp64 vector FLOP/s
+
+
+def angle_src_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1107_0270_amd", "csrc", "angle3.hpp"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def angle_roofline(n, launch_ms):
+    """The angle kernel against the fp64 vector peak (its work is plain fp64 arithmetic: Bessel
+    recurrences, quadrature sums, Legendre sums), with the VALU issue fraction beside it."""
+    t = ANGLE_COUNTERS
+    if n != t["pairs"] or angle_src_hash() != t["src_hash"]:
+        return None
+    achieved = t["f64_flop"] / (launch_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": round(achieved * 1e12 / FP64_VECTOR_PEAK, 4), "traffic": None,
+            "flop_per_launch": t["f64_flop"], "flop_source": "rocprofv3 fp64 VALU counters (executed, not algorithmic)",
+            "valu_issue_frac": round(t["valu"] / VALU_WAVE_INSTR_PER_S / (launch_ms * 1e-3), 4)}
+
+
 def describe(cfg):
     bc = {0: "absorbing", 1: "reflecting", 2: "radiation"}[cfg["bc"]]
     rev = "reversible A+B<->C" if cfg["k_off"] > 0 else "irreversible A+B->C"
@@ -267,7 +299,7 @@ def angle(args, I, S):
     t0 = time.perf_counter()
     for _ in range(args.steps):
         h.eval_angle_device(*call)
-    el = time.perf_counter() - t0
+    el = time.perf_counter() - t0  # each call returns when its launch is done
     R = bR.download(np.empty(n))
     c = bc.download(np.empty(n))
     for b in (bR, bR0, bu, bc):
@@ -292,7 +324,8 @@ def angle(args, I, S):
     log(f"[angle] {n} pairs: {rate:.3e} pairs/s, mean cos Theta {c.mean():.4f}, mean R'' {R.mean():.4f}")
     print(json.dumps({
         "metric": "propagated-pair angles/s (kernel only)", "value": round(rate, 1), "unit": "pairs/s",
-        "mean_cos_theta": round(float(c.mean()), 6), "cpu_baseline": cpu,
+        "mean_cos_theta": round(float(c.mean()), 6), "roofline": angle_roofline(n, el * 1e3 / args.steps),
+        "cpu_baseline": cpu,
         "n_gpus": 1, "pairs": n, "repeats": args.steps, "ms_per_call": round(el * 1e3 / args.steps, 4),
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"3D propagated pairs of the benchmark workload: R0 uniform in the shell 1 < R0 < "

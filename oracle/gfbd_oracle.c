@@ -1271,7 +1271,8 @@ uint64_t orc_first_passage(int dim, const double *xi, const double *xf, double t
 /* Terms n = 0 .. N, N = min(160, 8 + ceil(sqrt(45 R R0 / tau))): the       */
 /* coefficients fall like e^{-n(n+1) tau / (R R0)} (angular diffusion at    */
 /* radius about sqrt(R R0)).  A node stops adding orders once |Y_nu(x)|      */
-/* exceeds 2^600: there the products are below 1e-150.                      */
+/* exceeds 2^500: there the products are below 1e-220 (and A^2 + B^2 stays  */
+/* finite).                                                                 */
 /* kind 1 replaces the bracket by J_nu(Rx) J_nu(R0x) (the free-space terms,   */
 /* a check of the Bessel functions and the rule against Weber's integral)   */
 /* and takes f = R + R0 + 1.                                                */
@@ -1330,7 +1331,7 @@ void orc_angle3_coef(int kind, double R, double R0, double tau, int N, double *w
                     w[n] += g * Jr[k] * Jq[k];
                     continue;
                 }
-                if (fabs(Yx[k]) > 0x1p600) break;
+                if (fabs(Yx[k]) > 0x1p500) break;
                 double Ar = (2.0 * n + 2.0) * Yx[k] - 2.0 * x * Yx[k - 1];
                 double Br = (2.0 * n + 2.0) * Jx[k] - 2.0 * x * Jx[k - 1];
                 double Aa = Yx[k], Ba = Jx[k];

@@ -19,10 +19,10 @@
 //   - x integral: 16-point Gauss-Legendre panels of equal width, at most
 //     min(1, 2 pi / (R + R0 - 1)), over [0, sqrt(50 / tau)];
 //   - Bessel functions of half-integer order (eq. 3termBessel): J by the downward
-//     recurrence from above both N and the turning point, normalised to the
+//     recurrence from above both N and the turning point (start below), normalised to the
 //     elementary J_{1/2}, J_{-1/2}; Y by the upward recurrence from Y_{-1/2}, Y_{1/2};
-//     a node stops adding orders once |Y_nu(x)| exceeds 2^600 (its products are
-//     then below 1e-150);
+//     a node stops adding orders once |Y_nu(x)| exceeds 2^500 (its products are
+//     then below 1e-220, and A^2 + B^2 stays finite);
 //   - pairs with R + R0 - 2 > 40 sqrt(tau) (beyond any encounter) or not a number give NaN;
 //   - inversion: nine rounds of a 65-way search over [-1, 1] (one point per lane),
 //     a final interval of 2 / 65^9 < 1.1e-16.
@@ -52,13 +52,15 @@ __device__ __forceinline__ double wave_allsum(double v)
     return v;
 }
 
-// J_{k-1/2}(z) for k = 0 .. kmax into t[], for three arguments at once (the downward
-// recurrence C_{nu-1} = (2 nu / z) C_nu - C_{nu+1}, nu = k - 1/2, from k = m down).
-__device__ __noinline__ void ang_miller3(int kmax, const double z[3], double (*t)[ANG_NCAP + 2])
+// J_{k-1/2}(z) for k = 0 .. kmax, for three arguments at once (the downward recurrence
+// C_{nu-1} = (2 nu / z) C_nu - C_{nu+1}, nu = k - 1/2, from k = m down): t[j][k] times lam[j].
+__device__ __noinline__ void ang_miller3(int kmax, const double z[3], double (*t)[ANG_NCAP + 2], double lam[3])
 {
+    // start: J_m / |Y_m| at m = z + t falls like e^{-0.94 t^{3/2} / sqrt(z)} (beyond the turning
+    // point), below 1e-18 for t >= 8 z^{1/3}; and at least 8 orders above kmax
     const double zm = fmax(z[0], fmax(z[1], z[2]));
-    const int zc = (int)ceil(zm) + (int)ceil(12.0 * cbrt(zm));
-    const int m = (kmax > zc ? kmax : zc) + 20;
+    const int zc = (int)ceil(zm + 8.0 * cbrt(zm));
+    const int m = (kmax > zc ? kmax : zc) + 8;
     double a[3], b[3], inv[3];  // a = C_{k}, b = C_{k+1}
     for (int j = 0; j < 3; ++j) {
         a[j] = 1.0;
@@ -85,17 +87,25 @@ __device__ __noinline__ void ang_miller3(int kmax, const double z[3], double (*t
         sincos(z[j], &s0, &c0);
         const double s = sqrt(2.0 / (PI_D * z[j]));
         const double M = fmax(fabs(t[j][0]), fabs(t[j][1])), a0 = t[j][0] / M, a1 = t[j][1] / M;
-        const double lam = s * (s0 * a1 + c0 * a0) / (a1 * a1 + a0 * a0) / M;
-        for (int q = 0; q <= kmax; ++q) t[j][q] *= lam;
+        lam[j] = s * (s0 * a1 + c0 * a0) / (a1 * a1 + a0 * a0) / M;
     }
 }
+
+struct InvTable {
+    double v[ANG_NCAP + 2];
+    constexpr InvTable() : v()
+    {
+        for (int n = 0; n < ANG_NCAP + 2; ++n) v[n] = 1.0 / (n + 1.0);
+    }
+};
+__constant__ constexpr InvTable ANG_INV{};  // 1 / (n + 1)
 
 __device__ __forceinline__ double ang_cdf(const double *W, int N, double c)
 {
     double s = 1.0 + c, pm = 1.0, p = c;
     const double inv0 = 1.0 / W[0];
     for (int n = 1; n <= N; ++n) {
-        const double pn1 = ((2.0 * n + 1.0) * c * p - n * pm) / (n + 1.0);
+        const double pn1 = ((2.0 * n + 1.0) * c * p - n * pm) * ANG_INV.v[n];
         s += W[n] * inv0 * (pn1 - pm);
         pm = p;
         p = pn1;
@@ -131,34 +141,39 @@ __global__ __launch_bounds__(BLOCK) void k_angle3(double tau, uint64_t n, const 
             const int qq = live ? q : 0;
             const double x = h * ((qq >> 4) + 0.5 + 0.5 * gl.x[qq & 15]);
             const double g = live ? 0.5 * h * gl.w[qq & 15] * exp(-tau * x * x) * x : 0.0;
-            double t[3][ANG_NCAP + 2];
+            double t[3][ANG_NCAP + 2], lam[3];
             const double z[3] = {x, R * x, R0 * x};
-            ang_miller3(N + 1, z, t);
-            double ym[3], y0[3];  // Y_{nu-1}, Y_nu
+            ang_miller3(N + 1, z, t, lam);
+            double ym[3], y0[3], iz[3];  // Y_{nu-1}, Y_nu, 1/z
             for (int j = 0; j < 3; ++j) {
                 double s0, c0;
                 sincos(z[j], &s0, &c0);
                 const double s = sqrt(2.0 / (PI_D * z[j]));
                 ym[j] = s * s0;   // Y_{-1/2}
                 y0[j] = -s * c0;  // Y_{1/2}
+                iz[j] = 1.0 / z[j];
             }
             bool dead = !live;
+            double jm = lam[0] * t[0][0];  // J_{nu-1}(x)
             for (int nn = 0; nn <= N; ++nn) {  // uniform over the wave
                 const int k = nn + 1;
-                if (fabs(y0[0]) > 0x1p600) dead = true;
+                if (fabs(y0[0]) > 0x1p500) dead = true;
                 double term = 0.0;
+                const double jx = lam[0] * t[0][k];
                 if (!dead) {
+                    // F(R) F(R0) = (J(Rx) A - Y(Rx) B)(J(R0x) A - Y(R0x) B) / (A^2 + B^2)
+                    const double jr = lam[1] * t[1][k], jq = lam[2] * t[2][k];
                     const double Ar = (2.0 * nn + 2.0) * y0[0] - 2.0 * x * ym[0];
-                    const double Br = (2.0 * nn + 2.0) * t[0][k] - 2.0 * x * t[0][k - 1];
-                    const double Aa = y0[0], Ba = t[0][k];
-                    const double ir = 1.0 / sqrt(Ar * Ar + Br * Br), ia = 1.0 / sqrt(Aa * Aa + Ba * Ba);
-                    const double frR = (t[1][k] * Ar - y0[1] * Br) * ir, frQ = (t[2][k] * Ar - y0[2] * Br) * ir;
-                    const double faR = (t[1][k] * Aa - y0[1] * Ba) * ia, faQ = (t[2][k] * Aa - y0[2] * Ba) * ia;
-                    term = g * (frR * frQ - faR * faQ);
+                    const double Br = (2.0 * nn + 2.0) * jx - 2.0 * x * jm;
+                    const double Aa = y0[0], Ba = jx;
+                    const double pr = (jr * Ar - y0[1] * Br) / (Ar * Ar + Br * Br) * (jq * Ar - y0[2] * Br);
+                    const double pa = (jr * Aa - y0[1] * Ba) / (Aa * Aa + Ba * Ba) * (jq * Aa - y0[2] * Ba);
+                    term = g * (pr - pa);
                 }
+                jm = jx;
                 W[nn] += wave_allsum(term);  // every lane writes the same value and reads its own
                 for (int j = 0; j < 3; ++j) {  // Y_{nu+1} = (2 nu / z) Y_nu - Y_{nu-1}
-                    const double yn = (2.0 * k - 1.0) / z[j] * y0[j] - ym[j];
+                    const double yn = (2.0 * k - 1.0) * iz[j] * y0[j] - ym[j];
                     ym[j] = y0[j];
                     y0[j] = yn;
                 }
