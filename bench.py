@@ -46,28 +46,28 @@ def algorithmic_bytes(kernel, n_live, n_a, n_b, n_keys):
 # commands are in profiles/rad3d_step_traffic.md.  Valid only for the kernel sources they were taken
 # on (hash below): after any change to them the field is reported as null.
 MEASURED_TRAFFIC = {
-    "src_hash": "89a7e0b8a320c327",
+    "src_hash": "76b82afc80ae06ee",
     "scale_fetch": 1.9998, "scale_write": 1.0,
     "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
-        "move": (9872.4, 31395.4),
-        "scan": (5809.6 + 5824.0, 11.3 + 17376.3),
-        "scatter": (16985.6, 29456.0),
-        "pairs": (9762.4, 299.3),
-        "eval": (3276.2, 199.3),
-        "select_a": (251.0, 60.3),
-        "select_b": (257.0, 12.0),
-        "events": (349.5 + 2.8, 52.9 + 0.9),
+        "move": (9910.1, 31395.4),
+        "scan": (5809.6 + 5818.8, 11.3 + 17376.1),
+        "scatter": (16994.2, 29459.9),
+        "pairs": (9757.2, 299.3),
+        "eval": (3275.5, 199.9),
+        "select_a": (251.2, 60.3),
+        "select_b": (267.1, 12.1),
+        "events": (336.7 + 2.8, 53.0 + 0.9),
     },
     # stage -> VALU wave-instructions per launch (SQ_INSTS_VALU summed over the stage's kernels)
     "valu": {
-        "move": 8175112,
+        "move": 8175113,
         "scan": 144800 + 271542,
-        "scatter": 723654,
-        "pairs": 5250101,
-        "eval": 636237,
-        "select_a": 70064,
-        "select_b": 214678,
-        "events": 1204458 + 21,
+        "scatter": 723656,
+        "pairs": 5249986,
+        "eval": 636169,
+        "select_a": 69942,
+        "select_b": 214555,
+        "events": 1204430 + 21,
     },
 }
 
