@@ -95,6 +95,10 @@ def lib():
         "orc_angle3_coef": (None, [i, d, d, d, i, P(d)]),
         "orc_angle3_cdf": (d, [P(d), i, d]),
         "orc_sample_angle3": (d, [d, d, d, d]),
+        "orc_bessel_int": (None, [i, d, P(d), P(d)]),
+        "orc_angle2_coef": (None, [i, d, d, d, i, P(d)]),
+        "orc_angle2_cdf": (d, [P(d), i, d]),
+        "orc_sample_angle2": (d, [d, d, d, d]),
         "orc_sim_create": (vp, [P(Params), u64, vp, vp, vp]),
         "orc_sim_destroy": (None, [vp]),
         "orc_sim_step": (None, [vp]),
@@ -305,6 +309,35 @@ def angle3_cdf(w, c):
 def sample_angle3(R, R0, tau, u):
     """cos Theta drawn from J (G_ref - G_abs) given R by inversion at u."""
     return lib().orc_sample_angle3(float(R), float(R0), float(tau), float(u))
+
+
+def bessel_int(kmax, z):
+    """(J, Y): J[k] = J_{k-1}(z), Y[k] = Y_{k-1}(z) for k = 0 .. kmax."""
+    J = np.zeros(kmax + 1)
+    Y = np.zeros(kmax + 1)
+    lib().orc_bessel_int(int(kmax), float(z), _dp(J), _dp(Y))
+    return J, Y
+
+
+def angle2_coef(kind, R, R0, tau, N=None):
+    """Coefficients w_0..w_N of the cos(n theta) series of G_ref - G_abs (kind 0) or of the
+    free Green's function (kind 1), eq. genericGF in units a = 1, D_eff = 1."""
+    if N is None:
+        N = angle3_terms(R, R0, tau)
+    w = np.zeros(N + 1)
+    lib().orc_angle2_coef(int(kind), float(R), float(R0), float(tau), int(N), _dp(w))
+    return w
+
+
+def angle2_cdf(w, t):
+    """Distribution function of |theta| in [0, pi] given R from the coefficients w."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    return lib().orc_angle2_cdf(_dp(w), len(w) - 1, float(t))
+
+
+def sample_angle2(R, R0, tau, u):
+    """|theta| drawn from r (G_ref - G_abs) given R by inversion at u."""
+    return lib().orc_sample_angle2(float(R), float(R0), float(tau), float(u))
 
 
 def rcut(dim, bc, a, Deff, dt, kappa_a, eps):

@@ -1374,3 +1374,124 @@ double orc_sample_angle3(double R, double R0, double tau, double u)
     free(w);
     return 0.5 * (lo + hi);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Angular propagator in 2D (Sec. 3, Details, with J = r; eq. genericGF).    */
+/*                                                                          */
+/* With h -> 0 (reflecting) and h -> infinity (absorbing), units a = 1 and  */
+/* D_eff = 1:                                                               */
+/*   G_ref - G_abs = [w_0 + 2 sum_{n>=1} w_n cos(n theta)] / (2 pi),          */
+/*   w_n = int_0^inf e^{-tau x^2} [C^r_n(R,x) C^r_n(R0,x) - C^a_n C^a_n] x dx,*/
+/* (C_{-n} C_{-n} = C_n C_n), C_n = [J_n(Rx) A - Y_n(Rx) B] / sqrt(A^2+B^2)  */
+/* from eq. fRad with x C'_n = x C_{n-1} - n C_n:                           */
+/*   reflecting: A = x Y_{n-1}(x) - n Y_n(x), B likewise with J;            */
+/*   absorbing (divide by -h, h -> inf): A = Y_n(x), B = J_n(x).            */
+/* The angular integral leaves w_0 = 2 pi (g_ref - g_abs)(R | R0) (radial    */
+/* functions of the exact 2D section above).  |theta| in [0, pi] given R    */
+/* has the distribution function                                            */
+/*   F(t) = [w_0 t + 2 sum_{n>=1} w_n sin(n t) / n] / (pi w_0),               */
+/* and the draw is its root at u; the side (sign of theta) is the caller's. */
+/*                                                                          */
+/* Bessel functions of integer order (eq. 3termBessel): J by Miller's       */
+/* downward recurrence normalised to the C library's j0, j1; Y upward from  */
+/* its y0, y1.  The x integral: 32 Gauss-Legendre panels of ratio 2 on      */
+/* [2^-32, 1] (Y_0 has a logarithm at x = 0), then panels of equal width at */
+/* most min(1, 2 pi / (R + R0 - 1)) up to sqrt(50/tau).  Terms and order    */
+/* cut-off as in 3D.  kind 1 gives the free-space terms J_n(Rx) J_n(R0x).    */
+/* ------------------------------------------------------------------------ */
+
+/* J[k] = J_{k-1}(z), Y[k] = Y_{k-1}(z), k = 0 .. kmax (z > 0): index 0 is order -1. */
+void orc_bessel_int(int kmax, double z, double *J, double *Y)
+{
+    int nmax = kmax - 1;  /* highest order */
+    double zc = ceil(z);
+    int m = (nmax > (int)zc + (int)ceil(12.0 * cbrt(z)) ? nmax : (int)zc + (int)ceil(12.0 * cbrt(z))) + 20;
+    double *t = (double *)calloc((size_t)m + 2, sizeof(double));  /* t[n] ~ J_n, n = 0 .. m + 1 */
+    t[m + 1] = 0.0;
+    t[m] = 1.0;
+    for (int n = m; n >= 1; --n) {  /* J_{n-1} = (2n / z) J_n - J_{n+1} */
+        t[n - 1] = 2.0 * n / z * t[n] - t[n + 1];
+        if (fabs(t[n - 1]) > 1e250)
+            for (int j = n - 1; j <= m + 1; ++j) t[j] *= 1e-250;
+    }
+    double a0 = j0(z), a1 = j1(z);
+    double M = fmax(fabs(t[0]), fabs(t[1])), b0 = t[0] / M, b1 = t[1] / M;
+    double lam = (a0 * b0 + a1 * b1) / (b0 * b0 + b1 * b1) / M;
+    for (int n = 0; n <= nmax; ++n) J[n + 1] = lam * t[n];
+    J[0] = -J[2];
+    free(t);
+    Y[1] = y0(z);
+    if (kmax >= 2) Y[2] = y1(z);
+    Y[0] = -y1(z);
+    for (int n = 1; n < nmax; ++n) Y[n + 2] = 2.0 * n / z * Y[n + 1] - Y[n];
+}
+
+void orc_angle2_coef(int kind, double R, double R0, double tau, int N, double *w)
+{
+    gl_init();
+    double X = sqrt(50.0 / tau), x1 = X < 1.0 ? X : 1.0, f = R + R0 + (kind == 1 ? 1.0 : -1.0);
+    double hmax = fmin(1.0, 2.0 * PI / f);
+    int ngeo = 32, nuni = X > x1 ? (int)ceil((X - x1) / hmax) : 0;
+    double huni = nuni > 0 ? (X - x1) / nuni : 0.0;
+    double *Jx = (double *)malloc(sizeof(double) * (size_t)(N + 2) * 6);
+    double *Yx = Jx + (N + 2), *Jr = Yx + (N + 2), *Yr = Jr + (N + 2), *Jq = Yr + (N + 2), *Yq = Jq + (N + 2);
+    for (int n = 0; n <= N; ++n) w[n] = 0.0;
+    for (int p = 0; p < ngeo + nuni; ++p) {
+        double lo, hi;
+        if (p < ngeo) {
+            lo = ldexp(x1, p - ngeo);
+            hi = 2.0 * lo;
+        } else {
+            lo = x1 + (p - ngeo) * huni;
+            hi = lo + huni;
+        }
+        double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+        for (int i = 0; i < GLN; ++i) {
+            double x = c + h * gl_x[i];
+            double g = h * gl_w[i] * exp(-tau * x * x) * x;
+            orc_bessel_int(N + 1, x, Jx, Yx);
+            orc_bessel_int(N + 1, R * x, Jr, Yr);
+            orc_bessel_int(N + 1, R0 * x, Jq, Yq);
+            for (int n = 0; n <= N; ++n) {
+                int k = n + 1;  /* order n */
+                if (kind == 1) {
+                    w[n] += g * Jr[k] * Jq[k];
+                    continue;
+                }
+                if (fabs(Yx[k]) > 0x1p500) break;
+                double Ar = x * Yx[k - 1] - n * Yx[k], Br = x * Jx[k - 1] - n * Jx[k];
+                double Aa = Yx[k], Ba = Jx[k];
+                double nr = sqrt(Ar * Ar + Br * Br), na = sqrt(Aa * Aa + Ba * Ba);
+                double crR = (Jr[k] * Ar - Yr[k] * Br) / nr, crQ = (Jq[k] * Ar - Yq[k] * Br) / nr;
+                double caR = (Jr[k] * Aa - Yr[k] * Ba) / na, caQ = (Jq[k] * Aa - Yq[k] * Ba) / na;
+                w[n] += g * (crR * crQ - caR * caQ);
+            }
+        }
+    }
+    free(Jx);
+}
+
+double orc_angle2_cdf(const double *w, int N, double t)
+{
+    double s = w[0] * t;
+    for (int n = 1; n <= N; ++n) s += 2.0 * w[n] * sin(n * t) / n;
+    return s / (PI * w[0]);
+}
+
+double orc_sample_angle2(double R, double R0, double tau, double u)
+{
+    if (!(R + R0 - 2.0 <= 40.0 * sqrt(tau))) return NAN;  /* beyond any encounter (e^{-400}), or not a number */
+    R = fmax(R, 1.0);
+    R0 = fmax(R0, 1.0);
+    int N = orc_angle3_terms(R, R0, tau);
+    double *w = (double *)malloc(sizeof(double) * (size_t)(N + 1));
+    orc_angle2_coef(0, R, R0, tau, N, w);
+    double lo = 0.0, hi = PI;
+    for (int it = 0; it < 200 && hi - lo > 8e-16; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (orc_angle2_cdf(w, N, mid) < u) lo = mid;
+        else hi = mid;
+    }
+    free(w);
+    return 0.5 * (lo + hi);
+}

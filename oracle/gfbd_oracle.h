@@ -120,6 +120,15 @@ void orc_angle3_coef(int kind, double R, double R0, double tau, int N, double *w
 double orc_angle3_cdf(const double *w, int N, double c);
 double orc_sample_angle3(double R, double R0, double tau, double u);
 
+/* Angular propagator in 2D (Sec. 3, Details; eq. genericGF): integer-order
+ * Bessel functions J[k] = J_{k-1}(z), Y[k] = Y_{k-1}(z), the coefficients
+ * w[0..N] of G_ref - G_abs (kind 0) or of the free Green's function (kind 1),
+ * the distribution function of |theta| in [0, pi] given R, and one draw. */
+void orc_bessel_int(int kmax, double z, double *J, double *Y);
+void orc_angle2_coef(int kind, double R, double R0, double tau, int N, double *w);
+double orc_angle2_cdf(const double *w, int N, double t);
+double orc_sample_angle2(double R, double R0, double tau, double u);
+
 typedef struct orc_sim orc_sim;
 
 orc_sim *orc_sim_create(const orc_params *p, uint64_t n, const int32_t *species, const double *pos,
