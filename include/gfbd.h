@@ -291,23 +291,24 @@ int sim_eval_propagator(sim_t *h, uint64_t n, const double *R0, uint32_t step, i
 int sim_eval_first_passage(sim_t *h, uint64_t n, const double *xi, const double *xf, int32_t levels, uint32_t step,
                            uint64_t *lo, uint32_t *attempts);
 
-/* Draws the angle of the propagated pair (Sec. 3, Details: after the radius, the angle Theta
- * between the separations before and after the step comes from J (G_ref - G_abs),
- * J = 2 pi sin(Theta) r^2) for n pairs of a 3D handle: cos_theta[i] is the root of the
- * distribution function of cos Theta given the radii at u[i].  R[i] is the new and R0[i] the old
- * separation in units of a (values below 1 count as 1), tau = D_eff dt / a^2 the handle's; a pair
- * with R + R0 - 2 > 40 sqrt(tau) (no encounter reaches that far) or a NaN radius gets NaN.
- * G_ref - G_abs is the Legendre series of eq. genericGF3D (reflecting minus absorbing surface)
- * with terms n <= min(160, 8 + ceil(sqrt(45 R R0 / tau))), each coefficient an integral over x
- * by 16-point Gauss-Legendre panels of width at most min(1, 2 pi / (R + R0 - 1)) on
- * [0, sqrt(50 / tau)], the half-integer Bessel functions by the three-term recurrences of
+/* Draws the angle of the propagated pair (Sec. 3, Details: after the radius, the angle between
+ * the separations before and after the step comes from J (G_ref - G_abs), J = 2 pi sin(Theta) r^2
+ * in 3D and r in 2D) for n pairs: out[i] is the root, at u[i], of the distribution function of
+ * cos Theta (3D handles) or of |theta| in [0, pi] (2D handles) given the radii.  R[i] is the new
+ * and R0[i] the old separation in units of a (values below 1 count as 1), tau = D_eff dt / a^2
+ * the handle's; a pair with R + R0 - 2 > 40 sqrt(tau) (no encounter reaches that far) or a NaN
+ * radius gets NaN.  G_ref - G_abs is the series of eq. genericGF3D (Legendre polynomials,
+ * half-integer orders) or eq. genericGF with eq. fRad (cos n theta, integer orders), reflecting
+ * minus absorbing surface, with terms n <= min(160, 8 + ceil(sqrt(45 R R0 / tau))); each
+ * coefficient is an integral over x by 16-point Gauss-Legendre panels of width at most
+ * min(1, 2 pi / (R + R0 - 1)) on [0, sqrt(50 / tau)] (2D: 32 panels of ratio 2 on [2^-32, 1]
+ * first, where Y_0 has its logarithm), the Bessel functions by the three-term recurrences of
  * Sec. 4.1 (eq. 3termBessel).  The cap of 160 terms keeps the truncation below 1e-15 for
- * R R0 / tau <= 500.  The direction about the old separation (the azimuth) is uniform and left
- * to the caller.  R, R0, u and cos_theta (n doubles each) are DEVICE pointers owned by the
- * caller; u in (0, 1).  Returns when done; SIM_EINVAL for a NULL pointer, n = 0 or n > 2^32;
- * SIM_EUNSUPPORTED for a 2D handle; SIM_EDEVICE if a HIP call fails.  Uses replica 0's
- * parameters. */
-int sim_eval_angle(sim_t *h, uint64_t n, const double *R, const double *R0, const double *u, double *cos_theta);
+ * R R0 / tau <= 500.  The azimuth (3D) or the side (2D) is uniform and left to the caller.
+ * R, R0, u and out (n doubles each) are DEVICE pointers owned by the caller; u in (0, 1).
+ * Returns when done; SIM_EINVAL for a NULL pointer, n = 0 or n > 2^32; SIM_EDEVICE if a HIP
+ * call fails.  Uses replica 0's parameters. */
+int sim_eval_angle(sim_t *h, uint64_t n, const double *R, const double *R0, const double *u, double *out);
 
 /* Releases all device memory of the handle; NULL is accepted. */
 int sim_destroy(sim_t *h);

@@ -3,7 +3,7 @@
 // of one step (Sec. 3 of Pruestel & Meier-Schellersheim, arXiv:1107.0270).
 #include "../../include/gfbd.h"
 #include "kernels.hpp"
-#include "angle3.hpp"
+#include "angle2.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -121,7 +121,7 @@ struct sim {
     virtual int eval_prop(uint64_t n, const double *R0, uint32_t step, int wave, double *Rpp, uint32_t *attempts) = 0;
     virtual int eval_first_passage(uint64_t n, const double *xi, const double *xf, int levels, uint32_t step, uint64_t *lo,
                                    uint32_t *attempts) = 0;
-    virtual int eval_angle(uint64_t n, const double *R, const double *R0, const double *u, double *cos_theta) = 0;
+    virtual int eval_angle(uint64_t n, const double *R, const double *R0, const double *u, double *out) = 0;
     virtual int admit(const sim_replica &, uint32_t *) { return fail(SIM_ESTATE, "not a pool"); }
     virtual int retire(uint32_t) { return fail(SIM_ESTATE, "not a pool"); }
     virtual int read_member(uint32_t, int, void *, uint64_t, uint64_t *) { return fail(SIM_ESTATE, "not a pool"); }
@@ -1050,18 +1050,16 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         return SIM_OK;
     }
 
-    int eval_angle(uint64_t n, const double *R, const double *R0, const double *u, double *cos_theta) override
+    int eval_angle(uint64_t n, const double *R, const double *R0, const double *u, double *out) override
     {
-        if constexpr (DIM == 2) return fail(SIM_EUNSUPPORTED, "the angular propagator is built for 3D handles");
-        else {
-            if (n > 0xFFFFFFFFull) return fail(SIM_EINVAL, "at most 2^32 pairs");
-            GL16 gl;
-            gauss_legendre16(gl.x, gl.w);
-            k_angle3<<<grid_for(64 * n, 8192), BLOCK, 0, M.stream>>>(P.tau, n, R, R0, u, cos_theta, gl);
-            HIPCHECK(hipGetLastError());
-            HIPCHECK(hipStreamSynchronize(M.stream));
-            return SIM_OK;
-        }
+        if (n > 0xFFFFFFFFull) return fail(SIM_EINVAL, "at most 2^32 pairs");
+        GL16 gl;
+        gauss_legendre16(gl.x, gl.w);
+        if constexpr (DIM == 2) k_angle2<<<grid_for(64 * n, 8192), BLOCK, 0, M.stream>>>(P.tau, n, R, R0, u, out, gl);
+        else k_angle3<<<grid_for(64 * n, 8192), BLOCK, 0, M.stream>>>(P.tau, n, R, R0, u, out, gl);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipStreamSynchronize(M.stream));
+        return SIM_OK;
     }
 
     template <int NC> void launch_prop(uint64_t n, const double *R0, uint32_t step, int wave, double *Rpp, uint32_t *attempts)
@@ -1484,10 +1482,10 @@ int sim_eval_propagator(sim_t *h, uint64_t n, const double *R0, uint32_t step, i
     return h->eval_prop(n, R0, step, wave, Rpp, attempts);
 }
 
-int sim_eval_angle(sim_t *h, uint64_t n, const double *R, const double *R0, const double *u, double *cos_theta)
+int sim_eval_angle(sim_t *h, uint64_t n, const double *R, const double *R0, const double *u, double *out)
 {
-    if (!h || !R || !R0 || !u || !cos_theta || n == 0) { g_err = "null argument or n = 0"; return SIM_EINVAL; }
-    return h->eval_angle(n, R, R0, u, cos_theta);
+    if (!h || !R || !R0 || !u || !out || n == 0) { g_err = "null argument or n = 0"; return SIM_EINVAL; }
+    return h->eval_angle(n, R, R0, u, out);
 }
 
 int sim_eval_first_passage(sim_t *h, uint64_t n, const double *xi, const double *xf, int32_t levels, uint32_t step,

@@ -399,8 +399,8 @@ class Sim:
         self._check(lib().sim_eval_first_passage(self._h, int(n), xi, xf, int(levels), int(step), lo, attempts))
 
     def eval_angle(self, R, R0, u):
-        """cos Theta of propagated pairs (sim_eval_angle): R, R0 the new and old separations in
-        units of a, u the uniforms of the draws (3D handles)."""
+        """Angles of propagated pairs (sim_eval_angle): cos Theta (3D handles) or |theta| in
+        [0, pi] (2D handles); R, R0 the new and old separations in units of a, u the uniforms."""
         R = np.ascontiguousarray(R, dtype=np.float64).ravel()
         R0 = np.ascontiguousarray(R0, dtype=np.float64).ravel()
         u = np.ascontiguousarray(u, dtype=np.float64).ravel()
@@ -417,9 +417,9 @@ class Sim:
             for b in bufs:
                 b.free()
 
-    def eval_angle_device(self, n, R, R0, u, cos_theta):
+    def eval_angle_device(self, n, R, R0, u, out):
         """sim_eval_angle on caller-owned device pointers (ints)."""
-        self._check(lib().sim_eval_angle(self._h, int(n), R, R0, u, cos_theta))
+        self._check(lib().sim_eval_angle(self._h, int(n), R, R0, u, out))
 
     def eval_pairs_device(self, n, R, R0, penc, preac):
         """sim_eval_pairs on caller-owned device pointers (ints or None)."""

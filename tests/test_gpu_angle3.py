@@ -104,12 +104,7 @@ def test_full_size_launch_sampled_against_the_oracle():
     _check(tau, R[pick], R0[pick], u[pick], c[pick])
 
 
-def test_rejects_2d_handles_and_bad_arguments():
-    h = _handle(5e-6, 0.1, 0.005, dim=2)
-    with pytest.raises(S.SimError) as e:
-        h.eval_angle(np.ones(4), np.ones(4), np.full(4, 0.5))
-    assert e.value.code == S.SIM_EUNSUPPORTED
-    h.close()
+def test_rejects_bad_arguments():
     h = _handle(1e-5, 1.0, 0.005)
     with pytest.raises(S.SimError) as e:
         h.eval_angle_device(0, 1, 1, 1, 1)
