@@ -104,30 +104,37 @@ def valu_issue(stage, launch_ms):
             "frac": round(at_peak / launch_ms, 4), "peak_wave_instr_per_s": VALU_WAVE_INSTR_PER_S}
 
 
-# k_angle3 on the --angle workload (10^6 pairs, tau = 0.8): fp64 operations and VALU wave-
-# instructions per launch from rocprofv3 (SQ_INSTS_VALU_{ADD,MUL,FMA}_F64 x 64 lanes, an FMA
-# counting two; SQ_INSTS_VALU), profiles/angle3_kernels.md.  Valid for the source it was taken on.
-ANGLE_COUNTERS = {
+# k_angle3 / k_angle2 on the --angle workloads (3D: 10^6 pairs, tau = 0.8; 2D: 2 x 10^5 pairs,
+# tau = 0.04): fp64 operations and VALU wave-instructions per launch from rocprofv3
+# (SQ_INSTS_VALU_{ADD,MUL,FMA}_F64 x 64 lanes, an FMA counting two; SQ_INSTS_VALU),
+# profiles/angle3_kernels.md and profiles/angle2_kernels.md.  Valid for the source they were taken on.
+ANGLE_COUNTERS = {3: {
     "src_hash": "77752e75850f63b7",
     "pairs": 1000000,
     "f64_flop": 5.994743e+11,  # 64 x (ADD 999569215 + MUL 2386729574 + 2 x FMA 2990243945)
     "valu": 13138793499,
-}
+}, 2: {  # k_angle2 on --angle 200000 --dim 2 (membrane pairs, tau = 0.04)
+    "src_hash": "dc4ec5dd6661d92e",
+    "pairs": 200000,
+    "f64_flop": 1.377628e+12,  # 64 x (ADD 2661534920 + MUL 5660418886 + 2 x FMA 6601739326)
+    "valu": 34212092202,
+}}
 FP64_VECTOR_PEAK = 78.6e12  # MI355X dense fp64 vector FLOP/s
 
 
-def angle_src_hash():
+def angle_src_hash(dim=3):
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1107_0270_amd", "csrc", "angle3.hpp"), "rb") as fh:
-        h.update(fh.read())
+    for f in ["angle3.hpp"] + (["angle2.hpp"] if dim == 2 else []):
+        with open(os.path.join(ROOT, "paper_1107_0270_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def angle_roofline(n, launch_ms):
+def angle_roofline(n, launch_ms, dim=3):
     """The angle kernel against the fp64 vector peak (its work is plain fp64 arithmetic: Bessel
-    recurrences, quadrature sums, Legendre sums), with the VALU issue fraction beside it."""
-    t = ANGLE_COUNTERS
-    if n != t["pairs"] or angle_src_hash() != t["src_hash"]:
+    recurrences, quadrature sums, Legendre or sine sums), with the VALU issue fraction beside it."""
+    t = ANGLE_COUNTERS[dim]
+    if n != t["pairs"] or angle_src_hash(dim) != t["src_hash"]:
         return None
     achieved = t["f64_flop"] / (launch_ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
@@ -280,15 +287,16 @@ def angle(args, I, S):
     J (G_ref - G_abs) given the radii, Sec. 3, Details, eq. genericGF3D), on device-resident
     arrays.  Pairs: a pre-step separation uniform in the shell 1 < R0 < r_cut/a, the new radius
     drawn from the radial propagator by the step's own sampler (sim_eval_propagator), a uniform u."""
-    cfg = I.workload("cfg_rad3d")
+    dim = args.dim
+    cfg = I.workload("cfg_rad3d" if dim == 3 else "cfg_mem2d_small_tau")
     sp = np.array([0, 1], np.int32)
-    pos = np.array([[0.25] * 3, [0.75] * 3])
-    h = S.Sim(dim=3, box=cfg["box"], dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
+    pos = np.array([[0.25] * dim, [0.75] * dim])
+    h = S.Sim(dim=dim, box=cfg["box"], dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
               k_off=0.0, precision=S.PREC_FP64, seed=0, species=sp, pos=pos)
     der = h.derived()
     tau, rmax, n = der["tau"], der["rcut"] / der["a"], args.angle
     rng = np.random.default_rng(0)
-    R0 = np.ascontiguousarray((1.0 + (rmax ** 3 - 1.0) * rng.random(n)) ** (1.0 / 3.0))
+    R0 = np.ascontiguousarray((1.0 + (rmax ** dim - 1.0) * rng.random(n)) ** (1.0 / dim))
     u = rng.random(n)
     bR, bR0, bu, bc = (S.DeviceBuffer(8 * n) for _ in range(4))
     bR0.upload(R0)
@@ -314,23 +322,27 @@ def angle(args, I, S):
         tc = time.perf_counter()
         k = 0
         while k < m and time.perf_counter() - tc < 20.0:
-            O.sample_angle3(R[k], R0[k], tau, u[k])
+            (O.sample_angle3 if dim == 3 else O.sample_angle2)(R[k], R0[k], tau, u[k])
             k += 1
         tc = time.perf_counter() - tc
         cpu = {"value": round(k / tc, 1), "unit": "pairs/s", "cores": 1, "kind": "oracle",
                "sample": f"the first {k} of the same pairs, one call of the single-threaded FP64 C oracle each "
                          f"({tc:.1f} s)"}
         log(f"[angle] cpu baseline {cpu}")
-    log(f"[angle] {n} pairs: {rate:.3e} pairs/s, mean cos Theta {c.mean():.4f}, mean R'' {R.mean():.4f}")
+    what = "cos_theta" if dim == 3 else "abs_theta"
+    log(f"[angle] {n} pairs: {rate:.3e} pairs/s, mean {what} {c.mean():.4f}, mean R'' {R.mean():.4f}")
     print(json.dumps({
         "metric": "propagated-pair angles/s (kernel only)", "value": round(rate, 1), "unit": "pairs/s",
-        "mean_cos_theta": round(float(c.mean()), 6), "roofline": angle_roofline(n, el * 1e3 / args.steps),
+        f"mean_{what}": round(float(c.mean()), 6),
+        "roofline": angle_roofline(n, el * 1e3 / args.steps, dim),
         "cpu_baseline": cpu,
         "n_gpus": 1, "pairs": n, "repeats": args.steps, "ms_per_call": round(el * 1e3 / args.steps, 4),
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"3D propagated pairs of the benchmark workload: R0 uniform in the shell 1 < R0 < "
-                               f"r_cut/a = {rmax:.3f}, R'' from the radial propagator, tau = {tau:.4g}",
-                   "kernel": "k_angle3 (Legendre series of G_ref - G_abs, one wave per pair)"}}), flush=True)
+        "config": {"workload": f"{dim}D propagated pairs of the {'benchmark' if dim == 3 else 'membrane'} workload: "
+                               f"R0 uniform in the {'shell' if dim == 3 else 'ring'} 1 < R0 < r_cut/a = {rmax:.3f}, "
+                               f"R'' from the radial propagator, tau = {tau:.4g}",
+                   "kernel": "k_angle3 (Legendre series of G_ref - G_abs, one wave per pair)" if dim == 3 else
+                             "k_angle2 (cos(n theta) series of G_ref - G_abs, one wave per pair)"}}), flush=True)
 
 
 def batched(args, I, S):
@@ -488,8 +500,8 @@ def main():
                     help="time the 3D angular propagator on N propagated pairs instead of the step")
     ap.add_argument("--pair-probs", type=int, default=0, metavar="N",
                     help="only run the pair-probability micro-benchmark on N synthetic pairs and exit")
-    ap.add_argument("--dim", type=int, default=3, help="workload dimension for --pair-probs (2: the membrane "
-                    "workload at dt = 5 us)")
+    ap.add_argument("--dim", type=int, default=3, help="workload dimension for --pair-probs, --first-passage and "
+                    "--angle (2: the membrane workload at dt = 5 us)")
     ap.add_argument("--batch", type=int, default=0, metavar="R",
                     help="only run the batched-ensemble benchmark on R replicas (4096: the full ensemble) and exit")
     ap.add_argument("--single-sample", type=int, default=32,
