@@ -109,15 +109,15 @@ def valu_issue(stage, launch_ms):
 # (SQ_INSTS_VALU_{ADD,MUL,FMA}_F64 x 64 lanes, an FMA counting two; SQ_INSTS_VALU),
 # profiles/angle3_kernels.md and profiles/angle2_kernels.md.  Valid for the source they were taken on.
 ANGLE_COUNTERS = {3: {
-    "src_hash": "77752e75850f63b7",
+    "src_hash": "c4526d49b3bc106f",
     "pairs": 1000000,
-    "f64_flop": 5.994743e+11,  # 64 x (ADD 999569215 + MUL 2386729574 + 2 x FMA 2990243945)
-    "valu": 13138793499,
+    "f64_flop": 5.829525e+11,  # 64 x (ADD 999569215 + MUL 2356711619 + 2 x FMA 2876175716)
+    "valu": 12999570030,
 }, 2: {  # k_angle2 on --angle 200000 --dim 2 (membrane pairs, tau = 0.04)
-    "src_hash": "dc4ec5dd6661d92e",
+    "src_hash": "dbeb761e435a32a3",
     "pairs": 200000,
-    "f64_flop": 1.377628e+12,  # 64 x (ADD 2661534920 + MUL 5660418886 + 2 x FMA 6601739326)
-    "valu": 34212092202,
+    "f64_flop": 1.368732e+12,  # 64 x (ADD 2658334920 + MUL 5650218886 + 2 x FMA 6538939326)
+    "valu": 34495664968,
 }}
 FP64_VECTOR_PEAK = 78.6e12  # MI355X dense fp64 vector FLOP/s
 

@@ -37,7 +37,7 @@ __device__ __noinline__ void ang_bessel01(double z, double *j0z, double *j1z, do
 }
 
 // J_n(z) for n = 0 .. kmax, three arguments at once: t[j][n] times lam[j].
-__device__ __noinline__ void ang_miller3_int(int kmax, const double z[3], double (*t)[ANG_NCAP + 2], double lam[3],
+__device__ __forceinline__ void ang_miller3_int(int kmax, const double z[3], double (*t)[ANG_NCAP + 2], double lam[3],
                                              double y0z[3], double y1z[3])
 {
     const double zm = fmax(z[0], fmax(z[1], z[2]));

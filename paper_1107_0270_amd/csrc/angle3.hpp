@@ -54,7 +54,7 @@ __device__ __forceinline__ double wave_allsum(double v)
 
 // J_{k-1/2}(z) for k = 0 .. kmax, for three arguments at once (the downward recurrence
 // C_{nu-1} = (2 nu / z) C_nu - C_{nu+1}, nu = k - 1/2, from k = m down): t[j][k] times lam[j].
-__device__ __noinline__ void ang_miller3(int kmax, const double z[3], double (*t)[ANG_NCAP + 2], double lam[3])
+__device__ __forceinline__ void ang_miller3(int kmax, const double z[3], double (*t)[ANG_NCAP + 2], double lam[3])
 {
     // start: J_m / |Y_m| at m = z + t falls like e^{-0.94 t^{3/2} / sqrt(z)} (beyond the turning
     // point), below 1e-18 for t >= 8 z^{1/3}; and at least 8 orders above kmax
