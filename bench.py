@@ -114,10 +114,10 @@ ANGLE_COUNTERS = {3: {
     "f64_flop": 5.829525e+11,  # 64 x (ADD 999569215 + MUL 2356711619 + 2 x FMA 2876175716)
     "valu": 12999570030,
 }, 2: {  # k_angle2 on --angle 200000 --dim 2 (membrane pairs, tau = 0.04)
-    "src_hash": "dbeb761e435a32a3",
+    "src_hash": "1104b0885b8a5772",
     "pairs": 200000,
-    "f64_flop": 1.368732e+12,  # 64 x (ADD 2658334920 + MUL 5650218886 + 2 x FMA 6538939326)
-    "valu": 34495664968,
+    "f64_flop": 1.233329e+12,  # 64 x (ADD 2247871428 + MUL 4040642340 + 2 x FMA 6491125936)
+    "valu": 31842732517,
 }}
 FP64_VECTOR_PEAK = 78.6e12  # MI355X dense fp64 vector FLOP/s
 

@@ -38,7 +38,7 @@ __device__ __noinline__ void ang_bessel01(double z, double *j0z, double *j1z, do
 
 // J_n(z) for n = 0 .. kmax, three arguments at once: t[j][n] times lam[j].
 __device__ __forceinline__ void ang_miller3_int(int kmax, const double z[3], double (*t)[ANG_NCAP + 2], double lam[3],
-                                             double y0z[3], double y1z[3])
+                                                const double j0z[3], const double j1z[3])
 {
     const double zm = fmax(z[0], fmax(z[1], z[2]));
     const int zc = (int)ceil(zm + 8.0 * cbrt(zm));
@@ -63,8 +63,7 @@ __device__ __forceinline__ void ang_miller3_int(int kmax, const double z[3], dou
         }
     }
     for (int j = 0; j < 3; ++j) {
-        double a0, a1;
-        ang_bessel01(z[j], &a0, &a1, &y0z[j], &y1z[j]);
+        const double a0 = j0z[j], a1 = j1z[j];
         const double M = fmax(fabs(t[j][0]), fabs(t[j][1])), b0 = t[j][0] / M, b1 = t[j][1] / M;
         lam[j] = (a0 * b0 + a1 * b1) / (b0 * b0 + b1 * b1) / M;
     }
@@ -121,19 +120,37 @@ __global__ __launch_bounds__(BLOCK) void k_angle2(double tau, uint64_t n, const 
             const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
             const double x = c + h * gl.x[q & 15];
             const double g = live ? h * gl.w[q & 15] * exp(-tau * x * x) * x : 0.0;
-            double t[3][ANG_NCAP + 2], lam[3], y0v[3], ym[3], iz[3];  // Y_n, Y_{n-1}, 1/z
+            double t[3][ANG_NCAP + 2], lam[3], y0v[3], ym[3], iz[3], j0z[3], j1z[3];  // Y_n, Y_{n-1}, 1/z
             const double z[3] = {x, R * x, R0 * x};
-            ang_miller3_int(N + 1, z, t, lam, y0v, ym);
             for (int j = 0; j < 3; ++j) {
+                ang_bessel01(z[j], &j0z[j], &j1z[j], &y0v[j], &ym[j]);
                 ym[j] = -ym[j];  // Y_{-1} = -Y_1
                 iz[j] = 1.0 / z[j];
             }
+            // the first order whose |Y_n(x)| exceeds 2^500 ends the node's terms (the same
+            // recurrence as below): J is needed only up to there
+            int nd = N + 1;
+            {
+                double a = ym[0], b = y0v[0];
+                for (int nn = 0; nn <= N; ++nn) {
+                    if (fabs(b) > 0x1p500) {
+                        nd = nn;
+                        break;
+                    }
+                    const double c = (2.0 * nn) * iz[0] * b - a;
+                    a = b;
+                    b = c;
+                }
+            }
+            const int kmax = nd + 1 < N + 1 ? nd + 1 : N + 1;  // >= 1
+            ang_miller3_int(kmax, z, t, lam, j0z, j1z);
             bool dead = !live;
             double jm = -lam[0] * t[0][1];  // J_{-1}(x) = -J_1(x)
             for (int nn = 0; nn <= N; ++nn) {  // uniform over the wave
                 if (fabs(y0v[0]) > 0x1p500) dead = true;
+                if (__ballot(!dead) == 0) break;  // every node of the wave is past its last order
                 double term = 0.0;
-                const double jx = lam[0] * t[0][nn];
+                const double jx = nn <= kmax ? lam[0] * t[0][nn] : 0.0;
                 if (!dead) {
                     // C(R) C(R0) = (J(Rx) A - Y(Rx) B)(J(R0x) A - Y(R0x) B) / (A^2 + B^2)
                     const double jr = lam[1] * t[1][nn], jq = lam[2] * t[2][nn];
