@@ -46,28 +46,28 @@ def algorithmic_bytes(kernel, n_live, n_a, n_b, n_keys):
 # commands are in profiles/rad3d_step_traffic.md.  Valid only for the kernel sources they were taken
 # on (hash below): after any change to them the field is reported as null.
 MEASURED_TRAFFIC = {
-    "src_hash": "ed6c7e86b0d9e298",
+    "src_hash": "200ef1c5fe98b68c",
     "scale_fetch": 1.9998, "scale_write": 1.0,
     "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
-        "move": (9871.2, 31395.4),
+        "move": (9867.9, 31395.5),
         "scan": (5808.6 + 5824.3, 11.3 + 17376.1),
-        "scatter": (16999.5, 29457.2),
-        "pairs": (9762.5, 299.3),
-        "eval": (3269.4, 199.9),
-        "select_a": (241.5, 60.3),
-        "select_b": (267.9, 11.9),
-        "events": (343.9 + 2.8, 52.9 + 0.9),
+        "scatter": (16984.1, 29463.2),
+        "pairs": (9756.0, 299.3),
+        "eval": (3275.9, 199.4),
+        "select_a": (251.1, 60.4),
+        "select_b": (267.5, 12.1),
+        "events": (351.3 + 2.8, 52.9 + 0.9),
     },
     # stage -> VALU wave-instructions per launch (SQ_INSTS_VALU summed over the stage's kernels)
     "valu": {
-        "move": 8175114,
+        "move": 8175113,
         "scan": 144800 + 271542,
         "scatter": 723656,
-        "pairs": 5249924,
-        "eval": 636112,
-        "select_a": 69844,
-        "select_b": 214456,
-        "events": 1204458 + 21,
+        "pairs": 5250181,
+        "eval": 636125,
+        "select_a": 69866,
+        "select_b": 214480,
+        "events": 1204444 + 21,
     },
 }
 

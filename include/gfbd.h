@@ -306,7 +306,8 @@ int sim_eval_first_passage(sim_t *h, uint64_t n, const double *xi, const double 
  * Sec. 4.1 (eq. 3termBessel).  The cap of 160 terms keeps the truncation below 1e-15 for
  * R R0 / tau <= 500.  The azimuth (3D) or the side (2D) is uniform and left to the caller.
  * R, R0, u and out (n doubles each) are DEVICE pointers owned by the caller; u in (0, 1).
- * Returns when done; SIM_EINVAL for a NULL pointer, n = 0 or n > 2^32; SIM_EDEVICE if a HIP
+ * Returns when done; SIM_EINVAL for a NULL pointer, n = 0 or n > 2^32; SIM_EUNSUPPORTED for a
+ * handle with tau < 2e-3 (the series would need more than its 160 terms); SIM_EDEVICE if a HIP
  * call fails.  Uses replica 0's parameters. */
 int sim_eval_angle(sim_t *h, uint64_t n, const double *R, const double *R0, const double *u, double *out);
 

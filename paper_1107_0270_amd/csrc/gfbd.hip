@@ -1053,6 +1053,9 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     int eval_angle(uint64_t n, const double *R, const double *R0, const double *u, double *out) override
     {
         if (n > 0xFFFFFFFFull) return fail(SIM_EINVAL, "at most 2^32 pairs");
+        // below this the series needs more than its 160 terms (R R0 / tau > 500) and the
+        // quadrature grows like 1 / sqrt(tau) nodes per pair
+        if (!(P.tau >= 2e-3)) return fail(SIM_EUNSUPPORTED, "the angular series is built for tau >= 2e-3");
         GL16 gl;
         gauss_legendre16(gl.x, gl.w);
         if constexpr (DIM == 2) k_angle2<<<grid_for(64 * n, 8192), BLOCK, 0, M.stream>>>(P.tau, n, R, R0, u, out, gl);

@@ -111,3 +111,10 @@ def test_rejects_bad_arguments():
         h.eval_angle_device(0, 1, 1, 1, 1)
     assert e.value.code == S.SIM_EINVAL
     h.close()
+    for dim in (3, 2):  # tau = 8e-4: more terms than the series keeps
+        h = _handle(1e-8, 1.0, 0.005, dim=dim)
+        assert h.derived()["tau"] < 2e-3
+        with pytest.raises(S.SimError) as e:
+            h.eval_angle(np.full(4, 1.01), np.full(4, 1.01), np.full(4, 0.5))
+        assert e.value.code == S.SIM_EUNSUPPORTED
+        h.close()
