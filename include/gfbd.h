@@ -304,7 +304,11 @@ int sim_eval_first_passage(sim_t *h, uint64_t n, const double *xi, const double 
  * min(1, 2 pi / (R + R0 - 1)) on [0, sqrt(50 / tau)] (2D: 32 panels of ratio 2 on [2^-32, 1]
  * first, where Y_0 has its logarithm), the Bessel functions by the three-term recurrences of
  * Sec. 4.1 (eq. 3termBessel).  The cap of 160 terms keeps the truncation below 1e-15 for
- * R R0 / tau <= 500.  The azimuth (3D) or the side (2D) is uniform and left to the caller.
+ * R R0 / tau <= 500.  The coefficients sum terms of the size of the free Green's function down
+ * to the image term, so the distribution function is accurate to about
+ * 1e-14 e^{(R+R0-2)^2 / 4 tau}: to 1e-10 where the radial propagator puts nearly all its draws
+ * ((R+R0-2)^2 / 4 tau below 9), and not at all beyond about 36.  The azimuth (3D) or the side
+ * (2D) is uniform and left to the caller.
  * R, R0, u and out (n doubles each) are DEVICE pointers owned by the caller; u in (0, 1).
  * Returns when done; SIM_EINVAL for a NULL pointer, n = 0 or n > 2^32; SIM_EUNSUPPORTED for a
  * handle with tau < 2e-3 (the series would need more than its 160 terms); SIM_EDEVICE if a HIP
