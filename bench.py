@@ -515,8 +515,10 @@ def main():
                     help="precision mode (default: the workload's; fp32 = plain binary32, fp32nc = binary32 with "
                          "binary64 near-contact arguments and displacements)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain binary32 comparison run")
-    ap.add_argument("--green2d", choices=["expansion", "exact"], default="expansion",
-                    help="2D radial functions: small-time expansions, or exact (tables by quadrature)")
+    ap.add_argument("--green2d", choices=["auto", "expansion", "exact"], default="auto",
+                    help="2D radial functions: small-time expansions, or exact (tables by quadrature); auto takes "
+                         "the expansion where it holds the probabilities to 1e-6 (tau <= 0.05 at order 12) and "
+                         "the exact functions beyond (the membrane workload as written, tau = 0.8)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the cell edge and pair-search kernel by timing candidates on the workload first")
     ap.add_argument("--eps-cut", type=float, default=1e-6,
@@ -571,6 +573,9 @@ def main():
     log(f"[bench] state: {len(sp)} particles, {red} redrawn overlaps, {time.time() - t0:.1f}s")
     search = {"auto": S.PAIRS_AUTO, "bricks": S.PAIRS_BRICKS, "direct": S.PAIRS_DIRECT}[args.pair_search]
 
+    tau = (cfg["D"][0] + cfg["D"][1]) * cfg["dt"] / cfg["sigma"] ** 2
+    if args.green2d == "auto":
+        args.green2d = "exact" if dim == 2 and tau > 0.05 * (1 + 1e-9) else "expansion"
     g2 = S.G2_EXACT if args.green2d == "exact" else S.G2_EXPANSION
 
     launch = {}  # pair-stage and event workgroups (the library's defaults unless tuned)

@@ -112,17 +112,35 @@ typedef struct {
     int32_t green2d;               /* 2D radial functions: SIM_G2_EXPANSION or SIM_G2_EXACT (2D only) */
     int32_t pair_blocks;           /* workgroups of the pair-evaluation and selection kernels, 8..65536 (0 = 1024) */
     int32_t event_blocks;          /* workgroups of the event kernel, 1..65536 (0 = 1024) */
-    int32_t reserved;              /* must be 0 */
+    uint32_t flags;                /* SIM_F_* bits (0: the paper's method, validated ranges only) */
 } sim_config;
 
-/* sim_config.green2d.  EXPANSION: the small-time expansions of Sec. 4.2 to order n_terms (valid for
- * tau = D_eff dt / a^2 up to about 0.04 at 1e-6).  EXACT: the n = 0 term of the 2D Green's function
- * (Sec. 4.2, its Bessel-function form) by quadrature, tabulated on the device when the handle is
- * created (a grid of step sqrt(tau)/40 in R and R0, read by bicubic interpolation): p_enc, p_reac
- * and the propagator's distribution function, R'' then drawn by inversion of one uniform, word 0
- * of the counter of attempt 0.  EXACT is for any tau; it is refused in 3D (SIM_EINVAL) and in
- * batches and pools (SIM_EUNSUPPORTED), and SIM_EUNSUPPORTED if its tables would exceed 2^26 entries. */
+/* sim_config.green2d.
+ * EXPANSION: the small-time expansions of Sec. 4.2 (eq. smallTEabs and its reflecting and radiation
+ *   forms) to order n_terms.  Each order holds p_enc and p_reac to 1e-6 (measured against a numerical
+ *   inversion of the Laplace-domain forms eqs. absPert, refPert and radPert, worst case at contact,
+ *   h up to 0.8) only up to a tau = D_eff dt / a^2 that grows with the order: n_terms 5: 0.005,
+ *   6: 0.01, 7: 0.02, 8: 0.03, 9-10: 0.04, 11-13: 0.05, 14-19: 0.06, 20-32: 0.07; orders 1-4 reach
+ *   1e-6 nowhere.  Beyond that limit a 2D handle is refused (SIM_EUNSUPPORTED) unless flags has
+ *   SIM_F_UNVALIDATED_TAU.
+ * EXACT: the n = 0 term of the 2D Green's function (Sec. 4.2, its Bessel-function form, eqs.
+ *   genericGF and fRad) by quadrature, tabulated on the device when the handle is created (a grid of
+ *   step sqrt(tau)/160 in R, twice that in R0, read by bicubic interpolation): p_enc, p_reac and
+ *   the propagator's distribution function, R'' then drawn by inversion of one uniform, word 0 of
+ *   the counter of attempt 0.  Pairs with R0 beyond 1 + c sqrt(tau) (c = 8.4 for tau <= 0.5, 9 above)
+ *   use the order-n_terms expansion, which holds there.  Accuracy against the Laplace inversion:
+ *   1e-6 for tau <= 0.5, 1.5e-6 up to tau = 0.8; tau > 0.8 is refused (SIM_EUNSUPPORTED), as is
+ *   EXACT in 3D (SIM_EINVAL), in batches and pools (SIM_EUNSUPPORTED), and tables over 2^26 entries. */
 enum { SIM_G2_EXPANSION = 0, SIM_G2_EXACT = 1 };
+
+/* sim_config.flags.
+ * UNVALIDATED_TAU  accept the 2D expansion beyond the tau its order holds to 1e-6 (see green2d);
+ *                  the probabilities are then those of the truncated series, not the paper's.
+ * KEEP_DIRECTION   after a non-reactive encounter keep the direction of the pair's free end point
+ *                  and redraw only its length, instead of drawing the angle to the old separation
+ *                  from the full propagator (Sec. 3, Details); exact for every single-pair radial
+ *                  statistic, not for many-body geometry.  For comparison with that reading. */
+enum { SIM_F_UNVALIDATED_TAU = 1u, SIM_F_KEEP_DIRECTION = 2u };
 
 /* Creates a simulation with n slots.  species[i] in {A, B, C, FREE, RESERVED};
  * pos is n*dim doubles (slot-major, ignored for FREE/RESERVED); partner[i] is
@@ -226,16 +244,20 @@ enum {
 
 typedef struct { uint32_t i, j; double R, R0, p; uint32_t draw; int32_t cand; } sim_dbg_pair;
 typedef struct { uint32_t i, j; double p; } sim_dbg_pick;
-typedef struct { uint32_t i, j; int32_t reacted; uint32_t attempts; double Rpp, preac; } sim_dbg_match;
-typedef struct { uint32_t c, j; int32_t decayed, recombined; uint32_t attempts, pad; double Rpp, preac; } sim_dbg_diss;
+/* draw: the Philox word of the reaction test (TAG_REAC, word 0) of a matched pair, or of the
+ * geminate test (TAG_GEM) of a decay; cos_theta: the cosine of the angle between the pair's
+ * separations before and after a non-reactive propagation, NaN where none was drawn */
+typedef struct { uint32_t i, j; int32_t reacted; uint32_t attempts, draw, pad; double Rpp, preac, cos_theta; } sim_dbg_match;
+typedef struct { uint32_t c, j; int32_t decayed, recombined; uint32_t attempts, draw; double Rpp, preac; } sim_dbg_diss;
 
 /* Kernels timed with sim_config.timing: move + bucket count, bucket scan,
  * scatter into sorted order, pair search, p_enc + draw per pair, A-side
- * choice, B-side choice + decay draws, matched pairs and decays (one wave
- * each: propagation, reaction, dissociation) and the one-workgroup step close. */
+ * choice, B-side choice + decay draws, matched pairs and decays (propagated
+ * radius, reaction, dissociation), the angles of the propagated pairs (one
+ * workgroup each; not run with SIM_F_KEEP_DIRECTION) and the one-workgroup step close. */
 enum {
     SIM_K_MOVE = 0, SIM_K_SCAN, SIM_K_SCATTER, SIM_K_PAIRS, SIM_K_EVAL, SIM_K_SELECT_A, SIM_K_SELECT_B,
-    SIM_K_EVENTS, SIM_K_N
+    SIM_K_EVENTS, SIM_K_ANGLES, SIM_K_N
 };
 typedef struct { double ms; uint64_t launches; } sim_kernel_time;
 

@@ -36,16 +36,16 @@ class Params(C.Structure):
     _fields_ = [("dim", C.c_int32), ("bc", C.c_int32), ("store_f32", C.c_int32), ("n_terms", C.c_int32),
                 ("box", C.c_double * 3), ("dt", C.c_double), ("D", C.c_double * 3), ("sigma", C.c_double),
                 ("kappa_a", C.c_double), ("k_off", C.c_double), ("eps_cut", C.c_double), ("rcut", C.c_double),
-                ("seed", C.c_uint64), ("replica", C.c_uint32), ("exact2d", C.c_int32)]
+                ("seed", C.c_uint64), ("replica", C.c_uint32), ("exact2d", C.c_int32), ("keep_dir", C.c_int32)]
 
 
 PAIR_DT = np.dtype([("i", "<u4"), ("j", "<u4"), ("R", "<f8"), ("R0", "<f8"), ("p", "<f8"),
                     ("draw", "<u4"), ("cand", "<i4")], align=True)
 PICK_DT = np.dtype([("i", "<u4"), ("j", "<u4"), ("p", "<f8")], align=True)
-MATCH_DT = np.dtype([("i", "<u4"), ("j", "<u4"), ("reacted", "<i4"), ("attempts", "<u4"),
-                     ("Rpp", "<f8"), ("preac", "<f8")], align=True)
+MATCH_DT = np.dtype([("i", "<u4"), ("j", "<u4"), ("reacted", "<i4"), ("attempts", "<u4"), ("draw", "<u4"),
+                     ("pad", "<u4"), ("Rpp", "<f8"), ("preac", "<f8"), ("cos_theta", "<f8")], align=True)
 DISS_DT = np.dtype([("c", "<u4"), ("j", "<u4"), ("decayed", "<i4"), ("recombined", "<i4"),
-                    ("attempts", "<u4"), ("pad", "<u4"), ("Rpp", "<f8"), ("preac", "<f8")], align=True)
+                    ("attempts", "<u4"), ("draw", "<u4"), ("Rpp", "<f8"), ("preac", "<f8")], align=True)
 
 _lib = None
 
@@ -88,6 +88,7 @@ def lib():
         "orc_preac2x": (d, [d, d, d, d]),
         "orc_sample_prop2x": (d, [d, d, d]),
         "orc_x2_switch": (d, [d]),
+        "orc_x2_prop_switch": (d, [d]),
         "orc_first_passage": (u64, [i, P(d), P(d), d, i, i, u32, u32, P(u32), P(u32)]),
         "orc_rcut": (d, [i, i, d, d, d, d, d]),
         "orc_angle3_terms": (i, [d, d, d]),
@@ -263,6 +264,10 @@ def x2_switch(tau):
     return lib().orc_x2_switch(float(tau))
 
 
+def x2_prop_switch(tau):
+    return lib().orc_x2_prop_switch(float(tau))
+
+
 def first_passage(dim, xi, xf, tau, levels, c0, step, key, n_terms=12):
     """First contact of a pair by bisection (Appendix): the index lo of the interval
     [lo, lo + 1) * dt / 2^levels, and the midpoint proposals drawn."""
@@ -350,11 +355,14 @@ class OracleSim:
     """The step of Sec. 3 on a slot-indexed state, in FP64."""
 
     def __init__(self, *, dim, bc, box, dt, D, sigma, kappa_a=0.0, k_off=0.0, eps_cut=1e-3, rcut=0.0,
-                 seed=0, replica=0, store_f32=False, n_terms=12, exact2d=False, species, pos, partner=None):
+                 seed=0, replica=0, store_f32=False, n_terms=12, exact2d=False, keep_direction=False, species, pos,
+                 partner=None):
         L = lib()
         p = Params()
         p.dim, p.bc, p.store_f32, p.n_terms = int(dim), int(bc), int(bool(store_f32)), int(n_terms)
         p.exact2d = int(bool(exact2d))
+        p.keep_dir = int(bool(keep_direction))
+        self.keep_direction = bool(keep_direction)
         bx = list(box) + [1.0] * (3 - len(box))
         for k in range(3):
             p.box[k] = float(bx[k])

@@ -654,7 +654,7 @@ double orc_rcut(int dim, int bc, double a, double Deff, double dt, double kappa_
 /* {slot i, partner j or 0xFFFFFFFF, step, tag | attempt << 8}.             */
 /* ------------------------------------------------------------------------ */
 enum { TAG_MOVE = 1, TAG_ENC = 2, TAG_SELA = 3, TAG_SELB = 4, TAG_PROP = 5, TAG_REAC = 6,
-       TAG_UNI = 7, TAG_DPROP = 8, TAG_DIR = 9, TAG_GEM = 10, TAG_FPT = 11, TAG_FPTU = 12 };
+       TAG_UNI = 7, TAG_DPROP = 8, TAG_DIR = 9, TAG_GEM = 10, TAG_FPT = 11, TAG_FPTU = 12, TAG_ANG = 13 };
 #define NOSLOT 0xFFFFFFFFu
 
 struct orc_sim {
@@ -759,13 +759,26 @@ static int cmp_pick_bj(const void *a, const void *b)
     return 0;
 }
 
-/* The exact 2D functions serve pairs with R0 <= 1 + 8.4 sqrt(tau): there the
- * propagator's mass 1 - S_abs(R0) exceeds erfc(4.2) ~ 3e-9 and is resolved by
+/* The exact 2D functions serve pairs with R0 <= 1 + c sqrt(tau): there the
+ * propagator's mass 1 - S_abs(R0) exceeds about erfc(c/2) and is resolved by
  * the quadrature.  Farther out every argument x = (R + R0 - 2)/(2 sqrt tau) of
- * the pair is >= 4.2, where the small-time expansions hold, and they are used. */
-double orc_x2_switch(double tau) { return 1.0 + 8.4 * sqrt(tau); }
+ * the pair is >= c/2, where the order-12 small-time expansion (Sec. 4.2, eq.
+ * smallTEabs) holds, and it is used.  c = 8.4 up to tau = 0.5; above, the
+ * expansion's error at contact reaches 1e-6 only a little farther out, c = 9
+ * (both measured against a numerical inversion of the Laplace-domain forms,
+ * eqs. absPert, refPert, radPert). */
+double orc_x2_switch(double tau) { return 1.0 + (tau <= 0.5 ? 8.4 : 9.0) * sqrt(tau); }
+
+/* The propagator's distribution function is a ratio of masses of size
+ * 1 - S_abs(R0), which the quadrature resolves down to about erfc(4.2) ~ 3e-9:
+ * its switch stays at 1 + 8.4 sqrt(tau) for every tau. */
+double orc_x2_prop_switch(double tau) { return 1.0 + 8.4 * sqrt(tau); }
 
 static int use_x2(const orc_sim *s, double R0) { return s->p.dim == 2 && s->p.exact2d && R0 <= orc_x2_switch(s->tau); }
+static int use_x2_prop(const orc_sim *s, double R0)
+{
+    return s->p.dim == 2 && s->p.exact2d && R0 <= orc_x2_prop_switch(s->tau);
+}
 
 static double pair_prob(const orc_sim *s, double R, double R0)
 {
@@ -786,7 +799,7 @@ static double reac_prob(const orc_sim *s, double R, double R0)
  * inversion with word 0 of the counter's attempt 0 */
 static double propagate(const orc_sim *s, double R0, const uint32_t ctr[4], uint32_t *att, uint32_t *hits)
 {
-    if (use_x2(s, R0)) {
+    if (use_x2_prop(s, R0)) {
         uint32_t w[4];
         uint32_t ct[4] = {ctr[0], ctr[1], ctr[2], ctr[3] & 0xFFu};
         orc_philox4x32_10(ct, s->key, w);
@@ -811,6 +824,51 @@ static void separation(const orc_sim *s, uint32_t i, uint32_t j, double rv[3], d
     }
     *R = sqrt(r2) / s->a;
     *R0 = sqrt(r02) / s->a;
+}
+
+/* Direction of a propagated pair's new separation (Sec. 3, Details, second item
+ * of the propagation): the angle Theta between the new separation and the
+ * pre-step one r0v is drawn from J (G_ref - G_abs) given the new radius R''
+ * (eqs. genericGF3D and genericGF), with u = U(word 0) of the counter
+ * {i, j, step, ANG}.  In 3D the azimuth about r0v is uniform, 2 pi U(word 1),
+ * measured in the frame b1, b2 orthogonal to r0v of Duff et al., "Building an
+ * Orthonormal Basis, Revisited" (JCGT 2017); in 2D the side of the rotation is
+ * the top bit of word 1 (set: clockwise).  e receives the unit direction and
+ * *cth cos Theta.  A pre-step separation of length zero, or radii beyond any
+ * encounter (the sampler's NaN), keep the direction ef of the free end point
+ * (*cth = NaN). */
+static void new_direction(const orc_sim *s, const double r0v[3], const double ef[3], double Rpp, double R0,
+                          uint32_t i, uint32_t j, uint32_t stp, double e[3], double *cth)
+{
+    const int d = s->p.dim;
+    double n0 = 0.0;
+    for (int k = 0; k < d; ++k) n0 += r0v[k] * r0v[k];
+    n0 = sqrt(n0);
+    uint32_t ctr[4] = {i, j, stp, TAG_ANG}, w[4];
+    orc_philox4x32_10(ctr, s->key, w);
+    const double u = orc_u01(w[0]);
+    double c = NAN;
+    if (n0 > 0.0) c = d == 3 ? orc_sample_angle3(Rpp, R0, s->tau, u) : cos(orc_sample_angle2(Rpp, R0, s->tau, u));
+    *cth = c;
+    if (!(c == c)) {
+        for (int k = 0; k < 3; ++k) e[k] = ef[k];
+        return;
+    }
+    double n[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < d; ++k) n[k] = r0v[k] / n0;
+    if (d == 3) {
+        const double sg = n[2] >= 0.0 ? 1.0 : -1.0, a = -1.0 / (sg + n[2]), b = n[0] * n[1] * a;
+        const double b1[3] = {1.0 + sg * n[0] * n[0] * a, sg * b, -sg * n[0]};
+        const double b2[3] = {b, sg + n[1] * n[1] * a, -n[1]};
+        const double sn = sqrt(fmax(0.0, 1.0 - c * c)), ph = 2.0 * PI * orc_u01(w[1]);
+        const double cp = cos(ph), spp = sin(ph);
+        for (int k = 0; k < 3; ++k) e[k] = c * n[k] + sn * (cp * b1[k] + spp * b2[k]);
+    } else {
+        const double sn = (w[1] >> 31 ? -1.0 : 1.0) * sqrt(fmax(0.0, 1.0 - c * c));
+        e[0] = c * n[0] - sn * n[1];
+        e[1] = sn * n[0] + c * n[1];
+        e[2] = 0.0;
+    }
 }
 
 void orc_sim_step(orc_sim *s)
@@ -986,6 +1044,7 @@ void orc_sim_step(orc_sim *s)
         memset(mt, 0, sizeof(*mt));
         mt->i = s->picks[chosen].i;
         mt->j = s->picks[chosen].j;
+        mt->cos_theta = NAN;
         q = e;
     }
     s->st[ORC_ST_MATCHES] = s->n_matches;
@@ -1017,16 +1076,25 @@ void orc_sim_step(orc_sim *s)
             mt->preac = reac_prob(s, Rpp, R0);
             uint32_t c2[4] = {i, j, stp, TAG_REAC}, w[4];
             orc_philox4x32_10(c2, s->key, w);
+            mt->draw = w[0];
             react = orc_u01(w[0]) < mt->preac;
             if (!react) {
-                double rn = 0.0;
+                /* the free end point's direction, and unless the step keeps it, the
+                 * drawn one (Sec. 3, Details) */
+                double rn = 0.0, ef[3] = {0.0, 0.0, 0.0}, e[3], r0v[3] = {0.0, 0.0, 0.0};
                 for (int k = 0; k < d; ++k) rn += rv[k] * rv[k];
                 rn = sqrt(rn);
+                for (int k = 0; k < d; ++k) ef[k] = rn > 0.0 ? rv[k] / rn : (k == d - 1 ? 1.0 : 0.0);
+                if (s->p.keep_dir) {
+                    for (int k = 0; k < 3; ++k) e[k] = ef[k];
+                } else {
+                    for (int k = 0; k < d; ++k) r0v[k] = rv[k] - (s->dx[j * 3 + k] - s->dx[i * 3 + k]);
+                    new_direction(s, r0v, ef, Rpp, R0, i, j, stp, e, &mt->cos_theta);
+                }
                 for (int k = 0; k < d; ++k) {
-                    double e = rn > 0.0 ? rv[k] / rn : (k == d - 1 ? 1.0 : 0.0);
                     double cen = s->x[i * 3 + k] + fA * rv[k];
-                    double xi = cen - fA * s->a * Rpp * e;
-                    double xj = cen + fB * s->a * Rpp * e;
+                    double xi = cen - fA * s->a * Rpp * e[k];
+                    double xj = cen + fB * s->a * Rpp * e[k];
                     s->x[i * 3 + k] = wrap_store(s, xi, s->p.box[k]);
                     s->x[j * 3 + k] = wrap_store(s, xj, s->p.box[k]);
                 }
@@ -1075,6 +1143,7 @@ void orc_sim_step(orc_sim *s)
             ds->preac = reac_prob(s, Rpp, 1.0);
             uint32_t cg[4] = {(uint32_t)c, NOSLOT, stp, TAG_GEM};
             orc_philox4x32_10(cg, s->key, w);
+            ds->draw = w[0];
             if (orc_u01(w[0]) < ds->preac) {
                 ds->recombined = 1;
                 s->st[ORC_ST_GEMINATE]++;

@@ -57,7 +57,8 @@ void orc_m2x(double R, double R0, double tau, double out[2]);             /* int
 double orc_penc2x(double R, double R0, double tau);
 double orc_preac2x(double R, double R0, double tau, double hh);
 double orc_sample_prop2x(double R0, double tau, double u);                /* inversion, one uniform */
-double orc_x2_switch(double tau);  /* R0 above which the exact 2D mode uses the small-time expansions */
+double orc_x2_switch(double tau);  /* R0 above which the exact 2D mode takes p_enc, p_reac from the expansions */
+double orc_x2_prop_switch(double tau);  /* R0 above which it draws R'' from the expansion's propagator */
 /* ---- radial propagator sampler (Sec. 3, Details; Sec. 2.2.2) ---- */
 /* Draws R'' >= 1 from w_d r^{d-1}(g_ref - g_abs)(.|R0) by keyed rejection.
  * ctr[3] low byte is the tag; the attempt index is put in its upper 24 bits. */
@@ -87,12 +88,15 @@ typedef struct {
     uint64_t seed;
     uint32_t replica;
     int32_t exact2d;    /* 2D: 1 = exact radial functions by quadrature, 0 = small-time expansions */
+    int32_t keep_dir;   /* 1: a propagated pair keeps the direction of its free end point (no angle draw) */
 } orc_params;
 
 typedef struct { uint32_t i, j; double R, R0, p; uint32_t draw; int32_t cand; } orc_pair;
 typedef struct { uint32_t i, j; double p; } orc_pick;
-typedef struct { uint32_t i, j; int32_t reacted; uint32_t attempts; double Rpp, preac; } orc_match;
-typedef struct { uint32_t c, j; int32_t decayed, recombined; uint32_t attempts; double Rpp, preac; } orc_diss;
+/* draw: the reaction (matches) or geminate (decays) test's Philox word; cos_theta: the cosine
+ * of the angle between a propagated pair's separations before and after, NaN if none drawn */
+typedef struct { uint32_t i, j; int32_t reacted; uint32_t attempts, draw, pad; double Rpp, preac, cos_theta; } orc_match;
+typedef struct { uint32_t c, j; int32_t decayed, recombined; uint32_t attempts, draw; double Rpp, preac; } orc_diss;
 
 enum {
     ORC_ST_PAIRS = 0, ORC_ST_CAND, ORC_ST_OVERLAP, ORC_ST_R0CLAMP, ORC_ST_PICKS, ORC_ST_MATCHES,

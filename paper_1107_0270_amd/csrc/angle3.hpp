@@ -24,10 +24,9 @@
 //     a node stops adding orders once |Y_nu(x)| exceeds 2^500 (its products are
 //     then below 1e-220, and A^2 + B^2 stays finite);
 //   - pairs with R + R0 - 2 > 40 sqrt(tau) (beyond any encounter) or not a number give NaN;
-//   - inversion: nine rounds of a 65-way search over [-1, 1] (one point per lane),
-//     a final interval of 2 / 65^9 < 1.1e-16.
-// One wavefront per pair, lanes over the quadrature nodes; the per-order sums are
-// reduced over the wave, so every lane holds every w_n.
+//   - inversion: the root of F(c) = u by a search over [-1, 1].
+// This file holds the series' pieces (terms, Bessel recurrences, F); the kernels that
+// lay a pair's nodes over a workgroup and draw the angle are in angle_wg.hpp.
 #pragma once
 
 #include "kernels.hpp"
@@ -111,87 +110,6 @@ __device__ __forceinline__ double ang_cdf(const double *W, int N, double c)
         p = pn1;
     }
     return 0.5 * s;
-}
-
-__global__ __launch_bounds__(BLOCK) void k_angle3(double tau, uint64_t n, const double *__restrict__ Rv,
-                                                  const double *__restrict__ R0v, const double *__restrict__ uv,
-                                                  double *__restrict__ c_out, GL16 gl)
-{
-    constexpr int NW = BLOCK / 64;
-    __shared__ double wsh[NW][ANG_NCAP + 1];
-    const int lane = lane_id();
-    double *W = wsh[threadIdx.x / 64];
-    const uint64_t nwaves = (uint64_t)gridDim.x * NW;
-    for (uint64_t i = (uint64_t)blockIdx.x * NW + threadIdx.x / 64; i < n; i += nwaves) {  // uniform over the wave
-        const double Rin = Rv[i], R0in = R0v[i], u = uv[i];
-        if (!(Rin + R0in - 2.0 <= 40.0 * sqrt(tau))) {  // no encounter reaches that far (e^{-400}), or not a number
-            if (lane == 0) c_out[i] = __builtin_nan("");
-            continue;
-        }
-        const double R = fmax(Rin, 1.0), R0 = fmax(R0in, 1.0);  // separations below contact count as contact
-        const int N = ang_terms(R, R0, tau);
-        const double X = sqrt(50.0 / tau);
-        const double hmax = fmin(1.0, 2.0 * PI_D / (R + R0 - 1.0));
-        const int P = (int)ceil(X / hmax);
-        const double h = X / P;
-        for (int k = 0; k <= N; ++k) W[k] = 0.0;
-        for (int q0 = 0; q0 < 16 * P; q0 += 64) {  // uniform over the wave
-            const int q = q0 + lane;
-            const bool live = q < 16 * P;
-            const int qq = live ? q : 0;
-            const double x = h * ((qq >> 4) + 0.5 + 0.5 * gl.x[qq & 15]);
-            const double g = live ? 0.5 * h * gl.w[qq & 15] * exp(-tau * x * x) * x : 0.0;
-            double t[3][ANG_NCAP + 2], lam[3];
-            const double z[3] = {x, R * x, R0 * x};
-            ang_miller3(N + 1, z, t, lam);
-            double ym[3], y0[3], iz[3];  // Y_{nu-1}, Y_nu, 1/z
-            for (int j = 0; j < 3; ++j) {
-                double s0, c0;
-                sincos(z[j], &s0, &c0);
-                const double s = sqrt(2.0 / (PI_D * z[j]));
-                ym[j] = s * s0;   // Y_{-1/2}
-                y0[j] = -s * c0;  // Y_{1/2}
-                iz[j] = 1.0 / z[j];
-            }
-            bool dead = !live;
-            double jm = lam[0] * t[0][0];  // J_{nu-1}(x)
-            for (int nn = 0; nn <= N; ++nn) {  // uniform over the wave
-                const int k = nn + 1;
-                if (fabs(y0[0]) > 0x1p500) dead = true;
-                double term = 0.0;
-                const double jx = lam[0] * t[0][k];
-                if (!dead) {
-                    // F(R) F(R0) = (J(Rx) A - Y(Rx) B)(J(R0x) A - Y(R0x) B) / (A^2 + B^2)
-                    const double jr = lam[1] * t[1][k], jq = lam[2] * t[2][k];
-                    const double Ar = (2.0 * nn + 2.0) * y0[0] - 2.0 * x * ym[0];
-                    const double Br = (2.0 * nn + 2.0) * jx - 2.0 * x * jm;
-                    const double Aa = y0[0], Ba = jx;
-                    const double pr = (jr * Ar - y0[1] * Br) / (Ar * Ar + Br * Br) * (jq * Ar - y0[2] * Br);
-                    const double pa = (jr * Aa - y0[1] * Ba) / (Aa * Aa + Ba * Ba) * (jq * Aa - y0[2] * Ba);
-                    term = g * (pr - pa);
-                }
-                jm = jx;
-                W[nn] += wave_allsum(term);  // every lane writes the same value and reads its own
-                for (int j = 0; j < 3; ++j) {  // Y_{nu+1} = (2 nu / z) Y_nu - Y_{nu-1}
-                    const double yn = (2.0 * k - 1.0) * iz[j] * y0[j] - ym[j];
-                    ym[j] = y0[j];
-                    y0[j] = yn;
-                }
-            }
-        }
-        double lo = -1.0, hi = 1.0;
-        for (int it = 0; it < 9; ++it) {
-            const double d = (hi - lo) / 65.0;
-            const double c = lo + d * (lane + 1);
-            const u64 ge = __ballot(ang_cdf(W, N, c) >= u);
-            const int j = ge ? __ffsll((unsigned long long)ge) - 1 : 64;  // first point at or above u
-            const double nlo = j == 0 ? lo : lo + d * j;
-            const double nhi = j == 64 ? hi : lo + d * (j + 1);
-            lo = nlo;
-            hi = nhi;
-        }
-        if (lane == 0) c_out[i] = 0.5 * (lo + hi);
-    }
 }
 
 } // namespace gfbd

@@ -23,7 +23,7 @@ __host__ __device__ inline u32 meta_slot(u32 m) { return m & SLOT_MASK; }
 // Counter word 3: tag in the low byte, rejection-attempt index above it.
 enum : u32 {
     TAG_MOVE = 1, TAG_ENC = 2, TAG_SELA = 3, TAG_SELB = 4, TAG_PROP = 5, TAG_REAC = 6,
-    TAG_UNI = 7, TAG_DPROP = 8, TAG_DIR = 9, TAG_GEM = 10, TAG_FPT = 11, TAG_FPTU = 12
+    TAG_UNI = 7, TAG_DPROP = 8, TAG_DIR = 9, TAG_GEM = 10, TAG_FPT = 11, TAG_FPTU = 12, TAG_ANG = 13
 };
 
 // Arithmetic of the pair probability: binary64 throughout, binary32, or
@@ -100,6 +100,7 @@ struct Params {
     int bc;          // 0 absorbing, 1 reflecting, 2 radiation
     int reversible;  // k_off > 0
     int n_terms;     // 2D expansion order
+    int angles;      // propagated pairs draw their angle to the old separation (else keep the free direction)
     double L[3], Lh[3];
     double cs[3];    // cells per um along each axis (n / L)
     double ce[3];    // cell edge along each axis (L / n)
@@ -125,10 +126,11 @@ struct Params {
     const double *g2c;  // 2D constants: a_k(0), Q_abs, Q_ref, Q_rad (4 x (MAXTERMS+1))
     // exact 2D radial functions (green2x.hpp): tables over R = 1 + i h (i < x2_nr) and
     // R0 = 1 + 2 j h (j < x2_n0), column j contiguous: p_enc, p_reac, propagator distribution;
-    // pairs with R0 > x2_r0sw take the small-time expansions
+    // pairs with R0 > x2_r0sw take p_enc and p_reac from the small-time expansions, pairs with
+    // R0 > x2_r0sw_prop their propagation
     const double *x2_enc, *x2_reac, *x2_cdf;
-    double x2_h, x2_inv_h, x2_inv_h0, x2_r0sw;
-    u32 x2_nr, x2_n0;
+    double x2_h, x2_inv_h, x2_inv_h0, x2_r0sw, x2_r0sw_prop;
+    u32 x2_nr, x2_n0, x2_n0_prop;  // rows, columns; columns the propagator's interpolation may read
     // Batches of independent replicas: replica r owns slots [slot_base,
     // slot_base + n) and cells [cell_base, cell_base + own cell count) of
     // every species block.  A single system is replica 0 with both bases 0.
@@ -199,7 +201,7 @@ enum : u32 { PE_PAIR = 0, PE_CAND = 1, PE_PICKED = 2 };
 // Debug log entries (same layout as the public sim_dbg_* structs).
 struct DbgPair { u32 i, j; double R, R0, p; u32 draw; int cand; };
 struct DbgPick { u32 i, j; double p; };
-struct DbgMatch { u32 i, j; int reacted; u32 attempts; double Rpp, preac; };
-struct DbgDiss { u32 c, j; int decayed, recombined; u32 attempts, pad; double Rpp, preac; };
+struct DbgMatch { u32 i, j; int reacted; u32 attempts, draw, pad; double Rpp, preac, cos_theta; };
+struct DbgDiss { u32 c, j; int decayed, recombined; u32 attempts, draw; double Rpp, preac; };
 
 } // namespace gfbd

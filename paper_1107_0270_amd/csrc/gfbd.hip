@@ -3,7 +3,7 @@
 // of one step (Sec. 3 of Pruestel & Meier-Schellersheim, arXiv:1107.0270).
 #include "../../include/gfbd.h"
 #include "kernels.hpp"
-#include "angle2.hpp"
+#include "angle_wg.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -151,6 +151,7 @@ struct Model {
     double box[3], dt, D[3], sigma, kappa, k_off, eps, rcut_req, cell_req;
     int pair_search;
     int green2d;
+    uint32_t flags;  // SIM_F_*
     u32 pair_blocks, event_blocks;  // launch shapes of the pair stage and the event kernel
     uint64_t seed;
     uint32_t replica;
@@ -218,6 +219,8 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     PairEnt *plist = nullptr;
     CandEnt *cand = nullptr;
     u32 *flag = nullptr, *nextA = nullptr, *nextB = nullptr, *ev = nullptr;
+    AngEnt *ang = nullptr;  // propagated pairs handed to the angle stage (null: directions kept)
+    GL16 gl16;              // 16-point Gauss-Legendre rule of the angular series
     u64 *headA = nullptr, *headB = nullptr;
     Counters *ctr = nullptr;
     Params *dparams = nullptr;  // device copy of P for kernels that call out-of-line functions
@@ -282,6 +285,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         P.bc = M.bc;
         P.reversible = M.k_off > 0.0;
         P.n_terms = M.n_terms;
+        P.angles = M.bc != SIM_BC_ABSORBING && !(M.flags & SIM_F_KEEP_DIRECTION);
         const double Deff = M.D[0] + M.D[1];
         P.a = M.sigma;
         P.inv_a = 1.0 / M.sigma;
@@ -458,8 +462,8 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     }
 
     // Tables of the exact 2D radial functions (green2x.hpp): R steps of
-    // h = sqrt(tau)/160 and R0 steps of 2h, R0 up to the switch 1 + 8.4
-    // sqrt(tau) (plus the interpolation stencil), R up to the larger of
+    // h = sqrt(tau)/160 and R0 steps of 2h, R0 up to the switch 1 + c
+    // sqrt(tau) (x2_switch_c; plus the interpolation stencil), R up to the larger of
     // r_cut/a and the switch plus L = 12 sqrt(tau) + 1, the top of the
     // propagator's distribution function.  Quadrature nodes: 16-point
     // Gauss-Legendre panels, geometric (ratio 2) from 2^-30/4 to 1/4 where the
@@ -468,8 +472,8 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     int build_x2()
     {
         const double tau = P.tau, st = P.sqrt_tau, h = st / 160.0, h0 = X2S * h;
-        if (!(tau <= 1.0)) return fail(SIM_EUNSUPPORTED, "exact 2D functions need tau = D_eff dt / a^2 <= 1");
-        const double r0sw = 1.0 + 8.4 * st, L = 12.0 * st + 1.0;
+        if (!(tau * (1.0 - 1e-9) <= X2_TAU_MAX)) return fail(SIM_EUNSUPPORTED, "exact 2D functions need tau = D_eff dt / a^2 <= 0.8");
+        const double r0sw = 1.0 + x2_switch_c(tau) * st, L = 12.0 * st + 1.0;
         const u32 n0 = (u32)std::ceil((r0sw - 1.0) / h0) + 4;
         const double r0top = 1.0 + (n0 - 1) * h0;
         const double rtop = std::max(P.rcut / P.a, r0top + L) + 4.0 * h;
@@ -538,6 +542,8 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         P.x2_inv_h = 1.0 / h;
         P.x2_inv_h0 = 1.0 / h0;
         P.x2_r0sw = r0sw;
+        P.x2_r0sw_prop = 1.0 + 8.4 * st;  // the propagator's mass is resolved to about erfc(4.2)
+        P.x2_n0_prop = std::min<u32>(n0, (u32)std::ceil(8.4 * st / h0) + 4);
         P.x2_nr = nr;
         P.x2_n0 = n0;
         x2_build = {(double)K, (double)nr, (double)n0};
@@ -667,8 +673,10 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             (rc = alloc(plist, P.cap_pl)) || (rc = alloc(cand, P.cap_pl)) || (rc = alloc(flag, P.cap_pl)) ||
             (rc = alloc(nextA, P.cap_pl)) || (rc = alloc(nextB, P.cap_pl)) || (rc = alloc(headA, n)) ||
             (rc = alloc(headB, n)) || (rc = alloc(ev, n)) || (rc = alloc(ctr, 1)) || (rc = alloc(g2c, 4 * (MAXTERMS + 1))) ||
-            (rc = alloc(g_pos, n * DIM)) || (rc = alloc(g_sp, n)) || (batch && (rc = alloc(nkey, n))))
+            (rc = alloc(g_pos, n * DIM)) || (rc = alloc(g_sp, n)) || (batch && (rc = alloc(nkey, n))) ||
+            (P.angles && (rc = alloc(ang, n))))
             return rc;
+        gauss_legendre16(gl16.x, gl16.w);
         if (M.debug) {
             if ((rc = alloc(dbg_moved, n * DIM)) || (rc = alloc(dbg_cells, n)) || (rc = alloc(dbg_pairs, M.dbg_cap)) ||
                 (rc = alloc(dbg_picks, M.dbg_cap)) || (rc = alloc(dbg_matches, M.dbg_cap)) || (rc = alloc(dbg_diss, M.dbg_cap)))
@@ -976,9 +984,14 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             k_select_b<T, BATCH><<<nb_sel + nb_dec, BLOCK, 0, st>>>(P, plist, cand, flag, headB, nextB, out, start, okey, ev, ctr, nb_sel);
         });
         launch(SIM_K_EVENTS, [&] {
-            k_events<DIM, T, NC2, BATCH><<<M.event_blocks, BLOCK, 0, st>>>(dparams, out, plist, cand, ev, partner, ctr, dbg_matches, dbg_diss);
-            k_close<<<1, 64, 0, st>>>(ctr);
+            k_events<DIM, T, NC2, BATCH><<<M.event_blocks, BLOCK, 0, st>>>(dparams, out, plist, cand, ev, partner, ctr, dbg_matches,
+                                                                           dbg_diss, ang);
         });
+        if (ang)
+            launch(SIM_K_ANGLES, [&] {
+                k_angles<DIM, T, PM, BATCH><<<M.event_blocks, AWG, 0, st>>>(dparams, out, ang, ctr, dbg_matches, gl16);
+            });
+        k_close<<<1, 64, 0, st>>>(ctr);
     }
 
     int one_step()
@@ -1055,11 +1068,8 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         if (n > 0xFFFFFFFFull) return fail(SIM_EINVAL, "at most 2^32 pairs");
         // below this the series needs more than its 160 terms (R R0 / tau > 500) and the
         // quadrature grows like 1 / sqrt(tau) nodes per pair
-        if (!(P.tau >= 2e-3)) return fail(SIM_EUNSUPPORTED, "the angular series is built for tau >= 2e-3");
-        GL16 gl;
-        gauss_legendre16(gl.x, gl.w);
-        if constexpr (DIM == 2) k_angle2<<<grid_for(64 * n, 8192), BLOCK, 0, M.stream>>>(P.tau, n, R, R0, u, out, gl);
-        else k_angle3<<<grid_for(64 * n, 8192), BLOCK, 0, M.stream>>>(P.tau, n, R, R0, u, out, gl);
+        if (!(P.tau >= ANG_TAU_MIN)) return fail(SIM_EUNSUPPORTED, "the angular series is built for tau >= 2e-3");
+        k_angle_wg<DIM><<<(u32)std::min<uint64_t>(n, 16384), AWG, 0, M.stream>>>(P.tau, n, R, R0, u, out, gl16);
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipStreamSynchronize(M.stream));
         return SIM_OK;
@@ -1232,6 +1242,18 @@ int validate_state(int dim, bool reversible, uint64_t n, const int32_t *sp, cons
     return SIM_OK;
 }
 
+// The largest tau = D_eff dt / a^2 at which the 2D small-time expansion of order n holds p_enc and
+// p_reac to 1e-6: measured at contact (the worst place) against a numerical inversion of the
+// Laplace-domain forms of Sec. 4.2 (eqs. absPert, refPert, radPert), on the grid 0.005, 0.01, 0.02,
+// ..., 0.07, for intrinsic rates h up to 0.8.  Orders below 5 reach 1e-6 nowhere on it.
+double g2_tau_max(int n)
+{
+    static const double lim[33] = {0.0,  0.0,  0.0,  0.0,  0.0,  0.005, 0.01, 0.02, 0.03, 0.04, 0.04,
+                                   0.05, 0.05, 0.05, 0.06, 0.06, 0.06,  0.06, 0.06, 0.06, 0.07, 0.07,
+                                   0.07, 0.07, 0.07, 0.07, 0.07, 0.07,  0.07, 0.07, 0.07, 0.07, 0.07};
+    return n >= 0 && n <= 32 ? lim[n] : 0.0;
+}
+
 // Everything but the state.
 int validate_cfg(const sim_config *cfg, Model &M)
 {
@@ -1260,6 +1282,28 @@ int validate_cfg(const sim_config *cfg, Model &M)
     if (cfg->pair_search < SIM_PAIRS_AUTO || cfg->pair_search > SIM_PAIRS_DIRECT) { g_err = "unknown pair_search"; return SIM_EINVAL; }
     if (cfg->green2d != SIM_G2_EXPANSION && cfg->green2d != SIM_G2_EXACT) { g_err = "unknown green2d"; return SIM_EINVAL; }
     if (cfg->green2d == SIM_G2_EXACT && cfg->dim != 2) { g_err = "green2d = SIM_G2_EXACT is for 2D"; return SIM_EINVAL; }
+    if (cfg->flags & ~(uint32_t)(SIM_F_UNVALIDATED_TAU | SIM_F_KEEP_DIRECTION)) { g_err = "unknown flags"; return SIM_EINVAL; }
+    if (r.bc != SIM_BC_ABSORBING && !(cfg->flags & SIM_F_KEEP_DIRECTION) &&
+        !((cfg->species[0].D + cfg->species[1].D) * cfg->dt / (r.sigma * r.sigma) >= ANG_TAU_MIN)) {
+        g_err = "the angular propagator is built for tau = D_eff dt / a^2 >= 2e-3 (its series needs more than 160 terms "
+                "below): set SIM_F_KEEP_DIRECTION to keep the free end point's direction instead";
+        return SIM_EUNSUPPORTED;
+    }
+    if (cfg->dim == 2) {
+        // tau computed from the inputs may round just above a limit it equals (0.04, 0.8)
+        const double tau = (cfg->species[0].D + cfg->species[1].D) * cfg->dt / (r.sigma * r.sigma) * (1.0 - 1e-9);
+        const int nt = cfg->n_terms == 0 ? 12 : cfg->n_terms;
+        if (cfg->green2d == SIM_G2_EXACT && !(tau <= X2_TAU_MAX)) {
+            g_err = "exact 2D functions are validated for tau = D_eff dt / a^2 <= 0.8";
+            return SIM_EUNSUPPORTED;
+        }
+        if (cfg->green2d == SIM_G2_EXPANSION && !(cfg->flags & SIM_F_UNVALIDATED_TAU) && !(tau <= g2_tau_max(nt))) {
+            g_err = "the 2D small-time expansion of order " + std::to_string(nt) + " holds p_enc and p_reac to 1e-6 only for tau <= " +
+                    std::to_string(g2_tau_max(nt)) + " (tau = " + std::to_string(tau) +
+                    "): use green2d = SIM_G2_EXACT, a smaller dt or a higher order, or set SIM_F_UNVALIDATED_TAU";
+            return SIM_EUNSUPPORTED;
+        }
+    }
     if (cfg->pair_blocks != 0 && (cfg->pair_blocks < 8 || cfg->pair_blocks > 65536)) { g_err = "pair_blocks must be 0 or in [8, 65536]"; return SIM_EINVAL; }
     if (cfg->event_blocks < 0 || cfg->event_blocks > 65536) { g_err = "event_blocks must be in [0, 65536]"; return SIM_EINVAL; }
     M.dim = cfg->dim;
@@ -1276,6 +1320,7 @@ int validate_cfg(const sim_config *cfg, Model &M)
     M.cell_req = cfg->cell;
     M.pair_search = cfg->pair_search;
     M.green2d = cfg->green2d;
+    M.flags = cfg->flags;
     M.pair_blocks = cfg->pair_blocks ? (u32)cfg->pair_blocks : 1024u;
     M.event_blocks = cfg->event_blocks ? (u32)cfg->event_blocks : EV_BLOCKS;
     M.seed = cfg->seed;

@@ -341,7 +341,7 @@ template <int DIM, int NC>
 __device__ double sample_radius_wave(const Params &P, double R0, u32 c0, u32 c1, u32 step, u32 tag, u32 *attempts, u32 *hits)
 {
     if constexpr (DIM == 2 && NC == NC_EXACT) {
-        if (R0 > P.x2_r0sw) return sample_radius_wave<DIM, 0>(P, R0, c0, c1, step, tag, attempts, hits);
+        if (R0 > P.x2_r0sw_prop) return sample_radius_wave<DIM, 0>(P, R0, c0, c1, step, tag, attempts, hits);
         return sample_radius_x2(P, R0, c0, c1, step, tag, attempts, hits);
     }
     const PropSetup S = prop_setup<DIM>(P, R0);
@@ -372,7 +372,7 @@ template <int DIM, int NC>
 __device__ double sample_radius_lane(const Params &P, double R0, u32 c0, u32 c1, u32 step, u32 tag, u32 *attempts, u32 *hits)
 {
     if constexpr (DIM == 2 && NC == NC_EXACT) {
-        if (R0 > P.x2_r0sw) return sample_radius_lane<DIM, 0>(P, R0, c0, c1, step, tag, attempts, hits);
+        if (R0 > P.x2_r0sw_prop) return sample_radius_lane<DIM, 0>(P, R0, c0, c1, step, tag, attempts, hits);
         return sample_radius_x2(P, R0, c0, c1, step, tag, attempts, hits);
     }
     const PropSetup S = prop_setup<DIM>(P, R0);

@@ -20,15 +20,27 @@
 // with w_k the Gauss-Legendre weight times e^{-tau x_k^2}.  The tables are
 //   p_enc  = 1 - G_abs / g_free,   p_reac = (G_ref - G_rad) / (G_ref - G_abs),
 //   F      = (M_ref - M_abs)(R_i) / (M_ref - M_abs)(R0_j + L),  L = 12 sqrt(tau) + 1,
-// stored column by column (a column is one R0).  They cover R0 <= 1 + 8.4
-// sqrt(tau): there the propagator's mass 1 - S_abs(R0) stays above
-// erfc(4.2) ~ 3e-9, which the quadrature resolves; beyond it every pair has
-// x = (R + R0 - 2)/(2 sqrt tau) >= 4.2, where the small-time expansions hold.
+// stored column by column (a column is one R0).  They cover R0 <= 1 + c
+// sqrt(tau), c = 8.4 for tau <= 0.5 and 9 up to tau = 0.8: there the
+// propagator's mass 1 - S_abs(R0) stays above about erfc(c/2), which the
+// quadrature resolves; beyond it every pair has x = (R + R0 - 2)/(2 sqrt tau)
+// >= c/2, where the order-12 small-time expansion holds.  Against a numerical
+// inversion of the Laplace-domain forms of Sec. 4.2 both sides of the switch
+// hold 1e-6 for tau <= 0.5; from 0.5 to 0.8 the expansion's floor at contact
+// rises to about 1.3e-6 (higher orders do worse: the series is asymptotic) and
+// the quadrature loses resolution a little farther out, so c = 9 keeps both
+// within 1.5e-6.  The propagator's distribution function, a ratio of masses of
+// size 1 - S_abs(R0), keeps c = 8.4 at every tau (x2_r0sw_prop): beyond it the
+// expansion's rejection sampler draws R''.  tau > 0.8 is refused.
 // Included by green.hpp inside namespace gfbd, after i0e_d.
 #pragma once
 
 constexpr int NC_EXACT = -1;  // the order argument of the kernels that read the tables
 constexpr u32 X2S = 2;        // R0 grid step in R grid steps
+constexpr double X2_TAU_MAX = 0.8;  // largest tau of the exact 2D mode
+
+// c of the switch R0 = 1 + c sqrt(tau) between the tables and the expansion
+__host__ __device__ inline double x2_switch_c(double tau) { return tau <= 0.5 ? 8.4 : 9.0; }
 
 // Lagrange weights of the cubic through nodes 0, 1, 2, 3 at s.
 __device__ __forceinline__ void lag4(double s, double w[4])
@@ -82,7 +94,8 @@ __device__ inline double sample2x(const Params &P, double R0, double u)
 {
     double wj[4];
     const u32 nr = P.x2_nr;
-    const u32 bj = lag_base((R0 - 1.0) * P.x2_inv_h0, P.x2_n0, wj);
+    // the columns beyond the propagator's switch are not resolved for it: the stencil stays below
+    const u32 bj = lag_base((R0 - 1.0) * P.x2_inv_h0, P.x2_n0_prop, wj);
     const double *c = P.x2_cdf + (size_t)bj * nr;
     auto F = [&](u32 i) { return wj[0] * c[i] + wj[1] * c[nr + i] + wj[2] * c[2 * nr + i] + wj[3] * c[3 * nr + i]; };
     if (!(u > F(0))) return 1.0;

@@ -1390,9 +1390,15 @@ struct EvCount {
     u32 v[EV_ST];
 };
 
+// A propagated pair's hand-off to the angle stage (angle_wg.hpp); on = 0: no angle.
+struct AngEnt {
+    u32 ia, ib, on, dbg;
+    double Rpp, R0;
+};
+
 template <int DIM, class T, int NC, bool LANE>
 __device__ __forceinline__ EvCount ev_match(const Params &P, Rec<T> *__restrict__ rec, u32 ia, u32 ib, double R0,
-                                         u32 *__restrict__ partner, u32 step, Counters *C, DbgMatch *dbg)
+                                         u32 *__restrict__ partner, u32 step, Counters *C, DbgMatch *dbg, AngEnt *ang)
 {
 #pragma clang fp contract(off)
     Rec<T> ra = rec[ia], rb = rec[ib];
@@ -1409,17 +1415,17 @@ __device__ __forceinline__ EvCount ev_match(const Params &P, Rec<T> *__restrict_
     const double R = sqrt(r2) / P.a;
     bool react;
     double Rpp = R, preac = 1.0;
-    u32 att = 0, hits = 0, near = 0;
+    u32 att = 0, hits = 0, near = 0, wreac = 0;
     if (P.bc == 0) {
         react = true;
     } else {
         Rpp = LANE ? sample_radius_lane<DIM, NC>(P, R0, la, lb, step, TAG_PROP, &att, &hits)
                    : sample_radius_wave<DIM, NC>(P, R0, la, lb, step, TAG_PROP, &att, &hits);
         preac = reac_prob<NC>(P, DIM, Rpp, R0);
-        const u32 w = philox(la, lb, step, TAG_REAC, P.key).x;
-        react = below(w, preac);
-        near = fabs(u01(w) - preac) < 1e-6;
-        if (!react) {
+        wreac = philox(la, lb, step, TAG_REAC, P.key).x;
+        react = below(wreac, preac);
+        near = fabs(u01(wreac) - preac) < 1e-6;
+        if (!react && !P.angles) {  // keep the free end point's direction
             double rn = 0.0;
             for (int d = 0; d < DIM; ++d) rn += rv[d] * rv[d];
             rn = sqrt(rn);
@@ -1450,13 +1456,21 @@ __device__ __forceinline__ EvCount ev_match(const Params &P, Rec<T> *__restrict_
         cnt.v[1] = att;
         cnt.v[2] = hits;
         cnt.v[3] = near;
+        u32 q = NOSLOT;
         if (P.debug) {
-            const u32 q = atomicAdd(&C->n_dbg[2], 1u);
+            q = atomicAdd(&C->n_dbg[2], 1u);
             if (q < P.dbg_cap) {
                 DbgMatch d;
-                d.i = sa; d.j = sb; d.reacted = react; d.attempts = att; d.Rpp = Rpp; d.preac = preac;
+                d.i = sa; d.j = sb; d.reacted = react; d.attempts = att; d.draw = wreac; d.pad = 0;
+                d.Rpp = Rpp; d.preac = preac; d.cos_theta = __builtin_nan("");
                 dbg[q] = d;
             }
+        }
+        // the angle stage places a propagated pair (its post-move positions are left as they are)
+        if (ang) {
+            AngEnt g;
+            g.ia = ia; g.ib = ib; g.on = !react && P.angles; g.dbg = q; g.Rpp = Rpp; g.R0 = R0;
+            *ang = g;
         }
     }
     return cnt;
@@ -1474,7 +1488,8 @@ __device__ __forceinline__ EvCount ev_decay(const Params &P, Rec<T> *__restrict_
     const double Rpp = LANE ? sample_radius_lane<DIM, NC>(P, 1.0, lc, NOSLOT, step, TAG_DPROP, &att, &hits)
                             : sample_radius_wave<DIM, NC>(P, 1.0, lc, NOSLOT, step, TAG_DPROP, &att, &hits);
     const double preac = reac_prob<NC>(P, DIM, Rpp, 1.0);
-    const bool gem = below(philox(lc, NOSLOT, step, TAG_GEM, P.key).x, preac);
+    const u32 wgem = philox(lc, NOSLOT, step, TAG_GEM, P.key).x;
+    const bool gem = below(wgem, preac);
     const u32 sb = partner[sc];
     EvCount cnt = {{0, 0, 0, 0, 0, 0}};
     if (LANE || lane_id() == 0) {
@@ -1486,7 +1501,7 @@ __device__ __forceinline__ EvCount ev_decay(const Params &P, Rec<T> *__restrict_
             const u32 q = atomicAdd(&C->n_dbg[3], 1u);
             if (q < P.dbg_cap) {
                 DbgDiss d;
-                d.c = sc; d.j = sb; d.decayed = 1; d.recombined = gem; d.attempts = att; d.pad = 0; d.Rpp = Rpp; d.preac = preac;
+                d.c = sc; d.j = sb; d.decayed = 1; d.recombined = gem; d.attempts = att; d.draw = wgem; d.Rpp = Rpp; d.preac = preac;
                 dbg[q] = d;
             }
         }
@@ -1540,11 +1555,12 @@ template <bool BATCH, class T> __device__ __forceinline__ const Params &ev_param
     else return P;
 }
 
+// ang (null when no pair draws an angle): event w's hand-off to the angle stage.
 template <int DIM, class T, int NC, bool BATCH>
 __global__ __launch_bounds__(BLOCK) void k_events(const Params *__restrict__ Pd, Rec<T> *__restrict__ rec,
                                                    const PairEnt *__restrict__ list, const CandEnt *__restrict__ cand,
                                                    const u32 *__restrict__ ev, u32 *__restrict__ partner, Counters *C,
-                                                   DbgMatch *dbg_m, DbgDiss *dbg_d)
+                                                   DbgMatch *dbg_m, DbgDiss *dbg_d, AngEnt *ang)
 {
     __shared__ u32 lds[BLOCK / 64];
     const Params &P = *Pd;
@@ -1563,9 +1579,10 @@ __global__ __launch_bounds__(BLOCK) void k_events(const Params *__restrict__ Pd,
             if (e & EV_DECAY) {
                 const u32 i = e & ~EV_DECAY;
                 add(ev_decay<DIM, T, NC, true>(ev_params<BATCH>(P, rec, i), rec, i, partner, step, C, dbg_d));
+                if (ang) ang[w].on = 0;
             } else {
                 add(ev_match<DIM, T, NC, true>(rep_params<BATCH>(P, cand[e].a_slot), rec, list[e].a_idx, list[e].b_idx,
-                                               cand[e].R0, partner, step, C, dbg_m));
+                                               cand[e].R0, partner, step, C, dbg_m, ang ? ang + w : nullptr));
             }
         }
     } else {
@@ -1575,9 +1592,10 @@ __global__ __launch_bounds__(BLOCK) void k_events(const Params *__restrict__ Pd,
             if (e & EV_DECAY) {
                 const u32 i = e & ~EV_DECAY;
                 add(ev_decay<DIM, T, NC, false>(ev_params<BATCH>(P, rec, i), rec, i, partner, step, C, dbg_d));
+                if (ang && lane_id() == 0) ang[w].on = 0;
             } else {
                 add(ev_match<DIM, T, NC, false>(rep_params<BATCH>(P, cand[e].a_slot), rec, list[e].a_idx, list[e].b_idx,
-                                                cand[e].R0, partner, step, C, dbg_m));
+                                                cand[e].R0, partner, step, C, dbg_m, ang ? ang + w : nullptr));
             }
         }
     }

@@ -20,19 +20,20 @@ BC_ABSORBING, BC_REFLECTING, BC_RADIATION = 0, 1, 2
 PREC_FP64, PREC_FP32, PREC_FP32_FP64NC = 0, 1, 2
 PAIRS_AUTO, PAIRS_BRICKS, PAIRS_DIRECT = 0, 1, 2
 G2_EXPANSION, G2_EXACT = 0, 1
+F_UNVALIDATED_TAU, F_KEEP_DIRECTION = 1, 2
 (READ_POS, READ_SPECIES, READ_PARTNER, READ_COUNTS, READ_STATS, READ_STATS_SUM, READ_DERIVED, READ_DBG_MOVED,
  READ_DBG_PAIRS, READ_DBG_PICKS, READ_DBG_MATCHES, READ_DBG_DISS, READ_DBG_CELLS, READ_TIMING, READ_GRID) = range(15)
 STAT_NAMES = ["pairs", "cand", "overlap", "r0clamp", "picks", "matches", "react", "decay", "geminate",
               "attempts", "bound_hits", "near", "lds_fallback"]
-KERNEL_NAMES = ["move", "scan", "scatter", "pairs", "eval", "select_a", "select_b", "events"]
+KERNEL_NAMES = ["move", "scan", "scatter", "pairs", "eval", "select_a", "select_b", "events", "angles"]
 
 PAIR_DT = np.dtype([("i", "<u4"), ("j", "<u4"), ("R", "<f8"), ("R0", "<f8"), ("p", "<f8"),
                     ("draw", "<u4"), ("cand", "<i4")], align=True)
 PICK_DT = np.dtype([("i", "<u4"), ("j", "<u4"), ("p", "<f8")], align=True)
-MATCH_DT = np.dtype([("i", "<u4"), ("j", "<u4"), ("reacted", "<i4"), ("attempts", "<u4"),
-                     ("Rpp", "<f8"), ("preac", "<f8")], align=True)
+MATCH_DT = np.dtype([("i", "<u4"), ("j", "<u4"), ("reacted", "<i4"), ("attempts", "<u4"), ("draw", "<u4"),
+                     ("pad", "<u4"), ("Rpp", "<f8"), ("preac", "<f8"), ("cos_theta", "<f8")], align=True)
 DISS_DT = np.dtype([("c", "<u4"), ("j", "<u4"), ("decayed", "<i4"), ("recombined", "<i4"),
-                    ("attempts", "<u4"), ("pad", "<u4"), ("Rpp", "<f8"), ("preac", "<f8")], align=True)
+                    ("attempts", "<u4"), ("draw", "<u4"), ("Rpp", "<f8"), ("preac", "<f8")], align=True)
 
 
 class SimSpecies(C.Structure):
@@ -56,7 +57,7 @@ class SimConfig(C.Structure):
                 ("species", C.POINTER(SimSpecies)), ("n_reactions", C.c_int32),
                 ("reactions", C.POINTER(SimReaction)), ("debug", C.c_uint32), ("timing", C.c_uint32),
                 ("debug_cap", C.c_uint64), ("hip_stream", C.c_void_p), ("green2d", C.c_int32),
-                ("pair_blocks", C.c_int32), ("event_blocks", C.c_int32), ("reserved", C.c_int32)]
+                ("pair_blocks", C.c_int32), ("event_blocks", C.c_int32), ("flags", C.c_uint32)]
 
 
 _hip_rt = None
@@ -184,11 +185,11 @@ class Sim:
     def __init__(self, *, dim, box, dt, D, sigma, bc, species, pos, kappa=0.0, k_off=0.0,
                  precision=PREC_FP32_FP64NC, seed=0, replica=0, n_terms=12, eps_cut=1e-3, rcut=0.0, cell=0.0,
                  pair_search=PAIRS_AUTO, partner=None, debug=False, timing=False, debug_cap=0, stream=None,
-                 green2d=G2_EXPANSION, pair_blocks=0, event_blocks=0):
+                 green2d=G2_EXPANSION, pair_blocks=0, event_blocks=0, flags=0):
         self._config(dim=dim, box=box, dt=dt, D=D, sigma=sigma, bc=bc, species=species, pos=pos, kappa=kappa,
                      k_off=k_off, precision=precision, seed=seed, replica=replica, n_terms=n_terms, eps_cut=eps_cut,
                      rcut=rcut, cell=cell, pair_search=pair_search, debug=debug, timing=timing, debug_cap=debug_cap,
-                     stream=stream, green2d=green2d, pair_blocks=pair_blocks, event_blocks=event_blocks)
+                     stream=stream, green2d=green2d, pair_blocks=pair_blocks, event_blocks=event_blocks, flags=flags)
         L = lib()
         cfg = self.cfg
         sp = np.ascontiguousarray(species, dtype=np.int32)
@@ -208,7 +209,7 @@ class Sim:
     def _config(self, *, dim, box, dt, D, sigma, bc, species, pos, kappa=0.0, k_off=0.0,
                 precision=PREC_FP32_FP64NC, seed=0, replica=0, n_terms=12, eps_cut=1e-3, rcut=0.0, cell=0.0,
                 pair_search=PAIRS_AUTO, debug=False, timing=False, debug_cap=0, stream=None, green2d=G2_EXPANSION,
-                pair_blocks=0, event_blocks=0):
+                pair_blocks=0, event_blocks=0, flags=0):
         cfg = SimConfig()
         cfg.dim, cfg.precision = int(dim), int(precision)
         bx = list(box) if np.ndim(box) else [float(box)] * int(dim)
@@ -229,6 +230,7 @@ class Sim:
         cfg.hip_stream = stream
         cfg.green2d = int(green2d)
         cfg.pair_blocks, cfg.event_blocks = int(pair_blocks), int(event_blocks)
+        cfg.flags = int(flags)
         self.cfg = cfg
         self.dim = int(dim)
 

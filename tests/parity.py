@@ -37,6 +37,8 @@ class Report:
     max_dp: float = 0.0
     max_dRpp: float = 0.0
     max_dpreac: float = 0.0
+    max_dcos: float = 0.0
+    angles: int = 0
     pair_set_mismatch: int = 0
     pair_set_near_cut: int = 0
     draw_mismatch: int = 0
@@ -49,17 +51,25 @@ class Report:
 
 
 def make_pair(*, dim, bc, box, dt, D, sigma, kappa, k_off, precision, species, pos, partner=None, seed=0,
-              n_terms=12, eps_cut=1e-3, rcut=0.0, cell=0.0, debug_cap=1 << 21, pair_search=S.PAIRS_AUTO, exact2d=False):
+              n_terms=12, eps_cut=1e-3, rcut=0.0, cell=0.0, debug_cap=1 << 21, pair_search=S.PAIRS_AUTO, exact2d=False,
+              keep_direction=False):
     gpu = S.Sim(dim=dim, box=box, dt=dt, D=D, sigma=sigma, bc=bc, kappa=kappa, k_off=k_off, precision=precision,
                 seed=seed, n_terms=n_terms, eps_cut=eps_cut, rcut=rcut, cell=cell, species=species, pos=pos,
                 partner=partner, debug=True, debug_cap=debug_cap, pair_search=pair_search,
-                green2d=S.G2_EXACT if exact2d else S.G2_EXPANSION)
+                green2d=S.G2_EXACT if exact2d else S.G2_EXPANSION, flags=S.F_KEEP_DIRECTION if keep_direction else 0)
     if pair_search != S.PAIRS_AUTO and min(gpu.grid()[:dim]) >= 3:
         assert gpu.grid()[4] == pair_search
     orc = O.OracleSim(dim=dim, bc=bc, box=[box] * dim, dt=dt, D=D, sigma=sigma, kappa_a=kappa, k_off=k_off,
                       eps_cut=eps_cut, rcut=rcut, seed=seed, store_f32=precision != S.PREC_FP64, n_terms=n_terms,
-                      exact2d=exact2d, species=species, pos=pos, partner=partner)
+                      exact2d=exact2d, keep_direction=keep_direction, species=species, pos=pos, partner=partner)
     return gpu, orc
+
+
+def _near(draw, p, p_tol):
+    """True where the uniform (w + 1/2) 2^-32 of Philox word w lies within the tolerance of p, the
+    only place where the two sides may legitimately take different Bernoulli decisions."""
+    u = (draw.astype(np.float64) + 0.5) * 2.0 ** -32
+    return np.abs(u - p) < max(NEAR, 2 * p_tol)
 
 
 def _key(a, b):
@@ -104,8 +114,7 @@ def compare_step(gpu, orc, rep: Report, *, p_tol, pos_tol, box, rcut, sp_before,
         rep.draw_mismatch += int((g["draw"] != o["draw"]).sum())
         bad = g["cand"] != o["cand"]
         if bad.any():
-            u = (o["draw"][bad].astype(np.float64) + 0.5) * 2.0 ** -32
-            near = np.abs(u - o["p"][bad]) < max(NEAR, 2 * p_tol)
+            near = _near(o["draw"][bad], o["p"][bad], p_tol)
             rep.near_decisions += int(near.sum())
             rep.unexplained += int((~near).sum())
             decisions_ok = False
@@ -130,21 +139,46 @@ def compare_step(gpu, orc, rep: Report, *, p_tol, pos_tol, box, rcut, sp_before,
         elif len(gs):
             rep.max_dRpp = max(rep.max_dRpp, float(np.abs(gs["Rpp"] - os_["Rpp"]).max()))
             rep.max_dpreac = max(rep.max_dpreac, float(np.abs(gs["preac"] - os_["preac"]).max()))
+            rep.draw_mismatch += int((gs["draw"] != os_["draw"]).sum())
+            # the angle of each propagated pair (NaN where none was drawn, on both sides)
+            same = gs["reacted"] == os_["reacted"]
+            gn, on = np.isnan(gs["cos_theta"][same]), np.isnan(os_["cos_theta"][same])
+            if not np.array_equal(gn, on):
+                rep.notes.append(f"step {rep.steps}: angles drawn for different pairs")
+                rep.unexplained += 1
+            elif (~on).any():
+                d = np.abs(gs["cos_theta"][same][~on] - os_["cos_theta"][same][~on])
+                rep.max_dcos = max(rep.max_dcos, float(d.max()))
+                rep.angles += int((~on).sum())
+            # a reaction flag may differ only where the draw lies within the tolerance of p_reac
             badr = gs["reacted"] != os_["reacted"]
             if badr.any():
-                rep.near_decisions += int(badr.sum())
+                near = _near(os_["draw"][badr], os_["preac"][badr], p_tol)
+                rep.near_decisions += int(near.sum())
+                rep.unexplained += int((~near).sum())
+                if (~near).any():
+                    rep.notes.append(f"step {rep.steps}: reaction flags differ away from p_reac")
                 decisions_ok = False
     # 6. dissociations
     gd, od = gpu.dbg_diss(), orc.dissociations()
     rep.decays += len(od)
     if decisions_ok:
         gs, os_ = gd[np.argsort(gd["c"])], od[np.argsort(od["c"])]
-        if not (np.array_equal(gs["c"], os_["c"]) and np.array_equal(gs["recombined"], os_["recombined"])):
+        if not np.array_equal(gs["c"], os_["c"]):
             rep.notes.append(f"step {rep.steps}: dissociations differ")
             rep.unexplained += 1
             decisions_ok = False
         elif len(gs):
             rep.max_dRpp = max(rep.max_dRpp, float(np.abs(gs["Rpp"] - os_["Rpp"]).max()))
+            rep.draw_mismatch += int((gs["draw"] != os_["draw"]).sum())
+            badg = gs["recombined"] != os_["recombined"]
+            if badg.any():
+                near = _near(os_["draw"][badg], os_["preac"][badg], p_tol)
+                rep.near_decisions += int(near.sum())
+                rep.unexplained += int((~near).sum())
+                if (~near).any():
+                    rep.notes.append(f"step {rep.steps}: geminate flags differ away from p_reac")
+                decisions_ok = False
     # 7. state
     gsp, gpos, gpt = gpu.state()
     osp, opos, opt = orc.state()
@@ -172,7 +206,13 @@ def compare_step(gpu, orc, rep: Report, *, p_tol, pos_tol, box, rcut, sp_before,
     return osp
 
 
-def run(gpu, orc, steps, *, p_tol, pos_tol, box, lockstep=False):
+def run(gpu, orc, steps, *, p_tol, pos_tol, box, lockstep=None):
+    """lockstep: reload the GPU with the oracle's state after a step whose positions agree
+    within pos_tol but not bit for bit.  By default on wherever angles are drawn: the two
+    sides' roots of the angular distribution function differ in their last bits, which moves
+    binary64 positions by about 1e-14 and the next step's p_enc by about 1e-12."""
+    if lockstep is None:
+        lockstep = not orc.keep_direction
     rep = Report()
     rcut = orc.derived()["rcut"]
     sp, _, _ = orc.state()

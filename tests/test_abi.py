@@ -52,7 +52,7 @@ int main(void) {
          offsetof(sim_config, pair_search),
          sizeof(sim_reaction), sizeof(sim_dbg_pair), sizeof(sim_dbg_diss));
   printf("%zu %zu %zu %zu\n", offsetof(sim_config, green2d), offsetof(sim_config, pair_blocks),
-         offsetof(sim_config, event_blocks), offsetof(sim_config, reserved));
+         offsetof(sim_config, event_blocks), offsetof(sim_config, flags));
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(sim_dbg_pick), sizeof(sim_dbg_match), sizeof(sim_kernel_time),
          sizeof(sim_replica), offsetof(sim_replica, box), offsetof(sim_replica, replica));
   return 0; }
@@ -66,7 +66,7 @@ int main(void) {
                    C.sizeof(S.SimReaction),
                    S.PAIR_DT.itemsize, S.DISS_DT.itemsize]
     assert [int(x) for x in g.split()] == [S.SimConfig.green2d.offset, S.SimConfig.pair_blocks.offset,
-                                          S.SimConfig.event_blocks.offset, S.SimConfig.reserved.offset]
+                                          S.SimConfig.event_blocks.offset, S.SimConfig.flags.offset]
     assert [int(x) for x in b.split()] == [S.PICK_DT.itemsize, S.MATCH_DT.itemsize, 16, C.sizeof(S.SimReplica),
                                           S.SimReplica.box.offset, S.SimReplica.replica.offset]
 
@@ -77,6 +77,10 @@ def _args(**over):
               precision=S.PREC_FP64)
     kw.update(over)
     return kw
+
+
+# a 2D membrane system: D_eff = 0.2 um^2/s, sigma = 5 nm, so tau = 8000 dt / s
+MEM2D = dict(dim=2, D=(0.1, 0.1, 0.05), bc=S.BC_RADIATION, kappa=0.05, pos=np.array([[0.1, 0.1], [0.5, 0.5]]))
 
 
 @pytest.mark.parametrize("over,code", [
@@ -100,6 +104,15 @@ def _args(**over):
     (dict(event_blocks=65537), S.SIM_EINVAL),
     # C without a reserved partner in a reversible system
     (dict(species=np.array([2, 1], np.int32), k_off=1.0), S.SIM_EINVAL),
+    (dict(flags=4), S.SIM_EINVAL),
+    # 2D small-time expansion beyond the tau its order holds to 1e-6: the membrane workload as
+    # written (tau = 0.8), and orders 12 and 8 just above their limits 0.05 and 0.03
+    (dict(MEM2D, dt=1e-4), S.SIM_EUNSUPPORTED),
+    (dict(MEM2D, dt=6.5e-6), S.SIM_EUNSUPPORTED),
+    (dict(MEM2D, dt=4e-6, n_terms=8), S.SIM_EUNSUPPORTED),
+    (dict(MEM2D, dt=1e-5, n_terms=4), S.SIM_EUNSUPPORTED),
+    # exact 2D functions beyond tau = 0.8
+    (dict(MEM2D, dt=1.2e-4, green2d=S.G2_EXACT), S.SIM_EUNSUPPORTED),
 ])
 def test_invalid_input_is_rejected_before_the_device(over, code):
     if not os.path.exists(S.LIB_PATH):
@@ -176,3 +189,25 @@ def test_pool_calls_reject_null_arguments_on_the_host():
     assert L.sim_pool_admit(None, None, C.byref(m)) == S.SIM_EINVAL
     assert L.sim_pool_retire(None, 0) == S.SIM_EINVAL
     assert L.sim_pool_read(None, 0, S.READ_POS, None, 0, None) == S.SIM_EINVAL
+
+
+@pytest.mark.parametrize("dt,n_terms", [(6.0e-6, 12), (3.5e-6, 8), (5e-6, 10)])
+def test_expansion_within_its_tau_passes_validation(dt, n_terms):
+    # tau = 0.048 (order 12), 0.028 (order 8), 0.04 (order 10): within the limits, so the
+    # refusal above is not a blanket one; on a machine without a GPU creation then fails at
+    # the device, never with SIM_EUNSUPPORTED or SIM_EINVAL
+    if not os.path.exists(S.LIB_PATH):
+        pytest.skip("libgfbd.so not built")
+    try:
+        S.Sim(**_args(**dict(MEM2D, dt=dt, n_terms=n_terms))).close()
+    except S.SimError as e:
+        assert e.code not in (S.SIM_EUNSUPPORTED, S.SIM_EINVAL), str(e)
+
+
+def test_pool_of_2d_expansion_systems_beyond_its_tau_is_refused():
+    if not os.path.exists(S.LIB_PATH):
+        pytest.skip("libgfbd.so not built")
+    with pytest.raises(S.SimError) as e:
+        S.Pool(dim=2, box=1.0, slot_cap=100, cell_cap=100, rep_cap=2, dt=1e-4, D=(0.1, 0.1, 0.05), sigma=0.005,
+               bc=S.BC_RADIATION, k_off=1.0, precision=S.PREC_FP64)
+    assert e.value.code == S.SIM_EUNSUPPORTED

@@ -17,11 +17,11 @@ from paper_1107_0270_amd import sim as S
 pytestmark = pytest.mark.gpu
 
 
-def _handle(dt, D, sigma, dim=3):
+def _handle(dt, D, sigma, dim=3, flags=0):
     sp = np.array([0, 1], np.int32)
     pos = np.array([[0.25] * dim, [0.75] * dim])
     return S.Sim(dim=dim, box=1.0, dt=dt, D=(D, D, D), sigma=sigma, bc=O.BC_RAD, kappa=0.1, k_off=0.0,
-                 precision=S.PREC_FP64, seed=1, species=sp, pos=pos)
+                 precision=S.PREC_FP64, seed=1, species=sp, pos=pos, flags=flags)
 
 
 def _inputs(rng, n, tau, rmax):
@@ -88,7 +88,11 @@ def test_angle_matches_the_oracle(dt, D, sigma):
     print(f"tau {tau:.3g}: {len(R)} pairs, mean cos {c.mean():.4f}")
     _check(tau, R, R0, u, c)
     assert c[0] == pytest.approx(c[0])  # finite
-    assert c[5] < -0.999 and c[6] > 0.99999  # the two ends of the distribution
+    # the two ends of the distribution: u = 1e-300 and 1 - 2^-53 lie below the noise of F (its
+    # terms cancel to about 1e-16), so the draws must sit where F is within that noise of 0 and 1
+    for k, end in ((5, 0.0), (6, 1.0)):
+        w = O.angle3_coef(0, max(R[k], 1.0), max(R0[k], 1.0), tau)
+        assert abs(O.angle3_cdf(w, c[k]) - end) < 1e-12, (k, c[k])
 
 
 def test_full_size_launch_sampled_against_the_oracle():
@@ -112,7 +116,12 @@ def test_rejects_bad_arguments():
     assert e.value.code == S.SIM_EINVAL
     h.close()
     for dim in (3, 2):  # tau = 8e-4: more terms than the series keeps
-        h = _handle(1e-8, 1.0, 0.005, dim=dim)
+        # a step that would draw angles is refused at creation; one that keeps the free end
+        # point's direction is created, and its angle evaluation is refused
+        with pytest.raises(S.SimError) as e:
+            _handle(1e-8, 1.0, 0.005, dim=dim)
+        assert e.value.code == S.SIM_EUNSUPPORTED
+        h = _handle(1e-8, 1.0, 0.005, dim=dim, flags=S.F_KEEP_DIRECTION)
         assert h.derived()["tau"] < 2e-3
         with pytest.raises(S.SimError) as e:
             h.eval_angle(np.full(4, 1.01), np.full(4, 1.01), np.full(4, 0.5))

@@ -75,7 +75,7 @@ def test_exact_propagator_inverts_the_distribution_function(wave):
     seed, step = 13, 4
     h = _handle(1e-4, seed=seed)
     tau = h.derived()["tau"]
-    sw = O.x2_switch(tau)
+    sw = O.x2_prop_switch(tau)
     rng = np.random.default_rng(8)
     n = 200
     R0 = 1.0 + (sw - 1.0) * rng.random(n) ** 2
@@ -93,8 +93,16 @@ def test_exact_propagator_inverts_the_distribution_function(wave):
         top = r0 + 12 * math.sqrt(tau) + 1
         mt, m = O.m2x(top, r0, tau), O.m2x(Rg[i], r0, tau)
         errF = max(errF, abs((m[1] - m[0]) / (mt[1] - mt[0]) - u))
-        errR = max(errR, abs(Rg[i] - O.sample_prop2x(r0, tau, u)))
-    print(f"wave {wave}: max |F(R'') - u| {errF:.2e}, max |dR''| {errR:.2e}")
+        # R'' against the oracle's own inversion, in probability: |dR''| times the density there.
+        # At the switch the propagator's mass is about erfc(4.2) = 3e-9, which the two
+        # quadratures resolve to a few 1e-7 of F, so R'' itself is no better than that over the
+        # density (up to a few 1e-6 in R there).
+        Ro = O.sample_prop2x(r0, tau, u)
+        e = 1e-5
+        dens = (O.m2x(Ro + e, r0, tau)[1] - O.m2x(Ro + e, r0, tau)[0] - O.m2x(Ro - e, r0, tau)[1]
+                + O.m2x(Ro - e, r0, tau)[0]) / (2 * e * (mt[1] - mt[0]))
+        errR = max(errR, abs(Rg[i] - Ro) * dens)
+    print(f"wave {wave}: max |F(R'') - u| {errF:.2e}, max |dR''| x density {errR:.2e}")
     assert errF <= 1e-6 and errR <= 1e-6
     h.close()
 

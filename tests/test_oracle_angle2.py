@@ -126,3 +126,24 @@ def test_distribution_function_and_its_inverse(R, R0, tau):
 def test_out_of_range_pairs_give_nan():
     assert math.isnan(O.sample_angle2(1.0 + 41.0 * math.sqrt(0.04), 1.0, 0.04, 0.5))
     assert math.isnan(O.sample_angle2(float("nan"), 1.2, 0.04, 0.5))
+
+
+@pytest.mark.slow
+def test_step_propagation_matches_reflected_brownian_motion():
+    # The 2D counterpart of the 3D step-level pin (Sec. 3, Details; eq. genericGF): after one
+    # step of isolated pairs the propagated pairs' (R, cos theta) follow the planar reflected
+    # Brownian paths that met the circle, the side of the rotation is even (E[sin theta] = 0),
+    # and keeping the free end point's direction is rejected.  tau = 0.5 is beyond the
+    # small-time expansion, so the radial functions are the exact ones.
+    from .test_oracle_angle3 import _moment_z, _step_angles
+
+    tau, R0 = 0.5, 1.2
+    r, c = _reflected_paths(R0, tau, 300, 100000, 3)
+    wins = ((1.0, 1.3), (1.3, 1.7))
+    funcs = (lambda x: x, lambda x: 2.0 * x * x - 1.0)  # cos theta, cos 2 theta
+    R, cs, sn = _step_angles(2, tau, R0, 12000, False, 5, exact2d=True)
+    assert len(R) > 6000
+    assert _moment_z(R, cs, r, c, wins, funcs) < 4.0
+    assert abs(sn.mean()) < 4.0 * sn.std() / math.sqrt(len(sn))
+    R, cs, _ = _step_angles(2, tau, R0, 12000, True, 5, exact2d=True)
+    assert _moment_z(R, cs, r, c, wins, funcs) > 6.0

@@ -127,3 +127,61 @@ def test_terms_follow_the_angular_spread():
     assert O.angle3_terms(1.0, 1.0, 1e-4) == 160  # the cap
     w = O.angle3_coef(0, 1.4, 1.1, 0.08)
     assert abs(w[-1] / w[0]) < 1e-15  # the last term kept is negligible
+
+
+def _step_angles(dim, tau, R0, M, keep_direction, seed, **kw):
+    """One oracle step of M isolated pairs at separation R0 a (random orientations), reflecting
+    surface: the new radius and the cosine (and in 2D the sine) of the angle between each
+    propagated pair's separations before and after, from the positions."""
+    from .test_oracle_sim import _isolated_pairs
+
+    a, Deff = 0.005, 2.0
+    sp, pos, box = _isolated_pairs(M, 0.25, R0 * a, dim, seed=seed)
+    s = O.OracleSim(dim=dim, bc=O.BC_REF, box=[box] * dim, dt=tau * a * a / Deff, D=(1.0, 1.0, 0.5), sigma=a,
+                    eps_cut=1e-14, species=sp, pos=pos, seed=seed, keep_direction=keep_direction, **kw)
+    s.step()
+    _, x, _ = s.state()
+    mt = s.matches()
+    i, j = mt["i"].astype(np.int64), mt["j"].astype(np.int64)
+    mi = lambda d: d - box * np.round(d / box)
+    r0v, rn = mi(pos[j] - pos[i]), mi(x[j] - x[i])
+    n0, n1 = np.linalg.norm(r0v, axis=1), np.linalg.norm(rn, axis=1)
+    cs = (r0v * rn).sum(1) / (n0 * n1)
+    sn = (r0v[:, 0] * rn[:, 1] - r0v[:, 1] * rn[:, 0]) / (n0 * n1) if dim == 2 else None
+    R = n1 / a
+    assert np.abs(R - mt["Rpp"]).max() < 1e-9  # the placement has the drawn radius
+    if not keep_direction:
+        assert np.abs(cs - mt["cos_theta"]).max() < 1e-9  # and the drawn angle
+    return R, cs, sn
+
+
+def _moment_z(R, cs, r, c, windows, funcs):
+    """Largest |difference| of window moments between the step and the Monte Carlo, in
+    standard errors after a 0.006 allowance for the Monte Carlo's discretisation."""
+    zs = []
+    for lo, hi in windows:
+        sa, sb = (R >= lo) & (R < hi), (r >= lo) & (r < hi)
+        for f in funcs:
+            A, B = f(cs[sa]), f(c[sb])
+            d = max(abs(A.mean() - B.mean()) - 0.006, 0.0)
+            zs.append(d / math.sqrt(A.var() / len(A) + B.var() / len(B)))
+    return max(zs)
+
+
+@pytest.mark.slow
+def test_step_propagation_matches_reflected_brownian_motion():
+    # Step level (Sec. 3, Details): the matched pairs of one step, re-propagated from their
+    # pre-step separation R0 with the radius from w_3 r^2 (g_ref - g_abs) and the angle from
+    # J (G_ref - G_abs), end where reflected Brownian paths that met the sphere end: their
+    # (R, cos Theta) law is the normalised G_ref - G_abs.  The window moments E[P_1], E[P_2] of
+    # cos Theta agree with the Monte Carlo; keeping the free end point's direction (the
+    # reading this step replaced) does not.
+    tau, R0 = 0.5, 1.2
+    r, c = _reflected_paths(R0, tau, 300, 100000, 11)
+    wins = ((1.0, 1.3), (1.3, 1.7))
+    funcs = (lambda x: x, lambda x: 1.5 * x * x - 0.5)
+    R, cs, _ = _step_angles(3, tau, R0, 40000, False, 3)
+    assert len(R) > 20000
+    assert _moment_z(R, cs, r, c, wins, funcs) < 4.0
+    R, cs, _ = _step_angles(3, tau, R0, 40000, True, 3)
+    assert _moment_z(R, cs, r, c, wins, funcs) > 6.0

@@ -129,3 +129,81 @@ def test_large_h_reaction_probability():
     assert O.preac2x(R, R0, tau, 20.0) == pytest.approx((gref - grad) / (gref - gabs), rel=1e-7)
     assert O.preac2x(R, R0, tau, 1e7) == pytest.approx(1.0, abs=1e-5)
     assert abs(O.preac2(R, R0, tau, 20.0, 12)) > 10  # the expansion is useless there
+
+
+# ---------------------------------------------------------------------------
+# An independent reference beyond the quadrature's floor: the boundary parts of
+# the 2D radial Green's function in the Laplace domain (Sec. 4.2, eqs. absPert,
+# refPert, radPert; reduced units a = 1, D = 1) inverted numerically on Talbot's
+# contour (mpmath).  They are computed without subtracting the free part, so
+# they keep their relative precision where the x quadrature, which sums O(1)
+# oscillating terms to a result of size e^{-(R+R0-2)^2/4tau}, cannot.
+# ---------------------------------------------------------------------------
+def _laplace_probs(R, R0, tau, hh):
+    import mpmath as mp
+
+    mp.mp.dps = 15
+
+    def inv(kind):
+        def f(p):
+            q = mp.sqrt(p)
+            if kind == 0:
+                ratio = mp.besseli(0, q) / mp.besselk(0, q)
+            elif kind == 1:
+                ratio = -mp.besseli(1, q) / mp.besselk(1, q)
+            else:
+                ratio = (hh / q * mp.besseli(0, q) - mp.besseli(1, q)) / (hh / q * mp.besselk(0, q) + mp.besselk(1, q))
+            return -ratio * mp.besselk(0, q * R0) * mp.besselk(0, q * R) / (2 * mp.pi)
+
+        return mp.invertlaplace(f, tau, method="talbot")
+
+    ga, gr, gd = inv(0), inv(1), inv(2)
+    gf = mp.exp(-(R * R + R0 * R0) / (4 * tau)) * mp.besseli(0, R * R0 / (2 * tau)) / (4 * mp.pi * tau)  # Weber
+    return float(-ga / gf), float((gr - gd) / (gr - ga))
+
+
+def test_laplace_reference_agrees_with_scipy_quadrature():
+    # the reference itself, where scipy's quadrature resolves the boundary parts
+    R, R0, tau, hh = 1.05, 1.1, 0.04, 0.8
+    pe, pr = _laplace_probs(R, R0, tau, hh)
+    gf = O.g2_free(R, R0, tau)
+    ga, gr, gd = g2_exact(R, R0, tau, np.inf), g2_exact(R, R0, tau, 0.0), g2_exact(R, R0, tau, hh)
+    assert pe == pytest.approx(1.0 - ga / gf, abs=1e-9)
+    assert pr == pytest.approx((gr - gd) / (gr - ga), abs=1e-9)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("tau,tol", [(0.2, 1e-6), (0.5, 1e-6), (0.8, 1.5e-6)])
+def test_exact_mode_on_both_sides_of_its_switch(tau, tol):
+    # The exact 2D mode evaluates pairs with R0 <= x2_switch(tau) by quadrature and farther out
+    # by the order-12 expansion.  Just inside the switch and sqrt(tau) beyond it, both hold
+    # p_enc and p_reac to 1e-6 for tau <= 0.5 and to 1.5e-6 at tau = 0.8 near contact, where
+    # the expansion is weakest (h = 0.8, larger than the membrane workload's 0.04).
+    sw = O.x2_switch(tau)
+    assert sw == pytest.approx(1.0 + (8.4 if tau <= 0.5 else 9.0) * math.sqrt(tau))
+    hh = 0.8
+    for R0 in (sw - 0.5 * math.sqrt(tau), sw + math.sqrt(tau)):
+        for R in (1.0005, 1.3):
+            pe, pr = _laplace_probs(R, R0, tau, hh)
+            if R0 <= sw:
+                got = O.penc2x(R, R0, tau), O.preac2x(R, R0, tau, hh)
+            else:
+                got = O.penc2(R, R0, tau, 12), O.preac2(R, R0, tau, hh, 12)
+            assert abs(got[0] - pe) <= tol, (R, R0, got[0], pe)
+            assert abs(got[1] - pr) <= tol, (R, R0, got[1], pr)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("n,tau", [(8, 0.03), (12, 0.05)])
+def test_expansion_holds_1e6_up_to_its_tau_limit(n, tau):
+    # The library accepts the order-n expansion up to a tau that grows with n (8: 0.03,
+    # 12: 0.05; beyond it sim_create refuses the handle): at that limit it holds p_enc and
+    # p_reac to 1e-6 at contact, where it is weakest, and three orders fewer do not.
+    hh = 0.8
+    worst, worst_lower = 0.0, 0.0
+    for R, R0 in ((1.0005, 1.0005), (1.02, 1.1)):
+        pe, pr = _laplace_probs(R, R0, tau, hh)
+        worst = max(worst, abs(O.penc2(R, R0, tau, n) - pe), abs(O.preac2(R, R0, tau, hh, n) - pr))
+        worst_lower = max(worst_lower, abs(O.penc2(R, R0, tau, n - 3) - pe), abs(O.preac2(R, R0, tau, hh, n - 3) - pr))
+    assert worst <= 1e-6
+    assert worst_lower > 1e-6

@@ -251,3 +251,97 @@ def test_exact_2d_isolated_pairs_and_geminate_recombination():
     n = len(ds)
     assert n > 3000
     assert abs(ds["recombined"].sum() - Pg * n) < 4.5 * math.sqrt(n * Pg * (1 - Pg)), (ds["recombined"].sum() / n, Pg)
+
+
+def test_b_side_arbitration_is_proportional_to_p_enc():
+    # Sec. 3, Details: a B picked by several A's chooses one of them with probability
+    # p_enc / sum p_enc over those A's (the same cumulative rule as the A side).  Over many
+    # multi-pick B's of a dense system, the suitor with the largest p_enc must win as often as
+    # those weights predict; the same outcomes reject uniform weights and weights 1 - p_enc
+    # (z = 9 and 64 on this fixture), so the test has the power to see either mistake.
+    s = _sim(3, O.BC_RAD, 700, 700, 0.12, 0.006, D=(1.0, 1.0, 0.5), dt=4e-6, kappa_a=0.05, seed=5)
+    groups = []  # (p of each suitor, index of the winner)
+    for _ in range(80):
+        s.step()
+        pk, mt = s.picks(), s.matches()
+        won = {int(b): int(a) for a, b in zip(mt["i"], mt["j"])}
+        for b in np.unique(pk["j"]):
+            rows = pk[pk["j"] == b]
+            if len(rows) < 2:
+                continue
+            # suitors in ascending A slot, as the rule orders them
+            rows = rows[np.argsort(rows["i"])]
+            groups.append((rows["p"].copy(), int(np.nonzero(rows["i"] == won[int(b)])[0][0])))
+    assert len(groups) > 300
+    def score(weight):
+        # how often the suitor with the largest p_enc wins, against the weights' prediction, in
+        # standard errors (groups whose suitors have equal p_enc say nothing and are left out)
+        num = var = 0.0
+        for p, k in groups:
+            if p.max() - p.min() < 1e-9:
+                continue
+            w = weight(p)
+            h = int(np.argmax(p))
+            pr = w[h] / w.sum()
+            num += (k == h) - pr
+            var += pr * (1.0 - pr)
+        return num / math.sqrt(var)
+
+    assert abs(score(lambda p: p)) < 4.0
+    assert score(lambda p: np.ones_like(p)) > 5.0
+    assert score(lambda p: 1.0 - p + 1e-12) > 5.0
+
+
+@pytest.mark.parametrize("bc", [O.BC_RAD, O.BC_REF])
+def test_placement_keeps_the_diffusion_centre(bc):
+    # eq. Rcoo: the centre R = (D_B r_A + D_A r_B) / D_eff diffuses freely and independently of
+    # the separation (Sec. 2.1), so re-propagating an encountered pair changes only the
+    # separation: the centre of the post-move (free) positions is kept, the new separation has
+    # length a R'', and a reaction puts C at that centre.  D_A != D_B makes the weights matter
+    # (swapping them moves the centre).
+    M, a, dt = 3000, 0.005, 1e-5
+    D = (0.4, 1.6, 0.32)
+    sp, pos, box = _isolated_pairs(M, 0.25, 1.15 * a, 3, seed=11)
+    s = O.OracleSim(dim=3, bc=bc, box=[box] * 3, dt=dt, D=D, sigma=a, kappa_a=0.05 if bc == O.BC_RAD else 0.0,
+                    k_off=0.0, species=sp, pos=pos, seed=2)
+    fA, fB = D[0] / (D[0] + D[1]), D[1] / (D[0] + D[1])
+    mi = lambda d: d - box * np.round(d / box)
+    n_prop = n_react = 0
+    for _ in range(2):
+        s.step()
+        xm = s.moved()
+        spn, x, _ = s.state()
+        for m in s.matches():
+            i, j = int(m["i"]), int(m["j"])
+            cen = xm[i] + fA * mi(xm[j] - xm[i])
+            if m["reacted"]:
+                n_react += 1
+                assert spn[i] == O.SP_C
+                assert np.abs(mi(x[i] - cen)).max() < 1e-12
+            else:
+                n_prop += 1
+                sep = mi(x[j] - x[i])
+                assert np.linalg.norm(sep) == pytest.approx(a * m["Rpp"], rel=1e-12)
+                assert np.abs(mi(x[i] + fA * sep - cen)).max() < 1e-12
+    assert n_prop > 200
+    if bc == O.BC_RAD:
+        assert n_react > 5
+
+
+def test_immobile_a_never_moves():
+    # D_A = 0: the A's own displacement is zero and its weight D_A / D_eff in the placement is
+    # zero, so an A stays where it is through encounters, reactions (C at the centre, which is
+    # the A's position) and dissociations (D_C = D_A D_B / D_eff = 0).
+    M, a, dt = 2000, 0.005, 1e-5
+    sp, pos, box = _isolated_pairs(M, 0.25, 1.1 * a, 3, seed=12)
+    s = O.OracleSim(dim=3, bc=O.BC_RAD, box=[box] * 3, dt=dt, D=(0.0, 2.0, 0.0), sigma=a, kappa_a=0.05,
+                    k_off=3000.0, species=sp, pos=pos, seed=4)
+    _, x0, _ = s.state()
+    n_match = 0
+    for _ in range(4):
+        s.step()
+        n_match += len(s.matches())
+        spn, x, pt = s.state()
+        a_side = np.arange(M)  # slots of the A's (reacted ones hold C)
+        assert np.array_equal(x[a_side], x0[a_side])
+    assert n_match > 200
