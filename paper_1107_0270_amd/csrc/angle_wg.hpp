@@ -1,4 +1,4 @@
-// The angular propagator at step size: one workgroup of 256 threads per pair.
+// The angular propagator at step size: one workgroup of 128 threads per pair.
 //
 // After a non-reactive encounter the pair's new separation makes an angle Theta with
 // its pre-step separation drawn from J (G_ref - G_abs) given the new radius (Sec. 3,
@@ -8,112 +8,167 @@
 // what differs is how the work is laid out:
 //
 //   - the pair's quadrature nodes are spread over the workgroup, one node per thread
-//     (more than 256 nodes: batches of 256), so a pair's latency is about that of one
-//     node rather than of a wave's share of nodes;
+//     (more than 128 nodes: batches of 128), so a pair's latency is about that of one
+//     node.  A pair of the 3D workload at tau = 0.8 has exactly 128 nodes, and two
+//     workgroups fit a compute unit, so a step's few hundred pairs run at once;
 //   - the Bessel sequence J of a node comes from the downward recurrence, which yields
 //     it highest order first while the products need it lowest order first.  Instead
-//     of storing it per thread (per-lane scratch memory), the first sweep keeps the
-//     pair (J_k, J_{k+1}) at every eighth order k in registers (checkpoints), and the
-//     second pass regenerates each chunk of eight orders downward from its checkpoint,
-//     then consumes it upward beside the upward recurrence of Y.  Rescaling during the
-//     first sweep scales the checkpoints already kept, so every value is the same
-//     solution of the recurrence up to one common factor, removed by the normalisation
-//     to the elementary J_{-1/2}, J_{1/2} (3D) or to J_0, J_1 (2D).  This covers
-//     N <= ANG_FAST_N terms; pairs with more (small tau, far pairs) keep the stored
-//     sequence;
-//   - the per-order sums are reduced over each wave in a fixed order and added into
-//     the wave's own row of LDS; the rows are summed in wave order at the end, so the
+//     of storing the sequence per thread (per-lane scratch memory), the first sweep
+//     keeps the pair (J_k, J_{k+1}) at every sixteenth order k in the thread's column
+//     of LDS (checkpoints), and the second pass regenerates each chunk of sixteen
+//     orders downward from its checkpoint into registers, then consumes it upward
+//     beside the upward recurrence of Y.  Rescaling during the first sweep scales the
+//     checkpoints already kept, so every value is the same solution of the recurrence
+//     up to one common factor, removed by the normalisation to the elementary
+//     J_{-1/2}, J_{1/2} (3D) or to J_0, J_1 (2D).  Eleven checkpoints cover the series'
+//     cap of 160 terms;
+//   - each chunk's sixteen per-order terms are summed over the wave by a transposing
+//     reduction (halving the orders a lane holds at each exchange: 17 exchanges per
+//     chunk instead of 6 per order) and added into the wave's own row of LDS; the rows
+//     are summed in wave order at the end.  Every sum runs in a fixed order, so the
 //     coefficients, and the draw, do not depend on timing;
-//   - the root of F(.) = u is found by seven rounds of a 257-way search (one point per
-//     thread), an interval of 2 / 257^7 < 3e-17 (3D) or pi / 257^7 (2D).
+//   - the root of F(.) = u is found by eight rounds of a 129-way search (one point per
+//     thread), an interval of 2 / 129^8 < 3e-17 (3D) or pi / 129^8 (2D).
 #pragma once
 
 #include "angle2.hpp"
 
 namespace gfbd {
 
-constexpr int AWG = 256;               // threads per pair
+constexpr int AWG = 128;               // threads per pair
 constexpr int AW_NW = AWG / 64;        // waves per pair
-constexpr int ACS = 8;                 // orders per regenerated chunk
-constexpr int ANCK = 9;                // checkpoints kept in registers
-constexpr int ANG_FAST_N = ACS * ANCK - 2;  // most terms of the register form (orders 0 .. 71 stored)
+constexpr int ACS = 16;                // orders per regenerated chunk
+constexpr int ANCK = 11;               // checkpoints: orders 0 .. 175 (the cap needs 0 .. 161)
+static_assert(ACS * ANCK >= ANG_NCAP + 2, "checkpoints must cover the series' cap");
 // below this tau the series would need more than ANG_NCAP terms (R R0 / tau > 500 near
 // contact) and the quadrature grows like 1 / sqrt(tau) nodes per pair
 constexpr double ANG_TAU_MIN = 2e-3;
 
 struct AngShared {
+    double ck[ANCK][3][2][AWG];     // checkpoints of the J sequences, a column per thread
     double w[AW_NW][ANG_NCAP + 1];  // per-wave partial coefficient sums
     double W[ANG_NCAP + 1];         // the coefficients w_n
     int hit[AW_NW];
 };
 
+// 1/d from the hardware estimate refined by two Newton steps (the estimate's relative
+// error e becomes e^4): within an ulp or two of the correctly rounded quotient, at a
+// third of the cost of the IEEE division sequence.  d > 0 and finite here.
+__device__ __forceinline__ double ang_rcp(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+}
+
 // Coefficient of the downward step C_{k-1} = coef * C_k / z - C_{k+1}:
 // half-integer orders nu = k - 1/2 (3D): 2 nu = 2k - 1; integer orders (2D): 2k.
 template <int DIM> __device__ __forceinline__ double ang_coef(int k) { return DIM == 3 ? 2.0 * k - 1.0 : 2.0 * k; }
 
-// The terms of one node (x, weight g) for orders 0 .. N, register form: each order's
-// sum over the wave is added to wrow[order] by lane 0.  Uniform over the workgroup:
-// N; over the wave: every call.
-template <int DIM>
-__device__ __forceinline__ void ang_node_fast(double x, double g, bool live, double R, double R0, int N, double *wrow)
+// The distribution functions on normalised coefficients V (angle3.hpp, angle2.hpp):
+// 3D F(c) = (1 + c)/2 + sum_{n=1..N} V_n (P_{n+1}(c) - P_{n-1}(c)), V_n = w_n / (2 w_0);
+// 2D F(t) = t / pi + sum_{n=1..N} V_n sin(n t), V_n = 2 w_n / (n pi w_0).
+__device__ __forceinline__ double ang_cdf_n(const double *V, int N, double c)
 {
-    const int lane = lane_id();
+    double s = 0.5 * (1.0 + c), pm = 1.0, p = c;
+    for (int n = 1; n <= N; ++n) {
+        const double pn1 = ((2.0 * n + 1.0) * c * p - n * pm) * ANG_INV.v[n];  // Bonnet's recurrence
+        s += V[n] * (pn1 - pm);
+        pm = p;
+        p = pn1;
+    }
+    return s;
+}
+
+__device__ __forceinline__ double ang2_cdf_n(const double *V, int N, double t)
+{
+    const double c2 = 2.0 * cos(t);
+    double sm = 0.0, s = sin(t), acc = t * (1.0 / PI_D);  // sin((n-1) t), sin(n t) at n = 1
+    for (int n = 1; n <= N; ++n) {
+        acc += V[n] * s;
+        const double sn = c2 * s - sm;
+        sm = s;
+        s = sn;
+    }
+    return acc;
+}
+
+// One step of the transposing reduction: lanes that differ in bit `m` exchange the half
+// of their n values the other keeps, and add.  Afterwards lanes with bit m clear hold
+// the lower half, lanes with it set the upper half.
+template <int n>
+__device__ __forceinline__ void ang_fold(double *v, int lane, int m)
+{
+    const bool up = lane & m;
+#pragma unroll
+    for (int k = 0; k < n / 2; ++k) {
+        const double lo = v[k], hi = v[k + n / 2];
+        const double give = up ? lo : hi, keep = up ? hi : lo;
+        v[k] = keep + __shfl_xor(give, m, 64);
+    }
+}
+
+// The terms of one node (x, weight g) for orders 0 .. N: each order's sum over the wave
+// is added to wrow[order].  Uniform over the workgroup: N; over the wave: every call.
+template <int DIM>
+__device__ __forceinline__ void ang_node(double x, double g, bool live, double R, double R0, int N, double *wrow,
+                                         AngShared &sh)
+{
+    const int tid = threadIdx.x, lane = lane_id();
     // stored indices k: 3D C_k = J_{k-1/2}, k = 0 .. N + 1; 2D J_k, k = 0 .. N
     const int KT = DIM == 3 ? N + 2 : N + 1;
     const int nck = (KT + ACS - 1) / ACS;  // <= ANCK
     const double z[3] = {x, R * x, R0 * x};
     double inv[3], a[3], b[3];
-    double cka[3][ANCK], ckb[3][ANCK];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         inv[j] = 1.0 / z[j];
         a[j] = 1.0;  // C_m
         b[j] = 0.0;  // C_{m+1}
-#pragma unroll
-        for (int s = 0; s < ANCK; ++s) cka[j][s] = ckb[j][s] = 0.0;
     }
     // first sweep, from above both the last order and the turning point (as in angle3.hpp)
     const double zm = fmax(z[0], fmax(z[1], z[2]));
     const int zc = (int)ceil(zm + 8.0 * cbrt(zm));
     int m = (KT - 1 > zc ? KT - 1 : zc) + 8;
     if (m < ACS * nck) m = ACS * nck;
-    for (int k = m; k > ACS * nck; --k) {
+    for (int k = m; k > ACS * nck; --k) {  // nothing kept yet: rescale by selects, no branch
         const double cf = ang_coef<DIM>(k);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const double c = cf * inv[j] * a[j] - b[j];
-            b[j] = a[j];
-            a[j] = c;
-            if (fabs(c) > 1e250) {
-                a[j] *= 1e-250;
-                b[j] *= 1e-250;
-            }
+            const bool big = fabs(c) > 1e250;
+            b[j] = big ? a[j] * 1e-250 : a[j];
+            a[j] = big ? c * 1e-250 : c;
         }
     }
+    for (int s = nck - 1; s >= 0; --s) {
 #pragma unroll
-    for (int s = ANCK - 1; s >= 0; --s) {
-        if (s < nck) {
+        for (int j = 0; j < 3; ++j) {
+            sh.ck[s][j][0][tid] = a[j];  // C at order ACS (s + 1)
+            sh.ck[s][j][1][tid] = b[j];  // and ACS (s + 1) + 1
+        }
+        const double base = 2.0 * ACS * s;
+#pragma unroll
+        for (int i = ACS - 1; i >= 0; --i) {
+            const double cf = base + (DIM == 3 ? 2.0 * i + 1.0 : 2.0 * i + 2.0);  // of index ACS s + i + 1
+            double c[3];
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                cka[j][s] = a[j];  // C at order ACS (s + 1)
-                ckb[j][s] = b[j];  // and ACS (s + 1) + 1
+                c[j] = cf * inv[j] * a[j] - b[j];
+                b[j] = a[j];
+                a[j] = c[j];
             }
-#pragma unroll
-            for (int i = ACS - 1; i >= 0; --i) {
-                const double cf = ang_coef<DIM>(ACS * s + i + 1);
+            if (fmax(fabs(c[0]), fmax(fabs(c[1]), fabs(c[2]))) > 1e250) {  // rare: one test for the three
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
-                    const double c = cf * inv[j] * a[j] - b[j];
-                    b[j] = a[j];
-                    a[j] = c;
-                    if (fabs(c) > 1e250) {  // rescale, including the checkpoints kept so far
-                        a[j] *= 1e-250;
-                        b[j] *= 1e-250;
-#pragma unroll
-                        for (int t = s; t < ANCK; ++t) {
-                            cka[j][t] *= 1e-250;
-                            ckb[j][t] *= 1e-250;
-                        }
+                    if (!(fabs(c[j]) > 1e250)) continue;
+                    a[j] *= 1e-250;  // rescale, including the checkpoints kept so far
+                    b[j] *= 1e-250;
+                    for (int t = s; t < nck; ++t) {
+                        sh.ck[t][j][0][tid] *= 1e-250;
+                        sh.ck[t][j][1][tid] *= 1e-250;
                     }
                 }
             }
@@ -142,119 +197,72 @@ __device__ __forceinline__ void ang_node_fast(double x, double g, bool live, dou
     // J_{nu-1}(x) of the first order: 3D J_{-1/2} = lam C_0; 2D J_{-1} = -J_1
     double jm = DIM == 3 ? lam[0] * a[0] : -lam[0] * b[0];
     bool dead = !live;
+    for (int s = 0; s < nck; ++s) {
+        if (__ballot(!dead) == 0) break;  // every node of the wave is past its last order
+        // the chunk, normalised (the recurrence is linear, so scaling its two starting
+        // values scales every value it gives)
+        const double base = 2.0 * ACS * s;  // 2 k at the chunk's first order
+        double v[3][ACS];
 #pragma unroll
-    for (int s = 0; s < ANCK; ++s) {
-        if (s < nck && __ballot(!dead) != 0) {  // uniform over the wave
-            double v[3][ACS];
+        for (int j = 0; j < 3; ++j) {
+            double aa = lam[j] * sh.ck[s][j][0][tid], bb = lam[j] * sh.ck[s][j][1][tid];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                double aa = cka[j][s], bb = ckb[j][s];
-#pragma unroll
-                for (int i = ACS - 1; i >= 0; --i) {
-                    const double c = ang_coef<DIM>(ACS * s + i + 1) * inv[j] * aa - bb;
-                    bb = aa;
-                    aa = c;
-                    v[j][i] = c;  // C at order ACS s + i
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < ACS; ++i) {
-                const int k = ACS * s + i;
-                const int nn = DIM == 3 ? k - 1 : k;  // the series order this index serves
-                if (nn < 0 || nn > N) continue;      // uniform
-                if (fabs(y0[0]) > 0x1p500) dead = true;
-                const double jx = lam[0] * v[0][i];
-                double term = 0.0;
-                if (!dead) {
-                    // F(R) F(R0) = (J(Rx) A - Y(Rx) B)(J(R0x) A - Y(R0x) B) / (A^2 + B^2)
-                    const double jr = lam[1] * v[1][i], jq = lam[2] * v[2][i];
-                    double Ar, Br;
-                    if constexpr (DIM == 3) {
-                        Ar = (2.0 * nn + 2.0) * y0[0] - 2.0 * x * ym[0];
-                        Br = (2.0 * nn + 2.0) * jx - 2.0 * x * jm;
-                    } else {
-                        Ar = x * ym[0] - nn * y0[0];
-                        Br = x * jm - nn * jx;
-                    }
-                    const double Aa = y0[0], Ba = jx;
-                    const double pr = (jr * Ar - y0[1] * Br) / (Ar * Ar + Br * Br) * (jq * Ar - y0[2] * Br);
-                    const double pa = (jr * Aa - y0[1] * Ba) / (Aa * Aa + Ba * Ba) * (jq * Aa - y0[2] * Ba);
-                    term = g * (pr - pa);
-                }
-                jm = jx;
-                const double sum = wave_allsum(term);
-                if (lane == 0) wrow[nn] += sum;
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {  // Y_{nu+1} = (2 nu / z) Y_nu - Y_{nu-1}
-                    const double yn = (DIM == 3 ? 2.0 * nn + 1.0 : 2.0 * nn) * inv[j] * y0[j] - ym[j];
-                    ym[j] = y0[j];
-                    y0[j] = yn;
-                }
+            for (int i = ACS - 1; i >= 0; --i) {
+                const double cf = base + (DIM == 3 ? 2.0 * i + 1.0 : 2.0 * i + 2.0);  // of index ACS s + i + 1
+                const double c = cf * inv[j] * aa - bb;
+                bb = aa;
+                aa = c;
+                v[j][i] = c;  // J at index ACS s + i
             }
         }
-    }
-}
-
-// The same terms from a stored sequence (per-lane memory), for pairs with more terms
-// than the register form holds.
-template <int DIM>
-__device__ __noinline__ void ang_node_stored(double x, double g, bool live, double R, double R0, int N, double *wrow)
-{
-    const int lane = lane_id();
-    double t[3][ANG_NCAP + 2], lam[3], y0[3], ym[3], iz[3];
-    const double z[3] = {x, R * x, R0 * x};
-    double jm;
-    if constexpr (DIM == 3) {
-        ang_miller3(N + 1, z, t, lam);
-        for (int j = 0; j < 3; ++j) {
-            double s0, c0;
-            sincos(z[j], &s0, &c0);
-            const double s = sqrt(2.0 / (PI_D * z[j]));
-            ym[j] = s * s0;
-            y0[j] = -s * c0;
-            iz[j] = 1.0 / z[j];
-        }
-        jm = lam[0] * t[0][0];
-    } else {
-        double j0z[3], j1z[3];
-        for (int j = 0; j < 3; ++j) {
-            ang_bessel01(z[j], &j0z[j], &j1z[j], &y0[j], &ym[j]);
-            ym[j] = -ym[j];
-            iz[j] = 1.0 / z[j];
-        }
-        ang_miller3_int(N, z, t, lam, j0z, j1z);
-        jm = -lam[0] * t[0][1];
-    }
-    bool dead = !live;
-    for (int nn = 0; nn <= N; ++nn) {  // uniform over the wave
-        if (fabs(y0[0]) > 0x1p500) dead = true;
-        if (__ballot(!dead) == 0) break;
-        const int k = DIM == 3 ? nn + 1 : nn;
-        const double jx = lam[0] * t[0][k];
-        double term = 0.0;
-        if (!dead) {
-            const double jr = lam[1] * t[1][k], jq = lam[2] * t[2][k];
-            double Ar, Br;
-            if constexpr (DIM == 3) {
-                Ar = (2.0 * nn + 2.0) * y0[0] - 2.0 * x * ym[0];
-                Br = (2.0 * nn + 2.0) * jx - 2.0 * x * jm;
-            } else {
-                Ar = x * ym[0] - nn * y0[0];
-                Br = x * jm - nn * jx;
+        const int nn0 = ACS * s - (DIM == 3 ? 1 : 0);  // the series order of v[.][0]
+        const double dn0 = (double)nn0;
+        double t[ACS];
+#pragma unroll
+        for (int i = 0; i < ACS; ++i) {
+            const int nn = nn0 + i;
+            const double dn = dn0 + i;
+            t[i] = 0.0;
+            if (nn < 0 || nn > N) continue;  // uniform
+            if (fabs(y0[0]) > 0x1p500) dead = true;
+            const double jx = v[0][i];
+            if (!dead) {
+                // F(R) F(R0) = (J(Rx) A - Y(Rx) B)(J(R0x) A - Y(R0x) B) / (A^2 + B^2)
+                const double jr = v[1][i], jq = v[2][i];
+                double Ar, Br;
+                if constexpr (DIM == 3) {
+                    Ar = (2.0 * dn + 2.0) * y0[0] - 2.0 * x * ym[0];
+                    Br = (2.0 * dn + 2.0) * jx - 2.0 * x * jm;
+                } else {
+                    Ar = x * ym[0] - dn * y0[0];
+                    Br = x * jm - dn * jx;
+                }
+                const double Aa = y0[0], Ba = jx;
+                const double pr = (jr * Ar - y0[1] * Br) * ang_rcp(Ar * Ar + Br * Br) * (jq * Ar - y0[2] * Br);
+                const double pa = (jr * Aa - y0[1] * Ba) * ang_rcp(Aa * Aa + Ba * Ba) * (jq * Aa - y0[2] * Ba);
+                t[i] = g * (pr - pa);
             }
-            const double Aa = y0[0], Ba = jx;
-            const double pr = (jr * Ar - y0[1] * Br) / (Ar * Ar + Br * Br) * (jq * Ar - y0[2] * Br);
-            const double pa = (jr * Aa - y0[1] * Ba) / (Aa * Aa + Ba * Ba) * (jq * Aa - y0[2] * Ba);
-            term = g * (pr - pa);
+            jm = jx;
+            const double cy = DIM == 3 ? 2.0 * dn + 1.0 : 2.0 * dn;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {  // Y_{nu+1} = (2 nu / z) Y_nu - Y_{nu-1}
+                const double yn = cy * inv[j] * y0[j] - ym[j];
+                ym[j] = y0[j];
+                y0[j] = yn;
+            }
         }
-        jm = jx;
-        const double sum = wave_allsum(term);
-        if (lane == 0) wrow[nn] += sum;
-        for (int j = 0; j < 3; ++j) {
-            const double yn = (DIM == 3 ? 2.0 * nn + 1.0 : 2.0 * nn) * iz[j] * y0[j] - ym[j];
-            ym[j] = y0[j];
-            y0[j] = yn;
-        }
+        // sum the chunk's orders over the wave: after the folds on lane bits 5, 4, 3, 2 a
+        // lane holds order 8 b5 + 4 b4 + 2 b3 + b2, summed over its four lanes by bits 1, 0
+        ang_fold<16>(t, lane, 32);
+        ang_fold<8>(t, lane, 16);
+        ang_fold<4>(t, lane, 8);
+        ang_fold<2>(t, lane, 4);
+        double v0 = t[0];
+        v0 += __shfl_xor(v0, 2, 64);
+        v0 += __shfl_xor(v0, 1, 64);
+        const int o = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+        const int nn = nn0 + o;
+        if ((lane & 3) == 0 && nn >= 0 && nn <= N) wrow[nn] += v0;
     }
 }
 
@@ -262,7 +270,7 @@ __device__ __noinline__ void ang_node_stored(double x, double g, bool live, doub
 // |theta| (2D) at the uniform u, NaN for radii beyond any encounter or not a number.
 // Every thread returns the value.  Uniform: all arguments.
 template <int DIM>
-__device__ double ang_draw_wg(double tau, double Rin, double R0in, double u, const GL16 &gl, AngShared &sh)
+__device__ __forceinline__ double ang_draw_wg(double tau, double Rin, double R0in, double u, const GL16 &gl, AngShared &sh)
 {
     const int tid = threadIdx.x, wv = tid >> 6;
     if (!(Rin + R0in - 2.0 <= 40.0 * sqrt(tau))) return __builtin_nan("");  // no encounter reaches that far (e^{-400})
@@ -306,8 +314,7 @@ __device__ double ang_draw_wg(double tau, double Rin, double R0in, double u, con
             x = c + hw * gl.x[qq & 15];
             g = live ? hw * gl.w[qq & 15] * exp(-tau * x * x) * x : 0.0;
         }
-        if (N <= ANG_FAST_N) ang_node_fast<DIM>(x, g, live, R, R0, N, wrow);
-        else ang_node_stored<DIM>(x, g, live, R, R0, N, wrow);
+        ang_node<DIM>(x, g, live, R, R0, N, wrow, sh);
     }
     __syncthreads();
     for (int t = tid; t <= N; t += AWG) {
@@ -316,13 +323,30 @@ __device__ double ang_draw_wg(double tau, double Rin, double R0in, double u, con
         sh.W[t] = s;
     }
     __syncthreads();
+    // the distribution function's coefficients relative to w_0, and the last order whose
+    // coefficient is above 1e-17 of w_0 (the rest change F by less than 1e-16)
+    const double inv0 = 1.0 / sh.W[0];
+    int last = 0;
+    for (int t = tid; t <= N; t += AWG) {
+        const double v = sh.W[t] * inv0;
+        if (t > 0 && fabs(v) > 1e-17) last = t;
+        // 3D: F = [1 + c + sum v_n (P_{n+1} - P_{n-1})] / 2; 2D: F = t / pi + sum (2 v_n / (n pi)) sin(n t)
+        sh.w[0][t] = DIM == 3 ? 0.5 * v : (t > 0 ? 2.0 * v / (t * PI_D) : 0.0);
+    }
+    for (int o = 32; o >= 1; o >>= 1) last = max(last, __shfl_xor(last, o, 64));
+    if ((tid & 63) == 0) sh.hit[wv] = last;
+    __syncthreads();
+    int Ne = 0;
+    for (int w = 0; w < AW_NW; ++w) Ne = max(Ne, sh.hit[w]);
+    const double *V = sh.w[0];
+    __syncthreads();
     // root of F(.) = u: F is nondecreasing; each round keeps the cell between the last point
     // below u and the first at or above it
     double lo = DIM == 3 ? -1.0 : 0.0, hi = DIM == 3 ? 1.0 : PI_D;
-    for (int it = 0; it < 7; ++it) {
+    for (int it = 0; it < 8; ++it) {
         const double d = (hi - lo) / (AWG + 1);
         const double c = lo + d * (tid + 1);
-        const bool ge = (DIM == 3 ? ang_cdf(sh.W, N, c) : ang2_cdf(sh.W, N, c)) >= u;
+        const bool ge = (DIM == 3 ? ang_cdf_n(V, Ne, c) : ang2_cdf_n(V, Ne, c)) >= u;
         const u64 bal = __ballot(ge);
         if ((tid & 63) == 0) sh.hit[wv] = bal ? __ffsll((unsigned long long)bal) - 1 : 64;
         __syncthreads();
