@@ -278,6 +278,23 @@ int sim_load_state(sim_t *h, uint64_t step, const int32_t *species, const double
  * when done.  SIM_EINVAL for NULL R, R0 or n = 0; SIM_EDEVICE if a HIP call fails. */
 int sim_eval_pairs(sim_t *h, uint64_t n, const double *R, const double *R0, double *penc, double *preac);
 
+/* For callers that cannot allocate device memory: code under HIP graph capture, serving loops
+ * that may not call hipMalloc, harnesses that forbid it.  The same p_enc and p_reac as
+ * sim_eval_pairs, bit for bit, for a system described by cfg instead of a handle (which
+ * allocates when it is created): it validates cfg as sim_create does, enqueues the evaluation
+ * on cfg->hip_stream (NULL: the null stream) and returns without waiting; the caller
+ * synchronises that stream before reading penc and preac.  R, R0, penc, preac: DEVICE pointers,
+ * as for sim_eval_pairs.  It allocates nothing: the one piece of device memory its kernel
+ * needs beyond them, the constants of the 2D expansion (4 x 33 doubles, expansion orders up
+ * to 32, the largest n_terms accepted), lives in a fixed array of the library that each GPU
+ * holds for the life of the process; the entry point rewrites it on every 2D call.  Calls
+ * that overlap on one GPU (on different streams, or from different threads) race on that
+ * array; calls on one stream are ordered.  SIM_EINVAL for NULL R or R0, n = 0 or an invalid
+ * cfg (n_terms above 32 among them); SIM_EUNSUPPORTED for green2d = SIM_G2_EXACT (its tables
+ * are device memory a handle builds); SIM_EDEVICE if a HIP call fails. */
+int sim_eval_pairs_noalloc(const sim_config *cfg, uint64_t n, const double *R, const double *R0, double *penc,
+                           double *preac);
+
 /* Draws n radii R'' >= 1 (in units of a) from the radial propagator w_d r^{d-1}(g_ref - g_abs)(.|R0)
  * (Sec. 2.2.2; 3D closed forms of Sec. 4.1, 2D expansion of Sec. 4.2) with the step's own rejection
  * sampler and the handle's parameters.  Draw i starts from R0[i] >= 1 and uses the Philox counter

@@ -9,11 +9,15 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 using namespace gfbd;
+
+// Device memory of sim_eval_pairs_noalloc (see there): the 2D expansion constants.
+static __device__ __align__(256) double scratch[4 * (MAXTERMS + 1)];
 
 namespace {
 
@@ -58,9 +62,11 @@ double h_rcut(int dim, int bc, double a, double tau, double hh, double eps)
     return a * hi;
 }
 
-// Power-series quotient z = x / y, truncated after n.
-void h_series_div(const double *x, const double *y, int n, double *z)
+// Power-series quotient z = x / y, truncated after n.  Host and device run the same
+// correctly rounded operations (no contraction), so both give the same bits.
+__host__ __device__ void h_series_div(const double *x, const double *y, int n, double *z)
 {
+#pragma clang fp contract(off)
     for (int k = 0; k <= n; ++k) {
         double s = x[k];
         for (int m = 1; m <= k; ++m) s -= y[m] * z[k - m];
@@ -71,8 +77,9 @@ void h_series_div(const double *x, const double *y, int n, double *z)
 // 2D constants: a_k(0) and the R-independent quotient series of the three
 // boundary components (Sec. 4.2): Abar_0/A_0, Abar_1/A_1 and
 // (Abar_1 - h s Abar_0)/(A_1 + h s A_0).
-void h_g2_constants(double hh, double *out)
+__host__ __device__ void h_g2_constants(double hh, double *out)
 {
+#pragma clang fp contract(off)
     const int n = MAXTERMS;
     double a0[MAXTERMS + 1], a1[MAXTERMS + 1], b0[MAXTERMS + 1], b1[MAXTERMS + 1], nu[MAXTERMS + 1], de[MAXTERMS + 1];
     a0[0] = a1[0] = 1.0;
@@ -87,7 +94,7 @@ void h_g2_constants(double hh, double *out)
         nu[k] = b1[k] - (k ? hh * b0[k - 1] : 0.0);
         de[k] = a1[k] + (k ? hh * a0[k - 1] : 0.0);
     }
-    std::memcpy(out, a0, sizeof(a0));
+    for (int k = 0; k <= n; ++k) out[k] = a0[k];
     h_series_div(b0, a0, n, out + (n + 1));
     h_series_div(b1, a1, n, out + 2 * (n + 1));
     h_series_div(nu, de, n, out + 3 * (n + 1));
@@ -164,6 +171,52 @@ struct Model {
 bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
 int validate_box(int dim, int prec, const double *box);
 int validate_state(int dim, bool reversible, uint64_t n, const int32_t *sp, const double *pos, const uint32_t *pt);
+
+// The physics of one system (or one replica of a batch) from its configuration: what the
+// step's device functions and the kernel-level evaluations read, cut-off included.
+void phys_params(const Model &M, Params &P)
+{
+    std::memset(&P, 0, sizeof(P));
+    P.dim = M.dim;
+    P.bc = M.bc;
+    P.reversible = M.k_off > 0.0;
+    P.n_terms = M.n_terms;
+    P.angles = M.bc != SIM_BC_ABSORBING && !(M.flags & SIM_F_KEEP_DIRECTION);
+    const double Deff = M.D[0] + M.D[1];
+    P.a = M.sigma;
+    P.inv_a = 1.0 / M.sigma;
+    P.tau = Deff * M.dt / (M.sigma * M.sigma);
+    P.inv_tau = 1.0 / P.tau;
+    P.sqrt_tau = std::sqrt(P.tau);
+    if (M.bc == SIM_BC_RADIATION)
+        P.hh = M.dim == 3 ? M.kappa / (4.0 * M_PI * M.sigma * Deff) : M.kappa / (2.0 * M_PI * Deff);
+    P.rcut = M.rcut_req > 0.0 ? M.rcut_req : h_rcut(M.dim, M.bc, M.sigma, P.tau, P.hh, M.eps);
+    P.rcut2 = P.rcut * P.rcut;
+    P.rcut2f = (float)P.rcut2;
+    P.rcut2f_wide = (float)(P.rcut2 * (1.0 + 1e-4));
+    {
+        // prefilter radius for brick-relative binary32 coordinates: each
+        // coordinate is off by at most two binary32 roundings of a value
+        // below the box edge
+        double lmax = 0.0;
+        for (int k = 0; k < M.dim; ++k) lmax = std::max(lmax, M.box[k]);
+        const double slack = 4.0 * std::ldexp(1.0, std::ilogb(lmax) - 23) * std::sqrt((double)M.dim);
+        P.rcut2f_pre = (float)((P.rcut + slack) * (P.rcut + slack) * (1.0 + 1e-5));
+        // neighbour cells farther than this from an A are skipped: the
+        // margin exceeds every rounding of a binary32 coordinate below
+        // the box edge by a factor of 16 or more
+        P.reach = P.rcut * (1.0 + 1e-6) + 64.0 * std::ldexp(1.0, std::ilogb(lmax) - 23);
+    }
+    P.inv_af = (float)P.inv_a;
+    P.inv_tauf = (float)P.inv_tau;
+    P.fA = M.D[0] / Deff;
+    P.fB = M.D[1] / Deff;
+    P.p_uni = -std::expm1(-M.k_off * M.dt);
+    P.key.k0 = (u32)M.seed;
+    P.key.k1 = (u32)(M.seed >> 32) ^ M.replica;
+    for (int s = 0; s < 3; ++s) P.sd[s] = std::sqrt(2.0 * M.D[s] * M.dt);
+}
+
 
 // First-fit allocator of index ranges in [0, cap) (the slots and cells of a
 // pool), merging neighbours on release.
@@ -280,45 +333,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     // batch) with n_r slots and species sp.
     int setup_replica(const Model &M, uint64_t n, const int32_t *sp, Params &P, double &cell_edge, double &pair_tests, bool &narrow)
     {
-        std::memset(&P, 0, sizeof(P));
-        P.dim = DIM;
-        P.bc = M.bc;
-        P.reversible = M.k_off > 0.0;
-        P.n_terms = M.n_terms;
-        P.angles = M.bc != SIM_BC_ABSORBING && !(M.flags & SIM_F_KEEP_DIRECTION);
-        const double Deff = M.D[0] + M.D[1];
-        P.a = M.sigma;
-        P.inv_a = 1.0 / M.sigma;
-        P.tau = Deff * M.dt / (M.sigma * M.sigma);
-        P.inv_tau = 1.0 / P.tau;
-        P.sqrt_tau = std::sqrt(P.tau);
-        if (M.bc == SIM_BC_RADIATION)
-            P.hh = DIM == 3 ? M.kappa / (4.0 * M_PI * M.sigma * Deff) : M.kappa / (2.0 * M_PI * Deff);
-        P.rcut = M.rcut_req > 0.0 ? M.rcut_req : h_rcut(DIM, M.bc, M.sigma, P.tau, P.hh, M.eps);
-        P.rcut2 = P.rcut * P.rcut;
-        P.rcut2f = (float)P.rcut2;
-        P.rcut2f_wide = (float)(P.rcut2 * (1.0 + 1e-4));
-        {
-            // prefilter radius for brick-relative binary32 coordinates: each
-            // coordinate is off by at most two binary32 roundings of a value
-            // below the box edge
-            double lmax = 0.0;
-            for (int k = 0; k < DIM; ++k) lmax = std::max(lmax, M.box[k]);
-            const double slack = 4.0 * std::ldexp(1.0, std::ilogb(lmax) - 23) * std::sqrt((double)DIM);
-            P.rcut2f_pre = (float)((P.rcut + slack) * (P.rcut + slack) * (1.0 + 1e-5));
-            // neighbour cells farther than this from an A are skipped: the
-            // margin exceeds every rounding of a binary32 coordinate below
-            // the box edge by a factor of 16 or more
-            P.reach = P.rcut * (1.0 + 1e-6) + 64.0 * std::ldexp(1.0, std::ilogb(lmax) - 23);
-        }
-        P.inv_af = (float)P.inv_a;
-        P.inv_tauf = (float)P.inv_tau;
-        P.fA = M.D[0] / Deff;
-        P.fB = M.D[1] / Deff;
-        P.p_uni = -std::expm1(-M.k_off * M.dt);
-        P.key.k0 = (u32)M.seed;
-        P.key.k1 = (u32)(M.seed >> 32) ^ M.replica;
-        for (int s = 0; s < 3; ++s) P.sd[s] = std::sqrt(2.0 * M.D[s] * M.dt);
+        phys_params(M, P);
         double Lmin = 1e300;
         for (int k = 0; k < DIM; ++k) Lmin = std::min(Lmin, M.box[k]);
         if (!(P.rcut < 0.5 * Lmin)) return fail(SIM_EINVAL, "r_cut must be below half the smallest box edge");
@@ -1388,7 +1403,53 @@ int make_pool(const Model &M, uint64_t slot_cap, uint64_t cell_cap, uint32_t rep
     return SIM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// sim_eval_pairs_noalloc: the pair probabilities of sim_eval_pairs without a handle
+// and without allocating.  The kernel reads the 2D expansion constants from device
+// memory; a handle keeps them in a buffer of its own, this entry point in `scratch`
+// below, a file-scope array of which every device holds its own copy.  Host code
+// never uses the array's name as an address: the address is looked up once per
+// device (hipGetSymbolAddress, with that device current) and kept.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_DOUBLES = 4 * (MAXTERMS + 1);  // a_k(0) and three quotient series, orders 0 .. 32
+constexpr int NOALLOC_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[NOALLOC_DEVICES] = {};
+
+int scratch_address(double **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { g_err = "hipGetDevice failed"; return SIM_EDEVICE; }
+    if (dev < 0 || dev >= NOALLOC_DEVICES) { g_err = "device index beyond the table of scratch addresses"; return SIM_EUNSUPPORTED; }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            g_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return SIM_EDEVICE;
+        }
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SIM_OK;
+}
+
+template <int DIM, int PM> void launch_probs(const Params &P, uint64_t n, const double *R, const double *R0, double *penc,
+                                             double *preac, hipStream_t st)
+{
+    const u32 g = (u32)std::max<uint64_t>(1, std::min<uint64_t>((n + BLOCK - 1) / BLOCK, 16384));
+    if (DIM == 2 && P.n_terms == 12) k_eval_probs<DIM, PM, 12><<<g, BLOCK, 0, st>>>(P, n, R, R0, penc, preac);
+    else k_eval_probs<DIM, PM, 0><<<g, BLOCK, 0, st>>>(P, n, R, R0, penc, preac);
+}
+
 } // namespace
+
+// the constants of the 2D expansion for intrinsic rate hh into out (one thread)
+__global__ void k_g2_constants(double hh, double *out)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) h_g2_constants(hh, out);
+}
 
 extern "C" {
 
@@ -1522,6 +1583,38 @@ int sim_eval_pairs(sim_t *h, uint64_t n, const double *R, const double *R0, doub
 {
     if (!h || !R || !R0 || n == 0) { g_err = "null argument or n = 0"; return SIM_EINVAL; }
     return h->eval_pairs(n, R, R0, penc, preac);
+}
+
+int sim_eval_pairs_noalloc(const sim_config *cfg, uint64_t n, const double *R, const double *R0, double *penc, double *preac)
+{
+    if (!cfg || !R || !R0 || n == 0) { g_err = "null argument or n = 0"; return SIM_EINVAL; }
+    Model M;
+    int rc;
+    if ((rc = validate_cfg(cfg, M))) return rc;
+    if (M.green2d == SIM_G2_EXACT) {
+        g_err = "the exact 2D functions are tables a handle builds (device memory): use sim_eval_pairs";
+        return SIM_EUNSUPPORTED;
+    }
+    static_assert(NOALLOC_DOUBLES == sizeof(scratch) / sizeof(double), "scratch holds the 2D constants");
+    double *ptr = nullptr;
+    if ((rc = scratch_address(&ptr))) return rc;
+    Params P;
+    phys_params(M, P);
+    P.g2c = ptr;  // read by the 2D expansion only
+    hipStream_t st = (hipStream_t)cfg->hip_stream;
+    if (M.dim == 2) k_g2_constants<<<1, 64, 0, st>>>(P.hh, ptr);
+    if (M.dim == 3) {
+        if (M.prec == SIM_PREC_FP64) launch_probs<3, PM_F64>(P, n, R, R0, penc, preac, st);
+        else if (M.prec == SIM_PREC_FP32) launch_probs<3, PM_F32>(P, n, R, R0, penc, preac, st);
+        else launch_probs<3, PM_F32NC>(P, n, R, R0, penc, preac, st);
+    } else {
+        if (M.prec == SIM_PREC_FP64) launch_probs<2, PM_F64>(P, n, R, R0, penc, preac, st);
+        else if (M.prec == SIM_PREC_FP32) launch_probs<2, PM_F32>(P, n, R, R0, penc, preac, st);
+        else launch_probs<2, PM_F32NC>(P, n, R, R0, penc, preac, st);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { g_err = std::string("sim_eval_pairs_noalloc: ") + hipGetErrorString(e); return SIM_EDEVICE; }
+    return SIM_OK;
 }
 
 int sim_eval_propagator(sim_t *h, uint64_t n, const double *R0, uint32_t step, int wave, double *Rpp, uint32_t *attempts)

@@ -144,6 +144,8 @@ def lib():
     L.sim_load_state.restype = C.c_int
     L.sim_eval_pairs.argtypes = [vp, u64, vp, vp, vp, vp]
     L.sim_eval_pairs.restype = C.c_int
+    L.sim_eval_pairs_noalloc.argtypes = [C.POINTER(SimConfig), u64, vp, vp, vp, vp]
+    L.sim_eval_pairs_noalloc.restype = C.c_int
     L.sim_eval_propagator.argtypes = [vp, u64, vp, u32, C.c_int, vp, vp]
     L.sim_eval_propagator.restype = C.c_int
     L.sim_eval_first_passage.argtypes = [vp, u64, vp, vp, C.c_int32, u32, vp, vp]
@@ -521,3 +523,30 @@ class Pool(Sim):
     def member_counts(self, member):
         out = self._read_member(member, READ_COUNTS, np.zeros(5, np.int64))
         return dict(zip(["A", "B", "C", "FREE", "RESERVED"], out.tolist()))
+
+
+def eval_pairs_noalloc(R, R0, *, dim, dt, D, sigma, bc, kappa=0.0, precision=PREC_FP32_FP64NC, n_terms=12, **kw):
+    """sim_eval_pairs_noalloc: p_enc and p_reac of (R, R0) pairs for a system given by its
+    configuration (no handle), on the null stream.  R and R0 are host arrays, copied to device
+    buffers and the results back after the device has finished."""
+    holder = Sim.__new__(Sim)
+    Sim._config(holder, dim=dim, box=kw.pop("box", 1.0), dt=dt, D=D, sigma=sigma, bc=bc, kappa=kappa,
+                species=np.zeros(1, np.int32), pos=np.zeros(dim), precision=precision, n_terms=n_terms, **kw)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    R0 = np.ascontiguousarray(R0, dtype=np.float64)
+    n = R.size
+    bufs = [DeviceBuffer(8 * n) for _ in range(4)]
+    try:
+        bufs[0].upload(R)
+        bufs[1].upload(R0)
+        L = lib()
+        rc = L.sim_eval_pairs_noalloc(C.byref(holder.cfg), n, bufs[0].ptr, bufs[1].ptr, bufs[2].ptr, bufs[3].ptr)
+        if rc != SIM_OK:
+            raise SimError(rc, L.sim_last_error(None).decode())
+        if hip_runtime().hipDeviceSynchronize() != 0:
+            raise RuntimeError("hipDeviceSynchronize failed")
+        return bufs[2].download(np.empty(n, np.float64)), bufs[3].download(np.empty(n, np.float64))
+    finally:
+        for b in bufs:
+            b.free()
+

@@ -23,8 +23,8 @@ def _declared():
 def test_header_declares_the_boundary():
     assert _declared() == sorted(["sim_create", "sim_batch_create", "sim_pool_create", "sim_pool_admit",
                                   "sim_pool_retire", "sim_pool_read", "sim_step", "sim_read", "sim_load_state",
-                                  "sim_eval_pairs", "sim_eval_propagator", "sim_eval_first_passage", "sim_eval_angle", "sim_destroy",
-                                  "sim_last_error"])
+                                  "sim_eval_pairs", "sim_eval_pairs_noalloc", "sim_eval_propagator",
+                                  "sim_eval_first_passage", "sim_eval_angle", "sim_destroy", "sim_last_error"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -211,3 +211,20 @@ def test_pool_of_2d_expansion_systems_beyond_its_tau_is_refused():
         S.Pool(dim=2, box=1.0, slot_cap=100, cell_cap=100, rep_cap=2, dt=1e-4, D=(0.1, 0.1, 0.05), sigma=0.005,
                bc=S.BC_RADIATION, k_off=1.0, precision=S.PREC_FP64)
     assert e.value.code == S.SIM_EUNSUPPORTED
+
+
+def test_noalloc_entry_point_rejects_bad_input_on_the_host():
+    if not os.path.exists(S.LIB_PATH):
+        pytest.skip("libgfbd.so not built")
+    L = S.lib()
+    assert L.sim_eval_pairs_noalloc(None, 4, 1, 1, None, None) == S.SIM_EINVAL
+    h = S.Sim.__new__(S.Sim)
+    base = dict(dim=2, box=1.0, dt=5e-6, D=(0.1, 0.1, 0.05), sigma=0.005, bc=S.BC_RADIATION, kappa=0.05,
+                species=np.zeros(1, np.int32), pos=np.zeros(2))
+    for over, code in ((dict(n_terms=40), S.SIM_EINVAL), (dict(green2d=S.G2_EXACT), S.SIM_EUNSUPPORTED),
+                       (dict(dt=1e-4), S.SIM_EUNSUPPORTED)):
+        S.Sim._config(h, **dict(base, **over))
+        assert L.sim_eval_pairs_noalloc(C.byref(h.cfg), 4, 1, 1, None, None) == code
+    S.Sim._config(h, **base)
+    assert L.sim_eval_pairs_noalloc(C.byref(h.cfg), 0, 1, 1, None, None) == S.SIM_EINVAL
+    assert L.sim_eval_pairs_noalloc(C.byref(h.cfg), 4, None, 1, None, None) == S.SIM_EINVAL
