@@ -143,6 +143,44 @@ def angle_roofline(n, launch_ms, dim=3):
             "valu_issue_frac": round(t["valu"] / VALU_WAVE_INSTR_PER_S / (launch_ms * 1e-3), 4)}
 
 
+# The step's angle stage (k_angles) on the default run of this workload: fp64 operations and VALU
+# wave-instructions per launch from rocprofv3 (SQ_INSTS_VALU_{ADD,MUL,FMA}_F64 x 64 lanes, an FMA
+# counting two; SQ_INSTS_VALU), and its HBM bytes (FETCH_SIZE, WRITE_SIZE scaled as above),
+# profiles/rad3d_step_angles.md.  Valid for the sources they were taken on (hash below).
+ANGLE_STEP_COUNTERS = {
+    "src_hash": None,
+    "f64_flop": None,
+    "valu": None,
+    "traffic": None,
+}
+ANGLE_STEP_SOURCES = ["common.hpp", "green.hpp", "green2x.hpp", "kernels.hpp", "angle3.hpp", "angle2.hpp",
+                      "angle_wg.hpp", "gfbd.hip"]
+
+
+def angle_step_src_hash():
+    h = hashlib.sha256()
+    for f in ANGLE_STEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_1107_0270_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def angle_step_roofline(launch_ms, profiled):
+    """The angle stage against the fp64 vector peak: plain fp64 arithmetic (Bessel recurrences,
+    quadrature sums, Legendre sums) on a few hundred pairs, a workgroup each.  The operations are
+    the ones the kernel executes (counters), not an algorithmic count."""
+    t = ANGLE_STEP_COUNTERS
+    valid = profiled and t["src_hash"] is not None and angle_step_src_hash() == t["src_hash"]
+    out = {"kernel": "angles", "bound": "alu", "achieved": None, "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+           "frac": None, "traffic": t["traffic"] if valid else None, "avg_launch_ms": round(launch_ms, 5),
+           "flop_source": "rocprofv3 fp64 VALU counters of k_angles (executed operations)", "valu_issue_frac": None}
+    if valid:
+        ach = t["f64_flop"] / (launch_ms * 1e-3) / 1e12
+        out.update(achieved=round(ach, 3), frac=round(ach * 1e12 / FP64_VECTOR_PEAK, 4), flop_per_launch=t["f64_flop"],
+                   valu_issue_frac=round(t["valu"] / VALU_WAVE_INSTR_PER_S / (launch_ms * 1e-3), 4))
+    return out
+
+
 def describe(cfg):
     bc = {0: "absorbing", 1: "reflecting", 2: "radiation"}[cfg["bc"]]
     rev = "reversible A+B<->C" if cfg["k_off"] > 0 else "irreversible A+B->C"
@@ -153,17 +191,20 @@ def describe(cfg):
 
 
 def pair_probs(args, I, S):
+    print(json.dumps(pair_probs_record(args.pair_probs, args.steps, args.dim, I, S)), flush=True)
+
+
+def pair_probs_record(n, repeats, d, I, S):
     """p_enc and p_reac of N pairs drawn from the workload's pair distribution (uniform positions:
     R uniform in the ball of radius r_cut/a; R0 = |R + sqrt(2 tau) z| >= 1, z standard normal),
     evaluated by sim_eval_pairs with the step's device functions on device-resident arrays."""
-    cfg = I.workload("cfg_rad3d" if args.dim == 3 else "cfg_mem2d_small_tau")
-    d = args.dim
+    cfg = I.workload("cfg_rad3d" if d == 3 else "cfg_mem2d_small_tau")
     sp = np.array([0, 1], np.int32)
     pos = np.array([[0.25] * d, [0.75] * d])
     h = S.Sim(dim=d, box=cfg["box"], dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"], kappa=cfg["kappa_a"],
-              k_off=0.0, precision=cfg["precision"], seed=0, species=sp, pos=pos)
+              k_off=0.0, precision=cfg["precision"], seed=0, species=sp, pos=pos, eps_cut=1e-6)
     der = h.derived()
-    tau, rmax, n = der["tau"], der["rcut"] / der["a"], args.pair_probs
+    tau, rmax = der["tau"], der["rcut"] / der["a"]
     rng = np.random.default_rng(0)
     v = rng.standard_normal((n, d))
     v /= np.linalg.norm(v, axis=1, keepdims=True)
@@ -180,20 +221,20 @@ def pair_probs(args, I, S):
         args4 = (n, bufs[0].ptr, bufs[1].ptr, bufs[2].ptr, bufs[3].ptr if want_preac else None)
         h.eval_pairs_device(*args4)  # warm-up
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(repeats):
             h.eval_pairs_device(*args4)
-        out[name] = n * args.steps / (time.perf_counter() - t0)
+        out[name] = n * repeats / (time.perf_counter() - t0)
         log(f"[pair-probs] {name}: {out[name]:.3e} pair evals/s")
     for b in bufs:
         b.free()
     h.close()
-    print(json.dumps({
+    return {
         "metric": "pair-probability evals/s (kernel only)", "value": round(out["penc"], 1), "unit": "pair evals/s",
-        "penc_and_preac_per_s": round(out["penc_preac"], 1), "n_gpus": 1, "pairs": n, "repeats": args.steps,
+        "penc_and_preac_per_s": round(out["penc_preac"], 1), "n_gpus": 1, "pairs": n, "repeats": repeats,
         "dtype": {0: "f64", 1: "f32", 2: "f32+f64-args"}[cfg["precision"]], "data": "synthetic",
-        "config": {"workload": f"{d}D pair distribution of the benchmark workload: R uniform in the ball of radius "
-                               f"r_cut/a = {rmax:.3f}, R0 = |R + sqrt(2 tau) z|, tau = {tau:.4g}",
-                   "kernel": "k_eval_probs (the step's p_enc / p_reac device functions)"}}), flush=True)
+        "config": {"workload": f"{d}D pair distribution of the benchmark workload at the 1e-6 cut-off: R uniform in "
+                               f"the ball of radius r_cut/a = {rmax:.3f}, R0 = |R + sqrt(2 tau) z|, tau = {tau:.4g}",
+                   "kernel": "k_eval_probs (the step's p_enc / p_reac device functions)"}}
 
 
 def first_passage(args, I, S):
@@ -417,6 +458,131 @@ def batched(args, I, S):
                    "step_launch": "one hipGraph replay per step for all replicas"}}), flush=True)
 
 
+ENSEMBLE_SHARED = dict(dt=1e-5, D=(1.0, 1.0, 0.5), sigma=0.005, k_off=10.0, seed=0, eps_cut=1e-6)
+
+
+def ensemble_record(reps, S, steps=50, warmup=5, sample=16):
+    """The batched ensemble (one graph replay per step for all replicas) and the plain path on a
+    sample of the same replicas, one handle each, for the default benchmark line."""
+    shared = dict(ENSEMBLE_SHARED, bc=S.BC_RADIATION, precision=S.PREC_FP32_FP64NC)
+    n_tot = sum(len(r["species"]) for r in reps)
+    t0 = time.time()
+    b = S.Sim.batch(reps, **shared)
+    t_create = time.time() - t0
+    b.step(warmup)
+    c0 = b.counts()
+    t0 = time.perf_counter()
+    b.step(steps)
+    el = time.perf_counter() - t0
+    c1 = b.counts()
+    b.close()
+    rate = 0.5 * sum(c0[k] + c1[k] for k in ("A", "B", "C")) * steps / el
+    rng = np.random.default_rng(1)
+    t1, ps1 = 0.0, 0.0
+    for r in rng.choice(len(reps), size=min(sample, len(reps)), replace=False):
+        rd = reps[r]
+        sim = S.Sim(dim=3, box=rd["box"], species=rd["species"], pos=rd["pos"], kappa=rd["kappa"], replica=rd["replica"],
+                    **shared)
+        sim.step(warmup)
+        t0 = time.perf_counter()
+        sim.step(steps)
+        t1 += time.perf_counter() - t0
+        ps1 += len(rd["species"]) * steps
+        sim.close()
+    log(f"[bench] ensemble: {rate:.3e} particle-steps/s; plain path {ps1 / t1:.3e}")
+    return {"value": round(rate, 1), "unit": "particle-steps/s", "ms_per_step": round(el * 1e3 / steps, 4),
+            "steps": steps, "warmup": warmup, "handle_creation_s": round(t_create, 2),
+            "plain_path": {"value": round(ps1 / t1, 1), "unit": "particle-steps/s",
+                           "sample": f"{min(sample, len(reps))} replicas of the ensemble, one handle each, "
+                                     f"{steps} steps each after {warmup} warm-up"},
+            "speedup_vs_plain_path": round(rate * t1 / ps1, 2),
+            "workload": f"{len(reps)} independent 3D replicas, A+B<->C radiation surface, N log-uniform in [1e3, 1e5] "
+                        f"(total {n_tot}), kappa uniform in [0.01, 1] um^3/s, L = (N/1000)^(1/3) um, D=1 um^2/s, "
+                        "sigma=5 nm, k_off=10/s, dt=10 us, binary32 state with binary64 near-contact arguments, "
+                        "pair cut-off 1e-6"}
+
+
+def served_record(trace, S, pool_slots=1 << 26, tick=200, sample=8):
+    """The served stream on a given (shortened) trace: p50/p99 latency and aggregate
+    particle-steps/s, against the plain path on a sample of its requests."""
+    from paper_1107_0270_amd import serve as V
+    work = sum(r.n * r.steps for r in trace)
+    rng = np.random.default_rng(1)
+    t1, ps1 = 0.0, 0
+    for i in rng.choice(len(trace), size=min(sample, len(trace)), replace=False):
+        r = trace[i]
+        p = dict(V.GROUP_PARAMS[r.dim])
+        dim = p.pop("dim")
+        sim = S.Sim(dim=dim, box=r.box, species=r.species, pos=r.pos, replica=r.id, **p)
+        k = min(r.steps, 200)
+        t0 = time.perf_counter()
+        sim.step(k)
+        t1 += time.perf_counter() - t0
+        ps1 += r.n * k
+        sim.close()
+    srv = V.Server(slot_cap={3: pool_slots, 2: pool_slots}, tick=tick, keep_results=False, read_results=True,
+                   progress=None)
+    srv.run(trace)
+    summ = srv.summary(trace)
+    log(f"[bench] served: {summ}")
+    return {"value": round(summ["particle_steps_per_s"], 1), "unit": "particle-steps/s",
+            "p50_latency_s": round(summ["p50_latency_s"], 4), "p99_latency_s": round(summ["p99_latency_s"], 4),
+            "mean_queue_s": round(summ["mean_queue_s"], 4), "wall_s": round(summ["wall_s"], 3),
+            "offered_particle_steps_per_s": round(work / trace[-1].arrival, 1),
+            "plain_path": {"value": round(ps1 / t1, 1), "unit": "particle-steps/s",
+                           "sample": f"{min(sample, len(trace))} requests of the trace, one handle each, at most 200 "
+                                     "steps each"},
+            "speedup_vs_plain_path": round(summ["particle_steps_per_s"] * t1 / ps1, 2),
+            "workload": f"shortened served stream: the first {len(trace)} requests of the Poisson trace at 200 req/s "
+                        "(seed 0); 3D or 2D with p = 1/2; N log-uniform in [1e3, 1e6]; steps log-uniform in "
+                        "[100, 1e4]; overlapping A-B pairs redrawn; 3D: the headline parameters; 2D: D=0.1 um^2/s, "
+                        "kappa=0.05 um^2/s, k_off=10/s, dt=5 us; pair cut-off 1e-6",
+            "admission": f"one pool per dimension of {pool_slots} slots; each pool steps to its next completion, "
+                         f"at most {tick} steps per call"}
+
+
+def _oracle_worker(payload):
+    """One oracle on its own core (a spawned process that never touches the GPU)."""
+    cfg, sp, pos, box, steps, eps = payload
+    sys.path.insert(0, ROOT)
+    import oracle as O
+    orc = O.OracleSim(dim=cfg["dim"], bc=cfg["bc"], box=[box] * cfg["dim"], dt=cfg["dt"], D=cfg["D"],
+                      sigma=cfg["sigma"], kappa_a=cfg["kappa_a"], k_off=cfg["k_off"], store_f32=cfg["precision"] != 0,
+                      eps_cut=eps, species=sp, pos=pos)
+    t0 = time.perf_counter()
+    orc.step(steps)
+    return time.perf_counter() - t0
+
+
+def cpu_baselines(cfg, sp, pos, box, steps, eps):
+    """The FP64 oracle as it stands on the same workload and initial state: one process on one
+    core, and one process per available core (up to 16, the box's share) each stepping its own copy
+    at once.  Runs before the benchmark touches the GPU (the workers are spawned processes)."""
+    import multiprocessing as mp
+    payload = (cfg, sp, pos, box, steps, eps)
+    t1 = _oracle_worker(payload)
+    single = {"value": round(len(sp) * steps / t1, 1), "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+              "sample": f"{steps} steps of the same {len(sp)}-particle workload from the same initial state, "
+                        f"single-threaded FP64 C oracle ({t1:.1f} s)"}
+    log(f"[bench] cpu baseline, one core: {single}")
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(16, cores))
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        times = pool.map(_oracle_worker, [payload] * cores)
+    wall = time.perf_counter() - t0
+    rate = cores * len(sp) * steps / max(times)
+    log(f"[bench] cpu baseline, {cores} cores: {rate:.3e} particle-steps/s (slowest worker {max(times):.1f} s, "
+        f"wall {wall:.1f} s)")
+    return {"value": round(rate, 1), "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} copies of the same {len(sp)}-particle workload, {steps} steps each from the same "
+                      f"initial state, one single-threaded FP64 C oracle per core at once (slowest {max(times):.1f} s)",
+            "single_core": single}
+
+
 def served(args, S):
     """The served stream: Poisson arrivals of 2D/3D reversible simulations (N and steps
     log-uniform), continuous batching in one pool per dimension; p50/p99 latency and aggregate
@@ -485,7 +651,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-steps", type=int, default=60, help="oracle steps timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=30,
+                    help="oracle steps timed for the CPU baselines, on one core and on each core (0 = skip)")
+    ap.add_argument("--no-extras", dest="extras", action="store_false",
+                    help="leave the ensemble, the shortened served stream and the pair-probability rate out of the line")
+    ap.add_argument("--serve-requests-short", type=int, default=100,
+                    help="requests of the shortened served stream in the default line")
     ap.add_argument("--no-timing", action="store_true", help="time without per-kernel events")
     ap.add_argument("--pair-search", choices=["auto", "bricks", "direct"], default="auto",
                     help="pair-search kernel (auto = the library's choice)")
@@ -544,33 +715,53 @@ def main():
         sys.exit(2)
 
     from paper_1107_0270_amd import inputs as I
-    from paper_1107_0270_amd import sim as S
 
-    if args.pair_probs:
-        pair_probs(args, I, S)
-        return
-    if args.first_passage:
-        first_passage(args, I, S)
-        return
-    if args.angle:
-        angle(args, I, S)
-        return
-    if args.batch:
-        batched(args, I, S)
-        return
-    if args.serve:
-        served(args, S)
+    if args.pair_probs or args.first_passage or args.angle or args.batch or args.serve:
+        from paper_1107_0270_amd import sim as S
+        if args.pair_probs:
+            pair_probs(args, I, S)
+        elif args.first_passage:
+            first_passage(args, I, S)
+        elif args.angle:
+            angle(args, I, S)
+        elif args.batch:
+            batched(args, I, S)
+        else:
+            served(args, S)
         return
 
     cfg = I.workload(args.workload)
     if args.precision != "workload":
-        cfg["precision"] = {"fp64": S.PREC_FP64, "fp32": S.PREC_FP32, "fp32nc": S.PREC_FP32_FP64NC}[args.precision]
+        cfg["precision"] = {"fp64": I.PREC_FP64, "fp32": I.PREC_FP32, "fp32nc": I.PREC_FP32_FP64NC}[args.precision]
     dim = cfg["dim"]
     t0 = time.time()
     sp, pos, box, red = I.state_for(cfg, seed=0, scale=args.scale)
     if args.scale != 1.0:  # the same density in a box scaled with the particle count
-        cfg = dict(cfg, n_a=int(np.sum(sp == S.SP_A)), n_b=int(np.sum(sp == S.SP_B)), box=box)
+        cfg = dict(cfg, n_a=int(np.sum(sp == I.SP_A)), n_b=int(np.sum(sp == I.SP_B)), box=box)
     log(f"[bench] state: {len(sp)} particles, {red} redrawn overlaps, {time.time() - t0:.1f}s")
+    # the oracle on the host's cores first: its worker processes start before anything here
+    # touches the GPU
+    cpu = cpu_baselines(cfg, sp, pos, box, args.cpu_steps, args.eps_cut) if args.cpu_steps > 0 else None
+    # the default line also reports the ensemble and a shortened served stream: their inputs are
+    # generated on the host while the headline runs on the device
+    extras = {}
+    gen = None
+    if args.extras:
+        import threading
+
+        def _generate():
+            from paper_1107_0270_amd import serve as V
+            t = time.time()
+            extras["reps"] = I.ensemble(4096)
+            trace = V.make_trace(args.serve_requests_short, 200.0, seed=0)
+            for r in trace:
+                V.initial_state(r, redraw=True)
+            extras["trace"] = trace
+            log(f"[bench] ensemble and trace inputs in {time.time() - t:.1f}s")
+
+        gen = threading.Thread(target=_generate)
+        gen.start()
+    from paper_1107_0270_amd import sim as S
     search = {"auto": S.PAIRS_AUTO, "bricks": S.PAIRS_BRICKS, "direct": S.PAIRS_DIRECT}[args.pair_search]
 
     tau = (cfg["D"][0] + cfg["D"][1]) * cfg["dt"] / cfg["sigma"] ** 2
@@ -655,32 +846,28 @@ def main():
     # the rocprofv3 counts were taken on the default run of this workload
     profiled = (args.workload == "cfg_rad3d" and args.precision == "workload" and args.pair_search == "auto"
                 and args.cell == 0.0 and not args.autotune and args.scale == 1.0 and args.eps_cut == 1e-6)
-    roof = None
-    if dom is not None and per[dom] > 0:
-        nb = algorithmic_bytes(dom, n_live, 0.5 * (c0["A"] + c1["A"]), 0.5 * (c0["B"] + c1["B"]), n_keys)
-        if nb is not None:
-            nb *= rec_scale
-            ach = nb / (per[dom] * 1e-3) / 1e9
-            roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom) if profiled else None,
-                    "algorithmic_bytes_per_launch": int(nb), "avg_launch_ms": round(per[dom], 5),
-                    "valu_issue": valu_issue(dom, per[dom]) if profiled else None}
 
-    cpu = None
-    if args.cpu_steps > 0:
-        import oracle as O
+    def hbm_roof(k):
+        if per.get(k, 0.0) <= 0.0:
+            return None
+        nb = algorithmic_bytes(k, n_live, 0.5 * (c0["A"] + c1["A"]), 0.5 * (c0["B"] + c1["B"]), n_keys)
+        if nb is None:
+            return None
+        nb *= rec_scale
+        ach = nb / (per[k] * 1e-3) / 1e9
+        return {"kernel": k, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(k) if profiled else None,
+                "algorithmic_bytes_per_launch": int(nb), "avg_launch_ms": round(per[k], 5),
+                "valu_issue": valu_issue(k, per[k]) if profiled else None}
 
-        orc = O.OracleSim(dim=dim, bc=cfg["bc"], box=[box] * dim, dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"],
-                          kappa_a=cfg["kappa_a"], k_off=cfg["k_off"], store_f32=cfg["precision"] != S.PREC_FP64,
-                          eps_cut=args.eps_cut, species=sp, pos=pos)
-        tc = time.perf_counter()
-        orc.step(args.cpu_steps)
-        tc = time.perf_counter() - tc
-        cpu = {"value": round(len(sp) * args.cpu_steps / tc, 1), "unit": "particle-steps/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{args.cpu_steps} steps of the same {len(sp)}-particle workload from the same initial "
-                         f"state, single-threaded FP64 C oracle ({tc:.1f} s)"}
-        log(f"[bench] cpu baseline {cpu}")
+    move_roof = hbm_roof("move")
+    roof = angle_step_roofline(per["angles"], profiled) if dom == "angles" else (hbm_roof(dom) if dom else None)
+
+    if args.extras:
+        gen.join()
+        extras["pair_probs"] = pair_probs_record(10_000_000, 20, 3, I, S)
+        extras["ensemble"] = ensemble_record(extras.pop("reps"), S)
+        extras["served"] = served_record(extras.pop("trace"), S)
 
     out = {
         "metric": "particle-steps/s at 1e-6 pair-probability accuracy",
@@ -711,8 +898,12 @@ def main():
         "autotune": tuned,
         "plain_fp32": plain,
         "roofline": roof,
+        "move_roofline": move_roof,
         "kernel_ms_per_step": {k: round(v[0] / max(args.steps, 1), 5) for k, v in kt.items()},
         "cpu_baseline": cpu,
+        "ensemble": extras.get("ensemble"),
+        "served": extras.get("served"),
+        "pair_probs": extras.get("pair_probs"),
     }
     print(json.dumps(out), flush=True)
 
