@@ -15,17 +15,15 @@
 // Evaluation as in 3D (angle3.hpp) except:
 //   - Bessel functions of integer order: J by the downward recurrence normalised to j0, j1;
 //     Y upward from y0, y1;
-//   - x integral: 32 Gauss-Legendre panels of ratio 2 on [2^-32, 1] (Y_0 has a logarithm at
-//     x = 0), then panels of equal width at most min(1, 2 pi / (R + R0 - 1)) up to
-//     sqrt(50 / tau);
+//   - x integral: geometric Gauss-Legendre panels on (0, 1] (Y_0 has a logarithm at
+//     x = 0; the kernel's layout is in angle_wg.hpp), then panels of equal width at most
+//     min(1, 2 pi / (R + R0 - 1)) up to sqrt(50 / tau);
 //   - sin(n t) by the three-term recurrence s_{n+1} = 2 cos(t) s_n - s_{n-1}.
 #pragma once
 
 #include "angle3.hpp"
 
 namespace gfbd {
-
-constexpr int ANG2_GEO = 32;  // geometric panels on [2^-32, 1]
 
 // J_0, J_1, Y_0, Y_1 at z (kept out of line: the four library functions are long)
 __device__ __noinline__ void ang_bessel01(double z, double *j0z, double *j1z, double *y0z, double *y1z)

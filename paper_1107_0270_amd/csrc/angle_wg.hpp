@@ -3,32 +3,42 @@
 // After a non-reactive encounter the pair's new separation makes an angle Theta with
 // its pre-step separation drawn from J (G_ref - G_abs) given the new radius (Sec. 3,
 // Details, second item of the propagation; the series of eqs. genericGF3D and
-// genericGF, the Bessel recurrences of eq. 3termBessel).  The series, its quadrature
-// and the distribution functions are those of angle3.hpp (3D) and angle2.hpp (2D);
-// what differs is how the work is laid out:
+// genericGF, the Bessel recurrences of eq. 3termBessel).  The series and the
+// distribution functions are those of angle3.hpp (3D) and angle2.hpp (2D); what
+// differs is how the work is laid out and how much of it is done:
 //
 //   - the pair's quadrature nodes are spread over the workgroup, one node per thread
 //     (more than 128 nodes: batches of 128), so a pair's latency is about that of one
-//     node.  A pair of the 3D workload at tau = 0.8 has exactly 128 nodes, and two
-//     workgroups fit a compute unit, so a step's few hundred pairs run at once;
+//     node.  A pair of the 3D workload at tau = 0.8 has exactly 128 nodes;
+//   - a node computes the orders up to ceil(z + 8 z^{1/3}) + 8 only, z the largest of
+//     its three Bessel arguments (and at most the series' N): beyond the turning point
+//     by that much, J_n(z) and with it every product term is below 1e-28 of w_0 (the
+//     terms fall like ((z/2)^n / n!)^2).  Nodes at small x, which would otherwise carry
+//     all N orders, need a fraction of them;
 //   - the Bessel sequence J of a node comes from the downward recurrence, which yields
 //     it highest order first while the products need it lowest order first.  Instead
 //     of storing the sequence per thread (per-lane scratch memory), the first sweep
-//     keeps the pair (J_k, J_{k+1}) at every sixteenth order k in the thread's column
-//     of LDS (checkpoints), and the second pass regenerates each chunk of sixteen
-//     orders downward from its checkpoint into registers, then consumes it upward
-//     beside the upward recurrence of Y.  Rescaling during the first sweep scales the
-//     checkpoints already kept, so every value is the same solution of the recurrence
-//     up to one common factor, removed by the normalisation to the elementary
-//     J_{-1/2}, J_{1/2} (3D) or to J_0, J_1 (2D).  Eleven checkpoints cover the series'
-//     cap of 160 terms;
+//     keeps the pair (J_k, J_{k+1}) at every 32nd order k in the thread's column of LDS
+//     (checkpoints), and the second pass regenerates each 16-order half of a block
+//     downward from its checkpoint into registers (the lower half runs through the
+//     upper one first), then consumes it upward beside the upward recurrence of Y.
+//     Rescaling during the first sweep scales the checkpoints already kept, so every
+//     value is the same solution of the recurrence up to one common factor, removed by
+//     the normalisation to the elementary J_{-1/2}, J_{1/2} (3D) or to J_0, J_1 (2D).
+//     Six checkpoints cover the series' cap of 160 terms in 37 KB of LDS, so four
+//     workgroups (two waves per SIMD) share a compute unit;
 //   - each chunk's sixteen per-order terms are summed over the wave by a transposing
 //     reduction (halving the orders a lane holds at each exchange: 17 exchanges per
 //     chunk instead of 6 per order) and added into the wave's own row of LDS; the rows
 //     are summed in wave order at the end.  Every sum runs in a fixed order, so the
 //     coefficients, and the draw, do not depend on timing;
-//   - the root of F(.) = u is found by eight rounds of a 129-way search (one point per
-//     thread), an interval of 2 / 129^8 < 3e-17 (3D) or pi / 129^8 (2D).
+//   - 2D: the geometric panels near x = 0 have ratio 4 (twelve on [4^-12, 1]) instead
+//     of the ratio 2 of angle2.hpp; below 4^-12 the integrand (x times a power of
+//     1 / log x) adds less than 1e-17 of w_0;
+//   - the root of F(.) = u is bracketed by four rounds of a 129-way search (one point
+//     per thread), a cell of 2 / 129^4 < 1e-8 (3D) or pi / 129^4 (2D), and then taken
+//     by linear interpolation of F across the cell: F is smooth there, so the error is
+//     about cell^2 |F''/F'| / 8, below 1e-14 for the narrowest distributions allowed.
 #pragma once
 
 #include "angle2.hpp"
@@ -38,18 +48,31 @@ namespace gfbd {
 constexpr int AWG = 128;               // threads per pair
 constexpr int AW_NW = AWG / 64;        // waves per pair
 constexpr int ACS = 16;                // orders per regenerated chunk
-constexpr int ANCK = 11;               // checkpoints: orders 0 .. 175 (the cap needs 0 .. 161)
-static_assert(ACS * ANCK >= ANG_NCAP + 2, "checkpoints must cover the series' cap");
+constexpr int ACK = 2 * ACS;           // most orders between checkpoints
+constexpr int ANCK = 6;                // checkpoints: orders 0 .. 191 (the cap needs 0 .. 161)
+constexpr int ANG_ROUNDS = 4;          // rounds of the 129-way root search
+constexpr int ANG2_GEO4 = 12;          // 2D geometric panels of ratio 4 on [4^-12, 1]
+static_assert(ACK * ANCK >= ANG_NCAP + 2, "checkpoints must cover the series' cap");
 // below this tau the series would need more than ANG_NCAP terms (R R0 / tau > 500 near
 // contact) and the quadrature grows like 1 / sqrt(tau) nodes per pair
 constexpr double ANG_TAU_MIN = 2e-3;
 
 struct AngShared {
-    double ck[ANCK][3][2][AWG];     // checkpoints of the J sequences, a column per thread
+    union {
+        double ck[ANCK][3][2][AWG];  // checkpoints of the J sequences, a column per thread
+        double W[ANG_NCAP + 1];      // the coefficients w_n (after the nodes)
+    };
     double w[AW_NW][ANG_NCAP + 1];  // per-wave partial coefficient sums
-    double W[ANG_NCAP + 1];         // the coefficients w_n
+    double Fv[AWG];                 // F at the search points of a round
     int hit[AW_NW];
 };
+static_assert(sizeof(AngShared) <= 40960, "four workgroups must share a compute unit's LDS");
+
+__device__ __forceinline__ int wave_max_i(int v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
 
 // 1/d from the hardware estimate refined by two Newton steps (the estimate's relative
 // error e becomes e^4): within an ulp or two of the correctly rounded quotient, at a
@@ -110,6 +133,20 @@ __device__ __forceinline__ void ang_fold(double *v, int lane, int m)
     }
 }
 
+// All folds of a chunk of `top` values: on lane bits 32, 16, .. (one per halving); returns
+// the order the lane then holds, its folded bits read high to low.
+template <int n, int top>
+__device__ __forceinline__ int ang_fold_all(double *v, int lane)
+{
+    if constexpr (n == 1) {
+        return 0;
+    } else {
+        constexpr int m = 32 * n / top;  // lane bit of this fold
+        ang_fold<n>(v, lane, m);
+        return ((lane & m) ? n / 2 : 0) + ang_fold_all<n / 2, top>(v, lane);
+    }
+}
+
 // The terms of one node (x, weight g) for orders 0 .. N: each order's sum over the wave
 // is added to wrow[order].  Uniform over the workgroup: N; over the wave: every call.
 template <int DIM>
@@ -119,7 +156,6 @@ __device__ __forceinline__ void ang_node(double x, double g, bool live, double R
     const int tid = threadIdx.x, lane = lane_id();
     // stored indices k: 3D C_k = J_{k-1/2}, k = 0 .. N + 1; 2D J_k, k = 0 .. N
     const int KT = DIM == 3 ? N + 2 : N + 1;
-    const int nck = (KT + ACS - 1) / ACS;  // <= ANCK
     const double z[3] = {x, R * x, R0 * x};
     double inv[3], a[3], b[3];
 #pragma unroll
@@ -128,12 +164,22 @@ __device__ __forceinline__ void ang_node(double x, double g, bool live, double R
         a[j] = 1.0;  // C_m
         b[j] = 0.0;  // C_{m+1}
     }
-    // first sweep, from above both the last order and the turning point (as in angle3.hpp)
+    // this node's indices: up to 8 z^{1/3} + 8 orders beyond the largest argument's turning
+    // point, where every term has fallen below 1e-28 of w_0
     const double zm = fmax(z[0], fmax(z[1], z[2]));
     const int zc = (int)ceil(zm + 8.0 * cbrt(zm));
-    int m = (KT - 1 > zc ? KT - 1 : zc) + 8;
-    if (m < ACS * nck) m = ACS * nck;
-    for (int k = m; k > ACS * nck; --k) {  // nothing kept yet: rescale by selects, no branch
+    const int kt = live ? min(KT, zc + 9) : 0;
+    const int klast = kt - 1;                                 // last index this node uses
+    // 16-order chunks, and checkpoints at every chunk when six of them cover the wave's
+    // orders, else at every other chunk (uniform)
+    const int nch = wave_max_i((max(kt, 1) + ACS - 1) / ACS);
+    const int spc = nch <= ANCK ? 1 : 2;  // chunks per checkpoint
+    const int nck = (nch + spc - 1) / spc;
+    const int top = ACS * spc * nck;      // index of the highest checkpoint
+    // first sweep, from above both the node's last index and the turning point
+    int m = max(klast, zc) + 8;
+    if (m < top) m = top;
+    for (int k = m; k > top; --k) {  // nothing kept yet: rescale by selects, no branch
         const double cf = ang_coef<DIM>(k);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
@@ -143,16 +189,19 @@ __device__ __forceinline__ void ang_node(double x, double g, bool live, double R
             a[j] = big ? c * 1e-250 : c;
         }
     }
-    for (int s = nck - 1; s >= 0; --s) {
+    for (int ch = spc * nck - 1; ch >= 0; --ch) {
+        const int s = ch / spc;
+        if (ch % spc == spc - 1) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            sh.ck[s][j][0][tid] = a[j];  // C at order ACS (s + 1)
-            sh.ck[s][j][1][tid] = b[j];  // and ACS (s + 1) + 1
+            for (int j = 0; j < 3; ++j) {
+                sh.ck[s][j][0][tid] = a[j];  // C at index ACS spc (s + 1)
+                sh.ck[s][j][1][tid] = b[j];  // and the one above
+            }
         }
-        const double base = 2.0 * ACS * s;
+        const double base = 2.0 * ACS * ch;
 #pragma unroll
         for (int i = ACS - 1; i >= 0; --i) {
-            const double cf = base + (DIM == 3 ? 2.0 * i + 1.0 : 2.0 * i + 2.0);  // of index ACS s + i + 1
+            const double cf = base + (DIM == 3 ? 2.0 * i + 1.0 : 2.0 * i + 2.0);  // of index ACS ch + i + 1
             double c[3];
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
@@ -197,25 +246,33 @@ __device__ __forceinline__ void ang_node(double x, double g, bool live, double R
     // J_{nu-1}(x) of the first order: 3D J_{-1/2} = lam C_0; 2D J_{-1} = -J_1
     double jm = DIM == 3 ? lam[0] * a[0] : -lam[0] * b[0];
     bool dead = !live;
-    for (int s = 0; s < nck; ++s) {
+    for (int ch = 0; ch < spc * nck; ++ch) {
         if (__ballot(!dead) == 0) break;  // every node of the wave is past its last order
-        // the chunk, normalised (the recurrence is linear, so scaling its two starting
-        // values scales every value it gives)
-        const double base = 2.0 * ACS * s;  // 2 k at the chunk's first order
+        // the chunk, normalised (the recurrence is linear, so scaling its two starting values
+        // scales every value it gives); a lower chunk of a checkpoint runs through the upper
+        const int s = ch / spc, K = ACS * spc * (s + 1);
         double v[3][ACS];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             double aa = lam[j] * sh.ck[s][j][0][tid], bb = lam[j] * sh.ck[s][j][1][tid];
+#pragma unroll 1
+            for (int k = K; k > ACS * (ch + 1); --k) {
+                const double c = ang_coef<DIM>(k) * inv[j] * aa - bb;
+                bb = aa;
+                aa = c;
+            }
+            const double base = 2.0 * ACS * ch;
 #pragma unroll
             for (int i = ACS - 1; i >= 0; --i) {
-                const double cf = base + (DIM == 3 ? 2.0 * i + 1.0 : 2.0 * i + 2.0);  // of index ACS s + i + 1
+                const double cf = base + (DIM == 3 ? 2.0 * i + 1.0 : 2.0 * i + 2.0);  // of index ACS ch + i + 1
                 const double c = cf * inv[j] * aa - bb;
                 bb = aa;
                 aa = c;
-                v[j][i] = c;  // J at index ACS s + i
+                v[j][i] = c;  // J at index ACS ch + i
             }
         }
-        const int nn0 = ACS * s - (DIM == 3 ? 1 : 0);  // the series order of v[.][0]
+        const int k0 = ACS * ch;                  // index of v[.][0]
+        const int nn0 = k0 - (DIM == 3 ? 1 : 0);  // its series order
         const double dn0 = (double)nn0;
         double t[ACS];
 #pragma unroll
@@ -224,7 +281,7 @@ __device__ __forceinline__ void ang_node(double x, double g, bool live, double R
             const double dn = dn0 + i;
             t[i] = 0.0;
             if (nn < 0 || nn > N) continue;  // uniform
-            if (fabs(y0[0]) > 0x1p500) dead = true;
+            if (k0 + i > klast || fabs(y0[0]) > 0x1p500) dead = true;
             const double jx = v[0][i];
             if (!dead) {
                 // F(R) F(R0) = (J(Rx) A - Y(Rx) B)(J(R0x) A - Y(R0x) B) / (A^2 + B^2)
@@ -251,18 +308,14 @@ __device__ __forceinline__ void ang_node(double x, double g, bool live, double R
                 y0[j] = yn;
             }
         }
-        // sum the chunk's orders over the wave: after the folds on lane bits 5, 4, 3, 2 a
-        // lane holds order 8 b5 + 4 b4 + 2 b3 + b2, summed over its four lanes by bits 1, 0
-        ang_fold<16>(t, lane, 32);
-        ang_fold<8>(t, lane, 16);
-        ang_fold<4>(t, lane, 8);
-        ang_fold<2>(t, lane, 4);
+        // sum the chunk's orders over the wave: the folds on lane bits 5, 4, .. leave a lane
+        // holding one order (its folded bits, high to low), summed over the lanes that
+        // differ in the remaining low bits
+        const int o = ang_fold_all<ACS, ACS>(t, lane);
         double v0 = t[0];
-        v0 += __shfl_xor(v0, 2, 64);
-        v0 += __shfl_xor(v0, 1, 64);
-        const int o = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+        for (int m = 64 / ACS / 2; m >= 1; m >>= 1) v0 += __shfl_xor(v0, m, 64);
         const int nn = nn0 + o;
-        if ((lane & 3) == 0 && nn >= 0 && nn <= N) wrow[nn] += v0;
+        if ((lane & (64 / ACS - 1)) == 0 && nn >= 0 && nn <= N) wrow[nn] += v0;
     }
 }
 
@@ -278,7 +331,7 @@ __device__ __forceinline__ double ang_draw_wg(double tau, double Rin, double R0i
     const int N = ang_terms(R, R0, tau);
     for (int t = tid; t < AW_NW * (ANG_NCAP + 1); t += AWG) (&sh.w[0][0])[t] = 0.0;
     __syncthreads();
-    // nodes: 3D equal panels on [0, X]; 2D geometric panels on [2^-32, 1], then equal ones
+    // nodes: 3D equal panels on [0, X]; 2D geometric panels on [4^-12, 1], then equal ones
     const double X = sqrt(50.0 / tau), hmax = fmin(1.0, 2.0 * PI_D / (R + R0 - 1.0));
     int Q, nuni;
     double h, x1 = 0.0;
@@ -290,7 +343,7 @@ __device__ __forceinline__ double ang_draw_wg(double tau, double Rin, double R0i
         x1 = X < 1.0 ? X : 1.0;
         nuni = X > x1 ? (int)ceil((X - x1) / hmax) : 0;
         h = nuni > 0 ? (X - x1) / nuni : 0.0;
-        Q = 16 * (ANG2_GEO + nuni);
+        Q = 16 * (ANG2_GEO4 + nuni);
     }
     double *wrow = sh.w[wv];
     for (int q0 = 0; q0 < Q; q0 += AWG) {  // uniform
@@ -303,11 +356,11 @@ __device__ __forceinline__ double ang_draw_wg(double tau, double Rin, double R0i
             g = live ? 0.5 * h * gl.w[qq & 15] * exp(-tau * x * x) * x : 0.0;
         } else {
             double lo, hi;
-            if (p < ANG2_GEO) {
-                lo = ldexp(x1, p - ANG2_GEO);
-                hi = 2.0 * lo;
+            if (p < ANG2_GEO4) {
+                lo = ldexp(x1, 2 * (p - ANG2_GEO4));
+                hi = 4.0 * lo;
             } else {
-                lo = x1 + (p - ANG2_GEO) * h;
+                lo = x1 + (p - ANG2_GEO4) * h;
                 hi = lo + h;
             }
             const double c = 0.5 * (lo + hi), hw = 0.5 * (hi - lo);
@@ -341,30 +394,35 @@ __device__ __forceinline__ double ang_draw_wg(double tau, double Rin, double R0i
     const double *V = sh.w[0];
     __syncthreads();
     // root of F(.) = u: F is nondecreasing; each round keeps the cell between the last point
-    // below u and the first at or above it
-    double lo = DIM == 3 ? -1.0 : 0.0, hi = DIM == 3 ? 1.0 : PI_D;
-    for (int it = 0; it < 8; ++it) {
+    // below u and the first at or above it, with F at both ends (F = 0 and 1 at the domain's)
+    double lo = DIM == 3 ? -1.0 : 0.0, hi = DIM == 3 ? 1.0 : PI_D, Flo = 0.0, Fhi = 1.0;
+    for (int it = 0; it < ANG_ROUNDS; ++it) {
         const double d = (hi - lo) / (AWG + 1);
         const double c = lo + d * (tid + 1);
-        const bool ge = (DIM == 3 ? ang_cdf_n(V, Ne, c) : ang2_cdf_n(V, Ne, c)) >= u;
-        const u64 bal = __ballot(ge);
+        const double Fc = DIM == 3 ? ang_cdf_n(V, Ne, c) : ang2_cdf_n(V, Ne, c);
+        sh.Fv[tid] = Fc;
+        const u64 bal = __ballot(Fc >= u);
         if ((tid & 63) == 0) sh.hit[wv] = bal ? __ffsll((unsigned long long)bal) - 1 : 64;
         __syncthreads();
         int j = AWG;  // first point at or above u
         for (int w = AW_NW - 1; w >= 0; --w)
             if (sh.hit[w] < 64) j = 64 * w + sh.hit[w];
-        const double nlo = j == 0 ? lo : lo + d * j;
-        const double nhi = j == AWG ? hi : lo + d * (j + 1);
+        const double nlo = j == 0 ? lo : lo + d * j, nFlo = j == 0 ? Flo : sh.Fv[j - 1];
+        const double nhi = j == AWG ? hi : lo + d * (j + 1), nFhi = j == AWG ? Fhi : sh.Fv[j];
         lo = nlo;
         hi = nhi;
+        Flo = nFlo;
+        Fhi = nFhi;
         __syncthreads();
     }
-    return 0.5 * (lo + hi);
+    // F is linear across the final cell to within cell^2 |F''| / 8
+    const double r = Fhi > Flo ? fmin(fmax((u - Flo) / (Fhi - Flo), 0.0), 1.0) : 0.5;
+    return lo + r * (hi - lo);
 }
 
 // sim_eval_angle: one workgroup per pair.
 template <int DIM>
-__global__ __launch_bounds__(AWG) void k_angle_wg(double tau, uint64_t n, const double *__restrict__ Rv,
+__global__ __launch_bounds__(AWG, 2) void k_angle_wg(double tau, uint64_t n, const double *__restrict__ Rv,
                                                   const double *__restrict__ R0v, const double *__restrict__ uv,
                                                   double *__restrict__ out, GL16 gl)
 {
@@ -391,7 +449,7 @@ __global__ __launch_bounds__(AWG) void k_angle_wg(double tau, uint64_t n, const 
 // R'' a apart along the drawn direction.  A pre-step separation of length zero, or
 // radii beyond any encounter, keep the free end point's direction.
 template <int DIM, class T, int PM, bool BATCH>
-__global__ __launch_bounds__(AWG) void k_angles(const Params *__restrict__ Pd, Rec<T> *__restrict__ rec,
+__global__ __launch_bounds__(AWG, 2) void k_angles(const Params *__restrict__ Pd, Rec<T> *__restrict__ rec,
                                                 const AngEnt *__restrict__ ang, const Counters *__restrict__ C,
                                                 DbgMatch *dbg, GL16 gl)
 {
@@ -403,13 +461,19 @@ __global__ __launch_bounds__(AWG) void k_angles(const Params *__restrict__ Pd, R
     for (u32 w = blockIdx.x; w < n; w += gridDim.x) {  // uniform
         const AngEnt e = ang[w];
         if (!e.on) continue;
-        Rec<T> ra = rec[e.ia], rb = rec[e.ib];
-        const u32 sa = meta_slot(rec_meta(ra)), sb = meta_slot(rec_meta(rb));
-        const Params &Q = rep_params<BATCH>(P, sa);
-        const u32 la = sa - Q.slot_base, lb = sb - Q.slot_base, ls = step - Q.step_base;
-        const uint4 r = philox(la, lb, ls, TAG_ANG, Q.key);
-        const double v = ang_draw_wg<DIM>(Q.tau, e.Rpp, e.R0, u01(r.x), gl, sh);
-        if (threadIdx.x == 0) {
+        double v;
+        {
+            const u32 sa = meta_slot(rec_meta(rec[e.ia])), sb = meta_slot(rec_meta(rec[e.ib]));
+            const Params &Q = rep_params<BATCH>(P, sa);
+            const uint4 r = philox(sa - Q.slot_base, sb - Q.slot_base, step - Q.step_base, TAG_ANG, Q.key);
+            v = ang_draw_wg<DIM>(Q.tau, e.Rpp, e.R0, u01(r.x), gl, sh);
+        }
+        if (threadIdx.x == 0) {  // the records again: nothing held across the draw
+            Rec<T> ra = rec[e.ia], rb = rec[e.ib];
+            const u32 sa = meta_slot(rec_meta(ra)), sb = meta_slot(rec_meta(rb));
+            const Params &Q = rep_params<BATCH>(P, sa);
+            const u32 la = sa - Q.slot_base, lb = sb - Q.slot_base, ls = step - Q.step_base;
+            const uint4 r = philox(la, lb, ls, TAG_ANG, Q.key);
             const double xa[3] = {(double)ra.x, (double)ra.y, (double)ra.z};
             const double xb[3] = {(double)rb.x, (double)rb.y, (double)rb.z};
             double dA[3], dB[3];
