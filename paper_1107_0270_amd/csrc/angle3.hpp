@@ -45,51 +45,6 @@ __device__ __forceinline__ int ang_terms(double R, double R0, double tau)
     return n < ANG_NCAP ? n : ANG_NCAP;
 }
 
-__device__ __forceinline__ double wave_allsum(double v)
-{
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// J_{k-1/2}(z) for k = 0 .. kmax, for three arguments at once (the downward recurrence
-// C_{nu-1} = (2 nu / z) C_nu - C_{nu+1}, nu = k - 1/2, from k = m down): t[j][k] times lam[j].
-__device__ __forceinline__ void ang_miller3(int kmax, const double z[3], double (*t)[ANG_NCAP + 2], double lam[3])
-{
-    // start: J_m / |Y_m| at m = z + t falls like e^{-0.94 t^{3/2} / sqrt(z)} (beyond the turning
-    // point), below 1e-18 for t >= 8 z^{1/3}; and at least 8 orders above kmax
-    const double zm = fmax(z[0], fmax(z[1], z[2]));
-    const int zc = (int)ceil(zm + 8.0 * cbrt(zm));
-    const int m = (kmax > zc ? kmax : zc) + 8;
-    double a[3], b[3], inv[3];  // a = C_{k}, b = C_{k+1}
-    for (int j = 0; j < 3; ++j) {
-        a[j] = 1.0;
-        b[j] = 0.0;
-        inv[j] = 1.0 / z[j];
-    }
-    if (m <= kmax)
-        for (int j = 0; j < 3; ++j) t[j][m] = a[j];
-    for (int k = m; k >= 1; --k) {
-        for (int j = 0; j < 3; ++j) {
-            const double c = (2.0 * k - 1.0) * inv[j] * a[j] - b[j];
-            b[j] = a[j];
-            a[j] = c;
-            if (fabs(c) > 1e250) {  // rescale, including what is already stored
-                a[j] *= 1e-250;
-                b[j] *= 1e-250;
-                for (int q = k; q <= kmax; ++q) t[j][q] *= 1e-250;
-            }
-            if (k - 1 <= kmax) t[j][k - 1] = a[j];
-        }
-    }
-    for (int j = 0; j < 3; ++j) {
-        double s0, c0;
-        sincos(z[j], &s0, &c0);
-        const double s = sqrt(2.0 / (PI_D * z[j]));
-        const double M = fmax(fabs(t[j][0]), fabs(t[j][1])), a0 = t[j][0] / M, a1 = t[j][1] / M;
-        lam[j] = s * (s0 * a1 + c0 * a0) / (a1 * a1 + a0 * a0) / M;
-    }
-}
-
 struct InvTable {
     double v[ANG_NCAP + 2];
     constexpr InvTable() : v()
@@ -98,18 +53,5 @@ struct InvTable {
     }
 };
 __constant__ constexpr InvTable ANG_INV{};  // 1 / (n + 1)
-
-__device__ __forceinline__ double ang_cdf(const double *W, int N, double c)
-{
-    double s = 1.0 + c, pm = 1.0, p = c;
-    const double inv0 = 1.0 / W[0];
-    for (int n = 1; n <= N; ++n) {
-        const double pn1 = ((2.0 * n + 1.0) * c * p - n * pm) * ANG_INV.v[n];
-        s += W[n] * inv0 * (pn1 - pm);
-        pm = p;
-        p = pn1;
-    }
-    return 0.5 * s;
-}
 
 } // namespace gfbd

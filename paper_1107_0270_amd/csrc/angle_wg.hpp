@@ -118,6 +118,37 @@ __device__ __forceinline__ double ang2_cdf_n(const double *V, int N, double t)
     return acc;
 }
 
+// Weights of the Neumann series of J_0, Y_0 and Y_1 in J_k(z), k = 0 .. ANG_KMAX - 1
+// (Abramowitz & Stegun 9.1.88 and 9.1.89, and the derivative of 9.1.89 with Y_0' = -Y_1,
+// J_k' = (J_{k-1} - J_{k+1}) / 2):
+//   1   = J_0 + 2 sum_{k>=1} J_{2k},
+//   Y_0 = (2/pi) [(log(z/2) + gamma) J_0 - 2 sum_{k>=1} (-1)^k J_{2k} / k],
+//   Y_1 = (2/pi) [(log(z/2) + gamma) J_1 - J_0 / z + sum_{j>=0} d_{2j+1} J_{2j+1}],
+//         d_1 = -1, d_{2j+1} = (-1)^{j+1} (1/j + 1/(j+1)).
+// The Miller sweep of a 2D node accumulates the three sums beside the recurrence, so the
+// normalisation and the Y recurrences' starting values need no Bessel function call.
+// w[k]: (-1)^{k/2} / (k/2) at even k >= 2 (0 at k = 0), d_k at odd k.  A node's sweep
+// starts below ANG_KMAX: its arguments are at most (1 + 40 sqrt(tau)) sqrt(50 / tau) <= 442
+// for tau >= ANG_TAU_MIN, so the start z + 8 z^{1/3} + 16 stays below 520.
+constexpr int ANG_KMAX = 1024;
+struct NeumannTable {
+    double w[ANG_KMAX];
+    constexpr NeumannTable() : w()
+    {
+        for (int k = 0; k < ANG_KMAX; ++k) {
+            if (k % 2 == 0) {
+                const int h = k / 2;
+                w[k] = h == 0 ? 0.0 : (h % 2 == 0 ? 1.0 : -1.0) / h;
+            } else {
+                const int j = (k - 1) / 2;
+                w[k] = j == 0 ? -1.0 : (j % 2 == 1 ? 1.0 : -1.0) * (1.0 / j + 1.0 / (j + 1));
+            }
+        }
+    }
+};
+__constant__ constexpr NeumannTable ANG_NEU{};
+constexpr double EULER_GAMMA = 0.57721566490153286061;
+
 // One step of the transposing reduction: lanes that differ in bit `m` exchange the half
 // of their n values the other keeps, and add.  Afterwards lanes with bit m clear hold
 // the lower half, lanes with it set the upper half.
@@ -172,21 +203,50 @@ __device__ __forceinline__ void ang_node(double x, double g, bool live, double R
     const int klast = kt - 1;                                 // last index this node uses
     // 16-order chunks, and checkpoints at every chunk when six of them cover the wave's
     // orders, else at every other chunk (uniform)
-    const int nch = wave_max_i((max(kt, 1) + ACS - 1) / ACS);
+    const int nch = __builtin_amdgcn_readfirstlane(wave_max_i((max(kt, 1) + ACS - 1) / ACS));
     const int spc = nch <= ANCK ? 1 : 2;  // chunks per checkpoint
     const int nck = (nch + spc - 1) / spc;
     const int top = ACS * spc * nck;      // index of the highest checkpoint
-    // first sweep, from above both the node's last index and the turning point
+    // first sweep, from above both the node's last index and the turning point (2D: from the
+    // wave's highest start, so the index is uniform and the series weights are scalar loads)
     int m = max(klast, zc) + 8;
     if (m < top) m = top;
+    if constexpr (DIM == 2) m = __builtin_amdgcn_readfirstlane(wave_max_i(m));
+    // 2D: the Neumann sums (even indices: 2 C_k and w_k C_k; odd: w_k C_k), from C_m = 1
+    double sn[3] = {0.0, 0.0, 0.0}, se[3] = {0.0, 0.0, 0.0}, so[3] = {0.0, 0.0, 0.0};
+    if constexpr (DIM == 2) {
+        const double wm = ANG_NEU.w[m];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            if (m & 1) {
+                so[j] = wm;
+            } else {
+                sn[j] = 2.0;
+                se[j] = wm;
+            }
+        }
+    }
     for (int k = m; k > top; --k) {  // nothing kept yet: rescale by selects, no branch
         const double cf = ang_coef<DIM>(k);
+        const double wk = DIM == 2 ? ANG_NEU.w[k - 1] : 0.0;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const double c = cf * inv[j] * a[j] - b[j];
             const bool big = fabs(c) > 1e250;
             b[j] = big ? a[j] * 1e-250 : a[j];
             a[j] = big ? c * 1e-250 : c;
+            if constexpr (DIM == 2) {
+                const double f = big ? 1e-250 : 1.0;
+                if ((k - 1) & 1) {
+                    sn[j] *= f;
+                    se[j] *= f;
+                    so[j] = so[j] * f + wk * a[j];
+                } else {
+                    sn[j] = sn[j] * f + 2.0 * a[j];
+                    se[j] = se[j] * f + wk * a[j];
+                    so[j] *= f;
+                }
+            }
         }
     }
     for (int ch = spc * nck - 1; ch >= 0; --ch) {
@@ -208,13 +268,25 @@ __device__ __forceinline__ void ang_node(double x, double g, bool live, double R
                 c[j] = cf * inv[j] * a[j] - b[j];
                 b[j] = a[j];
                 a[j] = c[j];
+                if constexpr (DIM == 2) {
+                    const double wk = ANG_NEU.w[ACS * ch + i];
+                    if (i & 1) {
+                        so[j] += wk * c[j];
+                    } else {
+                        sn[j] += 2.0 * c[j];
+                        se[j] += wk * c[j];
+                    }
+                }
             }
             if (fmax(fabs(c[0]), fmax(fabs(c[1]), fabs(c[2]))) > 1e250) {  // rare: one test for the three
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
                     if (!(fabs(c[j]) > 1e250)) continue;
-                    a[j] *= 1e-250;  // rescale, including the checkpoints kept so far
+                    a[j] *= 1e-250;  // rescale, including the checkpoints and sums kept so far
                     b[j] *= 1e-250;
+                    sn[j] *= 1e-250;
+                    se[j] *= 1e-250;
+                    so[j] *= 1e-250;
                     for (int t = s; t < nck; ++t) {
                         sh.ck[t][j][0][tid] *= 1e-250;
                         sh.ck[t][j][1][tid] *= 1e-250;
@@ -227,8 +299,8 @@ __device__ __forceinline__ void ang_node(double x, double g, bool live, double R
     double lam[3], y0[3], ym[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        const double M = fmax(fabs(a[j]), fabs(b[j])), a0 = a[j] / M, a1 = b[j] / M;
         if constexpr (DIM == 3) {
+            const double M = fmax(fabs(a[j]), fabs(b[j])), a0 = a[j] / M, a1 = b[j] / M;
             double s0, c0;
             sincos(z[j], &s0, &c0);
             const double sc = sqrt(2.0 / (PI_D * z[j]));
@@ -236,11 +308,11 @@ __device__ __forceinline__ void ang_node(double x, double g, bool live, double R
             ym[j] = sc * s0;   // Y_{-1/2}
             y0[j] = -sc * c0;  // Y_{1/2}
         } else {
-            double j0z, j1z, y0z, y1z;
-            ang_bessel01(z[j], &j0z, &j1z, &y0z, &y1z);
-            lam[j] = (j0z * a0 + j1z * a1) / (a0 * a0 + a1 * a1) / M;
-            y0[j] = y0z;   // Y_0
-            ym[j] = -y1z;  // Y_{-1} = -Y_1
+            const double l = 1.0 / (sn[j] - a[j]);  // the sum counted C_0 twice
+            const double J0 = l * a[j], J1 = l * b[j], L = log(0.5 * z[j]) + EULER_GAMMA;
+            lam[j] = l;
+            y0[j] = (2.0 / PI_D) * (L * J0 - 2.0 * l * se[j]);             // Y_0
+            ym[j] = -(2.0 / PI_D) * (L * J1 - J0 * inv[j] + l * so[j]);  // Y_{-1} = -Y_1
         }
     }
     // J_{nu-1}(x) of the first order: 3D J_{-1/2} = lam C_0; 2D J_{-1} = -J_1
