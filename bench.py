@@ -46,28 +46,28 @@ def algorithmic_bytes(kernel, n_live, n_a, n_b, n_keys):
 # commands are in profiles/rad3d_step_traffic.md.  Valid only for the kernel sources they were taken
 # on (hash below): after any change to them the field is reported as null.
 MEASURED_TRAFFIC = {
-    "src_hash": "200ef1c5fe98b68c",
+    "src_hash": "48f37c1df50fbf1c",
     "scale_fetch": 1.9998, "scale_write": 1.0,
     "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
-        "move": (9867.9, 31395.5),
-        "scan": (5808.6 + 5824.3, 11.3 + 17376.1),
-        "scatter": (16984.1, 29463.2),
-        "pairs": (9756.0, 299.3),
-        "eval": (3275.9, 199.4),
-        "select_a": (251.1, 60.4),
-        "select_b": (267.5, 12.1),
-        "events": (351.3 + 2.8, 52.9 + 0.9),
+        "move": (9863.2, 31398.0),
+        "scan": (11632.9, 17387.4),
+        "scatter": (17033.0, 29440.7),
+        "pairs": (9762.9, 299.2),
+        "eval": (3275.8, 199.9),
+        "select_a": (251.6, 60.7),
+        "select_b": (263.6, 12.4),
+        "events": (343.8, 73.8),
     },
     # stage -> VALU wave-instructions per launch (SQ_INSTS_VALU summed over the stage's kernels)
     "valu": {
-        "move": 8175113,
-        "scan": 144800 + 271542,
-        "scatter": 723656,
-        "pairs": 5250181,
-        "eval": 636125,
-        "select_a": 69866,
-        "select_b": 214480,
-        "events": 1204444 + 21,
+        "move": 8175115,
+        "scan": 416342,
+        "scatter": 723654,
+        "pairs": 5250462,
+        "eval": 635944,
+        "select_a": 69729,
+        "select_b": 214471,
+        "events": 1146462,
     },
 }
 
@@ -144,14 +144,14 @@ def angle_roofline(n, launch_ms, dim=3):
 
 
 # The step's angle stage (k_angles) on the default run of this workload: fp64 operations and VALU
-# wave-instructions per launch from rocprofv3 (SQ_INSTS_VALU_{ADD,MUL,FMA}_F64 x 64 lanes, an FMA
-# counting two; SQ_INSTS_VALU), and its HBM bytes (FETCH_SIZE, WRITE_SIZE scaled as above),
-# profiles/rad3d_step_angles.md.  Valid for the sources they were taken on (hash below).
+# wave-instructions per launch from rocprofv3 (SQ_INSTS_VALU_{ADD,MUL,TRANS,FMA}_F64 x 64 lanes, an
+# FMA counting two; SQ_INSTS_VALU), and its HBM bytes (FETCH_SIZE, WRITE_SIZE scaled as above),
+# profiles/rad3d_step_valu.md and profiles/rad3d_step_traffic.md.  Valid for the sources they were taken on (hash below).
 ANGLE_STEP_COUNTERS = {
-    "src_hash": None,
-    "f64_flop": None,
-    "valu": None,
-    "traffic": None,
+    "src_hash": "17d6d994515ec2e9",
+    "f64_flop": 2.445523e+08,  # 64 x (ADD 252363 + MUL 949018 + TRANS 85469 + 2 x FMA 1267140)
+    "valu": 4230347,
+    "traffic": 935529,
 }
 ANGLE_STEP_SOURCES = ["common.hpp", "green.hpp", "green2x.hpp", "kernels.hpp", "angle3.hpp", "angle2.hpp",
                       "angle_wg.hpp", "gfbd.hip"]
