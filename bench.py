@@ -104,27 +104,27 @@ def valu_issue(stage, launch_ms):
             "frac": round(at_peak / launch_ms, 4), "peak_wave_instr_per_s": VALU_WAVE_INSTR_PER_S}
 
 
-# k_angle3 / k_angle2 on the --angle workloads (3D: 10^6 pairs, tau = 0.8; 2D: 2 x 10^5 pairs,
-# tau = 0.04): fp64 operations and VALU wave-instructions per launch from rocprofv3
-# (SQ_INSTS_VALU_{ADD,MUL,FMA}_F64 x 64 lanes, an FMA counting two; SQ_INSTS_VALU),
+# k_angle_wg on the --angle workloads (3D: 10^6 pairs, tau = 0.8; 2D: 2 x 10^5 pairs, tau = 0.04):
+# fp64 operations and VALU wave-instructions per launch from rocprofv3
+# (SQ_INSTS_VALU_{ADD,MUL,TRANS,FMA}_F64 x 64 lanes, an FMA counting two; SQ_INSTS_VALU),
 # profiles/angle3_kernels.md and profiles/angle2_kernels.md.  Valid for the source they were taken on.
 ANGLE_COUNTERS = {3: {
-    "src_hash": "c4526d49b3bc106f",
+    "src_hash": "15e9c7e6faa9b4f2",
     "pairs": 1000000,
-    "f64_flop": 5.829525e+11,  # 64 x (ADD 999569215 + MUL 2356711619 + 2 x FMA 2876175716)
-    "valu": 12999570030,
-}, 2: {  # k_angle2 on --angle 200000 --dim 2 (membrane pairs, tau = 0.04)
-    "src_hash": "1104b0885b8a5772",
+    "f64_flop": 4.996610e+11,  # 64 x (ADD 477553144 + MUL 2033187870 + TRANS 167947286 + 2 x FMA 2564257147)
+    "valu": 8195779186,
+}, 2: {  # k_angle_wg<2> on --angle 200000 --dim 2 (membrane pairs, tau = 0.04)
+    "src_hash": "c96d0910d1aefd6f",
     "pairs": 200000,
-    "f64_flop": 1.233329e+12,  # 64 x (ADD 2247871428 + MUL 4040642340 + 2 x FMA 6491125936)
-    "valu": 31842732517,
+    "f64_flop": 7.410691e+11,  # 64 x (ADD 659523594 + MUL 2804765535 + TRANS 222414722 + 2 x FMA 3946250088)
+    "valu": 10996797065,
 }}
 FP64_VECTOR_PEAK = 78.6e12  # MI355X dense fp64 vector FLOP/s
 
 
 def angle_src_hash(dim=3):
     h = hashlib.sha256()
-    for f in ["angle3.hpp"] + (["angle2.hpp"] if dim == 2 else []):
+    for f in ["angle3.hpp", "angle_wg.hpp"] + (["angle2.hpp"] if dim == 2 else []):
         with open(os.path.join(ROOT, "paper_1107_0270_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
