@@ -206,6 +206,61 @@ def compare_step(gpu, orc, rep: Report, *, p_tol, pos_tol, box, rcut, sp_before,
     return osp
 
 
+class MemberView:
+    """One member of a batch or pool handle, seen by compare_step in the member's own slot
+    numbering (slots lo .. lo + n - 1 of the handle become 0 .. n - 1).  Stepping it steps the
+    whole handle.  Its logs are the handle's logs restricted to the member's slots; a member's
+    pairs, picks, matches and dissociations never involve another member's slots.  There is no
+    per-member reload, so a comparison that would need one fails."""
+
+    def __init__(self, h, lo, n):
+        self.h, self.lo, self.n = h, int(lo), int(n)
+
+    def step(self):
+        self.h.step()
+
+    def _cut(self, log, key, shift):
+        keep = (log[key] >= self.lo) & (log[key] < self.lo + self.n)
+        out = log[keep].copy()
+        for f in shift:
+            if f in out.dtype.names:
+                ok = out[f] != np.uint32(0xFFFFFFFF)
+                out[f][ok] -= np.uint32(self.lo)
+        return out
+
+    def dbg_moved(self):
+        return self.h.dbg_moved()[self.lo:self.lo + self.n]
+
+    def dbg_pairs(self):
+        full = self.h.dbg_pairs()
+        if len(full) != self.h.stats()["pairs"]:
+            raise AssertionError(f"GPU pair log truncated: {len(full)} of {self.h.stats()['pairs']} (raise debug_cap)")
+        return self._cut(full, "i", ("i", "j"))
+
+    def stats(self):
+        return {"pairs": len(self.dbg_pairs())}
+
+    def dbg_picks(self):
+        return self._cut(self.h.dbg_picks(), "i", ("i", "j"))
+
+    def dbg_matches(self):
+        return self._cut(self.h.dbg_matches(), "i", ("i", "j"))
+
+    def dbg_diss(self):
+        return self._cut(self.h.dbg_diss(), "c", ("c", "j"))
+
+    def state(self):
+        sp, pos, pt = self.h.state()
+        sl = slice(self.lo, self.lo + self.n)
+        sp, pos, pt = sp[sl].copy(), pos[sl].copy(), pt[sl].copy()
+        c = sp == S.SP_C
+        pt[c] -= np.uint32(self.lo)
+        return sp, pos, pt
+
+    def load_state(self, *args, **kw):
+        raise AssertionError("the member left the oracle's trajectory (a batch member cannot be reloaded alone)")
+
+
 def run(gpu, orc, steps, *, p_tol, pos_tol, box, lockstep=None):
     """lockstep: reload the GPU with the oracle's state after a step whose positions agree
     within pos_tol but not bit for bit.  By default on wherever angles are drawn: the two

@@ -1,6 +1,6 @@
 """Batches of independent replicas: every replica of a batch must follow exactly the trajectory
-it follows alone (same draws, same arithmetic), whatever the other replicas are.  Single-system
-trajectories are held to the oracle by test_gpu_parity.py."""
+it follows alone (same draws, same arithmetic), whatever the other replicas are, and a replica is
+held to the oracle directly, stage by stage (test_a_batch_member_follows_the_oracle)."""
 import numpy as np
 import pytest
 
@@ -139,4 +139,48 @@ def test_replicas_joining_at_their_own_steps():
     assert np.array_equal(pos[lo:hi][live], ref[1][1][live])
     c = ref[1][0] == S.SP_C
     assert np.array_equal(pt[lo:hi][c].astype(np.int64) - lo, ref[1][2][c].astype(np.int64))
+    b.close()
+
+
+@pytest.mark.parametrize("dim", [3, 2])
+def test_a_batch_member_follows_the_oracle(dim):
+    # One replica of a batch (its own kappa, box and Philox key) in lock step with the oracle's
+    # step of that replica alone (OracleSim(replica=r)): after every step the batch's stage logs
+    # restricted to the replica's slots (post-move positions, pairs with p_enc and draws, picks,
+    # matches with R'', p_reac and the angle, dissociations) and its state are compared with the
+    # oracle's, to the tolerances of the single-system parity tests.
+    import oracle as O
+    from . import parity as PT
+
+    prec = S.PREC_FP32_FP64NC
+    if dim == 3:
+        shared = dict(SHARED)
+        counts = [1200, 2600, 1800]
+        reps = _replicas(counts, prec, seed=11)
+    else:
+        shared = dict(dt=5e-6, D=(0.1, 0.1, 0.05), sigma=0.005, bc=S.BC_RADIATION, k_off=2000.0, seed=3)
+        counts = [900, 1600, 1100]
+        reps = []
+        for r, n in enumerate(counts):
+            box = float(np.float32((n / 1250.0) ** 0.5))
+            sp, pos, _ = I.uniform_state(n // 2, n - n // 2, box=box, dim=2, sigma=0.005, seed=70 + r, f32=True)
+            reps.append(dict(species=sp, pos=pos, box=box, kappa=0.02 + 0.03 * r, replica=4 + r))
+    b = S.Sim.batch(reps, dim=dim, precision=prec, debug=True, debug_cap=1 << 20, eps_cut=1e-3, **shared)
+    r = 1
+    rd = reps[r]
+    view = PT.MemberView(b, b.slot_base[r], counts[r])
+    orc = O.OracleSim(dim=dim, bc=shared["bc"], box=[rd["box"]] * dim, dt=shared["dt"], D=shared["D"],
+                      sigma=shared["sigma"], kappa_a=rd["kappa"], k_off=shared["k_off"], eps_cut=1e-3,
+                      seed=shared["seed"], replica=rd["replica"], store_f32=True, species=rd["species"], pos=rd["pos"])
+    rep = PT.run(view, orc, 24 if dim == 3 else 6, p_tol=1e-6 if dim == 3 else 1e-9, pos_tol=0.0, box=rd["box"],
+                 lockstep=False)
+    print(rep)
+    assert rep.unexplained == 0, rep.notes
+    assert rep.resyncs == 0
+    assert rep.pair_set_mismatch == 0 and rep.draw_mismatch == 0
+    assert rep.near_decisions <= 2
+    assert rep.max_dp <= (1e-6 if dim == 3 else 1e-9)
+    assert rep.max_dRpp <= 1e-9 and rep.max_dpreac <= 1e-9
+    assert rep.max_dcos <= 1e-8
+    assert rep.matches > 0 and rep.angles > 0
     b.close()

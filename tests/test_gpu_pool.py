@@ -1,7 +1,8 @@
 """Pools (continuous batching): systems join a running pool and leave it between steps, and
 every member follows exactly the trajectory it follows alone, whenever it joined, whoever
 shared the pool and wherever its slots landed (including slots freed by a member that left).
-Single-system trajectories are held to the oracle by test_gpu_parity.py."""
+A member that joins a running pool is held to the oracle directly, stage by stage
+(test_a_pool_member_follows_the_oracle)."""
 import numpy as np
 import pytest
 
@@ -160,3 +161,39 @@ def test_pool_errors_and_capacity():
     assert S.lib().sim_pool_admit(single._h, S.C.byref(rep), S.C.byref(m)) == S.SIM_ESTATE
     assert S.lib().sim_pool_retire(single._h, 0) == S.SIM_ESTATE
     single.close()
+
+
+def test_a_pool_member_follows_the_oracle():
+    # A member that joins a running pool (own kappa, box, Philox key, its own step counter
+    # starting at 0 while the pool is at step 5) in lock step with the oracle's step of that
+    # system alone (OracleSim(replica=r)): stage logs restricted to the member's slots and its
+    # state after every step, to the tolerances of the single-system parity tests.
+    import oracle as O
+    from . import parity as PT
+
+    prec = S.PREC_FP32_FP64NC
+    x = _system(3000, 3, 31, 1000.0, prec, kappa=0.5, replica=2)
+    y = _system(2400, 3, 32, 1000.0, prec, kappa=0.1, replica=9)
+    pool = _pool(SHARED3, prec, slot_cap=8000, debug=True, debug_cap=1 << 20, eps_cut=1e-3)
+    pool.admit(**x)
+    pool.step(5)
+    my = pool.admit(**y)
+    # the member's slots in the pool: the first free range after x's (checked against its own read)
+    lo = 3000
+    sp_m, pos_m, _ = pool.member_state(my)
+    sp_all, pos_all, _ = pool.state()
+    assert np.array_equal(sp_all[lo:lo + 2400], sp_m) and np.array_equal(pos_all[lo:lo + 2400], pos_m)
+    view = PT.MemberView(pool, lo, 2400)
+    sh = dict(SHARED3)
+    orc = O.OracleSim(dim=3, bc=sh["bc"], box=[y["box"]] * 3, dt=sh["dt"], D=sh["D"], sigma=sh["sigma"],
+                      kappa_a=y["kappa"], k_off=sh["k_off"], eps_cut=1e-3, seed=sh["seed"], replica=y["replica"],
+                      store_f32=True, species=y["species"], pos=y["pos"])
+    rep = PT.run(view, orc, 20, p_tol=1e-6, pos_tol=0.0, box=y["box"], lockstep=False)
+    print(rep)
+    assert rep.unexplained == 0, rep.notes
+    assert rep.resyncs == 0
+    assert rep.pair_set_mismatch == 0 and rep.draw_mismatch == 0
+    assert rep.near_decisions <= 2
+    assert rep.max_dp <= 1e-6 and rep.max_dRpp <= 1e-9 and rep.max_dpreac <= 1e-9 and rep.max_dcos <= 1e-8
+    assert rep.matches > 0 and rep.angles > 0
+    pool.close()
