@@ -502,6 +502,9 @@ def ensemble_record(reps, S, steps=50, warmup=5, sample=16):
                         "pair cut-off 1e-6"}
 
 
+SERVE_HBM_BUDGET = 32 << 30  # the served stream's ledger: device bytes of running requests, both pools
+
+
 def served_record(trace, S, pool_slots=1 << 26, tick=200, sample=8):
     """The served stream on a given (shortened) trace: p50/p99 latency and aggregate
     particle-steps/s, against the plain path on a sample of its requests."""
@@ -521,7 +524,7 @@ def served_record(trace, S, pool_slots=1 << 26, tick=200, sample=8):
         ps1 += r.n * k
         sim.close()
     srv = V.Server(slot_cap={3: pool_slots, 2: pool_slots}, tick=tick, keep_results=False, read_results=True,
-                   progress=None)
+                   progress=None, hbm_budget=SERVE_HBM_BUDGET)
     srv.run(trace)
     summ = srv.summary(trace)
     log(f"[bench] served: {summ}")
@@ -537,8 +540,11 @@ def served_record(trace, S, pool_slots=1 << 26, tick=200, sample=8):
                         "(seed 0); 3D or 2D with p = 1/2; N log-uniform in [1e3, 1e6]; steps log-uniform in "
                         "[100, 1e4]; overlapping A-B pairs redrawn; 3D: the headline parameters; 2D: D=0.1 um^2/s, "
                         "kappa=0.05 um^2/s, k_off=10/s, dt=5 us; pair cut-off 1e-6",
-            "admission": f"one pool per dimension of {pool_slots} slots; each pool steps to its next completion, "
-                         f"at most {tick} steps per call"}
+            "admission": f"one pool per dimension of {pool_slots} slots; an HBM ledger of {SERVE_HBM_BUDGET >> 30} GiB "
+                         f"for both ({V.BYTES_PER_SLOT} B per particle); arrival order with at most {srv.max_bypass} "
+                         f"later requests admitted ahead of one that does not fit; each pool steps to its next "
+                         f"completion, at most {tick} steps per call",
+            "bypasses": summ["bypasses"], "ledger_peak_bytes": summ["ledger_peak_bytes"]}
 
 
 def _oracle_worker(payload):
@@ -614,7 +620,7 @@ def served(args, S):
     rate1 = ps_single / t_single
     log(f"[serve] plain path on {len(pick)} requests: {rate1:.3e} particle-steps/s")
     srv = V.Server(slot_cap={3: args.pool_slots, 2: args.pool_slots}, tick=args.tick, keep_results=False,
-                   read_results=True, progress=log)
+                   read_results=True, progress=log, hbm_budget=SERVE_HBM_BUDGET)
     srv.run(trace)
     summ = srv.summary(trace)
     log(f"[serve] {summ}")

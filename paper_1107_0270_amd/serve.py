@@ -4,11 +4,16 @@ Requests (a 2D or 3D system of N particles to run for S steps) arrive over time.
 dimension has a worker thread that owns one pool (sim_pool_create) on its own stream, so 2D
 and 3D work proceeds on the device at the same time.  A worker repeatedly
 
-  1. admits waiting requests of its dimension in arrival order while the pool has a free range
-     of slots and cells for them (sim_pool_admit; a request that does not fit waits for
-     members to leave),
+  1. admits arrived requests of its dimension: a request is admitted when the server's HBM
+     ledger (device bytes of all running requests, both pools, against one budget) has room
+     for its footprint and its pool has a free range of slots and cells (sim_pool_admit).
+     Requests go in arrival order, except that when the oldest waiting request does not fit,
+     later arrived requests that fit may go ahead of it, at most `max_bypass` times for that
+     request; after that nothing more is admitted in its dimension until it fits, so no
+     request waits for ever;
   2. steps the pool up to the next completion (at most `tick` steps), and
-  3. reads each finished request's final state and retires it, which frees its slots.
+  3. reads each finished request's final state and retires it, which frees its slots and
+     returns its footprint to the ledger.
 
 A request's result is the one it gets alone: the same draws (keyed on its replica number =
 request id, its own slots and its own steps) and the same arithmetic, whoever shares the pool.
@@ -24,7 +29,9 @@ import numpy as np
 from . import inputs as I
 from . import sim as S
 
-BYTES_PER_PARTICLE = 400  # device memory per slot: records, sort buffers, pair and event lists
+# Device bytes a pool holds per slot (binary32 state): 112 B of records and slot arrays, 176 B of
+# pair lists (4 pairs per slot), 18 B of bucket arrays (half a cell per slot).
+BYTES_PER_SLOT = 306
 
 
 @dataclasses.dataclass
@@ -41,6 +48,7 @@ class Request:
     admitted: float = None
     finished: float = None
     result: tuple = None               # (species, positions, partner) when kept
+    bypassed: int = 0                  # later requests admitted ahead of this one
 
 
 # Shared parameters of each dimension (3D: the radiation workload; 2D: the membrane workload at
@@ -70,10 +78,11 @@ def make_trace(count, rate, seed=0, n_range=(1e3, 1e6), step_range=(100, 10_000)
     return [Request(id=i, dim=int(dims[i]), n=int(ns[i]), steps=int(steps[i]), arrival=float(t[i])) for i in range(count)]
 
 
-def initial_state(req, redraw=False):
-    """Uniform A and B (half each) at the workload density, binary32-exact, from PCG64(10000 + id).
-    Overlapping A-B pairs are left as drawn unless `redraw` (at these densities about 3 in 10^4 B's
-    start within sigma of an A; the step treats them as overlaps)."""
+def initial_state(req, redraw=True):
+    """Uniform A and B (half each) at the workload density, binary32-exact, from PCG64(10000 + id),
+    every B closer than sigma to an A redrawn.  `redraw=False` leaves overlapping pairs as drawn
+    (at these densities about 3 in 10^4 B's start within sigma of an A; the step treats them as
+    overlaps), which generates a large trace several times faster."""
     req.box = request_box(req.dim, req.n)
     n_a = req.n // 2
     if redraw:
@@ -100,6 +109,11 @@ def run_alone(req, keep=True):
     return out
 
 
+def footprint(req):
+    """Device bytes a request holds in its pool while it runs (the ledger's unit)."""
+    return int(req.n) * BYTES_PER_SLOT
+
+
 class _Running:
     def __init__(self, req):
         self.req = req
@@ -110,8 +124,18 @@ class Server:
     """Continuous-batching server: one pool per dimension with room for `slot_cap[dim]` slots
     (its cells: half as many, which covers about one cell per B) and `rep_cap` members."""
 
-    def __init__(self, slot_cap=None, rep_cap=4096, tick=200, keep_results=False, read_results=None, progress=None):
+    def __init__(self, slot_cap=None, rep_cap=4096, tick=200, keep_results=False, read_results=None, progress=None,
+                 hbm_budget=None, max_bypass=8, max_scan=64, pool_factory=None):
         self.slot_cap = dict(slot_cap or {3: 1 << 24, 2: 1 << 24})
+        # the ledger: device bytes of running requests, both pools together (default: what the
+        # two pools hold, so only the pools bound admission)
+        self.hbm_budget = int(hbm_budget) if hbm_budget is not None else sum(self.slot_cap.values()) * BYTES_PER_SLOT
+        self.ledger = 0
+        self.ledger_peak = 0
+        self.max_bypass = int(max_bypass)
+        self.max_scan = int(max_scan)  # waiting requests looked at per admission round
+        self.bypasses = 0
+        self.pool_factory = pool_factory or self._pool
         self.read = keep_results if read_results is None else read_results  # read each final state
         self.progress = progress  # called with a line after every 100th completed request
         self.completed = 0
@@ -129,12 +153,14 @@ class Server:
         for r in requests:
             if r.n > self.slot_cap[r.dim]:
                 raise ValueError(f"request {r.id} needs {r.n} slots, the {r.dim}D pool has {self.slot_cap[r.dim]}")
+            if footprint(r) > self.hbm_budget:
+                raise ValueError(f"request {r.id} needs {footprint(r)} B of the {self.hbm_budget} B ledger")
         self.realtime = realtime
         ordered = sorted(requests, key=lambda r: r.arrival)
         self.pending = {d: [r for r in ordered if r.dim == d] for d in (2, 3)}
         self.errors = []
         # pools are created before the clock starts
-        self.pools = {d: self._pool(d) for d in (2, 3) if self.pending[d]}
+        self.pools = {d: self.pool_factory(d) for d in (2, 3) if self.pending[d]}
         workers = [threading.Thread(target=self._worker, args=(d,)) for d in self.pools]
         self.t0 = time.perf_counter()
         for w in workers:
@@ -166,27 +192,57 @@ class Server:
             else:
                 self.step_calls += n
 
+    def _take(self, fp):
+        with self.lock:
+            if self.ledger + fp > self.hbm_budget:
+                return False
+            self.ledger += fp
+            self.ledger_peak = max(self.ledger_peak, self.ledger)
+            return True
+
+    def _give(self, fp):
+        with self.lock:
+            self.ledger -= fp
+
+    def _admit_ready(self, pool, q, running):
+        """Admit arrived requests of one dimension (see the module text); returns how many."""
+        admitted, i = 0, 0
+        while i < min(len(q), self.max_scan):
+            r = q[i]
+            if self.realtime and r.arrival > self.now():
+                break  # not arrived yet (q is in arrival order)
+            if i > 0 and q[0].bypassed >= self.max_bypass:
+                break  # the oldest request has been passed over enough: it goes next
+            fp = footprint(r)
+            took = self._take(fp)
+            m = pool.try_admit(r.species, r.pos, r.box, replica=r.id) if took else None
+            if m is None:
+                if took:
+                    self._give(fp)  # the ledger had room, the pool had no free range
+                i += 1  # no room for this one: a later arrived request may fit
+                continue
+            q.pop(i)
+            if i > 0:
+                q[0].bypassed += 1
+                with self.lock:
+                    self.bypasses += 1
+            r.admitted = self.now()
+            running[m] = _Running(r)
+            admitted += 1
+        return admitted
+
     def _worker(self, dim):
         try:
             pool, q = self.pools[dim], self.pending[dim]
             running = {}  # member entry -> _Running
             while running or q:
                 t = time.perf_counter()
-                admitted = 0
-                while q and (not self.realtime or q[0].arrival <= self.now()):
-                    r = q[0]
-                    m = pool.try_admit(r.species, r.pos, r.box, replica=r.id)
-                    if m is None:
-                        break  # no room: wait for members to leave
-                    q.pop(0)
-                    r.admitted = self.now()
-                    running[m] = _Running(r)
-                    admitted += 1
+                admitted = self._admit_ready(pool, q, running)
                 if admitted:
                     self._count("admit_s", time.perf_counter() - t, admitted)
                 if not running:
-                    if q and self.realtime:
-                        time.sleep(max(0.0, min(0.02, q[0].arrival - self.now())))
+                    if q:  # nothing arrived yet, or no room while the other pool holds the ledger
+                        time.sleep(min(0.02, max(0.001, q[0].arrival - self.now())) if self.realtime else 0.001)
                     continue
                 k = min(self.tick, min(x.req.steps - x.done for x in running.values()))
                 t = time.perf_counter()
@@ -201,6 +257,7 @@ class Server:
                         if self.keep:
                             x.req.result = out
                     pool.retire(m)
+                    self._give(footprint(x.req))
                     x.req.finished = self.now()
                     with self.lock:
                         self.completed += 1
@@ -223,6 +280,9 @@ class Server:
             "wall_s": self.t_end,
             "particle_steps_per_s": work / self.t_end,
             "admissions": self.admissions,
+            "bypasses": self.bypasses,
+            "hbm_budget_bytes": self.hbm_budget,
+            "ledger_peak_bytes": self.ledger_peak,
             "admit_s": self.admit_s,
             "step_calls": self.step_calls,
             "step_s": self.step_s,
