@@ -129,8 +129,10 @@ typedef struct {
  *   the propagator's distribution function, R'' then drawn by inversion of one uniform, word 0 of
  *   the counter of attempt 0.  Pairs with R0 beyond 1 + c sqrt(tau) (c = 8.4 for tau <= 0.5, 9 above)
  *   use the order-n_terms expansion, which holds there.  Accuracy against the Laplace inversion:
- *   1e-6 for tau <= 0.5, 1.5e-6 up to tau = 0.8; tau > 0.8 is refused (SIM_EUNSUPPORTED), as is
- *   EXACT in 3D (SIM_EINVAL), in batches and pools (SIM_EUNSUPPORTED), and tables over 2^26 entries. */
+ *   1e-6 for tau <= 0.5, 1.5e-6 up to tau = 0.8; tau > 0.8 is refused (SIM_EUNSUPPORTED), as are
+ *   EXACT in 3D (SIM_EINVAL) and tables over 2^26 entries (SIM_EUNSUPPORTED).  Batches and pools
+ *   build one set of tables per distinct kappa (per cut-off) of their replicas or members, kept
+ *   until the handle is destroyed: about 60 MB at tau = 0.8 (three tables of 3,500 x 720 doubles). */
 enum { SIM_G2_EXPANSION = 0, SIM_G2_EXACT = 1 };
 
 /* sim_config.flags.
@@ -176,7 +178,7 @@ typedef struct {
  * sum(n) slots: replica r owns slots [n_0 + ... + n_{r-1}, + n_r) in every read, and partner
  * indices in sim_read / sim_load_state are global.  SIM_READ_DERIVED and SIM_READ_GRID
  * describe replica 0; sim_eval_pairs, sim_eval_propagator, sim_eval_first_passage and sim_eval_angle use replica 0's
- * parameters.
+ * parameters (its exact 2D tables too).
  * pos of replica r holds n * dim values.  Errors as sim_create (reported for the first replica
  * that fails). */
 int sim_batch_create(const sim_config *cfg, uint32_t n_rep, const sim_replica *reps, sim_t **out);
@@ -198,7 +200,10 @@ int sim_pool_create(const sim_config *cfg, uint64_t slot_cap, uint64_t cell_cap,
  * pool and whenever it joins.  *member receives its entry, valid until it is retired.
  * SIM_ECAPACITY if no member entry, no contiguous range of rep->n slots or of its cells is free
  * (nothing changes then: retire members or wait); SIM_EINVAL for an invalid state or box;
- * SIM_ESTATE if h is not a pool.  Synchronises the pool's stream. */
+ * SIM_ESTATE if h is not a pool; SIM_ENOMEM if the exact 2D tables of a new kappa (green2d =
+ * SIM_G2_EXACT, built here before any slot is taken) cannot be allocated.  Synchronises the
+ * pool's stream.  A pool's own sim_eval_pairs and sim_eval_propagator refuse the exact mode
+ * (SIM_EUNSUPPORTED): its tables are its members'. */
 int sim_pool_admit(sim_t *h, const sim_replica *rep, uint32_t *member);
 
 /* Removes a member; its slots and cells are free for later admissions.  SIM_EINVAL if member

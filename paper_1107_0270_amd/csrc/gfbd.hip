@@ -289,7 +289,15 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     bool pool = false;
     std::vector<uint64_t> member_n;  // slots of each member entry, 0 if the entry is free
     RangeAlloc slot_free, cell_free;
-    std::vector<double> x2_build;  // exact 2D tables: quadrature nodes, rows, columns
+    std::vector<double> x2_build;  // exact 2D tables: quadrature nodes, rows, columns (the last built)
+    // exact 2D tables, one set per (h~, r_cut): the members of a batch or pool with equal kappa
+    // share theirs; every set lives as long as the handle
+    bool exact2d = false;
+    struct X2Set {
+        double hh, rcut;
+        Params tab;  // its x2_* fields
+    };
+    std::vector<X2Set> x2_sets;
     hipStream_t own_stream = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     uint32_t n_bricks = 0;
@@ -447,7 +455,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             P.nbz = DIM == 3 ? (P.nc[2] + P.bz - 1) / P.bz : 1;
             n_bricks = P.nbx * P.nby * P.nbz;
         }
-        if (DIM == 2 && M.green2d == SIM_G2_EXACT && (rc = build_x2())) return rc;
+        if (DIM == 2 && M.green2d == SIM_G2_EXACT && (rc = x2_tables(P))) return rc;
         return finish_init(sp, pos, pt);
     }
 
@@ -484,14 +492,45 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     // Gauss-Legendre panels, geometric (ratio 2) from 2^-30/4 to 1/4 where the
     // absorbing and radiation kernels vary like 1/ln x, then of width at most
     // min(1/4, pi / (R_top + R0_top + 1)) up to x = sqrt(50/tau).
-    int build_x2()
+    // The tables of a system (or of a replica or member, into its own parameters Q): from the
+    // handle's sets when one was built for the same h~ and cut-off, else built.
+    int x2_tables(Params &Q)
     {
-        const double tau = P.tau, st = P.sqrt_tau, h = st / 160.0, h0 = X2S * h;
+        exact2d = true;
+        for (const X2Set &x : x2_sets)
+            if (x.hh == Q.hh && x.rcut == Q.rcut) {
+                copy_x2(x.tab, Q);
+                return SIM_OK;
+            }
+        int rc;
+        if ((rc = build_x2(Q))) return rc;
+        x2_sets.push_back({Q.hh, Q.rcut, Q});
+        return SIM_OK;
+    }
+
+    static void copy_x2(const Params &src, Params &Q)
+    {
+        Q.x2_enc = src.x2_enc;
+        Q.x2_reac = src.x2_reac;
+        Q.x2_cdf = src.x2_cdf;
+        Q.x2_h = src.x2_h;
+        Q.x2_inv_h = src.x2_inv_h;
+        Q.x2_inv_h0 = src.x2_inv_h0;
+        Q.x2_r0sw = src.x2_r0sw;
+        Q.x2_r0sw_prop = src.x2_r0sw_prop;
+        Q.x2_n0_prop = src.x2_n0_prop;
+        Q.x2_nr = src.x2_nr;
+        Q.x2_n0 = src.x2_n0;
+    }
+
+    int build_x2(Params &Q)
+    {
+        const double tau = Q.tau, st = Q.sqrt_tau, h = st / 160.0, h0 = X2S * h;
         if (!(tau * (1.0 - 1e-9) <= X2_TAU_MAX)) return fail(SIM_EUNSUPPORTED, "exact 2D functions need tau = D_eff dt / a^2 <= 0.8");
         const double r0sw = 1.0 + x2_switch_c(tau) * st, L = 12.0 * st + 1.0;
         const u32 n0 = (u32)std::ceil((r0sw - 1.0) / h0) + 4;
         const double r0top = 1.0 + (n0 - 1) * h0;
-        const double rtop = std::max(P.rcut / P.a, r0top + L) + 4.0 * h;
+        const double rtop = std::max(Q.rcut / Q.a, r0top + L) + 4.0 * h;
         const u32 nr = (u32)std::ceil((rtop - 1.0) / h) + 1;
         const u32 top = (u32)std::ceil(L / h);
         if ((uint64_t)nr * n0 > (1ull << 26) || nr > 65535u * X2T)
@@ -535,7 +574,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             if ((e = hipMemcpyAsync(d_x, xs.data(), sizeof(double) * K, hipMemcpyHostToDevice, sm)) != hipSuccess) return e;
             if ((e = hipMemcpyAsync(d_s1, s1.data(), sizeof(double) * K, hipMemcpyHostToDevice, sm)) != hipSuccess) return e;
             if ((e = hipMemcpyAsync(d_s2, s2.data(), sizeof(double) * K, hipMemcpyHostToDevice, sm)) != hipSuccess) return e;
-            k_x2_nodes<<<(K + 255) / 256, 256, 0, sm>>>(d_x, K, P.hh, d_nd);
+            k_x2_nodes<<<(K + 255) / 256, 256, 0, sm>>>(d_x, K, Q.hh, d_nd);
             k_x2_rows<<<(u32)((NK + 255) / 256), 256, 0, sm>>>(d_x, d_nd, K, nr, h, Cabs, Cref, Crad, Kabs, Kref);
             const dim3 g((n0 + X2T - 1) / X2T, (nr + X2T - 1) / X2T);
             k_x2_gemm<<<g, 256, 0, sm>>>(Cabs, Cabs, d_s1, nr, n0, K, Gabs);
@@ -550,17 +589,17 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         const hipError_t e = run();
         (void)hipFree(tmp_buf);
         if (e != hipSuccess) return fail(SIM_EDEVICE, std::string("exact 2D tables: ") + hipGetErrorString(e));
-        P.x2_enc = enc;
-        P.x2_reac = reac;
-        P.x2_cdf = cdf;
-        P.x2_h = h;
-        P.x2_inv_h = 1.0 / h;
-        P.x2_inv_h0 = 1.0 / h0;
-        P.x2_r0sw = r0sw;
-        P.x2_r0sw_prop = 1.0 + 8.4 * st;  // the propagator's mass is resolved to about erfc(4.2)
-        P.x2_n0_prop = std::min<u32>(n0, (u32)std::ceil(8.4 * st / h0) + 4);
-        P.x2_nr = nr;
-        P.x2_n0 = n0;
+        Q.x2_enc = enc;
+        Q.x2_reac = reac;
+        Q.x2_cdf = cdf;
+        Q.x2_h = h;
+        Q.x2_inv_h = 1.0 / h;
+        Q.x2_inv_h0 = 1.0 / h0;
+        Q.x2_r0sw = r0sw;
+        Q.x2_r0sw_prop = 1.0 + 8.4 * st;  // the propagator's mass is resolved to about erfc(4.2)
+        Q.x2_n0_prop = std::min<u32>(n0, (u32)std::ceil(8.4 * st / h0) + 4);
+        Q.x2_nr = nr;
+        Q.x2_n0 = n0;
         x2_build = {(double)K, (double)nr, (double)n0};
         return SIM_OK;
     }
@@ -587,6 +626,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             double ce = 0.0, tests = 0.0;
             bool nar = true;
             if ((rc = setup_replica(ms[r], nr[r], sp + sbase, reps_h[r], ce, tests, nar))) return rc;
+            if (DIM == 2 && M.green2d == SIM_G2_EXACT && (rc = x2_tables(reps_h[r]))) return rc;
             reps_h[r].slot_base = (u32)sbase;
             reps_h[r].cell_base = (u32)cbase;
             reps_h[r].step_base = 0u - step0[r];  // own step = counter (0 at creation) - base
@@ -641,6 +681,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         int rc;
         if ((rc = open_stream())) return rc;
         batch = pool = true;
+        exact2d = DIM == 2 && M.green2d == SIM_G2_EXACT;  // tables come with each member
         if ((rc = setup_replica(M, 0, nullptr, P, cell_edge, pair_tests, narrow))) return rc;
         narrow = true;  // until a member needs the general pair search
         reps_h.assign(rep_cap, P);
@@ -780,6 +821,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         double ce = 0.0, tests = 0.0;
         bool nar = true;
         if ((rc = setup_replica(mr, rp.n, rp.species, Q, ce, tests, nar))) return rc;
+        if (DIM == 2 && M.green2d == SIM_G2_EXACT && (rc = x2_tables(Q))) return rc;  // before any slot is taken
         uint64_t s0 = 0, c0 = 0;
         if (!slot_free.take(rp.n, s0)) return fail(SIM_ECAPACITY, "no free range of slots");
         if (!cell_free.take(Q.n_cells, c0)) {
@@ -953,7 +995,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     void enqueue_step(int c)
     {
         if constexpr (DIM == 2) {
-            if (P.x2_enc) return enqueue_step_n<NC_EXACT>(c);
+            if (exact2d) return enqueue_step_n<NC_EXACT>(c);
             if (P.n_terms == 12) return enqueue_step_n<12>(c);
         }
         enqueue_step_n<0>(c);
@@ -1035,6 +1077,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
 
     int eval_pairs(uint64_t n, const double *R, const double *R0, double *penc, double *preac) override
     {
+        if (exact2d && !P.x2_enc) return fail(SIM_EUNSUPPORTED, "the exact 2D tables of a pool are its members': evaluate on a handle of the system");
         const u32 g = grid_for(n, 16384);
         bool done = false;
         if constexpr (DIM == 2) {
@@ -1055,6 +1098,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     int eval_prop(uint64_t n, const double *R0, uint32_t step, int wave, double *Rpp, uint32_t *attempts) override
     {
         if (n > 0xFFFFFFFFull) return fail(SIM_EINVAL, "at most 2^32 draws");
+        if (exact2d && !P.x2_enc) return fail(SIM_EUNSUPPORTED, "the exact 2D tables of a pool are its members': evaluate on a handle of the system");
         if (DIM == 2 && P.x2_enc) launch_prop<NC_EXACT>(n, R0, step, wave, Rpp, attempts);
         else if (DIM == 2 && P.n_terms == 12) launch_prop<12>(n, R0, step, wave, Rpp, attempts);
         else launch_prop<0>(n, R0, step, wave, Rpp, attempts);
@@ -1066,7 +1110,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     int eval_first_passage(uint64_t n, const double *xi, const double *xf, int levels, uint32_t step, uint64_t *lo,
                            uint32_t *attempts) override
     {
-        if (DIM == 2 && (P.x2_enc || P.n_terms != 12))
+        if (DIM == 2 && (exact2d || P.n_terms != 12))
             return fail(SIM_EUNSUPPORTED, "the 2D first-passage bisection takes the expansion of order 12");
         if (n > 0xFFFFFFFFull) return fail(SIM_EINVAL, "at most 2^32 pairs");
         if (levels < 1 || levels > 52) return fail(SIM_EINVAL, "levels must be in [1, 52]");
@@ -1493,7 +1537,6 @@ int sim_batch_create(const sim_config *cfg, uint32_t n_rep, const sim_replica *r
     if (!out) { g_err = "null output handle"; return SIM_EINVAL; }
     *out = nullptr;
     if (!cfg || !reps || n_rep == 0) { g_err = "null argument or no replicas"; return SIM_EINVAL; }
-    if (cfg->green2d == SIM_G2_EXACT) { g_err = "exact 2D tables are per system: not in batches"; return SIM_EUNSUPPORTED; }
     std::vector<Model> ms(n_rep);
     std::vector<uint64_t> nr(n_rep);
     std::vector<u32> step0(n_rep);
@@ -1547,7 +1590,6 @@ int sim_pool_create(const sim_config *cfg, uint64_t slot_cap, uint64_t cell_cap,
     Model M;
     int rc;
     if ((rc = validate_cfg(cfg, M))) return rc;
-    if (M.green2d == SIM_G2_EXACT) { g_err = "exact 2D tables are per system: not in pools"; return SIM_EUNSUPPORTED; }
     if (slot_cap == 0 || slot_cap > SLOT_MASK) { g_err = "slot capacity must be in [1, 2^29)"; return SIM_EINVAL; }
     if (cell_cap == 0 || cell_cap > (1ull << 28)) { g_err = "cell capacity must be in [1, 2^28]"; return SIM_EINVAL; }
     if (rep_cap == 0 || rep_cap > (1u << 20)) { g_err = "member capacity must be in [1, 2^20]"; return SIM_EINVAL; }

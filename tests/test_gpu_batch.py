@@ -184,3 +184,32 @@ def test_a_batch_member_follows_the_oracle(dim):
     assert rep.max_dcos <= 1e-8
     assert rep.matches > 0 and rep.angles > 0
     b.close()
+
+
+def test_2d_exact_batch_replicas_run_as_alone():
+    # tau = 0.8: the batch builds exact 2D tables per distinct kappa (replicas 0 and 2 share a
+    # set) and every replica follows its single-system trajectory (exact tables too) bit for bit
+    shared2 = dict(dim=2, dt=1e-4, D=(0.1, 0.1, 0.05), sigma=0.005, bc=S.BC_RADIATION, k_off=2000.0, seed=3,
+                   precision=S.PREC_FP32_FP64NC, green2d=S.G2_EXACT)
+    reps = []
+    for r, (n, kappa) in enumerate([(1000, 0.05), (1500, 0.1), (1200, 0.05)]):
+        box = float(np.float32((n / 1250.0) ** 0.5))
+        sp, pos, _ = I.uniform_state(n // 2, n - n // 2, box=box, dim=2, sigma=0.005, seed=80 + r, f32=True)
+        reps.append(dict(species=sp, pos=pos, box=box, kappa=kappa, replica=r))
+    b = S.Sim.batch(reps, **shared2)
+    b.step(8)
+    sp, pos, pt = b.state()
+    for r, rd in enumerate(reps):
+        kw = dict(shared2)
+        kw.pop("dim")
+        a = S.Sim(dim=2, box=rd["box"], species=rd["species"], pos=rd["pos"], kappa=rd["kappa"], replica=rd["replica"], **kw)
+        a.step(8)
+        sp1, pos1, pt1 = a.state()
+        st = a.stats(total=True)
+        a.close()
+        lo, hi = b.slot_base[r], b.slot_base[r] + len(rd["species"])
+        assert np.array_equal(sp[lo:hi], sp1), f"replica {r}"
+        live = sp1 <= S.SP_C
+        assert np.array_equal(pos[lo:hi][live], pos1[live]), f"replica {r}"
+        print(f"replica {r}: matches {st['matches']} reactions {st['react']}")
+    b.close()

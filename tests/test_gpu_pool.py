@@ -197,3 +197,42 @@ def test_a_pool_member_follows_the_oracle():
     assert rep.max_dp <= 1e-6 and rep.max_dRpp <= 1e-9 and rep.max_dpreac <= 1e-9 and rep.max_dcos <= 1e-8
     assert rep.matches > 0 and rep.angles > 0
     pool.close()
+
+
+def test_2d_exact_pool_member_follows_the_oracle():
+    # The membrane workload as written (tau = 0.8) needs the exact 2D tables (the expansion is
+    # refused there).  A pool builds them per member kappa (members with equal kappa share a
+    # set); a member that joins the running pool is held to the oracle's exact step of its own
+    # system.  binary64 state: R'' comes from interpolated tables, so products may land ~1e-9 um
+    # from the oracle's, held to 1e-7 um without reloading.
+    import oracle as O
+    from . import parity as PT
+
+    prec = S.PREC_FP64
+    sh = dict(SHARED2, dt=1e-4)
+    x = _system(1400, 2, 41, 2500.0, prec, kappa=0.05, replica=3)
+    y = _system(1200, 2, 42, 2500.0, prec, kappa=0.2, replica=8)
+    pool = _pool(sh, prec, slot_cap=4000, debug=True, debug_cap=1 << 20, eps_cut=1e-3, green2d=S.G2_EXACT)
+    pool.admit(**x)
+    pool.step(3)
+    my = pool.admit(**y)
+    lo = 1400
+    sp_m, pos_m, _ = pool.member_state(my)
+    sp_all, pos_all, _ = pool.state()
+    assert np.array_equal(sp_all[lo:lo + 1200], sp_m) and np.array_equal(pos_all[lo:lo + 1200], pos_m)
+    view = PT.MemberView(pool, lo, 1200)
+    orc = O.OracleSim(dim=2, bc=sh["bc"], box=[y["box"]] * 2, dt=sh["dt"], D=sh["D"], sigma=sh["sigma"],
+                      kappa_a=y["kappa"], k_off=sh["k_off"], eps_cut=1e-3, seed=sh["seed"], replica=y["replica"],
+                      store_f32=False, exact2d=True, species=y["species"], pos=y["pos"])
+    rep = PT.run(view, orc, 6, p_tol=1e-6, pos_tol=1e-7, box=y["box"], lockstep=False)
+    print(rep)
+    assert rep.unexplained == 0, rep.notes
+    assert rep.resyncs == 0
+    assert rep.pair_set_mismatch == 0 and rep.draw_mismatch == 0
+    assert rep.near_decisions <= 2
+    assert rep.max_dp <= 1e-6 and rep.max_dRpp <= 1e-4 and rep.max_dpreac <= 1e-6
+    assert rep.matches > 0 and rep.angles > 0
+    # the pool's own kernel-level evaluation has no tables of its own: refused, not approximated
+    with pytest.raises(S.SimError):
+        pool.eval_pairs(np.array([1.1]), np.array([1.2]))
+    pool.close()
