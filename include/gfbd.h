@@ -65,9 +65,13 @@ enum { SIM_BC_ABSORBING = 0, SIM_BC_REFLECTING = 1, SIM_BC_RADIATION = 2 };
  *  FP64          state and all arithmetic in binary64;
  *  FP32          binary32 state; displacements (Box-Muller), pair search and p_enc in binary32;
  *  FP32_FP64NC   binary32 state, binary64 displacements, binary32 p_enc whose arguments (r, r - a,
- *                r0 - a and the exponent arguments) are formed in binary64.
+ *                r0 - a and the exponent arguments) are formed in binary64;
+ *  FP32D_FP64NC  as FP32_FP64NC, with the displacements of FP32 (binary32 Box-Muller).  Its moves
+ *                differ from the binary64 ones by binary32 roundings of the displacement, so its
+ *                trajectories are compared stage by stage from the step's own post-move state
+ *                (SIM_READ_DBG_MOVED, SIM_READ_DBG_DISP).
  * Placements, the propagator and p_reac are binary64 in all modes. */
-enum { SIM_PREC_FP64 = 0, SIM_PREC_FP32 = 1, SIM_PREC_FP32_FP64NC = 2 };
+enum { SIM_PREC_FP64 = 0, SIM_PREC_FP32 = 1, SIM_PREC_FP32_FP64NC = 2, SIM_PREC_FP32D_FP64NC = 3 };
 
 /* Kernel of the pair search (step 2); both find exactly the same pairs.
  *  BRICKS  one workgroup per brick of cells stages the B records of the brick
@@ -238,7 +242,9 @@ enum {
     SIM_READ_DBG_DISS = 11, /* sim_dbg_diss[] (debug) */
     SIM_READ_DBG_CELLS = 12,/* uint32[n]: sort key (species * n_cells + cell) of each live slot after binning, else 0xFFFFFFFF (debug) */
     SIM_READ_TIMING = 13,   /* sim_kernel_time[SIM_K_N]: accumulated kernel times (timing) */
-    SIM_READ_GRID = 14      /* int64[5]: cells per edge x, y, z, total cells, pair-search kernel (SIM_PAIRS_BRICKS or _DIRECT) */
+    SIM_READ_GRID = 14,     /* int64[5]: cells per edge x, y, z, total cells, pair-search kernel (SIM_PAIRS_BRICKS or _DIRECT) */
+    SIM_READ_DBG_DISP = 15  /* double[n*dim]: the displacement each live slot took in the move of the last step, as
+                             * the step's later stages regenerate it (debug); NaN for FREE/RESERVED */
 };
 
 enum {

@@ -108,6 +108,8 @@ def lib():
         "orc_sim_derived": (None, [vp, P(d)]),
         "orc_sim_state": (None, [vp, vp, vp, vp]),
         "orc_sim_moved": (None, [vp, vp]),
+        "orc_sim_set_moved": (None, [vp, vp, vp]),
+        "orc_sim_moved_own": (None, [vp, vp]),
         "orc_sim_stats": (None, [vp, P(u64)]),
         "orc_sim_n_pairs": (u64, [vp]),
         "orc_sim_n_picks": (u64, [vp]),
@@ -410,6 +412,19 @@ class OracleSim:
     def moved(self):
         pos = np.zeros((self.n, self.dim))
         lib().orc_sim_moved(self._h, pos.ctypes.data)
+        return pos
+
+    def set_moved(self, pos, disp):
+        """Stage parity: the next step takes these post-move positions and displacements ((n, dim)
+        each, by slot) in place of its own move; its own move is kept (moved_own)."""
+        pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(self.n, self.dim)
+        disp = np.ascontiguousarray(disp, dtype=np.float64).reshape(self.n, self.dim)
+        lib().orc_sim_set_moved(self._h, pos.ctypes.data, disp.ctypes.data)
+        self._given = (pos, disp)
+
+    def moved_own(self):
+        pos = np.zeros((self.n, self.dim))
+        lib().orc_sim_moved_own(self._h, pos.ctypes.data)
         return pos
 
     def stats(self):

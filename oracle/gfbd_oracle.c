@@ -662,6 +662,10 @@ struct orc_sim {
     uint64_t cap, step;
     int32_t *sp;
     double *x, *xm, *dx;
+    /* stage parity: the next step takes its post-move positions and displacements from the
+     * caller (orc_sim_set_moved); its own move goes to xo for comparison */
+    int given;
+    double *xg, *dg, *xo;
     uint32_t *partner;
     uint8_t *born;
     double Deff, tau, hh, rcut, a, p_uni;
@@ -739,6 +743,7 @@ void orc_sim_destroy(orc_sim *s)
 {
     if (!s) return;
     free(s->sp); free(s->x); free(s->xm); free(s->dx); free(s->partner); free(s->born);
+    free(s->xg); free(s->dg); free(s->xo);
     free(s->pairs); free(s->picks); free(s->matches); free(s->diss);
     free(s);
 }
@@ -895,10 +900,18 @@ void orc_sim_step(orc_sim *s)
         double sc = sqrt(2.0 * s->p.D[sp] * s->p.dt);
         for (int k = 0; k < d; ++k) {
             double dk = sc * z[k];
-            s->dx[i * 3 + k] = dk;
-            s->x[i * 3 + k] = wrap_store(s, s->x[i * 3 + k] + dk, s->p.box[k]);
+            double y = wrap_store(s, s->x[i * 3 + k] + dk, s->p.box[k]);
+            if (s->given) {  /* its own move, kept for comparison; the step goes on from the caller's */
+                s->xo[i * 3 + k] = y;
+                s->dx[i * 3 + k] = s->dg[i * 3 + k];
+                s->x[i * 3 + k] = s->xg[i * 3 + k];
+            } else {
+                s->dx[i * 3 + k] = dk;
+                s->x[i * 3 + k] = y;
+            }
         }
     }
+    s->given = 0;
     memcpy(s->xm, s->x, n * 3 * sizeof(double));
 
     /* Steps 2 and 3: all A-B pairs within r_cut (Sec. 3, Details, cut-off),
@@ -1193,6 +1206,34 @@ void orc_sim_state(const orc_sim *s, int32_t *species, double *pos, uint32_t *pa
         if (pos)
             for (int k = 0; k < d; ++k) pos[i * d + k] = s->x[i * 3 + k];
     }
+}
+
+/* Stage parity: the next step uses these post-move positions and displacements (n * dim
+ * each, by slot; entries of FREE and RESERVED slots are ignored) in place of its own move,
+ * and runs every later stage on them; its own move is kept for orc_sim_moved_own. */
+void orc_sim_set_moved(orc_sim *s, const double *pos, const double *disp)
+{
+    const int d = s->p.dim;
+    const uint64_t n = s->cap;
+    if (!s->xg) {
+        s->xg = (double *)calloc(n * 3, sizeof(double));
+        s->dg = (double *)calloc(n * 3, sizeof(double));
+        s->xo = (double *)calloc(n * 3, sizeof(double));
+    }
+    for (uint64_t i = 0; i < n; ++i)
+        for (int k = 0; k < d; ++k) {
+            s->xg[i * 3 + k] = pos[i * d + k];
+            s->dg[i * 3 + k] = disp[i * d + k];
+        }
+    s->given = 1;
+}
+
+/* The oracle's own post-move positions of the last step taken after orc_sim_set_moved. */
+void orc_sim_moved_own(const orc_sim *s, double *pos)
+{
+    int d = s->p.dim;
+    for (uint64_t i = 0; i < s->cap; ++i)
+        for (int k = 0; k < d; ++k) pos[i * d + k] = s->xo ? s->xo[i * 3 + k] : NAN;
 }
 
 void orc_sim_moved(const orc_sim *s, double *pos)

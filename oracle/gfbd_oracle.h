@@ -144,6 +144,8 @@ uint64_t orc_sim_stepno(const orc_sim *s);
 void orc_sim_derived(const orc_sim *s, double out[6]); /* Deff, tau, hh, rcut, a, p_uni */
 void orc_sim_state(const orc_sim *s, int32_t *species, double *pos, uint32_t *partner);
 void orc_sim_moved(const orc_sim *s, double *pos_after_move);
+void orc_sim_set_moved(orc_sim *s, const double *pos, const double *disp);
+void orc_sim_moved_own(const orc_sim *s, double *pos);
 void orc_sim_stats(const orc_sim *s, uint64_t out[ORC_ST_N]);
 uint64_t orc_sim_n_pairs(const orc_sim *s);
 uint64_t orc_sim_n_picks(const orc_sim *s);

@@ -27,8 +27,9 @@ enum : u32 {
 };
 
 // Arithmetic of the pair probability: binary64 throughout, binary32, or
-// binary32 with binary64 separations and exponent arguments.
-enum { PM_F64 = 0, PM_F32 = 1, PM_F32NC = 2 };
+// binary32 with binary64 separations and exponent arguments (displacements in
+// binary64, or in binary32 as the plain mode takes them: PM_F32D).
+enum { PM_F64 = 0, PM_F32 = 1, PM_F32NC = 2, PM_F32D = 3 };
 
 struct Key {
     u32 k0, k1;

@@ -302,7 +302,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     uint32_t n_bricks = 0;
     double *g2c = nullptr;
-    double *g_pos = nullptr, *dbg_moved = nullptr;
+    double *g_pos = nullptr, *dbg_moved = nullptr, *dbg_disp = nullptr;
     int *g_sp = nullptr;
     u32 *dbg_cells = nullptr;
     DbgPair *dbg_pairs = nullptr;
@@ -734,7 +734,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             return rc;
         gauss_legendre16(gl16.x, gl16.w);
         if (M.debug) {
-            if ((rc = alloc(dbg_moved, n * DIM)) || (rc = alloc(dbg_cells, n)) || (rc = alloc(dbg_pairs, M.dbg_cap)) ||
+            if ((rc = alloc(dbg_moved, n * DIM)) || (rc = alloc(dbg_disp, n * DIM)) || (rc = alloc(dbg_cells, n)) || (rc = alloc(dbg_pairs, M.dbg_cap)) ||
                 (rc = alloc(dbg_picks, M.dbg_cap)) || (rc = alloc(dbg_matches, M.dbg_cap)) || (rc = alloc(dbg_diss, M.dbg_cap)))
                 return rc;
         }
@@ -1022,6 +1022,8 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         if (M.debug) {
             k_fill<<<grid_for(n * DIM, 2048), BLOCK, 0, st>>>(dbg_moved, n * DIM, (int *)dbg_cells, (u32)n);
             k_gather<DIM, T><<<g_all, BLOCK, 0, st>>>(out, partner, ctr, 1, dbg_moved, nullptr, (u32)n);
+            k_fill<<<grid_for(n * DIM, 2048), BLOCK, 0, st>>>(dbg_disp, n * DIM, nullptr, 0);
+            k_dbg_disp<DIM, T, PM, BATCH><<<g_all, BLOCK, 0, st>>>(P, out, ctr, dbg_disp, (u32)n);
             k_dbg_cells<<<g_all, BLOCK, 0, st>>>(P, std::is_same<T, float>::value ? (const Rec<float> *)out : nullptr,
                                                  std::is_same<T, double>::value ? (const Rec<double> *)out : nullptr, start, ctr,
                                                  dbg_cells);
@@ -1256,6 +1258,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         if (!M.debug) return fail(SIM_ESTATE, "debug logs need sim_config.debug = 1");
         switch (what) {
         case SIM_READ_DBG_MOVED: return copy_out(dbg_moved, sizeof(double) * n * DIM, dst, cap, written);
+        case SIM_READ_DBG_DISP: return copy_out(dbg_disp, sizeof(double) * n * DIM, dst, cap, written);
         case SIM_READ_DBG_CELLS: return copy_out(dbg_cells, sizeof(u32) * n, dst, cap, written);
         case SIM_READ_DBG_PAIRS: return copy_out(dbg_pairs, sizeof(DbgPair) * std::min<uint64_t>(c.n_dbg[0], M.dbg_cap), dst, cap, written);
         case SIM_READ_DBG_PICKS: return copy_out(dbg_picks, sizeof(DbgPick) * std::min<uint64_t>(c.n_dbg[1], M.dbg_cap), dst, cap, written);
@@ -1318,7 +1321,7 @@ int validate_cfg(const sim_config *cfg, Model &M)
 {
     if (!cfg) { g_err = "null argument"; return SIM_EINVAL; }
     if (cfg->dim != 2 && cfg->dim != 3) { g_err = "dim must be 2 or 3"; return SIM_EINVAL; }
-    if (cfg->precision < 0 || cfg->precision > 2) { g_err = "unknown precision"; return SIM_EINVAL; }
+    if (cfg->precision < 0 || cfg->precision > 3) { g_err = "unknown precision"; return SIM_EINVAL; }
     if (cfg->n_species != 3 || !cfg->species) { g_err = "exactly three species (A, B, C) are supported"; return SIM_EUNSUPPORTED; }
     if (cfg->n_reactions != 1 || !cfg->reactions) { g_err = "exactly one reaction A + B <-> C is supported"; return SIM_EUNSUPPORTED; }
     const sim_reaction &r = cfg->reactions[0];
@@ -1507,10 +1510,12 @@ int sim_create(const sim_config *cfg, uint64_t n, const int32_t *species, const 
     if (M.dim == 3) {
         if (M.prec == SIM_PREC_FP64) return make<3, double, PM_F64>(M, n, species, pos, partner, out);
         if (M.prec == SIM_PREC_FP32) return make<3, float, PM_F32>(M, n, species, pos, partner, out);
+        if (M.prec == SIM_PREC_FP32D_FP64NC) return make<3, float, PM_F32D>(M, n, species, pos, partner, out);
         return make<3, float, PM_F32NC>(M, n, species, pos, partner, out);
     }
     if (M.prec == SIM_PREC_FP64) return make<2, double, PM_F64>(M, n, species, pos, partner, out);
     if (M.prec == SIM_PREC_FP32) return make<2, float, PM_F32>(M, n, species, pos, partner, out);
+    if (M.prec == SIM_PREC_FP32D_FP64NC) return make<2, float, PM_F32D>(M, n, species, pos, partner, out);
     return make<2, float, PM_F32NC>(M, n, species, pos, partner, out);
 }
 
@@ -1576,10 +1581,12 @@ int sim_batch_create(const sim_config *cfg, uint32_t n_rep, const sim_replica *r
     if (d == 3) {
         if (M.prec == SIM_PREC_FP64) return make_batch<3, double, PM_F64>(ms, nr, step0, sp.data(), pos.data(), pt.data(), out);
         if (M.prec == SIM_PREC_FP32) return make_batch<3, float, PM_F32>(ms, nr, step0, sp.data(), pos.data(), pt.data(), out);
+        if (M.prec == SIM_PREC_FP32D_FP64NC) return make_batch<3, float, PM_F32D>(ms, nr, step0, sp.data(), pos.data(), pt.data(), out);
         return make_batch<3, float, PM_F32NC>(ms, nr, step0, sp.data(), pos.data(), pt.data(), out);
     }
     if (M.prec == SIM_PREC_FP64) return make_batch<2, double, PM_F64>(ms, nr, step0, sp.data(), pos.data(), pt.data(), out);
     if (M.prec == SIM_PREC_FP32) return make_batch<2, float, PM_F32>(ms, nr, step0, sp.data(), pos.data(), pt.data(), out);
+    if (M.prec == SIM_PREC_FP32D_FP64NC) return make_batch<2, float, PM_F32D>(ms, nr, step0, sp.data(), pos.data(), pt.data(), out);
     return make_batch<2, float, PM_F32NC>(ms, nr, step0, sp.data(), pos.data(), pt.data(), out);
 }
 
@@ -1596,10 +1603,12 @@ int sim_pool_create(const sim_config *cfg, uint64_t slot_cap, uint64_t cell_cap,
     if (M.dim == 3) {
         if (M.prec == SIM_PREC_FP64) return make_pool<3, double, PM_F64>(M, slot_cap, cell_cap, rep_cap, out);
         if (M.prec == SIM_PREC_FP32) return make_pool<3, float, PM_F32>(M, slot_cap, cell_cap, rep_cap, out);
+        if (M.prec == SIM_PREC_FP32D_FP64NC) return make_pool<3, float, PM_F32D>(M, slot_cap, cell_cap, rep_cap, out);
         return make_pool<3, float, PM_F32NC>(M, slot_cap, cell_cap, rep_cap, out);
     }
     if (M.prec == SIM_PREC_FP64) return make_pool<2, double, PM_F64>(M, slot_cap, cell_cap, rep_cap, out);
     if (M.prec == SIM_PREC_FP32) return make_pool<2, float, PM_F32>(M, slot_cap, cell_cap, rep_cap, out);
+    if (M.prec == SIM_PREC_FP32D_FP64NC) return make_pool<2, float, PM_F32D>(M, slot_cap, cell_cap, rep_cap, out);
     return make_pool<2, float, PM_F32NC>(M, slot_cap, cell_cap, rep_cap, out);
 }
 
@@ -1648,10 +1657,12 @@ int sim_eval_pairs_noalloc(const sim_config *cfg, uint64_t n, const double *R, c
     if (M.dim == 3) {
         if (M.prec == SIM_PREC_FP64) launch_probs<3, PM_F64>(P, n, R, R0, penc, preac, st);
         else if (M.prec == SIM_PREC_FP32) launch_probs<3, PM_F32>(P, n, R, R0, penc, preac, st);
+        else if (M.prec == SIM_PREC_FP32D_FP64NC) launch_probs<3, PM_F32D>(P, n, R, R0, penc, preac, st);
         else launch_probs<3, PM_F32NC>(P, n, R, R0, penc, preac, st);
     } else {
         if (M.prec == SIM_PREC_FP64) launch_probs<2, PM_F64>(P, n, R, R0, penc, preac, st);
         else if (M.prec == SIM_PREC_FP32) launch_probs<2, PM_F32>(P, n, R, R0, penc, preac, st);
+        else if (M.prec == SIM_PREC_FP32D_FP64NC) launch_probs<2, PM_F32D>(P, n, R, R0, penc, preac, st);
         else launch_probs<2, PM_F32NC>(P, n, R, R0, penc, preac, st);
     }
     const hipError_t e = hipGetLastError();

@@ -96,16 +96,16 @@ template <class T> __device__ __forceinline__ double cos_turn(double u)
     return sizeof(T) == 8 ? cos((2.0 * PI_D) * u) : cospi(2.0 * u);
 }
 
-// The plain binary32 mode (PM_F32) takes the same draws through a binary32
-// Box-Muller: its displacements differ from the binary64 ones by a few
-// binary32 rounding errors of the displacement.
+// The plain binary32 mode (PM_F32), and PM_F32D, take the same draws through a
+// binary32 Box-Muller: their displacements differ from the binary64 ones by a
+// few binary32 rounding errors of the displacement.
 __device__ __forceinline__ float u01f(u32 w) { return ((float)w + 0.5f) * 0x1p-32f; }
 
 template <int DIM, class T, int PM> __device__ inline void displacement(const Params &P, u32 slot, u32 sp, u32 step, double d[3])
 {
 #pragma clang fp contract(off)
     const uint4 r = philox(slot, NOSLOT, step, TAG_MOVE, P.key);
-    if constexpr (PM == PM_F32) {
+    if constexpr (PM == PM_F32 || PM == PM_F32D) {
         const float s = (float)P.sd[sp];
         const float r0 = sqrtf(-2.0f * logf(u01f(r.x)));
         float s0, c0;
@@ -1778,6 +1778,24 @@ __global__ void k_gather(const Rec<T> *__restrict__ rec, const u32 *__restrict__
             species[s] = (int)sp;
             if (sp == SP_C && partner[s] < cap) species[partner[s]] = 4;
         }
+    }
+}
+
+// The displacement every live record took in this step's move, by slot, as the
+// later stages regenerate it (debug).
+template <int DIM, class T, int PM, bool BATCH>
+__global__ void k_dbg_disp(const Params P, const Rec<T> *__restrict__ rec, const Counters *C, double *__restrict__ disp,
+                           u32 cap)
+{
+    const u32 n = C->n_live, step = C->step;
+    for (u32 i = gtid(); i < n; i += gstride()) {
+        const Rec<T> r = rec[i];
+        const u32 m = rec_meta(r), sp = meta_sp(m), s = meta_slot(m);
+        if (sp > SP_C || s >= cap) continue;
+        const Params &Q = rep_params<BATCH>(P, s);
+        double d[3];
+        displacement<DIM, T, PM>(Q, local_slot<BATCH>(Q, s), sp, local_step<BATCH>(Q, step), d);
+        for (int k = 0; k < DIM; ++k) disp[(u64)s * DIM + k] = d[k];
     }
 }
 

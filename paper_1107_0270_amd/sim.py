@@ -17,12 +17,13 @@ LIB_PATH = os.path.join(HERE, "libgfbd.so")
 SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_ESTATE, SIM_EUNSUPPORTED, SIM_ECAPACITY = 0, -1, -2, -3, -4, -5, -6
 SP_A, SP_B, SP_C, SP_FREE, SP_RESERVED = 0, 1, 2, 3, 4
 BC_ABSORBING, BC_REFLECTING, BC_RADIATION = 0, 1, 2
-PREC_FP64, PREC_FP32, PREC_FP32_FP64NC = 0, 1, 2
+PREC_FP64, PREC_FP32, PREC_FP32_FP64NC, PREC_FP32D_FP64NC = 0, 1, 2, 3
 PAIRS_AUTO, PAIRS_BRICKS, PAIRS_DIRECT = 0, 1, 2
 G2_EXPANSION, G2_EXACT = 0, 1
 F_UNVALIDATED_TAU, F_KEEP_DIRECTION = 1, 2
 (READ_POS, READ_SPECIES, READ_PARTNER, READ_COUNTS, READ_STATS, READ_STATS_SUM, READ_DERIVED, READ_DBG_MOVED,
- READ_DBG_PAIRS, READ_DBG_PICKS, READ_DBG_MATCHES, READ_DBG_DISS, READ_DBG_CELLS, READ_TIMING, READ_GRID) = range(15)
+ READ_DBG_PAIRS, READ_DBG_PICKS, READ_DBG_MATCHES, READ_DBG_DISS, READ_DBG_CELLS, READ_TIMING, READ_GRID,
+ READ_DBG_DISP) = range(16)
 STAT_NAMES = ["pairs", "cand", "overlap", "r0clamp", "picks", "matches", "react", "decay", "geminate",
               "attempts", "bound_hits", "near", "lds_fallback"]
 KERNEL_NAMES = ["move", "scan", "scatter", "pairs", "eval", "select_a", "select_b", "events", "angles"]
@@ -443,6 +444,11 @@ class Sim:
     def dbg_moved(self):
         out = np.zeros((self.n, self.dim))
         self._read(READ_DBG_MOVED, out)
+        return out
+
+    def dbg_disp(self):
+        out = np.zeros((self.n, self.dim))
+        self._read(READ_DBG_DISP, out)
         return out
 
     def dbg_cells(self):

@@ -76,18 +76,27 @@ def _key(a, b):
     return (a.astype(np.uint64) << np.uint64(32)) | b.astype(np.uint64)
 
 
-def compare_step(gpu, orc, rep: Report, *, p_tol, pos_tol, box, rcut, sp_before, lockstep=False):
-    """Advance both sides one step and compare; returns True if the states agree afterwards."""
+def compare_step(gpu, orc, rep: Report, *, p_tol, pos_tol, box, rcut, sp_before, lockstep=False, stage=False):
+    """Advance both sides one step and compare; returns True if the states agree afterwards.
+    stage: stage parity (the oracle takes the GPU's post-move positions and displacements and
+    runs every later stage on them; the move itself is compared with the oracle's own)."""
     gpu.step()
-    orc.step()
-    rep.steps += 1
     live = sp_before <= O.SP_C
+    if stage:
+        gm, gd = gpu.dbg_moved(), gpu.dbg_disp()
+        orc.set_moved(np.where(np.isnan(gm), 0.0, gm), np.where(np.isnan(gd), 0.0, gd))
+        orc.step()
+        om = orc.moved_own()
+    else:
+        orc.step()
+        gm, om = gpu.dbg_moved(), orc.moved()
+    rep.steps += 1
     # 1. move
-    gm, om = gpu.dbg_moved(), orc.moved()
     if live.any():
         d = np.abs(gm[live] - om[live])
         d = np.minimum(d, box - d)
-        rep.max_dpos = max(rep.max_dpos, float(d.max()))
+        if not stage:  # in stage parity the later stages start from the GPU's move
+            rep.max_dpos = max(rep.max_dpos, float(d.max()))
         rep.max_dmove = max(rep.max_dmove, float(d.max()))
     # 2.-3. pairs, p_enc, draws, candidates
     gp, op = gpu.dbg_pairs(), orc.pairs()
@@ -261,7 +270,7 @@ class MemberView:
         raise AssertionError("the member left the oracle's trajectory (a batch member cannot be reloaded alone)")
 
 
-def run(gpu, orc, steps, *, p_tol, pos_tol, box, lockstep=None):
+def run(gpu, orc, steps, *, p_tol, pos_tol, box, lockstep=None, stage=False):
     """lockstep: reload the GPU with the oracle's state after a step whose positions agree
     within pos_tol but not bit for bit.  By default on wherever angles are drawn: the two
     sides' roots of the angular distribution function differ in their last bits, which moves
@@ -273,7 +282,7 @@ def run(gpu, orc, steps, *, p_tol, pos_tol, box, lockstep=None):
     sp, _, _ = orc.state()
     for k in range(steps):
         sp = compare_step(gpu, orc, rep, p_tol=p_tol, pos_tol=pos_tol, box=box, rcut=rcut, sp_before=sp,
-                          lockstep=lockstep)
+                          lockstep=lockstep, stage=stage)
         print(f"  step {k}: pairs {rep.pairs} matches {rep.matches} reactions {rep.reactions} "
               f"max|dp| {rep.max_dp:.2e} resyncs {rep.resyncs}", flush=True)
     return rep

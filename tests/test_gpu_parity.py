@@ -86,6 +86,36 @@ def test_rad3d_reversible_binary32(prec, p_tol, pair_search):
         assert rep.max_dmove == 0.0 and rep.pos_resyncs == 0
 
 
+@pytest.mark.parametrize("dim", [3, 2])
+def test_binary32_displacements_stage_parity(dim):
+    # FP32D_FP64NC: binary32 Box-Muller displacements, binary64 near-contact pair arithmetic.
+    # Its moves differ from the oracle's binary64 ones by binary32 roundings of the
+    # displacement, held to 1e-5 of the box.  Stage parity: after each GPU step the oracle takes
+    # the GPU's post-move positions and displacements and runs every later stage itself, held
+    # to the near-contact mode's bar: pair sets identical, p_enc within 1e-6 (3D; 1e-9 with the
+    # binary64 2D expansion), decisions identical but for draws within 1e-6 of p, R'' and p_reac
+    # to 1e-9, angles to 1e-8, states after the step bit for bit.
+    prec = S.PREC_FP32D_FP64NC
+    if dim == 3:
+        n, box, steps = 7812, 2.5, 30
+        sp, pos = _state(n, n, box, 3, 0.005, 1, True)
+        gpu, orc = make_pair(dim=3, bc=O.BC_RAD, box=box, dt=1e-5, D=(1.0, 1.0, 0.5), sigma=0.005, kappa=0.1,
+                             k_off=2000.0, precision=prec, species=sp, pos=pos, seed=3)
+        p_tol = 1e-6
+    else:
+        n, box, steps = 3000, 1.5, 8
+        sp, pos = _state(n, n, box, 2, 0.005, 7, True)
+        gpu, orc = make_pair(dim=2, bc=O.BC_RAD, box=box, dt=5e-6, D=(0.1, 0.1, 0.05), sigma=0.005, kappa=0.05,
+                             k_off=2000.0, precision=prec, species=sp, pos=pos, seed=8)
+        p_tol = 1e-9
+    rep = run(gpu, orc, steps, p_tol=p_tol, pos_tol=0.0, box=box, lockstep=True, stage=True)
+    _check(rep, p_tol=p_tol)
+    print(f"binary32 displacements: max |dx| against the binary64 move {rep.max_dmove:.3e} um, "
+          f"{rep.pos_resyncs} lock-step reloads in {steps} steps")
+    assert 0.0 < rep.max_dmove <= 1e-5 * box
+    assert rep.matches > 0 and rep.angles > 0
+
+
 @pytest.mark.parametrize("pair_search", KERNELS)
 @pytest.mark.parametrize("cell", [0.0, 0.075])
 def test_rad3d_dense(cell, pair_search):

@@ -345,3 +345,45 @@ def test_immobile_a_never_moves():
         a_side = np.arange(M)  # slots of the A's (reacted ones hold C)
         assert np.array_equal(x[a_side], x0[a_side])
     assert n_match > 200
+
+
+@pytest.mark.parametrize("dim", [3, 2])
+def test_stage_override_with_its_own_move_is_the_plain_step(dim):
+    # Stage parity hands a step its post-move positions and displacements from outside.  Given
+    # exactly what its own move produces (from a twin oracle, binary64 state: the displacement is
+    # the min-image difference of the positions to within an ulp of the box), the step must
+    # take the same pairs, draws, decisions, angles and final state as the plain step, and
+    # report its own move unchanged.
+    box = 0.12 if dim == 3 else 0.2
+    kw = dict(kappa_a=0.05 if dim == 3 else 0.02, k_off=3000.0)
+    a = _sim(dim, O.BC_RAD, 700, 700, box, 0.006, dt=4e-6, seed=7, **kw)
+    b = _sim(dim, O.BC_RAD, 700, 700, box, 0.006, dt=4e-6, seed=7, **kw)
+    n_angles = 0
+    for _ in range(6):
+        sp0, x0, _ = a.state()
+        a.step()
+        xm = a.moved()
+        live = sp0 <= O.SP_C
+        disp = xm - x0
+        disp = disp - box * np.round(disp / box)
+        b.set_moved(np.where(live[:, None], xm, 0.0), np.where(live[:, None], disp, 0.0))
+        b.step()
+        dm = np.abs(b.moved_own()[live] - xm[live])
+        assert np.minimum(dm, box - dm).max() <= 1e-13  # the states differ in last bits from step 2 on
+        pa, pb = a.pairs(), b.pairs()
+        assert np.array_equal(pa["i"], pb["i"]) and np.array_equal(pa["j"], pb["j"])
+        assert np.allclose(pa["p"], pb["p"], atol=1e-12, rtol=0)
+        assert np.array_equal(pa["cand"], pb["cand"])
+        ma, mb = a.matches(), b.matches()
+        assert np.array_equal(ma["i"], mb["i"]) and np.array_equal(ma["reacted"], mb["reacted"])
+        ok = np.isfinite(ma["cos_theta"])
+        assert np.array_equal(ok, np.isfinite(mb["cos_theta"]))
+        assert np.allclose(ma["cos_theta"][ok], mb["cos_theta"][ok], atol=1e-9, rtol=0)
+        n_angles += int(ok.sum())
+        spa, xa, pta = a.state()
+        spb, xb, ptb = b.state()
+        assert np.array_equal(spa, spb)
+        lv = spa <= O.SP_C
+        d = np.abs(xa[lv] - xb[lv])
+        assert np.minimum(d, box - d).max() <= 1e-12
+    assert n_angles > 0
