@@ -3,8 +3,8 @@
 
 Workload (synthetic, seeded): 3D reversible A + B <-> C with a radiation surface,
 5e5 A + 5e5 B uniform in a periodic 10 um cube, D_A = D_B = 1 um^2/s, sigma = 5 nm,
-kappa_a = 0.1 um^3/s, k_off = 10/s, dt = 10 us, binary32 state with binary64
-near-contact arguments.  One step = move, bin, pairs + p_enc, selection,
+kappa_a = 0.1 um^3/s, k_off = 10/s, dt = 10 us, binary32 state and displacements with
+binary64 near-contact arguments.  One step = move, bin, pairs + p_enc, selection,
 propagation/reaction, dissociation (the whole step of Sec. 3).
 
 Prints one JSON line.  Kernel durations come from HIP events recorded on the
@@ -46,28 +46,28 @@ def algorithmic_bytes(kernel, n_live, n_a, n_b, n_keys):
 # commands are in profiles/rad3d_step_traffic.md.  Valid only for the kernel sources they were taken
 # on (hash below): after any change to them the field is reported as null.
 MEASURED_TRAFFIC = {
-    "src_hash": "48f37c1df50fbf1c",
+    "src_hash": "1a451aebe608b1ec",
     "scale_fetch": 1.9998, "scale_write": 1.0,
     "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
-        "move": (9863.2, 31398.0),
-        "scan": (11632.9, 17387.4),
-        "scatter": (17033.0, 29440.7),
-        "pairs": (9762.9, 299.2),
-        "eval": (3275.8, 199.9),
-        "select_a": (251.6, 60.7),
-        "select_b": (263.6, 12.4),
-        "events": (343.8, 73.8),
+        "move": (9963.2, 31398.2),
+        "scan": (11630.1, 17387.5),
+        "scatter": (17018.4, 29443.5),
+        "pairs": (9755.7, 299.2),
+        "eval": (3255.5, 199.6),
+        "select_a": (251.5, 60.6),
+        "select_b": (269.4, 12.3),
+        "events": (348.5, 73.9),
     },
     # stage -> VALU wave-instructions per launch (SQ_INSTS_VALU summed over the stage's kernels)
     "valu": {
-        "move": 8175115,
+        "move": 6003796,
         "scan": 416342,
         "scatter": 723654,
-        "pairs": 5250462,
-        "eval": 635944,
-        "select_a": 69729,
-        "select_b": 214471,
-        "events": 1146462,
+        "pairs": 5250267,
+        "eval": 437669,
+        "select_a": 69866,
+        "select_b": 214612,
+        "events": 1143639,
     },
 }
 
@@ -148,10 +148,10 @@ def angle_roofline(n, launch_ms, dim=3):
 # FMA counting two; SQ_INSTS_VALU), and its HBM bytes (FETCH_SIZE, WRITE_SIZE scaled as above),
 # profiles/rad3d_step_valu.md and profiles/rad3d_step_traffic.md.  Valid for the sources they were taken on (hash below).
 ANGLE_STEP_COUNTERS = {
-    "src_hash": "17d6d994515ec2e9",
-    "f64_flop": 2.445523e+08,  # 64 x (ADD 252363 + MUL 949018 + TRANS 85469 + 2 x FMA 1267140)
-    "valu": 4230347,
-    "traffic": 935529,
+    "src_hash": "9f0a6483636d34cc",
+    "f64_flop": 2.327191e+08,  # 64 x (ADD 235383 + MUL 924491 + TRANS 81695 + 2 x FMA 1197334)
+    "valu": 4114628,
+    "traffic": 879235,
 }
 ANGLE_STEP_SOURCES = ["common.hpp", "green.hpp", "green2x.hpp", "kernels.hpp", "angle3.hpp", "angle2.hpp",
                       "angle_wg.hpp", "gfbd.hip"]
@@ -231,7 +231,7 @@ def pair_probs_record(n, repeats, d, I, S):
     return {
         "metric": "pair-probability evals/s (kernel only)", "value": round(out["penc"], 1), "unit": "pair evals/s",
         "penc_and_preac_per_s": round(out["penc_preac"], 1), "n_gpus": 1, "pairs": n, "repeats": repeats,
-        "dtype": {0: "f64", 1: "f32", 2: "f32+f64-args"}[cfg["precision"]], "data": "synthetic",
+        "dtype": {0: "f64", 1: "f32", 2: "f32+f64-args", 3: "f32+f64-args"}[cfg["precision"]], "data": "synthetic",
         "config": {"workload": f"{d}D pair distribution of the benchmark workload at the 1e-6 cut-off: R uniform in "
                                f"the ball of radius r_cut/a = {rmax:.3f}, R0 = |R + sqrt(2 tau) z|, tau = {tau:.4g}",
                    "kernel": "k_eval_probs (the step's p_enc / p_reac device functions)"}}
@@ -382,15 +382,15 @@ def angle(args, I, S):
         "config": {"workload": f"{dim}D propagated pairs of the {'benchmark' if dim == 3 else 'membrane'} workload: "
                                f"R0 uniform in the {'shell' if dim == 3 else 'ring'} 1 < R0 < r_cut/a = {rmax:.3f}, "
                                f"R'' from the radial propagator, tau = {tau:.4g}",
-                   "kernel": "k_angle3 (Legendre series of G_ref - G_abs, one wave per pair)" if dim == 3 else
-                             "k_angle2 (cos(n theta) series of G_ref - G_abs, one wave per pair)"}}), flush=True)
+                   "kernel": "k_angle_wg<3> (Legendre series of G_ref - G_abs, one workgroup per pair)" if dim == 3 else
+                             "k_angle_wg<2> (cos(n theta) series of G_ref - G_abs, one workgroup per pair)"}}), flush=True)
 
 
 def batched(args, I, S):
     """R independent 3D replicas stepped together (sim_batch_create, one graph replay per step)
     against the plain path: a sample of the same replicas stepped one handle at a time."""
     shared = dict(dt=1e-5, D=(1.0, 1.0, 0.5), sigma=0.005, bc=S.BC_RADIATION, k_off=10.0, seed=0, eps_cut=args.eps_cut,
-                  precision=S.PREC_FP32_FP64NC)
+                  precision=S.PREC_FP32D_FP64NC)
     t0 = time.time()
     reps = I.ensemble(args.batch)
     n_tot = sum(len(r["species"]) for r in reps)
@@ -464,7 +464,7 @@ ENSEMBLE_SHARED = dict(dt=1e-5, D=(1.0, 1.0, 0.5), sigma=0.005, k_off=10.0, seed
 def ensemble_record(reps, S, steps=50, warmup=5, sample=16):
     """The batched ensemble (one graph replay per step for all replicas) and the plain path on a
     sample of the same replicas, one handle each, for the default benchmark line."""
-    shared = dict(ENSEMBLE_SHARED, bc=S.BC_RADIATION, precision=S.PREC_FP32_FP64NC)
+    shared = dict(ENSEMBLE_SHARED, bc=S.BC_RADIATION, precision=S.PREC_FP32D_FP64NC)
     n_tot = sum(len(r["species"]) for r in reps)
     t0 = time.time()
     b = S.Sim.batch(reps, **shared)
@@ -498,8 +498,8 @@ def ensemble_record(reps, S, steps=50, warmup=5, sample=16):
             "speedup_vs_plain_path": round(rate * t1 / ps1, 2),
             "workload": f"{len(reps)} independent 3D replicas, A+B<->C radiation surface, N log-uniform in [1e3, 1e5] "
                         f"(total {n_tot}), kappa uniform in [0.01, 1] um^3/s, L = (N/1000)^(1/3) um, D=1 um^2/s, "
-                        "sigma=5 nm, k_off=10/s, dt=10 us, binary32 state with binary64 near-contact arguments, "
-                        "pair cut-off 1e-6"}
+                        "sigma=5 nm, k_off=10/s, dt=10 us, binary32 state and displacements with binary64 "
+                        "near-contact arguments, pair cut-off 1e-6"}
 
 
 SERVE_HBM_BUDGET = 32 << 30  # the served stream's ledger: device bytes of running requests, both pools
@@ -688,10 +688,12 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests in the served trace (--serve)")
     ap.add_argument("--pool-slots", type=int, default=1 << 26, help="slots of each pool (--serve)")
     ap.add_argument("--tick", type=int, default=200, help="most steps per pool call (--serve)")
-    ap.add_argument("--precision", choices=["workload", "fp64", "fp32", "fp32nc"], default="workload",
+    ap.add_argument("--precision", choices=["workload", "fp64", "fp32", "fp32nc", "fp32d"], default="workload",
                     help="precision mode (default: the workload's; fp32 = plain binary32, fp32nc = binary32 with "
-                         "binary64 near-contact arguments and displacements)")
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain binary32 comparison run")
+                         "binary64 near-contact arguments and displacements, fp32d = fp32nc with binary32 "
+                         "displacements)")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain binary32 and binary32-displacement comparison runs")
     ap.add_argument("--green2d", choices=["auto", "expansion", "exact"], default="auto",
                     help="2D radial functions: small-time expansions, or exact (tables by quadrature); auto takes "
                          "the expansion where it holds the probabilities to 1e-6 (tau <= 0.05 at order 12) and "
@@ -738,7 +740,8 @@ def main():
 
     cfg = I.workload(args.workload)
     if args.precision != "workload":
-        cfg["precision"] = {"fp64": I.PREC_FP64, "fp32": I.PREC_FP32, "fp32nc": I.PREC_FP32_FP64NC}[args.precision]
+        cfg["precision"] = {"fp64": I.PREC_FP64, "fp32": I.PREC_FP32, "fp32nc": I.PREC_FP32_FP64NC,
+                            "fp32d": I.PREC_FP32D_FP64NC}[args.precision]
     dim = cfg["dim"]
     t0 = time.time()
     sp, pos, box, red = I.state_for(cfg, seed=0, scale=args.scale)
@@ -826,8 +829,8 @@ def main():
     ps = n_live * args.steps / el
     log(f"[bench] graph: {args.steps} steps in {el * 1e3:.1f} ms; {ps:.3e} particle-steps/s; {pairs / el:.3e} pair evals/s")
     # the same workload in the plain binary32 mode (binary32 displacements and p_enc)
-    plain = None
-    if cfg["precision"] == S.PREC_FP32_FP64NC and not args.no_plain:
+    plain = fp32d = None
+    if cfg["precision"] in (S.PREC_FP32_FP64NC, S.PREC_FP32D_FP64NC) and not args.no_plain:
         sim = make(False, S.PREC_FP32)
         el32, n32, pairs32, _, _, _ = timed(sim)
         sim.close()
@@ -835,6 +838,20 @@ def main():
                  "ms_per_step": round(el32 * 1e3 / args.steps, 5), "pair_evals_per_s": round(pairs32 / el32, 1),
                  "precision": "binary32 state, displacements, pair test and p_enc; binary64 propagation"}
         log(f"[bench] plain binary32: {plain}")
+        # the other near-contact mode: binary64 displacements (bit-identical trajectories to the
+        # oracle's) when the headline takes binary32 ones, and the reverse
+        other = S.PREC_FP32_FP64NC if cfg["precision"] == S.PREC_FP32D_FP64NC else S.PREC_FP32D_FP64NC
+        sim = make(False, other)
+        elo, no, pairso, _, _, _ = timed(sim)
+        sim.close()
+        fp32d = {"value": round(no * args.steps / elo, 1), "unit": "particle-steps/s",
+                 "ms_per_step": round(elo * 1e3 / args.steps, 5), "pair_evals_per_s": round(pairso / elo, 1),
+                 "precision": ("binary32 state, binary64 displacements (trajectories bit for bit the oracle's), "
+                               "p_enc with binary64 near-contact arguments, binary64 propagation"
+                               if other == S.PREC_FP32_FP64NC else
+                               "binary32 state and displacements (binary32 Box-Muller); p_enc with binary64 "
+                               "near-contact arguments; binary64 propagation; held to the oracle by stage parity")}
+        log(f"[bench] other near-contact mode: {fp32d}")
     # pass 2: the same steps with HIP events around every kernel -> kernel durations
     kt, el_ev = {}, None
     if not args.no_timing:
@@ -894,7 +911,9 @@ def main():
                    "precision": {S.PREC_FP64: "binary64 throughout",
                                  S.PREC_FP32: "binary32 state, pair test and p_enc; binary64 propagation",
                                  S.PREC_FP32_FP64NC: "binary32 state and p_enc, binary64 near-contact arguments and "
-                                                     "propagation"}[cfg["precision"]],
+                                                     "propagation",
+                                 S.PREC_FP32D_FP64NC: "binary32 state, displacements and p_enc, binary64 near-contact "
+                                                      "arguments and propagation"}[cfg["precision"]],
                    "particles": len(sp), "r_cut_um": der["rcut"], "cells": grid[:3],
                    "pair_search": {S.PAIRS_BRICKS: "lds-bricks", S.PAIRS_DIRECT: "direct"}[grid[4]],
                    "step_launch": "one hipGraph replay per step",
@@ -903,6 +922,7 @@ def main():
                    "handle_creation_s": round(t_create, 3)},
         "autotune": tuned,
         "plain_fp32": plain,
+        "other_near_contact_mode": fp32d,
         "roofline": roof,
         "move_roofline": move_roof,
         "kernel_ms_per_step": {k: round(v[0] / max(args.steps, 1), 5) for k, v in kt.items()},

@@ -10,7 +10,8 @@ Workloads (all periodic, uniform, A:B = 1:1, no C at t = 0):
 * ``cfg_abs3d``      3D irreversible A+B->C, absorbing; 1,000 A + 1,000 B, L = 1 um,
                      D = 1 um^2/s, sigma = 5 nm, dt = 1 us, FP64.
 * ``cfg_rad3d``      3D reversible A+B<->C, radiation; 5e5 A + 5e5 B, L = 10 um,
-                     D = 1 um^2/s, sigma = 5 nm, kappa = 0.1 um^3/s, k_off = 10/s, dt = 10 us.
+                     D = 1 um^2/s, sigma = 5 nm, kappa = 0.1 um^3/s, k_off = 10/s, dt = 10 us,
+                     binary32 displacements and state, binary64 near-contact pair arithmetic.
                      ``cfg_rad3d_dense`` is the heaviest pair load of the same grid
                      (D = 10 um^2/s, sigma = 10 nm).
 * ``cfg_mem2d``      2D membrane A+B<->C; 5e5 A + 5e5 B on L = 20 um, D = 0.1 um^2/s,
@@ -23,7 +24,7 @@ import numpy as np
 
 SP_A, SP_B, SP_C, SP_FREE, SP_RESERVED = 0, 1, 2, 3, 4
 BC_ABS, BC_REF, BC_RAD = 0, 1, 2
-PREC_FP64, PREC_FP32, PREC_FP32_FP64NC = 0, 1, 2
+PREC_FP64, PREC_FP32, PREC_FP32_FP64NC, PREC_FP32D_FP64NC = 0, 1, 2, 3
 
 
 def workload(name: str, **over) -> dict:
@@ -32,10 +33,10 @@ def workload(name: str, **over) -> dict:
         "cfg_abs3d": dict(dim=3, bc=BC_ABS, n_a=1000, n_b=1000, box=1.0, D=(1.0, 1.0), sigma=0.005,
                           kappa_a=0.0, k_off=0.0, dt=1e-6, steps=100, precision=PREC_FP64),
         "cfg_rad3d": dict(dim=3, bc=BC_RAD, n_a=500_000, n_b=500_000, box=10.0, D=(1.0, 1.0), sigma=0.005,
-                          kappa_a=0.1, k_off=10.0, dt=1e-5, steps=1000, precision=PREC_FP32_FP64NC),
+                          kappa_a=0.1, k_off=10.0, dt=1e-5, steps=1000, precision=PREC_FP32D_FP64NC),
         "cfg_rad3d_dense": dict(dim=3, bc=BC_RAD, n_a=500_000, n_b=500_000, box=10.0, D=(10.0, 10.0),
                                 sigma=0.010, kappa_a=0.1, k_off=10.0, dt=1e-5, steps=1000,
-                                precision=PREC_FP32_FP64NC),
+                                precision=PREC_FP32D_FP64NC),
         "cfg_mem2d": dict(dim=2, bc=BC_RAD, n_a=500_000, n_b=500_000, box=20.0, D=(0.1, 0.1), sigma=0.005,
                           kappa_a=0.05, k_off=10.0, dt=1e-4, steps=1000, precision=PREC_FP32_FP64NC),
         "cfg_mem2d_small_tau": dict(dim=2, bc=BC_RAD, n_a=500_000, n_b=500_000, box=20.0, D=(0.1, 0.1),

@@ -56,7 +56,7 @@ class Request:
 # the box at the workload's density, the steps and the key.
 GROUP_PARAMS = {
     3: dict(dim=3, dt=1e-5, D=(1.0, 1.0, 0.5), sigma=0.005, bc=S.BC_RADIATION, kappa=0.1, k_off=10.0, seed=0,
-            precision=S.PREC_FP32_FP64NC, eps_cut=1e-6),
+            precision=S.PREC_FP32D_FP64NC, eps_cut=1e-6),
     2: dict(dim=2, dt=5e-6, D=(0.1, 0.1, 0.05), sigma=0.005, bc=S.BC_RADIATION, kappa=0.05, k_off=10.0, seed=0,
             precision=S.PREC_FP32_FP64NC, eps_cut=1e-6),
 }

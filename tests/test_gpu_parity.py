@@ -181,7 +181,8 @@ def test_rad3d_full_size_one_step(pair_search):
     gpu, orc = make_pair(dim=3, bc=cfg["bc"], box=cfg["box"], dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"],
                          kappa=cfg["kappa_a"], k_off=cfg["k_off"], precision=cfg["precision"], species=sp, pos=pos,
                          pair_search=pair_search)
-    rep = run(gpu, orc, 2, p_tol=1e-6, pos_tol=0.0, box=cfg["box"])
+    # binary32 displacements: stage parity (the oracle continues from the GPU's own move)
+    rep = run(gpu, orc, 2, p_tol=1e-6, pos_tol=0.0, box=cfg["box"], stage=cfg["precision"] == S.PREC_FP32D_FP64NC)
     _check(rep, p_tol=1e-6)
     assert rep.pairs > 10000
 
@@ -194,7 +195,7 @@ def test_full_size_many_events(name, p_tol):
     sp, pos = _state(cfg["n_a"], cfg["n_b"], cfg["box"], cfg["dim"], cfg["sigma"], 0, True)
     gpu, orc = make_pair(dim=cfg["dim"], bc=cfg["bc"], box=cfg["box"], dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"],
                          kappa=cfg["kappa_a"], k_off=cfg["k_off"], precision=cfg["precision"], species=sp, pos=pos)
-    rep = run(gpu, orc, 1, p_tol=p_tol, pos_tol=0.0, box=cfg["box"])
+    rep = run(gpu, orc, 1, p_tol=p_tol, pos_tol=0.0, box=cfg["box"], stage=cfg["precision"] == S.PREC_FP32D_FP64NC)
     _check(rep, p_tol=p_tol, allow_near=4)
     st = gpu.stats()
     print("events", st["matches"] + st["decay"])
