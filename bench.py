@@ -49,25 +49,25 @@ MEASURED_TRAFFIC = {
     "src_hash": "1a451aebe608b1ec",
     "scale_fetch": 1.9998, "scale_write": 1.0,
     "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
-        "move": (9963.2, 31398.2),
-        "scan": (11630.1, 17387.5),
-        "scatter": (17018.4, 29443.5),
-        "pairs": (9755.7, 299.2),
-        "eval": (3255.5, 199.6),
-        "select_a": (251.5, 60.6),
-        "select_b": (269.4, 12.3),
-        "events": (348.5, 73.9),
+        "move": (9933.8, 31398.0),
+        "scan": (11626.9, 17387.4),
+        "scatter": (17011.9, 29443.4),
+        "pairs": (9763.0, 299.2),
+        "eval": (3255.4, 199.5),
+        "select_a": (246.1, 60.6),
+        "select_b": (265.1, 11.8),
+        "events": (345.8, 73.9),
     },
     # stage -> VALU wave-instructions per launch (SQ_INSTS_VALU summed over the stage's kernels)
     "valu": {
-        "move": 6003796,
+        "move": 6003797,
         "scan": 416342,
-        "scatter": 723654,
-        "pairs": 5250267,
-        "eval": 437669,
-        "select_a": 69866,
-        "select_b": 214612,
-        "events": 1143639,
+        "scatter": 723655,
+        "pairs": 5250334,
+        "eval": 437662,
+        "select_a": 69853,
+        "select_b": 214598,
+        "events": 1143659,
     },
 }
 
@@ -109,15 +109,15 @@ def valu_issue(stage, launch_ms):
 # (SQ_INSTS_VALU_{ADD,MUL,TRANS,FMA}_F64 x 64 lanes, an FMA counting two; SQ_INSTS_VALU),
 # profiles/angle3_kernels.md and profiles/angle2_kernels.md.  Valid for the source they were taken on.
 ANGLE_COUNTERS = {3: {
-    "src_hash": "15e9c7e6faa9b4f2",
+    "src_hash": "9e4f84efec2850aa",
     "pairs": 1000000,
-    "f64_flop": 4.996610e+11,  # 64 x (ADD 477553144 + MUL 2033187870 + TRANS 167947286 + 2 x FMA 2564257147)
-    "valu": 8195779186,
+    "f64_flop": 4.721196e+11,  # 64 x (ADD 468250600 + MUL 1794655758 + TRANS 166947286 + 2 x FMA 2473507475)
+    "valu": 7764300338,
 }, 2: {  # k_angle_wg<2> on --angle 200000 --dim 2 (membrane pairs, tau = 0.04)
-    "src_hash": "c96d0910d1aefd6f",
+    "src_hash": "b3add8d003b132dc",
     "pairs": 200000,
-    "f64_flop": 7.410691e+11,  # 64 x (ADD 659523594 + MUL 2804765535 + TRANS 222414722 + 2 x FMA 3946250088)
-    "valu": 10996797065,
+    "f64_flop": 7.336980e+11,  # 64 x (ADD 635191238 + MUL 2794391123 + TRANS 221512762 + 2 x FMA 3906467704)
+    "valu": 10737683353,
 }}
 FP64_VECTOR_PEAK = 78.6e12  # MI355X dense fp64 vector FLOP/s
 
@@ -148,10 +148,10 @@ def angle_roofline(n, launch_ms, dim=3):
 # FMA counting two; SQ_INSTS_VALU), and its HBM bytes (FETCH_SIZE, WRITE_SIZE scaled as above),
 # profiles/rad3d_step_valu.md and profiles/rad3d_step_traffic.md.  Valid for the sources they were taken on (hash below).
 ANGLE_STEP_COUNTERS = {
-    "src_hash": "9f0a6483636d34cc",
-    "f64_flop": 2.327191e+08,  # 64 x (ADD 235383 + MUL 924491 + TRANS 81695 + 2 x FMA 1197334)
-    "valu": 4114628,
-    "traffic": 879235,
+    "src_hash": "750a35211015a574",
+    "f64_flop": 2.203498e+08,  # 64 x (ADD 230588 + MUL 816412 + TRANS 81224 + 2 x FMA 1157371)
+    "valu": 3965161,
+    "traffic": 881284,
 }
 ANGLE_STEP_SOURCES = ["common.hpp", "green.hpp", "green2x.hpp", "kernels.hpp", "angle3.hpp", "angle2.hpp",
                       "angle_wg.hpp", "gfbd.hip"]

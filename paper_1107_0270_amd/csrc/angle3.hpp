@@ -45,13 +45,4 @@ __device__ __forceinline__ int ang_terms(double R, double R0, double tau)
     return n < ANG_NCAP ? n : ANG_NCAP;
 }
 
-struct InvTable {
-    double v[ANG_NCAP + 2];
-    constexpr InvTable() : v()
-    {
-        for (int n = 0; n < ANG_NCAP + 2; ++n) v[n] = 1.0 / (n + 1.0);
-    }
-};
-__constant__ constexpr InvTable ANG_INV{};  // 1 / (n + 1)
-
 } // namespace gfbd

@@ -36,9 +36,12 @@
 //     of the ratio 2 of angle2.hpp; below 4^-12 the integrand (x times a power of
 //     1 / log x) adds less than 1e-17 of w_0;
 //   - the root of F(.) = u is bracketed by four rounds of a 129-way search (one point
-//     per thread), a cell of 2 / 129^4 < 1e-8 (3D) or pi / 129^4 (2D), and then taken
-//     by linear interpolation of F across the cell: F is smooth there, so the error is
-//     about cell^2 |F''/F'| / 8, below 1e-14 for the narrowest distributions allowed.
+//     per thread), a cell h of 2 / 129^4 < 1e-8 (3D) or pi / 129^4 (2D), and then taken
+//     from the quadratic through the cell's two ends and the next point of the last
+//     round (one Newton step on it from the secant's root): F is smooth there, so the
+//     error is about h^3 |F^(3) / F'| / 16, far below the rounding of c even for the
+//     narrowest distributions allowed, where linear interpolation (error about
+//     h^2 |F''/F'| / 8) left some 1e-15.
 #pragma once
 
 #include "angle2.hpp"
@@ -60,9 +63,12 @@ constexpr double ANG_TAU_MIN = 2e-3;
 struct AngShared {
     union {
         double ck[ANCK][3][2][AWG];  // checkpoints of the J sequences, a column per thread
-        double W[ANG_NCAP + 1];      // the coefficients w_n (after the nodes)
+        struct {                     // after the nodes:
+            double W[ANG_NCAP + 1];  // the coefficients w_n
+            alignas(16) double S[ANG_NCAP + 2][4];  // 3D: the search's series, a row per order
+        } co;
     };
-    double w[AW_NW][ANG_NCAP + 1];  // per-wave partial coefficient sums
+    double w[AW_NW][ANG_NCAP + 1];  // per-wave partial coefficient sums; 2D: then the search's series
     double Fv[AWG];                 // F at the search points of a round
     int hit[AW_NW];
 };
@@ -90,28 +96,67 @@ __device__ __forceinline__ double ang_rcp(double d)
 // half-integer orders nu = k - 1/2 (3D): 2 nu = 2k - 1; integer orders (2D): 2k.
 template <int DIM> __device__ __forceinline__ double ang_coef(int k) { return DIM == 3 ? 2.0 * k - 1.0 : 2.0 * k; }
 
-// The distribution functions on normalised coefficients V (angle3.hpp, angle2.hpp):
-// 3D F(c) = (1 + c)/2 + sum_{n=1..N} V_n (P_{n+1}(c) - P_{n-1}(c)), V_n = w_n / (2 w_0);
-// 2D F(t) = t / pi + sum_{n=1..N} V_n sin(n t), V_n = 2 w_n / (n pi w_0).
-__device__ __forceinline__ double ang_cdf_n(const double *V, int N, double c)
+// The distribution functions (angle3.hpp, angle2.hpp), with V_n = w_n / w_0:
+// 3D F(c) = (1 + c)/2 + sum_{n=1..N} (V_n / 2) (P_{n+1}(c) - P_{n-1}(c)), rewritten as
+// sum_{m=0..N+1} a_m P_m(c) with a_m = (V_{m-1} - V_{m+1}) / 2 (V_0 and V_{>N} taken as 0)
+// plus 1/2 in a_0 and a_1, and summed downward (Clenshaw) with Bonnet's recurrence
+// P_{m+1} = (2m+1)/(m+1) c P_m - m/(m+1) P_{m-1}: one dependent FMA per order.  Row m of S
+// holds a_m, (2m+1)/(m+1) and -(m+1)/(m+2);
+// 2D F(t) = t / pi + sum_{n=1..N} a_n sin(n t), a_n = 2 V_n / (n pi), summed upward with
+// the sines from their three-term recurrence.  The coefficients sit in LDS, the same
+// address in every lane; eight rows are loaded before they are used, so that the loads
+// overlap.
+__device__ __forceinline__ double ang_cdf_n(const double (*S)[4], int M, double c)
 {
-    double s = 0.5 * (1.0 + c), pm = 1.0, p = c;
-    for (int n = 1; n <= N; ++n) {
-        const double pn1 = ((2.0 * n + 1.0) * c * p - n * pm) * ANG_INV.v[n];  // Bonnet's recurrence
-        s += V[n] * (pn1 - pm);
-        pm = p;
-        p = pn1;
+    double b1 = 0.0, b2 = 0.0;
+    int k = M;
+    for (; k >= 8; k -= 8) {  // eight orders: their rows' loads first, then the recurrence
+        double a[8], p[8], q[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            a[j] = S[k - j][0];
+            p[j] = S[k - j][1];
+            q[j] = S[k - j][2];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const double b = fma(p[j] * c, b1, fma(q[j], b2, a[j]));
+            b2 = b1;
+            b1 = b;
+        }
     }
-    return s;
+    for (; k >= 1; --k) {
+        const double b = fma(S[k][1] * c, b1, fma(S[k][2], b2, S[k][0]));
+        b2 = b1;
+        b1 = b;
+    }
+    return fma(c, b1, fma(-0.5, b2, S[0][0]));
 }
 
-__device__ __forceinline__ double ang2_cdf_n(const double *V, int N, double t)
+__device__ __forceinline__ double ang2_cdf_n(const double *a, int N, double t)
 {
-    const double c2 = 2.0 * cos(t);
-    double sm = 0.0, s = sin(t), acc = t * (1.0 / PI_D);  // sin((n-1) t), sin(n t) at n = 1
-    for (int n = 1; n <= N; ++n) {
-        acc += V[n] * s;
-        const double sn = c2 * s - sm;
+    double s, cs;
+    sincos(t, &s, &cs);
+    const double c2 = 2.0 * cs;
+    double sm = 0.0, acc = t * (1.0 / PI_D);  // sin((n-1) t), sin(n t) at n = 1
+    int n = 1;
+    for (; n + 7 <= N; n += 8) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = a[n + j];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            acc = fma(v[j], s, acc);
+            const double sn = fma(c2, s, -sm);
+            sm = s;
+            s = sn;
+        }
+    }
+    for (; n <= N; ++n) {
+        acc = fma(a[n], s, acc);
+        const double sn = fma(c2, s, -sm);
         sm = s;
         s = sn;
     }
@@ -445,33 +490,42 @@ __device__ __forceinline__ double ang_draw_wg(double tau, double Rin, double R0i
     for (int t = tid; t <= N; t += AWG) {
         double s = 0.0;
         for (int w = 0; w < AW_NW; ++w) s += sh.w[w][t];  // in wave order
-        sh.W[t] = s;
+        sh.co.W[t] = s;
     }
     __syncthreads();
-    // the distribution function's coefficients relative to w_0, and the last order whose
-    // coefficient is above 1e-17 of w_0 (the rest change F by less than 1e-16)
-    const double inv0 = 1.0 / sh.W[0];
+    // the last order whose coefficient is above 1e-17 of w_0 (the rest change F by less
+    // than 1e-16), then the series the search evaluates (ang_cdf_n, ang2_cdf_n)
+    const double inv0 = 1.0 / sh.co.W[0];
     int last = 0;
-    for (int t = tid; t <= N; t += AWG) {
-        const double v = sh.W[t] * inv0;
-        if (t > 0 && fabs(v) > 1e-17) last = t;
-        // 3D: F = [1 + c + sum v_n (P_{n+1} - P_{n-1})] / 2; 2D: F = t / pi + sum (2 v_n / (n pi)) sin(n t)
-        sh.w[0][t] = DIM == 3 ? 0.5 * v : (t > 0 ? 2.0 * v / (t * PI_D) : 0.0);
-    }
+    for (int t = tid; t <= N; t += AWG)
+        if (t > 0 && fabs(sh.co.W[t] * inv0) > 1e-17) last = t;
     for (int o = 32; o >= 1; o >>= 1) last = max(last, __shfl_xor(last, o, 64));
     if ((tid & 63) == 0) sh.hit[wv] = last;
     __syncthreads();
     int Ne = 0;
     for (int w = 0; w < AW_NW; ++w) Ne = max(Ne, sh.hit[w]);
-    const double *V = sh.w[0];
+    const int M = DIM == 3 ? Ne + 1 : Ne;
+    for (int m = tid; m <= M; m += AWG) {
+        if constexpr (DIM == 3) {
+            const double lo = m >= 2 ? sh.co.W[m - 1] : 0.0, hi = m + 1 <= Ne ? sh.co.W[m + 1] : 0.0;
+            sh.co.S[m][0] = 0.5 * (lo - hi) * inv0 + (m <= 1 ? 0.5 : 0.0);
+            sh.co.S[m][1] = (2.0 * m + 1.0) / (m + 1.0);
+            sh.co.S[m][2] = -(m + 1.0) / (m + 2.0);
+        } else {
+            sh.w[0][m] = m > 0 ? 2.0 * sh.co.W[m] * inv0 / (m * PI_D) : 0.0;
+        }
+    }
     __syncthreads();
     // root of F(.) = u: F is nondecreasing; each round keeps the cell between the last point
-    // below u and the first at or above it, with F at both ends (F = 0 and 1 at the domain's)
-    double lo = DIM == 3 ? -1.0 : 0.0, hi = DIM == 3 ? 1.0 : PI_D, Flo = 0.0, Fhi = 1.0;
+    // below u and the first at or above it, with F at both ends (F = 0 and 1 at the domain's);
+    // the last round also keeps F at a third point, the next one beyond the cell (a round's
+    // points and the ends of its range are equally spaced)
+    double lo = DIM == 3 ? -1.0 : 0.0, hi = DIM == 3 ? 1.0 : PI_D, Flo = 0.0, Fhi = 1.0, F3 = 0.0;
+    bool above = true;  // the third point lies above the cell (else below it)
     for (int it = 0; it < ANG_ROUNDS; ++it) {
-        const double d = (hi - lo) / (AWG + 1);
+        const double d = (hi - lo) * (1.0 / (AWG + 1));
         const double c = lo + d * (tid + 1);
-        const double Fc = DIM == 3 ? ang_cdf_n(V, Ne, c) : ang2_cdf_n(V, Ne, c);
+        const double Fc = DIM == 3 ? ang_cdf_n(sh.co.S, M, c) : ang2_cdf_n(sh.w[0], M, c);
         sh.Fv[tid] = Fc;
         const u64 bal = __ballot(Fc >= u);
         if ((tid & 63) == 0) sh.hit[wv] = bal ? __ffsll((unsigned long long)bal) - 1 : 64;
@@ -481,15 +535,23 @@ __device__ __forceinline__ double ang_draw_wg(double tau, double Rin, double R0i
             if (sh.hit[w] < 64) j = 64 * w + sh.hit[w];
         const double nlo = j == 0 ? lo : lo + d * j, nFlo = j == 0 ? Flo : sh.Fv[j - 1];
         const double nhi = j == AWG ? hi : lo + d * (j + 1), nFhi = j == AWG ? Fhi : sh.Fv[j];
+        above = j + 1 < AWG;
+        F3 = sh.Fv[above ? j + 1 : j - 2];
         lo = nlo;
         hi = nhi;
         Flo = nFlo;
         Fhi = nFhi;
         __syncthreads();
     }
-    // F is linear across the final cell to within cell^2 |F''| / 8
-    const double r = Fhi > Flo ? fmin(fmax((u - Flo) / (Fhi - Flo), 0.0), 1.0) : 0.5;
-    return lo + r * (hi - lo);
+    // on the cell, t in [0, 1]: F ~ Flo + s t + q t (t - 1), q half the second difference
+    // (the third point at t = 2 or t = -1); one Newton step from the secant's root
+    const double s = Fhi - Flo;
+    if (!(s > 0.0)) return 0.5 * (lo + hi);
+    const double q = 0.5 * (above ? F3 - 2.0 * Fhi + Flo : Fhi - 2.0 * Flo + F3);
+    double t = fmin(fmax((u - Flo) / s, 0.0), 1.0);
+    const double g = s + q * (2.0 * t - 1.0);
+    if (g > 0.0) t = fmin(fmax(t - q * t * (t - 1.0) / g, 0.0), 1.0);
+    return lo + t * (hi - lo);
 }
 
 // sim_eval_angle: one workgroup per pair.
