@@ -225,6 +225,20 @@ int sim_pool_read(sim_t *h, uint32_t member, int what, void *dst, uint64_t cap_b
  * reports an overflow of the per-step pair list in any of the steps. */
 int sim_step(sim_t *h, uint32_t nsteps);
 
+/* The same steps, enqueued on the handle's stream without waiting (Sec. 3: each step depends
+ * only on the device state the previous one left, so no host round trip is needed between
+ * steps).  The call returns once the graph replays are enqueued; host work, or work the
+ * caller orders after them on the same stream (sim_config.stream), overlaps them.  Calls on
+ * one handle are ordered by its stream.  SIM_EINVAL on a handle with debug logs or kernel
+ * timing (they read back after every step).  A per-step buffer overflow is reported by the
+ * next sim_sync or sim_step.  sim_read, sim_load_state and the pool calls wait for the stream
+ * as they always do; sim_destroy waits for it before freeing. */
+int sim_step_async(sim_t *h, uint32_t nsteps);
+
+/* Waits for every step enqueued on the handle and reports SIM_ECAPACITY if any of them
+ * overflowed a per-step buffer since the last sim_sync or sim_step. */
+int sim_sync(sim_t *h);
+
 /* What sim_read copies to the host buffer dst (cap_bytes long); *written gets
  * the number of bytes.  Reads synchronise the handle's stream. */
 enum {

@@ -122,6 +122,8 @@ struct sim {
     std::string err;
     virtual ~sim() {}
     virtual int step(uint32_t n) = 0;
+    virtual int step_async(uint32_t n) = 0;
+    virtual int sync() = 0;
     virtual int read(int what, void *dst, uint64_t cap, uint64_t *written) = 0;
     virtual int load(uint64_t step, const int32_t *sp, const double *pos, const uint32_t *partner) = 0;
     virtual int eval_pairs(uint64_t n, const double *R, const double *R0, double *penc, double *preac) = 0;
@@ -1148,6 +1150,22 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             const int rc = one_step();
             if (rc) return rc;
         }
+        return sync();
+    }
+
+    int step_async(uint32_t nsteps) override
+    {
+        if (M.debug || M.timing) return fail(SIM_EINVAL, "sim_step_async needs a handle without debug logs or kernel timing");
+        for (uint32_t i = 0; i < nsteps; ++i) {
+            const int rc = one_step();
+            if (rc) return rc;
+        }
+        return SIM_OK;
+    }
+
+    // Waits for the stream; the capacity flags of every step since the last check.
+    int sync() override
+    {
         u32 errflags = 0;
         HIPCHECK(hipMemcpyAsync(&errflags, &ctr->err, sizeof(u32), hipMemcpyDeviceToHost, M.stream));
         HIPCHECK(hipStreamSynchronize(M.stream));
@@ -1523,6 +1541,18 @@ int sim_step(sim_t *h, uint32_t nsteps)
 {
     if (!h) { g_err = "null handle"; return SIM_EINVAL; }
     return h->step(nsteps);
+}
+
+int sim_step_async(sim_t *h, uint32_t nsteps)
+{
+    if (!h) { g_err = "null handle"; return SIM_EINVAL; }
+    return h->step_async(nsteps);
+}
+
+int sim_sync(sim_t *h)
+{
+    if (!h) { g_err = "null handle"; return SIM_EINVAL; }
+    return h->sync();
 }
 
 int sim_read(sim_t *h, int what, void *dst, uint64_t cap_bytes, uint64_t *written)

@@ -139,6 +139,10 @@ def lib():
     L.sim_pool_read.restype = C.c_int
     L.sim_step.argtypes = [vp, u32]
     L.sim_step.restype = C.c_int
+    L.sim_step_async.argtypes = [vp, u32]
+    L.sim_step_async.restype = C.c_int
+    L.sim_sync.argtypes = [vp]
+    L.sim_sync.restype = C.c_int
     L.sim_read.argtypes = [vp, C.c_int, vp, u64, C.POINTER(u64)]
     L.sim_read.restype = C.c_int
     L.sim_load_state.argtypes = [vp, u64, vp, vp, vp]
@@ -276,6 +280,14 @@ class Sim:
 
     def step(self, n=1):
         self._check(lib().sim_step(self._h, int(n)))
+
+    def step_async(self, n=1):
+        """sim_step_async: enqueue n steps on the handle's stream and return."""
+        self._check(lib().sim_step_async(self._h, int(n)))
+
+    def sync(self):
+        """sim_sync: wait for the enqueued steps (raises on a per-step buffer overflow)."""
+        self._check(lib().sim_sync(self._h))
 
     def load_state(self, step, species, pos, partner=None):
         sp = np.ascontiguousarray(species, dtype=np.int32)

@@ -22,7 +22,8 @@ def _declared():
 
 def test_header_declares_the_boundary():
     assert _declared() == sorted(["sim_create", "sim_batch_create", "sim_pool_create", "sim_pool_admit",
-                                  "sim_pool_retire", "sim_pool_read", "sim_step", "sim_read", "sim_load_state",
+                                  "sim_pool_retire", "sim_pool_read", "sim_step", "sim_step_async", "sim_sync", "sim_read",
+                                  "sim_load_state",
                                   "sim_eval_pairs", "sim_eval_pairs_noalloc", "sim_eval_propagator",
                                   "sim_eval_first_passage", "sim_eval_angle", "sim_destroy", "sim_last_error"])
 
