@@ -197,15 +197,70 @@ constexpr double EULER_GAMMA = 0.57721566490153286061;
 // One step of the transposing reduction: lanes that differ in bit `m` exchange the half
 // of their n values the other keeps, and add.  Afterwards lanes with bit m clear hold
 // the lower half, lanes with it set the upper half.
-template <int n>
-__device__ __forceinline__ void ang_fold(double *v, int lane, int m)
+// Lane exchanges of the reduction, in the VALU rather than through the LDS crossbar:
+// v_permlane32_swap exchanges lanes 32-63 of a with lanes 0-31 of b, v_permlane16_swap the odd
+// rows of a with the even rows of b (rows of 16 lanes); DPP moves read lane l ^ 8 (row_ror:8),
+// l + 4 and l - 4 within a row (row_shl:4, row_shr:4) and l ^ 2, l ^ 1 (quad_perm).
+__device__ __forceinline__ void ang_swap(double &a, double &b, bool rows16)
 {
-    const bool up = lane & m;
+    const unsigned long long x = (unsigned long long)__double_as_longlong(a), y = (unsigned long long)__double_as_longlong(b);
+    const unsigned xl = (unsigned)x, xh = (unsigned)(x >> 32), yl = (unsigned)y, yh = (unsigned)(y >> 32);
+    unsigned al, ah, bl, bh;
+    if (rows16) {
+        const auto lo = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+        al = lo[0]; bl = lo[1]; ah = hi[0]; bh = hi[1];
+    } else {
+        const auto lo = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+        al = lo[0]; bl = lo[1]; ah = hi[0]; bh = hi[1];
+    }
+    a = __longlong_as_double((long long)(((unsigned long long)ah << 32) | al));
+    b = __longlong_as_double((long long)(((unsigned long long)bh << 32) | bl));
+}
+
+template <int CTRL> __device__ __forceinline__ double ang_dpp(double v)
+{
+    const unsigned long long x = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)x, CTRL, 0xf, 0xf, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(x >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// v of lane l ^ m, m = 8, 4, 2 or 1 (every lane of the wave active)
+template <int m> __device__ __forceinline__ double ang_xor(double v, int lane)
+{
+    static_assert(m == 8 || m == 4 || m == 2 || m == 1, "row-local exchanges only");
+    if constexpr (m == 8) return ang_dpp<0x128>(v);
+    else if constexpr (m == 4) {
+        const double up = ang_dpp<0x104>(v), down = ang_dpp<0x114>(v);
+        return (lane & 4) ? down : up;
+    } else if constexpr (m == 2) return ang_dpp<0x4E>(v);
+    else return ang_dpp<0xB1>(v);
+}
+
+// One fold of n values on lane bit m: the lane keeps the half of its values selected by
+// that bit and adds its partner's (lane ^ m) copy of the same half.
+template <int n, int m>
+__device__ __forceinline__ void ang_fold(double *v, int lane)
+{
+    if constexpr (m == 32 || m == 16) {
+        // after the swap a lane holds its kept value in one operand and its partner's in the
+        // other: the sum of the two, in either order the same
 #pragma unroll
-    for (int k = 0; k < n / 2; ++k) {
-        const double lo = v[k], hi = v[k + n / 2];
-        const double give = up ? lo : hi, keep = up ? hi : lo;
-        v[k] = keep + __shfl_xor(give, m, 64);
+        for (int k = 0; k < n / 2; ++k) {
+            double a = v[k], b = v[k + n / 2];
+            ang_swap(a, b, m == 16);
+            v[k] = a + b;
+        }
+    } else {
+        const bool up = lane & m;
+#pragma unroll
+        for (int k = 0; k < n / 2; ++k) {
+            const double lo = v[k], hi = v[k + n / 2];
+            const double give = up ? lo : hi, keep = up ? hi : lo;
+            v[k] = keep + ang_xor<m>(give, lane);
+        }
     }
 }
 
@@ -218,7 +273,7 @@ __device__ __forceinline__ int ang_fold_all(double *v, int lane)
         return 0;
     } else {
         constexpr int m = 32 * n / top;  // lane bit of this fold
-        ang_fold<n>(v, lane, m);
+        ang_fold<n, m>(v, lane);
         return ((lane & m) ? n / 2 : 0) + ang_fold_all<n / 2, top>(v, lane);
     }
 }
@@ -429,8 +484,10 @@ __device__ __forceinline__ void ang_node(double x, double g, bool live, double R
         // holding one order (its folded bits, high to low), summed over the lanes that
         // differ in the remaining low bits
         const int o = ang_fold_all<ACS, ACS>(t, lane);
+        static_assert(ACS == 16, "the last two exchanges below are those of 16-order chunks");
         double v0 = t[0];
-        for (int m = 64 / ACS / 2; m >= 1; m >>= 1) v0 += __shfl_xor(v0, m, 64);
+        v0 += ang_xor<2>(v0, lane);
+        v0 += ang_xor<1>(v0, lane);
         const int nn = nn0 + o;
         if ((lane & (64 / ACS - 1)) == 0 && nn >= 0 && nn <= N) wrow[nn] += v0;
     }
