@@ -74,10 +74,18 @@ struct AngShared {
 };
 static_assert(sizeof(AngShared) <= 40960, "four workgroups must share a compute unit's LDS");
 
+// The largest v of the wave (every lane active), the same in every lane: within each row of
+// 16 lanes by DPP moves (lanes l ^ 1 and l ^ 2 by quad_perm, l ^ 4 by a row shift either way,
+// l ^ 8 by row_ror:8), then over the four rows by v_readlane.
 __device__ __forceinline__ int wave_max_i(int v)
 {
-    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
+    v = max(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xf, 0xf, true));
+    v = max(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xf, 0xf, true));
+    const int up = __builtin_amdgcn_mov_dpp(v, 0x104, 0xf, 0xf, true), down = __builtin_amdgcn_mov_dpp(v, 0x114, 0xf, 0xf, true);
+    v = max(v, (threadIdx.x & 4) ? down : up);
+    v = max(v, __builtin_amdgcn_mov_dpp(v, 0x128, 0xf, 0xf, true));
+    return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
 // 1/d from the hardware estimate refined by two Newton steps (the estimate's relative
@@ -298,7 +306,7 @@ __device__ __forceinline__ void ang_node(double x, double g, bool live, double R
     // this node's indices: up to 8 z^{1/3} + 8 orders beyond the largest argument's turning
     // point, where every term has fallen below 1e-28 of w_0
     const double zm = fmax(z[0], fmax(z[1], z[2]));
-    const int zc = (int)ceil(zm + 8.0 * cbrt(zm));
+    const int zc = (int)ceil(zm + 8.0 * (double)cbrtf((float)zm));  // a bound: binary32 serves
     const int kt = live ? min(KT, zc + 9) : 0;
     const int klast = kt - 1;                                 // last index this node uses
     // 16-order chunks, and checkpoints at every chunk when six of them cover the wave's
@@ -556,7 +564,7 @@ __device__ __forceinline__ double ang_draw_wg(double tau, double Rin, double R0i
     int last = 0;
     for (int t = tid; t <= N; t += AWG)
         if (t > 0 && fabs(sh.co.W[t] * inv0) > 1e-17) last = t;
-    for (int o = 32; o >= 1; o >>= 1) last = max(last, __shfl_xor(last, o, 64));
+    last = wave_max_i(last);
     if ((tid & 63) == 0) sh.hit[wv] = last;
     __syncthreads();
     int Ne = 0;
