@@ -46,28 +46,28 @@ def algorithmic_bytes(kernel, n_live, n_a, n_b, n_keys):
 # commands are in profiles/rad3d_step_traffic.md.  Valid only for the kernel sources they were taken
 # on (hash below): after any change to them the field is reported as null.
 MEASURED_TRAFFIC = {
-    "src_hash": "1a451aebe608b1ec",
+    "src_hash": "a160a55f103af923",
     "scale_fetch": 1.9998, "scale_write": 1.0,
     "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
-        "move": (9933.8, 31398.0),
+        "move": (9968.9, 31398.0),
         "scan": (11626.9, 17387.4),
-        "scatter": (17011.9, 29443.4),
-        "pairs": (9763.0, 299.2),
-        "eval": (3255.4, 199.5),
-        "select_a": (246.1, 60.6),
-        "select_b": (265.1, 11.8),
-        "events": (345.8, 73.9),
+        "scatter": (17034.4, 29447.3),
+        "pairs": (9760.1, 299.2),
+        "eval": (3255.7, 200.2),
+        "select_a": (251.6, 60.5),
+        "select_b": (263.7, 12.4),
+        "events": (343.9, 73.8),
     },
     # stage -> VALU wave-instructions per launch (SQ_INSTS_VALU summed over the stage's kernels)
     "valu": {
-        "move": 6003797,
+        "move": 6003796,
         "scan": 416342,
-        "scatter": 723655,
-        "pairs": 5250334,
-        "eval": 437662,
-        "select_a": 69853,
+        "scatter": 723654,
+        "pairs": 5250570,
+        "eval": 437653,
+        "select_a": 69851,
         "select_b": 214598,
-        "events": 1143659,
+        "events": 1143652,
     },
 }
 
@@ -109,15 +109,15 @@ def valu_issue(stage, launch_ms):
 # (SQ_INSTS_VALU_{ADD,MUL,TRANS,FMA}_F64 x 64 lanes, an FMA counting two; SQ_INSTS_VALU),
 # profiles/angle3_kernels.md and profiles/angle2_kernels.md.  Valid for the source they were taken on.
 ANGLE_COUNTERS = {3: {
-    "src_hash": "9e4f84efec2850aa",
+    "src_hash": "30b74b13452ebef8",
     "pairs": 1000000,
-    "f64_flop": 4.721196e+11,  # 64 x (ADD 468250600 + MUL 1794655758 + TRANS 166947286 + 2 x FMA 2473507475)
-    "valu": 7764300338,
+    "f64_flop": 4.690402e+11,  # 64 x (ADD 462186159 + MUL 1790650961 + TRANS 164944892 + 2 x FMA 2455485925)
+    "valu": 7658656103,
 }, 2: {  # k_angle_wg<2> on --angle 200000 --dim 2 (membrane pairs, tau = 0.04)
-    "src_hash": "b3add8d003b132dc",
+    "src_hash": "9244602494d8fca4",
     "pairs": 200000,
-    "f64_flop": 7.336980e+11,  # 64 x (ADD 635191238 + MUL 2794391123 + TRANS 221512762 + 2 x FMA 3906467704)
-    "valu": 10737683353,
+    "f64_flop": 7.303188e+11,  # 64 x (ADD 632791239 + MUL 2789591141 + TRANS 219112762 + 2 x FMA 3884867713)
+    "valu": 10657579447,
 }}
 FP64_VECTOR_PEAK = 78.6e12  # MI355X dense fp64 vector FLOP/s
 
@@ -148,10 +148,10 @@ def angle_roofline(n, launch_ms, dim=3):
 # FMA counting two; SQ_INSTS_VALU), and its HBM bytes (FETCH_SIZE, WRITE_SIZE scaled as above),
 # profiles/rad3d_step_valu.md and profiles/rad3d_step_traffic.md.  Valid for the sources they were taken on (hash below).
 ANGLE_STEP_COUNTERS = {
-    "src_hash": "750a35211015a574",
-    "f64_flop": 2.203498e+08,  # 64 x (ADD 230588 + MUL 816412 + TRANS 81224 + 2 x FMA 1157371)
-    "valu": 3965161,
-    "traffic": 881284,
+    "src_hash": "4797c5fa010bd428",
+    "f64_flop": 2.188997e+08,  # 64 x (ADD 227747 + MUL 814525 + TRANS 80280 + 2 x FMA 1148878)
+    "valu": 3900816,
+    "traffic": 863878,
 }
 ANGLE_STEP_SOURCES = ["common.hpp", "green.hpp", "green2x.hpp", "kernels.hpp", "angle3.hpp", "angle2.hpp",
                       "angle_wg.hpp", "gfbd.hip"]
