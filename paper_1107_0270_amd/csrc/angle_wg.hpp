@@ -35,13 +35,13 @@
 //   - 2D: the geometric panels near x = 0 have ratio 4 (twelve on [4^-12, 1]) instead
 //     of the ratio 2 of angle2.hpp; below 4^-12 the integrand (x times a power of
 //     1 / log x) adds less than 1e-17 of w_0;
-//   - the root of F(.) = u is bracketed by four rounds of a 129-way search (one point
-//     per thread), a cell h of 2 / 129^4 < 1e-8 (3D) or pi / 129^4 (2D), and then taken
-//     from the quadratic through the cell's two ends and the next point of the last
-//     round (one Newton step on it from the secant's root): F is smooth there, so the
-//     error is about h^3 |F^(3) / F'| / 16, far below the rounding of c even for the
-//     narrowest distributions allowed, where linear interpolation (error about
-//     h^2 |F''/F'| / 8) left some 1e-15.
+//   - the root of F(.) = u is bracketed by four rounds of a 128-point search (one point
+//     per thread, the ends of the range included), a cell h of 2 / 127^4 < 1e-8 (3D) or
+//     pi / 127^4 (2D), and then taken from the quadratic through the cell's two ends and
+//     the next point of the last round (one Newton step on it from the secant's root): F
+//     is smooth there, so the error is about h^3 |F^(3) / F'| / 16, far below the rounding
+//     of c even for the narrowest distributions allowed, where linear interpolation (error
+//     about h^2 |F''/F'| / 8) left some 1e-15.
 #pragma once
 
 #include "angle2.hpp"
@@ -69,8 +69,9 @@ struct AngShared {
         } co;
     };
     double w[AW_NW][ANG_NCAP + 1];  // per-wave partial coefficient sums; 2D: then the search's series
-    double Fv[AWG];                 // F at the search points of a round
+    double Fv[AWG];                 // F at the search points of the last round
     int hit[AW_NW];
+    int hitr[2][AW_NW];             // the search's per-wave first points, alternate rounds
 };
 static_assert(sizeof(AngShared) <= 40960, "four workgroups must share a compute unit's LDS");
 
@@ -581,32 +582,36 @@ __device__ __forceinline__ double ang_draw_wg(double tau, double Rin, double R0i
         }
     }
     __syncthreads();
-    // root of F(.) = u: F is nondecreasing; each round keeps the cell between the last point
-    // below u and the first at or above it, with F at both ends (F = 0 and 1 at the domain's);
-    // the last round also keeps F at a third point, the next one beyond the cell (a round's
-    // points and the ends of its range are equally spaced)
+    // root of F(.) = u: F is nondecreasing; each round evaluates AWG equally spaced points
+    // from lo to hi (both ends included) and keeps the cell between the last point below u
+    // and the first at or above it; the last round also keeps F at the cell's ends and at
+    // the next point beyond it.  The rounds' first-point flags alternate between two LDS
+    // slots, so a round needs one barrier.
     double lo = DIM == 3 ? -1.0 : 0.0, hi = DIM == 3 ? 1.0 : PI_D, Flo = 0.0, Fhi = 1.0, F3 = 0.0;
     bool above = true;  // the third point lies above the cell (else below it)
     for (int it = 0; it < ANG_ROUNDS; ++it) {
-        const double d = (hi - lo) * (1.0 / (AWG + 1));
-        const double c = lo + d * (tid + 1);
+        const bool last_round = it == ANG_ROUNDS - 1;
+        const double d = (hi - lo) * (1.0 / (AWG - 1));
+        const double c = lo + d * tid;
         const double Fc = DIM == 3 ? ang_cdf_n(sh.co.S, M, c) : ang2_cdf_n(sh.w[0], M, c);
-        sh.Fv[tid] = Fc;
+        if (last_round) sh.Fv[tid] = Fc;
         const u64 bal = __ballot(Fc >= u);
-        if ((tid & 63) == 0) sh.hit[wv] = bal ? __ffsll((unsigned long long)bal) - 1 : 64;
+        int *hit = sh.hitr[it & 1];
+        if ((tid & 63) == 0) hit[wv] = bal ? __ffsll((unsigned long long)bal) - 1 : 64;
         __syncthreads();
         int j = AWG;  // first point at or above u
         for (int w = AW_NW - 1; w >= 0; --w)
-            if (sh.hit[w] < 64) j = 64 * w + sh.hit[w];
-        const double nlo = j == 0 ? lo : lo + d * j, nFlo = j == 0 ? Flo : sh.Fv[j - 1];
-        const double nhi = j == AWG ? hi : lo + d * (j + 1), nFhi = j == AWG ? Fhi : sh.Fv[j];
-        above = j + 1 < AWG;
-        F3 = sh.Fv[above ? j + 1 : j - 2];
+            if (hit[w] < 64) j = 64 * w + hit[w];
+        j = min(max(j, 1), AWG - 1);  // the ends bracket the root up to rounding
+        const double nlo = lo + d * (j - 1), nhi = lo + d * j;
+        if (last_round) {
+            Flo = sh.Fv[j - 1];
+            Fhi = sh.Fv[j];
+            above = j + 1 < AWG;
+            F3 = sh.Fv[above ? j + 1 : j - 2];
+        }
         lo = nlo;
         hi = nhi;
-        Flo = nFlo;
-        Fhi = nFhi;
-        __syncthreads();
     }
     // on the cell, t in [0, 1]: F ~ Flo + s t + q t (t - 1), q half the second difference
     // (the third point at t = 2 or t = -1); one Newton step from the secant's root
