@@ -49,25 +49,25 @@ MEASURED_TRAFFIC = {
     "src_hash": "a160a55f103af923",
     "scale_fetch": 1.9998, "scale_write": 1.0,
     "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
-        "move": (9968.9, 31398.0),
-        "scan": (11626.9, 17387.4),
-        "scatter": (17034.4, 29447.3),
-        "pairs": (9760.1, 299.2),
-        "eval": (3255.7, 200.2),
-        "select_a": (251.6, 60.5),
-        "select_b": (263.7, 12.4),
-        "events": (343.9, 73.8),
+        "move": (9937.9, 31398.0),
+        "scan": (11626.6, 17387.5),
+        "scatter": (17004.2, 29446.7),
+        "pairs": (9762.7, 299.2),
+        "eval": (3255.4, 199.9),
+        "select_a": (251.6, 60.3),
+        "select_b": (269.4, 12.3),
+        "events": (341.8, 73.9),
     },
     # stage -> VALU wave-instructions per launch (SQ_INSTS_VALU summed over the stage's kernels)
     "valu": {
-        "move": 6003796,
+        "move": 6003795,
         "scan": 416342,
         "scatter": 723654,
-        "pairs": 5250570,
-        "eval": 437653,
-        "select_a": 69851,
-        "select_b": 214598,
-        "events": 1143652,
+        "pairs": 5250550,
+        "eval": 437604,
+        "select_a": 69757,
+        "select_b": 214500,
+        "events": 1143665,
     },
 }
 
@@ -109,15 +109,15 @@ def valu_issue(stage, launch_ms):
 # (SQ_INSTS_VALU_{ADD,MUL,TRANS,FMA}_F64 x 64 lanes, an FMA counting two; SQ_INSTS_VALU),
 # profiles/angle3_kernels.md and profiles/angle2_kernels.md.  Valid for the source they were taken on.
 ANGLE_COUNTERS = {3: {
-    "src_hash": "30b74b13452ebef8",
+    "src_hash": "a0ddd011ee764d05",
     "pairs": 1000000,
-    "f64_flop": 4.690402e+11,  # 64 x (ADD 462186159 + MUL 1790650961 + TRANS 164944892 + 2 x FMA 2455485925)
-    "valu": 7658656103,
+    "f64_flop": 4.690402e+11,  # 64 x (ADD 460186159 + MUL 1788650961 + TRANS 164944892 + 2 x FMA 2457485925)
+    "valu": 7608590567,
 }, 2: {  # k_angle_wg<2> on --angle 200000 --dim 2 (membrane pairs, tau = 0.04)
-    "src_hash": "9244602494d8fca4",
+    "src_hash": "c35a1e0773bd2f3d",
     "pairs": 200000,
-    "f64_flop": 7.303188e+11,  # 64 x (ADD 632791239 + MUL 2789591141 + TRANS 219112762 + 2 x FMA 3884867713)
-    "valu": 10657579447,
+    "f64_flop": 7.303188e+11,  # 64 x (ADD 632391239 + MUL 2789191141 + TRANS 219112762 + 2 x FMA 3885267713)
+    "valu": 10644215607,
 }}
 FP64_VECTOR_PEAK = 78.6e12  # MI355X dense fp64 vector FLOP/s
 
@@ -148,10 +148,10 @@ def angle_roofline(n, launch_ms, dim=3):
 # FMA counting two; SQ_INSTS_VALU), and its HBM bytes (FETCH_SIZE, WRITE_SIZE scaled as above),
 # profiles/rad3d_step_valu.md and profiles/rad3d_step_traffic.md.  Valid for the sources they were taken on (hash below).
 ANGLE_STEP_COUNTERS = {
-    "src_hash": "4797c5fa010bd428",
-    "f64_flop": 2.188997e+08,  # 64 x (ADD 227747 + MUL 814525 + TRANS 80280 + 2 x FMA 1148878)
-    "valu": 3900816,
-    "traffic": 863878,
+    "src_hash": "80e4aed7dc22c308",
+    "f64_flop": 2.188997e+08,  # 64 x (ADD 226804 + MUL 813582 + TRANS 80280 + 2 x FMA 1149822)
+    "valu": 3874077,
+    "traffic": 866927,
 }
 ANGLE_STEP_SOURCES = ["common.hpp", "green.hpp", "green2x.hpp", "kernels.hpp", "angle3.hpp", "angle2.hpp",
                       "angle_wg.hpp", "gfbd.hip"]
