@@ -46,7 +46,7 @@ def algorithmic_bytes(kernel, n_live, n_a, n_b, n_keys):
 # commands are in profiles/rad3d_step_traffic.md.  Valid only for the kernel sources they were taken
 # on (hash below): after any change to them the field is reported as null.
 MEASURED_TRAFFIC = {
-    "src_hash": "a160a55f103af923",
+    "src_hash": "b926decbef6411a5",
     "scale_fetch": 1.9998, "scale_write": 1.0,
     "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
         "move": (9937.9, 31398.0),
@@ -72,12 +72,42 @@ MEASURED_TRAFFIC = {
 }
 
 
-def kernel_src_hash():
+def _code_text(path):
+    """A source file without its comments and with every run of white space made one blank:
+    what the compiler reads, so that edits to comments leave the hashes below unchanged."""
+    src = open(path, encoding="utf-8").read()
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":  # a literal, escapes included
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
+def _src_hash(files):
     h = hashlib.sha256()
-    for f in ["common.hpp", "green.hpp", "kernels.hpp", "gfbd.hip"]:
-        with open(os.path.join(ROOT, "paper_1107_0270_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for f in files:
+        h.update(_code_text(os.path.join(ROOT, "paper_1107_0270_amd", "csrc", f)).encode())
+        h.update(b"\0")
     return h.hexdigest()[:16]
+
+
+def kernel_src_hash():
+    return _src_hash(["common.hpp", "green.hpp", "kernels.hpp", "gfbd.hip"])
 
 
 def measured_traffic(stage):
@@ -109,12 +139,12 @@ def valu_issue(stage, launch_ms):
 # (SQ_INSTS_VALU_{ADD,MUL,TRANS,FMA}_F64 x 64 lanes, an FMA counting two; SQ_INSTS_VALU),
 # profiles/angle3_kernels.md and profiles/angle2_kernels.md.  Valid for the source they were taken on.
 ANGLE_COUNTERS = {3: {
-    "src_hash": "a0ddd011ee764d05",
+    "src_hash": "d956bc790ba5fe42",
     "pairs": 1000000,
     "f64_flop": 4.690402e+11,  # 64 x (ADD 460186159 + MUL 1788650961 + TRANS 164944892 + 2 x FMA 2457485925)
     "valu": 7608590567,
 }, 2: {  # k_angle_wg<2> on --angle 200000 --dim 2 (membrane pairs, tau = 0.04)
-    "src_hash": "c35a1e0773bd2f3d",
+    "src_hash": "b5e1590469766e71",
     "pairs": 200000,
     "f64_flop": 7.303188e+11,  # 64 x (ADD 632391239 + MUL 2789191141 + TRANS 219112762 + 2 x FMA 3885267713)
     "valu": 10644215607,
@@ -123,11 +153,7 @@ FP64_VECTOR_PEAK = 78.6e12  # MI355X dense fp64 vector FLOP/s
 
 
 def angle_src_hash(dim=3):
-    h = hashlib.sha256()
-    for f in ["angle3.hpp", "angle_wg.hpp"] + (["angle2.hpp"] if dim == 2 else []):
-        with open(os.path.join(ROOT, "paper_1107_0270_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    return _src_hash(["angle3.hpp", "angle_wg.hpp"] + (["angle2.hpp"] if dim == 2 else []))
 
 
 def angle_roofline(n, launch_ms, dim=3):
@@ -148,7 +174,7 @@ def angle_roofline(n, launch_ms, dim=3):
 # FMA counting two; SQ_INSTS_VALU), and its HBM bytes (FETCH_SIZE, WRITE_SIZE scaled as above),
 # profiles/rad3d_step_valu.md and profiles/rad3d_step_traffic.md.  Valid for the sources they were taken on (hash below).
 ANGLE_STEP_COUNTERS = {
-    "src_hash": "80e4aed7dc22c308",
+    "src_hash": "d1a30ed499e69787",
     "f64_flop": 2.188997e+08,  # 64 x (ADD 226804 + MUL 813582 + TRANS 80280 + 2 x FMA 1149822)
     "valu": 3874077,
     "traffic": 866927,
@@ -158,11 +184,7 @@ ANGLE_STEP_SOURCES = ["common.hpp", "green.hpp", "green2x.hpp", "kernels.hpp", "
 
 
 def angle_step_src_hash():
-    h = hashlib.sha256()
-    for f in ANGLE_STEP_SOURCES:
-        with open(os.path.join(ROOT, "paper_1107_0270_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    return _src_hash(ANGLE_STEP_SOURCES)
 
 
 def angle_step_roofline(launch_ms, profiled):

@@ -18,10 +18,11 @@
 //   - the Bessel sequence J of a node comes from the downward recurrence, which yields
 //     it highest order first while the products need it lowest order first.  Instead
 //     of storing the sequence per thread (per-lane scratch memory), the first sweep
-//     keeps the pair (J_k, J_{k+1}) at every 32nd order k in the thread's column of LDS
-//     (checkpoints), and the second pass regenerates each 16-order half of a block
-//     downward from its checkpoint into registers (the lower half runs through the
-//     upper one first), then consumes it upward beside the upward recurrence of Y.
+//     keeps the pair (J_k, J_{k+1}) at every 16th order k (every 32nd when six such
+//     checkpoints would not cover the wave's orders) in the thread's column of LDS, and
+//     the second pass regenerates each 16-order chunk downward from its checkpoint into
+//     registers (a lower chunk runs through the upper one first), then consumes it
+//     upward beside the upward recurrence of Y.
 //     Rescaling during the first sweep scales the checkpoints already kept, so every
 //     value is the same solution of the recurrence up to one common factor, removed by
 //     the normalisation to the elementary J_{-1/2}, J_{1/2} (3D) or to J_0, J_1 (2D).
@@ -29,9 +30,12 @@
 //     workgroups (two waves per SIMD) share a compute unit;
 //   - each chunk's sixteen per-order terms are summed over the wave by a transposing
 //     reduction (halving the orders a lane holds at each exchange: 17 exchanges per
-//     chunk instead of 6 per order) and added into the wave's own row of LDS; the rows
-//     are summed in wave order at the end.  Every sum runs in a fixed order, so the
-//     coefficients, and the draw, do not depend on timing;
+//     chunk instead of 6 per order, done by permlane swaps and DPP moves in the VALU)
+//     and added into the wave's own row of LDS; the rows are summed in wave order at
+//     the end.  Every sum runs in a fixed order, so the coefficients, and the draw, do
+//     not depend on timing;
+//   - the search evaluates the 3D distribution function as a Legendre series summed
+//     downward (Clenshaw), its coefficients and recurrence constants in rows of LDS;
 //   - 2D: the geometric panels near x = 0 have ratio 4 (twelve on [4^-12, 1]) instead
 //     of the ratio 2 of angle2.hpp; below 4^-12 the integrand (x times a power of
 //     1 / log x) adds less than 1e-17 of w_0;
