@@ -46,28 +46,28 @@ def algorithmic_bytes(kernel, n_live, n_a, n_b, n_keys):
 # commands are in profiles/rad3d_step_traffic.md.  Valid only for the kernel sources they were taken
 # on (hash below): after any change to them the field is reported as null.
 MEASURED_TRAFFIC = {
-    "src_hash": "b926decbef6411a5",
+    "src_hash": "9e47985eab1657ec",
     "scale_fetch": 1.9998, "scale_write": 1.0,
     "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
-        "move": (9937.9, 31398.0),
-        "scan": (11626.6, 17387.5),
-        "scatter": (17004.2, 29446.7),
-        "pairs": (9762.7, 299.2),
-        "eval": (3255.4, 199.9),
-        "select_a": (251.6, 60.3),
-        "select_b": (269.4, 12.3),
-        "events": (341.8, 73.9),
+        "move": (9955.7, 31398.1),
+        "scan": (11626.6, 17387.4),
+        "scatter": (16995.7, 29441.9),
+        "pairs": (9762.9, 299.2),
+        "eval": (3255.4, 199.8),
+        "select_a": (251.8, 60.5),
+        "select_b": (269.5, 12.2),
+        "events": (335.0, 73.8),
     },
     # stage -> VALU wave-instructions per launch (SQ_INSTS_VALU summed over the stage's kernels)
     "valu": {
         "move": 6003795,
         "scan": 416342,
         "scatter": 723654,
-        "pairs": 5250550,
-        "eval": 437604,
-        "select_a": 69757,
-        "select_b": 214500,
-        "events": 1143665,
+        "pairs": 5250598,
+        "eval": 437589,
+        "select_a": 69725,
+        "select_b": 214468,
+        "events": 1143653,
     },
 }
 
@@ -174,10 +174,10 @@ def angle_roofline(n, launch_ms, dim=3):
 # FMA counting two; SQ_INSTS_VALU), and its HBM bytes (FETCH_SIZE, WRITE_SIZE scaled as above),
 # profiles/rad3d_step_valu.md and profiles/rad3d_step_traffic.md.  Valid for the sources they were taken on (hash below).
 ANGLE_STEP_COUNTERS = {
-    "src_hash": "d1a30ed499e69787",
+    "src_hash": "8522bcabe37bbec5",
     "f64_flop": 2.188997e+08,  # 64 x (ADD 226804 + MUL 813582 + TRANS 80280 + 2 x FMA 1149822)
     "valu": 3874077,
-    "traffic": 866927,
+    "traffic": 864880,
 }
 ANGLE_STEP_SOURCES = ["common.hpp", "green.hpp", "green2x.hpp", "kernels.hpp", "angle3.hpp", "angle2.hpp",
                       "angle_wg.hpp", "gfbd.hip"]

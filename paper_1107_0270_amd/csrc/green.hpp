@@ -187,14 +187,11 @@ template <int NC> __device__ inline double corr2_n(const Params &P, double Rp, d
 #include "green2x.hpp"
 
 // The order NC (12, or 0 for any order; NC_EXACT: the tables of green2x.hpp) is a template parameter of the
-// kernels that evaluate the expansion, chosen on the host.  The run-time
-// order forms (arrays in scratch) are called, not inlined: inlined into the
-// event handler's wave sampler they gave acceptance decisions that differ
-// from the oracle's, while called (and inlined into a kernel) they agree
-// draw by draw.
-__device__ __noinline__ double penc2_any(const Params &P, double R, double R0) { return penc2_n<0>(P, R, R0); }
-__device__ __noinline__ double preac2_any(const Params &P, double R, double R0) { return preac2_n<0>(P, R, R0); }
-__device__ __noinline__ double corr2_any(const Params &P, double Rp, double R0) { return corr2_n<0>(P, Rp, R0); }
+// kernels that evaluate the expansion, chosen on the host; NC = 0 takes the
+// run-time order (its arrays sized for MAXTERMS).
+__device__ inline double penc2_any(const Params &P, double R, double R0) { return penc2_n<0>(P, R, R0); }
+__device__ inline double preac2_any(const Params &P, double R, double R0) { return preac2_n<0>(P, R, R0); }
+__device__ inline double corr2_any(const Params &P, double Rp, double R0) { return corr2_n<0>(P, Rp, R0); }
 template <int NC> __device__ inline double penc2(const Params &P, double R, double R0)
 {
     if constexpr (NC == NC_EXACT) return R0 <= P.x2_r0sw ? penc2x(P, R, R0) : penc2_any(P, R, R0);
