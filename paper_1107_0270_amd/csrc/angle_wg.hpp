@@ -39,6 +39,10 @@
 //   - 2D: the geometric panels near x = 0 have ratio 4 (twelve on [4^-12, 1]) instead
 //     of the ratio 2 of angle2.hpp; below 4^-12 the integrand (x times a power of
 //     1 / log x) adds less than 1e-17 of w_0;
+//   - the x integral stops at sqrt(40 / tau), where e^{-tau x^2} = e^{-40}, instead of
+//     sqrt(50 / tau): the rest is below 5e-18 of the integral of the terms' magnitudes,
+//     far below the rounding the cancellation in G_ref - G_abs brings, and in 3D at
+//     tau = 0.8 pairs with R + R0 up to 8.1 (up to 7.36 before) fit one batch of nodes;
 //   - the root of F(.) = u is bracketed by four rounds of a 128-point search (one point
 //     per thread, the ends of the range included), a cell h of 2 / 127^4 < 1e-8 (3D) or
 //     pi / 127^4 (2D), and then taken from the quadratic through the cell's two ends and
@@ -186,8 +190,8 @@ __device__ __forceinline__ double ang2_cdf_n(const double *a, int N, double t)
 // The Miller sweep of a 2D node accumulates the three sums beside the recurrence, so the
 // normalisation and the Y recurrences' starting values need no Bessel function call.
 // w[k]: (-1)^{k/2} / (k/2) at even k >= 2 (0 at k = 0), d_k at odd k.  A node's sweep
-// starts below ANG_KMAX: its arguments are at most (1 + 40 sqrt(tau)) sqrt(50 / tau) <= 442
-// for tau >= ANG_TAU_MIN, so the start z + 8 z^{1/3} + 16 stays below 520.
+// starts below ANG_KMAX: its arguments are at most (1 + 40 sqrt(tau)) sqrt(40 / tau) <= 395
+// for tau >= ANG_TAU_MIN, so the start z + 8 z^{1/3} + 16 stays below 470.
 constexpr int ANG_KMAX = 1024;
 struct NeumannTable {
     double w[ANG_KMAX];
@@ -519,7 +523,7 @@ __device__ __forceinline__ double ang_draw_wg(double tau, double Rin, double R0i
     for (int t = tid; t < AW_NW * (ANG_NCAP + 1); t += AWG) (&sh.w[0][0])[t] = 0.0;
     __syncthreads();
     // nodes: 3D equal panels on [0, X]; 2D geometric panels on [4^-12, 1], then equal ones
-    const double X = sqrt(50.0 / tau), hmax = fmin(1.0, 2.0 * PI_D / (R + R0 - 1.0));
+    const double X = sqrt(40.0 / tau), hmax = fmin(1.0, 2.0 * PI_D / (R + R0 - 1.0));
     int Q, nuni;
     double h, x1 = 0.0;
     if constexpr (DIM == 3) {
