@@ -49,25 +49,25 @@ MEASURED_TRAFFIC = {
     "src_hash": "9e47985eab1657ec",
     "scale_fetch": 1.9998, "scale_write": 1.0,
     "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
-        "move": (9955.7, 31398.1),
+        "move": (9961.1, 31397.9),
         "scan": (11626.6, 17387.4),
-        "scatter": (16995.7, 29441.9),
-        "pairs": (9762.9, 299.2),
-        "eval": (3255.4, 199.8),
-        "select_a": (251.8, 60.5),
-        "select_b": (269.5, 12.2),
-        "events": (335.0, 73.8),
+        "scatter": (17013.0, 29449.7),
+        "pairs": (9762.8, 299.2),
+        "eval": (3256.4, 200.2),
+        "select_a": (251.2, 60.7),
+        "select_b": (268.8, 12.4),
+        "events": (334.8, 73.8),
     },
     # stage -> VALU wave-instructions per launch (SQ_INSTS_VALU summed over the stage's kernels)
     "valu": {
-        "move": 6003795,
+        "move": 6003797,
         "scan": 416342,
-        "scatter": 723654,
-        "pairs": 5250598,
-        "eval": 437589,
-        "select_a": 69725,
-        "select_b": 214468,
-        "events": 1143653,
+        "scatter": 723655,
+        "pairs": 5250708,
+        "eval": 437690,
+        "select_a": 69901,
+        "select_b": 214652,
+        "events": 1143663,
     },
 }
 
@@ -139,15 +139,15 @@ def valu_issue(stage, launch_ms):
 # (SQ_INSTS_VALU_{ADD,MUL,TRANS,FMA}_F64 x 64 lanes, an FMA counting two; SQ_INSTS_VALU),
 # profiles/angle3_kernels.md and profiles/angle2_kernels.md.  Valid for the source they were taken on.
 ANGLE_COUNTERS = {3: {
-    "src_hash": "d956bc790ba5fe42",
+    "src_hash": "fa904578223810ec",
     "pairs": 1000000,
-    "f64_flop": 4.690402e+11,  # 64 x (ADD 460186159 + MUL 1788650961 + TRANS 164944892 + 2 x FMA 2457485925)
-    "valu": 7608590567,
+    "f64_flop": 4.631595e+11,  # 64 x (ADD 459791425 + MUL 1741552687 + TRANS 164812436 + 2 x FMA 2435355467)
+    "valu": 7445373893,
 }, 2: {  # k_angle_wg<2> on --angle 200000 --dim 2 (membrane pairs, tau = 0.04)
-    "src_hash": "b5e1590469766e71",
+    "src_hash": "4175384f1b737beb",
     "pairs": 200000,
-    "f64_flop": 7.303188e+11,  # 64 x (ADD 632391239 + MUL 2789191141 + TRANS 219112762 + 2 x FMA 3885267713)
-    "valu": 10644215607,
+    "f64_flop": 6.560815e+11,  # 64 x (ADD 602869869 + MUL 2437297157 + TRANS 198034386 + 2 x FMA 3506536180)
+    "valu": 9468675080,
 }}
 FP64_VECTOR_PEAK = 78.6e12  # MI355X dense fp64 vector FLOP/s
 
@@ -174,9 +174,9 @@ def angle_roofline(n, launch_ms, dim=3):
 # FMA counting two; SQ_INSTS_VALU), and its HBM bytes (FETCH_SIZE, WRITE_SIZE scaled as above),
 # profiles/rad3d_step_valu.md and profiles/rad3d_step_traffic.md.  Valid for the sources they were taken on (hash below).
 ANGLE_STEP_COUNTERS = {
-    "src_hash": "8522bcabe37bbec5",
-    "f64_flop": 2.188997e+08,  # 64 x (ADD 226804 + MUL 813582 + TRANS 80280 + 2 x FMA 1149822)
-    "valu": 3874077,
+    "src_hash": "0c14d0623319b3e0",
+    "f64_flop": 2.166964e+08,  # 64 x (ADD 226747 + MUL 795576 + TRANS 80261 + 2 x FMA 1141648)
+    "valu": 3813262,
     "traffic": 864880,
 }
 ANGLE_STEP_SOURCES = ["common.hpp", "green.hpp", "green2x.hpp", "kernels.hpp", "angle3.hpp", "angle2.hpp",
