@@ -365,7 +365,7 @@ int sim_eval_first_passage(sim_t *h, uint64_t n, const double *xi, const double 
  * half-integer orders) or eq. genericGF with eq. fRad (cos n theta, integer orders), reflecting
  * minus absorbing surface, with terms n <= min(160, 8 + ceil(sqrt(45 R R0 / tau))); each
  * coefficient is an integral over x by 16-point Gauss-Legendre panels of width at most
- * min(1, 2 pi / (R + R0 - 1)) on [0, sqrt(50 / tau)] (2D: 32 panels of ratio 2 on [2^-32, 1]
+ * min(1, 2 pi / (R + R0 - 1)) on [0, sqrt(40 / tau)] (2D: 12 panels of ratio 4 on [4^-12, 1]
  * first, where Y_0 has its logarithm), the Bessel functions by the three-term recurrences of
  * Sec. 4.1 (eq. 3termBessel).  The cap of 160 terms keeps the truncation below 1e-15 for
  * R R0 / tau <= 500.  The coefficients sum terms of the size of the free Green's function down

@@ -25,9 +25,10 @@ def _u(w):
 
 
 def _batches(dim, R, R0, tau):
-    """Node batches of 128 of the pair's quadrature."""
+    """Node batches of 128 of the pair's quadrature (the kernel's layout: 16-point panels to
+    sqrt(40 / tau), in 2D twelve geometric ones on [4^-12, 1] first)."""
     R, R0 = max(R, 1.0), max(R0, 1.0)
-    X = math.sqrt(50.0 / tau)
+    X = math.sqrt(40.0 / tau)
     hmax = min(1.0, 2.0 * math.pi / (R + R0 - 1.0))
     if dim == 3:
         q = 16 * math.ceil(X / hmax)
@@ -50,7 +51,7 @@ def _propagated(gpu, step=0, key=(0, 0)):
 def test_3d_step_angles_equal_eval_angle(dt):
     # the 3D radiation workload at 4.2e5 particles in a 7.5 um box (about the same density);
     # tau = 0.5 puts every pair in two batches or more, tau = 0.8 (the benchmark's) only
-    # pairs with R + R0 > 1 + 2 pi
+    # pairs with R + R0 > 8.1
     cfg = I.workload("cfg_rad3d", n_a=210_000, n_b=210_000, box=7.5, dt=dt)
     sp, pos, _ = I.uniform_state(cfg["n_a"], cfg["n_b"], box=cfg["box"], dim=3, sigma=cfg["sigma"], seed=2)
     gpu = S.Sim(dim=3, box=cfg["box"], dt=cfg["dt"], D=cfg["D"], sigma=cfg["sigma"], bc=cfg["bc"],
