@@ -126,12 +126,15 @@ struct Params {
     u32 dbg_cap;
     const double *g2c;  // 2D constants: a_k(0), Q_abs, Q_ref, Q_rad (4 x (MAXTERMS+1))
     // exact 2D radial functions (green2x.hpp): tables over R = 1 + i h (i < x2_nr) and
-    // R0 = 1 + 2 j h (j < x2_n0), column j contiguous: p_enc, p_reac, propagator distribution;
+    // R0 = 1 + 2 j h (j < x2_n0): p_enc and p_reac in binary32 tiles of 8 x 4 (x2_ntr row
+    // tiles), the propagator's distribution function in binary64 with column j contiguous;
     // pairs with R0 > x2_r0sw take p_enc and p_reac from the small-time expansions, pairs with
     // R0 > x2_r0sw_prop their propagation
-    const double *x2_enc, *x2_reac, *x2_cdf;
+    const float *x2_enc, *x2_reac;
+    const double *x2_cdf;
     double x2_h, x2_inv_h, x2_inv_h0, x2_r0sw, x2_r0sw_prop;
     u32 x2_nr, x2_n0, x2_n0_prop;  // rows, columns; columns the propagator's interpolation may read
+    u32 x2_ntr;                    // row tiles of the p_enc and p_reac tables
     // Batches of independent replicas: replica r owns slots [slot_base,
     // slot_base + n) and cells [cell_base, cell_base + own cell count) of
     // every species block.  A single system is replica 0 with both bases 0.

@@ -523,6 +523,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         Q.x2_n0_prop = src.x2_n0_prop;
         Q.x2_nr = src.x2_nr;
         Q.x2_n0 = src.x2_n0;
+        Q.x2_ntr = src.x2_ntr;
     }
 
     int build_x2(Params &Q)
@@ -564,15 +565,21 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         double *d_x = tmp_buf, *d_s1 = d_x + K, *d_s2 = d_s1 + K, *d_nd = d_s2 + K;
         double *Cabs = d_nd + 8 * (size_t)K, *Cref = Cabs + NK, *Crad = Cref + NK, *Kabs = Crad + NK, *Kref = Kabs + NK;
         double *Gabs = Kref + NK, *Gref = Gabs + NT, *Grad = Gref + NT, *Mabs = Grad + NT, *Mref = Mabs + NT;
-        double *enc = nullptr, *reac = nullptr, *cdf = nullptr;
+        // p_enc and p_reac in binary32 tiles of X2TR rows by X2TC columns (the padding is never read)
+        const u32 ntr = (nr + X2TR - 1) / X2TR, ntc = (n0 + X2TC - 1) / X2TC;
+        const size_t NB = (size_t)ntr * ntc * X2TR * X2TC;
+        float *enc = nullptr, *reac = nullptr;
+        double *cdf = nullptr;
         int rc;
-        if ((rc = alloc(enc, NT)) || (rc = alloc(reac, NT)) || (rc = alloc(cdf, NT))) {
+        if ((rc = alloc(enc, NB)) || (rc = alloc(reac, NB)) || (rc = alloc(cdf, NT))) {
             (void)hipFree(tmp_buf);
             return rc;
         }
         hipStream_t sm = M.stream;
         auto run = [&]() -> hipError_t {
             hipError_t e;
+            if ((e = hipMemsetAsync(enc, 0, sizeof(float) * NB, sm)) != hipSuccess) return e;
+            if ((e = hipMemsetAsync(reac, 0, sizeof(float) * NB, sm)) != hipSuccess) return e;
             if ((e = hipMemcpyAsync(d_x, xs.data(), sizeof(double) * K, hipMemcpyHostToDevice, sm)) != hipSuccess) return e;
             if ((e = hipMemcpyAsync(d_s1, s1.data(), sizeof(double) * K, hipMemcpyHostToDevice, sm)) != hipSuccess) return e;
             if ((e = hipMemcpyAsync(d_s2, s2.data(), sizeof(double) * K, hipMemcpyHostToDevice, sm)) != hipSuccess) return e;
@@ -584,7 +591,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             k_x2_gemm<<<g, 256, 0, sm>>>(Crad, Crad, d_s1, nr, n0, K, Grad);
             k_x2_gemm<<<g, 256, 0, sm>>>(Kabs, Cabs, d_s2, nr, n0, K, Mabs);
             k_x2_gemm<<<g, 256, 0, sm>>>(Kref, Cref, d_s2, nr, n0, K, Mref);
-            k_x2_tables<<<(u32)((NT + 255) / 256), 256, 0, sm>>>(Gabs, Gref, Grad, Mabs, Mref, nr, n0, h, tau, top, enc, reac, cdf);
+            k_x2_tables<<<(u32)((NT + 255) / 256), 256, 0, sm>>>(Gabs, Gref, Grad, Mabs, Mref, nr, n0, h, tau, top, ntr, enc, reac, cdf);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             return hipStreamSynchronize(sm);  // the host vectors are read by the copies
         };
@@ -602,6 +609,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         Q.x2_n0_prop = std::min<u32>(n0, (u32)std::ceil(8.4 * st / h0) + 4);
         Q.x2_nr = nr;
         Q.x2_n0 = n0;
+        Q.x2_ntr = ntr;
         x2_build = {(double)K, (double)nr, (double)n0};
         return SIM_OK;
     }

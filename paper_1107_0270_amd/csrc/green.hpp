@@ -192,15 +192,24 @@ template <int NC> __device__ inline double corr2_n(const Params &P, double Rp, d
 __device__ inline double penc2_any(const Params &P, double R, double R0) { return penc2_n<0>(P, R, R0); }
 __device__ inline double preac2_any(const Params &P, double R, double R0) { return preac2_n<0>(P, R, R0); }
 __device__ inline double corr2_any(const Params &P, double Rp, double R0) { return corr2_n<0>(P, Rp, R0); }
+// Beyond the tables' switch (NC_EXACT) the expansion runs at the handle's order, in its
+// compiled form when that is the default order 12 (uniform branch): a wave whose pairs
+// straddle the switch runs both forms, and the run-time-order one costs several times more.
 template <int NC> __device__ inline double penc2(const Params &P, double R, double R0)
 {
-    if constexpr (NC == NC_EXACT) return R0 <= P.x2_r0sw ? penc2x(P, R, R0) : penc2_any(P, R, R0);
+    if constexpr (NC == NC_EXACT) {
+        if (R0 <= P.x2_r0sw) return penc2x(P, R, R0);
+        return P.n_terms == 12 ? penc2_n<12>(P, R, R0) : penc2_any(P, R, R0);
+    }
     else if constexpr (NC == 0) return penc2_any(P, R, R0);
     else return penc2_n<NC>(P, R, R0);
 }
 template <int NC> __device__ inline double preac2(const Params &P, double R, double R0)
 {
-    if constexpr (NC == NC_EXACT) return R0 <= P.x2_r0sw ? preac2x(P, R, R0) : preac2_any(P, R, R0);
+    if constexpr (NC == NC_EXACT) {
+        if (R0 <= P.x2_r0sw) return preac2x(P, R, R0);
+        return P.n_terms == 12 ? preac2_n<12>(P, R, R0) : preac2_any(P, R, R0);
+    }
     else if constexpr (NC == 0) return preac2_any(P, R, R0);
     else return preac2_n<NC>(P, R, R0);
 }

@@ -61,8 +61,23 @@ __device__ __forceinline__ u32 lag_base(double f, u32 n, double w[4])
     return (u32)b;
 }
 
-// Bicubic value of table T (column-major over R0) at (R, R0).
-__device__ inline double x2_table(const Params &P, const double *__restrict__ T, double R, double R0)
+// The p_enc and p_reac tables are read at pairs in cell order, that is at random
+// (R, R0): each lookup gathers a 4 x 4 stencil.  They are kept in binary32 (p_enc and
+// p_reac are probabilities: the rounding is below 6e-8, the interpolation sums it to
+// below 1e-7) in tiles of 8 rows (R) by 4 columns (R0), one 128-byte line each, a
+// tile's columns of 8 rows one after the other, tiles ordered row tile fastest.  A
+// stencil then touches 2.4 lines on average (4 to 5 in column-major binary64), and
+// the rows that pairs within the cut-off read take half the bytes.
+constexpr u32 X2TR = 8, X2TC = 4;
+
+// Index of element (row i, column j) of a blocked table with ntr row tiles.
+__device__ __forceinline__ size_t x2_bidx(u32 i, u32 j, u32 ntr)
+{
+    return ((size_t)(j / X2TC) * ntr + i / X2TR) * (X2TR * X2TC) + (j % X2TC) * X2TR + i % X2TR;
+}
+
+// Bicubic value of blocked table T at (R, R0).
+__device__ inline double x2_table(const Params &P, const float *__restrict__ T, double R, double R0)
 {
     double wi[4], wj[4];
     const u32 bi = lag_base((R - 1.0) * P.x2_inv_h, P.x2_nr, wi);
@@ -70,8 +85,14 @@ __device__ inline double x2_table(const Params &P, const double *__restrict__ T,
     double v = 0.0;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        const double *c = T + (size_t)(bj + m) * P.x2_nr + bi;
-        v += wj[m] * (wi[0] * c[0] + wi[1] * c[1] + wi[2] * c[2] + wi[3] * c[3]);
+        const float *c = T + x2_bidx(0, bj + m, P.x2_ntr);  // the column in its first row tile
+        double f[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const u32 i = bi + k;
+            f[k] = (double)c[(size_t)(i / X2TR) * (X2TR * X2TC) + i % X2TR];
+        }
+        v += wj[m] * (wi[0] * f[0] + wi[1] * f[1] + wi[2] * f[2] + wi[3] * f[3]);
     }
     return v;
 }
@@ -212,11 +233,13 @@ __global__ __launch_bounds__(256) void k_x2_gemm(const double *__restrict__ L, c
         }
 }
 
-// The tables from the products (row-major nr x n0) into column-major form.
+// The tables from the products (row-major nr x n0): p_enc and p_reac blocked in
+// binary32 (ntr row tiles), the distribution function column-major in binary64.
 // top: rows from R_j to the top of its distribution function.
 __global__ void k_x2_tables(const double *__restrict__ Gabs, const double *__restrict__ Gref, const double *__restrict__ Grad,
                             const double *__restrict__ Mabs, const double *__restrict__ Mref, u32 nr, u32 n0, double h,
-                            double tau, u32 top, double *__restrict__ enc, double *__restrict__ reac, double *__restrict__ cdf)
+                            double tau, u32 top, u32 ntr, float *__restrict__ enc, float *__restrict__ reac,
+                            double *__restrict__ cdf)
 {
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (size_t)nr * n0) return;
@@ -225,9 +248,10 @@ __global__ void k_x2_tables(const double *__restrict__ Gabs, const double *__res
     const double R = 1.0 + i * h, R0 = 1.0 + (double)(X2S * j) * h;
     // free function e^{-(R-R0)^2/4tau} i0e(R R0/2tau) / (4 pi tau)
     const double gf = exp(-(R - R0) * (R - R0) / (4.0 * tau)) * i0e_d(R * R0 / (2.0 * tau)) / (4.0 * PI_D * tau);
-    enc[t] = i == 0 ? 1.0 : 1.0 - Gabs[a] / gf;
+    const size_t b = x2_bidx(i, j, ntr);
+    enc[b] = (float)(i == 0 ? 1.0 : 1.0 - Gabs[a] / gf);
     const double den = Gref[a] - Gabs[a];
-    reac[t] = den > 0.0 ? (Gref[a] - Grad[a]) / den : 0.0;
+    reac[b] = (float)(den > 0.0 ? (Gref[a] - Grad[a]) / den : 0.0);
     const u32 it = min(X2S * j + top, nr - 1);
     const size_t at = (size_t)it * n0 + j;
     const double mt = Mref[at] - Mabs[at];
