@@ -46,28 +46,28 @@ def algorithmic_bytes(kernel, n_live, n_a, n_b, n_keys):
 # commands are in profiles/rad3d_step_traffic.md.  Valid only for the kernel sources they were taken
 # on (hash below): after any change to them the field is reported as null.
 MEASURED_TRAFFIC = {
-    "src_hash": "2b20a134f0dd64fe",
+    "src_hash": "de1a82eea077bcc7",
     "scale_fetch": 1.9998, "scale_write": 1.0,
     "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
-        "move": (9950.7, 31398.0),
+        "move": (9940.4, 31398.1),
         "scan": (11633.6, 17387.4),
-        "scatter": (17018.7, 29445.9),
-        "pairs": (9762.1, 299.2),
-        "eval": (3255.4, 200.0),
-        "select_a": (251.4, 60.5),
-        "select_b": (268.0, 12.3),
-        "events": (336.1, 73.8),
+        "scatter": (16985.7, 29458.0),
+        "pairs": (9762.9, 299.2),
+        "eval": (3256.1, 199.8),
+        "select_a": (249.4, 60.5),
+        "select_b": (257.6, 12.2),
+        "events": (2.2, 0.9),  # k_close only: the 3D events run in the angle stage's kernel
     },
     # stage -> VALU wave-instructions per launch (SQ_INSTS_VALU summed over the stage's kernels)
     "valu": {
         "move": 6003797,
         "scan": 416342,
         "scatter": 723655,
-        "pairs": 5250208,
-        "eval": 437598,
-        "select_a": 69738,
-        "select_b": 214482,
-        "events": 1143656,
+        "pairs": 5250540,
+        "eval": 437532,
+        "select_a": 69654,
+        "select_b": 214393,
+        "events": 21,
     },
 }
 
@@ -139,12 +139,12 @@ def valu_issue(stage, launch_ms):
 # (SQ_INSTS_VALU_{ADD,MUL,TRANS,FMA}_F64 x 64 lanes, an FMA counting two; SQ_INSTS_VALU),
 # profiles/angle3_kernels.md and profiles/angle2_kernels.md.  Valid for the source they were taken on.
 ANGLE_COUNTERS = {3: {
-    "src_hash": "fa904578223810ec",
+    "src_hash": "e095a5bdba4de5a4",
     "pairs": 1000000,
     "f64_flop": 4.631595e+11,  # 64 x (ADD 459791425 + MUL 1741552687 + TRANS 164812436 + 2 x FMA 2435355467)
     "valu": 7445373893,
 }, 2: {  # k_angle_wg<2> on --angle 200000 --dim 2 (membrane pairs, tau = 0.04)
-    "src_hash": "4175384f1b737beb",
+    "src_hash": "d7b5d01096fa47d2",
     "pairs": 200000,
     "f64_flop": 6.560815e+11,  # 64 x (ADD 602869869 + MUL 2437297157 + TRANS 198034386 + 2 x FMA 3506536180)
     "valu": 9468675080,
@@ -169,15 +169,16 @@ def angle_roofline(n, launch_ms, dim=3):
             "valu_issue_frac": round(t["valu"] / VALU_WAVE_INSTR_PER_S / (launch_ms * 1e-3), 4)}
 
 
-# The step's angle stage (k_angles) on the default run of this workload: fp64 operations and VALU
+# The step's angle stage on the default run of this workload (3D: k_events_angles, which runs each
+# event and then the angle of its propagated pair; 2D: k_angles): fp64 operations and VALU
 # wave-instructions per launch from rocprofv3 (SQ_INSTS_VALU_{ADD,MUL,TRANS,FMA}_F64 x 64 lanes, an
 # FMA counting two; SQ_INSTS_VALU), and its HBM bytes (FETCH_SIZE, WRITE_SIZE scaled as above),
 # profiles/rad3d_step_valu.md and profiles/rad3d_step_traffic.md.  Valid for the sources they were taken on (hash below).
 ANGLE_STEP_COUNTERS = {
-    "src_hash": "4a7fd8a9abee8cfe",
-    "f64_flop": 2.166964e+08,  # 64 x (ADD 226747 + MUL 795576 + TRANS 80261 + 2 x FMA 1141648)
-    "valu": 3813262,
-    "traffic": 870021,
+    "src_hash": "26c7cacc03e229a4",
+    "f64_flop": 2.701000e+08,  # 64 x (ADD 425290 + MUL 845650 + TRANS 98717 + 2 x FMA 1425328)
+    "valu": 4848213,
+    "traffic": 1411188,
 }
 ANGLE_STEP_SOURCES = ["common.hpp", "green.hpp", "green2x.hpp", "kernels.hpp", "angle3.hpp", "angle2.hpp",
                       "angle_wg.hpp", "gfbd.hip"]
@@ -189,13 +190,15 @@ def angle_step_src_hash():
 
 def angle_step_roofline(launch_ms, profiled):
     """The angle stage against the fp64 vector peak: plain fp64 arithmetic (Bessel recurrences,
-    quadrature sums, Legendre sums) on a few hundred pairs, a workgroup each.  The operations are
-    the ones the kernel executes (counters), not an algorithmic count."""
+    quadrature sums, Legendre sums) on a few hundred pairs, a workgroup each (in 3D the same
+    launch runs the step's events first, one wave each).  The operations are the ones the kernel
+    executes (counters), not an algorithmic count."""
     t = ANGLE_STEP_COUNTERS
     valid = profiled and t["src_hash"] is not None and angle_step_src_hash() == t["src_hash"]
-    out = {"kernel": "angles", "bound": "alu", "achieved": None, "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+    out = {"kernel": "k_events_angles (the step's events, then the angles of its propagated pairs)", "bound": "alu", "achieved": None, "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
            "frac": None, "traffic": t["traffic"] if valid else None, "avg_launch_ms": round(launch_ms, 5),
-           "flop_source": "rocprofv3 fp64 VALU counters of k_angles (executed operations)", "valu_issue_frac": None}
+           "flop_source": "rocprofv3 fp64 VALU counters of k_events_angles (events and angles; executed operations)",
+           "valu_issue_frac": None}
     if valid:
         ach = t["f64_flop"] / (launch_ms * 1e-3) / 1e12
         out.update(achieved=round(ach, 3), frac=round(ach * 1e12 / FP64_VECTOR_PEAK, 4), flop_per_launch=t["f64_flop"],

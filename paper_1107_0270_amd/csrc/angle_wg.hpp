@@ -660,12 +660,80 @@ __global__ __launch_bounds__(AWG, 2) void k_angle_wg(double tau, uint64_t n, con
 // centre of diffusion keeps its free end point (eq. Rcoo), and the pair is placed
 // R'' a apart along the drawn direction.  A pre-step separation of length zero, or
 // radii beyond any encounter, keep the free end point's direction.
+// One propagated pair (event e of the step): its angle and new positions, drawn by the whole
+// workgroup.  Uniform: every argument.
+template <int DIM, class T, int PM, bool BATCH>
+__device__ __forceinline__ void ang_place(const Params &P, Rec<T> *__restrict__ rec, const AngEnt &e, u32 step, DbgMatch *dbg,
+                                          const GL16 &gl, AngShared &sh)
+{
+#pragma clang fp contract(off)
+    double v;
+    {
+        const u32 sa = meta_slot(rec_meta(rec[e.ia])), sb = meta_slot(rec_meta(rec[e.ib]));
+        const Params &Q = rep_params<BATCH>(P, sa);
+        const uint4 r = philox(sa - Q.slot_base, sb - Q.slot_base, step - Q.step_base, TAG_ANG, Q.key);
+        v = ang_draw_wg<DIM>(Q.tau, e.Rpp, e.R0, u01(r.x), gl, sh);
+    }
+    if (threadIdx.x == 0) {  // the records again: nothing held across the draw
+        Rec<T> ra = rec[e.ia], rb = rec[e.ib];
+        const u32 sa = meta_slot(rec_meta(ra)), sb = meta_slot(rec_meta(rb));
+        const Params &Q = rep_params<BATCH>(P, sa);
+        const u32 la = sa - Q.slot_base, lb = sb - Q.slot_base, ls = step - Q.step_base;
+        const uint4 r = philox(la, lb, ls, TAG_ANG, Q.key);
+        const double xa[3] = {(double)ra.x, (double)ra.y, (double)ra.z};
+        const double xb[3] = {(double)rb.x, (double)rb.y, (double)rb.z};
+        double dA[3], dB[3];
+        displacement<DIM, T, PM>(Q, la, SP_A, ls, dA);
+        displacement<DIM, T, PM>(Q, lb, SP_B, ls, dB);
+        double rv[3] = {0.0, 0.0, 0.0}, r0v[3] = {0.0, 0.0, 0.0}, rn = 0.0, n0 = 0.0;
+        for (int d = 0; d < DIM; ++d) {
+            rv[d] = min_image_d(xb[d] - xa[d], Q.L[d], Q.Lh[d]);
+            r0v[d] = rv[d] - (dB[d] - dA[d]);
+            rn += rv[d] * rv[d];
+            n0 += r0v[d] * r0v[d];
+        }
+        rn = sqrt(rn);
+        n0 = sqrt(n0);
+        const double c = n0 > 0.0 ? (DIM == 3 ? v : cos(v)) : __builtin_nan("");
+        double ev[3] = {0.0, 0.0, 0.0};
+        if (!(c == c)) {  // the free end point's direction
+            for (int d = 0; d < DIM; ++d) ev[d] = rn > 0.0 ? rv[d] / rn : (d == DIM - 1 ? 1.0 : 0.0);
+        } else {
+            double nv[3] = {0.0, 0.0, 0.0};
+            for (int d = 0; d < DIM; ++d) nv[d] = r0v[d] / n0;
+            if constexpr (DIM == 3) {
+                const double sg = nv[2] >= 0.0 ? 1.0 : -1.0, aa = -1.0 / (sg + nv[2]), bb = nv[0] * nv[1] * aa;
+                const double b1[3] = {1.0 + sg * nv[0] * nv[0] * aa, sg * bb, -sg * nv[0]};
+                const double b2[3] = {bb, sg + nv[1] * nv[1] * aa, -nv[1]};
+                const double sn = sqrt(fmax(0.0, 1.0 - c * c));
+                double sp, cp;
+                sincos_turn<T>(u01(r.y), &sp, &cp);
+                for (int d = 0; d < 3; ++d) ev[d] = c * nv[d] + sn * (cp * b1[d] + sp * b2[d]);
+            } else {
+                const double sn = (r.y >> 31 ? -1.0 : 1.0) * sqrt(fmax(0.0, 1.0 - c * c));
+                ev[0] = c * nv[0] - sn * nv[1];
+                ev[1] = sn * nv[0] + c * nv[1];
+            }
+        }
+        T na[3] = {0, 0, 0}, nb[3] = {0, 0, 0};
+        for (int d = 0; d < DIM; ++d) {
+            const double cen = xa[d] + Q.fA * rv[d];
+            na[d] = wrap_store<T>(cen - Q.fA * Q.a * e.Rpp * ev[d], Q.L[d]);
+            nb[d] = wrap_store<T>(cen + Q.fB * Q.a * e.Rpp * ev[d], Q.L[d]);
+        }
+        ra.x = na[0]; ra.y = na[1]; ra.z = na[2];
+        rb.x = nb[0]; rb.y = nb[1]; rb.z = nb[2];
+        rec[e.ia] = ra;
+        rec[e.ib] = rb;
+        if (P.debug && e.dbg < P.dbg_cap) dbg[e.dbg].cos_theta = c;
+    }
+}
+
 template <int DIM, class T, int PM, bool BATCH>
 __global__ __launch_bounds__(AWG, 2) void k_angles(const Params *__restrict__ Pd, Rec<T> *__restrict__ rec,
                                                 const AngEnt *__restrict__ ang, const Counters *__restrict__ C,
                                                 DbgMatch *dbg, GL16 gl)
 {
-#pragma clang fp contract(off)
     __shared__ AngShared sh;
     const Params &P = *Pd;
     const u32 n = min(C->n_ev, P.cap);
@@ -673,67 +741,108 @@ __global__ __launch_bounds__(AWG, 2) void k_angles(const Params *__restrict__ Pd
     for (u32 w = blockIdx.x; w < n; w += gridDim.x) {  // uniform
         const AngEnt e = ang[w];
         if (!e.on) continue;
-        double v;
-        {
-            const u32 sa = meta_slot(rec_meta(rec[e.ia])), sb = meta_slot(rec_meta(rec[e.ib]));
-            const Params &Q = rep_params<BATCH>(P, sa);
-            const uint4 r = philox(sa - Q.slot_base, sb - Q.slot_base, step - Q.step_base, TAG_ANG, Q.key);
-            v = ang_draw_wg<DIM>(Q.tau, e.Rpp, e.R0, u01(r.x), gl, sh);
-        }
-        if (threadIdx.x == 0) {  // the records again: nothing held across the draw
-            Rec<T> ra = rec[e.ia], rb = rec[e.ib];
-            const u32 sa = meta_slot(rec_meta(ra)), sb = meta_slot(rec_meta(rb));
-            const Params &Q = rep_params<BATCH>(P, sa);
-            const u32 la = sa - Q.slot_base, lb = sb - Q.slot_base, ls = step - Q.step_base;
-            const uint4 r = philox(la, lb, ls, TAG_ANG, Q.key);
-            const double xa[3] = {(double)ra.x, (double)ra.y, (double)ra.z};
-            const double xb[3] = {(double)rb.x, (double)rb.y, (double)rb.z};
-            double dA[3], dB[3];
-            displacement<DIM, T, PM>(Q, la, SP_A, ls, dA);
-            displacement<DIM, T, PM>(Q, lb, SP_B, ls, dB);
-            double rv[3] = {0.0, 0.0, 0.0}, r0v[3] = {0.0, 0.0, 0.0}, rn = 0.0, n0 = 0.0;
-            for (int d = 0; d < DIM; ++d) {
-                rv[d] = min_image_d(xb[d] - xa[d], Q.L[d], Q.Lh[d]);
-                r0v[d] = rv[d] - (dB[d] - dA[d]);
-                rn += rv[d] * rv[d];
-                n0 += r0v[d] * r0v[d];
+        ang_place<DIM, T, PM, BATCH>(P, rec, e, step, dbg, gl, sh);
+        __syncthreads();  // sh is reused by the next pair
+    }
+}
+
+// Event w in the wave form (every lane of the wave active): its counts (lane 0) and, in
+// lane 0, the hand-off of a propagated pair.
+template <int DIM, class T, int NC, bool BATCH>
+__device__ __forceinline__ EvCount ev_wave(const Params &P, Rec<T> *__restrict__ rec, const PairEnt *__restrict__ list,
+                                           const CandEnt *__restrict__ cand, const u32 *__restrict__ ev, u32 *__restrict__ partner,
+                                           u32 step, Counters *C, DbgMatch *dbg_m, DbgDiss *dbg_d, u32 w, AngEnt *g)
+{
+    const u32 e = ev[w];
+    if (e & EV_DECAY) {
+        const u32 i = e & ~EV_DECAY;
+        return ev_decay<DIM, T, NC, false>(ev_params<BATCH>(P, rec, i), rec, i, partner, step, C, dbg_d);
+    }
+    return ev_match<DIM, T, NC, false>(rep_params<BATCH>(P, cand[e].a_slot), rec, list[e].a_idx, list[e].b_idx, cand[e].R0,
+                                       partner, step, C, dbg_m, g);
+}
+
+// A hand-off that this workgroup wrote to device memory before its last barrier, read
+// with vector loads (a scalar load could see a line cached before the write).
+__device__ __forceinline__ AngEnt ang_load(const AngEnt *a)
+{
+    AngEnt e;
+    e.ia = __hip_atomic_load(&a->ia, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    e.ib = __hip_atomic_load(&a->ib, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    e.on = __hip_atomic_load(&a->on, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    e.dbg = __hip_atomic_load(&a->dbg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    e.Rpp = __hip_atomic_load(&a->Rpp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    e.R0 = __hip_atomic_load(&a->R0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return e;
+}
+
+// The events of the step and the angles of their propagated pairs in one launch (a step
+// whose pairs draw angles): one workgroup per event.  Its first wave runs the event in the
+// wave form of k_events (the same draws), hands the pair to the workgroup through LDS,
+// and a propagated pair then takes its angle as in k_angles.  A grid with fewer
+// workgroups than events takes its workgroup's events first and then their angles.  Records of different events
+// are disjoint, so the workgroups share nothing; a pair's records are written and read
+// again within its workgroup only.  This saves the second launch and the angle stage's
+// reloading of the event list.
+template <int DIM, class T, int NC, int PM, bool BATCH>
+__global__ __launch_bounds__(AWG, 2) void k_events_angles(const Params *__restrict__ Pd, Rec<T> *__restrict__ rec,
+                                                       const PairEnt *__restrict__ list, const CandEnt *__restrict__ cand,
+                                                       const u32 *__restrict__ ev, u32 *__restrict__ partner, Counters *C,
+                                                       DbgMatch *dbg_m, DbgDiss *dbg_d, AngEnt *ang, GL16 gl)
+{
+    __shared__ AngShared sh;
+    __shared__ AngEnt hand;
+    __shared__ u32 st[EV_ST];  // the wave form's counts (lane 0 of the first wave), kept out of registers
+    const Params &P = *Pd;
+    const u32 step = C->step;
+    const u32 n = min(C->n_ev, P.cap);
+    if (blockIdx.x >= n) return;  // no event for this workgroup (uniform): nothing to count either
+    if (threadIdx.x == 0)
+        for (int k = 0; k < EV_ST; ++k) st[k] = 0;
+    if (n <= gridDim.x) {  // one event per workgroup, handed over in LDS (uniform)
+        const u32 w = blockIdx.x;
+        if (threadIdx.x < 64) {
+            AngEnt g;
+            g.on = 0;
+            const EvCount c = ev_wave<DIM, T, NC, BATCH>(P, rec, list, cand, ev, partner, step, C, dbg_m, dbg_d, w, &g);
+            if (threadIdx.x == 0) {
+#pragma unroll
+                for (int k = 0; k < EV_ST; ++k) st[k] += c.v[k];
+                hand = g;
             }
-            rn = sqrt(rn);
-            n0 = sqrt(n0);
-            const double c = n0 > 0.0 ? (DIM == 3 ? v : cos(v)) : __builtin_nan("");
-            double ev[3] = {0.0, 0.0, 0.0};
-            if (!(c == c)) {  // the free end point's direction
-                for (int d = 0; d < DIM; ++d) ev[d] = rn > 0.0 ? rv[d] / rn : (d == DIM - 1 ? 1.0 : 0.0);
-            } else {
-                double nv[3] = {0.0, 0.0, 0.0};
-                for (int d = 0; d < DIM; ++d) nv[d] = r0v[d] / n0;
-                if constexpr (DIM == 3) {
-                    const double sg = nv[2] >= 0.0 ? 1.0 : -1.0, aa = -1.0 / (sg + nv[2]), bb = nv[0] * nv[1] * aa;
-                    const double b1[3] = {1.0 + sg * nv[0] * nv[0] * aa, sg * bb, -sg * nv[0]};
-                    const double b2[3] = {bb, sg + nv[1] * nv[1] * aa, -nv[1]};
-                    const double sn = sqrt(fmax(0.0, 1.0 - c * c));
-                    double sp, cp;
-                    sincos_turn<T>(u01(r.y), &sp, &cp);
-                    for (int d = 0; d < 3; ++d) ev[d] = c * nv[d] + sn * (cp * b1[d] + sp * b2[d]);
-                } else {
-                    const double sn = (r.y >> 31 ? -1.0 : 1.0) * sqrt(fmax(0.0, 1.0 - c * c));
-                    ev[0] = c * nv[0] - sn * nv[1];
-                    ev[1] = sn * nv[0] + c * nv[1];
+        }
+        __syncthreads();  // the records and the hand-off are written
+        const AngEnt e = hand;
+        if (e.on) ang_place<DIM, T, PM, BATCH>(P, rec, e, step, dbg_m, gl, sh);
+    } else {
+        // more events than workgroups: this workgroup's events first, their hand-offs in
+        // device memory, then their angles (two loops rather than one, so that neither
+        // loop holds the other's invariants across its body)
+        if (threadIdx.x < 64) {
+            for (u32 w = blockIdx.x; w < n; w += gridDim.x) {
+                AngEnt g;
+                g.on = 0;
+                const EvCount c = ev_wave<DIM, T, NC, BATCH>(P, rec, list, cand, ev, partner, step, C, dbg_m, dbg_d, w, &g);
+                if (threadIdx.x == 0) {
+#pragma unroll
+                    for (int k = 0; k < EV_ST; ++k) st[k] += c.v[k];
+                    ang[w] = g;
                 }
             }
-            T na[3] = {0, 0, 0}, nb[3] = {0, 0, 0};
-            for (int d = 0; d < DIM; ++d) {
-                const double cen = xa[d] + Q.fA * rv[d];
-                na[d] = wrap_store<T>(cen - Q.fA * Q.a * e.Rpp * ev[d], Q.L[d]);
-                nb[d] = wrap_store<T>(cen + Q.fB * Q.a * e.Rpp * ev[d], Q.L[d]);
-            }
-            ra.x = na[0]; ra.y = na[1]; ra.z = na[2];
-            rb.x = nb[0]; rb.y = nb[1]; rb.z = nb[2];
-            rec[e.ia] = ra;
-            rec[e.ib] = rb;
-            if (P.debug && e.dbg < P.dbg_cap) dbg[e.dbg].cos_theta = c;
         }
-        __syncthreads();  // sh is reused by the next pair
+        __syncthreads();  // the records and the hand-offs are written
+        for (u32 w = blockIdx.x; w < n; w += gridDim.x) {  // uniform
+            const AngEnt e = ang_load(ang + w);
+            if (!e.on) continue;
+            ang_place<DIM, T, PM, BATCH>(P, rec, e, step, dbg_m, gl, sh);
+            __syncthreads();  // sh is reused by the next pair
+        }
+    }
+    if (threadIdx.x == 0) {
+        const int map[EV_ST] = {ST_REACT, ST_ATTEMPTS, ST_BOUND, ST_NEAR, ST_DECAY, ST_GEMINATE};
+#pragma unroll
+        for (int k = 0; k < EV_ST; ++k)
+            if (st[k]) atomicAdd((unsigned long long *)&C->stats[map[k]], (unsigned long long)st[k]);
     }
 }
 

@@ -274,7 +274,8 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     PairEnt *plist = nullptr;
     CandEnt *cand = nullptr;
     u32 *flag = nullptr, *nextA = nullptr, *nextB = nullptr, *ev = nullptr;
-    AngEnt *ang = nullptr;  // propagated pairs handed to the angle stage (null: directions kept)
+    bool angles = false;    // propagated pairs draw their angle (otherwise they keep their direction)
+    AngEnt *ang = nullptr;  // hand-offs of the events to their angles when the events outnumber the workgroups
     GL16 gl16;              // 16-point Gauss-Legendre rule of the angular series
     u64 *headA = nullptr, *headB = nullptr;
     Counters *ctr = nullptr;
@@ -742,6 +743,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
             (rc = alloc(g_pos, n * DIM)) || (rc = alloc(g_sp, n)) || (batch && (rc = alloc(nkey, n))) ||
             (P.angles && (rc = alloc(ang, n))))
             return rc;
+        angles = P.angles != 0;
         gauss_legendre16(gl16.x, gl16.w);
         if (M.debug) {
             if ((rc = alloc(dbg_moved, n * DIM)) || (rc = alloc(dbg_disp, n * DIM)) || (rc = alloc(dbg_cells, n)) || (rc = alloc(dbg_pairs, M.dbg_cap)) ||
@@ -1052,14 +1054,23 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         launch(SIM_K_SELECT_B, [&] {
             k_select_b<T, BATCH><<<nb_sel + nb_dec, BLOCK, 0, st>>>(P, plist, cand, flag, headB, nextB, out, start, okey, ev, ctr, nb_sel);
         });
-        launch(SIM_K_EVENTS, [&] {
-            k_events<DIM, T, NC2, BATCH><<<M.event_blocks, BLOCK, 0, st>>>(dparams, out, plist, cand, ev, partner, ctr, dbg_matches,
-                                                                           dbg_diss, ang);
-        });
-        if (ang)
-            launch(SIM_K_ANGLES, [&] {
-                k_angles<DIM, T, PM, BATCH><<<M.event_blocks, AWG, 0, st>>>(dparams, out, ang, ctr, dbg_matches, gl16);
+        if (DIM == 3 && angles) {  // 3D: events and angles in one launch (timed as the angle stage)
+            if constexpr (DIM == 3)
+                launch(SIM_K_ANGLES, [&] {
+                    k_events_angles<DIM, T, NC2, PM, BATCH><<<M.event_blocks, AWG, 0, st>>>(dparams, out, plist, cand, ev, partner,
+                                                                                            ctr, dbg_matches, dbg_diss, ang, gl16);
+                });
+        } else {
+            // 2D: the two held together spill (the expansion's arrays beside the angle's), so apart
+            launch(SIM_K_EVENTS, [&] {
+                k_events<DIM, T, NC2, BATCH><<<M.event_blocks, BLOCK, 0, st>>>(dparams, out, plist, cand, ev, partner, ctr,
+                                                                               dbg_matches, dbg_diss, angles ? ang : nullptr);
             });
+            if (angles)
+                launch(SIM_K_ANGLES, [&] {
+                    k_angles<DIM, T, PM, BATCH><<<M.event_blocks, AWG, 0, st>>>(dparams, out, ang, ctr, dbg_matches, gl16);
+                });
+        }
         k_close<<<1, 64, 0, st>>>(ctr);
     }
 
