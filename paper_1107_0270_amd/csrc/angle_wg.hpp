@@ -776,14 +776,14 @@ __device__ __forceinline__ AngEnt ang_load(const AngEnt *a)
     return e;
 }
 
-// The events of the step and the angles of their propagated pairs in one launch (a step
+// The events of the step and the angles of their propagated pairs in one launch (a 3D step
 // whose pairs draw angles): one workgroup per event.  Its first wave runs the event in the
 // wave form of k_events (the same draws), hands the pair to the workgroup through LDS,
-// and a propagated pair then takes its angle as in k_angles.  A grid with fewer
-// workgroups than events takes its workgroup's events first and then their angles.  Records of different events
-// are disjoint, so the workgroups share nothing; a pair's records are written and read
-// again within its workgroup only.  This saves the second launch and the angle stage's
-// reloading of the event list.
+// and a propagated pair then takes its angle as in k_angles.  With fewer workgroups than
+// events, a workgroup runs its events first and then their angles.  Records of different
+// events are disjoint, so the workgroups share nothing; a pair's records are written and
+// read again within its workgroup only.  This saves the second launch and the angle
+// stage's reloading of the event list.
 template <int DIM, class T, int NC, int PM, bool BATCH>
 __global__ __launch_bounds__(AWG, 2) void k_events_angles(const Params *__restrict__ Pd, Rec<T> *__restrict__ rec,
                                                        const PairEnt *__restrict__ list, const CandEnt *__restrict__ cand,
