@@ -46,27 +46,27 @@ def algorithmic_bytes(kernel, n_live, n_a, n_b, n_keys):
 # commands are in profiles/rad3d_step_traffic.md.  Valid only for the kernel sources they were taken
 # on (hash below): after any change to them the field is reported as null.
 MEASURED_TRAFFIC = {
-    "src_hash": "de1a82eea077bcc7",
+    "src_hash": "c378ed2de7747a9c",
     "scale_fetch": 1.9998, "scale_write": 1.0,
     "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
-        "move": (9940.4, 31398.1),
-        "scan": (11633.6, 17387.4),
-        "scatter": (16985.7, 29458.0),
-        "pairs": (9762.9, 299.2),
-        "eval": (3256.1, 199.8),
-        "select_a": (249.4, 60.5),
-        "select_b": (257.6, 12.2),
-        "events": (2.2, 0.9),  # k_close only: the 3D events run in the angle stage's kernel
+        "move": (9977.2, 31398.0),
+        "scan": (11644.6, 17387.4),
+        "scatter": (17003.7, 29450.9),
+        "pairs": (9759.5, 299.2),
+        "eval": (3256.8, 199.9),
+        "select_a": (251.4, 60.7),
+        "select_b": (269.0, 12.4),
+        "events": (2.8, 0.9),  # k_close only: the 3D events run in the angle stage's kernel
     },
     # stage -> VALU wave-instructions per launch (SQ_INSTS_VALU summed over the stage's kernels)
     "valu": {
-        "move": 6003797,
-        "scan": 416342,
-        "scatter": 723655,
-        "pairs": 5250540,
-        "eval": 437532,
-        "select_a": 69654,
-        "select_b": 214393,
+        "move": 6003798,
+        "scan": 439478,
+        "scatter": 723656,
+        "pairs": 5250463,
+        "eval": 437598,
+        "select_a": 69737,
+        "select_b": 214480,
         "events": 21,
     },
 }
@@ -175,10 +175,10 @@ def angle_roofline(n, launch_ms, dim=3):
 # FMA counting two; SQ_INSTS_VALU), and its HBM bytes (FETCH_SIZE, WRITE_SIZE scaled as above),
 # profiles/rad3d_step_valu.md and profiles/rad3d_step_traffic.md.  Valid for the sources they were taken on (hash below).
 ANGLE_STEP_COUNTERS = {
-    "src_hash": "26c7cacc03e229a4",
+    "src_hash": "4b6233e114853f3b",
     "f64_flop": 2.701000e+08,  # 64 x (ADD 425290 + MUL 845650 + TRANS 98717 + 2 x FMA 1425328)
     "valu": 4848213,
-    "traffic": 1411188,
+    "traffic": 1436770,
 }
 ANGLE_STEP_SOURCES = ["common.hpp", "green.hpp", "green2x.hpp", "kernels.hpp", "angle3.hpp", "angle2.hpp",
                       "angle_wg.hpp", "gfbd.hip"]

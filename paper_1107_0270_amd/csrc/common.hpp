@@ -172,7 +172,7 @@ struct Counters {
     u32 step;       // step number used by every draw of this step
     u32 err;
     u32 n_dbg[4];   // pairs, picks, matches, dissociations logged this step
-    u32 unused0;
+    u32 cell_hw;    // cells in use from the start of every species block (a pool's high-water mark)
     u32 n_sorted;   // leading records whose bucket keys the last binning noted
     u32 n_kept;     // records kept by a pool compaction (zero between compactions)
     u32 pad[3];

@@ -265,6 +265,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
     uint64_t n = 0, stepno = 0;
     int cur = 0;
     uint32_t maxA = 0, maxC = 0, nb_scan = 0;
+    u32 cell_hw = 0;  // a pool: cells taken by its members so far, from the start of each species block
     double cell_edge = 0.0, pair_tests = 0.0;
     bool narrow = false;
     // device memory
@@ -783,6 +784,7 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         c.n_rec = (u32)live;
         c.n_live = (u32)live;
         c.step = (u32)step0;
+        c.cell_hw = pool ? cell_hw : P.n_cells;  // a pool: the cells its members have taken so far
         HIPCHECK(hipMemcpyAsync(ctr, &c, sizeof(c), hipMemcpyHostToDevice, M.stream));
         HIPCHECK(hipMemsetAsync(headA, 0, sizeof(u64) * n, M.stream));  // no chain survives a reload
         HIPCHECK(hipMemsetAsync(headB, 0, sizeof(u64) * n, M.stream));
@@ -911,6 +913,8 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         HIPCHECK(hipMemcpyAsync(partner + s0, hp.data(), sizeof(u32) * m, hipMemcpyHostToDevice, M.stream));
         if (!h.empty()) HIPCHECK(hipMemcpyAsync(rec[cur] + n_rec, h.data(), sizeof(Rec<T>) * h.size(), hipMemcpyHostToDevice, M.stream));
         HIPCHECK(hipMemcpyAsync(&ctr->n_rec, &n_new, sizeof(u32), hipMemcpyHostToDevice, M.stream));
+        cell_hw = std::max<u32>(cell_hw, (u32)(c0 + Q.n_cells));  // never lowered: cells of members that left may still hold dead records
+        HIPCHECK(hipMemcpyAsync(&ctr->cell_hw, &cell_hw, sizeof(u32), hipMemcpyHostToDevice, M.stream));
         HIPCHECK(hipStreamSynchronize(M.stream));  // the host buffers above are read by the copies
         reps_h[idx] = Q;
         member_n[idx] = m;
@@ -1027,8 +1031,8 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         const u32 g_pl = M.pair_blocks;
         launch(SIM_K_MOVE, [&] { k_move_count<DIM, T, PM, BATCH><<<g_all, BLOCK, 0, st>>>(P, in, okey, tmp, rank, cnt, scnt, nkey, ctr); });
         launch(SIM_K_SCAN, [&] {
-            k_scan_tiles<<<nb_scan, BLOCK, 0, st>>>(cnt, scnt, bsum);
-            k_scan<<<nb_scan, BLOCK, 0, st>>>(cnt, scnt, bsum, start, ctr);
+            k_scan_tiles<<<nb_scan, BLOCK, 0, st>>>(cnt, scnt, bsum, ctr, P.n_cells);
+            k_scan<<<nb_scan, BLOCK, 0, st>>>(cnt, scnt, bsum, start, ctr, P.n_cells);
         });
         launch(SIM_K_SCATTER, [&] { k_scatter<DIM, T, BATCH><<<g_all, BLOCK, 0, st>>>(P, tmp, rank, start, out, okey, nkey, ctr); });
         if (M.debug) {

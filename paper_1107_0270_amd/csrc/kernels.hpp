@@ -340,9 +340,24 @@ __device__ __forceinline__ void load_counts(const u32 *cnt, u32 g, u32 region_le
     for (int r = 0; r < 16; ++r) v[r] = cnt[(size_t)r * region_len + g];
 }
 
-__global__ __launch_bounds__(BLOCK) void k_scan_tiles(const u32 *__restrict__ cnt, const u32 *__restrict__ scnt, u32 *__restrict__ tsum)
+// A tile of keys lying wholly in the unused tail of one species block (cells beyond the
+// high-water mark hw, the first of them excluded: its start closes the last used bucket)
+// holds no record: its counts stay zero and no kernel reads its starts.  A pool sized for
+// its capacity has most of its tiles there, and the scan skips them.
+__device__ __forceinline__ bool scan_tile_idle(u32 b, u32 n_cells, u32 hw)
+{
+    const uint64_t k0 = (uint64_t)b * SCAN_TILE, s0 = k0 / n_cells, c0 = k0 - s0 * n_cells;
+    return c0 > hw && k0 + SCAN_TILE <= (s0 + 1) * n_cells;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_tiles(const u32 *__restrict__ cnt, const u32 *__restrict__ scnt, u32 *__restrict__ tsum,
+                                                       const Counters *__restrict__ C, u32 n_cells)
 {
     __shared__ u32 lds[BLOCK / 64];
+    if (scan_tile_idle(blockIdx.x, n_cells, C->cell_hw)) {  // uniform
+        if (threadIdx.x == 0) tsum[blockIdx.x] = 0u;
+        return;
+    }
     u32 v[16], w[16];
     load_counts(cnt, gtid(), gridDim.x * BLOCK, v);
     load_counts(scnt, gtid(), gridDim.x * BLOCK, w);
@@ -356,9 +371,11 @@ __global__ __launch_bounds__(BLOCK) void k_scan_tiles(const u32 *__restrict__ cn
 }
 
 __global__ __launch_bounds__(BLOCK) void k_scan(u32 *__restrict__ cnt, u32 *__restrict__ scnt, const u32 *__restrict__ tsum,
-                                                 u32 *__restrict__ start, Counters *C)
+                                                 u32 *__restrict__ start, Counters *C, u32 n_cells)
 {
     __shared__ u32 lds[BLOCK / 64];
+    // an idle tile has nothing to write (the last one still writes the total)
+    if (blockIdx.x + 1 < gridDim.x && scan_tile_idle(blockIdx.x, n_cells, C->cell_hw)) return;  // uniform
     const size_t base = (size_t)blockIdx.x * SCAN_TILE + SCAN_ITEMS * threadIdx.x;
     const u32 rl = gridDim.x * BLOCK;
     u32 v[16], w[16];
