@@ -49,13 +49,13 @@ MEASURED_TRAFFIC = {
     "src_hash": "c378ed2de7747a9c",
     "scale_fetch": 1.9998, "scale_write": 1.0,
     "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
-        "move": (9977.2, 31398.0),
+        "move": (9939.5, 31398.0),
         "scan": (11644.6, 17387.4),
-        "scatter": (17003.7, 29450.9),
-        "pairs": (9759.5, 299.2),
-        "eval": (3256.8, 199.9),
-        "select_a": (251.4, 60.7),
-        "select_b": (269.0, 12.4),
+        "scatter": (17012.2, 29452.5),
+        "pairs": (9762.9, 299.2),
+        "eval": (3254.5, 200.0),
+        "select_a": (251.8, 60.6),
+        "select_b": (269.6, 12.5),
         "events": (2.8, 0.9),  # k_close only: the 3D events run in the angle stage's kernel
     },
     # stage -> VALU wave-instructions per launch (SQ_INSTS_VALU summed over the stage's kernels)
@@ -63,10 +63,10 @@ MEASURED_TRAFFIC = {
         "move": 6003798,
         "scan": 439478,
         "scatter": 723656,
-        "pairs": 5250463,
-        "eval": 437598,
-        "select_a": 69737,
-        "select_b": 214480,
+        "pairs": 5250591,
+        "eval": 437626,
+        "select_a": 69792,
+        "select_b": 214540,
         "events": 21,
     },
 }
@@ -139,12 +139,12 @@ def valu_issue(stage, launch_ms):
 # (SQ_INSTS_VALU_{ADD,MUL,TRANS,FMA}_F64 x 64 lanes, an FMA counting two; SQ_INSTS_VALU),
 # profiles/angle3_kernels.md and profiles/angle2_kernels.md.  Valid for the source they were taken on.
 ANGLE_COUNTERS = {3: {
-    "src_hash": "e095a5bdba4de5a4",
+    "src_hash": "19e71876d53c5d1c",
     "pairs": 1000000,
     "f64_flop": 4.631595e+11,  # 64 x (ADD 459791425 + MUL 1741552687 + TRANS 164812436 + 2 x FMA 2435355467)
     "valu": 7445373893,
 }, 2: {  # k_angle_wg<2> on --angle 200000 --dim 2 (membrane pairs, tau = 0.04)
-    "src_hash": "d7b5d01096fa47d2",
+    "src_hash": "e86c7c93a4030e22",
     "pairs": 200000,
     "f64_flop": 6.560815e+11,  # 64 x (ADD 602869869 + MUL 2437297157 + TRANS 198034386 + 2 x FMA 3506536180)
     "valu": 9468675080,
@@ -175,10 +175,10 @@ def angle_roofline(n, launch_ms, dim=3):
 # FMA counting two; SQ_INSTS_VALU), and its HBM bytes (FETCH_SIZE, WRITE_SIZE scaled as above),
 # profiles/rad3d_step_valu.md and profiles/rad3d_step_traffic.md.  Valid for the sources they were taken on (hash below).
 ANGLE_STEP_COUNTERS = {
-    "src_hash": "4b6233e114853f3b",
+    "src_hash": "7a67e493f3fd301e",
     "f64_flop": 2.701000e+08,  # 64 x (ADD 425290 + MUL 845650 + TRANS 98717 + 2 x FMA 1425328)
-    "valu": 4848213,
-    "traffic": 1436770,
+    "valu": 4841123,
+    "traffic": 1426601,
 }
 ANGLE_STEP_SOURCES = ["common.hpp", "green.hpp", "green2x.hpp", "kernels.hpp", "angle3.hpp", "angle2.hpp",
                       "angle_wg.hpp", "gfbd.hip"]

@@ -746,9 +746,9 @@ __global__ __launch_bounds__(AWG, 2) void k_angles(const Params *__restrict__ Pd
     }
 }
 
-// Event w in the wave form (every lane of the wave active): its counts (lane 0) and, in
-// lane 0, the hand-off of a propagated pair.
-template <int DIM, class T, int NC, bool BATCH>
+// Event w in the wave form (LANE false: every lane of the wave active; the counts and the
+// hand-off in lane 0) or the lane form (one event per lane).
+template <int DIM, class T, int NC, bool BATCH, bool LANE = false>
 __device__ __forceinline__ EvCount ev_wave(const Params &P, Rec<T> *__restrict__ rec, const PairEnt *__restrict__ list,
                                            const CandEnt *__restrict__ cand, const u32 *__restrict__ ev, u32 *__restrict__ partner,
                                            u32 step, Counters *C, DbgMatch *dbg_m, DbgDiss *dbg_d, u32 w, AngEnt *g)
@@ -756,10 +756,10 @@ __device__ __forceinline__ EvCount ev_wave(const Params &P, Rec<T> *__restrict__
     const u32 e = ev[w];
     if (e & EV_DECAY) {
         const u32 i = e & ~EV_DECAY;
-        return ev_decay<DIM, T, NC, false>(ev_params<BATCH>(P, rec, i), rec, i, partner, step, C, dbg_d);
+        return ev_decay<DIM, T, NC, LANE>(ev_params<BATCH>(P, rec, i), rec, i, partner, step, C, dbg_d);
     }
-    return ev_match<DIM, T, NC, false>(rep_params<BATCH>(P, cand[e].a_slot), rec, list[e].a_idx, list[e].b_idx, cand[e].R0,
-                                       partner, step, C, dbg_m, g);
+    return ev_match<DIM, T, NC, LANE>(rep_params<BATCH>(P, cand[e].a_slot), rec, list[e].a_idx, list[e].b_idx, cand[e].R0,
+                                      partner, step, C, dbg_m, g);
 }
 
 // A hand-off that this workgroup wrote to device memory before its last barrier, read
@@ -815,22 +815,21 @@ __global__ __launch_bounds__(AWG, 2) void k_events_angles(const Params *__restri
         const AngEnt e = hand;
         if (e.on) ang_place<DIM, T, PM, BATCH>(P, rec, e, step, dbg_m, gl, sh);
     } else {
-        // more events than workgroups: this workgroup's events first, their hand-offs in
-        // device memory, then their angles (two loops rather than one, so that neither
-        // loop holds the other's invariants across its body)
-        if (threadIdx.x < 64) {
-            for (u32 w = blockIdx.x; w < n; w += gridDim.x) {
-                AngEnt g;
-                g.on = 0;
-                const EvCount c = ev_wave<DIM, T, NC, BATCH>(P, rec, list, cand, ev, partner, step, C, dbg_m, dbg_d, w, &g);
-                if (threadIdx.x == 0) {
+        // more events than workgroups: this workgroup's events first, one per thread (the
+        // lane form: the same draws), their hand-offs in device memory, then their angles (two
+        // loops rather than one, so that neither loop holds the other's invariants across
+        // its body)
+        __syncthreads();  // st is cleared
+        for (u32 w = blockIdx.x + threadIdx.x * gridDim.x; w < n; w += AWG * gridDim.x) {
+            AngEnt g;
+            g.on = 0;
+            const EvCount c = ev_wave<DIM, T, NC, BATCH, true>(P, rec, list, cand, ev, partner, step, C, dbg_m, dbg_d, w, &g);
 #pragma unroll
-                    for (int k = 0; k < EV_ST; ++k) st[k] += c.v[k];
-                    ang[w] = g;
-                }
-            }
+            for (int k = 0; k < EV_ST; ++k)
+                if (c.v[k]) atomicAdd(&st[k], c.v[k]);
+            ang[w] = g;  // a decay's stays off
         }
-        __syncthreads();  // the records and the hand-offs are written
+        __syncthreads();  // the records, the hand-offs and the counts are written
         for (u32 w = blockIdx.x; w < n; w += gridDim.x) {  // uniform
             const AngEnt e = ang_load(ang + w);
             if (!e.on) continue;
