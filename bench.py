@@ -46,27 +46,27 @@ def algorithmic_bytes(kernel, n_live, n_a, n_b, n_keys):
 # commands are in profiles/rad3d_step_traffic.md.  Valid only for the kernel sources they were taken
 # on (hash below): after any change to them the field is reported as null.
 MEASURED_TRAFFIC = {
-    "src_hash": "c378ed2de7747a9c",
+    "src_hash": "1b95076bde67f42b",
     "scale_fetch": 1.9998, "scale_write": 1.0,
     "kib": {  # stage -> (FETCH_SIZE, WRITE_SIZE) summed over the stage's kernels
-        "move": (9939.5, 31398.0),
-        "scan": (11644.6, 17387.4),
-        "scatter": (17012.2, 29452.5),
-        "pairs": (9762.9, 299.2),
-        "eval": (3254.5, 200.0),
-        "select_a": (251.8, 60.6),
-        "select_b": (269.6, 12.5),
+        "move": (9935.4, 31398.0),
+        "scan": (11642.1, 17387.4),
+        "scatter": (17008.8, 29448.9),
+        "pairs": (9762.8, 299.2),
+        "eval": (3255.2, 200.1),
+        "select_a": (251.5, 60.5),
+        "select_b": (269.3, 12.2),
         "events": (2.8, 0.9),  # k_close only: the 3D events run in the angle stage's kernel
     },
     # stage -> VALU wave-instructions per launch (SQ_INSTS_VALU summed over the stage's kernels)
     "valu": {
-        "move": 6003798,
-        "scan": 439478,
-        "scatter": 723656,
-        "pairs": 5250591,
-        "eval": 437626,
-        "select_a": 69792,
-        "select_b": 214540,
+        "move": 6003796,
+        "scan": 416342,
+        "scatter": 723654,
+        "pairs": 5250566,
+        "eval": 437557,
+        "select_a": 69692,
+        "select_b": 214434,
         "events": 21,
     },
 }
@@ -175,10 +175,10 @@ def angle_roofline(n, launch_ms, dim=3):
 # FMA counting two; SQ_INSTS_VALU), and its HBM bytes (FETCH_SIZE, WRITE_SIZE scaled as above),
 # profiles/rad3d_step_valu.md and profiles/rad3d_step_traffic.md.  Valid for the sources they were taken on (hash below).
 ANGLE_STEP_COUNTERS = {
-    "src_hash": "7a67e493f3fd301e",
+    "src_hash": "46853af3da5233a3",
     "f64_flop": 2.701000e+08,  # 64 x (ADD 425290 + MUL 845650 + TRANS 98717 + 2 x FMA 1425328)
     "valu": 4841123,
-    "traffic": 1426601,
+    "traffic": 1426467,
 }
 ANGLE_STEP_SOURCES = ["common.hpp", "green.hpp", "green2x.hpp", "kernels.hpp", "angle3.hpp", "angle2.hpp",
                       "angle_wg.hpp", "gfbd.hip"]

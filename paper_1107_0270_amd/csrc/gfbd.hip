@@ -1031,8 +1031,9 @@ template <int DIM, class T, int PM> struct Engine final : sim {
         const u32 g_pl = M.pair_blocks;
         launch(SIM_K_MOVE, [&] { k_move_count<DIM, T, PM, BATCH><<<g_all, BLOCK, 0, st>>>(P, in, okey, tmp, rank, cnt, scnt, nkey, ctr); });
         launch(SIM_K_SCAN, [&] {
-            k_scan_tiles<<<nb_scan, BLOCK, 0, st>>>(cnt, scnt, bsum, ctr, P.n_cells);
-            k_scan<<<nb_scan, BLOCK, 0, st>>>(cnt, scnt, bsum, start, ctr, P.n_cells);
+            const u32 *hw = pool ? &ctr->cell_hw : nullptr;
+            k_scan_tiles<<<nb_scan, BLOCK, 0, st>>>(cnt, scnt, bsum, hw, P.n_cells);
+            k_scan<<<nb_scan, BLOCK, 0, st>>>(cnt, scnt, bsum, start, ctr, hw, P.n_cells);
         });
         launch(SIM_K_SCATTER, [&] { k_scatter<DIM, T, BATCH><<<g_all, BLOCK, 0, st>>>(P, tmp, rank, start, out, okey, nkey, ctr); });
         if (M.debug) {

@@ -350,11 +350,13 @@ __device__ __forceinline__ bool scan_tile_idle(u32 b, u32 n_cells, u32 hw)
     return c0 > hw && k0 + SCAN_TILE <= (s0 + 1) * n_cells;
 }
 
+// hw: the pool's high-water mark in its counters (null for a single system or a batch, whose
+// keys are all in use: no dependent load in front of the scan).
 __global__ __launch_bounds__(BLOCK) void k_scan_tiles(const u32 *__restrict__ cnt, const u32 *__restrict__ scnt, u32 *__restrict__ tsum,
-                                                       const Counters *__restrict__ C, u32 n_cells)
+                                                       const u32 *hw, u32 n_cells)
 {
     __shared__ u32 lds[BLOCK / 64];
-    if (scan_tile_idle(blockIdx.x, n_cells, C->cell_hw)) {  // uniform
+    if (hw && scan_tile_idle(blockIdx.x, n_cells, *hw)) {  // uniform
         if (threadIdx.x == 0) tsum[blockIdx.x] = 0u;
         return;
     }
@@ -371,11 +373,11 @@ __global__ __launch_bounds__(BLOCK) void k_scan_tiles(const u32 *__restrict__ cn
 }
 
 __global__ __launch_bounds__(BLOCK) void k_scan(u32 *__restrict__ cnt, u32 *__restrict__ scnt, const u32 *__restrict__ tsum,
-                                                 u32 *__restrict__ start, Counters *C, u32 n_cells)
+                                                 u32 *__restrict__ start, Counters *C, const u32 *hw, u32 n_cells)
 {
     __shared__ u32 lds[BLOCK / 64];
     // an idle tile has nothing to write (the last one still writes the total)
-    if (blockIdx.x + 1 < gridDim.x && scan_tile_idle(blockIdx.x, n_cells, C->cell_hw)) return;  // uniform
+    if (hw && blockIdx.x + 1 < gridDim.x && scan_tile_idle(blockIdx.x, n_cells, *hw)) return;  // uniform
     const size_t base = (size_t)blockIdx.x * SCAN_TILE + SCAN_ITEMS * threadIdx.x;
     const u32 rl = gridDim.x * BLOCK;
     u32 v[16], w[16];
